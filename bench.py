@@ -1,0 +1,176 @@
+#!/usr/bin/env python3
+"""Throughput of the per-fold training Gram path on one MI355X.
+
+One step = the whole hot path over one batch of synthetic input:
+cvgram_create (fold bookkeeping, statistics, grouped Gram) + every fold's 12
+distinct training products (4 X^T X + 8 X^T Y classes) + cvgram_destroy.
+Inputs are resident in HBM before timing starts.
+
+Prints ONE JSON line.  ``value`` is sets/s, a set being one fold's
+(X^T X, X^T Y) pair for one combination: P * 12 sets per step.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}  # TFLOP/s dense MFMA, MI355X
+HBM_PEAK = 8000.0  # GB/s
+
+
+def f_alg(n, k, m):
+    """Algorithmic flops of one Gram pass over all rows: the upper triangle
+    of X^T X (N K (K+1)) and all of X^T Y (2 N K M)."""
+    return n * k * (k + 1) + 2 * n * k * m
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--mode", default="fp64", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline legs")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    return ap.parse_args()
+
+
+def cpu_legs(X, Y, fold, P, gpu_xx, gpu_xy, budget_s):
+    """CPU baselines on the host cores: the oracle on a bounded sample (one
+    fold, all 12 classes) and the paper's fast algorithm on all folds."""
+    from oracle import cv_oracle as O
+    from oracle import fast_cpu
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count()])
+    except Exception:
+        threads = os.cpu_count()
+    t0 = time.perf_counter()
+    oxx, oxy = O.fold_all_classes(X, Y, fold, 0, ddof=1)
+    t_or = time.perf_counter() - t0
+    errs = []
+    for c in range(4):
+        errs.append(np.linalg.norm(gpu_xx[0, c] - oxx[c]) / np.linalg.norm(oxx[c]))
+    for c in range(8):
+        errs.append(np.linalg.norm(gpu_xy[0, c] - oxy[c]) / np.linalg.norm(oxy[c]))
+    cpu = {"value": 12.0 / t_or, "unit": "sets/s", "cores": int(threads), "kind": "oracle",
+           "sample": f"fold 0 of {P}, all 12 distinct classes, FP64 naive baseline",
+           "seconds": round(t_or, 3)}
+    fast = None
+    if t_or < budget_s:
+        t0 = time.perf_counter()
+        for _ in fast_cpu.fast_all_folds(X, Y, fold, ddof=1):
+            pass
+        t_fast = time.perf_counter() - t0
+        fast = {"value": P * 12.0 / t_fast, "unit": "sets/s", "cores": int(threads),
+                "kind": "paper fast algorithm (Algorithm 7, all classes), FP64 NumPy",
+                "sample": f"all {P} folds", "seconds": round(t_fast, 3)}
+    return cpu, fast, float(max(errs))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1 "
+                          "(the multi-GPU sharding is described in DESIGN.md, not built)"}))
+        sys.exit(2)
+    import torch
+    import paper_2401_13185_amd as cv
+    from synth import generators as G
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    wid = 2
+    shape, (X, Y, fold) = G.workload(wid)
+    N, K, M, P = shape.n, shape.k, shape.m, shape.p
+    print(f"[bench] workload {shape.name} generated", file=sys.stderr, flush=True)
+    Xd = torch.from_numpy(X).to(dev)
+    Yd = torch.from_numpy(Y).to(dev)
+    fd = torch.from_numpy(fold).to(dev)
+    odt = torch.float64 if args.mode == "fp64" else torch.float32
+    xx = torch.empty(P, 4, K, K, dtype=odt, device=dev)
+    xy = torch.empty(P, 8, K, M, dtype=odt, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step(timing=False):
+        h = cv.cvgram_create(Xd, Yd, fd, 1, 1, 1, 1, ddof=1, mode=args.mode, stream=stream)
+        if timing:
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+        cv.cvgram_folds_all(h, 0, P, xx, xy)
+        if timing:
+            e1.record(stream)
+            st = cv.cvgram_stage_times(h)
+            torch.cuda.synchronize()
+            st["correct"] = e0.elapsed_time(e1)
+        cv.cvgram_destroy(h)
+        return st if timing else None
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    print("[bench] warmup done", file=sys.stderr, flush=True)
+
+    # timed region: exactly `steps` steps
+    cv.cvgram_set_stage_timing(True)
+    stages = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        stages.append(step(timing=True))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    cv.cvgram_set_stage_timing(False)
+    ms = (t1 - t0) * 1e3 / args.steps
+    print("[bench] timed steps done", file=sys.stderr, flush=True)
+
+    sets = P * 12
+    stage_ms = {k: float(np.mean([s[k] for s in stages])) for k in stages[0]}
+    flops = f_alg(N, K, M)
+    gram_tflops = flops / (stage_ms["gram"] * 1e-3) / 1e12
+    out = {
+        "metric": "per-fold train Gram sets/s (12 distinct centering/scaling classes per fold)",
+        "value": sets / (ms * 1e-3),
+        "unit": "sets/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.mode == "fp64" else ("f32" if args.mode == "fp32" else "bf16x3+f32acc"),
+        "data": "synthetic",
+        "config": {"workload": shape.name, "N": N, "K": K, "M": M, "P": P, "folds": "Dirichlet(2)",
+                   "mode": args.mode, "classes_per_fold": 12, "ddof": 1},
+        "tflops_alg": flops / (ms * 1e-3) / 1e12,
+        "stage_ms": stage_ms,
+        "roofline": {"bound": "mfma", "kernel": "gram_f64_kernel" if args.mode == "fp64" else args.mode,
+                     "achieved": gram_tflops, "peak": PEAK[args.mode], "unit": "TFLOP/s",
+                     "frac": gram_tflops / PEAK[args.mode], "traffic": None},
+    }
+    if not args.no_cpu:
+        torch.cuda.synchronize()
+        gxx = xx.double().cpu().numpy()
+        gxy = xy.double().cpu().numpy()
+        cpu, fast, err = cpu_legs(X, Y, fold, P, gxx, gxy, args.cpu_seconds)
+        out["cpu_baseline"] = cpu
+        if fast:
+            out["cpu_fast"] = fast
+        out["max_rel_err_vs_oracle_fold0"] = err
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,202 @@
+/*
+ * cvgram.h -- fold-independent cross-validation Gram products on AMD MI355X
+ * (gfx950).
+ *
+ * Given X (N x K), Y (N x M) and a fold label per row, the library returns,
+ * for every fold p, the training-partition products X_T^T X_T and X_T^T Y_T
+ * (T = rows whose label is not p), with X and Y centred and/or scaled by
+ * statistics of the training rows only.  This is the problem of Engstrom &
+ * Jensen, "Fast Partition-Based Cross-Validation With Centering and Scaling
+ * for X^T X and X^T Y": Definition 1 (partitions), Definitions 2-5
+ * (means, centering, Bessel-corrected deviations, scaling), Section 6 and
+ * Table 1 (the 16 centering/scaling combinations, 12 of them distinct).
+ * The computation follows the paper's fast method (Algorithm 7, generalised
+ * to all combinations): full-data products once, validation-block products
+ * and column sums/sums of squares per fold, then subtraction (Lemmas 2-3),
+ * mean downdate (Lemma 7), rank-one centering (Propositions 7-8), deviation
+ * from sums (Lemmas 12-14) and Hadamard division (Propositions 15-16).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - All matrix arguments are DEVICE pointers (memory of the current HIP
+ *    device), dense row-major with no padding: X[n*K + k], Y[n*M + m],
+ *    out_XtX[i*K + j], out_XtY[i*M + j].
+ *  - Fold labels are int32, 0-based: label p is the paper's partition p+1.
+ *    The number of folds is P = max(label) + 1.  Definition 1 requires
+ *    2 <= P <= N, every label in [0, P) and every fold non-empty.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Device work is enqueued on it; calls return without waiting for it
+ *    except where stated.  Outputs are complete once the stream reaches the
+ *    point where the call enqueued its work.
+ *  - Every entry point returns a cvgram_status; nothing is thrown across the
+ *    ABI.  On an error the output arguments are left untouched (a handle
+ *    out-parameter is set to NULL) and nothing leaks;
+ *    cvgram_last_error_message() gives details for the calling thread.
+ *  - NaN or Inf inputs are not checked; they propagate into the outputs.
+ *  - Calls on one handle must not overlap from several host threads.
+ */
+#ifndef CVGRAM_H
+#define CVGRAM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cvgram_handle* cvgram_t;
+
+typedef enum {
+  CVGRAM_OK = 0,
+  CVGRAM_EINVAL = 1,        /* null pointer, bad size, bad flag or mode      */
+  CVGRAM_EFOLDS = 2,        /* partitioning violates Definition 1            */
+  CVGRAM_ENOTSCALABLE = 3,  /* scaling asked for but some |T_p| - ddof < 1
+                               (Definition 6, generalised to ddof)           */
+  CVGRAM_ENOMEM = 4,        /* device or pinned-host allocation failed       */
+  CVGRAM_EDEVICE = 5,       /* a HIP runtime call or kernel launch failed    */
+  CVGRAM_ERANGE = 6         /* fold index out of range                       */
+} cvgram_status;
+
+/* element type of X and Y */
+typedef enum { CVGRAM_F32 = 0, CVGRAM_F64 = 1 } cvgram_dtype;
+
+/* arithmetic of the Gram contractions (statistics and corrections are
+   always FP64):
+     CVGRAM_MODE_FP64    FP64 MFMA on FP64 pivot-shifted data; outputs FP64.
+     CVGRAM_MODE_FP32    FP32 MFMA, FP32 accumulation over row blocks that
+                         are combined in FP64; outputs FP32.
+     CVGRAM_MODE_BF16X3  each pivot-shifted value split as hi + lo in bf16;
+                         hi*hi + hi*lo + lo*hi on bf16 MFMA with FP32
+                         accumulation, row blocks combined in FP64; outputs
+                         FP32. */
+typedef enum {
+  CVGRAM_MODE_FP64 = 0,
+  CVGRAM_MODE_FP32 = 1,
+  CVGRAM_MODE_BF16X3 = 2
+} cvgram_mode;
+
+/* Class numbering of the distinct products (Section 6, Table 1).
+   X^T X depends only on X's preprocessing:
+     xtx class = 2*center_x + scale_x   (0 raw, 1 scaled, 2 centred,
+                                          3 centred and scaled)
+   X^T Y depends on whether X or Y (or both) is centred (Lemma 9) and on
+   each scaling:
+     xty class = 4*(center_x | center_y) + 2*scale_x + scale_y            */
+#define CVGRAM_XTX_CLASSES 4
+#define CVGRAM_XTY_CLASSES 8
+
+/*
+ * cvgram_create -- plan and run the per-fold statistics and Gram pass.
+ *
+ * Inputs: X (N x K) and Y (N x M) of element type `dtype`, fold_id[N]
+ * (int32); all device pointers.  Y may be NULL only when M == 0.
+ * N >= 2, K >= 1, M >= 0.  center_x/scale_x/center_y/scale_y (0 or 1)
+ * select the combination returned by cvgram_fold(); ddof is 0 or 1 (1 is
+ * the paper's Bessel correction, Definition 4); deviations divide by
+ * |T_p| - ddof.
+ *
+ * What it does (Algorithm 1; Algorithm 7 steps 3-4, 8, 10, 17, 19): sorts
+ * the rows by fold label on the device (stable: rows ascending within a
+ * fold), validates the partitioning, computes per-column pivots, the FP64
+ * column sums, sums of squares, minima and maxima of every validation
+ * block, and the validation-block Gram products of all folds in one grouped
+ * MFMA launch.  It waits on `stream` twice, for a few bytes of validation
+ * results; everything after that is only enqueued.
+ *
+ * Ownership: X, Y and fold_id are borrowed; they must stay valid and
+ * unchanged until the work this call enqueued has completed.  The handle
+ * owns all its device workspace and is freed by cvgram_destroy().
+ *
+ * Errors: CVGRAM_EINVAL (bad argument), CVGRAM_EFOLDS (Definition 1),
+ * CVGRAM_ENOTSCALABLE (a scale flag is set and some |T_p| - ddof < 1),
+ * CVGRAM_ENOMEM, CVGRAM_EDEVICE.  *out is NULL on any error.
+ */
+cvgram_status cvgram_create(const void* X, const void* Y, const int32_t* fold_id,
+                            int64_t N, int64_t K, int64_t M, cvgram_dtype dtype,
+                            int center_x, int scale_x, int center_y, int scale_y,
+                            int ddof, cvgram_mode mode, void* stream, cvgram_t* out);
+
+/* Number of folds P of the handle's partitioning (host out-parameter). */
+cvgram_status cvgram_num_folds(cvgram_t h, int32_t* P);
+
+/* Copy of the fold bookkeeping of Algorithm 1 as a stable counting sort:
+ * perm[N] (int32) lists the rows of fold 0, then fold 1, ..., each in
+ * ascending row order; offsets[P+1] (int64) delimits fold p as
+ * perm[offsets[p] .. offsets[p+1]).  Device pointers, caller-allocated; either
+ * may be NULL.  Enqueued on the handle's stream. */
+cvgram_status cvgram_partition(cvgram_t h, int32_t* perm, int64_t* offsets);
+
+/*
+ * cvgram_fold -- training products of fold p (0 <= p < P) for the
+ * combination given at create time (Algorithm 7 steps 9, 11-16, 18, 20-27,
+ * with Table 1 for the other combinations).
+ * out_XtX: K x K, the full symmetric matrix (lower triangle mirrored from the
+ * upper, so it is bit-symmetric).  out_XtY: K x M.  Element type: double in
+ * CVGRAM_MODE_FP64, float in the mixed modes.  Either output may be NULL to
+ * skip it.  Caller-allocated device memory; enqueued on the handle's stream.
+ * Errors: CVGRAM_ERANGE for a bad p.
+ */
+cvgram_status cvgram_fold(cvgram_t h, int32_t p, void* out_XtX, void* out_XtY);
+
+/* As cvgram_fold, for any of the 16 combinations (flags 0 or 1).  Returns
+ * CVGRAM_ENOTSCALABLE if a scale flag is set on a partitioning that is not
+ * scalable for the handle's ddof.  Equivalent combinations (Lemma 9) return
+ * identical bits. */
+cvgram_status cvgram_fold_combo(cvgram_t h, int32_t p, int center_x, int scale_x,
+                                int center_y, int scale_y, void* out_XtX, void* out_XtY);
+
+/* All distinct products of folds p_begin <= p < p_end in one launch:
+ * out_XtX[(p - p_begin)][c][K][K] for the 4 X^T X classes and
+ * out_XtY[(p - p_begin)][c][K][M] for the 8 X^T Y classes (class numbering
+ * above).  Either pointer may be NULL.  With a partitioning that is not
+ * scalable, only the unscaled classes are written (classes 0 and 2 of X^T X,
+ * 0 and 4 of X^T Y; the others are left untouched).  Element type as in
+ * cvgram_fold. */
+cvgram_status cvgram_folds_all(cvgram_t h, int32_t p_begin, int32_t p_end,
+                               void* out_XtX, void* out_XtY);
+
+/* Training-partition statistics of fold p in FP64: column means
+ * (Definition 2) and deviations with divisor |T_p| - ddof (Definition 4);
+ * a column constant over T_p reports deviation 1 (Algorithm 7 step 24).
+ * Device pointers of length K, K, M, M; any may be NULL.  If the partition is
+ * not scalable, deviations of folds with |T_p| - ddof < 1 are NaN. */
+cvgram_status cvgram_fold_stats(cvgram_t h, int32_t p, double* mean_x, double* std_x,
+                                double* mean_y, double* std_y);
+
+/* Per-stage device timing.  When enabled (process-wide; off by default),
+ * cvgram_create records HIP events on its stream around its stages and
+ * cvgram_stage_times() returns their durations in milliseconds, waiting for
+ * them if needed: ms[0] fold bookkeeping (includes the two host waits),
+ * ms[1] column statistics, ms[2] grouped Gram launch, ms[3] slab reduction.
+ * n is the capacity of ms (at most 4 entries are written).  Returns
+ * CVGRAM_EINVAL if the handle was created with timing off. */
+cvgram_status cvgram_set_stage_timing(int on);
+cvgram_status cvgram_stage_times(cvgram_t h, double* ms, int32_t n);
+
+/* Device workspace released by cvgram_destroy() is kept in a per-device
+ * cache and reused by later handles of similar size (bounded to 32 GiB per
+ * device).  cvgram_trim_cache() frees every cached block of the current
+ * device. */
+cvgram_status cvgram_trim_cache(void);
+
+/* Change the stream used by later calls on this handle. */
+cvgram_status cvgram_set_stream(cvgram_t h, void* stream);
+
+/* Wait for the handle's outstanding work, then free it (NULL is a no-op). */
+cvgram_status cvgram_destroy(cvgram_t h);
+
+/* Static description of a status code. */
+const char* cvgram_status_string(cvgram_status s);
+
+/* Details of the last error raised on the calling thread ("" if none). */
+const char* cvgram_last_error_message(void);
+
+/* Library version as major*10000 + minor*100 + patch. */
+int32_t cvgram_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CVGRAM_H */

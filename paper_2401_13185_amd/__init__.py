@@ -1,0 +1,333 @@
+"""Python binding of libcvgram: fold-independent cross-validation Gram
+products on MI355X (gfx950).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of ``libcvgram.so``; torch supplies device memory and the stream.
+The functions mirror the C ABI of ``include/cvgram.h`` (same names, same
+meaning); tensors are passed as device pointers.  There is no CPU path: if the
+library is missing, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+__all__ = [
+    "CVGramError", "lib_path", "load", "exported_symbols", "header_symbols",
+    "cvgram_create", "cvgram_num_folds", "cvgram_partition", "cvgram_fold",
+    "cvgram_fold_combo", "cvgram_folds_all", "cvgram_fold_stats", "cvgram_set_stream",
+    "cvgram_destroy", "cvgram_status_string", "cvgram_last_error_message", "cvgram_version",
+    "cvgram_set_stage_timing", "cvgram_stage_times", "cvgram_trim_cache",
+    "CVGram", "MODES", "XTX_CLASSES", "XTY_CLASSES",
+]
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+_ROOT = os.path.dirname(_PKG)
+HEADER = os.path.join(_ROOT, "include", "cvgram.h")
+MODES = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+XTX_CLASSES = 4
+XTY_CLASSES = 8
+
+STATUS = {0: "CVGRAM_OK", 1: "CVGRAM_EINVAL", 2: "CVGRAM_EFOLDS", 3: "CVGRAM_ENOTSCALABLE",
+          4: "CVGRAM_ENOMEM", 5: "CVGRAM_EDEVICE", 6: "CVGRAM_ERANGE"}
+
+
+class CVGramError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+        super().__init__(f"{self.name}: {message}")
+
+
+def lib_path() -> str:
+    return os.path.join(_PKG, "libcvgram.so")
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+_int = ctypes.c_int
+
+_SIGS = {
+    "cvgram_create": (_int, [_vp, _vp, _vp, _i64, _i64, _i64, _int, _int, _int, _int, _int, _int,
+                             _int, _vp, ctypes.POINTER(_vp)]),
+    "cvgram_num_folds": (_int, [_vp, ctypes.POINTER(_i32)]),
+    "cvgram_partition": (_int, [_vp, _vp, _vp]),
+    "cvgram_fold": (_int, [_vp, _i32, _vp, _vp]),
+    "cvgram_fold_combo": (_int, [_vp, _i32, _int, _int, _int, _int, _vp, _vp]),
+    "cvgram_folds_all": (_int, [_vp, _i32, _i32, _vp, _vp]),
+    "cvgram_fold_stats": (_int, [_vp, _i32, _vp, _vp, _vp, _vp]),
+    "cvgram_set_stream": (_int, [_vp, _vp]),
+    "cvgram_destroy": (_int, [_vp]),
+    "cvgram_status_string": (ctypes.c_char_p, [_int]),
+    "cvgram_last_error_message": (ctypes.c_char_p, []),
+    "cvgram_version": (_i32, []),
+    "cvgram_set_stage_timing": (_int, [_int]),
+    "cvgram_stage_times": (_int, [_vp, ctypes.POINTER(ctypes.c_double), _i32]),
+    "cvgram_trim_cache": (_int, []),
+}
+
+
+def load():
+    """Load libcvgram.so (built by ``python -m paper_2401_13185_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = lib_path()
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2401_13185_amd.build`")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def header_symbols() -> list[str]:
+    """Function names declared in include/cvgram.h."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(cvgram_[a-z_0-9]+)\s*\(", text)))
+
+
+def exported_symbols() -> list[str]:
+    lib = load()
+    return [s for s in header_symbols() if hasattr(lib, s)]
+
+
+def _check(st: int):
+    if st != 0:
+        msg = load().cvgram_last_error_message().decode()
+        raise CVGramError(st, msg or load().cvgram_status_string(st).decode())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t, what: str, dtype=None, numel=None):
+    if t is None:
+        return None
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{what} must be a CUDA (HIP) tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous (row-major)")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{what} must have dtype {dtype}, got {t.dtype}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{what} must have {numel} elements, got {t.numel()}")
+    return t.data_ptr()
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+class Handle:
+    """Owns a cvgram_t; keeps the input tensors alive while work may use them."""
+
+    def __init__(self, ptr, X, Y, fold_id, N, K, M, mode, stream):
+        self.ptr = ptr
+        self._keep = (X, Y, fold_id)
+        self.N, self.K, self.M = N, K, M
+        self.mode = mode
+        self.stream = stream
+        self.out_dtype = _torch().float64 if mode == "fp64" else _torch().float32
+        self.device = X.device
+
+    def __del__(self):
+        try:
+            if self.ptr:
+                cvgram_destroy(self)
+        except Exception:
+            pass
+
+
+def cvgram_create(X, Y, fold_id, center_x=0, scale_x=0, center_y=0, scale_y=0, ddof=1,
+                  mode="fp64", stream=None) -> Handle:
+    torch = _torch()
+    lib = load()
+    if X.dim() != 2:
+        raise ValueError("X must be N x K")
+    N, K = X.shape
+    if Y is None:
+        M = 0
+    else:
+        if Y.dim() != 2 or Y.shape[0] != N:
+            raise ValueError("Y must be N x M")
+        M = Y.shape[1]
+        if Y.dtype != X.dtype:
+            raise TypeError("X and Y must have the same dtype")
+    if X.dtype == torch.float64:
+        dt = 1
+    elif X.dtype == torch.float32:
+        dt = 0
+    else:
+        raise TypeError("X must be float32 or float64")
+    if mode not in MODES:
+        raise ValueError(f"mode must be one of {sorted(MODES)}")
+    xp = _ptr(X, "X")
+    yp = _ptr(Y, "Y") if M > 0 else None
+    fp = _ptr(fold_id, "fold_id", torch.int32, N)
+    s = _stream_ptr(stream)
+    out = _vp()
+    _check(lib.cvgram_create(xp, yp, fp, N, K, M, dt, int(center_x), int(scale_x), int(center_y),
+                             int(scale_y), int(ddof), MODES[mode], s, ctypes.byref(out)))
+    return Handle(out.value, X, Y, fold_id, N, K, M, mode, s)
+
+
+def cvgram_num_folds(h: Handle) -> int:
+    P = _i32()
+    _check(load().cvgram_num_folds(h.ptr, ctypes.byref(P)))
+    return P.value
+
+
+def cvgram_partition(h: Handle, perm=None, offsets=None):
+    torch = _torch()
+    P = cvgram_num_folds(h)
+    if perm is None:
+        perm = torch.empty(h.N, dtype=torch.int32, device=h.device)
+    if offsets is None:
+        offsets = torch.empty(P + 1, dtype=torch.int64, device=h.device)
+    _check(load().cvgram_partition(h.ptr, _ptr(perm, "perm", torch.int32, h.N),
+                                   _ptr(offsets, "offsets", torch.int64, P + 1)))
+    return perm, offsets
+
+
+def _outs(h: Handle, out_XtX, out_XtY, lead=()):
+    torch = _torch()
+    if out_XtX is None:
+        out_XtX = torch.empty(*lead, h.K, h.K, dtype=h.out_dtype, device=h.device)
+    if out_XtY is None and h.M > 0:
+        out_XtY = torch.empty(*lead, h.K, h.M, dtype=h.out_dtype, device=h.device)
+    n_lead = 1
+    for v in lead:
+        n_lead *= v
+    xp = _ptr(out_XtX, "out_XtX", h.out_dtype, n_lead * h.K * h.K) if out_XtX is not False else None
+    yp = (_ptr(out_XtY, "out_XtY", h.out_dtype, n_lead * h.K * h.M)
+          if (out_XtY is not None and out_XtY is not False) else None)
+    return out_XtX, out_XtY, xp, yp
+
+
+def cvgram_fold(h: Handle, p: int, out_XtX=None, out_XtY=None):
+    out_XtX, out_XtY, xp, yp = _outs(h, out_XtX, out_XtY)
+    _check(load().cvgram_fold(h.ptr, int(p), xp, yp))
+    return out_XtX, out_XtY
+
+
+def cvgram_fold_combo(h: Handle, p: int, center_x, scale_x, center_y, scale_y, out_XtX=None,
+                      out_XtY=None):
+    out_XtX, out_XtY, xp, yp = _outs(h, out_XtX, out_XtY)
+    _check(load().cvgram_fold_combo(h.ptr, int(p), int(center_x), int(scale_x), int(center_y),
+                                    int(scale_y), xp, yp))
+    return out_XtX, out_XtY
+
+
+def cvgram_folds_all(h: Handle, p_begin: int, p_end: int, out_XtX=None, out_XtY=None):
+    torch = _torch()
+    n = int(p_end) - int(p_begin)
+    if out_XtX is None:
+        out_XtX = torch.empty(n, XTX_CLASSES, h.K, h.K, dtype=h.out_dtype, device=h.device)
+    if out_XtY is None and h.M > 0:
+        out_XtY = torch.empty(n, XTY_CLASSES, h.K, h.M, dtype=h.out_dtype, device=h.device)
+    xp = _ptr(out_XtX, "out_XtX", h.out_dtype, n * XTX_CLASSES * h.K * h.K) if out_XtX is not False else None
+    yp = (_ptr(out_XtY, "out_XtY", h.out_dtype, n * XTY_CLASSES * h.K * h.M)
+          if (out_XtY is not None and out_XtY is not False) else None)
+    _check(load().cvgram_folds_all(h.ptr, int(p_begin), int(p_end), xp, yp))
+    return out_XtX, out_XtY
+
+
+def cvgram_fold_stats(h: Handle, p: int):
+    torch = _torch()
+    f64 = dict(dtype=torch.float64, device=h.device)
+    mx, sx = torch.empty(h.K, **f64), torch.empty(h.K, **f64)
+    my, sy = torch.empty(h.M, **f64), torch.empty(h.M, **f64)
+    _check(load().cvgram_fold_stats(h.ptr, int(p), mx.data_ptr(), sx.data_ptr(),
+                                    my.data_ptr() if h.M else None,
+                                    sy.data_ptr() if h.M else None))
+    return mx, sx, my, sy
+
+
+def cvgram_set_stream(h: Handle, stream):
+    s = _stream_ptr(stream)
+    _check(load().cvgram_set_stream(h.ptr, s))
+    h.stream = s
+
+
+def cvgram_destroy(h: Handle):
+    if h.ptr:
+        ptr, h.ptr = h.ptr, None
+        _check(load().cvgram_destroy(ptr))
+        h._keep = None
+
+
+def cvgram_set_stage_timing(on: bool):
+    _check(load().cvgram_set_stage_timing(1 if on else 0))
+
+
+STAGES = ("partition", "stats", "gram", "reduce")
+
+
+def cvgram_stage_times(h: Handle) -> dict:
+    """Stage durations (ms) recorded by cvgram_create with timing enabled."""
+    ms = (ctypes.c_double * 4)()
+    _check(load().cvgram_stage_times(h.ptr, ms, 4))
+    return dict(zip(STAGES, list(ms)))
+
+
+def cvgram_trim_cache():
+    _check(load().cvgram_trim_cache())
+
+
+def cvgram_status_string(status: int) -> str:
+    return load().cvgram_status_string(int(status)).decode()
+
+
+def cvgram_last_error_message() -> str:
+    return load().cvgram_last_error_message().decode()
+
+
+def cvgram_version() -> int:
+    return int(load().cvgram_version())
+
+
+class CVGram:
+    """Convenience wrapper: ``with CVGram(X, Y, folds, center_x=1, ...) as cv:
+    XtX, XtY = cv.fold(p)``."""
+
+    def __init__(self, X, Y, fold_id, **kw):
+        self.h = cvgram_create(X, Y, fold_id, **kw)
+        self.P = cvgram_num_folds(self.h)
+
+    def fold(self, p, **kw):
+        return cvgram_fold(self.h, p, **kw)
+
+    def fold_combo(self, p, cx, sx, cy, sy, **kw):
+        return cvgram_fold_combo(self.h, p, cx, sx, cy, sy, **kw)
+
+    def folds_all(self, p_begin=0, p_end=None, **kw):
+        return cvgram_folds_all(self.h, p_begin, self.P if p_end is None else p_end, **kw)
+
+    def stats(self, p):
+        return cvgram_fold_stats(self.h, p)
+
+    def partition(self):
+        return cvgram_partition(self.h)
+
+    def close(self):
+        cvgram_destroy(self.h)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

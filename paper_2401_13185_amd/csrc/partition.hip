@@ -1,0 +1,230 @@
+// Fold bookkeeping on the device: Algorithm 1 (validation partitions) as a
+// stable sort of the rows by fold label.  Rows inside a fold stay in
+// ascending order, which is the order in which Algorithm 1 visits them, so
+// the output is unique and compared bit for bit.
+//
+// The sort is least-significant-digit radix with 8-bit digits and only as
+// many passes as the largest label needs (one pass for P <= 256).  Each pass
+// is: per-tile digit histogram -> exclusive scan of the digit-major
+// histogram -> stable scatter, where ranks inside a tile come from wave-wide
+// ballots (no atomics on the output, so the result is deterministic).
+#include <climits>
+
+#include "internal.h"
+
+namespace cvg {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kItems = 8;
+constexpr int kTileElems = kThreads * kItems;  // rows per radix tile
+constexpr int kWaves = kThreads / 64;
+
+__global__ void fill_i32_kernel(int32_t* p, int64_t n, int32_t v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = v;
+}
+
+__device__ inline int wave_min(int v) {
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ inline int wave_max(int v) {
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+__global__ __launch_bounds__(kThreads) void label_minmax_kernel(const int32_t* __restrict__ f,
+                                                                int64_t n, int32_t* info) {
+  int lo = INT_MAX, hi = INT_MIN;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) {
+    int v = f[i];
+    lo = min(lo, v);
+    hi = max(hi, v);
+  }
+  lo = wave_min(lo);
+  hi = wave_max(hi);
+  __shared__ int slo[kWaves], shi[kWaves];
+  int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    slo[w] = lo;
+    shi[w] = hi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < kWaves; ++k) {
+      lo = min(lo, slo[k]);
+      hi = max(hi, shi[k]);
+    }
+    atomicMin(&info[0], lo);
+    atomicMax(&info[1], hi);
+  }
+}
+
+// hist is digit-major: hist[d * tiles + t]
+__global__ __launch_bounds__(kThreads) void radix_hist_kernel(const int32_t* __restrict__ keys,
+                                                              int64_t n, int shift,
+                                                              int32_t* __restrict__ hist,
+                                                              int64_t tiles) {
+  __shared__ int h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kTileElems;
+#pragma unroll
+  for (int it = 0; it < kItems; ++it) {
+    int64_t idx = base + it * kThreads + threadIdx.x;
+    if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & 255], 1);
+  }
+  __syncthreads();
+  hist[(int64_t)threadIdx.x * tiles + blockIdx.x] = h[threadIdx.x];
+}
+
+// Exclusive scan of n int32 counts (sum < 2^31) by one workgroup of 1024.
+__global__ __launch_bounds__(1024) void scan_exclusive_kernel(int32_t* a, int64_t n) {
+  __shared__ int32_t part[1024];
+  const int t = threadIdx.x;
+  const int64_t per = (n + 1023) / 1024;
+  const int64_t b = t * per;
+  const int64_t e = b + per < n ? b + per : n;
+  int32_t s = 0;
+  for (int64_t i = b; i < e; ++i) s += a[i];
+  part[t] = s;
+  __syncthreads();
+  // Hillis-Steele inclusive scan of the 1024 partial sums
+  for (int o = 1; o < 1024; o <<= 1) {
+    int32_t v = t >= o ? part[t - o] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int32_t run = t ? part[t - 1] : 0;
+  for (int64_t i = b; i < e; ++i) {
+    int32_t v = a[i];
+    a[i] = run;
+    run += v;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void radix_scatter_kernel(
+    const int32_t* __restrict__ keys_in, const int32_t* __restrict__ vals_in,
+    int32_t* __restrict__ keys_out, int32_t* __restrict__ vals_out, int64_t n, int shift,
+    const int32_t* __restrict__ scanned, int64_t tiles) {
+  __shared__ int run[256];
+  __shared__ int wcnt[kWaves][256];
+  const int t = threadIdx.x;
+  const int lane = t & 63;
+  const int w = t >> 6;
+  run[t] = scanned[(int64_t)t * tiles + blockIdx.x];
+#pragma unroll
+  for (int k = 0; k < kWaves; ++k) wcnt[k][t] = 0;
+  __syncthreads();
+  const unsigned long long lt = (lane == 0) ? 0ull : ((~0ull) >> (64 - lane));
+  const int64_t base = (int64_t)blockIdx.x * kTileElems;
+  for (int it = 0; it < kItems; ++it) {
+    const int64_t idx = base + it * kThreads + t;
+    const bool valid = idx < n;
+    const int32_t key = valid ? keys_in[idx] : 0;
+    const int32_t val = valid ? (vals_in ? vals_in[idx] : (int32_t)idx) : 0;
+    const int d = (key >> shift) & 255;
+    unsigned long long peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (d >> b) & 1;
+      const unsigned long long bal = __ballot(bit);
+      peers &= bit ? bal : ~bal;
+    }
+    const int rank = __popcll(peers & lt);
+    if (valid && rank == 0) wcnt[w][d] = __popcll(peers);
+    __syncthreads();
+    if (valid) {
+      int pos = run[d] + rank;
+      for (int k = 0; k < w; ++k) pos += wcnt[k][d];
+      keys_out[pos] = key;
+      vals_out[pos] = val;
+    }
+    __syncthreads();
+    int add = 0;
+#pragma unroll
+    for (int k = 0; k < kWaves; ++k) {
+      add += wcnt[k][t];
+      wcnt[k][t] = 0;
+    }
+    run[t] += add;
+    __syncthreads();
+  }
+}
+
+// offsets[p] = first sorted position whose label is >= p; flag[0] |= 1 when
+// some label in [0, P) has no row.
+__global__ void fold_offsets_kernel(const int32_t* __restrict__ sk, int64_t n, int32_t P,
+                                    int64_t* __restrict__ offsets, int32_t* flag) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t k = sk[i];
+  const int32_t prev = i ? sk[i - 1] : -1;
+  if (k != prev) {
+    for (int32_t l = prev + 1; l <= k && l <= P; ++l) offsets[l] = i;
+    if (k - prev > 1) atomicOr(flag, 1);
+  }
+  if (i == n - 1) {
+    for (int32_t l = k + 1; l <= P; ++l) offsets[l] = n;
+    if (k != P - 1) atomicOr(flag, 1);
+  }
+}
+
+}  // namespace
+
+void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
+  if (n <= 0) return;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  fill_i32_kernel<<<(unsigned)blocks, 256, 0, s>>>(p, n, v);
+  CVG_LAUNCH_CHECK();
+}
+
+void launch_label_minmax(const int32_t* fold, int64_t N, int32_t* info, hipStream_t s) {
+  int64_t blocks = (N + kThreads - 1) / kThreads;
+  if (blocks > 2048) blocks = 2048;
+  label_minmax_kernel<<<(unsigned)blocks, kThreads, 0, s>>>(fold, N, info);
+  CVG_LAUNCH_CHECK();
+}
+
+int64_t radix_hist_entries(int64_t N) { return 256 * ((N + kTileElems - 1) / kTileElems); }
+
+void radix_partition(const int32_t* fold, int64_t N, int bits, int32_t* keys_a, int32_t* keys_b,
+                     int32_t* perm, int32_t* perm_tmp, int32_t* hist, const int32_t** sorted_keys,
+                     hipStream_t s) {
+  const int64_t tiles = (N + kTileElems - 1) / kTileElems;
+  int passes = (bits + 7) / 8;
+  if (passes < 1) passes = 1;
+  // ping-pong so that the last pass writes the payload into `perm`
+  const int32_t* kin = fold;
+  const int32_t* vin = nullptr;  // identity payload on the first pass
+  for (int pass = 0; pass < passes; ++pass) {
+    int32_t* kout = (pass & 1) ? keys_b : keys_a;
+    int32_t* vout = ((passes - 1 - pass) & 1) ? perm_tmp : perm;
+    const int shift = 8 * pass;
+    radix_hist_kernel<<<(unsigned)tiles, kThreads, 0, s>>>(kin, N, shift, hist, tiles);
+    CVG_LAUNCH_CHECK();
+    scan_exclusive_kernel<<<1, 1024, 0, s>>>(hist, 256 * tiles);
+    CVG_LAUNCH_CHECK();
+    radix_scatter_kernel<<<(unsigned)tiles, kThreads, 0, s>>>(kin, vin, kout, vout, N, shift,
+                                                              hist, tiles);
+    CVG_LAUNCH_CHECK();
+    kin = kout;
+    vin = vout;
+  }
+  *sorted_keys = kin;
+}
+
+void launch_fold_offsets(const int32_t* sorted_keys, int64_t N, int32_t P, int64_t* offsets,
+                         int32_t* flag, hipStream_t s) {
+  fold_offsets_kernel<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(sorted_keys, N, P, offsets,
+                                                                   flag);
+  CVG_LAUNCH_CHECK();
+}
+
+}  // namespace cvg
