@@ -24,6 +24,9 @@ sys.path.insert(0, ROOT)
 
 PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}  # TFLOP/s dense MFMA, MI355X
 HBM_PEAK = 8000.0  # GB/s
+# stated relative Frobenius error bounds of the mixed modes (per fold, class
+# and output, against FP64)
+MIXED_BOUND = {"fp32": 1e-6, "bf16x3": 2e-5}
 
 
 def f_alg(n, k, m):
@@ -40,6 +43,9 @@ def parse():
     ap.add_argument("--mode", default="fp64", choices=["fp64", "fp32", "bf16x3"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline legs")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the mixed-vs-FP64 block on the precision-stress workload")
+    ap.add_argument("--mixed-steps", type=int, default=5)
     return ap.parse_args()
 
 
@@ -76,6 +82,48 @@ def cpu_legs(X, Y, fold, P, gpu_xx, gpu_xy, budget_s):
     return cpu, fast, float(max(errs))
 
 
+def measure(cv, torch, Xd, Yd, fd, P, K, M, mode, steps, warmup):
+    """Time `steps` whole steps (after `warmup`): create + all folds x 12
+    classes + destroy.  Stage times come from HIP events on the same stream."""
+    odt = torch.float64 if mode == "fp64" else torch.float32
+    dev = Xd.device
+    xx = torch.empty(P, 4, K, K, dtype=odt, device=dev)
+    xy = torch.empty(P, 8, K, M, dtype=odt, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step(timing=False):
+        h = cv.cvgram_create(Xd, Yd, fd, 1, 1, 1, 1, ddof=1, mode=mode, stream=stream)
+        if timing:
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+        cv.cvgram_folds_all(h, 0, P, xx, xy)
+        st = None
+        if timing:
+            e1.record(stream)
+            st = cv.cvgram_stage_times(h)
+        cv.cvgram_destroy(h)
+        if timing:
+            st["correct"] = e0.elapsed_time(e1)
+        return st
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    cv.cvgram_set_stage_timing(True)
+    stages = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        stages.append(step(timing=True))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    cv.cvgram_set_stage_timing(False)
+    ms = (t1 - t0) * 1e3 / steps
+    stage_ms = {k: float(np.mean([s[k] for s in stages])) for k in stages[0]}
+    return ms, stage_ms, xx, xy
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -90,55 +138,20 @@ def main():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(1)
     dev = torch.device("cuda:0")
-    wid = 2
-    shape, (X, Y, fold) = G.workload(wid)
+    shape, (X, Y, fold) = G.workload(2)
     N, K, M, P = shape.n, shape.k, shape.m, shape.p
     print(f"[bench] workload {shape.name} generated", file=sys.stderr, flush=True)
     Xd = torch.from_numpy(X).to(dev)
     Yd = torch.from_numpy(Y).to(dev)
     fd = torch.from_numpy(fold).to(dev)
-    odt = torch.float64 if args.mode == "fp64" else torch.float32
-    xx = torch.empty(P, 4, K, K, dtype=odt, device=dev)
-    xy = torch.empty(P, 8, K, M, dtype=odt, device=dev)
-    stream = torch.cuda.current_stream()
-
-    def step(timing=False):
-        h = cv.cvgram_create(Xd, Yd, fd, 1, 1, 1, 1, ddof=1, mode=args.mode, stream=stream)
-        if timing:
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-        cv.cvgram_folds_all(h, 0, P, xx, xy)
-        if timing:
-            e1.record(stream)
-            st = cv.cvgram_stage_times(h)
-            torch.cuda.synchronize()
-            st["correct"] = e0.elapsed_time(e1)
-        cv.cvgram_destroy(h)
-        return st if timing else None
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    print("[bench] warmup done", file=sys.stderr, flush=True)
-
-    # timed region: exactly `steps` steps
-    cv.cvgram_set_stage_timing(True)
-    stages = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        stages.append(step(timing=True))
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    cv.cvgram_set_stage_timing(False)
-    ms = (t1 - t0) * 1e3 / args.steps
-    print("[bench] timed steps done", file=sys.stderr, flush=True)
+    ms, stage_ms, xx, xy = measure(cv, torch, Xd, Yd, fd, P, K, M, args.mode, args.steps,
+                                   args.warmup)
+    print("[bench] headline timed steps done", file=sys.stderr, flush=True)
 
     sets = P * 12
-    stage_ms = {k: float(np.mean([s[k] for s in stages])) for k in stages[0]}
     flops = f_alg(N, K, M)
     gram_tflops = flops / (stage_ms["gram"] * 1e-3) / 1e12
+    kname = {"fp64": "gram_f64_kernel", "fp32": "gram_f32_kernel", "bf16x3": "gram_bf16x3_kernel"}
     out = {
         "metric": "per-fold train Gram sets/s (12 distinct centering/scaling classes per fold)",
         "value": sets / (ms * 1e-3),
@@ -150,14 +163,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.mode == "fp64" else ("f32" if args.mode == "fp32" else "bf16x3+f32acc"),
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3+f32acc"}[args.mode],
         "data": "synthetic",
         "config": {"workload": shape.name, "N": N, "K": K, "M": M, "P": P, "folds": "Dirichlet(2)",
                    "mode": args.mode, "classes_per_fold": 12, "ddof": 1},
         "tflops_alg": flops / (ms * 1e-3) / 1e12,
         "stage_ms": stage_ms,
-        "roofline": {"bound": "mfma", "kernel": "gram_f64_kernel" if args.mode == "fp64" else args.mode,
-                     "achieved": gram_tflops, "peak": PEAK[args.mode], "unit": "TFLOP/s",
+        "roofline": {"bound": "mfma", "kernel": kname[args.mode], "achieved": gram_tflops,
+                     "peak": PEAK[args.mode], "unit": "TFLOP/s",
                      "frac": gram_tflops / PEAK[args.mode], "traffic": None},
     }
     if not args.no_cpu:
@@ -169,7 +182,53 @@ def main():
         if fast:
             out["cpu_fast"] = fast
         out["max_rel_err_vs_oracle_fold0"] = err
+    del xx, xy
+    if not args.no_mixed:
+        out["mixed"] = mixed_block(cv, torch, G, dev, args)
     print(json.dumps(out))
+
+
+def mixed_block(cv, torch, G, dev, args):
+    """Mixed precision vs plain FP64 on the precision-stress workload (FP32
+    input, column means in [1e3, 1e4]): sets/s and Gram TFLOP/s per mode, and
+    each mixed mode's worst relative Frobenius error over all folds and
+    classes against the FP64 GPU form (itself within 1e-10 of the oracle)."""
+    shape, (X, Y, fold) = G.workload(3)
+    N, K, M, P = shape.n, shape.k, shape.m, shape.p
+    print(f"[bench] workload {shape.name} generated", file=sys.stderr, flush=True)
+    Xd = torch.from_numpy(X).to(dev)
+    Yd = torch.from_numpy(Y).to(dev)
+    fd = torch.from_numpy(fold).to(dev)
+    del X, Y
+    flops = f_alg(N, K, M)
+    res = {"workload": shape.name, "classes_per_fold": 12, "modes": {}}
+    ref = None
+    for mode in ("fp64", "fp32", "bf16x3"):
+        ms, st, xx, xy = measure(cv, torch, Xd, Yd, fd, P, K, M, mode, args.mixed_steps, 1)
+        g = flops / (st["gram"] * 1e-3) / 1e12
+        r = {"sets_per_s": P * 12 / (ms * 1e-3), "ms_per_step": ms, "stage_ms": st,
+             "gram_tflops_alg": g, "gram_frac_of_peak": g / PEAK[mode], "peak_tflops": PEAK[mode]}
+        if mode == "fp64":
+            ref = (xx, xy)
+        else:
+            worst = 0.0
+            for q in range(P):
+                for c in range(4):
+                    a, b = xx[q, c].double(), ref[0][q, c]
+                    worst = max(worst, (torch.linalg.norm(a - b) / torch.linalg.norm(b)).item())
+                for c in range(8):
+                    a, b = xy[q, c].double(), ref[1][q, c]
+                    worst = max(worst, (torch.linalg.norm(a - b) / torch.linalg.norm(b)).item())
+            r["max_rel_err_vs_fp64"] = worst
+            r["stated_bound"] = MIXED_BOUND[mode]
+            r["within_bound"] = worst <= MIXED_BOUND[mode]
+            del xx, xy
+        res["modes"][mode] = r
+        print(f"[bench] mixed-block mode {mode} done", file=sys.stderr, flush=True)
+    f64 = res["modes"]["fp64"]["ms_per_step"]
+    for mode in ("fp32", "bf16x3"):
+        res["modes"][mode]["speedup_vs_fp64"] = f64 / res["modes"][mode]["ms_per_step"]
+    return res
 
 
 if __name__ == "__main__":

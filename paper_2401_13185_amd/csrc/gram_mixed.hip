@@ -203,6 +203,10 @@ __global__ __launch_bounds__(kThreads) void gram_bf16x3_kernel(
   const int wm = wave >> 1, wn = wave & 1;
   const bool active = !(diag && wm > wn);
 
+  // A diagonal tile whose columns all lie inside X has B == A: load it once.
+  // (A diagonal tile that crosses column K also holds Y columns in B.)
+  const bool same = diag && j0 + BM <= K;
+
   // loader: one column, RPT consecutive rows of the stage
   const int lcol = t % BM;
   const int lrow = (t / BM) * RPT;
@@ -219,7 +223,7 @@ __global__ __launch_bounds__(kThreads) void gram_bf16x3_kernel(
       const bool vr = rr < w.r1;
       const int64_t n = vr ? (int64_t)perm[rr] : 0;
       ra[u] = (vr && va) ? zload32(X, Y, K, M, n, gi, pa) : 0.f;
-      rb[u] = (vr && vb && !diag) ? zload32(X, Y, K, M, n, gj, pb) : 0.f;
+      rb[u] = (vr && vb && !same) ? zload32(X, Y, K, M, n, gj, pb) : 0.f;
     }
   };
   auto store_stage = [&]() {
@@ -239,14 +243,14 @@ __global__ __launch_bounds__(kThreads) void gram_bf16x3_kernel(
       const int off = lcol * LDK + lrow + h * 8;
       *(bf16x8_t*)&Ahi[off] = xh;
       *(bf16x8_t*)&Alo[off] = xl;
-      if (!diag) {
+      if (!same) {
         *(bf16x8_t*)&Bhi[off] = yh;
         *(bf16x8_t*)&Blo[off] = yl;
       }
     }
   };
-  const __bf16* Bh = diag ? Ahi : Bhi;
-  const __bf16* Bl = diag ? Alo : Blo;
+  const __bf16* Bh = same ? Ahi : Bhi;
+  const __bf16* Bl = same ? Alo : Blo;
 
   float4_t acc[NB][NB];
   double a64[NB][NB][4];
