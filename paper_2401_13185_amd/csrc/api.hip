@@ -117,10 +117,15 @@ void free_all(cvgram_handle* h) {
     }
 }
 
+// Asynchronous upload of a host plan; the handle keeps the host bytes alive
+// until it is destroyed.
 template <typename T>
-void upload(T* dst, const std::vector<T>& src, hipStream_t s) {
+void upload(cvgram_handle* h, T* dst, const std::vector<T>& src, hipStream_t s) {
   if (src.empty()) return;
-  CVG_HIP(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  const char* b = (const char*)src.data();
+  h->host_plans.emplace_back(b, b + src.size() * sizeof(T));
+  CVG_HIP(hipMemcpyAsync(dst, h->host_plans.back().data(), src.size() * sizeof(T),
+                         hipMemcpyHostToDevice, s));
 }
 
 int bit_length(uint32_t v) {
@@ -132,7 +137,7 @@ int bit_length(uint32_t v) {
   return b;
 }
 
-constexpr int64_t kStatChunkRows = 2048;
+constexpr int64_t kStatChunkRows = 1024;  // multiple of kPanelRows
 constexpr int64_t kGramTargetItems = 2048;
 constexpr int64_t kGramMinRows = 512;
 
@@ -189,35 +194,55 @@ cvgram_status build(cvgram_handle* h, const void* X, const void* Y, const int32_
                 "scaling needs |T_p| - ddof >= 1 for every fold (Definition 6)");
 
   // ---- plans --------------------------------------------------------------
-  std::vector<RowChunk> chunks;
+  // packed rows: each fold padded to whole panels
+  const int64_t PR = kPanelRows;
+  std::vector<int64_t> poff(P + 1, 0);
+  for (int64_t p = 0; p < P; ++p) {
+    const int64_t n = h->h_offsets[p + 1] - h->h_offsets[p];
+    poff[p + 1] = poff[p] + (n + PR - 1) / PR * PR;
+  }
+  h->Np = poff[P];
+  // packed columns: X, zeros to Kp, Y, zeros to Wp
+  h->Kp = (K + kGramTile - 1) / kGramTile * kGramTile;
+  const bool xy_diag = M > 0 && M <= kYDiagCols;
+  h->Mp = M == 0 ? 0 : (xy_diag ? kYDiagCols : (M + kGramTile - 1) / kGramTile * kGramTile);
+  h->Wp = h->Kp + h->Mp;
+
+  std::vector<PackChunk> chunks;
   std::vector<int32_t> chunk_begin(P + 1, 0);
   for (int64_t p = 0; p < P; ++p) {
     chunk_begin[p] = (int32_t)chunks.size();
-    for (int64_t r = h->h_offsets[p]; r < h->h_offsets[p + 1]; r += kStatChunkRows)
-      chunks.push_back({r, std::min(r + kStatChunkRows, h->h_offsets[p + 1])});
+    for (int64_t d = poff[p]; d < poff[p + 1]; d += kStatChunkRows)
+      chunks.push_back({d, std::min(d + kStatChunkRows, poff[p + 1]),
+                        h->h_offsets[p] + (d - poff[p]), h->h_offsets[p + 1]});
   }
   chunk_begin[P] = (int32_t)chunks.size();
   h->n_chunks = (int64_t)chunks.size();
 
-  const int BM = h->tile;
-  const int64_t nti = (K + BM - 1) / BM, ntj = (W + BM - 1) / BM;
+  const int64_t nt = h->Kp / kGramTile;
+  const int64_t nyt = xy_diag ? 0 : h->Mp / kGramTile;
   std::vector<std::pair<int32_t, int32_t>> gtiles;
-  for (int64_t ti = 0; ti < nti; ++ti)
-    for (int64_t tj = ti; tj < ntj; ++tj) gtiles.push_back({(int32_t)ti, (int32_t)tj});
+  for (int64_t ti = 0; ti < nt; ++ti) {
+    for (int64_t tj = ti; tj < nt; ++tj) gtiles.push_back({(int32_t)ti, (int32_t)tj});
+    for (int64_t y = 0; y < nyt; ++y) gtiles.push_back({(int32_t)ti, (int32_t)(nt + y)});
+  }
   const int64_t ntile = (int64_t)gtiles.size();
-  int64_t rows_per_split = (N * ntile + kGramTargetItems - 1) / kGramTargetItems;
+  // split folds along rows until the launch has enough items to fill the chip
+  int64_t rows_per_split = (h->Np * ntile + kGramTargetItems - 1) / kGramTargetItems;
   rows_per_split = std::max(rows_per_split, kGramMinRows);
-  rows_per_split = (rows_per_split + 15) / 16 * 16;
+  rows_per_split = (rows_per_split + PR - 1) / PR * PR;
   std::vector<GramWork> work;
   std::vector<int32_t> slab_begin(P + 1, 0);
   int32_t slab = 0;
   for (int64_t p = 0; p < P; ++p) {
     slab_begin[p] = slab;
-    const int64_t a = h->h_offsets[p], b = h->h_offsets[p + 1];
-    const int64_t splits = std::max<int64_t>(1, (b - a + rows_per_split - 1) / rows_per_split);
+    const int64_t a = poff[p], b = poff[p + 1];
+    const int64_t panels = (b - a) / PR;
+    const int64_t splits =
+        std::min(panels, std::max<int64_t>(1, (b - a + rows_per_split - 1) / rows_per_split));
     for (int64_t sp = 0; sp < splits; ++sp) {
-      const int64_t r0 = a + (b - a) * sp / splits;
-      const int64_t r1 = a + (b - a) * (sp + 1) / splits;
+      const int64_t r0 = a + panels * sp / splits * PR;
+      const int64_t r1 = a + panels * (sp + 1) / splits * PR;
       for (auto& tt : gtiles) work.push_back({(int32_t)p, slab, tt.first, tt.second, r0, r1});
       ++slab;
     }
@@ -244,7 +269,15 @@ cvgram_status build(cvgram_handle* h, const void* X, const void* Y, const int32_
 
   // ---- workspace ---------------------------------------------------------
   h->d_pivot = alloc<double>(h, W);
-  h->d_chunks = alloc<RowChunk>(h, h->n_chunks);
+  h->d_chunks = alloc<PackChunk>(h, h->n_chunks);
+  if (h->mode == CVGRAM_MODE_FP64) {
+    h->d_packed = alloc<double>(h, h->Np * h->Wp);
+  } else if (h->mode == CVGRAM_MODE_FP32) {
+    h->d_packed = alloc<float>(h, h->Np * h->Wp);
+  } else {
+    h->d_packed = alloc<uint16_t>(h, h->Np * h->Wp);
+    h->d_packed_lo = alloc<uint16_t>(h, h->Np * h->Wp);
+  }
   h->d_chunk_begin = alloc<int32_t>(h, P + 1);
   h->d_part = alloc<double>(h, 4 * h->n_chunks * W);
   h->d_fold = alloc<double>(h, 4 * P * W);
@@ -260,34 +293,39 @@ cvgram_status build(cvgram_handle* h, const void* X, const void* Y, const int32_
   h->d_slab_begin = alloc<int32_t>(h, P + 1);
   h->d_work = alloc<GramWork>(h, h->n_work);
   h->d_ctiles = alloc<int32_t>(h, (int64_t)ctiles.size());
-  upload(h->d_chunks, chunks, s);
-  upload(h->d_chunk_begin, chunk_begin, s);
-  upload(h->d_slab_begin, slab_begin, s);
-  upload(h->d_work, work, s);
-  upload(h->d_ctiles, ctiles, s);
+  upload(h, h->d_chunks, chunks, s);
+  upload(h, h->d_chunk_begin, chunk_begin, s);
+  upload(h, h->d_slab_begin, slab_begin, s);
+  upload(h, h->d_work, work, s);
+  upload(h, h->d_ctiles, ctiles, s);
 
   // ---- statistics and Gram pass -------------------------------------------
   const bool mixed = h->mode != CVGRAM_MODE_FP64;
   mark(1);
   launch_pivot(X, Y, h->dtype, mixed, N, K, M, h->d_pivot, s);
-  launch_colstats(X, Y, h->dtype, K, M, h->d_perm, h->d_chunks, h->n_chunks, h->d_pivot,
-                  h->d_part, s);
+  launch_pack(h->mode, X, Y, h->dtype, K, M, h->Kp, h->Wp, h->d_perm, h->d_chunks, h->n_chunks,
+              h->d_pivot, h->d_packed, h->d_packed_lo, h->d_part, s);
   launch_stats_reduce(h->d_part, h->n_chunks, h->d_chunk_begin, (int32_t)P, W, h->d_fold, s);
   launch_train_stats(h->d_fold, h->d_offsets, (int32_t)P, N, W, h->ddof, h->d_pivot,
                      h->d_scratch, h->d_tr_sum, h->d_tr_mean, h->d_tr_std, h->d_tr_mu,
                      h->d_tr_const, h->d_ntrain, s);
   mark(2);
-  if (h->mode == CVGRAM_MODE_FP64)
-    launch_gram_f64(X, Y, h->dtype, K, M, h->d_perm, h->d_pivot, h->d_work, h->n_work, h->tile,
-                    h->d_slabs, s);
-  else
-    launch_gram_mixed(h->mode, X, Y, h->dtype, K, M, h->d_perm, h->d_pivot, h->d_work,
-                      h->n_work, h->d_slabs, s);
+  GramArgs ga;
+  ga.Zp = h->d_packed;
+  ga.Zlo = h->d_packed_lo;
+  ga.Wp = h->Wp;
+  ga.K = K;
+  ga.M = M;
+  ga.Kp = h->Kp;
+  ga.nt = (int32_t)nt;
+  ga.xy_diag = xy_diag ? 1 : 0;
+  ga.work = h->d_work;
+  ga.n_work = h->n_work;
+  ga.slabs = h->d_slabs;
+  launch_gram(h->mode, ga, s);
   mark(3);
   launch_reduce_slabs(h->d_slabs, h->n_slabs, K * W, h->d_G, s);
   mark(4);
-  // keep host plans alive until the uploads have been consumed
-  CVG_HIP(hipStreamSynchronize(s));
   return CVGRAM_OK;
 }
 
@@ -352,7 +390,6 @@ cvgram_status cvgram_create(const void* X, const void* Y, const int32_t* fold_id
   h->cy = center_y;
   h->sy = scale_y;
   h->ddof = ddof;
-  h->tile = mode == CVGRAM_MODE_FP64 ? 64 : mixed_tile();
   h->timing = g_stage_timing.load() != 0;
   cvgram_status st;
   try {

@@ -50,10 +50,32 @@ struct GramWork {
   int64_t r1;
 };
 
-// A fold-aligned block of rows for the column statistics.
-struct RowChunk {
-  int64_t r0;
-  int64_t r1;
+// Packed row space: every fold's rows, in fold order, padded with zero rows
+// to a multiple of kPanelRows.  A pack chunk covers packed rows [d0, d1) of
+// one fold (a whole number of panels); packed row d holds the permuted row
+// src0 + (d - d0) when that is below src1, else zeros.
+constexpr int kPanelRows = 32;
+struct PackChunk {
+  int64_t d0;
+  int64_t d1;
+  int64_t src0;
+  int64_t src1;
+};
+
+// Gram tiling: square output tiles of kGramTile columns; X^T Y is computed
+// inside diagonal tiles when M <= kYDiagCols.
+constexpr int kGramTile = 128;
+constexpr int kYDiagCols = 32;
+
+struct GramArgs {
+  const void* Zp;       // packed panels (FP64 / FP32 / bf16 hi)
+  const void* Zlo;      // bf16 lo panel (BF16X3 only)
+  int64_t Wp, K, M, Kp;
+  int32_t nt;           // tiles along X's columns (Kp / kGramTile)
+  int32_t xy_diag;      // X^T Y inside diagonal tiles
+  const GramWork* work;
+  int64_t n_work;
+  double* slabs;
 };
 
 }  // namespace cvg
@@ -70,7 +92,6 @@ struct cvgram_handle {
   std::vector<int64_t> h_offsets;   // [P+1]
 
   // Gram layout
-  int tile = 64;                    // square Gram tile edge
   int64_t n_slabs = 0;
   int64_t n_work = 0;
 
@@ -85,6 +106,9 @@ struct cvgram_handle {
   int64_t* d_ntrain = nullptr;      // [P]
   double* d_pivot = nullptr;        // [W]
   double* d_part = nullptr;         // [4][chunks][W]  sum, sumsq, min, max
+  void* d_packed = nullptr;         // packed panels (see PackChunk)
+  void* d_packed_lo = nullptr;      // bf16 lo panel
+  int64_t Kp = 0, Mp = 0, Wp = 0, Np = 0;
   double* d_fold = nullptr;         // [4][P][W]
   double* d_tr_sum = nullptr;       // [P][W]   shifted training sums
   double* d_tr_mean = nullptr;      // [P][W]   shifted training means
@@ -92,7 +116,7 @@ struct cvgram_handle {
   double* d_tr_mu = nullptr;        // [P][W]   unshifted training means
   double* d_scratch = nullptr;      // [2][P][W] suffix min/max
   uint8_t* d_tr_const = nullptr;    // [P][W]
-  cvg::RowChunk* d_chunks = nullptr;
+  cvg::PackChunk* d_chunks = nullptr;
   int32_t* d_chunk_begin = nullptr; // [P+1]
   int64_t n_chunks = 0;
   double* d_slabs = nullptr;        // [n_slabs][K][W]
@@ -101,6 +125,10 @@ struct cvgram_handle {
   cvg::GramWork* d_work = nullptr;  // [n_work]
   int32_t* d_ctiles = nullptr;      // correction tile list: pairs (bi, bj)
   int32_t n_ctiles_xx = 0, n_ctiles_xy = 0;
+
+  // host copies of the uploaded plans; kept until destroy so that the
+  // asynchronous uploads never read freed host memory
+  std::vector<std::vector<char>> host_plans;
 
   bool timing = false;              // stage events recorded at create
   hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -120,12 +148,15 @@ int64_t radix_hist_entries(int64_t N);
 void launch_fold_offsets(const int32_t* sorted_keys, int64_t N, int32_t P, int64_t* offsets,
                          int32_t* flag, hipStream_t s);
 
-// ------------------------------- stats.hip ---------------------------------
+// -------------------------------- pack.hip ---------------------------------
 void launch_pivot(const void* X, const void* Y, cvgram_dtype dt, bool round_f32, int64_t N,
                   int64_t K, int64_t M, double* pivot, hipStream_t s);
-void launch_colstats(const void* X, const void* Y, cvgram_dtype dt, int64_t K, int64_t M,
-                     const int32_t* perm, const RowChunk* chunks, int64_t n_chunks,
-                     const double* pivot, double* part, hipStream_t s);
+void launch_pack(cvgram_mode mode, const void* X, const void* Y, cvgram_dtype dt, int64_t K,
+                 int64_t M, int64_t Kp, int64_t Wp, const int32_t* perm, const PackChunk* chunks,
+                 int64_t n_chunks, const double* pivot, void* packed, void* packed_lo,
+                 double* part, hipStream_t s);
+
+// ------------------------------- stats.hip ---------------------------------
 void launch_stats_reduce(const double* part, int64_t n_chunks, const int32_t* chunk_begin,
                          int32_t P, int64_t W, double* fold, hipStream_t s);
 void launch_train_stats(const double* fold, const int64_t* offsets, int32_t P, int64_t N,
@@ -135,16 +166,8 @@ void launch_train_stats(const double* fold, const int64_t* offsets, int32_t P, i
 void launch_fold_stats(const double* tr_mu, const double* tr_std, int32_t p, int64_t K,
                        int64_t M, double* mx, double* sx, double* my, double* sy, hipStream_t s);
 
-// ------------------------------ gram_f64.hip -------------------------------
-void launch_gram_f64(const void* X, const void* Y, cvgram_dtype dt, int64_t K, int64_t M,
-                     const int32_t* perm, const double* pivot, const GramWork* work,
-                     int64_t n_work, int tile, double* slabs, hipStream_t s);
-
-// ----------------------------- gram_mixed.hip ------------------------------
-int mixed_tile();
-void launch_gram_mixed(cvgram_mode mode, const void* X, const void* Y, cvgram_dtype dt, int64_t K,
-                       int64_t M, const int32_t* perm, const double* pivot, const GramWork* work,
-                       int64_t n_work, double* slabs, hipStream_t s);
+// -------------------------------- gram.hip ---------------------------------
+void launch_gram(cvgram_mode mode, const GramArgs& g, hipStream_t s);
 
 // ------------------------------- correct.hip -------------------------------
 void launch_reduce_slabs(const double* slabs, int64_t n_slabs, int64_t elems, double* G,

@@ -1,16 +1,12 @@
 // Column statistics of the validation blocks and of the training partitions.
 //
-//  * pivot: one shift c_j per column of Z = [X | Y] (the FP64 mean of the
-//    first min(N, 256) rows, rounded to the input precision in the mixed
-//    modes).  Every output is invariant to c: centred results do not depend
-//    on a common shift, and uncentred ones are rebuilt exactly from the
-//    shifted sums.  Shifting keeps the sums of squares of Lemma 12 small, so
-//    the variance form does not cancel on columns with a large mean.
-//  * per validation block V_p (Algorithm 7 steps 10, 17, 19): FP64 sums and
-//    sums of squares of the shifted values, and the raw minimum and maximum
-//    (used for an exact "column constant over T_p" test).  Rows are read in
-//    fold-aligned chunks through the fold permutation; chunk partials are
-//    combined in a fixed order, so results are deterministic.
+//  * per validation block V_p (Algorithm 7 steps 10, 17, 19): the FP64 sums
+//    and sums of squares of the pivot-shifted values and the raw minimum and
+//    maximum (for an exact "column constant over T_p" test), combined in a
+//    fixed order from the per-chunk partials of the pack pass, so results
+//    are deterministic.  The shift c (one per column) keeps the sums of
+//    squares of Lemma 12 small, so the variance form does not cancel on
+//    columns with a large mean; every output is invariant to c.
 //  * per training partition T_p: the downdates of Lemma 14 and Lemma 7, the
 //    deviation by Lemma 12 with divisor |T_p| - ddof, and the zero -> 1 rule
 //    of Algorithm 7 step 24 read as "column constant over T_p".
@@ -20,71 +16,6 @@
 
 namespace cvg {
 namespace {
-
-template <typename T>
-__device__ inline double zval(const T* __restrict__ X, const T* __restrict__ Y, int64_t K,
-                              int64_t M, int64_t row, int64_t j) {
-  return j < K ? (double)X[row * K + j] : (double)Y[row * M + (j - K)];
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void pivot_kernel(const T* __restrict__ X,
-                                                    const T* __restrict__ Y, int64_t rows,
-                                                    int64_t K, int64_t M, int round_f32,
-                                                    double* __restrict__ pivot) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= K + M) return;
-  double s = 0.0;
-  for (int64_t r = 0; r < rows; ++r) s += zval(X, Y, K, M, r, j);
-  double c = s / (double)rows;
-  if (round_f32) c = (double)(float)c;
-  pivot[j] = c;
-}
-
-constexpr int kStatCols = 256;
-constexpr int kUnroll = 8;
-
-// part layout: [4][n_chunks][W] = sum, sumsq, min, max
-template <typename T>
-__global__ __launch_bounds__(kStatCols) void colstats_kernel(
-    const T* __restrict__ X, const T* __restrict__ Y, int64_t K, int64_t M,
-    const int32_t* __restrict__ perm, const RowChunk* __restrict__ chunks, int64_t n_chunks,
-    const double* __restrict__ pivot, double* __restrict__ part) {
-  const int64_t W = K + M;
-  const int64_t j = (int64_t)blockIdx.y * kStatCols + threadIdx.x;
-  const int64_t c = blockIdx.x;
-  if (j >= W) return;
-  const RowChunk ch = chunks[c];
-  const double piv = pivot[j];
-  double s = 0.0, q = 0.0, mn = INFINITY, mx = -INFINITY;
-  int64_t r = ch.r0;
-  for (; r + kUnroll <= ch.r1; r += kUnroll) {
-    double v[kUnroll];
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u) v[u] = zval(X, Y, K, M, (int64_t)perm[r + u], j);
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-      const double d = v[u] - piv;
-      s += d;
-      q = fma(d, d, q);
-      mn = fmin(mn, v[u]);
-      mx = fmax(mx, v[u]);
-    }
-  }
-  for (; r < ch.r1; ++r) {
-    const double x = zval(X, Y, K, M, (int64_t)perm[r], j);
-    const double d = x - piv;
-    s += d;
-    q = fma(d, d, q);
-    mn = fmin(mn, x);
-    mx = fmax(mx, x);
-  }
-  const int64_t stride = n_chunks * W;
-  part[0 * stride + c * W + j] = s;
-  part[1 * stride + c * W + j] = q;
-  part[2 * stride + c * W + j] = mn;
-  part[3 * stride + c * W + j] = mx;
-}
 
 // fold layout: [4][P][W]
 __global__ __launch_bounds__(256) void stats_reduce_kernel(const double* __restrict__ part,
@@ -192,32 +123,6 @@ __global__ void fold_stats_kernel(const double* __restrict__ tr_mu,
 }
 
 }  // namespace
-
-void launch_pivot(const void* X, const void* Y, cvgram_dtype dt, bool round_f32, int64_t N,
-                  int64_t K, int64_t M, double* pivot, hipStream_t s) {
-  const int64_t rows = N < 256 ? N : 256;
-  const unsigned blocks = (unsigned)((K + M + 255) / 256);
-  if (dt == CVGRAM_F64)
-    pivot_kernel<double><<<blocks, 256, 0, s>>>((const double*)X, (const double*)Y, rows, K, M,
-                                                round_f32 ? 1 : 0, pivot);
-  else
-    pivot_kernel<float><<<blocks, 256, 0, s>>>((const float*)X, (const float*)Y, rows, K, M,
-                                               round_f32 ? 1 : 0, pivot);
-  CVG_LAUNCH_CHECK();
-}
-
-void launch_colstats(const void* X, const void* Y, cvgram_dtype dt, int64_t K, int64_t M,
-                     const int32_t* perm, const RowChunk* chunks, int64_t n_chunks,
-                     const double* pivot, double* part, hipStream_t s) {
-  dim3 grid((unsigned)n_chunks, (unsigned)((K + M + kStatCols - 1) / kStatCols));
-  if (dt == CVGRAM_F64)
-    colstats_kernel<double><<<grid, kStatCols, 0, s>>>((const double*)X, (const double*)Y, K, M,
-                                                       perm, chunks, n_chunks, pivot, part);
-  else
-    colstats_kernel<float><<<grid, kStatCols, 0, s>>>((const float*)X, (const float*)Y, K, M,
-                                                      perm, chunks, n_chunks, pivot, part);
-  CVG_LAUNCH_CHECK();
-}
 
 void launch_stats_reduce(const double* part, int64_t n_chunks, const int32_t* chunk_begin,
                          int32_t P, int64_t W, double* fold, hipStream_t s) {
