@@ -180,6 +180,72 @@ cvgram_status cvgram_stage_times(cvgram_t h, double* ms, int32_t n);
  * device. */
 cvgram_status cvgram_trim_cache(void);
 
+/* ---------------------------------------------------------------------------
+ * Batched form: many independent cross-validation problems (different N, K,
+ * M and P) computed together.  Every stage runs as one launch over all
+ * problems (one grouped MFMA Gram launch for every fold of every problem),
+ * and the whole pipeline -- pivots, pack pass with validation-block
+ * statistics, training statistics, grouped Gram, slab reduction and the 12
+ * distinct training products of every fold (Algorithm 7 generalised as in
+ * Table 1) -- is captured once in a HIP graph and replayed by
+ * cvgram_batch_run().
+ * ------------------------------------------------------------------------- */
+typedef struct cvgram_batch* cvgram_batch_t;
+
+typedef struct {
+  const void* X;            /* device, N x K row-major, element type of the batch */
+  const void* Y;            /* device, N x M row-major; NULL only when M == 0      */
+  const int32_t* fold_id;   /* device, N labels (Definition 1, 0-based)            */
+  int64_t N, K, M;
+  void* out_XtX;            /* device, [P][4][K][K] (class order above), or NULL   */
+  void* out_XtY;            /* device, [P][8][K][M], or NULL                       */
+} cvgram_problem;
+
+/* Validate and plan a batch of n problems (n >= 1), all of element type
+ * `dtype`, arithmetic `mode` and deviation divisor |T_p| - ddof.  Runs the
+ * fold bookkeeping of every problem (Algorithm 1; waits on `stream`), checks
+ * Definition 1 (CVGRAM_EFOLDS, with the failing problem's index in the error
+ * message), allocates one workspace for the batch and captures the pipeline
+ * into a HIP graph on `stream`.  Scaled classes of a problem whose
+ * partitioning is not scalable for ddof (Definition 6) are not written.
+ * Problem arrays and outputs are borrowed: they must stay valid until
+ * cvgram_batch_destroy(); their contents may change between runs (the fold
+ * labels must not).  Output element type: double in CVGRAM_MODE_FP64, float
+ * otherwise.  Gram tile shapes come from the autotuning table
+ * (cvgram_autotune), else from a built-in rule. */
+cvgram_status cvgram_batch_create(const cvgram_problem* problems, int32_t n, cvgram_dtype dtype,
+                                  int ddof, cvgram_mode mode, void* stream, cvgram_batch_t* out);
+
+/* Replay the captured pipeline on the batch's stream (asynchronous): every
+ * problem's outputs are recomputed from the current contents of X and Y. */
+cvgram_status cvgram_batch_run(cvgram_batch_t b);
+
+/* Run the same pipeline eagerly (kernel by kernel, no graph) -- identical
+ * results; for comparison and debugging. */
+cvgram_status cvgram_batch_run_eager(cvgram_batch_t b);
+
+/* Number of folds of problem i, and whether it is scalable (host outputs;
+ * either may be NULL). */
+cvgram_status cvgram_batch_problem_info(cvgram_batch_t b, int32_t i, int32_t* P,
+                                        int32_t* scalable);
+
+/* Wait for the batch's outstanding work, then free it (NULL is a no-op). */
+cvgram_status cvgram_batch_destroy(cvgram_batch_t b);
+
+/* ---------------------------------------------------------------------------
+ * Autotuner of the grouped Gram launch.  Times the candidate tile edges (64,
+ * 128) and work-list sizes on the given problem (device data as in
+ * cvgram_create), records the fastest in a process-wide table keyed by
+ * (mode, dtype, K, M and N rounded to powers of two), and returns it.  Later
+ * cvgram_create / cvgram_batch_create calls whose problem falls in a tuned
+ * bucket use the recorded choice.  With the environment variable
+ * CVGRAM_TUNE_FILE set, the table is loaded from that file at first use and
+ * rewritten after each tuning.  Waits on `stream`.
+ * ------------------------------------------------------------------------- */
+cvgram_status cvgram_autotune(const void* X, const void* Y, const int32_t* fold_id, int64_t N,
+                              int64_t K, int64_t M, cvgram_dtype dtype, cvgram_mode mode,
+                              void* stream, int32_t* tile, int32_t* target_items);
+
 /* Change the stream used by later calls on this handle. */
 cvgram_status cvgram_set_stream(cvgram_t h, void* stream);
 

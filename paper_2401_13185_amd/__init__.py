@@ -19,6 +19,8 @@ __all__ = [
     "cvgram_fold_combo", "cvgram_folds_all", "cvgram_fold_stats", "cvgram_set_stream",
     "cvgram_destroy", "cvgram_status_string", "cvgram_last_error_message", "cvgram_version",
     "cvgram_set_stage_timing", "cvgram_stage_times", "cvgram_trim_cache",
+    "cvgram_batch_create", "cvgram_batch_run", "cvgram_batch_run_eager",
+    "cvgram_batch_problem_info", "cvgram_batch_destroy", "cvgram_autotune", "Batch",
     "CVGram", "MODES", "XTX_CLASSES", "XTY_CLASSES",
 ]
 
@@ -65,6 +67,13 @@ _SIGS = {
     "cvgram_last_error_message": (ctypes.c_char_p, []),
     "cvgram_version": (_i32, []),
     "cvgram_set_stage_timing": (_int, [_int]),
+    "cvgram_batch_create": (_int, [_vp, _i32, _int, _int, _int, _vp, ctypes.POINTER(_vp)]),
+    "cvgram_batch_run": (_int, [_vp]),
+    "cvgram_batch_run_eager": (_int, [_vp]),
+    "cvgram_batch_problem_info": (_int, [_vp, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
+    "cvgram_batch_destroy": (_int, [_vp]),
+    "cvgram_autotune": (_int, [_vp, _vp, _vp, _i64, _i64, _i64, _int, _int, _vp,
+                               ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "cvgram_stage_times": (_int, [_vp, ctypes.POINTER(ctypes.c_double), _i32]),
     "cvgram_trim_cache": (_int, []),
 }
@@ -298,6 +307,99 @@ def cvgram_last_error_message() -> str:
 
 def cvgram_version() -> int:
     return int(load().cvgram_version())
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [("X", _vp), ("Y", _vp), ("fold_id", _vp), ("N", _i64), ("K", _i64), ("M", _i64),
+                ("out_XtX", _vp), ("out_XtY", _vp)]
+
+
+class Batch:
+    """Owns a cvgram_batch_t and the tensors it borrows."""
+
+    def __init__(self, ptr, keep, outs, mode, stream):
+        self.ptr = ptr
+        self._keep = keep
+        self.outs = outs
+        self.mode = mode
+        self.stream = stream
+
+    def __del__(self):
+        try:
+            if self.ptr:
+                cvgram_batch_destroy(self)
+        except Exception:
+            pass
+
+
+def cvgram_batch_create(problems, ddof=1, mode="fp64", stream=None) -> Batch:
+    """problems: sequence of (X, Y, fold_id) CUDA tensors (same dtype).  The
+    outputs are allocated here: Batch.outs[i] = (XtX [P][4][K][K],
+    XtY [P][8][K][M] or None)."""
+    torch = _torch()
+    lib = load()
+    if not problems:
+        raise ValueError("need at least one problem")
+    dt = problems[0][0].dtype
+    if dt not in (torch.float32, torch.float64):
+        raise TypeError("X must be float32 or float64")
+    if mode not in MODES:
+        raise ValueError(f"mode must be one of {sorted(MODES)}")
+    odt = torch.float64 if mode == "fp64" else torch.float32
+    arr = (_Problem * len(problems))()
+    keep, outs = [], []
+    for i, (X, Y, f) in enumerate(problems):
+        if X.dtype != dt or (Y is not None and Y.dtype != dt):
+            raise TypeError("every X and Y of a batch must have the same dtype")
+        N, K = X.shape
+        M = 0 if Y is None else Y.shape[1]
+        P = int(f.max().item()) + 1 if f.numel() else 0
+        xx = torch.empty(max(P, 0), XTX_CLASSES, K, K, dtype=odt, device=X.device)
+        xy = torch.empty(max(P, 0), XTY_CLASSES, K, M, dtype=odt, device=X.device) if M else None
+        arr[i] = _Problem(_ptr(X, "X"), _ptr(Y, "Y") if M else None,
+                          _ptr(f, "fold_id", torch.int32, N), N, K, M, xx.data_ptr(),
+                          xy.data_ptr() if xy is not None else None)
+        keep.append((X, Y, f))
+        outs.append((xx, xy))
+    s = _stream_ptr(stream)
+    out = _vp()
+    _check(lib.cvgram_batch_create(arr, len(problems), 1 if dt == torch.float64 else 0, int(ddof),
+                                   MODES[mode], s, ctypes.byref(out)))
+    return Batch(out.value, keep, outs, mode, s)
+
+
+def cvgram_batch_run(b: Batch):
+    _check(load().cvgram_batch_run(b.ptr))
+
+
+def cvgram_batch_run_eager(b: Batch):
+    _check(load().cvgram_batch_run_eager(b.ptr))
+
+
+def cvgram_batch_problem_info(b: Batch, i: int):
+    P, sc = _i32(), _i32()
+    _check(load().cvgram_batch_problem_info(b.ptr, int(i), ctypes.byref(P), ctypes.byref(sc)))
+    return P.value, bool(sc.value)
+
+
+def cvgram_batch_destroy(b: Batch):
+    if b.ptr:
+        ptr, b.ptr = b.ptr, None
+        _check(load().cvgram_batch_destroy(ptr))
+        b._keep = None
+
+
+def cvgram_autotune(X, Y, fold_id, mode="fp64", stream=None):
+    """Tune the grouped Gram launch on this problem; returns (tile, target_items)."""
+    torch = _torch()
+    N, K = X.shape
+    M = 0 if Y is None else Y.shape[1]
+    tile, items = _i32(), _i32()
+    _check(load().cvgram_autotune(_ptr(X, "X"), _ptr(Y, "Y") if M else None,
+                                  _ptr(fold_id, "fold_id", torch.int32, N), N, K, M,
+                                  1 if X.dtype == torch.float64 else 0, MODES[mode],
+                                  _stream_ptr(stream), ctypes.byref(tile), ctypes.byref(items)))
+    return tile.value, items.value
 
 
 class CVGram:

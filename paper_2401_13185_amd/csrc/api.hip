@@ -1,14 +1,18 @@
 // C ABI of libcvgram: argument checks, fold bookkeeping and validation,
-// planning of the grouped Gram launch, workspace ownership and dispatch of
-// the per-fold correction kernels.
+// planning of every launch, workspace ownership, the batched pipeline and
+// its HIP graph, and the autotuning table.
 #include <algorithm>
 #include <atomic>
+#include <climits>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "internal.h"
@@ -28,105 +32,289 @@ cvgram_status fail(cvgram_status st, const std::string& msg) {
 }
 
 // ---------------------------------------------------------------------------
-// per-device workspace cache: blocks released by cvgram_destroy are reused by
-// later handles when a cached block is at least as large as the request and
-// at most about twice as large.
+// workspace caches.  Device blocks (per device) and pinned host blocks
+// released by a handle are reused by later handles when a cached block is at
+// least as large as the request and at most about twice as large.
 // ---------------------------------------------------------------------------
 constexpr size_t kCacheCap = (size_t)32 << 30;
+constexpr size_t kHostCacheCap = (size_t)1 << 30;
 constexpr int kMaxDev = 64;
 
 struct Cache {
   std::mutex mu;
-  std::multimap<size_t, void*> blocks[kMaxDev];
-  size_t total[kMaxDev] = {};
+  std::multimap<size_t, void*> dev[kMaxDev];
+  size_t dev_total[kMaxDev] = {};
+  std::multimap<size_t, void*> host;
+  size_t host_total = 0;
 };
 Cache& cache() {
   static Cache* c = new Cache();  // never destroyed: outlives static teardown
   return *c;
 }
 
-void cache_give(int dev, void* p, size_t bytes) {
-  Cache& c = cache();
-  {
-    std::lock_guard<std::mutex> g(c.mu);
-    if (dev >= 0 && dev < kMaxDev && c.total[dev] + bytes <= kCacheCap) {
-      c.blocks[dev].insert({bytes, p});
-      c.total[dev] += bytes;
-      return;
-    }
-  }
-  (void)hipFree(p);
-}
-
-void cache_trim(int dev) {
+void cache_trim_dev(int dev) {
   Cache& c = cache();
   std::lock_guard<std::mutex> g(c.mu);
   if (dev < 0 || dev >= kMaxDev) return;
-  for (auto& kv : c.blocks[dev]) (void)hipFree(kv.second);
-  c.blocks[dev].clear();
-  c.total[dev] = 0;
+  for (auto& kv : c.dev[dev]) (void)hipFree(kv.second);
+  c.dev[dev].clear();
+  c.dev_total[dev] = 0;
 }
 
-template <typename T>
-T* alloc(cvgram_handle* h, int64_t count) {
-  if (count <= 0) count = 1;
-  const size_t want = ((size_t)count * sizeof(T) + 255) / 256 * 256;
-  void* p = nullptr;
-  size_t got = want;
-  {
+void* take(std::multimap<size_t, void*>& m, size_t& total, size_t want, size_t* got) {
+  auto it = m.lower_bound(want);
+  if (it == m.end() || it->first > 2 * want + 4096) return nullptr;
+  void* p = it->second;
+  *got = it->first;
+  total -= it->first;
+  m.erase(it);
+  return p;
+}
+
+// one owned block: device or pinned host
+struct Block {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+  bool host = false;
+};
+
+struct Owned {
+  int device = 0;
+  std::vector<Block> blocks;
+
+  void* dev(size_t want) {
+    want = (want + 255) / 256 * 256;
+    if (want == 0) want = 256;
+    size_t got = want;
+    void* p = nullptr;
+    {
+      Cache& c = cache();
+      std::lock_guard<std::mutex> g(c.mu);
+      if (device >= 0 && device < kMaxDev) p = take(c.dev[device], c.dev_total[device], want, &got);
+    }
+    if (!p) {
+      hipError_t e = hipMalloc(&p, want);
+      if (e == hipErrorOutOfMemory) {
+        (void)hipGetLastError();
+        cache_trim_dev(device);
+        e = hipMalloc(&p, want);
+      }
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("hipMalloc(" + std::to_string(want) + "): " + hipGetErrorString(e));
+        throw Fail{e == hipErrorOutOfMemory ? CVGRAM_ENOMEM : CVGRAM_EDEVICE};
+      }
+      got = want;
+    }
+    blocks.push_back({p, got, false});
+    return p;
+  }
+
+  void* pinned(size_t want) {
+    want = (want + 4095) / 4096 * 4096;
+    if (want == 0) want = 4096;
+    size_t got = want;
+    void* p = nullptr;
+    {
+      Cache& c = cache();
+      std::lock_guard<std::mutex> g(c.mu);
+      p = take(c.host, c.host_total, want, &got);
+    }
+    if (!p) {
+      hipError_t e = hipHostMalloc(&p, want, hipHostMallocDefault);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("hipHostMalloc(" + std::to_string(want) + "): " + hipGetErrorString(e));
+        throw Fail{CVGRAM_ENOMEM};
+      }
+      got = want;
+    }
+    blocks.push_back({p, got, true});
+    return p;
+  }
+
+  // give one block back early (scratch)
+  void give_back(void* p) {
+    for (size_t i = 0; i < blocks.size(); ++i)
+      if (blocks[i].ptr == p) {
+        release_one(blocks[i]);
+        blocks.erase(blocks.begin() + (long)i);
+        return;
+      }
+  }
+
+  void release_one(const Block& b) {
     Cache& c = cache();
-    std::lock_guard<std::mutex> g(c.mu);
-    if (h->device >= 0 && h->device < kMaxDev) {
-      auto it = c.blocks[h->device].lower_bound(want);
-      if (it != c.blocks[h->device].end() && it->first <= 2 * want + 4096) {
-        p = it->second;
-        got = it->first;
-        c.total[h->device] -= it->first;
-        c.blocks[h->device].erase(it);
+    {
+      std::lock_guard<std::mutex> g(c.mu);
+      if (b.host) {
+        if (c.host_total + b.bytes <= kHostCacheCap) {
+          c.host.insert({b.bytes, b.ptr});
+          c.host_total += b.bytes;
+          return;
+        }
+      } else if (device >= 0 && device < kMaxDev && c.dev_total[device] + b.bytes <= kCacheCap) {
+        c.dev[device].insert({b.bytes, b.ptr});
+        c.dev_total[device] += b.bytes;
+        return;
       }
     }
+    if (b.host)
+      (void)hipHostFree(b.ptr);
+    else
+      (void)hipFree(b.ptr);
   }
-  if (!p) {
-    hipError_t e = hipMalloc(&p, want);
-    if (e == hipErrorOutOfMemory) {
-      (void)hipGetLastError();
-      cache_trim(h->device);
-      e = hipMalloc(&p, want);
-    }
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      set_error(std::string("hipMalloc(") + std::to_string(want) + "): " + hipGetErrorString(e));
-      throw Fail{e == hipErrorOutOfMemory ? CVGRAM_ENOMEM : CVGRAM_EDEVICE};
-    }
+
+  void release() {
+    for (auto& b : blocks) release_one(b);
+    blocks.clear();
   }
-  DevBuf b;
-  b.ptr = p;
-  b.bytes = got;
-  h->bufs.push_back(b);
-  return (T*)p;
+};
+
+// ---------------------------------------------------------------------------
+// launch configuration and the autotuning table
+// ---------------------------------------------------------------------------
+struct Config {
+  int tile = 128;
+  int64_t target_items = 1024;  // Gram work items to aim for
+};
+
+int log2_bucket(int64_t v) {
+  int b = 0;
+  while ((int64_t(1) << b) < v && b < 62) ++b;
+  return b;
 }
 
-void free_all(cvgram_handle* h) {
-  for (auto& b : h->bufs)
-    if (b.ptr) cache_give(h->device, b.ptr, b.bytes);
-  h->bufs.clear();
-  for (auto& e : h->ev)
-    if (e) {
-      (void)hipEventDestroy(e);
-      e = nullptr;
-    }
+struct TuneTable {
+  std::mutex mu;
+  std::map<std::tuple<int, int, int, int, int>, Config> t;
+  bool loaded = false;
+};
+TuneTable& tune_table() {
+  static TuneTable* t = new TuneTable();
+  return *t;
 }
 
-// Asynchronous upload of a host plan; the handle keeps the host bytes alive
-// until it is destroyed.
-template <typename T>
-void upload(cvgram_handle* h, T* dst, const std::vector<T>& src, hipStream_t s) {
-  if (src.empty()) return;
-  const char* b = (const char*)src.data();
-  h->host_plans.emplace_back(b, b + src.size() * sizeof(T));
-  CVG_HIP(hipMemcpyAsync(dst, h->host_plans.back().data(), src.size() * sizeof(T),
-                         hipMemcpyHostToDevice, s));
+std::tuple<int, int, int, int, int> tune_key(cvgram_mode mode, cvgram_dtype dt, int64_t K,
+                                             int64_t M, int64_t N) {
+  return std::make_tuple((int)mode, (int)dt, log2_bucket(K), log2_bucket(M + 1), log2_bucket(N));
 }
+
+void tune_load_locked(TuneTable& tt) {
+  if (tt.loaded) return;
+  tt.loaded = true;
+  const char* path = std::getenv("CVGRAM_TUNE_FILE");
+  if (!path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  int a, b, c, d, e, tile;
+  long long items;
+  while (std::fscanf(f, "%d %d %d %d %d %d %lld", &a, &b, &c, &d, &e, &tile, &items) == 7)
+    if ((tile == 64 || tile == 128) && items > 0) tt.t[std::make_tuple(a, b, c, d, e)] = {tile, items};
+  std::fclose(f);
+}
+
+void tune_save_locked(TuneTable& tt) {
+  const char* path = std::getenv("CVGRAM_TUNE_FILE");
+  if (!path) return;
+  FILE* f = std::fopen(path, "w");
+  if (!f) return;
+  for (auto& kv : tt.t)
+    std::fprintf(f, "%d %d %d %d %d %d %lld\n", std::get<0>(kv.first), std::get<1>(kv.first),
+                 std::get<2>(kv.first), std::get<3>(kv.first), std::get<4>(kv.first),
+                 kv.second.tile, (long long)kv.second.target_items);
+  std::fclose(f);
+}
+
+Config default_config(cvgram_mode mode, int64_t K) {
+  Config c;
+  c.tile = K <= 64 ? 64 : 128;
+  c.target_items = mode == CVGRAM_MODE_FP64 ? 2048 : 1024;
+  return c;
+}
+
+Config choose_config(cvgram_mode mode, cvgram_dtype dt, int64_t K, int64_t M, int64_t N) {
+  TuneTable& tt = tune_table();
+  std::lock_guard<std::mutex> g(tt.mu);
+  tune_load_locked(tt);
+  auto it = tt.t.find(tune_key(mode, dt, K, M, N));
+  if (it != tt.t.end()) return it->second;
+  return default_config(mode, K);
+}
+
+// ---------------------------------------------------------------------------
+// plans
+// ---------------------------------------------------------------------------
+struct ProbPlan {
+  const void* X = nullptr;
+  const void* Y = nullptr;
+  const int32_t* fold = nullptr;
+  int64_t N = 0, K = 0, M = 0, W = 0;
+  void* out_xx = nullptr;
+  void* out_xy = nullptr;
+  int32_t P = 0;
+  bool scalable = false;
+  std::vector<int64_t> offsets;  // [P+1]
+  Config cfg;
+  int64_t Kp = 0, Mp = 0, Wp = 0, Np = 0;
+  bool xy_diag = false;
+  int32_t nt = 0;
+  std::vector<int64_t> poff;  // [P+1] packed row offsets
+  std::vector<int32_t> chunk_begin, slab_begin, ctiles;
+  int64_t n_chunks = 0, n_slabs = 0;
+  int32_t n_ctiles_xx = 0, n_ctiles_xy = 0;
+  int32_t* d_perm = nullptr;
+};
+
+// the device pipeline of a batch (a single handle is a batch of one)
+struct Batch {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  cvgram_mode mode = CVGRAM_MODE_FP64;
+  cvgram_dtype dtype = CVGRAM_F64;
+  int ddof = 1;
+  bool batched = false;           // outputs written by the pipeline itself
+  bool force_cfg = false;         // autotuner candidates
+  Config forced;
+  std::vector<ProbPlan> pp;
+  Owned mem;
+  std::vector<ProbDesc> h_pd;     // host copies of the descriptors
+  ProbDesc* d_pd = nullptr;
+  OutDesc* d_out = nullptr;
+  Item* d_pivot_items = nullptr;
+  int64_t n_pivot_items = 0;
+  PackChunk* d_chunks = nullptr;
+  int64_t n_chunks = 0;
+  int32_t max_pack_cb = 0;
+  Item* d_fold_items = nullptr;
+  int64_t n_fold_items = 0;
+  int32_t max_cb64 = 0, max_cb256 = 0;
+  Item* d_cb_items = nullptr;
+  int64_t n_cb_items = 0;
+  GramWork* d_work = nullptr;
+  int64_t n_work64 = 0, n_work128 = 0;
+  Item* d_red_items = nullptr;
+  int64_t n_red_items = 0;
+  Item* d_corr_items = nullptr;
+  int64_t n_corr_items = 0;
+  bool timing = false;
+  hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+
+  void release() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    gexec = nullptr;
+    graph = nullptr;
+    for (auto& e : ev)
+      if (e) {
+        (void)hipEventDestroy(e);
+        e = nullptr;
+      }
+    mem.release();
+  }
+};
 
 int bit_length(uint32_t v) {
   int b = 0;
@@ -137,225 +325,436 @@ int bit_length(uint32_t v) {
   return b;
 }
 
-constexpr int64_t kStatChunkRows = 1024;  // multiple of kPanelRows
-constexpr int64_t kGramTargetItems = 2048;
-constexpr int64_t kGramMinRows = 512;
+constexpr int64_t kPackTargetBlocks = 8192;
+constexpr int64_t kMaxChunkRows = 1024;   // multiple of kPanelRows
+constexpr int64_t kGramMinRows = 256;
 
-bool out_is_f64(const cvgram_handle* h) { return h->mode == CVGRAM_MODE_FP64; }
-
-// Runs the whole create pipeline; throws Fail on device errors.
-cvgram_status build(cvgram_handle* h, const void* X, const void* Y, const int32_t* fold) {
-  hipStream_t s = h->stream;
-  const int64_t N = h->N, K = h->K, M = h->M, W = h->W;
-
-  auto mark = [&](int k) {
-    if (h->timing) CVG_HIP(hipEventRecord(h->ev[k], s));
-  };
-  if (h->timing)
-    for (auto& e : h->ev) CVG_HIP(hipEventCreate(&e));
-  mark(0);
-  // ---- Algorithm 1: labels -> P, stable partition, offsets ---------------
-  h->d_info = alloc<int32_t>(h, 64);
-  launch_fill_i32(h->d_info, 1, INT32_MAX, s);
-  launch_fill_i32(h->d_info + 1, 1, INT32_MIN, s);
-  launch_fill_i32(h->d_info + 2, 62, 0, s);
-  launch_label_minmax(fold, N, h->d_info, s);
-  int32_t info[2] = {0, 0};
-  CVG_HIP(hipMemcpyAsync(info, h->d_info, sizeof(info), hipMemcpyDeviceToHost, s));
-  CVG_HIP(hipStreamSynchronize(s));
-  if (info[0] < 0) return fail(CVGRAM_EFOLDS, "fold label < 0 (Definition 1)");
-  const int64_t P = (int64_t)info[1] + 1;
-  if (P < 2) return fail(CVGRAM_EFOLDS, "fewer than 2 folds (Definition 1)");
-  if (P > N) return fail(CVGRAM_EFOLDS, "more folds than rows (Definition 1)");
-  h->P = (int32_t)P;
-
-  h->d_keys = alloc<int32_t>(h, 2 * N);
-  h->d_perm = alloc<int32_t>(h, N);
-  h->d_perm_tmp = alloc<int32_t>(h, N);
-  h->d_hist = alloc<int32_t>(h, radix_hist_entries(N));
-  h->d_offsets = alloc<int64_t>(h, P + 1);
-  const int32_t* sorted = nullptr;
-  radix_partition(fold, N, bit_length((uint32_t)(P - 1)), h->d_keys, h->d_keys + N, h->d_perm,
-                  h->d_perm_tmp, h->d_hist, &sorted, s);
-  launch_fold_offsets(sorted, N, (int32_t)P, h->d_offsets, h->d_info + 2, s);
-  h->h_offsets.assign(P + 1, 0);
-  int32_t flag = 0;
-  CVG_HIP(hipMemcpyAsync(h->h_offsets.data(), h->d_offsets, (P + 1) * sizeof(int64_t),
-                         hipMemcpyDeviceToHost, s));
-  CVG_HIP(hipMemcpyAsync(&flag, h->d_info + 2, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-  CVG_HIP(hipStreamSynchronize(s));
-  if (flag) return fail(CVGRAM_EFOLDS, "a fold label in [0, P) has no rows (Definition 1)");
-  int64_t max_fold = 0;
-  for (int64_t p = 0; p < P; ++p)
-    max_fold = std::max(max_fold, h->h_offsets[p + 1] - h->h_offsets[p]);
-  h->scalable = (N - max_fold - h->ddof) >= 1;
-  if ((h->sx || h->sy) && !h->scalable)
-    return fail(CVGRAM_ENOTSCALABLE,
-                "scaling needs |T_p| - ddof >= 1 for every fold (Definition 6)");
-
-  // ---- plans --------------------------------------------------------------
-  // packed rows: each fold padded to whole panels
-  const int64_t PR = kPanelRows;
-  std::vector<int64_t> poff(P + 1, 0);
-  for (int64_t p = 0; p < P; ++p) {
-    const int64_t n = h->h_offsets[p + 1] - h->h_offsets[p];
-    poff[p + 1] = poff[p] + (n + PR - 1) / PR * PR;
+// Algorithm 1 on the device for every problem, with the checks of
+// Definition 1 and Definition 6.  Fills P, offsets, scalable and d_perm.
+cvgram_status bookkeeping(Batch& b) {
+  hipStream_t s = b.stream;
+  int64_t sumN = 0, maxN = 0;
+  for (auto& p : b.pp) {
+    sumN += p.N;
+    maxN = std::max(maxN, p.N);
   }
-  h->Np = poff[P];
-  // packed columns: X, zeros to Kp, Y, zeros to Wp
-  h->Kp = (K + kGramTile - 1) / kGramTile * kGramTile;
-  const bool xy_diag = M > 0 && M <= kYDiagCols;
-  h->Mp = M == 0 ? 0 : (xy_diag ? kYDiagCols : (M + kGramTile - 1) / kGramTile * kGramTile);
-  h->Wp = h->Kp + h->Mp;
+  int32_t* perm_block = (int32_t*)b.mem.dev((size_t)sumN * sizeof(int32_t));
+  Owned scratch;
+  scratch.device = b.device;
+  int32_t* info = (int32_t*)scratch.dev(64 * sizeof(int32_t));
+  int32_t* keys = (int32_t*)scratch.dev((size_t)2 * maxN * sizeof(int32_t));
+  int32_t* perm_tmp = (int32_t*)scratch.dev((size_t)maxN * sizeof(int32_t));
+  int32_t* hist = (int32_t*)scratch.dev((size_t)radix_hist_entries(maxN) * sizeof(int32_t));
+  int64_t* offs = (int64_t*)scratch.dev((size_t)(maxN + 1) * sizeof(int64_t));
+  int32_t* hbuf = (int32_t*)scratch.pinned(64 * sizeof(int32_t));
+  cvgram_status st = CVGRAM_OK;
+  int64_t at = 0;
+  try {
+    for (size_t i = 0; i < b.pp.size() && st == CVGRAM_OK; ++i) {
+      ProbPlan& p = b.pp[i];
+      const std::string tag = b.pp.size() > 1 ? "problem " + std::to_string(i) + ": " : "";
+      p.d_perm = perm_block + at;
+      at += p.N;
+      launch_fill_i32(info, 1, INT32_MAX, s);
+      launch_fill_i32(info + 1, 1, INT32_MIN, s);
+      launch_fill_i32(info + 2, 62, 0, s);
+      launch_label_minmax(p.fold, p.N, info, s);
+      CVG_HIP(hipMemcpyAsync(hbuf, info, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      CVG_HIP(hipStreamSynchronize(s));
+      if (hbuf[0] < 0) {
+        st = fail(CVGRAM_EFOLDS, tag + "fold label < 0 (Definition 1)");
+        break;
+      }
+      const int64_t P = (int64_t)hbuf[1] + 1;
+      if (P < 2) {
+        st = fail(CVGRAM_EFOLDS, tag + "fewer than 2 folds (Definition 1)");
+        break;
+      }
+      if (P > p.N) {
+        st = fail(CVGRAM_EFOLDS, tag + "more folds than rows (Definition 1)");
+        break;
+      }
+      p.P = (int32_t)P;
+      const int32_t* sorted = nullptr;
+      radix_partition(p.fold, p.N, bit_length((uint32_t)(P - 1)), keys, keys + maxN, p.d_perm,
+                      perm_tmp, hist, &sorted, s);
+      launch_fold_offsets(sorted, p.N, (int32_t)P, offs, info + 2, s);
+      p.offsets.assign(P + 1, 0);
+      CVG_HIP(hipMemcpyAsync(p.offsets.data(), offs, (P + 1) * sizeof(int64_t),
+                             hipMemcpyDeviceToHost, s));
+      CVG_HIP(hipMemcpyAsync(hbuf + 2, info + 2, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      CVG_HIP(hipStreamSynchronize(s));
+      if (hbuf[2]) {
+        st = fail(CVGRAM_EFOLDS, tag + "a fold label in [0, P) has no rows (Definition 1)");
+        break;
+      }
+      int64_t max_fold = 0;
+      for (int64_t q = 0; q < P; ++q) max_fold = std::max(max_fold, p.offsets[q + 1] - p.offsets[q]);
+      p.scalable = (p.N - max_fold - b.ddof) >= 1;
+    }
+  } catch (const Fail& f) {
+    (void)hipStreamSynchronize(s);
+    scratch.release();
+    throw;
+  }
+  CVG_HIP(hipStreamSynchronize(s));
+  scratch.release();
+  return st;
+}
 
+// Layout of every problem and the flat work lists of every launch.
+struct HostLists {
+  std::vector<Item> pivot_items, fold_items, cb_items, red_items, corr_items;
   std::vector<PackChunk> chunks;
-  std::vector<int32_t> chunk_begin(P + 1, 0);
-  for (int64_t p = 0; p < P; ++p) {
-    chunk_begin[p] = (int32_t)chunks.size();
-    for (int64_t d = poff[p]; d < poff[p + 1]; d += kStatChunkRows)
-      chunks.push_back({d, std::min(d + kStatChunkRows, poff[p + 1]),
-                        h->h_offsets[p] + (d - poff[p]), h->h_offsets[p + 1]});
-  }
-  chunk_begin[P] = (int32_t)chunks.size();
-  h->n_chunks = (int64_t)chunks.size();
+  std::vector<GramWork> work64, work128;
+};
 
-  const int64_t nt = h->Kp / kGramTile;
-  const int64_t nyt = xy_diag ? 0 : h->Mp / kGramTile;
-  std::vector<std::pair<int32_t, int32_t>> gtiles;
-  for (int64_t ti = 0; ti < nt; ++ti) {
-    for (int64_t tj = ti; tj < nt; ++tj) gtiles.push_back({(int32_t)ti, (int32_t)tj});
-    for (int64_t y = 0; y < nyt; ++y) gtiles.push_back({(int32_t)ti, (int32_t)(nt + y)});
-  }
-  const int64_t ntile = (int64_t)gtiles.size();
-  // split folds along rows until the launch has enough items to fill the chip
-  int64_t rows_per_split = (h->Np * ntile + kGramTargetItems - 1) / kGramTargetItems;
-  rows_per_split = std::max(rows_per_split, kGramMinRows);
-  rows_per_split = (rows_per_split + PR - 1) / PR * PR;
-  std::vector<GramWork> work;
-  std::vector<int32_t> slab_begin(P + 1, 0);
-  int32_t slab = 0;
-  for (int64_t p = 0; p < P; ++p) {
-    slab_begin[p] = slab;
-    const int64_t a = poff[p], b = poff[p + 1];
-    const int64_t panels = (b - a) / PR;
-    const int64_t splits =
-        std::min(panels, std::max<int64_t>(1, (b - a + rows_per_split - 1) / rows_per_split));
-    for (int64_t sp = 0; sp < splits; ++sp) {
-      const int64_t r0 = a + panels * sp / splits * PR;
-      const int64_t r1 = a + panels * (sp + 1) / splits * PR;
-      for (auto& tt : gtiles) work.push_back({(int32_t)p, slab, tt.first, tt.second, r0, r1});
-      ++slab;
+void plan_layout(Batch& b, HostLists& L) {
+  const int64_t PR = kPanelRows;
+  int64_t pack_cols_rows = 0;  // sum over problems of Np * column blocks
+  int64_t gram_rows = 0;       // sum over problems of Np * tiles
+  for (auto& p : b.pp) {
+    p.cfg = b.force_cfg ? b.forced : choose_config(b.mode, b.dtype, p.K, p.M, p.N);
+    const int T = p.cfg.tile;
+    p.poff.assign(p.P + 1, 0);
+    for (int32_t q = 0; q < p.P; ++q) {
+      const int64_t n = p.offsets[q + 1] - p.offsets[q];
+      p.poff[q + 1] = p.poff[q] + (n + PR - 1) / PR * PR;
     }
+    p.Np = p.poff[p.P];
+    p.Kp = (p.K + T - 1) / T * T;
+    p.xy_diag = p.M > 0 && p.M <= kYDiagCols;
+    p.Mp = p.M == 0 ? 0 : (p.xy_diag ? kYDiagCols : (p.M + T - 1) / T * T);
+    p.Wp = p.Kp + p.Mp;
+    p.nt = (int32_t)(p.Kp / T);
+    const int64_t nyt = p.xy_diag ? 0 : p.Mp / T;
+    const int64_t ntile = (int64_t)p.nt * (p.nt + 1) / 2 + (int64_t)p.nt * nyt;
+    pack_cols_rows += p.Np * ((p.Wp + kPackCols - 1) / kPackCols);
+    gram_rows += p.Np * ntile;
   }
-  slab_begin[P] = slab;
-  h->n_slabs = slab;
-  h->n_work = (int64_t)work.size();
+  int64_t chunk_rows = (pack_cols_rows + kPackTargetBlocks - 1) / kPackTargetBlocks;
+  chunk_rows = std::min(kMaxChunkRows, std::max(PR, (chunk_rows + PR - 1) / PR * PR));
 
-  std::vector<int32_t> ctiles;
-  const int64_t nct = (K + kCorrTile - 1) / kCorrTile;
-  for (int64_t bi = 0; bi < nct; ++bi)
-    for (int64_t bj = bi; bj < nct; ++bj) {
-      ctiles.push_back((int32_t)bi);
-      ctiles.push_back((int32_t)bj);
+  for (size_t i = 0; i < b.pp.size(); ++i) {
+    ProbPlan& p = b.pp[i];
+    const int32_t pi = (int32_t)i;
+    const int T = p.cfg.tile;
+    // pivots
+    for (int64_t cb = 0; cb < (p.W + 63) / 64; ++cb) L.pivot_items.push_back({pi, (int32_t)cb, 0});
+    // pack chunks: whole panels of one fold
+    p.chunk_begin.assign(p.P + 1, 0);
+    int32_t nch = 0;
+    for (int32_t q = 0; q < p.P; ++q) {
+      p.chunk_begin[q] = nch;
+      for (int64_t d = p.poff[q]; d < p.poff[q + 1]; d += chunk_rows)
+        L.chunks.push_back({pi, nch++, d, std::min(d + chunk_rows, p.poff[q + 1]),
+                            p.offsets[q] + (d - p.poff[q]), p.offsets[q + 1]});
     }
-  h->n_ctiles_xx = (int32_t)(ctiles.size() / 2);
-  const int64_t ncy = (M + kCorrTile - 1) / kCorrTile;
-  for (int64_t bi = 0; bi < nct; ++bi)
-    for (int64_t bj = 0; bj < ncy; ++bj) {
-      ctiles.push_back((int32_t)bi);
-      ctiles.push_back((int32_t)bj);
+    p.chunk_begin[p.P] = nch;
+    p.n_chunks = nch;
+    b.max_pack_cb = std::max<int32_t>(b.max_pack_cb, (int32_t)((p.Wp + kPackCols - 1) / kPackCols));
+    // statistics
+    for (int32_t q = 0; q < p.P; ++q) L.fold_items.push_back({pi, q, 0});
+    for (int64_t cb = 0; cb < (p.W + 63) / 64; ++cb) L.cb_items.push_back({pi, (int32_t)cb, 0});
+    b.max_cb64 = std::max<int32_t>(b.max_cb64, (int32_t)((p.W + 63) / 64));
+    b.max_cb256 = std::max<int32_t>(b.max_cb256, (int32_t)((p.W + 255) / 256));
+    // Gram work: split folds along rows so the launch has about
+    // target_items items (shared over the batch)
+    std::vector<std::pair<int32_t, int32_t>> gtiles;
+    const int64_t nyt = p.xy_diag ? 0 : p.Mp / T;
+    for (int32_t ti = 0; ti < p.nt; ++ti) {
+      for (int32_t tj = ti; tj < p.nt; ++tj) gtiles.push_back({ti, tj});
+      for (int64_t y = 0; y < nyt; ++y) gtiles.push_back({ti, (int32_t)(p.nt + y)});
     }
-  h->n_ctiles_xy = (int32_t)(ctiles.size() / 2) - h->n_ctiles_xx;
-
-  // ---- workspace ---------------------------------------------------------
-  h->d_pivot = alloc<double>(h, W);
-  h->d_chunks = alloc<PackChunk>(h, h->n_chunks);
-  if (h->mode == CVGRAM_MODE_FP64) {
-    h->d_packed = alloc<double>(h, h->Np * h->Wp);
-  } else if (h->mode == CVGRAM_MODE_FP32) {
-    h->d_packed = alloc<float>(h, h->Np * h->Wp);
-  } else {
-    h->d_packed = alloc<uint16_t>(h, h->Np * h->Wp);
-    h->d_packed_lo = alloc<uint16_t>(h, h->Np * h->Wp);
+    int64_t rows_per_split = (gram_rows + p.cfg.target_items - 1) / p.cfg.target_items;
+    rows_per_split = std::max(rows_per_split, kGramMinRows);
+    rows_per_split = (rows_per_split + PR - 1) / PR * PR;
+    auto& wl = T == 64 ? L.work64 : L.work128;
+    p.slab_begin.assign(p.P + 1, 0);
+    int32_t slab = 0;
+    for (int32_t q = 0; q < p.P; ++q) {
+      p.slab_begin[q] = slab;
+      const int64_t a = p.poff[q], e = p.poff[q + 1];
+      const int64_t panels = (e - a) / PR;
+      const int64_t splits =
+          std::min(panels, std::max<int64_t>(1, (e - a + rows_per_split - 1) / rows_per_split));
+      for (int64_t sp = 0; sp < splits; ++sp) {
+        const int64_t r0 = a + panels * sp / splits * PR;
+        const int64_t r1 = a + panels * (sp + 1) / splits * PR;
+        for (auto& tt : gtiles) wl.push_back({pi, slab, tt.first, tt.second, r0, r1});
+        ++slab;
+      }
+    }
+    p.slab_begin[p.P] = slab;
+    p.n_slabs = slab;
+    // slab reduction
+    for (int64_t eb = 0; eb < (p.K * p.W + 255) / 256; ++eb) L.red_items.push_back({pi, (int32_t)eb, 0});
+    // correction tiles: upper triangle of X^T X, then X^T Y
+    p.ctiles.clear();
+    const int64_t nct = (p.K + kCorrTile - 1) / kCorrTile;
+    for (int64_t bi = 0; bi < nct; ++bi)
+      for (int64_t bj = bi; bj < nct; ++bj) {
+        p.ctiles.push_back((int32_t)bi);
+        p.ctiles.push_back((int32_t)bj);
+      }
+    p.n_ctiles_xx = (int32_t)(p.ctiles.size() / 2);
+    const int64_t ncy = (p.M + kCorrTile - 1) / kCorrTile;
+    for (int64_t bi = 0; bi < nct; ++bi)
+      for (int64_t bj = 0; bj < ncy; ++bj) {
+        p.ctiles.push_back((int32_t)bi);
+        p.ctiles.push_back((int32_t)bj);
+      }
+    p.n_ctiles_xy = (int32_t)(p.ctiles.size() / 2) - p.n_ctiles_xx;
+    if (b.batched)
+      for (int32_t q = 0; q < p.P; ++q)
+        for (int32_t tl = 0; tl < p.n_ctiles_xx + p.n_ctiles_xy; ++tl)
+          L.corr_items.push_back({pi, q, tl});
   }
-  h->d_chunk_begin = alloc<int32_t>(h, P + 1);
-  h->d_part = alloc<double>(h, 4 * h->n_chunks * W);
-  h->d_fold = alloc<double>(h, 4 * P * W);
-  h->d_scratch = alloc<double>(h, 2 * P * W);
-  h->d_tr_sum = alloc<double>(h, P * W);
-  h->d_tr_mean = alloc<double>(h, P * W);
-  h->d_tr_std = alloc<double>(h, P * W);
-  h->d_tr_mu = alloc<double>(h, P * W);
-  h->d_tr_const = alloc<uint8_t>(h, P * W);
-  h->d_ntrain = alloc<int64_t>(h, P);
-  h->d_slabs = alloc<double>(h, h->n_slabs * K * W);
-  h->d_G = alloc<double>(h, K * W);
-  h->d_slab_begin = alloc<int32_t>(h, P + 1);
-  h->d_work = alloc<GramWork>(h, h->n_work);
-  h->d_ctiles = alloc<int32_t>(h, (int64_t)ctiles.size());
-  upload(h, h->d_chunks, chunks, s);
-  upload(h, h->d_chunk_begin, chunk_begin, s);
-  upload(h, h->d_slab_begin, slab_begin, s);
-  upload(h, h->d_work, work, s);
-  upload(h, h->d_ctiles, ctiles, s);
+}
 
-  // ---- statistics and Gram pass -------------------------------------------
-  const bool mixed = h->mode != CVGRAM_MODE_FP64;
+// a growing plan blob with 256-byte aligned segments
+struct Blob {
+  std::vector<char> bytes;
+  template <typename T>
+  size_t put(const T* data, size_t count) {
+    const size_t off = (bytes.size() + 255) / 256 * 256;
+    bytes.resize(off + count * sizeof(T));
+    if (count && data) std::memcpy(bytes.data() + off, data, count * sizeof(T));
+    return off;
+  }
+  template <typename T>
+  size_t put(const std::vector<T>& v) {
+    return put(v.data(), v.size());
+  }
+};
+
+size_t elem_bytes(cvgram_mode m) { return m == CVGRAM_MODE_FP64 ? 8 : (m == CVGRAM_MODE_FP32 ? 4 : 2); }
+
+// Workspace arena + device descriptors + one upload of every plan.
+void allocate_and_upload(Batch& b, const HostLists& L) {
+  const size_t eb = elem_bytes(b.mode);
+  // arena layout per problem
+  struct Off {
+    size_t pivot, packed, packed_lo, part, fold, tot, tr_sum, tr_mean, tr_std, tr_mu, tr_const,
+        ntrain, slabs, G;
+  };
+  std::vector<Off> off(b.pp.size());
+  size_t total = 0;
+  auto take_bytes = [&](size_t bytes) {
+    const size_t o = total;
+    total += (bytes + 255) / 256 * 256;
+    return o;
+  };
+  for (size_t i = 0; i < b.pp.size(); ++i) {
+    const ProbPlan& p = b.pp[i];
+    Off& o = off[i];
+    o.pivot = take_bytes(p.W * 8);
+    o.packed = take_bytes((size_t)p.Np * p.Wp * eb);
+    o.packed_lo = b.mode == CVGRAM_MODE_BF16X3 ? take_bytes((size_t)p.Np * p.Wp * eb) : 0;
+    o.part = take_bytes((size_t)4 * p.n_chunks * p.W * 8);
+    o.fold = take_bytes((size_t)4 * p.P * p.W * 8);
+    o.tot = take_bytes((size_t)8 * p.W * 8);
+    o.tr_sum = take_bytes((size_t)p.P * p.W * 8);
+    o.tr_mean = take_bytes((size_t)p.P * p.W * 8);
+    o.tr_std = take_bytes((size_t)p.P * p.W * 8);
+    o.tr_mu = take_bytes((size_t)p.P * p.W * 8);
+    o.tr_const = take_bytes((size_t)p.P * p.W);
+    o.ntrain = take_bytes((size_t)p.P * 8);
+    o.slabs = take_bytes((size_t)p.n_slabs * p.K * p.W * 8);
+    o.G = take_bytes((size_t)p.K * p.W * 8);
+  }
+  char* arena = (char*)b.mem.dev(total);
+
+  // plan blob: per-problem small arrays first, then descriptors and lists
+  Blob blob;
+  std::vector<size_t> o_offsets(b.pp.size()), o_cbeg(b.pp.size()), o_sbeg(b.pp.size()),
+      o_ctiles(b.pp.size());
+  for (size_t i = 0; i < b.pp.size(); ++i) {
+    o_offsets[i] = blob.put(b.pp[i].offsets);
+    o_cbeg[i] = blob.put(b.pp[i].chunk_begin);
+    o_sbeg[i] = blob.put(b.pp[i].slab_begin);
+    o_ctiles[i] = blob.put(b.pp[i].ctiles);
+  }
+  const size_t o_pd = blob.put((const ProbDesc*)nullptr, b.pp.size());
+  const size_t o_out = blob.put((const OutDesc*)nullptr, b.pp.size());
+  const size_t o_pivot = blob.put(L.pivot_items);
+  const size_t o_chunks = blob.put(L.chunks);
+  const size_t o_fold = blob.put(L.fold_items);
+  const size_t o_cb = blob.put(L.cb_items);
+  std::vector<GramWork> work = L.work64;
+  work.insert(work.end(), L.work128.begin(), L.work128.end());
+  const size_t o_work = blob.put(work);
+  const size_t o_red = blob.put(L.red_items);
+  const size_t o_corr = blob.put(L.corr_items);
+  char* dblob = (char*)b.mem.dev(blob.bytes.size());
+
+  b.h_pd.assign(b.pp.size(), ProbDesc{});
+  std::vector<OutDesc> outs(b.pp.size());
+  for (size_t i = 0; i < b.pp.size(); ++i) {
+    const ProbPlan& p = b.pp[i];
+    const Off& o = off[i];
+    ProbDesc& d = b.h_pd[i];
+    std::memset(&d, 0, sizeof(d));
+    d.X = p.X;
+    d.Y = p.Y;
+    d.N = p.N;
+    d.K = p.K;
+    d.M = p.M;
+    d.W = p.W;
+    d.Kp = p.Kp;
+    d.Wp = p.Wp;
+    d.Np = p.Np;
+    d.P = p.P;
+    d.tile = p.cfg.tile;
+    d.nt = p.nt;
+    d.xy_diag = p.xy_diag ? 1 : 0;
+    d.ddof = b.ddof;
+    d.x_vec = (p.K % 4 == 0) && ((uintptr_t)p.X % 16 == 0) ? 1 : 0;
+    d.perm = p.d_perm;
+    d.offsets = (const int64_t*)(dblob + o_offsets[i]);
+    d.pivot = (double*)(arena + o.pivot);
+    d.packed = arena + o.packed;
+    d.packed_lo = b.mode == CVGRAM_MODE_BF16X3 ? arena + o.packed_lo : nullptr;
+    d.part = (double*)(arena + o.part);
+    d.n_chunks = p.n_chunks;
+    d.chunk_begin = (const int32_t*)(dblob + o_cbeg[i]);
+    d.fold = (double*)(arena + o.fold);
+    d.tot = (double*)(arena + o.tot);
+    d.tr_sum = (double*)(arena + o.tr_sum);
+    d.tr_mean = (double*)(arena + o.tr_mean);
+    d.tr_std = (double*)(arena + o.tr_std);
+    d.tr_mu = (double*)(arena + o.tr_mu);
+    d.tr_const = (uint8_t*)(arena + o.tr_const);
+    d.ntrain = (int64_t*)(arena + o.ntrain);
+    d.slabs = (double*)(arena + o.slabs);
+    d.slab_begin = (const int32_t*)(dblob + o_sbeg[i]);
+    d.G = (double*)(arena + o.G);
+    d.ctiles = (const int32_t*)(dblob + o_ctiles[i]);
+    d.n_ctiles_xx = p.n_ctiles_xx;
+    d.n_ctiles_xy = p.n_ctiles_xy;
+    // batched outputs: every fold, all 12 classes (scaled ones only if scalable)
+    OutDesc& od = outs[i];
+    std::memset(&od, 0, sizeof(od));
+    const size_t ob = b.mode == CVGRAM_MODE_FP64 ? 8 : 4;
+    const int64_t KK = p.K * p.K, KM = p.K * p.M;
+    for (int c = 0; c < CVGRAM_XTX_CLASSES; ++c)
+      od.xx[c] = (p.out_xx && (p.scalable || !(c & 1))) ? (char*)p.out_xx + c * KK * ob : nullptr;
+    for (int c = 0; c < CVGRAM_XTY_CLASSES; ++c)
+      od.xy[c] = (p.out_xy && p.M > 0 && (p.scalable || !(c & 3))) ? (char*)p.out_xy + c * KM * ob
+                                                                   : nullptr;
+    od.fold_stride_xx = CVGRAM_XTX_CLASSES * KK;
+    od.fold_stride_xy = CVGRAM_XTY_CLASSES * KM;
+    od.p_begin = 0;
+  }
+  std::memcpy(blob.bytes.data() + o_pd, b.h_pd.data(), b.h_pd.size() * sizeof(ProbDesc));
+  std::memcpy(blob.bytes.data() + o_out, outs.data(), outs.size() * sizeof(OutDesc));
+
+  b.d_pd = (ProbDesc*)(dblob + o_pd);
+  b.d_out = (OutDesc*)(dblob + o_out);
+  b.d_pivot_items = (Item*)(dblob + o_pivot);
+  b.n_pivot_items = (int64_t)L.pivot_items.size();
+  b.d_chunks = (PackChunk*)(dblob + o_chunks);
+  b.n_chunks = (int64_t)L.chunks.size();
+  b.d_fold_items = (Item*)(dblob + o_fold);
+  b.n_fold_items = (int64_t)L.fold_items.size();
+  b.d_cb_items = (Item*)(dblob + o_cb);
+  b.n_cb_items = (int64_t)L.cb_items.size();
+  b.d_work = (GramWork*)(dblob + o_work);
+  b.n_work64 = (int64_t)L.work64.size();
+  b.n_work128 = (int64_t)L.work128.size();
+  b.d_red_items = (Item*)(dblob + o_red);
+  b.n_red_items = (int64_t)L.red_items.size();
+  b.d_corr_items = (Item*)(dblob + o_corr);
+  b.n_corr_items = (int64_t)L.corr_items.size();
+
+  // one asynchronous upload from pinned memory (kept until the batch is freed)
+  void* hb = b.mem.pinned(blob.bytes.size());
+  std::memcpy(hb, blob.bytes.data(), blob.bytes.size());
+  CVG_HIP(hipMemcpyAsync(dblob, hb, blob.bytes.size(), hipMemcpyHostToDevice, b.stream));
+}
+
+// The device pipeline (Algorithm 7 steps 3-4, 8, 10, 17, 19 and, for a
+// batch, steps 9, 11-16, 18, 20-27 for every fold and class).
+void run_pipeline(Batch& b, bool with_events) {
+  hipStream_t s = b.stream;
+  auto mark = [&](int k) {
+    if (with_events && b.timing) CVG_HIP(hipEventRecord(b.ev[k], s));
+  };
+  const bool mixed = b.mode != CVGRAM_MODE_FP64;
   mark(1);
-  launch_pivot(X, Y, h->dtype, mixed, N, K, M, h->d_pivot, s);
-  launch_pack(h->mode, X, Y, h->dtype, K, M, h->Kp, h->Wp, h->d_perm, h->d_chunks, h->n_chunks,
-              h->d_pivot, h->d_packed, h->d_packed_lo, h->d_part, s);
-  launch_stats_reduce(h->d_part, h->n_chunks, h->d_chunk_begin, (int32_t)P, W, h->d_fold, s);
-  launch_train_stats(h->d_fold, h->d_offsets, (int32_t)P, N, W, h->ddof, h->d_pivot,
-                     h->d_scratch, h->d_tr_sum, h->d_tr_mean, h->d_tr_std, h->d_tr_mu,
-                     h->d_tr_const, h->d_ntrain, s);
+  launch_pivot(b.dtype, mixed, b.d_pd, b.d_pivot_items, b.n_pivot_items, s);
+  launch_pack(b.mode, b.dtype, b.d_pd, b.d_chunks, b.n_chunks, b.max_pack_cb, s);
+  launch_stats_reduce(b.d_pd, b.d_fold_items, b.n_fold_items, b.max_cb64, s);
+  launch_fold_totals(b.d_pd, b.d_cb_items, b.n_cb_items, s);
+  launch_train_stats(b.d_pd, b.d_fold_items, b.n_fold_items, b.max_cb256, s);
   mark(2);
-  GramArgs ga;
-  ga.Zp = h->d_packed;
-  ga.Zlo = h->d_packed_lo;
-  ga.Wp = h->Wp;
-  ga.K = K;
-  ga.M = M;
-  ga.Kp = h->Kp;
-  ga.nt = (int32_t)nt;
-  ga.xy_diag = xy_diag ? 1 : 0;
-  ga.work = h->d_work;
-  ga.n_work = h->n_work;
-  ga.slabs = h->d_slabs;
-  launch_gram(h->mode, ga, s);
+  launch_gram(b.mode, 64, b.d_pd, b.d_work, b.n_work64, s);
+  launch_gram(b.mode, 128, b.d_pd, b.d_work + b.n_work64, b.n_work128, s);
   mark(3);
-  launch_reduce_slabs(h->d_slabs, h->n_slabs, K * W, h->d_G, s);
+  launch_reduce_slabs(b.d_pd, b.d_red_items, b.n_red_items, s);
+  if (b.batched)
+    launch_correct_batch(b.d_pd, b.d_out, b.d_corr_items, b.n_corr_items,
+                         b.mode == CVGRAM_MODE_FP64, s);
   mark(4);
+}
+
+// bookkeeping + plan + workspace for a batch whose problems are filled in
+cvgram_status prepare(Batch& b) {
+  if (b.timing)
+    for (auto& e : b.ev) CVG_HIP(hipEventCreate(&e));
+  if (b.timing) CVG_HIP(hipEventRecord(b.ev[0], b.stream));
+  b.mem.device = b.device;
+  cvgram_status st = bookkeeping(b);
+  if (st != CVGRAM_OK) return st;
+  HostLists L;
+  plan_layout(b, L);
+  allocate_and_upload(b, L);
   return CVGRAM_OK;
 }
 
-CorrectArgs base_args(const cvgram_handle* h) {
-  CorrectArgs a;
-  std::memset(&a, 0, sizeof(a));
-  a.slabs = h->d_slabs;
-  a.G = h->d_G;
-  a.slab_begin = h->d_slab_begin;
-  a.pivot = h->d_pivot;
-  a.tr_sum = h->d_tr_sum;
-  a.tr_mean = h->d_tr_mean;
-  a.tr_std = h->d_tr_std;
-  a.tr_const = h->d_tr_const;
-  a.ntrain = h->d_ntrain;
-  a.tiles = h->d_ctiles;
-  a.K = h->K;
-  a.M = h->M;
-  a.W = h->W;
-  a.n_tiles_xx = h->n_ctiles_xx;
-  a.n_tiles_xy = h->n_ctiles_xy;
-  return a;
-}
-
 bool flag01(int v) { return v == 0 || v == 1; }
+
+cvgram_status check_problem(const void* X, const void* Y, const int32_t* fold, int64_t N,
+                            int64_t K, int64_t M) {
+  if (!X || !fold) return fail(CVGRAM_EINVAL, "X or fold_id is NULL");
+  if (M > 0 && !Y) return fail(CVGRAM_EINVAL, "Y is NULL with M > 0");
+  if (N < 2 || K < 1 || M < 0) return fail(CVGRAM_EINVAL, "need N >= 2, K >= 1, M >= 0");
+  if (N > (int64_t)INT32_MAX - 1) return fail(CVGRAM_EINVAL, "N must fit in int32");
+  if (K > (int64_t)1 << 24 || M > (int64_t)1 << 24) return fail(CVGRAM_EINVAL, "K or M too large");
+  return CVGRAM_OK;
+}
 
 }  // namespace
 }  // namespace cvg
 
 using namespace cvg;
+
+// a single problem: a batch of one, plus the combination asked for at create
+struct cvgram_handle {
+  Batch b;
+  int cx = 0, sx = 0, cy = 0, sy = 0;
+};
+
+struct cvgram_batch {
+  Batch b;
+};
+
+namespace {
+
+bool out_is_f64(const Batch& b) { return b.mode == CVGRAM_MODE_FP64; }
+
+cvgram_status correct_single(cvgram_t h, int32_t p0, int32_t p1, const OutDesc& od) {
+  const ProbDesc& d = h->b.h_pd[0];
+  try {
+    launch_correct_single(h->b.d_pd, 0, d.n_ctiles_xx + d.n_ctiles_xy, od, p1 - p0,
+                          out_is_f64(h->b), h->b.stream);
+  } catch (const Fail& f) {
+    return f.st;
+  }
+  return CVGRAM_OK;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -366,10 +765,8 @@ cvgram_status cvgram_create(const void* X, const void* Y, const int32_t* fold_id
   set_error("");
   if (!out) return fail(CVGRAM_EINVAL, "out is NULL");
   *out = nullptr;
-  if (!X || !fold_id) return fail(CVGRAM_EINVAL, "X or fold_id is NULL");
-  if (M > 0 && !Y) return fail(CVGRAM_EINVAL, "Y is NULL with M > 0");
-  if (N < 2 || K < 1 || M < 0) return fail(CVGRAM_EINVAL, "need N >= 2, K >= 1, M >= 0");
-  if (N > (int64_t)INT32_MAX - 1) return fail(CVGRAM_EINVAL, "N must fit in int32");
+  cvgram_status st = check_problem(X, Y, fold_id, N, K, M);
+  if (st != CVGRAM_OK) return st;
   if (dtype != CVGRAM_F32 && dtype != CVGRAM_F64) return fail(CVGRAM_EINVAL, "bad dtype");
   if (mode != CVGRAM_MODE_FP64 && mode != CVGRAM_MODE_FP32 && mode != CVGRAM_MODE_BF16X3)
     return fail(CVGRAM_EINVAL, "bad mode");
@@ -378,29 +775,39 @@ cvgram_status cvgram_create(const void* X, const void* Y, const int32_t* fold_id
   if (ddof != 0 && ddof != 1) return fail(CVGRAM_EINVAL, "ddof must be 0 or 1");
 
   std::unique_ptr<cvgram_handle> h(new cvgram_handle());
-  h->stream = (hipStream_t)stream;
-  h->N = N;
-  h->K = K;
-  h->M = M;
-  h->W = K + M;
-  h->dtype = dtype;
-  h->mode = mode;
+  Batch& b = h->b;
+  b.stream = (hipStream_t)stream;
+  b.mode = mode;
+  b.dtype = dtype;
+  b.ddof = ddof;
+  b.batched = false;
+  b.timing = g_stage_timing.load() != 0;
   h->cx = center_x;
   h->sx = scale_x;
   h->cy = center_y;
   h->sy = scale_y;
-  h->ddof = ddof;
-  h->timing = g_stage_timing.load() != 0;
-  cvgram_status st;
+  ProbPlan p;
+  p.X = X;
+  p.Y = M > 0 ? Y : nullptr;
+  p.fold = fold_id;
+  p.N = N;
+  p.K = K;
+  p.M = M;
+  p.W = K + M;
+  b.pp.push_back(p);
   try {
-    CVG_HIP(hipGetDevice(&h->device));
-    st = build(h.get(), X, Y, fold_id);
+    CVG_HIP(hipGetDevice(&b.device));
+    st = prepare(b);
+    if (st == CVGRAM_OK && (scale_x || scale_y) && !b.pp[0].scalable)
+      st = fail(CVGRAM_ENOTSCALABLE,
+                "scaling needs |T_p| - ddof >= 1 for every fold (Definition 6)");
+    if (st == CVGRAM_OK) run_pipeline(b, true);
   } catch (const Fail& f) {
     st = f.st;
   }
   if (st != CVGRAM_OK) {
-    (void)hipStreamSynchronize(h->stream);
-    free_all(h.get());
+    (void)hipStreamSynchronize(b.stream);
+    b.release();
     return st;
   }
   *out = h.release();
@@ -409,35 +816,20 @@ cvgram_status cvgram_create(const void* X, const void* Y, const int32_t* fold_id
 
 cvgram_status cvgram_num_folds(cvgram_t h, int32_t* P) {
   if (!h || !P) return fail(CVGRAM_EINVAL, "NULL argument");
-  *P = h->P;
+  *P = h->b.pp[0].P;
   return CVGRAM_OK;
 }
 
 cvgram_status cvgram_partition(cvgram_t h, int32_t* perm, int64_t* offsets) {
   if (!h) return fail(CVGRAM_EINVAL, "NULL handle");
+  const ProbPlan& p = h->b.pp[0];
   try {
     if (perm)
-      CVG_HIP(hipMemcpyAsync(perm, h->d_perm, h->N * sizeof(int32_t), hipMemcpyDeviceToDevice,
-                             h->stream));
+      CVG_HIP(hipMemcpyAsync(perm, p.d_perm, p.N * sizeof(int32_t), hipMemcpyDeviceToDevice,
+                             h->b.stream));
     if (offsets)
-      CVG_HIP(hipMemcpyAsync(offsets, h->d_offsets, (h->P + 1) * sizeof(int64_t),
-                             hipMemcpyDeviceToDevice, h->stream));
-  } catch (const Fail& f) {
-    return f.st;
-  }
-  return CVGRAM_OK;
-}
-
-static cvgram_status run_correct(cvgram_t h, int32_t p0, int32_t p1, void* const* xx,
-                                 void* const* xy) {
-  CorrectArgs a = base_args(h);
-  a.p_begin = p0;
-  for (int c = 0; c < CVGRAM_XTX_CLASSES; ++c) a.out_xx[c] = xx[c];
-  for (int c = 0; c < CVGRAM_XTY_CLASSES; ++c) a.out_xy[c] = xy[c];
-  a.fold_stride_xx = 0;
-  a.fold_stride_xy = 0;
-  try {
-    launch_correct(a, p1 - p0, out_is_f64(h), h->stream);
+      CVG_HIP(hipMemcpyAsync(offsets, h->b.h_pd[0].offsets, (p.P + 1) * sizeof(int64_t),
+                             hipMemcpyDeviceToDevice, h->b.stream));
   } catch (const Fail& f) {
     return f.st;
   }
@@ -447,17 +839,18 @@ static cvgram_status run_correct(cvgram_t h, int32_t p0, int32_t p1, void* const
 cvgram_status cvgram_fold_combo(cvgram_t h, int32_t p, int center_x, int scale_x, int center_y,
                                 int scale_y, void* out_XtX, void* out_XtY) {
   if (!h) return fail(CVGRAM_EINVAL, "NULL handle");
-  if (p < 0 || p >= h->P) return fail(CVGRAM_ERANGE, "fold index out of range");
+  const ProbPlan& pp = h->b.pp[0];
+  if (p < 0 || p >= pp.P) return fail(CVGRAM_ERANGE, "fold index out of range");
   if (!flag01(center_x) || !flag01(scale_x) || !flag01(center_y) || !flag01(scale_y))
     return fail(CVGRAM_EINVAL, "centering/scaling flags must be 0 or 1");
-  if ((scale_x || scale_y) && !h->scalable)
+  if ((scale_x || scale_y) && !pp.scalable)
     return fail(CVGRAM_ENOTSCALABLE, "partitioning is not scalable for this ddof");
-  void* xx[CVGRAM_XTX_CLASSES] = {nullptr, nullptr, nullptr, nullptr};
-  void* xy[CVGRAM_XTY_CLASSES] = {nullptr, nullptr, nullptr, nullptr,
-                                  nullptr, nullptr, nullptr, nullptr};
-  xx[2 * center_x + scale_x] = out_XtX;
-  if (h->M > 0) xy[4 * (center_x | center_y) + 2 * scale_x + scale_y] = out_XtY;
-  return run_correct(h, p, p + 1, xx, xy);
+  OutDesc od;
+  std::memset(&od, 0, sizeof(od));
+  od.xx[2 * center_x + scale_x] = out_XtX;
+  if (pp.M > 0) od.xy[4 * (center_x | center_y) + 2 * scale_x + scale_y] = out_XtY;
+  od.p_begin = p;
+  return correct_single(h, p, p + 1, od);
 }
 
 cvgram_status cvgram_fold(cvgram_t h, int32_t p, void* out_XtX, void* out_XtY) {
@@ -468,40 +861,32 @@ cvgram_status cvgram_fold(cvgram_t h, int32_t p, void* out_XtX, void* out_XtY) {
 cvgram_status cvgram_folds_all(cvgram_t h, int32_t p_begin, int32_t p_end, void* out_XtX,
                                void* out_XtY) {
   if (!h) return fail(CVGRAM_EINVAL, "NULL handle");
-  if (p_begin < 0 || p_end > h->P || p_begin > p_end)
+  const ProbPlan& pp = h->b.pp[0];
+  if (p_begin < 0 || p_end > pp.P || p_begin > p_end)
     return fail(CVGRAM_ERANGE, "fold range out of bounds");
   if (p_begin == p_end) return CVGRAM_OK;
-  CorrectArgs a = base_args(h);
-  a.p_begin = p_begin;
-  const size_t es = out_is_f64(h) ? sizeof(double) : sizeof(float);
-  const int64_t KK = h->K * h->K, KM = h->K * h->M;
-  for (int c = 0; c < CVGRAM_XTX_CLASSES; ++c) {
-    const bool scaled = c & 1;
-    a.out_xx[c] = (out_XtX && (h->scalable || !scaled)) ? (char*)out_XtX + c * KK * es : nullptr;
-  }
-  for (int c = 0; c < CVGRAM_XTY_CLASSES; ++c) {
-    const bool scaled = c & 3;
-    a.out_xy[c] = (out_XtY && h->M > 0 && (h->scalable || !scaled))
-                      ? (char*)out_XtY + c * KM * es
-                      : nullptr;
-  }
-  a.fold_stride_xx = CVGRAM_XTX_CLASSES * KK;
-  a.fold_stride_xy = CVGRAM_XTY_CLASSES * KM;
-  try {
-    launch_correct(a, p_end - p_begin, out_is_f64(h), h->stream);
-  } catch (const Fail& f) {
-    return f.st;
-  }
-  return CVGRAM_OK;
+  OutDesc od;
+  std::memset(&od, 0, sizeof(od));
+  const size_t es = out_is_f64(h->b) ? sizeof(double) : sizeof(float);
+  const int64_t KK = pp.K * pp.K, KM = pp.K * pp.M;
+  for (int c = 0; c < CVGRAM_XTX_CLASSES; ++c)
+    od.xx[c] = (out_XtX && (pp.scalable || !(c & 1))) ? (char*)out_XtX + c * KK * es : nullptr;
+  for (int c = 0; c < CVGRAM_XTY_CLASSES; ++c)
+    od.xy[c] = (out_XtY && pp.M > 0 && (pp.scalable || !(c & 3))) ? (char*)out_XtY + c * KM * es
+                                                                 : nullptr;
+  od.fold_stride_xx = CVGRAM_XTX_CLASSES * KK;
+  od.fold_stride_xy = CVGRAM_XTY_CLASSES * KM;
+  od.p_begin = p_begin;
+  return correct_single(h, p_begin, p_end, od);
 }
 
 cvgram_status cvgram_fold_stats(cvgram_t h, int32_t p, double* mean_x, double* std_x,
                                 double* mean_y, double* std_y) {
   if (!h) return fail(CVGRAM_EINVAL, "NULL handle");
-  if (p < 0 || p >= h->P) return fail(CVGRAM_ERANGE, "fold index out of range");
+  const ProbDesc& d = h->b.h_pd[0];
+  if (p < 0 || p >= d.P) return fail(CVGRAM_ERANGE, "fold index out of range");
   try {
-    launch_fold_stats(h->d_tr_mu, h->d_tr_std, p, h->K, h->M, mean_x, std_x, mean_y, std_y,
-                      h->stream);
+    launch_fold_stats(d.tr_mu, d.tr_std, p, d.K, d.M, mean_x, std_x, mean_y, std_y, h->b.stream);
   } catch (const Fail& f) {
     return f.st;
   }
@@ -515,12 +900,12 @@ cvgram_status cvgram_set_stage_timing(int on) {
 
 cvgram_status cvgram_stage_times(cvgram_t h, double* ms, int32_t n) {
   if (!h || (!ms && n > 0)) return fail(CVGRAM_EINVAL, "NULL argument");
-  if (!h->timing) return fail(CVGRAM_EINVAL, "handle created without stage timing");
+  if (!h->b.timing) return fail(CVGRAM_EINVAL, "handle created without stage timing");
   try {
-    CVG_HIP(hipEventSynchronize(h->ev[4]));
+    CVG_HIP(hipEventSynchronize(h->b.ev[4]));
     for (int k = 0; k < 4 && k < n; ++k) {
       float t = 0.f;
-      CVG_HIP(hipEventElapsedTime(&t, h->ev[k], h->ev[k + 1]));
+      CVG_HIP(hipEventElapsedTime(&t, h->b.ev[k], h->b.ev[k + 1]));
       ms[k] = t;
     }
   } catch (const Fail& f) {
@@ -532,22 +917,215 @@ cvgram_status cvgram_stage_times(cvgram_t h, double* ms, int32_t n) {
 cvgram_status cvgram_trim_cache(void) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return fail(CVGRAM_EDEVICE, "hipGetDevice failed");
-  cache_trim(dev);
+  cache_trim_dev(dev);
   return CVGRAM_OK;
 }
 
 cvgram_status cvgram_set_stream(cvgram_t h, void* stream) {
   if (!h) return fail(CVGRAM_EINVAL, "NULL handle");
-  h->stream = (hipStream_t)stream;
+  h->b.stream = (hipStream_t)stream;
   return CVGRAM_OK;
 }
 
 cvgram_status cvgram_destroy(cvgram_t h) {
   if (!h) return CVGRAM_OK;
-  hipError_t e = hipStreamSynchronize(h->stream);
-  free_all(h);
+  hipError_t e = hipStreamSynchronize(h->b.stream);
+  h->b.release();
   delete h;
   if (e != hipSuccess) return fail(CVGRAM_EDEVICE, hipGetErrorString(e));
+  return CVGRAM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// batched form
+// ---------------------------------------------------------------------------
+cvgram_status cvgram_batch_create(const cvgram_problem* problems, int32_t n, cvgram_dtype dtype,
+                                  int ddof, cvgram_mode mode, void* stream, cvgram_batch_t* out) {
+  set_error("");
+  if (!out) return fail(CVGRAM_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!problems || n < 1) return fail(CVGRAM_EINVAL, "need at least one problem");
+  if (dtype != CVGRAM_F32 && dtype != CVGRAM_F64) return fail(CVGRAM_EINVAL, "bad dtype");
+  if (mode != CVGRAM_MODE_FP64 && mode != CVGRAM_MODE_FP32 && mode != CVGRAM_MODE_BF16X3)
+    return fail(CVGRAM_EINVAL, "bad mode");
+  if (ddof != 0 && ddof != 1) return fail(CVGRAM_EINVAL, "ddof must be 0 or 1");
+  for (int32_t i = 0; i < n; ++i) {
+    const cvgram_problem& q = problems[i];
+    cvgram_status st = check_problem(q.X, q.Y, q.fold_id, q.N, q.K, q.M);
+    if (st != CVGRAM_OK) return fail(st, "problem " + std::to_string(i) + ": " + g_last_error);
+  }
+  std::unique_ptr<cvgram_batch> bb(new cvgram_batch());
+  Batch& b = bb->b;
+  b.stream = (hipStream_t)stream;
+  b.mode = mode;
+  b.dtype = dtype;
+  b.ddof = ddof;
+  b.batched = true;
+  for (int32_t i = 0; i < n; ++i) {
+    const cvgram_problem& q = problems[i];
+    ProbPlan p;
+    p.X = q.X;
+    p.Y = q.M > 0 ? q.Y : nullptr;
+    p.fold = q.fold_id;
+    p.N = q.N;
+    p.K = q.K;
+    p.M = q.M;
+    p.W = q.K + q.M;
+    p.out_xx = q.out_XtX;
+    p.out_xy = q.out_XtY;
+    b.pp.push_back(p);
+  }
+  cvgram_status st = CVGRAM_OK;
+  try {
+    CVG_HIP(hipGetDevice(&b.device));
+    st = prepare(b);
+    if (st == CVGRAM_OK) {
+      // The caller's stream may be the legacy null stream, which cannot be
+      // captured: capture on a private stream (default priority) and replay
+      // on the caller's stream.
+      CVG_HIP(hipStreamSynchronize(b.stream));  // the plan upload precedes capture
+      hipStream_t user = b.stream, cap = nullptr;
+      CVG_HIP(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+      b.stream = cap;
+      hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+      if (e == hipSuccess) {
+        try {
+          run_pipeline(b, false);
+          e = hipStreamEndCapture(cap, &b.graph);
+        } catch (const Fail&) {
+          hipGraph_t g = nullptr;
+          (void)hipStreamEndCapture(cap, &g);
+          if (g) (void)hipGraphDestroy(g);
+          b.stream = user;
+          (void)hipStreamDestroy(cap);
+          throw;
+        }
+      }
+      b.stream = user;
+      (void)hipStreamDestroy(cap);
+      CVG_HIP(e);
+      CVG_HIP(hipGraphInstantiate(&b.gexec, b.graph, nullptr, nullptr, 0));
+    }
+  } catch (const Fail& f) {
+    st = f.st;
+  }
+  if (st != CVGRAM_OK) {
+    (void)hipStreamSynchronize(b.stream);
+    b.release();
+    return st;
+  }
+  *out = bb.release();
+  return CVGRAM_OK;
+}
+
+cvgram_status cvgram_batch_run(cvgram_batch_t bb) {
+  if (!bb) return fail(CVGRAM_EINVAL, "NULL batch");
+  hipError_t e = hipGraphLaunch(bb->b.gexec, bb->b.stream);
+  if (e != hipSuccess) return fail(CVGRAM_EDEVICE, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
+  return CVGRAM_OK;
+}
+
+cvgram_status cvgram_batch_run_eager(cvgram_batch_t bb) {
+  if (!bb) return fail(CVGRAM_EINVAL, "NULL batch");
+  try {
+    run_pipeline(bb->b, false);
+  } catch (const Fail& f) {
+    return f.st;
+  }
+  return CVGRAM_OK;
+}
+
+cvgram_status cvgram_batch_problem_info(cvgram_batch_t bb, int32_t i, int32_t* P,
+                                        int32_t* scalable) {
+  if (!bb) return fail(CVGRAM_EINVAL, "NULL batch");
+  if (i < 0 || i >= (int32_t)bb->b.pp.size()) return fail(CVGRAM_ERANGE, "problem index out of range");
+  if (P) *P = bb->b.pp[i].P;
+  if (scalable) *scalable = bb->b.pp[i].scalable ? 1 : 0;
+  return CVGRAM_OK;
+}
+
+cvgram_status cvgram_batch_destroy(cvgram_batch_t bb) {
+  if (!bb) return CVGRAM_OK;
+  hipError_t e = hipStreamSynchronize(bb->b.stream);
+  bb->b.release();
+  delete bb;
+  if (e != hipSuccess) return fail(CVGRAM_EDEVICE, hipGetErrorString(e));
+  return CVGRAM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// autotuner
+// ---------------------------------------------------------------------------
+cvgram_status cvgram_autotune(const void* X, const void* Y, const int32_t* fold_id, int64_t N,
+                              int64_t K, int64_t M, cvgram_dtype dtype, cvgram_mode mode,
+                              void* stream, int32_t* tile, int32_t* target_items) {
+  set_error("");
+  cvgram_status st = check_problem(X, Y, fold_id, N, K, M);
+  if (st != CVGRAM_OK) return st;
+  if (dtype != CVGRAM_F32 && dtype != CVGRAM_F64) return fail(CVGRAM_EINVAL, "bad dtype");
+  if (mode != CVGRAM_MODE_FP64 && mode != CVGRAM_MODE_FP32 && mode != CVGRAM_MODE_BF16X3)
+    return fail(CVGRAM_EINVAL, "bad mode");
+  const int tiles[2] = {64, 128};
+  const int64_t items[4] = {512, 1024, 2048, 4096};
+  Config best;
+  double best_ms = 1e300;
+  try {
+    for (int ti = 0; ti < 2; ++ti) {
+      if (tiles[ti] == 64 && K > 1024) continue;  // too many tiles to pay off
+      for (int ii = 0; ii < 4; ++ii) {
+        Batch b;
+        b.stream = (hipStream_t)stream;
+        b.mode = mode;
+        b.dtype = dtype;
+        b.ddof = 1;
+        b.timing = true;
+        b.force_cfg = true;
+        b.forced.tile = tiles[ti];
+        b.forced.target_items = items[ii];
+        ProbPlan p;
+        p.X = X;
+        p.Y = M > 0 ? Y : nullptr;
+        p.fold = fold_id;
+        p.N = N;
+        p.K = K;
+        p.M = M;
+        p.W = K + M;
+        b.pp.push_back(p);
+        CVG_HIP(hipGetDevice(&b.device));
+        st = prepare(b);
+        if (st != CVGRAM_OK) {
+          b.release();
+          return st;
+        }
+        run_pipeline(b, true);   // warm
+        double ms = 1e300;
+        for (int rep = 0; rep < 3; ++rep) {
+          run_pipeline(b, true);
+          CVG_HIP(hipEventSynchronize(b.ev[4]));
+          float t = 0.f;
+          CVG_HIP(hipEventElapsedTime(&t, b.ev[1], b.ev[4]));
+          ms = std::min(ms, (double)t);
+        }
+        CVG_HIP(hipStreamSynchronize(b.stream));
+        b.release();
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = b.forced;
+        }
+      }
+    }
+  } catch (const Fail& f) {
+    return f.st;
+  }
+  {
+    TuneTable& tt = tune_table();
+    std::lock_guard<std::mutex> g(tt.mu);
+    tune_load_locked(tt);
+    tt.t[tune_key(mode, dtype, K, M, N)] = best;
+    tune_save_locked(tt);
+  }
+  if (tile) *tile = best.tile;
+  if (target_items) *target_items = (int32_t)best.target_items;
   return CVGRAM_OK;
 }
 
@@ -566,6 +1144,6 @@ const char* cvgram_status_string(cvgram_status s) {
 
 const char* cvgram_last_error_message(void) { return g_last_error.c_str(); }
 
-int32_t cvgram_version(void) { return 100; }
+int32_t cvgram_version(void) { return 200; }
 
 }  // extern "C"

@@ -24,43 +24,45 @@ constexpr int TS = kCorrTile;  // 32
 constexpr int kThreads = 256;
 constexpr int kRowsPerThread = TS * TS / kThreads;  // 4
 
-__global__ __launch_bounds__(256) void reduce_slabs_kernel(const double* __restrict__ slabs,
-                                                           int64_t n_slabs, int64_t elems,
-                                                           double* __restrict__ G) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// For every fold p, G'_p = sum of the fold's slabs (its row splits), written
+// into the fold's first slab; G' = sum over folds in fold order.  Entries
+// below the diagonal of the K x K block are never read (mirror image) and
+// are skipped.  Fixed summation order: deterministic.
+// items: (prob, block of 256 entries of the K x W slab)
+__global__ __launch_bounds__(256) void reduce_slabs_kernel(const ProbDesc* __restrict__ pds,
+                                                           const Item* __restrict__ items) {
+  const Item it = items[blockIdx.x];
+  const ProbDesc& pd = pds[it.prob];
+  const int64_t K = pd.K, W = pd.W, elems = K * W;
+  const int64_t e = (int64_t)it.a * 256 + threadIdx.x;
   if (e >= elems) return;
-  double s = 0.0;
-  for (int64_t k = 0; k < n_slabs; ++k) s += slabs[k * elems + e];
-  G[e] = s;
-}
-
-template <typename OutT>
-__device__ void correct_tile(const CorrectArgs& A, int32_t f);
-
-// grid.x = tiles, grid.y strides over the folds (a grid dimension other than
-// x is limited to 65535 blocks)
-template <typename OutT>
-__global__ __launch_bounds__(kThreads) void correct_kernel(CorrectArgs A, int32_t n_folds) {
-  for (int32_t f = blockIdx.y; f < n_folds; f += gridDim.y) {
-    correct_tile<OutT>(A, f);
-    __syncthreads();
+  const int64_t i = e / W, j = e - (e / W) * W;
+  if (j < K && j < i) return;
+  double* slabs = pd.slabs;
+  double g = 0.0;
+  for (int32_t p = 0; p < pd.P; ++p) {
+    const int32_t a = pd.slab_begin[p], b = pd.slab_begin[p + 1];
+    double f = slabs[(int64_t)a * elems + e];
+    for (int32_t k = a + 1; k < b; ++k) f += slabs[(int64_t)k * elems + e];
+    if (b > a + 1) slabs[(int64_t)a * elems + e] = f;
+    g += f;
   }
+  pd.G[e] = g;
 }
 
 template <typename OutT>
-__device__ void correct_tile(const CorrectArgs& A, int32_t f) {
-  const int32_t p = A.p_begin + f;
+__device__ void correct_tile(const ProbDesc& pd, const OutDesc& od, int32_t f, int tile) {
   __shared__ double T[TS][TS + 1];
   __shared__ double rc[TS], ra[TS], rmu[TS], rsd[TS];
   __shared__ double cc[TS], ca[TS], cmu[TS], csd[TS];
   __shared__ uint8_t rcs[TS], ccs[TS];
 
-  const int tile = blockIdx.x;
-  const bool is_xy = tile >= A.n_tiles_xx;
-  const int bi = A.tiles[2 * tile];
-  const int bj = A.tiles[2 * tile + 1];
+  const int32_t p = od.p_begin + f;
+  const bool is_xy = tile >= pd.n_ctiles_xx;
+  const int bi = pd.ctiles[2 * tile];
+  const int bj = pd.ctiles[2 * tile + 1];
   const bool diag = !is_xy && bi == bj;
-  const int64_t K = A.K, M = A.M, W = A.W;
+  const int64_t K = pd.K, M = pd.M, W = pd.W;
   const int64_t ncols = is_xy ? M : K;
   const int64_t coff = is_xy ? K : 0;  // column offset of the tile inside Z
 
@@ -70,29 +72,28 @@ __device__ void correct_tile(const CorrectArgs& A, int32_t f) {
   if (t < TS) {
     const int64_t i = (int64_t)bi * TS + t;
     if (i < K) {
-      rc[t] = A.pivot[i];
-      ra[t] = A.tr_sum[pw + i];
-      rmu[t] = A.tr_mean[pw + i];
-      rsd[t] = A.tr_std[pw + i];
-      rcs[t] = A.tr_const[pw + i];
+      rc[t] = pd.pivot[i];
+      ra[t] = pd.tr_sum[pw + i];
+      rmu[t] = pd.tr_mean[pw + i];
+      rsd[t] = pd.tr_std[pw + i];
+      rcs[t] = pd.tr_const[pw + i];
     }
   } else if (t < 2 * TS) {
     const int u = t - TS;
     const int64_t j = (int64_t)bj * TS + u;
     if (j < ncols) {
       const int64_t z = coff + j;
-      cc[u] = A.pivot[z];
-      ca[u] = A.tr_sum[pw + z];
-      cmu[u] = A.tr_mean[pw + z];
-      csd[u] = A.tr_std[pw + z];
-      ccs[u] = A.tr_const[pw + z];
+      cc[u] = pd.pivot[z];
+      ca[u] = pd.tr_sum[pw + z];
+      cmu[u] = pd.tr_mean[pw + z];
+      csd[u] = pd.tr_std[pw + z];
+      ccs[u] = pd.tr_const[pw + z];
     }
   }
   __syncthreads();
 
-  const double NT = (double)A.ntrain[p];
-  const int32_t sb = A.slab_begin[p], se = A.slab_begin[p + 1];
-  const int64_t slab_elems = K * W;
+  const double NT = (double)pd.ntrain[p];
+  const double* gp_slab = pd.slabs + (int64_t)pd.slab_begin[p] * K * W;  // fold sum G'_p
 
   double raw[kRowsPerThread], cen[kRowsPerThread];
   bool ok[kRowsPerThread];
@@ -106,18 +107,16 @@ __device__ void correct_tile(const CorrectArgs& A, int32_t f) {
     cen[r] = 0.0;
     if (!ok[r]) continue;
     const int64_t e = i * W + coff + j;
-    double gp = 0.0;
-    for (int32_t s = sb; s < se; ++s) gp += A.slabs[(int64_t)s * slab_elems + e];
-    const double g = A.G[e] - gp;
+    const double g = pd.G[e] - gp_slab[e];
     raw[r] = g + (rc[il] * ca[jl] + ra[il] * cc[jl]) + NT * (rc[il] * cc[jl]);
     cen[r] = (rcs[il] || ccs[jl]) ? 0.0 : g - NT * (rmu[il] * cmu[jl]);
   }
 
   if (!is_xy) {
     for (int c = 0; c < CVGRAM_XTX_CLASSES; ++c) {
-      OutT* out = (OutT*)A.out_xx[c];
+      OutT* out = (OutT*)od.xx[c];
       if (!out) continue;
-      out += (int64_t)f * A.fold_stride_xx;
+      out += (int64_t)f * od.fold_stride_xx;
       const bool centred = c & 2, scaled = c & 1;
       double v[kRowsPerThread];
 #pragma unroll
@@ -147,9 +146,9 @@ __device__ void correct_tile(const CorrectArgs& A, int32_t f) {
     }
   } else {
     for (int c = 0; c < CVGRAM_XTY_CLASSES; ++c) {
-      OutT* out = (OutT*)A.out_xy[c];
+      OutT* out = (OutT*)od.xy[c];
       if (!out) continue;
-      out += (int64_t)f * A.fold_stride_xy;
+      out += (int64_t)f * od.fold_stride_xy;
       const bool centred = c & 4, scx = c & 2, scy = c & 1;
 #pragma unroll
       for (int r = 0; r < kRowsPerThread; ++r) {
@@ -165,22 +164,54 @@ __device__ void correct_tile(const CorrectArgs& A, int32_t f) {
   }
 }
 
+// one problem: grid.x = its correction tiles, grid.y strides over the folds
+// (a grid dimension other than x is limited to 65535 blocks)
+template <typename OutT>
+__global__ __launch_bounds__(kThreads) void correct_single_kernel(const ProbDesc* __restrict__ pds,
+                                                                  int32_t prob, OutDesc od,
+                                                                  int32_t n_folds) {
+  const ProbDesc& pd = pds[prob];
+  for (int32_t f = blockIdx.y; f < n_folds; f += gridDim.y) {
+    correct_tile<OutT>(pd, od, f, blockIdx.x);
+    __syncthreads();
+  }
+}
+
+// many problems: items (prob, fold, tile), outputs of every fold
+template <typename OutT>
+__global__ __launch_bounds__(kThreads) void correct_batch_kernel(const ProbDesc* __restrict__ pds,
+                                                                 const OutDesc* __restrict__ outs,
+                                                                 const Item* __restrict__ items) {
+  const Item it = items[blockIdx.x];
+  correct_tile<OutT>(pds[it.prob], outs[it.prob], it.a, it.b);
+}
+
 }  // namespace
 
-void launch_reduce_slabs(const double* slabs, int64_t n_slabs, int64_t elems, double* G,
-                         hipStream_t s) {
-  reduce_slabs_kernel<<<(unsigned)((elems + 255) / 256), 256, 0, s>>>(slabs, n_slabs, elems, G);
+void launch_reduce_slabs(const ProbDesc* pd, const Item* items, int64_t n_items, hipStream_t s) {
+  if (n_items <= 0) return;
+  reduce_slabs_kernel<<<(unsigned)n_items, 256, 0, s>>>(pd, items);
   CVG_LAUNCH_CHECK();
 }
 
-void launch_correct(const CorrectArgs& a, int32_t n_folds, bool out_f64, hipStream_t s) {
-  const int32_t tiles = a.n_tiles_xx + a.n_tiles_xy;
-  if (tiles <= 0 || n_folds <= 0) return;
-  dim3 grid((unsigned)tiles, (unsigned)(n_folds < 65535 ? n_folds : 65535));
+void launch_correct_single(const ProbDesc* pd, int32_t prob, int32_t n_tiles, const OutDesc& out,
+                           int32_t n_folds, bool out_f64, hipStream_t s) {
+  if (n_tiles <= 0 || n_folds <= 0) return;
+  dim3 grid((unsigned)n_tiles, (unsigned)(n_folds < 65535 ? n_folds : 65535));
   if (out_f64)
-    correct_kernel<double><<<grid, kThreads, 0, s>>>(a, n_folds);
+    correct_single_kernel<double><<<grid, kThreads, 0, s>>>(pd, prob, out, n_folds);
   else
-    correct_kernel<float><<<grid, kThreads, 0, s>>>(a, n_folds);
+    correct_single_kernel<float><<<grid, kThreads, 0, s>>>(pd, prob, out, n_folds);
+  CVG_LAUNCH_CHECK();
+}
+
+void launch_correct_batch(const ProbDesc* pd, const OutDesc* outs, const Item* items,
+                          int64_t n_items, bool out_f64, hipStream_t s) {
+  if (n_items <= 0) return;
+  if (out_f64)
+    correct_batch_kernel<double><<<(unsigned)n_items, kThreads, 0, s>>>(pd, outs, items);
+  else
+    correct_batch_kernel<float><<<(unsigned)n_items, kThreads, 0, s>>>(pd, outs, items);
   CVG_LAUNCH_CHECK();
 }
 

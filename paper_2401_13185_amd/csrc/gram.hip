@@ -3,15 +3,16 @@
 //
 // For every fold p (Algorithm 7 step 8, Lemmas 2-3) the library needs
 // G'_p = Z'_{V_p}^T Z'_{V_p} restricted to its first K rows, Z' being the
-// pivot-shifted data.  All folds run in ONE launch over a work list of
-// (fold, packed row range, output tile) items; a fold's rows are contiguous
-// and zero-padded in the packed panels, so an item streams aligned 16-byte
-// vector loads with no gathers and no bounds checks.  Output tiles are
-// 128 x 128: every tile on or above the diagonal of the K x K block; the
-// K x M block is computed by the otherwise idle lower-left wave of each
-// diagonal tile when M <= 32 (so no extra pass over X), else by separate
-// tiles.  Each item writes its FP64 tile to its own slab (summed later in a
-// fixed order: deterministic, no floating-point atomics).
+// pivot-shifted data.  All folds of all problems run in ONE launch over a
+// work list of (problem, fold row range, output tile) items; a fold's rows
+// are contiguous and zero-padded in the packed panels, so an item streams
+// aligned 16-byte vector loads with no gathers and no bounds checks.
+// Output tiles are BM x BM (BM = 64 or 128, chosen per problem): every tile
+// on or above the diagonal of the K x K block; the K x M block is computed
+// by the otherwise idle lower-left wave of each diagonal tile when M <= 32
+// (so no extra pass over X), else by separate tiles.  Each item writes its
+// FP64 tile to its own slab (summed later in a fixed order: deterministic,
+// no floating-point atomics).
 //
 // Arithmetic per mode:
 //   FP64    v_mfma_f64_16x16x4_f64 on FP64 panels, FP64 accumulation.
@@ -37,36 +38,31 @@ typedef float float4_t __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 
 constexpr int kThreads = 256;
-constexpr int BM = kGramTile;      // 128
-constexpr int kWT = BM / 2;        // wave tile edge (64)
 constexpr int kYW = kYDiagCols;    // Y columns handled inside diagonal tiles (32)
 constexpr int kFlushRows = 256;
 
 template <int MODE>
 struct Mode;
-
 template <>
 struct Mode<CVGRAM_MODE_FP64> {
   typedef double E;
   typedef double4_t Acc;
   static constexpr int BK = 16;
-  static constexpr int LDA = BM + 4;    // doubles per LDS row of an operand tile
-  static constexpr int LDY = kYW + 4;
+  static constexpr int PAD = 4;       // doubles of padding per LDS row
 };
 template <>
 struct Mode<CVGRAM_MODE_FP32> {
   typedef float E;
   typedef float4_t Acc;
   static constexpr int BK = 16;
-  static constexpr int LDA = BM + 16;   // 576-byte rows: the 4 row groups of a
-  static constexpr int LDY = kYW + 16;  // fragment read hit different banks
-};
+  static constexpr int PAD = 16;      // rows of 144 / 80 floats: the 4 row groups of a
+};                                    // fragment read fall in different banks
 template <>
 struct Mode<CVGRAM_MODE_BF16X3> {
   typedef __bf16 E;
   typedef float4_t Acc;
   static constexpr int BK = 32;
-  static constexpr int LDK = BK + 8;    // 80-byte columns: conflict-free 16-byte reads
+  static constexpr int LDK = BK + 8;  // 80-byte columns: conflict-free 16-byte reads
 };
 
 // row of element e of lane l's accumulator inside a 16 x 16 MFMA block
@@ -75,109 +71,107 @@ __device__ inline int acc_row(int e, int fr) {
   return MODE == CVGRAM_MODE_FP64 ? 4 * e + fr : 4 * fr + e;
 }
 
-template <int MODE>
-struct Smem;
-
-template <>
-struct Smem<CVGRAM_MODE_FP64> {
-  double a[2][16 * Mode<CVGRAM_MODE_FP64>::LDA];
-  double b[2][16 * Mode<CVGRAM_MODE_FP64>::LDA];
-  double y[2][16 * Mode<CVGRAM_MODE_FP64>::LDY];
+template <int MODE, int BM>
+struct Smem {
+  static constexpr int LDA = BM + Mode<MODE>::PAD;
+  static constexpr int LDY = kYW + Mode<MODE>::PAD;
+  typename Mode<MODE>::E a[2][16 * LDA];
+  typename Mode<MODE>::E b[2][16 * LDA];
+  typename Mode<MODE>::E y[2][16 * LDY];
 };
-template <>
-struct Smem<CVGRAM_MODE_FP32> {
-  float a[2][16 * Mode<CVGRAM_MODE_FP32>::LDA];
-  float b[2][16 * Mode<CVGRAM_MODE_FP32>::LDA];
-  float y[2][16 * Mode<CVGRAM_MODE_FP32>::LDY];
-};
-template <>
-struct Smem<CVGRAM_MODE_BF16X3> {
+template <int BM>
+struct Smem<CVGRAM_MODE_BF16X3, BM> {
+  static constexpr int LDK = Mode<CVGRAM_MODE_BF16X3>::LDK;
   // [buffer][hi/lo][column * LDK + k]
-  __bf16 a[2][2][BM * Mode<CVGRAM_MODE_BF16X3>::LDK];
-  __bf16 b[2][2][BM * Mode<CVGRAM_MODE_BF16X3>::LDK];
-  __bf16 y[2][2][kYW * Mode<CVGRAM_MODE_BF16X3>::LDK];
+  __bf16 a[2][2][BM * LDK];
+  __bf16 b[2][2][BM * LDK];
+  __bf16 y[2][2][kYW * LDK];
 };
 
 // ---------------------------------------------------------------------------
 // global -> register staging of one stage (BK packed rows starting at row r)
 // ---------------------------------------------------------------------------
-template <int MODE>
+template <int MODE, int BM>
 struct Stage;
 
-// FP64: operand block BK x 128 doubles = 4 x 16 B per thread; Y block
-// BK x 32 doubles = 1 x 16 B per thread.
-template <>
-struct Stage<CVGRAM_MODE_FP64> {
-  double2_t a[4], b[4], y;
+// FP64: an operand block is 16 x BM doubles, BM / 16 per thread; the Y block
+// 16 x 32 doubles, one 16-byte pair per thread.
+template <int BM>
+struct Stage<CVGRAM_MODE_FP64, BM> {
+  static constexpr int V = BM / 32;  // double2 per thread per operand
+  double2_t a[V], b[V], y;
   __device__ void load(const double* Z, int64_t Wp, int64_t r, int64_t ca, int64_t cb,
                        int64_t cy, bool ld_b, bool ld_y, int t) {
-    const int row = t >> 4, col = (t & 15) * 8;
+    const int row = t >> 4, col = (t & 15) * (BM / 16);
     const double* pa = Z + (r + row) * Wp + ca + col;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) a[u] = *(const double2_t*)(pa + 2 * u);
+    for (int u = 0; u < V; ++u) a[u] = *(const double2_t*)(pa + 2 * u);
     if (ld_b) {
       const double* pb = Z + (r + row) * Wp + cb + col;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) b[u] = *(const double2_t*)(pb + 2 * u);
+      for (int u = 0; u < V; ++u) b[u] = *(const double2_t*)(pb + 2 * u);
     }
     if (ld_y) y = *(const double2_t*)(Z + (r + row) * Wp + cy + (t & 15) * 2);
   }
-  __device__ void store(Smem<CVGRAM_MODE_FP64>& s, int buf, bool st_b, bool st_y, int t) const {
-    constexpr int LDA = Mode<CVGRAM_MODE_FP64>::LDA, LDY = Mode<CVGRAM_MODE_FP64>::LDY;
-    const int row = t >> 4, col = (t & 15) * 8;
+  __device__ void store(Smem<CVGRAM_MODE_FP64, BM>& s, int buf, bool st_b, bool st_y,
+                        int t) const {
+    constexpr int LDA = Smem<CVGRAM_MODE_FP64, BM>::LDA, LDY = Smem<CVGRAM_MODE_FP64, BM>::LDY;
+    const int row = t >> 4, col = (t & 15) * (BM / 16);
 #pragma unroll
-    for (int u = 0; u < 4; ++u) *(double2_t*)&s.a[buf][row * LDA + col + 2 * u] = a[u];
+    for (int u = 0; u < V; ++u) *(double2_t*)&s.a[buf][row * LDA + col + 2 * u] = a[u];
     if (st_b)
 #pragma unroll
-      for (int u = 0; u < 4; ++u) *(double2_t*)&s.b[buf][row * LDA + col + 2 * u] = b[u];
+      for (int u = 0; u < V; ++u) *(double2_t*)&s.b[buf][row * LDA + col + 2 * u] = b[u];
     if (st_y) *(double2_t*)&s.y[buf][row * LDY + (t & 15) * 2] = y;
   }
 };
 
-// FP32: operand block BK x 128 floats = 2 x 16 B per thread; Y block
-// BK x 32 floats = 16 B for threads 0..127.
-template <>
-struct Stage<CVGRAM_MODE_FP32> {
-  float4_t a[2], b[2], y;
+// FP32: an operand block is 16 x BM floats, BM / 16 per thread; the Y block
+// 16 x 32 floats, 16 bytes for threads 0..127.
+template <int BM>
+struct Stage<CVGRAM_MODE_FP32, BM> {
+  static constexpr int V = BM / 64;  // float4 per thread per operand
+  float4_t a[V], b[V], y;
   __device__ void load(const float* Z, int64_t Wp, int64_t r, int64_t ca, int64_t cb, int64_t cy,
                        bool ld_b, bool ld_y, int t) {
-    const int row = t >> 4, col = (t & 15) * 8;
+    const int row = t >> 4, col = (t & 15) * (BM / 16);
     const float* pa = Z + (r + row) * Wp + ca + col;
-    a[0] = *(const float4_t*)pa;
-    a[1] = *(const float4_t*)(pa + 4);
+#pragma unroll
+    for (int u = 0; u < V; ++u) a[u] = *(const float4_t*)(pa + 4 * u);
     if (ld_b) {
       const float* pb = Z + (r + row) * Wp + cb + col;
-      b[0] = *(const float4_t*)pb;
-      b[1] = *(const float4_t*)(pb + 4);
+#pragma unroll
+      for (int u = 0; u < V; ++u) b[u] = *(const float4_t*)(pb + 4 * u);
     }
     if (ld_y && t < 128) y = *(const float4_t*)(Z + (r + (t >> 3)) * Wp + cy + (t & 7) * 4);
   }
-  __device__ void store(Smem<CVGRAM_MODE_FP32>& s, int buf, bool st_b, bool st_y, int t) const {
-    constexpr int LDA = Mode<CVGRAM_MODE_FP32>::LDA, LDY = Mode<CVGRAM_MODE_FP32>::LDY;
-    const int row = t >> 4, col = (t & 15) * 8;
-    *(float4_t*)&s.a[buf][row * LDA + col] = a[0];
-    *(float4_t*)&s.a[buf][row * LDA + col + 4] = a[1];
-    if (st_b) {
-      *(float4_t*)&s.b[buf][row * LDA + col] = b[0];
-      *(float4_t*)&s.b[buf][row * LDA + col + 4] = b[1];
-    }
+  __device__ void store(Smem<CVGRAM_MODE_FP32, BM>& s, int buf, bool st_b, bool st_y,
+                        int t) const {
+    constexpr int LDA = Smem<CVGRAM_MODE_FP32, BM>::LDA, LDY = Smem<CVGRAM_MODE_FP32, BM>::LDY;
+    const int row = t >> 4, col = (t & 15) * (BM / 16);
+#pragma unroll
+    for (int u = 0; u < V; ++u) *(float4_t*)&s.a[buf][row * LDA + col + 4 * u] = a[u];
+    if (st_b)
+#pragma unroll
+      for (int u = 0; u < V; ++u) *(float4_t*)&s.b[buf][row * LDA + col + 4 * u] = b[u];
     if (st_y && t < 128) *(float4_t*)&s.y[buf][(t >> 3) * LDY + (t & 7) * 4] = y;
   }
 };
 
-// BF16X3: a 32-row panel block of 128 columns is 8 KB per hi/lo array,
-// i.e. two 16-byte chunks per thread per array; the Y block (32 columns) is
-// one chunk of hi (threads 0..127) or lo (threads 128..255).
-template <>
-struct Stage<CVGRAM_MODE_BF16X3> {
-  bf16x8_t ah[2], al[2], bh[2], bl[2], y;
+// BF16X3: a 32-row panel block of BM columns is BM * 4 16-byte chunks per
+// hi/lo array (BM / 64 per thread); the Y block (32 columns) is one chunk of
+// hi (threads 0..127) or lo (threads 128..255).
+template <int BM>
+struct Stage<CVGRAM_MODE_BF16X3, BM> {
+  static constexpr int V = BM / 64;
+  bf16x8_t ah[V], al[V], bh[V], bl[V], y;
   __device__ void load(const __bf16* Zh, const __bf16* Zl, int64_t Wp, int64_t r, int64_t ca,
                        int64_t cb, int64_t cy, bool ld_b, bool ld_y, int t) {
     const int64_t panel = (r / 32) * Wp;
     const __bf16* ha = Zh + (panel + ca) * 32;
     const __bf16* la = Zl + (panel + ca) * 32;
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
+    for (int u = 0; u < V; ++u) {
       ah[u] = *(const bf16x8_t*)(ha + (t + 256 * u) * 8);
       al[u] = *(const bf16x8_t*)(la + (t + 256 * u) * 8);
     }
@@ -185,7 +179,7 @@ struct Stage<CVGRAM_MODE_BF16X3> {
       const __bf16* hb = Zh + (panel + cb) * 32;
       const __bf16* lb = Zl + (panel + cb) * 32;
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
+      for (int u = 0; u < V; ++u) {
         bh[u] = *(const bf16x8_t*)(hb + (t + 256 * u) * 8);
         bl[u] = *(const bf16x8_t*)(lb + (t + 256 * u) * 8);
       }
@@ -195,11 +189,11 @@ struct Stage<CVGRAM_MODE_BF16X3> {
       y = *(const bf16x8_t*)(src + (t & 127) * 8);
     }
   }
-  __device__ void store(Smem<CVGRAM_MODE_BF16X3>& s, int buf, bool st_b, bool st_y,
+  __device__ void store(Smem<CVGRAM_MODE_BF16X3, BM>& s, int buf, bool st_b, bool st_y,
                         int t) const {
     constexpr int LDK = Mode<CVGRAM_MODE_BF16X3>::LDK;
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
+    for (int u = 0; u < V; ++u) {
       const int q = t + 256 * u;           // chunk: column q/4, k-group q%4
       const int off = (q >> 2) * LDK + (q & 3) * 8;
       *(bf16x8_t*)&s.a[buf][0][off] = ah[u];
@@ -220,9 +214,9 @@ struct Stage<CVGRAM_MODE_BF16X3> {
 // one stage of MFMA work for a wave: NA x NB blocks of 16 x 16, A columns
 // from `acol0` of the A view, B columns from `bcol0` of the B view.
 // ---------------------------------------------------------------------------
-template <int NA, int NB>
+template <int NA, int NB, int NACC>
 __device__ inline void mma_f64(const double* A, int lda, int acol0, const double* B, int ldb,
-                               int bcol0, double4_t (&acc)[NA * NB], int fr, int fc) {
+                               int bcol0, double4_t (&acc)[NACC], int fr, int fc) {
 #pragma unroll
   for (int kk = 0; kk < 4; ++kk) {
     double af[NA], bf[NB];
@@ -239,9 +233,9 @@ __device__ inline void mma_f64(const double* A, int lda, int acol0, const double
   }
 }
 
-template <int NA, int NB>
+template <int NA, int NB, int NACC>
 __device__ inline void mma_f32(const float* A, int lda, int acol0, const float* B, int ldb,
-                               int bcol0, float4_t (&acc)[NA * NB], int fr, int fc) {
+                               int bcol0, float4_t (&acc)[NACC], int fr, int fc) {
 #pragma unroll
   for (int kk = 0; kk < 4; ++kk) {
     float af[NA], bf[NB];
@@ -258,9 +252,9 @@ __device__ inline void mma_f32(const float* A, int lda, int acol0, const float* 
   }
 }
 
-template <int NA, int NB>
+template <int NA, int NB, int NACC>
 __device__ inline void mma_bf16x3(const __bf16* Ah, const __bf16* Al, int acol0, const __bf16* Bh,
-                                  const __bf16* Bl, int bcol0, float4_t (&acc)[NA * NB], int fr,
+                                  const __bf16* Bl, int bcol0, float4_t (&acc)[NACC], int fr,
                                   int fc) {
   constexpr int LDK = Mode<CVGRAM_MODE_BF16X3>::LDK;
   bf16x8_t ah[NA], al[NA];
@@ -289,31 +283,44 @@ __device__ inline void mma_bf16x3(const __bf16* Ah, const __bf16* Al, int acol0,
 // ---------------------------------------------------------------------------
 // the kernel
 // ---------------------------------------------------------------------------
-template <int MODE>
-__global__ __launch_bounds__(kThreads) void gram_kernel(GramArgs g) {
+template <int MODE, int BM>
+__global__ __launch_bounds__(kThreads) void gram_kernel(const ProbDesc* __restrict__ pds,
+                                                        const GramWork* __restrict__ work,
+                                                        int64_t n_work) {
   typedef typename Mode<MODE>::Acc Acc;
   constexpr int BK = Mode<MODE>::BK;
   constexpr bool kF64 = MODE == CVGRAM_MODE_FP64;
-  __shared__ Smem<MODE> sm;
+  constexpr int WT = BM / 2;              // wave tile edge
+  constexpr int NW = WT / 16;             // 16 x 16 blocks per wave tile edge
+  constexpr int NY = BM / 16;             // blocks along the rows of the K x M block
+  constexpr int NACC = NW * NW > 2 * NY ? NW * NW : 2 * NY;
+  __shared__ __attribute__((aligned(16))) Smem<MODE, BM> sm;
 
   const int64_t per = (int64_t)gridDim.x / 8;
   const int64_t item = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
-  if (item >= g.n_work) return;
-  const GramWork w = g.work[item];
+  if (item >= n_work) return;
+  const GramWork w = work[item];
+  // descriptor fields in registers (never re-read inside the loop)
+  const ProbDesc& pdr = pds[w.prob];
+  const int64_t Wp = pdr.Wp, Kp = pdr.Kp, K = pdr.K, M = pdr.M;
+  const int32_t nt = pdr.nt;
+  const void* const packed = pdr.packed;
+  const void* const packed_lo = pdr.packed_lo;
+  double* const slabs = pdr.slabs;
+  const bool xy_diag = pdr.xy_diag != 0;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int fr = lane >> 4, fc = lane & 15;
 
-  const bool xy_tile = w.tj >= g.nt;
+  const bool xy_tile = w.tj >= nt;
   const bool diag = !xy_tile && w.ti == w.tj;
-  const int64_t ca = (int64_t)w.ti * BM;                                   // A columns
-  const int64_t cb = xy_tile ? g.Kp + (int64_t)(w.tj - g.nt) * BM : (int64_t)w.tj * BM;
-  const bool ydiag = diag && g.xy_diag;            // K x M block inside this diagonal tile
-  const bool ld_b = !diag;                          // diagonal tiles reuse A as B
-  // wave roles: 0 = 64 x 64 sub-tile, 1 = 128 x 32 K-by-M block, 2 = idle
+  const int64_t ca = (int64_t)w.ti * BM;                                    // A columns
+  const int64_t cb = xy_tile ? Kp + (int64_t)(w.tj - nt) * BM : (int64_t)w.tj * BM;
+  const bool ydiag = diag && xy_diag;      // K x M block inside this diagonal tile
+  const bool ld_b = !diag;                  // diagonal tiles reuse A as B
+  // wave roles: 0 = WT x WT sub-tile, 1 = BM x 32 K-by-M block, 2 = idle
   const int role = (diag && wm == 1 && wn == 0) ? (ydiag ? 1 : 2) : 0;
 
-  constexpr int NACC = 16;
   Acc acc[NACC];
   double a64[NACC][4];
 #pragma unroll
@@ -323,14 +330,14 @@ __global__ __launch_bounds__(kThreads) void gram_kernel(GramArgs g) {
     for (int e = 0; e < 4; ++e) a64[i][e] = 0.0;
   }
 
-  Stage<MODE> st;
+  Stage<MODE, BM> st;
   const int64_t nst = (w.r1 - w.r0) / BK;
   auto load = [&](int64_t s) {
     const int64_t r = w.r0 + s * BK;
     if constexpr (MODE == CVGRAM_MODE_BF16X3)
-      st.load((const __bf16*)g.Zp, (const __bf16*)g.Zlo, g.Wp, r, ca, cb, g.Kp, ld_b, ydiag, t);
+      st.load((const __bf16*)packed, (const __bf16*)packed_lo, Wp, r, ca, cb, Kp, ld_b, ydiag, t);
     else
-      st.load((const typename Mode<MODE>::E*)g.Zp, g.Wp, r, ca, cb, g.Kp, ld_b, ydiag, t);
+      st.load((const typename Mode<MODE>::E*)packed, Wp, r, ca, cb, Kp, ld_b, ydiag, t);
   };
 
   load(0);
@@ -342,30 +349,30 @@ __global__ __launch_bounds__(kThreads) void gram_kernel(GramArgs g) {
     const bool more = s + 1 < nst;
     if (more) load(s + 1);
     if constexpr (MODE == CVGRAM_MODE_FP64) {
-      constexpr int LDA = Mode<MODE>::LDA, LDY = Mode<MODE>::LDY;
+      constexpr int LDA = Smem<MODE, BM>::LDA, LDY = Smem<MODE, BM>::LDY;
       const double* A = sm.a[buf];
       const double* B = diag ? sm.a[buf] : sm.b[buf];
       if (role == 0)
-        mma_f64<4, 4>(A, LDA, wm * kWT, B, LDA, wn * kWT, acc, fr, fc);
+        mma_f64<NW, NW>(A, LDA, wm * WT, B, LDA, wn * WT, acc, fr, fc);
       else if (role == 1)
-        mma_f64<8, 2>(A, LDA, 0, sm.y[buf], LDY, 0, acc, fr, fc);
+        mma_f64<NY, 2>(A, LDA, 0, sm.y[buf], LDY, 0, acc, fr, fc);
     } else if constexpr (MODE == CVGRAM_MODE_FP32) {
-      constexpr int LDA = Mode<MODE>::LDA, LDY = Mode<MODE>::LDY;
+      constexpr int LDA = Smem<MODE, BM>::LDA, LDY = Smem<MODE, BM>::LDY;
       const float* A = sm.a[buf];
       const float* B = diag ? sm.a[buf] : sm.b[buf];
       if (role == 0)
-        mma_f32<4, 4>(A, LDA, wm * kWT, B, LDA, wn * kWT, acc, fr, fc);
+        mma_f32<NW, NW>(A, LDA, wm * WT, B, LDA, wn * WT, acc, fr, fc);
       else if (role == 1)
-        mma_f32<8, 2>(A, LDA, 0, sm.y[buf], LDY, 0, acc, fr, fc);
+        mma_f32<NY, 2>(A, LDA, 0, sm.y[buf], LDY, 0, acc, fr, fc);
     } else {
       const __bf16* Ah = sm.a[buf][0];
       const __bf16* Al = sm.a[buf][1];
       const __bf16* Bh = diag ? sm.a[buf][0] : sm.b[buf][0];
       const __bf16* Bl = diag ? sm.a[buf][1] : sm.b[buf][1];
       if (role == 0)
-        mma_bf16x3<4, 4>(Ah, Al, wm * kWT, Bh, Bl, wn * kWT, acc, fr, fc);
+        mma_bf16x3<NW, NW>(Ah, Al, wm * WT, Bh, Bl, wn * WT, acc, fr, fc);
       else if (role == 1)
-        mma_bf16x3<8, 2>(Ah, Al, 0, sm.y[buf][0], sm.y[buf][1], 0, acc, fr, fc);
+        mma_bf16x3<NY, 2>(Ah, Al, 0, sm.y[buf][0], sm.y[buf][1], 0, acc, fr, fc);
     }
     if constexpr (!kF64) {
       since += BK;
@@ -384,8 +391,8 @@ __global__ __launch_bounds__(kThreads) void gram_kernel(GramArgs g) {
   }
   if (role == 2) return;
 
-  const int64_t K = g.K, W = g.K + g.M;
-  double* out = g.slabs + (int64_t)w.slab * K * W;
+  const int64_t W = K + M;
+  double* out = slabs + (int64_t)w.slab * K * W;
   auto value = [&](int i, int e) -> double {
     if constexpr (kF64)
       return acc[i][e];
@@ -394,46 +401,56 @@ __global__ __launch_bounds__(kThreads) void gram_kernel(GramArgs g) {
   };
   if (role == 0) {
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < NW; ++a)
 #pragma unroll
-      for (int b = 0; b < 4; ++b)
+      for (int b = 0; b < NW; ++b)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const int64_t row = ca + wm * kWT + a * 16 + acc_row<MODE>(e, fr);
-          const int64_t cl = (xy_tile ? (int64_t)(w.tj - g.nt) * BM : cb) + wn * kWT + b * 16 + fc;
+          const int64_t row = ca + wm * WT + a * 16 + acc_row<MODE>(e, fr);
+          const int64_t cl = (xy_tile ? (int64_t)(w.tj - nt) * BM : cb) + wn * WT + b * 16 + fc;
           if (row >= K) continue;
           if (!xy_tile) {
-            if (cl < K) out[row * W + cl] = value(a * 4 + b, e);
-          } else if (cl < g.M) {
-            out[row * W + K + cl] = value(a * 4 + b, e);
+            if (cl < K) out[row * W + cl] = value(a * NW + b, e);
+          } else if (cl < M) {
+            out[row * W + K + cl] = value(a * NW + b, e);
           }
         }
   } else {
 #pragma unroll
-    for (int a = 0; a < 8; ++a)
+    for (int a = 0; a < NY; ++a)
 #pragma unroll
       for (int b = 0; b < 2; ++b)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
           const int64_t row = ca + a * 16 + acc_row<MODE>(e, fr);
           const int64_t cl = b * 16 + fc;
-          if (row < K && cl < g.M) out[row * W + K + cl] = value(a * 2 + b, e);
+          if (row < K && cl < M) out[row * W + K + cl] = value(a * 2 + b, e);
         }
   }
 }
 
+template <int MODE>
+void launch_mode(int tile, const ProbDesc* pd, const GramWork* work, int64_t n_work,
+                 hipStream_t s) {
+  const unsigned grid = (unsigned)(8 * ((n_work + 7) / 8));
+  if (tile == 64)
+    gram_kernel<MODE, 64><<<grid, kThreads, 0, s>>>(pd, work, n_work);
+  else
+    gram_kernel<MODE, 128><<<grid, kThreads, 0, s>>>(pd, work, n_work);
+  CVG_LAUNCH_CHECK();
+}
+
 }  // namespace
 
-void launch_gram(cvgram_mode mode, const GramArgs& g, hipStream_t s) {
-  if (g.n_work <= 0) return;
-  const unsigned grid = (unsigned)(8 * ((g.n_work + 7) / 8));
+void launch_gram(cvgram_mode mode, int tile, const ProbDesc* pd, const GramWork* work,
+                 int64_t n_work, hipStream_t s) {
+  if (n_work <= 0) return;
   if (mode == CVGRAM_MODE_FP64)
-    gram_kernel<CVGRAM_MODE_FP64><<<grid, kThreads, 0, s>>>(g);
+    launch_mode<CVGRAM_MODE_FP64>(tile, pd, work, n_work, s);
   else if (mode == CVGRAM_MODE_FP32)
-    gram_kernel<CVGRAM_MODE_FP32><<<grid, kThreads, 0, s>>>(g);
+    launch_mode<CVGRAM_MODE_FP32>(tile, pd, work, n_work, s);
   else
-    gram_kernel<CVGRAM_MODE_BF16X3><<<grid, kThreads, 0, s>>>(g);
-  CVG_LAUNCH_CHECK();
+    launch_mode<CVGRAM_MODE_BF16X3>(tile, pd, work, n_work, s);
 }
 
 }  // namespace cvg

@@ -5,16 +5,20 @@
 //       maxima of the validation block the chunk belongs to
 //       (Algorithm 7 steps 10, 17, 19).
 //
-// Packed row space: folds follow each other in label order, each padded with
-// zero rows to a multiple of kPanelRows, so every Gram work item streams a
-// contiguous, aligned block of rows with no bounds checks.  Packed column
-// space (width Wp): X columns [0, K), zeros up to Kp, Y columns [Kp, Kp + M),
-// zeros up to Wp.  Element formats:
+// Element formats of the packed panels (see ProbDesc for the row/column
+// spaces):
 //   FP64 mode   double, row-major  Zp[row * Wp + col]
 //   FP32 mode   float,  row-major  Zp[row * Wp + col]
 //   BF16X3 mode two bf16 panels (hi, lo), k-contiguous in blocks of 32 rows:
 //               Zp[((row / 32) * Wp + col) * 32 + row % 32]
-// The split is hi = bf16(z'), lo = bf16(z' - hi) with z' = fp32(z - c).
+// with z' = z - c in FP64 (FP64 mode) or fp32(z - c) (mixed modes), and the
+// split hi = bf16(z'), lo = bf16(z' - hi).
+//
+// Work shape: a 256-thread workgroup handles one chunk (whole 32-row panels
+// of one fold) x 256 packed columns.  Each thread loads 4 consecutive
+// columns of 8 rows per panel (16-byte loads when the columns allow it);
+// the bf16 panels are transposed through LDS so that every global store is
+// a contiguous 16-byte chunk of a fully written line.
 #include <cmath>
 
 #include "internal.h"
@@ -24,15 +28,21 @@ namespace {
 
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 
+// pivot: c_j = FP64 mean of the first min(N, 256) rows of column j of [X | Y]
+// (rounded to FP32 in the mixed modes).  items: (prob, block of 64 columns)
 template <typename T>
-__global__ __launch_bounds__(256) void pivot_kernel(const T* __restrict__ X,
-                                                    const T* __restrict__ Y, int64_t rows,
-                                                    int64_t K, int64_t M, int round_f32,
-                                                    double* __restrict__ pivot) {
-  // one workgroup per column block; each wave sums a strided subset of rows
+__global__ __launch_bounds__(256) void pivot_kernel(const ProbDesc* __restrict__ pds,
+                                                    const Item* __restrict__ items,
+                                                    int round_f32) {
   __shared__ double part[4][64];
+  const Item it = items[blockIdx.x];
+  const ProbDesc& pd = pds[it.prob];
+  const T* X = (const T*)pd.X;
+  const T* Y = (const T*)pd.Y;
+  const int64_t K = pd.K, M = pd.M;
+  const int64_t rows = pd.N < 256 ? pd.N : 256;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t j = (int64_t)blockIdx.x * 64 + lane;
+  const int64_t j = (int64_t)it.a * 64 + lane;
   double s = 0.0;
   if (j < K + M)
     for (int64_t r = w; r < rows; r += 4)
@@ -42,11 +52,12 @@ __global__ __launch_bounds__(256) void pivot_kernel(const T* __restrict__ X,
   if (w == 0 && j < K + M) {
     double c = ((part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane])) / (double)rows;
     if (round_f32) c = (double)(float)c;
-    pivot[j] = c;
+    pd.pivot[j] = c;
   }
 }
 
-// source column of packed column jp (or -1 for padding) and its stats index
+// source column (index into [X | Y], also the statistics index) of packed
+// column jp, or -1 for a padding column
 __device__ inline int64_t src_col(int64_t jp, int64_t K, int64_t Kp, int64_t M) {
   if (jp < K) return jp;
   if (jp >= Kp && jp - Kp < M) return K + (jp - Kp);
@@ -54,136 +65,240 @@ __device__ inline int64_t src_col(int64_t jp, int64_t K, int64_t Kp, int64_t M) 
 }
 
 template <typename T>
-__device__ inline double zval(const T* __restrict__ X, const T* __restrict__ Y, int64_t K,
-                              int64_t M, int64_t row, int64_t j) {
-  return j < K ? (double)X[row * K + j] : (double)Y[row * M + (j - K)];
+__device__ inline void load4(const T* __restrict__ X, const T* __restrict__ Y, int64_t K,
+                             int64_t M, int64_t row, const int64_t (&js)[4], bool vec,
+                             double (&x)[4]) {
+  if (vec) {
+    // four consecutive X columns, 16-byte aligned
+    if constexpr (sizeof(T) == 4) {
+      const float4 v = *(const float4*)&X[row * K + js[0]];
+      x[0] = v.x;
+      x[1] = v.y;
+      x[2] = v.z;
+      x[3] = v.w;
+    } else {
+      const double2 a = *(const double2*)&X[row * K + js[0]];
+      const double2 b = *(const double2*)&X[row * K + js[0] + 2];
+      x[0] = a.x;
+      x[1] = a.y;
+      x[2] = b.x;
+      x[3] = b.y;
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      x[u] = js[u] < 0 ? 0.0
+             : js[u] < K ? (double)X[row * K + js[u]]
+                         : (double)Y[row * M + (js[u] - K)];
+  }
 }
 
-// grid.x = chunks, grid.y = blocks of 256 packed columns.  A chunk covers a
-// whole number of 32-row panels of one fold.
-// part layout: [4][n_chunks][W] (sum, sumsq, min, max of the real rows)
-template <typename T, int MODE>
-__global__ __launch_bounds__(256) void pack_kernel(
-    const T* __restrict__ X, const T* __restrict__ Y, int64_t K, int64_t M, int64_t Kp,
-    int64_t Wp, const int32_t* __restrict__ perm, const PackChunk* __restrict__ chunks,
-    int64_t n_chunks, const double* __restrict__ pivot, void* __restrict__ packed,
-    void* __restrict__ packed_lo, double* __restrict__ part) {
-  const int64_t W = K + M;
-  const int64_t jp = (int64_t)blockIdx.y * 256 + threadIdx.x;
-  const int64_t c = blockIdx.x;
-  if (jp >= Wp) return;
-  const PackChunk ch = chunks[c];
-  const int64_t js = src_col(jp, K, Kp, M);
-  const double piv = js >= 0 ? pivot[js] : 0.0;
-  const float pivf = (float)piv;  // the pivot is FP32-representable in the mixed modes
-  double s = 0.0, q = 0.0, mn = INFINITY, mx = -INFINITY;
+constexpr int LDK = kPanelRows + 8;  // bf16 per column in the LDS transpose (80 B)
 
-  for (int64_t d0 = ch.d0; d0 < ch.d1; d0 += kPanelRows) {
-    double x[kPanelRows];
-    bool v[kPanelRows];
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void pack_kernel(const ProbDesc* __restrict__ pds,
+                                                   const PackChunk* __restrict__ chunks) {
+  constexpr int kT = MODE == CVGRAM_MODE_BF16X3 ? kPackCols * LDK : 8;
+  __shared__ __attribute__((aligned(16))) __bf16 th[kT];
+  __shared__ __attribute__((aligned(16))) __bf16 tl[kT];
+  __shared__ double red[256 * 4];
+
+  const PackChunk ch = chunks[blockIdx.x];
+  // descriptor fields in registers (the loops below store through other
+  // pointers; no field is re-read from memory)
+  const ProbDesc& pdr = pds[ch.prob];
+  const int64_t Wp = pdr.Wp;
+  const int64_t cb0 = (int64_t)blockIdx.y * kPackCols;
+  if (cb0 >= Wp) return;  // uniform over the workgroup
+  const T* __restrict__ X = (const T*)pdr.X;
+  const T* __restrict__ Y = (const T*)pdr.Y;
+  const int32_t* __restrict__ perm = pdr.perm;
+  const double* __restrict__ pivot = pdr.pivot;
+  void* const packed = pdr.packed;
+  void* const packed_lo = pdr.packed_lo;
+  double* const part = pdr.part;
+  const int64_t n_chunks = pdr.n_chunks;
+  const int x_vec = pdr.x_vec;
+  const int64_t K = pdr.K, M = pdr.M, Kp = pdr.Kp, W = pdr.W;
+  const int t = threadIdx.x, cg = t & 63, rg = t >> 6;
+  const int64_t jp0 = cb0 + 4 * cg;
+
+  int64_t js[4];
+  double piv[4];
+  float pivf[4];
+  bool any = false;
 #pragma unroll
-    for (int u = 0; u < kPanelRows; ++u) {
-      const int64_t src = ch.src0 + (d0 - ch.d0) + u;
-      v[u] = js >= 0 && src < ch.src1;
-      x[u] = v[u] ? zval(X, Y, K, M, (int64_t)perm[src], js) : 0.0;
+  for (int u = 0; u < 4; ++u) {
+    js[u] = jp0 + u < Wp ? src_col(jp0 + u, K, Kp, M) : -1;
+    piv[u] = js[u] >= 0 ? pivot[js[u]] : 0.0;
+    pivf[u] = (float)piv[u];  // FP32-representable in the mixed modes
+    any |= js[u] >= 0;
+  }
+  const bool vec = x_vec && jp0 + 3 < K;
+  double s[4] = {0, 0, 0, 0}, q[4] = {0, 0, 0, 0};
+  double mn[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
+  double mx[4] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
+
+  // permutation indices of this thread's 8 rows, one panel ahead
+  int32_t rows_next[8];
+  auto fetch_rows = [&](int64_t d0, int32_t (&r)[8]) {
+#pragma unroll
+    for (int g = 0; g < 8; ++g) {
+      const int64_t src = ch.src0 + (d0 - ch.d0) + rg * 8 + g;
+      r[g] = (d0 < ch.d1 && src < ch.src1) ? perm[src] : -1;
+    }
+  };
+  fetch_rows(ch.d0, rows_next);
+  for (int64_t d0 = ch.d0; d0 < ch.d1; d0 += kPanelRows) {
+    int32_t rows[8];
+#pragma unroll
+    for (int g = 0; g < 8; ++g) rows[g] = rows_next[g];
+    fetch_rows(d0 + kPanelRows, rows_next);
+    double x[8][4];
+    bool v[8];
+#pragma unroll
+    for (int g = 0; g < 8; ++g) {
+      v[g] = any && rows[g] >= 0;
+      if (v[g]) {
+        load4(X, Y, K, M, (int64_t)rows[g], js, vec, x[g]);
+      } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) x[g][u] = 0.0;
+      }
     }
 #pragma unroll
-    for (int u = 0; u < kPanelRows; ++u) {
-      if (!v[u]) continue;
-      const double d = x[u] - piv;
-      s += d;
-      q = fma(d, d, q);
-      mn = fmin(mn, x[u]);
-      mx = fmax(mx, x[u]);
+    for (int g = 0; g < 8; ++g) {
+      if (!v[g]) continue;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (js[u] < 0) continue;
+        const double d = x[g][u] - piv[u];
+        s[u] += d;
+        q[u] = fma(d, d, q[u]);
+        mn[u] = fmin(mn[u], x[g][u]);
+        mx[u] = fmax(mx[u], x[g][u]);
+      }
     }
     if constexpr (MODE == CVGRAM_MODE_BF16X3) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        bf16x8_t h, l;
+#pragma unroll
+        for (int g = 0; g < 8; ++g) {
+          const bool ok = v[g] && js[u] >= 0;
+          // z' = fp32(z - c): an exact FP32 subtraction for FP32 input
+          const float zf = !ok ? 0.f
+                           : (sizeof(T) == 4 ? (float)x[g][u] - pivf[u]
+                                             : (float)(x[g][u] - (double)pivf[u]));
+          const __bf16 hh = (__bf16)zf;
+          h[g] = hh;
+          l[g] = (__bf16)(zf - (float)hh);
+        }
+        *(bf16x8_t*)&th[(4 * cg + u) * LDK + rg * 8] = h;
+        *(bf16x8_t*)&tl[(4 * cg + u) * LDK + rg * 8] = l;
+      }
+      __syncthreads();
       __bf16* hi = (__bf16*)packed;
       __bf16* lo = (__bf16*)packed_lo;
-      bf16x8_t vh[kPanelRows / 8], vl[kPanelRows / 8];
+      const int64_t base = ((d0 / kPanelRows) * Wp + cb0) * kPanelRows;
 #pragma unroll
-      for (int u = 0; u < kPanelRows; ++u) {
-        // z' = fp32(z - c): exact FP32 subtraction for FP32 input
-        const float zf = !v[u] ? 0.f
-                         : (sizeof(T) == 4 ? (float)x[u] - pivf : (float)(x[u] - (double)pivf));
-        const __bf16 h = (__bf16)zf;
-        vh[u / 8][u % 8] = h;
-        vl[u / 8][u % 8] = (__bf16)(zf - (float)h);
+      for (int k = 0; k < 4; ++k) {
+        const int qc = t + 256 * k;  // 16-byte chunk: column qc / 4, rows 8 (qc % 4) ..
+        if (cb0 + (qc >> 2) < Wp) {
+          *(bf16x8_t*)&hi[base + qc * 8] = *(const bf16x8_t*)&th[(qc >> 2) * LDK + (qc & 3) * 8];
+          *(bf16x8_t*)&lo[base + qc * 8] = *(const bf16x8_t*)&tl[(qc >> 2) * LDK + (qc & 3) * 8];
+        }
       }
-      const int64_t base = ((d0 / kPanelRows) * Wp + jp) * kPanelRows;
-#pragma unroll
-      for (int g = 0; g < kPanelRows / 8; ++g) {
-        *(bf16x8_t*)&hi[base + g * 8] = vh[g];
-        *(bf16x8_t*)&lo[base + g * 8] = vl[g];
-      }
+      __syncthreads();
     } else if constexpr (MODE == CVGRAM_MODE_FP32) {
-      float* out = (float*)packed;
+      if (jp0 < Wp) {
+        float* out = (float*)packed;
 #pragma unroll
-      for (int u = 0; u < kPanelRows; ++u)
-        out[(d0 + u) * Wp + jp] = !v[u] ? 0.f
-                                  : (sizeof(T) == 4 ? (float)x[u] - pivf
-                                                    : (float)(x[u] - (double)pivf));
+        for (int g = 0; g < 8; ++g) {
+          float4 z;
+          float* zz = (float*)&z;
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const bool ok = v[g] && js[u] >= 0;
+            zz[u] = !ok ? 0.f
+                    : (sizeof(T) == 4 ? (float)x[g][u] - pivf[u]
+                                      : (float)(x[g][u] - (double)pivf[u]));
+          }
+          *(float4*)&out[(d0 + rg * 8 + g) * Wp + jp0] = z;
+        }
+      }
     } else {
-      double* out = (double*)packed;
+      if (jp0 < Wp) {
+        double* out = (double*)packed;
 #pragma unroll
-      for (int u = 0; u < kPanelRows; ++u) out[(d0 + u) * Wp + jp] = v[u] ? x[u] - piv : 0.0;
+        for (int g = 0; g < 8; ++g) {
+          double2 a, b;
+          a.x = (v[g] && js[0] >= 0) ? x[g][0] - piv[0] : 0.0;
+          a.y = (v[g] && js[1] >= 0) ? x[g][1] - piv[1] : 0.0;
+          b.x = (v[g] && js[2] >= 0) ? x[g][2] - piv[2] : 0.0;
+          b.y = (v[g] && js[3] >= 0) ? x[g][3] - piv[3] : 0.0;
+          *(double2*)&out[(d0 + rg * 8 + g) * Wp + jp0] = a;
+          *(double2*)&out[(d0 + rg * 8 + g) * Wp + jp0 + 2] = b;
+        }
+      }
     }
   }
-  if (js >= 0) {
-    const int64_t stride = n_chunks * W;
-    part[0 * stride + c * W + js] = s;
-    part[1 * stride + c * W + js] = q;
-    part[2 * stride + c * W + js] = mn;
-    part[3 * stride + c * W + js] = mx;
+
+  // combine the 4 row groups (waves) of each column, in wave order
+  const int64_t stride = n_chunks * W;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      red[t * 4 + u] = k == 0 ? s[u] : k == 1 ? q[u] : k == 2 ? mn[u] : mx[u];
+    __syncthreads();
+    if (rg == 0) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        double r = red[cg * 4 + u];
+        for (int g = 1; g < 4; ++g) {
+          const double o = red[(g * 64 + cg) * 4 + u];
+          r = k < 2 ? r + o : (k == 2 ? fmin(r, o) : fmax(r, o));
+        }
+        if (js[u] >= 0) part[k * stride + (int64_t)ch.chunk * W + js[u]] = r;
+      }
+    }
+    __syncthreads();
   }
 }
 
 template <typename T>
-void launch_pack_typed(cvgram_mode mode, const T* X, const T* Y, int64_t K, int64_t M,
-                       int64_t Kp, int64_t Wp, const int32_t* perm, const PackChunk* chunks,
-                       int64_t n_chunks, const double* pivot, void* packed, void* packed_lo,
-                       double* part, hipStream_t s) {
-  dim3 grid((unsigned)n_chunks, (unsigned)((Wp + 255) / 256));
+void launch_pack_typed(cvgram_mode mode, const ProbDesc* pd, const PackChunk* chunks,
+                       int64_t n_chunks, int32_t max_col_blocks, hipStream_t s) {
+  dim3 grid((unsigned)n_chunks, (unsigned)max_col_blocks);
   if (mode == CVGRAM_MODE_FP64)
-    pack_kernel<T, CVGRAM_MODE_FP64><<<grid, 256, 0, s>>>(X, Y, K, M, Kp, Wp, perm, chunks,
-                                                          n_chunks, pivot, packed, packed_lo,
-                                                          part);
+    pack_kernel<T, CVGRAM_MODE_FP64><<<grid, 256, 0, s>>>(pd, chunks);
   else if (mode == CVGRAM_MODE_FP32)
-    pack_kernel<T, CVGRAM_MODE_FP32><<<grid, 256, 0, s>>>(X, Y, K, M, Kp, Wp, perm, chunks,
-                                                          n_chunks, pivot, packed, packed_lo,
-                                                          part);
+    pack_kernel<T, CVGRAM_MODE_FP32><<<grid, 256, 0, s>>>(pd, chunks);
   else
-    pack_kernel<T, CVGRAM_MODE_BF16X3><<<grid, 256, 0, s>>>(X, Y, K, M, Kp, Wp, perm, chunks,
-                                                            n_chunks, pivot, packed, packed_lo,
-                                                            part);
+    pack_kernel<T, CVGRAM_MODE_BF16X3><<<grid, 256, 0, s>>>(pd, chunks);
   CVG_LAUNCH_CHECK();
 }
 
 }  // namespace
 
-void launch_pivot(const void* X, const void* Y, cvgram_dtype dt, bool round_f32, int64_t N,
-                  int64_t K, int64_t M, double* pivot, hipStream_t s) {
-  const int64_t rows = N < 256 ? N : 256;
-  const unsigned blocks = (unsigned)((K + M + 63) / 64);
+void launch_pivot(cvgram_dtype dt, bool round_f32, const ProbDesc* pd, const Item* items,
+                  int64_t n_items, hipStream_t s) {
+  if (n_items <= 0) return;
   if (dt == CVGRAM_F64)
-    pivot_kernel<double><<<blocks, 256, 0, s>>>((const double*)X, (const double*)Y, rows, K, M,
-                                                round_f32 ? 1 : 0, pivot);
+    pivot_kernel<double><<<(unsigned)n_items, 256, 0, s>>>(pd, items, round_f32 ? 1 : 0);
   else
-    pivot_kernel<float><<<blocks, 256, 0, s>>>((const float*)X, (const float*)Y, rows, K, M,
-                                               round_f32 ? 1 : 0, pivot);
+    pivot_kernel<float><<<(unsigned)n_items, 256, 0, s>>>(pd, items, round_f32 ? 1 : 0);
   CVG_LAUNCH_CHECK();
 }
 
-void launch_pack(cvgram_mode mode, const void* X, const void* Y, cvgram_dtype dt, int64_t K,
-                 int64_t M, int64_t Kp, int64_t Wp, const int32_t* perm, const PackChunk* chunks,
-                 int64_t n_chunks, const double* pivot, void* packed, void* packed_lo,
-                 double* part, hipStream_t s) {
+void launch_pack(cvgram_mode mode, cvgram_dtype dt, const ProbDesc* pd, const PackChunk* chunks,
+                 int64_t n_chunks, int32_t max_col_blocks, hipStream_t s) {
   if (n_chunks <= 0) return;
   if (dt == CVGRAM_F64)
-    launch_pack_typed<double>(mode, (const double*)X, (const double*)Y, K, M, Kp, Wp, perm,
-                              chunks, n_chunks, pivot, packed, packed_lo, part, s);
+    launch_pack_typed<double>(mode, pd, chunks, n_chunks, max_col_blocks, s);
   else
-    launch_pack_typed<float>(mode, (const float*)X, (const float*)Y, K, M, Kp, Wp, perm, chunks,
-                             n_chunks, pivot, packed, packed_lo, part, s);
+    launch_pack_typed<float>(mode, pd, chunks, n_chunks, max_col_blocks, s);
 }
 
 }  // namespace cvg

@@ -82,29 +82,82 @@ __global__ __launch_bounds__(kThreads) void radix_hist_kernel(const int32_t* __r
   hist[(int64_t)threadIdx.x * tiles + blockIdx.x] = h[threadIdx.x];
 }
 
-// Exclusive scan of n int32 counts (sum < 2^31) by one workgroup of 1024.
-__global__ __launch_bounds__(1024) void scan_exclusive_kernel(int32_t* a, int64_t n) {
-  __shared__ int32_t part[1024];
-  const int t = threadIdx.x;
-  const int64_t per = (n + 1023) / 1024;
-  const int64_t b = t * per;
-  const int64_t e = b + per < n ? b + per : n;
-  int32_t s = 0;
-  for (int64_t i = b; i < e; ++i) s += a[i];
-  part[t] = s;
+// Exclusive scan of n int32 counts (sum < 2^31): per-block totals, a scan of
+// the totals by one workgroup, then a per-block scan with the block offsets.
+// Each thread owns kScanItems consecutive elements (coalesced per wave).
+constexpr int kScanItems = 8;
+constexpr int kScanBlock = kThreads * kScanItems;
+
+__device__ inline int wave_incl_scan(int v, int lane) {
+  for (int o = 1; o < 64; o <<= 1) {
+    const int u = __shfl_up(v, o, 64);
+    if (lane >= o) v += u;
+  }
+  return v;
+}
+
+__global__ __launch_bounds__(kThreads) void scan_block_sums_kernel(const int32_t* __restrict__ a,
+                                                                   int64_t n,
+                                                                   int32_t* __restrict__ sums) {
+  __shared__ int ws[kWaves];
+  const int64_t base = (int64_t)blockIdx.x * kScanBlock + threadIdx.x * kScanItems;
+  int s = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i)
+    if (base + i < n) s += a[base + i];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = s;
   __syncthreads();
-  // Hillis-Steele inclusive scan of the 1024 partial sums
-  for (int o = 1; o < 1024; o <<= 1) {
-    int32_t v = t >= o ? part[t - o] : 0;
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int w = 0; w < kWaves; ++w) t += ws[w];
+    sums[blockIdx.x] = t;
+  }
+}
+
+// exclusive scan of the block totals in place (one workgroup, serial chunks)
+__global__ __launch_bounds__(kThreads) void scan_sums_kernel(int32_t* sums, int64_t nb) {
+  __shared__ int ws[kWaves];
+  __shared__ int carry;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int64_t b0 = 0; b0 < nb; b0 += kThreads) {
+    const int64_t i = b0 + threadIdx.x;
+    const int v = i < nb ? sums[i] : 0;
+    const int inc = wave_incl_scan(v, lane);
+    if (lane == 63) ws[w] = inc;
     __syncthreads();
-    part[t] += v;
+    int off = carry;
+    for (int k = 0; k < w; ++k) off += ws[k];
+    if (i < nb) sums[i] = off + inc - v;
+    __syncthreads();
+    if (threadIdx.x == kThreads - 1) carry = off + inc;
     __syncthreads();
   }
-  int32_t run = t ? part[t - 1] : 0;
-  for (int64_t i = b; i < e; ++i) {
-    int32_t v = a[i];
-    a[i] = run;
-    run += v;
+}
+
+__global__ __launch_bounds__(kThreads) void scan_apply_kernel(int32_t* __restrict__ a, int64_t n,
+                                                              const int32_t* __restrict__ sums) {
+  __shared__ int ws[kWaves];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t base = (int64_t)blockIdx.x * kScanBlock + threadIdx.x * kScanItems;
+  int v[kScanItems];
+  int t = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    v[i] = base + i < n ? a[base + i] : 0;
+    t += v[i];
+  }
+  const int inc = wave_incl_scan(t, lane);
+  if (lane == 63) ws[w] = inc;
+  __syncthreads();
+  int off = sums[blockIdx.x] + inc - t;
+  for (int k = 0; k < w; ++k) off += ws[k];
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    if (base + i < n) a[base + i] = off;
+    off += v[i];
   }
 }
 
@@ -186,13 +239,28 @@ void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
 }
 
 void launch_label_minmax(const int32_t* fold, int64_t N, int32_t* info, hipStream_t s) {
-  int64_t blocks = (N + kThreads - 1) / kThreads;
-  if (blocks > 2048) blocks = 2048;
+  // a few hundred blocks, each reducing many labels, then one atomic pair per block
+  int64_t blocks = (N + 16 * kThreads - 1) / (16 * kThreads);
+  if (blocks > 512) blocks = 512;
   label_minmax_kernel<<<(unsigned)blocks, kThreads, 0, s>>>(fold, N, info);
   CVG_LAUNCH_CHECK();
 }
 
-int64_t radix_hist_entries(int64_t N) { return 256 * ((N + kTileElems - 1) / kTileElems); }
+// hist holds 256 * tiles counts followed by the scan's block totals
+int64_t radix_hist_entries(int64_t N) {
+  const int64_t n = 256 * ((N + kTileElems - 1) / kTileElems);
+  return n + (n + kScanBlock - 1) / kScanBlock;
+}
+
+void scan_exclusive(int32_t* a, int64_t n, int32_t* sums, hipStream_t s) {
+  const int64_t nb = (n + kScanBlock - 1) / kScanBlock;
+  scan_block_sums_kernel<<<(unsigned)nb, kThreads, 0, s>>>(a, n, sums);
+  CVG_LAUNCH_CHECK();
+  scan_sums_kernel<<<1, kThreads, 0, s>>>(sums, nb);
+  CVG_LAUNCH_CHECK();
+  scan_apply_kernel<<<(unsigned)nb, kThreads, 0, s>>>(a, n, sums);
+  CVG_LAUNCH_CHECK();
+}
 
 void radix_partition(const int32_t* fold, int64_t N, int bits, int32_t* keys_a, int32_t* keys_b,
                      int32_t* perm, int32_t* perm_tmp, int32_t* hist, const int32_t** sorted_keys,
@@ -209,8 +277,7 @@ void radix_partition(const int32_t* fold, int64_t N, int bits, int32_t* keys_a, 
     const int shift = 8 * pass;
     radix_hist_kernel<<<(unsigned)tiles, kThreads, 0, s>>>(kin, N, shift, hist, tiles);
     CVG_LAUNCH_CHECK();
-    scan_exclusive_kernel<<<1, 1024, 0, s>>>(hist, 256 * tiles);
-    CVG_LAUNCH_CHECK();
+    scan_exclusive(hist, 256 * tiles, hist + 256 * tiles, s);
     radix_scatter_kernel<<<(unsigned)tiles, kThreads, 0, s>>>(kin, vin, kout, vout, N, shift,
                                                               hist, tiles);
     CVG_LAUNCH_CHECK();

@@ -10,6 +10,7 @@
 //  * per training partition T_p: the downdates of Lemma 14 and Lemma 7, the
 //    deviation by Lemma 12 with divisor |T_p| - ddof, and the zero -> 1 rule
 //    of Algorithm 7 step 24 read as "column constant over T_p".
+#include <climits>
 #include <cmath>
 
 #include "internal.h"
@@ -17,92 +18,172 @@
 namespace cvg {
 namespace {
 
-// fold layout: [4][P][W]
-__global__ __launch_bounds__(256) void stats_reduce_kernel(const double* __restrict__ part,
-                                                           int64_t n_chunks,
-                                                           const int32_t* __restrict__ cbeg,
-                                                           int32_t P, int64_t W,
-                                                           double* __restrict__ fold) {
-  const int64_t j = (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
-  const int32_t p = blockIdx.x;
-  if (j >= W) return;
-  const int64_t ps = n_chunks * W;
+// fold layout: [4][P][W].  items: (prob, fold); grid.y = blocks of 64
+// columns.  The 4 waves of a workgroup take every 4th chunk of the fold and
+// are combined in wave order (deterministic).
+__global__ __launch_bounds__(256) void stats_reduce_kernel(const ProbDesc* __restrict__ pds,
+                                                           const Item* __restrict__ items) {
+  __shared__ double sh[4][4][64];
+  const Item it = items[blockIdx.x];
+  const ProbDesc& pd = pds[it.prob];
+  const int32_t p = it.a;
+  const int64_t W = pd.W;
+  if ((int64_t)blockIdx.y * 64 >= W) return;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t j = (int64_t)blockIdx.y * 64 + lane;
+  const int64_t ps = pd.n_chunks * W;
+  const double* part = pd.part;
   double s = 0.0, q = 0.0, mn = INFINITY, mx = -INFINITY;
-  for (int32_t c = cbeg[p]; c < cbeg[p + 1]; ++c) {
-    s += part[0 * ps + (int64_t)c * W + j];
-    q += part[1 * ps + (int64_t)c * W + j];
-    mn = fmin(mn, part[2 * ps + (int64_t)c * W + j]);
-    mx = fmax(mx, part[3 * ps + (int64_t)c * W + j]);
+  if (j < W) {
+#pragma unroll 4
+    for (int32_t c = pd.chunk_begin[p] + w; c < pd.chunk_begin[p + 1]; c += 4) {
+      s += part[0 * ps + (int64_t)c * W + j];
+      q += part[1 * ps + (int64_t)c * W + j];
+      mn = fmin(mn, part[2 * ps + (int64_t)c * W + j]);
+      mx = fmax(mx, part[3 * ps + (int64_t)c * W + j]);
+    }
   }
-  const int64_t fs = (int64_t)P * W;
-  fold[0 * fs + (int64_t)p * W + j] = s;
-  fold[1 * fs + (int64_t)p * W + j] = q;
-  fold[2 * fs + (int64_t)p * W + j] = mn;
-  fold[3 * fs + (int64_t)p * W + j] = mx;
+  sh[0][w][lane] = s;
+  sh[1][w][lane] = q;
+  sh[2][w][lane] = mn;
+  sh[3][w][lane] = mx;
+  __syncthreads();
+  if (w == 0 && j < W) {
+    for (int k = 1; k < 4; ++k) {
+      s += sh[0][k][lane];
+      q += sh[1][k][lane];
+      mn = fmin(mn, sh[2][k][lane]);
+      mx = fmax(mx, sh[3][k][lane]);
+    }
+    const int64_t fs = (int64_t)pd.P * W;
+    pd.fold[0 * fs + (int64_t)p * W + j] = s;
+    pd.fold[1 * fs + (int64_t)p * W + j] = q;
+    pd.fold[2 * fs + (int64_t)p * W + j] = mn;
+    pd.fold[3 * fs + (int64_t)p * W + j] = mx;
+  }
 }
 
-// One thread per column; loops over folds in order (deterministic).
-// scratch: [2][P][W] suffix minima / maxima of the fold extrema.
-__global__ __launch_bounds__(256) void train_stats_kernel(
-    const double* __restrict__ fold, const int64_t* __restrict__ offsets, int32_t P, int64_t N,
-    int64_t W, int ddof, const double* __restrict__ pivot, double* __restrict__ scratch,
-    double* __restrict__ tr_sum, double* __restrict__ tr_mean, double* __restrict__ tr_std,
-    double* __restrict__ tr_mu, uint8_t* __restrict__ tr_const, int64_t* __restrict__ ntrain) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= W) return;
+// Column totals over all folds and, for the exact constant test, the
+// smallest and largest value of each column with the fold holding it and
+// the runner-up over the other folds: the extrema over T_p (all folds but p)
+// are then available for every p in O(1).
+// tot layout: [8][W] = S, Q, min1, argmin (as double), min2, max1, argmax, max2
+struct Ext {
+  double v1;
+  int32_t f1;
+  double v2;
+};
+
+__device__ inline Ext ext_min(Ext a, Ext b) {
+  // smallest value, the lower fold winning ties; runner-up from another fold
+  Ext r;
+  const bool a_first = a.v1 < b.v1 || (a.v1 == b.v1 && a.f1 <= b.f1);
+  r.v1 = a_first ? a.v1 : b.v1;
+  r.f1 = a_first ? a.f1 : b.f1;
+  r.v2 = fmin(fmin(a.v2, b.v2), a_first ? b.v1 : a.v1);
+  return r;
+}
+
+__device__ inline Ext ext_max(Ext a, Ext b) {
+  Ext r;
+  const bool a_first = a.v1 > b.v1 || (a.v1 == b.v1 && a.f1 <= b.f1);
+  r.v1 = a_first ? a.v1 : b.v1;
+  r.f1 = a_first ? a.f1 : b.f1;
+  r.v2 = fmax(fmax(a.v2, b.v2), a_first ? b.v1 : a.v1);
+  return r;
+}
+
+// items: (prob, block of 64 columns).  One workgroup reduces all folds of
+// its columns in a fixed order (folds w, w + 4, ... per wave, then waves
+// 0..3), so the totals are deterministic.
+__global__ __launch_bounds__(256) void fold_totals_kernel(const ProbDesc* __restrict__ pds,
+                                                          const Item* __restrict__ items) {
+  __shared__ double sS[4][64], sQ[4][64];
+  __shared__ Ext sMn[4][64], sMx[4][64];
+  const Item it = items[blockIdx.x];
+  const ProbDesc& pd = pds[it.prob];
+  const int64_t W = pd.W;
+  const int32_t P = pd.P;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t j = (int64_t)it.a * 64 + lane;
   const int64_t fs = (int64_t)P * W;
-  const double* fsum = fold;
-  const double* fsq = fold + fs;
-  const double* fmn = fold + 2 * fs;
-  const double* fmx = fold + 3 * fs;
-  double* smn = scratch;
-  double* smx = scratch + fs;
-  // totals over all rows (Algorithm 7 step 4, shifted) and suffix extrema
+  const double* fold = pd.fold;
   double S = 0.0, Q = 0.0;
-  for (int32_t p = 0; p < P; ++p) {
-    S += fsum[(int64_t)p * W + j];
-    Q += fsq[(int64_t)p * W + j];
-  }
-  double run_mn = INFINITY, run_mx = -INFINITY;
-  for (int32_t p = P - 1; p >= 0; --p) {
-    smn[(int64_t)p * W + j] = run_mn;  // extrema over folds > p
-    smx[(int64_t)p * W + j] = run_mx;
-    run_mn = fmin(run_mn, fmn[(int64_t)p * W + j]);
-    run_mx = fmax(run_mx, fmx[(int64_t)p * W + j]);
-  }
-  const double c = pivot[j];
-  double pre_mn = INFINITY, pre_mx = -INFINITY;
-  for (int32_t p = 0; p < P; ++p) {
-    const int64_t e = (int64_t)p * W + j;
-    const int64_t nv = offsets[p + 1] - offsets[p];
-    const int64_t nt = N - nv;
-    const double NT = (double)nt;
-    const double sT = S - fsum[e];                 // Lemma 14
-    const double qT = Q - fsq[e];
-    const double mu = sT / NT;                     // training mean of shifted values
-    const double tmn = fmin(pre_mn, smn[e]);
-    const double tmx = fmax(pre_mx, smx[e]);
-    const bool constant = tmn == tmx;
-    double sd;
-    if (nt - ddof < 1) {
-      sd = NAN;                                    // not scalable (Definition 6)
-    } else if (constant) {
-      sd = 1.0;                                    // Algorithm 7 step 24
-    } else {
-      // Lemma 12 on shifted values: (|T| mu^2 + sum x^2 - 2 mu sum x) / (|T| - ddof)
-      double var = (NT * mu * mu + qT - 2.0 * mu * sT) / (double)(nt - ddof);
-      sd = sqrt(var > 0.0 ? var : 0.0);
-      if (sd == 0.0) sd = 1.0;
+  Ext mn{INFINITY, INT32_MAX, INFINITY}, mx{-INFINITY, INT32_MAX, -INFINITY};
+  if (j < W) {
+#pragma unroll 4
+    for (int32_t p = w; p < P; p += 4) {
+      const int64_t e = (int64_t)p * W + j;
+      S += fold[e];
+      Q += fold[fs + e];
+      mn = ext_min(mn, Ext{fold[2 * fs + e], p, INFINITY});
+      mx = ext_max(mx, Ext{fold[3 * fs + e], p, -INFINITY});
     }
-    tr_sum[e] = sT;
-    tr_mean[e] = constant ? 0.0 : mu;
-    tr_std[e] = sd;
-    tr_mu[e] = constant ? tmn : c + mu;
-    tr_const[e] = constant ? 1 : 0;
-    if (j == 0) ntrain[p] = nt;
-    pre_mn = fmin(pre_mn, fmn[e]);
-    pre_mx = fmax(pre_mx, fmx[e]);
   }
+  sS[w][lane] = S;
+  sQ[w][lane] = Q;
+  sMn[w][lane] = mn;
+  sMx[w][lane] = mx;
+  __syncthreads();
+  if (w == 0 && j < W) {
+    for (int k = 1; k < 4; ++k) {
+      S += sS[k][lane];
+      Q += sQ[k][lane];
+      mn = ext_min(mn, sMn[k][lane]);
+      mx = ext_max(mx, sMx[k][lane]);
+    }
+    double* tot = pd.tot;
+    tot[0 * W + j] = S;
+    tot[1 * W + j] = Q;
+    tot[2 * W + j] = mn.v1;
+    tot[3 * W + j] = (double)mn.f1;
+    tot[4 * W + j] = mn.v2;
+    tot[5 * W + j] = mx.v1;
+    tot[6 * W + j] = (double)mx.f1;
+    tot[7 * W + j] = mx.v2;
+  }
+}
+
+// One thread per (fold, column): Lemma 14 and Lemma 7 downdates, Lemma 12
+// on shifted values, and the constant-column rule.  items: (prob, fold);
+// grid.y = blocks of 256 columns.
+__global__ __launch_bounds__(256) void train_stats_kernel(const ProbDesc* __restrict__ pds,
+                                                          const Item* __restrict__ items) {
+  const Item it = items[blockIdx.x];
+  const ProbDesc& pd = pds[it.prob];
+  const int32_t p = it.a;
+  const int64_t W = pd.W;
+  const int64_t j = (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
+  if (j >= W) return;
+  const int64_t fs = (int64_t)pd.P * W;
+  const int64_t e = (int64_t)p * W + j;
+  const int64_t nv = pd.offsets[p + 1] - pd.offsets[p];
+  const int64_t nt = pd.N - nv;
+  const double NT = (double)nt;
+  const double* tot = pd.tot;
+  const double sT = tot[0 * W + j] - pd.fold[e];          // Lemma 14
+  const double qT = tot[1 * W + j] - pd.fold[fs + e];
+  const double mu = sT / NT;                              // Lemma 7 (shifted)
+  const double tmn = (int32_t)tot[3 * W + j] == p ? tot[4 * W + j] : tot[2 * W + j];
+  const double tmx = (int32_t)tot[6 * W + j] == p ? tot[7 * W + j] : tot[5 * W + j];
+  const bool constant = tmn == tmx;
+  double sd;
+  if (nt - pd.ddof < 1) {
+    sd = NAN;                                             // not scalable (Definition 6)
+  } else if (constant) {
+    sd = 1.0;                                             // Algorithm 7 step 24
+  } else {
+    // Lemma 12 on shifted values: (|T| mu^2 + sum x^2 - 2 mu sum x) / (|T| - ddof)
+    const double var = (NT * mu * mu + qT - 2.0 * mu * sT) / (double)(nt - pd.ddof);
+    sd = sqrt(var > 0.0 ? var : 0.0);
+    if (sd == 0.0) sd = 1.0;
+  }
+  pd.tr_sum[e] = sT;
+  pd.tr_mean[e] = constant ? 0.0 : mu;
+  pd.tr_std[e] = sd;
+  pd.tr_mu[e] = constant ? tmn : pd.pivot[j] + mu;
+  pd.tr_const[e] = constant ? 1 : 0;
+  if (j == 0) pd.ntrain[p] = nt;
 }
 
 __global__ void fold_stats_kernel(const double* __restrict__ tr_mu,
@@ -124,20 +205,26 @@ __global__ void fold_stats_kernel(const double* __restrict__ tr_mu,
 
 }  // namespace
 
-void launch_stats_reduce(const double* part, int64_t n_chunks, const int32_t* chunk_begin,
-                         int32_t P, int64_t W, double* fold, hipStream_t s) {
-  dim3 grid((unsigned)P, (unsigned)((W + 255) / 256));
-  stats_reduce_kernel<<<grid, 256, 0, s>>>(part, n_chunks, chunk_begin, P, W, fold);
+void launch_stats_reduce(const ProbDesc* pd, const Item* fold_items, int64_t n_items,
+                         int32_t max_col_blocks64, hipStream_t s) {
+  if (n_items <= 0) return;
+  dim3 grid((unsigned)n_items, (unsigned)max_col_blocks64);
+  stats_reduce_kernel<<<grid, 256, 0, s>>>(pd, fold_items);
   CVG_LAUNCH_CHECK();
 }
 
-void launch_train_stats(const double* fold, const int64_t* offsets, int32_t P, int64_t N,
-                        int64_t W, int ddof, const double* pivot, double* scratch,
-                        double* tr_sum, double* tr_mean, double* tr_std, double* tr_mu,
-                        uint8_t* tr_const, int64_t* ntrain, hipStream_t s) {
-  train_stats_kernel<<<(unsigned)((W + 255) / 256), 256, 0, s>>>(
-      fold, offsets, P, N, W, ddof, pivot, scratch, tr_sum, tr_mean, tr_std, tr_mu, tr_const,
-      ntrain);
+void launch_fold_totals(const ProbDesc* pd, const Item* colblock_items, int64_t n_items,
+                        hipStream_t s) {
+  if (n_items <= 0) return;
+  fold_totals_kernel<<<(unsigned)n_items, 256, 0, s>>>(pd, colblock_items);
+  CVG_LAUNCH_CHECK();
+}
+
+void launch_train_stats(const ProbDesc* pd, const Item* fold_items, int64_t n_items,
+                        int32_t max_col_blocks256, hipStream_t s) {
+  if (n_items <= 0) return;
+  dim3 grid((unsigned)n_items, (unsigned)max_col_blocks256);
+  train_stats_kernel<<<grid, 256, 0, s>>>(pd, fold_items);
   CVG_LAUNCH_CHECK();
 }
 

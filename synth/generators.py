@@ -308,3 +308,48 @@ def batch_shapes(count: int = 256, n_lo: int = 1000, n_hi: int = 200_000,
 
 def batch_problem(shape: Shape, index: int):
     return make(shape, BATCH_WORKLOAD, index + 1)
+
+
+# ---------------------------------------------------------------------------
+# device-side drawing of the same value models (large workloads only)
+# ---------------------------------------------------------------------------
+
+def spectra_xy_torch(n: int, k: int, m: int, seed: int, device, dtype=None,
+                     chunk_rows: int = 65536):
+    """The spectra value model of ``spectra_xy`` drawn with torch's generator
+    on ``device`` (a different random stream from the NumPy path: used where
+    drawing gigabytes on the host would dominate, never by the oracle tests).
+    Returns (X, Y) of ``dtype`` (default float32)."""
+    import torch
+    dtype = dtype or torch.float32
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    f64 = dict(dtype=torch.float64, device=device)
+    W = torch.randn(k, m, generator=g, **f64) / math.sqrt(k)
+    t = torch.arange(k, **f64) / max(1, k - 1)
+    X = torch.empty(n, k, dtype=dtype, device=device)
+    Y = torch.empty(n, m, dtype=dtype, device=device)
+    for a in range(0, n, chunk_rows):
+        b = min(n, a + chunk_rows)
+        rows = b - a
+        base = 0.5 + 1.5 * torch.rand(rows, 1, generator=g, **f64)
+        centre = torch.rand(rows, 5, generator=g, **f64)
+        width = 0.01 + 0.09 * torch.rand(rows, 5, generator=g, **f64)
+        amp = 0.1 + 0.9 * torch.rand(rows, 5, generator=g, **f64)
+        out = base.expand(rows, k).clone()
+        for j in range(5):
+            z = (t[None, :] - centre[:, j:j + 1]) / width[:, j:j + 1]
+            out += amp[:, j:j + 1] * torch.exp(-0.5 * z * z)
+        out += 1e-3 * torch.randn(rows, k, generator=g, **f64)
+        X[a:b] = out.to(dtype)
+        Y[a:b] = (out @ W + 0.1 * torch.randn(rows, m, generator=g, **f64)).to(dtype)
+    return X, Y
+
+
+def batch_problem_device(shape: Shape, index: int, device):
+    """A problem of the batched workload with values drawn on ``device``
+    (spectra model) and fold labels drawn on the host (Dirichlet(2) sizes)."""
+    import torch
+    X, Y = spectra_xy_torch(shape.n, shape.k, shape.m, ROOT_SEED * 1000 + index, device)
+    fold = folds_dirichlet(shape.n, shape.p, _rng(BATCH_WORKLOAD, index + 1, _S_FOLDS))
+    return X, Y, torch.from_numpy(fold).to(device)

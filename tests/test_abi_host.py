@@ -77,6 +77,27 @@ def test_null_handle_calls():
     assert lib.cvgram_destroy(None) == 0
 
 
+def test_batch_and_autotune_reject_bad_arguments():
+    lib = cv.load()
+    out = ctypes.c_void_p(1)
+    assert lib.cvgram_batch_create(None, 1, 1, 1, 0, None, ctypes.byref(out)) == 1
+    assert out.value is None
+    probs = (cv._Problem * 1)()
+    probs[0] = cv._Problem(FAKE, FAKE, FAKE, 10, 3, 1, None, None)
+    assert lib.cvgram_batch_create(probs, 0, 1, 1, 0, None, ctypes.byref(out)) == 1
+    assert lib.cvgram_batch_create(probs, 1, 5, 1, 0, None, ctypes.byref(out)) == 1
+    assert lib.cvgram_batch_create(probs, 1, 1, 3, 0, None, ctypes.byref(out)) == 1
+    probs[0] = cv._Problem(FAKE, None, FAKE, 10, 3, 2, None, None)   # Y NULL with M > 0
+    assert lib.cvgram_batch_create(probs, 1, 1, 1, 0, None, ctypes.byref(out)) == 1
+    assert "problem 0" in cv.cvgram_last_error_message()
+    assert lib.cvgram_batch_run(None) == 1
+    assert lib.cvgram_batch_run_eager(None) == 1
+    assert lib.cvgram_batch_destroy(None) == 0
+    t, i = ctypes.c_int32(), ctypes.c_int32()
+    assert lib.cvgram_autotune(None, None, FAKE, 10, 3, 0, 1, 0, None, ctypes.byref(t),
+                               ctypes.byref(i)) == 1
+
+
 def test_product_path_has_no_oracle_or_cpu_fallback():
     """The package and its native sources never reference the oracle."""
     pkg = os.path.join(ROOT, "paper_2401_13185_amd")

@@ -1,0 +1,182 @@
+"""GPU tests of the batched form: many independent problems of different
+N, K, M and P in one pipeline (one launch per stage), captured in a HIP graph.
+
+* every problem's 12 classes against the FP64 oracle (FP64 mode: 1e-10
+  relative Frobenius; bf16x3: the stated bound);
+* graph replays against eager runs of the same pipeline, bit for bit, with
+  the inputs changed between replays and eager work in between;
+* the autotuner returns a valid choice that later plans use.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import paper_2401_13185_amd as cv
+from oracle import cv_oracle as O
+from synth import generators as G
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+FP64_TOL = 1e-10
+BF16X3_BOUND = 2e-5
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a GPU")
+    return torch.device("cuda:0")
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(_dev())
+
+
+def _relerr(a, b):
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / nb) if nb else float(np.linalg.norm(a))
+
+
+SHAPES = [
+    # n, k, m, p, values
+    (700, 64, 1, 3, "spectra"),
+    (1500, 100, 5, 7, "gaussian"),
+    (2200, 128, 16, 20, "spectra"),
+    (999, 200, 0, 4, "gaussian"),
+    (3000, 256, 40, 5, "offset"),
+    (1200, 33, 3, 11, "gaussian"),
+    (4100, 64, 16, 3, "spectra"),
+    (1800, 130, 9, 6, "offset"),
+]
+
+
+def _problems(dtype):
+    out = []
+    for i, (n, k, m, p, values) in enumerate(SHAPES):
+        shape = G.Shape(f"batch case {i}", n, k, m, p, dtype, values, "dirichlet")
+        out.append(G.make(shape, 400 + i, 0))
+    return out
+
+
+@pytest.mark.parametrize("mode,dtype", [("fp64", "f64"), ("fp64", "f32"), ("bf16x3", "f32"),
+                                        ("fp32", "f32")])
+def test_batch_matches_oracle(mode, dtype):
+    probs = _problems(dtype)
+    print(f"[batch] mode={mode} dtype={dtype} problems={len(probs)}", flush=True)
+    dev_probs = [(_t(X), _t(Y) if Y.shape[1] else None, _t(f)) for X, Y, f in probs]
+    b = cv.cvgram_batch_create(dev_probs, ddof=1, mode=mode)
+    cv.cvgram_batch_run(b)
+    torch.cuda.synchronize()
+    tol = {"fp64": FP64_TOL, "bf16x3": BF16X3_BOUND, "fp32": 1e-6}[mode]
+    for i, (X, Y, f) in enumerate(probs):
+        P, scalable = cv.cvgram_batch_problem_info(b, i)
+        assert P == int(f.max()) + 1 and scalable
+        xx = b.outs[i][0].cpu().numpy()
+        xy = b.outs[i][1].cpu().numpy() if b.outs[i][1] is not None else None
+        for q in range(P):
+            oxx, oxy = O.fold_all_classes(X, Y, f, q, ddof=1)
+            for c in range(4):
+                e = _relerr(xx[q, c], oxx[c])
+                assert e <= tol, (mode, i, q, "XtX", c, e)
+                assert np.array_equal(xx[q, c], xx[q, c].T)
+            for c in range(8 if Y.shape[1] else 0):
+                e = _relerr(xy[q, c], oxy[c])
+                assert e <= tol, (mode, i, q, "XtY", c, e)
+    cv.cvgram_batch_destroy(b)
+
+
+@pytest.mark.parametrize("mode", ["fp64", "bf16x3"])
+def test_graph_replays_match_eager_runs(mode):
+    probs = _problems("f32" if mode == "bf16x3" else "f64")
+    dev_probs = [(_t(X), _t(Y) if Y.shape[1] else None, _t(f)) for X, Y, f in probs]
+    b = cv.cvgram_batch_create(dev_probs, ddof=1, mode=mode)
+    rng = np.random.default_rng(0)
+    for rep in range(3):
+        # change the inputs in place (eager torch work between replays)
+        for X, Y, _ in dev_probs:
+            X.mul_(1.0 + 0.01 * rep).add_(float(rng.uniform(-1, 1)))
+            if Y is not None:
+                Y.add_(0.5 * rep)
+        cv.cvgram_batch_run(b)
+        torch.cuda.synchronize()
+        graph_out = [(xx.clone(), None if xy is None else xy.clone()) for xx, xy in b.outs]
+        for xx, xy in b.outs:           # scribble, then recompute eagerly
+            xx.fill_(float("nan"))
+            if xy is not None:
+                xy.fill_(float("nan"))
+        cv.cvgram_batch_run_eager(b)
+        torch.cuda.synchronize()
+        for (gx, gy), (ex, ey) in zip(graph_out, b.outs):
+            assert torch.equal(gx, ex)
+            if gy is not None:
+                assert torch.equal(gy, ey)
+    # the last replay also matches the oracle on the changed inputs
+    X, Y, f = (t.cpu().numpy() if t is not None else None for t in dev_probs[2])
+    oxx, oxy = O.fold_all_classes(X, Y, f, 1, ddof=1)
+    tol = FP64_TOL if mode == "fp64" else BF16X3_BOUND
+    for c in range(4):
+        assert _relerr(b.outs[2][0][1, c].cpu().numpy(), oxx[c]) <= tol
+    cv.cvgram_batch_destroy(b)
+
+
+def test_batch_equals_single_handles_fp64():
+    probs = _problems("f64")
+    dev_probs = [(_t(X), _t(Y) if Y.shape[1] else None, _t(f)) for X, Y, f in probs]
+    b = cv.cvgram_batch_create(dev_probs, ddof=0, mode="fp64")
+    cv.cvgram_batch_run(b)
+    for i, (X, Y, f) in enumerate(dev_probs):
+        h = cv.cvgram_create(X, Y, f, ddof=0, mode="fp64")
+        xx, xy = cv.cvgram_folds_all(h, 0, cv.cvgram_num_folds(h))
+        torch.cuda.synchronize()
+        d = (torch.linalg.norm(xx - b.outs[i][0]) / torch.linalg.norm(xx)).item()
+        assert d <= 1e-13, (i, d)
+        cv.cvgram_destroy(h)
+    cv.cvgram_batch_destroy(b)
+
+
+def test_batch_many_problems_sampled():
+    """A 64-problem batch of the batched workload's shape family (smaller N):
+    every 8th problem against the oracle."""
+    shapes = G.batch_shapes(64, n_lo=500, n_hi=6000)
+    probs = [G.batch_problem(s, i) for i, s in enumerate(shapes)]
+    dev_probs = [(_t(X), _t(Y), _t(f)) for X, Y, f in probs]
+    b = cv.cvgram_batch_create(dev_probs, ddof=1, mode="bf16x3")
+    cv.cvgram_batch_run(b)
+    torch.cuda.synchronize()
+    for i in range(0, 64, 8):
+        X, Y, f = probs[i]
+        P, _ = cv.cvgram_batch_problem_info(b, i)
+        for q in (0, P - 1):
+            oxx, oxy = O.fold_all_classes(X, Y, f, q, ddof=1)
+            for c in range(4):
+                assert _relerr(b.outs[i][0][q, c].cpu().numpy(), oxx[c]) <= BF16X3_BOUND, (i, q, c)
+            for c in range(8):
+                assert _relerr(b.outs[i][1][q, c].cpu().numpy(), oxy[c]) <= BF16X3_BOUND, (i, q, c)
+    cv.cvgram_batch_destroy(b)
+
+
+def test_batch_error_reports_problem_index():
+    ok = G.make(G.Shape("ok", 300, 10, 2, 3, "f64", "gaussian", "dirichlet"), 1, 0)
+    bad_fold = ok[2].copy()
+    bad_fold[bad_fold == 1] = 0          # fold 1 empty -> Definition 1 violated
+    probs = [(_t(ok[0]), _t(ok[1]), _t(ok[2])), (_t(ok[0]), _t(ok[1]), _t(bad_fold))]
+    with pytest.raises(cv.CVGramError) as ei:
+        cv.cvgram_batch_create(probs, mode="fp64")
+    assert ei.value.status == 2 and "problem 1" in str(ei.value)
+
+
+def test_autotune_returns_valid_choice_and_results_stay_correct():
+    shape = G.Shape("tune", 20000, 192, 8, 6, "f32", "spectra", "dirichlet")
+    X, Y, f = G.make(shape, 77, 0)
+    Xd, Yd, fd = _t(X), _t(Y), _t(f)
+    tile, items = cv.cvgram_autotune(Xd, Yd, fd, mode="bf16x3")
+    print(f"[autotune] tile={tile} items={items}", flush=True)
+    assert tile in (64, 128) and items in (512, 1024, 2048, 4096)
+    h = cv.cvgram_create(Xd, Yd, fd, 1, 1, 1, 1, mode="bf16x3")   # uses the tuned bucket
+    xx, xy = cv.cvgram_folds_all(h, 0, 6)
+    oxx, oxy = O.fold_all_classes(X, Y, f, 2, ddof=1)
+    for c in range(4):
+        assert _relerr(xx[2, c].cpu().numpy(), oxx[c]) <= BF16X3_BOUND
+    cv.cvgram_destroy(h)
