@@ -41,6 +41,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--mode", default="fp64", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--workload", type=int, default=2, choices=[2, 3],
+                    help="headline workload: 2 = spectra N=1e5 K=512 (default), "
+                         "3 = precision-stress N=1e6 K=1024 (for profiling one mode)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline legs")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-mixed", action="store_true",
@@ -49,6 +52,9 @@ def parse():
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched block (256 independent problems, graph replay)")
     ap.add_argument("--batch-steps", type=int, default=5)
+    ap.add_argument("--copy-ref-mib", type=int, default=0,
+                    help="first run one plain device-to-device copy of this many MiB: the "
+                         "reference dispatch that scales HBM byte counters in a profile")
     return ap.parse_args()
 
 
@@ -141,7 +147,14 @@ def main():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(1)
     dev = torch.device("cuda:0")
-    shape, (X, Y, fold) = G.workload(2)
+    if args.copy_ref_mib:
+        src = torch.empty(args.copy_ref_mib << 18, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    shape, (X, Y, fold) = G.workload(args.workload)
     N, K, M, P = shape.n, shape.k, shape.m, shape.p
     print(f"[bench] workload {shape.name} generated", file=sys.stderr, flush=True)
     Xd = torch.from_numpy(X).to(dev)
@@ -168,7 +181,7 @@ def main():
         "vs_baseline": None,
         "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3+f32acc"}[args.mode],
         "data": "synthetic",
-        "config": {"workload": shape.name, "N": N, "K": K, "M": M, "P": P, "folds": "Dirichlet(2)",
+        "config": {"workload": shape.name, "N": N, "K": K, "M": M, "P": P, "folds": {"dirichlet": "Dirichlet(2)", "near_equal": "near-equal"}[shape.folds],
                    "mode": args.mode, "classes_per_fold": 12, "ddof": 1},
         "tflops_alg": flops / (ms * 1e-3) / 1e12,
         "stage_ms": stage_ms,

@@ -38,16 +38,27 @@ __global__ __launch_bounds__(256) void reduce_slabs_kernel(const ProbDesc* __res
   if (e >= elems) return;
   const int64_t i = e / W, j = e - (e / W) * W;
   if (j < K && j < i) return;
-  double* slabs = pd.slabs;
+  CVG_GLOBAL double* slabs = gmem(pd.slabs) + e;
+  const CVG_GLOBAL int32_t* slab_begin = gmem(pd.slab_begin);
+  const int32_t P = pd.P;
   double g = 0.0;
-  for (int32_t p = 0; p < pd.P; ++p) {
-    const int32_t a = pd.slab_begin[p], b = pd.slab_begin[p + 1];
-    double f = slabs[(int64_t)a * elems + e];
-    for (int32_t k = a + 1; k < b; ++k) f += slabs[(int64_t)k * elems + e];
-    if (b > a + 1) slabs[(int64_t)a * elems + e] = f;
+  int32_t a = slab_begin[0];
+  for (int32_t p = 0; p < P; ++p) {
+    const int32_t b = slab_begin[p + 1];
+    double f = slabs[(int64_t)a * elems];
+    int32_t k = a + 1;
+    // four independent loads in flight per step; the sum keeps slab order
+    for (; k + 3 < b; k += 4) {
+      const double v0 = slabs[(int64_t)k * elems], v1 = slabs[(int64_t)(k + 1) * elems];
+      const double v2 = slabs[(int64_t)(k + 2) * elems], v3 = slabs[(int64_t)(k + 3) * elems];
+      f = (((f + v0) + v1) + v2) + v3;
+    }
+    for (; k < b; ++k) f += slabs[(int64_t)k * elems];
+    if (b > a + 1) slabs[(int64_t)a * elems] = f;
     g += f;
+    a = b;
   }
-  pd.G[e] = g;
+  gmem(pd.G)[e] = g;
 }
 
 template <typename OutT>
@@ -59,8 +70,14 @@ __device__ void correct_tile(const ProbDesc& pd, const OutDesc& od, int32_t f, i
 
   const int32_t p = od.p_begin + f;
   const bool is_xy = tile >= pd.n_ctiles_xx;
-  const int bi = pd.ctiles[2 * tile];
-  const int bj = pd.ctiles[2 * tile + 1];
+  const CVG_GLOBAL int32_t* ctiles = gmem(pd.ctiles);
+  const int bi = ctiles[2 * tile];
+  const int bj = ctiles[2 * tile + 1];
+  const CVG_GLOBAL double* pivot = gmem((const double*)pd.pivot);
+  const CVG_GLOBAL double* tr_sum = gmem((const double*)pd.tr_sum);
+  const CVG_GLOBAL double* tr_mean = gmem((const double*)pd.tr_mean);
+  const CVG_GLOBAL double* tr_std = gmem((const double*)pd.tr_std);
+  const CVG_GLOBAL uint8_t* tr_const = gmem((const uint8_t*)pd.tr_const);
   const bool diag = !is_xy && bi == bj;
   const int64_t K = pd.K, M = pd.M, W = pd.W;
   const int64_t ncols = is_xy ? M : K;
@@ -72,28 +89,30 @@ __device__ void correct_tile(const ProbDesc& pd, const OutDesc& od, int32_t f, i
   if (t < TS) {
     const int64_t i = (int64_t)bi * TS + t;
     if (i < K) {
-      rc[t] = pd.pivot[i];
-      ra[t] = pd.tr_sum[pw + i];
-      rmu[t] = pd.tr_mean[pw + i];
-      rsd[t] = pd.tr_std[pw + i];
-      rcs[t] = pd.tr_const[pw + i];
+      rc[t] = pivot[i];
+      ra[t] = tr_sum[pw + i];
+      rmu[t] = tr_mean[pw + i];
+      rsd[t] = tr_std[pw + i];
+      rcs[t] = tr_const[pw + i];
     }
   } else if (t < 2 * TS) {
     const int u = t - TS;
     const int64_t j = (int64_t)bj * TS + u;
     if (j < ncols) {
       const int64_t z = coff + j;
-      cc[u] = pd.pivot[z];
-      ca[u] = pd.tr_sum[pw + z];
-      cmu[u] = pd.tr_mean[pw + z];
-      csd[u] = pd.tr_std[pw + z];
-      ccs[u] = pd.tr_const[pw + z];
+      cc[u] = pivot[z];
+      ca[u] = tr_sum[pw + z];
+      cmu[u] = tr_mean[pw + z];
+      csd[u] = tr_std[pw + z];
+      ccs[u] = tr_const[pw + z];
     }
   }
   __syncthreads();
 
-  const double NT = (double)pd.ntrain[p];
-  const double* gp_slab = pd.slabs + (int64_t)pd.slab_begin[p] * K * W;  // fold sum G'_p
+  const double NT = (double)gmem((const int64_t*)pd.ntrain)[p];
+  const CVG_GLOBAL double* G = gmem((const double*)pd.G);
+  const CVG_GLOBAL double* gp_slab =
+      gmem((const double*)pd.slabs) + (int64_t)gmem(pd.slab_begin)[p] * K * W;  // fold sum G'_p
 
   double raw[kRowsPerThread], cen[kRowsPerThread];
   bool ok[kRowsPerThread];
@@ -107,16 +126,15 @@ __device__ void correct_tile(const ProbDesc& pd, const OutDesc& od, int32_t f, i
     cen[r] = 0.0;
     if (!ok[r]) continue;
     const int64_t e = i * W + coff + j;
-    const double g = pd.G[e] - gp_slab[e];
+    const double g = G[e] - gp_slab[e];
     raw[r] = g + (rc[il] * ca[jl] + ra[il] * cc[jl]) + NT * (rc[il] * cc[jl]);
     cen[r] = (rcs[il] || ccs[jl]) ? 0.0 : g - NT * (rmu[il] * cmu[jl]);
   }
 
   if (!is_xy) {
     for (int c = 0; c < CVGRAM_XTX_CLASSES; ++c) {
-      OutT* out = (OutT*)od.xx[c];
-      if (!out) continue;
-      out += (int64_t)f * od.fold_stride_xx;
+      if (!od.xx[c]) continue;
+      CVG_GLOBAL OutT* out = gmem((OutT*)od.xx[c]) + (int64_t)f * od.fold_stride_xx;
       const bool centred = c & 2, scaled = c & 1;
       double v[kRowsPerThread];
 #pragma unroll
@@ -146,9 +164,8 @@ __device__ void correct_tile(const ProbDesc& pd, const OutDesc& od, int32_t f, i
     }
   } else {
     for (int c = 0; c < CVGRAM_XTY_CLASSES; ++c) {
-      OutT* out = (OutT*)od.xy[c];
-      if (!out) continue;
-      out += (int64_t)f * od.fold_stride_xy;
+      if (!od.xy[c]) continue;
+      CVG_GLOBAL OutT* out = gmem((OutT*)od.xy[c]) + (int64_t)f * od.fold_stride_xy;
       const bool centred = c & 4, scx = c & 2, scy = c & 1;
 #pragma unroll
       for (int r = 0; r < kRowsPerThread; ++r) {

@@ -29,6 +29,8 @@
 // contiguous range of items, so tiles that read the same rows share an L2).
 #include "internal.h"
 
+#include <type_traits>
+
 namespace cvg {
 namespace {
 
@@ -100,18 +102,18 @@ template <int BM>
 struct Stage<CVGRAM_MODE_FP64, BM> {
   static constexpr int V = BM / 32;  // double2 per thread per operand
   double2_t a[V], b[V], y;
-  __device__ void load(const double* Z, int64_t Wp, int64_t r, int64_t ca, int64_t cb,
+  __device__ void load(const CVG_GLOBAL double* Z, int64_t Wp, int64_t r, int64_t ca, int64_t cb,
                        int64_t cy, bool ld_b, bool ld_y, int t) {
     const int row = t >> 4, col = (t & 15) * (BM / 16);
-    const double* pa = Z + (r + row) * Wp + ca + col;
+    const CVG_GLOBAL double* pa = Z + (r + row) * Wp + ca + col;
 #pragma unroll
-    for (int u = 0; u < V; ++u) a[u] = *(const double2_t*)(pa + 2 * u);
+    for (int u = 0; u < V; ++u) a[u] = *(const CVG_GLOBAL double2_t*)(pa + 2 * u);
     if (ld_b) {
-      const double* pb = Z + (r + row) * Wp + cb + col;
+      const CVG_GLOBAL double* pb = Z + (r + row) * Wp + cb + col;
 #pragma unroll
-      for (int u = 0; u < V; ++u) b[u] = *(const double2_t*)(pb + 2 * u);
+      for (int u = 0; u < V; ++u) b[u] = *(const CVG_GLOBAL double2_t*)(pb + 2 * u);
     }
-    if (ld_y) y = *(const double2_t*)(Z + (r + row) * Wp + cy + (t & 15) * 2);
+    if (ld_y) y = *(const CVG_GLOBAL double2_t*)(Z + (r + row) * Wp + cy + (t & 15) * 2);
   }
   __device__ void store(Smem<CVGRAM_MODE_FP64, BM>& s, int buf, bool st_b, bool st_y,
                         int t) const {
@@ -132,18 +134,19 @@ template <int BM>
 struct Stage<CVGRAM_MODE_FP32, BM> {
   static constexpr int V = BM / 64;  // float4 per thread per operand
   float4_t a[V], b[V], y;
-  __device__ void load(const float* Z, int64_t Wp, int64_t r, int64_t ca, int64_t cb, int64_t cy,
-                       bool ld_b, bool ld_y, int t) {
+  __device__ void load(const CVG_GLOBAL float* Z, int64_t Wp, int64_t r, int64_t ca, int64_t cb,
+                       int64_t cy, bool ld_b, bool ld_y, int t) {
     const int row = t >> 4, col = (t & 15) * (BM / 16);
-    const float* pa = Z + (r + row) * Wp + ca + col;
+    const CVG_GLOBAL float* pa = Z + (r + row) * Wp + ca + col;
 #pragma unroll
-    for (int u = 0; u < V; ++u) a[u] = *(const float4_t*)(pa + 4 * u);
+    for (int u = 0; u < V; ++u) a[u] = *(const CVG_GLOBAL float4_t*)(pa + 4 * u);
     if (ld_b) {
-      const float* pb = Z + (r + row) * Wp + cb + col;
+      const CVG_GLOBAL float* pb = Z + (r + row) * Wp + cb + col;
 #pragma unroll
-      for (int u = 0; u < V; ++u) b[u] = *(const float4_t*)(pb + 4 * u);
+      for (int u = 0; u < V; ++u) b[u] = *(const CVG_GLOBAL float4_t*)(pb + 4 * u);
     }
-    if (ld_y && t < 128) y = *(const float4_t*)(Z + (r + (t >> 3)) * Wp + cy + (t & 7) * 4);
+    if (ld_y && t < 128)
+      y = *(const CVG_GLOBAL float4_t*)(Z + (r + (t >> 3)) * Wp + cy + (t & 7) * 4);
   }
   __device__ void store(Smem<CVGRAM_MODE_FP32, BM>& s, int buf, bool st_b, bool st_y,
                         int t) const {
@@ -165,28 +168,30 @@ template <int BM>
 struct Stage<CVGRAM_MODE_BF16X3, BM> {
   static constexpr int V = BM / 64;
   bf16x8_t ah[V], al[V], bh[V], bl[V], y;
-  __device__ void load(const __bf16* Zh, const __bf16* Zl, int64_t Wp, int64_t r, int64_t ca,
-                       int64_t cb, int64_t cy, bool ld_b, bool ld_y, int t) {
+  __device__ void load(const CVG_GLOBAL __bf16* Zh, const CVG_GLOBAL __bf16* Zl, int64_t Wp,
+                       int64_t r, int64_t ca, int64_t cb, int64_t cy, bool ld_b, bool ld_y,
+                       int t) {
+    typedef const CVG_GLOBAL bf16x8_t* V8;
     const int64_t panel = (r / 32) * Wp;
-    const __bf16* ha = Zh + (panel + ca) * 32;
-    const __bf16* la = Zl + (panel + ca) * 32;
+    const CVG_GLOBAL __bf16* ha = Zh + (panel + ca) * 32;
+    const CVG_GLOBAL __bf16* la = Zl + (panel + ca) * 32;
 #pragma unroll
     for (int u = 0; u < V; ++u) {
-      ah[u] = *(const bf16x8_t*)(ha + (t + 256 * u) * 8);
-      al[u] = *(const bf16x8_t*)(la + (t + 256 * u) * 8);
+      ah[u] = *(V8)(ha + (t + 256 * u) * 8);
+      al[u] = *(V8)(la + (t + 256 * u) * 8);
     }
     if (ld_b) {
-      const __bf16* hb = Zh + (panel + cb) * 32;
-      const __bf16* lb = Zl + (panel + cb) * 32;
+      const CVG_GLOBAL __bf16* hb = Zh + (panel + cb) * 32;
+      const CVG_GLOBAL __bf16* lb = Zl + (panel + cb) * 32;
 #pragma unroll
       for (int u = 0; u < V; ++u) {
-        bh[u] = *(const bf16x8_t*)(hb + (t + 256 * u) * 8);
-        bl[u] = *(const bf16x8_t*)(lb + (t + 256 * u) * 8);
+        bh[u] = *(V8)(hb + (t + 256 * u) * 8);
+        bl[u] = *(V8)(lb + (t + 256 * u) * 8);
       }
     }
     if (ld_y) {
-      const __bf16* src = (t < 128 ? Zh : Zl) + (panel + cy) * 32;
-      y = *(const bf16x8_t*)(src + (t & 127) * 8);
+      const CVG_GLOBAL __bf16* src = (t < 128 ? Zh : Zl) + (panel + cy) * 32;
+      y = *(V8)(src + (t & 127) * 8);
     }
   }
   __device__ void store(Smem<CVGRAM_MODE_BF16X3, BM>& s, int buf, bool st_b, bool st_y,
@@ -257,7 +262,9 @@ __device__ inline void mma_bf16x3(const __bf16* Ah, const __bf16* Al, int acol0,
                                   const __bf16* Bl, int bcol0, float4_t (&acc)[NACC], int fr,
                                   int fc) {
   constexpr int LDK = Mode<CVGRAM_MODE_BF16X3>::LDK;
-  bf16x8_t ah[NA], al[NA];
+  // every fragment of the stage first, then the three products in passes
+  // over all blocks, so consecutive MFMAs update different accumulators
+  bf16x8_t ah[NA], al[NA], bh[NB], bl[NB];
 #pragma unroll
   for (int a = 0; a < NA; ++a) {
     const int off = (acol0 + a * 16 + fc) * LDK + fr * 8;
@@ -267,17 +274,24 @@ __device__ inline void mma_bf16x3(const __bf16* Ah, const __bf16* Al, int acol0,
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
     const int off = (bcol0 + b * 16 + fc) * LDK + fr * 8;
-    const bf16x8_t bh = *(const bf16x8_t*)&Bh[off];
-    const bf16x8_t bl = *(const bf16x8_t*)&Bl[off];
-#pragma unroll
-    for (int a = 0; a < NA; ++a) {
-      float4_t c = acc[a * NB + b];
-      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bh, c, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bl, c, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bh, c, 0, 0, 0);
-      acc[a * NB + b] = c;
-    }
+    bh[b] = *(const bf16x8_t*)&Bh[off];
+    bl[b] = *(const bf16x8_t*)&Bl[off];
   }
+#pragma unroll
+  for (int a = 0; a < NA; ++a)
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+      acc[a * NB + b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bh[b], acc[a * NB + b], 0, 0, 0);
+#pragma unroll
+  for (int a = 0; a < NA; ++a)
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+      acc[a * NB + b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bl[b], acc[a * NB + b], 0, 0, 0);
+#pragma unroll
+  for (int a = 0; a < NA; ++a)
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+      acc[a * NB + b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bh[b], acc[a * NB + b], 0, 0, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -304,11 +318,15 @@ __global__ __launch_bounds__(kThreads) void gram_kernel(const ProbDesc* __restri
   const ProbDesc& pdr = pds[w.prob];
   const int64_t Wp = pdr.Wp, Kp = pdr.Kp, K = pdr.K, M = pdr.M;
   const int32_t nt = pdr.nt;
-  const void* const packed = pdr.packed;
-  const void* const packed_lo = pdr.packed_lo;
-  double* const slabs = pdr.slabs;
+  typedef typename Mode<MODE>::E E;
+  const CVG_GLOBAL E* const packed = gmem((const E*)pdr.packed);
+  const CVG_GLOBAL E* const packed_lo = gmem((const E*)pdr.packed_lo);
+  CVG_GLOBAL double* const slabs = gmem(pdr.slabs);
   const bool xy_diag = pdr.xy_diag != 0;
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int t = threadIdx.x, lane = t & 63;
+  // wave index made scalar in the FP32-accumulating modes: their roles then
+  // branch uniformly; the FP64 loop keeps its vector form (fewer registers)
+  const int wave = kF64 ? (t >> 6) : __builtin_amdgcn_readfirstlane(t >> 6);
   const int wm = wave >> 1, wn = wave & 1;
   const int fr = lane >> 4, fc = lane & 15;
 
@@ -330,50 +348,18 @@ __global__ __launch_bounds__(kThreads) void gram_kernel(const ProbDesc* __restri
     for (int e = 0; e < 4; ++e) a64[i][e] = 0.0;
   }
 
-  Stage<MODE, BM> st;
+  // Global loads run PF stages ahead of the matrix cores: the next stage's
+  // panel block is in registers while the current one is consumed from LDS
+  // (PF = 2 keeps two stages in flight; FP64 stages are 4x longer and keep
+  // one, which also leaves room for two workgroups per CU).  The loop is
+  // instantiated per tile kind (off-diagonal / diagonal / diagonal with the
+  // K x M block) so that every stage issues the same loads: the wait before
+  // an LDS store then covers exactly the stage being stored, not the loads
+  // issued after it.  Loads past the last stage re-read the last stage.
+  constexpr int PF = kF64 ? 1 : 2;
   const int64_t nst = (w.r1 - w.r0) / BK;
-  auto load = [&](int64_t s) {
-    const int64_t r = w.r0 + s * BK;
-    if constexpr (MODE == CVGRAM_MODE_BF16X3)
-      st.load((const __bf16*)packed, (const __bf16*)packed_lo, Wp, r, ca, cb, Kp, ld_b, ydiag, t);
-    else
-      st.load((const typename Mode<MODE>::E*)packed, Wp, r, ca, cb, Kp, ld_b, ydiag, t);
-  };
-
-  load(0);
-  st.store(sm, 0, ld_b, ydiag, t);
-  __syncthreads();
   int since = 0;
-  for (int64_t s = 0; s < nst; ++s) {
-    const int buf = (int)(s & 1);
-    const bool more = s + 1 < nst;
-    if (more) load(s + 1);
-    if constexpr (MODE == CVGRAM_MODE_FP64) {
-      constexpr int LDA = Smem<MODE, BM>::LDA, LDY = Smem<MODE, BM>::LDY;
-      const double* A = sm.a[buf];
-      const double* B = diag ? sm.a[buf] : sm.b[buf];
-      if (role == 0)
-        mma_f64<NW, NW>(A, LDA, wm * WT, B, LDA, wn * WT, acc, fr, fc);
-      else if (role == 1)
-        mma_f64<NY, 2>(A, LDA, 0, sm.y[buf], LDY, 0, acc, fr, fc);
-    } else if constexpr (MODE == CVGRAM_MODE_FP32) {
-      constexpr int LDA = Smem<MODE, BM>::LDA, LDY = Smem<MODE, BM>::LDY;
-      const float* A = sm.a[buf];
-      const float* B = diag ? sm.a[buf] : sm.b[buf];
-      if (role == 0)
-        mma_f32<NW, NW>(A, LDA, wm * WT, B, LDA, wn * WT, acc, fr, fc);
-      else if (role == 1)
-        mma_f32<NY, 2>(A, LDA, 0, sm.y[buf], LDY, 0, acc, fr, fc);
-    } else {
-      const __bf16* Ah = sm.a[buf][0];
-      const __bf16* Al = sm.a[buf][1];
-      const __bf16* Bh = diag ? sm.a[buf][0] : sm.b[buf][0];
-      const __bf16* Bl = diag ? sm.a[buf][1] : sm.b[buf][1];
-      if (role == 0)
-        mma_bf16x3<NW, NW>(Ah, Al, wm * WT, Bh, Bl, wn * WT, acc, fr, fc);
-      else if (role == 1)
-        mma_bf16x3<NY, 2>(Ah, Al, 0, sm.y[buf][0], sm.y[buf][1], 0, acc, fr, fc);
-    }
+  auto flush = [&]() {
     if constexpr (!kF64) {
       since += BK;
       if (since >= kFlushRows) {
@@ -386,13 +372,90 @@ __global__ __launch_bounds__(kThreads) void gram_kernel(const ProbDesc* __restri
         }
       }
     }
-    if (more) st.store(sm, buf ^ 1, ld_b, ydiag, t);
+  };
+  auto main_loop = [&](auto diag_c, auto ydiag_c) {
+    constexpr bool DG = decltype(diag_c)::value;   // B is A
+    constexpr bool YD = decltype(ydiag_c)::value;  // K x M block in this tile
+    Stage<MODE, BM> st[PF];
+    auto load = [&](Stage<MODE, BM>& sg, int64_t s) {
+      const int64_t r = w.r0 + (s < nst ? s : nst - 1) * BK;
+      if constexpr (MODE == CVGRAM_MODE_BF16X3)
+        sg.load(packed, packed_lo, Wp, r, ca, cb, Kp, !DG, YD, t);
+      else
+        sg.load(packed, Wp, r, ca, cb, Kp, !DG, YD, t);
+    };
+    auto compute = [&](int buf) {
+      if constexpr (MODE == CVGRAM_MODE_FP64) {
+        constexpr int LDA = Smem<MODE, BM>::LDA, LDY = Smem<MODE, BM>::LDY;
+        const double* A = sm.a[buf];
+        const double* B = DG ? sm.a[buf] : sm.b[buf];
+        if (role == 0)
+          mma_f64<NW, NW>(A, LDA, wm * WT, B, LDA, wn * WT, acc, fr, fc);
+        else if (YD && role == 1)
+          mma_f64<NY, 2>(A, LDA, 0, sm.y[buf], LDY, 0, acc, fr, fc);
+      } else if constexpr (MODE == CVGRAM_MODE_FP32) {
+        constexpr int LDA = Smem<MODE, BM>::LDA, LDY = Smem<MODE, BM>::LDY;
+        const float* A = sm.a[buf];
+        const float* B = DG ? sm.a[buf] : sm.b[buf];
+        if (role == 0)
+          mma_f32<NW, NW>(A, LDA, wm * WT, B, LDA, wn * WT, acc, fr, fc);
+        else if (YD && role == 1)
+          mma_f32<NY, 2>(A, LDA, 0, sm.y[buf], LDY, 0, acc, fr, fc);
+      } else {
+        const __bf16* Ah = sm.a[buf][0];
+        const __bf16* Al = sm.a[buf][1];
+        const __bf16* Bh = DG ? sm.a[buf][0] : sm.b[buf][0];
+        const __bf16* Bl = DG ? sm.a[buf][1] : sm.b[buf][1];
+        if (role == 0)
+          mma_bf16x3<NW, NW>(Ah, Al, wm * WT, Bh, Bl, wn * WT, acc, fr, fc);
+        else if (YD && role == 1)
+          mma_bf16x3<NY, 2>(Ah, Al, 0, sm.y[buf][0], sm.y[buf][1], 0, acc, fr, fc);
+      }
+    };
+    load(st[0], 0);
+    st[0].store(sm, 0, !DG, YD, t);
+    if constexpr (PF == 2) load(st[1], 1);
     __syncthreads();
-  }
+    if constexpr (PF == 1) {
+      for (int64_t s = 0; s < nst; ++s) {
+        const int buf = (int)(s & 1);
+        const bool more = s + 1 < nst;
+        if (more) load(st[0], s + 1);
+        compute(buf);
+        flush();
+        if (more) st[0].store(sm, buf ^ 1, !DG, YD, t);
+        __syncthreads();
+      }
+    } else {
+      // stage s is in LDS buffer s & 1 and stage s+1 in registers; stage s+2
+      // is loaded while stage s computes.  Unrolled by two so that the two
+      // register sets keep fixed roles.
+      auto step = [&](int64_t s, Stage<MODE, BM>& next, Stage<MODE, BM>& far) {
+        const int buf = (int)(s & 1);
+        load(far, s + 2);
+        compute(buf);
+        flush();
+        if (s + 1 < nst) next.store(sm, buf ^ 1, !DG, YD, t);
+        __syncthreads();
+      };
+      int64_t s = 0;
+      for (; s + 1 < nst; s += 2) {
+        step(s, st[1], st[0]);
+        step(s + 1, st[0], st[1]);
+      }
+      if (s < nst) step(s, st[1], st[0]);
+    }
+  };
+  if (!diag)
+    main_loop(std::false_type{}, std::false_type{});
+  else if (ydiag)
+    main_loop(std::true_type{}, std::true_type{});
+  else
+    main_loop(std::true_type{}, std::false_type{});
   if (role == 2) return;
 
   const int64_t W = K + M;
-  double* out = slabs + (int64_t)w.slab * K * W;
+  CVG_GLOBAL double* out = slabs + (int64_t)w.slab * K * W;
   auto value = [&](int i, int e) -> double {
     if constexpr (kF64)
       return acc[i][e];

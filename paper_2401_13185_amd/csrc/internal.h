@@ -37,6 +37,19 @@ struct Fail {
 #define CVG_LAUNCH_CHECK() CVG_HIP(hipGetLastError())
 
 // ---------------------------------------------------------------------------
+// global-memory pointers
+// ---------------------------------------------------------------------------
+// A pointer read from a descriptor is generic (flat) to the compiler, and a
+// flat load or store also counts against the LDS wait counter: every wait for
+// an LDS read would then wait for the global traffic in flight as well.
+// Kernels re-type such pointers as global before use.
+#define CVG_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ CVG_GLOBAL T* gmem(T* p) {
+  return (CVG_GLOBAL T*)p;
+}
+
+// ---------------------------------------------------------------------------
 // layout constants
 // ---------------------------------------------------------------------------
 // Packed row space: every fold's rows, in fold order, padded with zero rows

@@ -27,6 +27,8 @@ namespace cvg {
 namespace {
 
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+typedef double double2_t __attribute__((ext_vector_type(2)));
 
 // pivot: c_j = FP64 mean of the first min(N, 256) rows of column j of [X | Y]
 // (rounded to FP32 in the mixed modes).  items: (prob, block of 64 columns)
@@ -37,8 +39,8 @@ __global__ __launch_bounds__(256) void pivot_kernel(const ProbDesc* __restrict__
   __shared__ double part[4][64];
   const Item it = items[blockIdx.x];
   const ProbDesc& pd = pds[it.prob];
-  const T* X = (const T*)pd.X;
-  const T* Y = (const T*)pd.Y;
+  const CVG_GLOBAL T* X = gmem((const T*)pd.X);
+  const CVG_GLOBAL T* Y = gmem((const T*)pd.Y);
   const int64_t K = pd.K, M = pd.M;
   const int64_t rows = pd.N < 256 ? pd.N : 256;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -52,7 +54,7 @@ __global__ __launch_bounds__(256) void pivot_kernel(const ProbDesc* __restrict__
   if (w == 0 && j < K + M) {
     double c = ((part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane])) / (double)rows;
     if (round_f32) c = (double)(float)c;
-    pd.pivot[j] = c;
+    gmem(pd.pivot)[j] = c;
   }
 }
 
@@ -65,20 +67,20 @@ __device__ inline int64_t src_col(int64_t jp, int64_t K, int64_t Kp, int64_t M) 
 }
 
 template <typename T>
-__device__ inline void load4(const T* __restrict__ X, const T* __restrict__ Y, int64_t K,
+__device__ inline void load4(const CVG_GLOBAL T* __restrict__ X, const CVG_GLOBAL T* __restrict__ Y, int64_t K,
                              int64_t M, int64_t row, const int64_t (&js)[4], bool vec,
                              double (&x)[4]) {
   if (vec) {
     // four consecutive X columns, 16-byte aligned
     if constexpr (sizeof(T) == 4) {
-      const float4 v = *(const float4*)&X[row * K + js[0]];
+      const float4_t v = *(const CVG_GLOBAL float4_t*)&X[row * K + js[0]];
       x[0] = v.x;
       x[1] = v.y;
       x[2] = v.z;
       x[3] = v.w;
     } else {
-      const double2 a = *(const double2*)&X[row * K + js[0]];
-      const double2 b = *(const double2*)&X[row * K + js[0] + 2];
+      const double2_t a = *(const CVG_GLOBAL double2_t*)&X[row * K + js[0]];
+      const double2_t b = *(const CVG_GLOBAL double2_t*)&X[row * K + js[0] + 2];
       x[0] = a.x;
       x[1] = a.y;
       x[2] = b.x;
@@ -110,13 +112,13 @@ __global__ __launch_bounds__(256) void pack_kernel(const ProbDesc* __restrict__ 
   const int64_t Wp = pdr.Wp;
   const int64_t cb0 = (int64_t)blockIdx.y * kPackCols;
   if (cb0 >= Wp) return;  // uniform over the workgroup
-  const T* __restrict__ X = (const T*)pdr.X;
-  const T* __restrict__ Y = (const T*)pdr.Y;
-  const int32_t* __restrict__ perm = pdr.perm;
-  const double* __restrict__ pivot = pdr.pivot;
+  const CVG_GLOBAL T* __restrict__ X = gmem((const T*)pdr.X);
+  const CVG_GLOBAL T* __restrict__ Y = gmem((const T*)pdr.Y);
+  const CVG_GLOBAL int32_t* __restrict__ perm = gmem(pdr.perm);
+  const CVG_GLOBAL double* __restrict__ pivot = gmem((const double*)pdr.pivot);
   void* const packed = pdr.packed;
   void* const packed_lo = pdr.packed_lo;
-  double* const part = pdr.part;
+  CVG_GLOBAL double* const part = gmem(pdr.part);
   const int64_t n_chunks = pdr.n_chunks;
   const int x_vec = pdr.x_vec;
   const int64_t K = pdr.K, M = pdr.M, Kp = pdr.Kp, W = pdr.W;
@@ -198,47 +200,48 @@ __global__ __launch_bounds__(256) void pack_kernel(const ProbDesc* __restrict__ 
         *(bf16x8_t*)&tl[(4 * cg + u) * LDK + rg * 8] = l;
       }
       __syncthreads();
-      __bf16* hi = (__bf16*)packed;
-      __bf16* lo = (__bf16*)packed_lo;
+      CVG_GLOBAL __bf16* hi = gmem((__bf16*)packed);
+      CVG_GLOBAL __bf16* lo = gmem((__bf16*)packed_lo);
       const int64_t base = ((d0 / kPanelRows) * Wp + cb0) * kPanelRows;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
         const int qc = t + 256 * k;  // 16-byte chunk: column qc / 4, rows 8 (qc % 4) ..
         if (cb0 + (qc >> 2) < Wp) {
-          *(bf16x8_t*)&hi[base + qc * 8] = *(const bf16x8_t*)&th[(qc >> 2) * LDK + (qc & 3) * 8];
-          *(bf16x8_t*)&lo[base + qc * 8] = *(const bf16x8_t*)&tl[(qc >> 2) * LDK + (qc & 3) * 8];
+          *(CVG_GLOBAL bf16x8_t*)&hi[base + qc * 8] =
+              *(const bf16x8_t*)&th[(qc >> 2) * LDK + (qc & 3) * 8];
+          *(CVG_GLOBAL bf16x8_t*)&lo[base + qc * 8] =
+              *(const bf16x8_t*)&tl[(qc >> 2) * LDK + (qc & 3) * 8];
         }
       }
       __syncthreads();
     } else if constexpr (MODE == CVGRAM_MODE_FP32) {
       if (jp0 < Wp) {
-        float* out = (float*)packed;
+        CVG_GLOBAL float* out = gmem((float*)packed);
 #pragma unroll
         for (int g = 0; g < 8; ++g) {
-          float4 z;
-          float* zz = (float*)&z;
+          float4_t z;
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
             const bool ok = v[g] && js[u] >= 0;
-            zz[u] = !ok ? 0.f
-                    : (sizeof(T) == 4 ? (float)x[g][u] - pivf[u]
-                                      : (float)(x[g][u] - (double)pivf[u]));
+            z[u] = !ok ? 0.f
+                   : (sizeof(T) == 4 ? (float)x[g][u] - pivf[u]
+                                     : (float)(x[g][u] - (double)pivf[u]));
           }
-          *(float4*)&out[(d0 + rg * 8 + g) * Wp + jp0] = z;
+          *(CVG_GLOBAL float4_t*)&out[(d0 + rg * 8 + g) * Wp + jp0] = z;
         }
       }
     } else {
       if (jp0 < Wp) {
-        double* out = (double*)packed;
+        CVG_GLOBAL double* out = gmem((double*)packed);
 #pragma unroll
         for (int g = 0; g < 8; ++g) {
-          double2 a, b;
+          double2_t a, b;
           a.x = (v[g] && js[0] >= 0) ? x[g][0] - piv[0] : 0.0;
           a.y = (v[g] && js[1] >= 0) ? x[g][1] - piv[1] : 0.0;
           b.x = (v[g] && js[2] >= 0) ? x[g][2] - piv[2] : 0.0;
           b.y = (v[g] && js[3] >= 0) ? x[g][3] - piv[3] : 0.0;
-          *(double2*)&out[(d0 + rg * 8 + g) * Wp + jp0] = a;
-          *(double2*)&out[(d0 + rg * 8 + g) * Wp + jp0 + 2] = b;
+          *(CVG_GLOBAL double2_t*)&out[(d0 + rg * 8 + g) * Wp + jp0] = a;
+          *(CVG_GLOBAL double2_t*)&out[(d0 + rg * 8 + g) * Wp + jp0 + 2] = b;
         }
       }
     }

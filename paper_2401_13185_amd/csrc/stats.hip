@@ -32,11 +32,13 @@ __global__ __launch_bounds__(256) void stats_reduce_kernel(const ProbDesc* __res
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t j = (int64_t)blockIdx.y * 64 + lane;
   const int64_t ps = pd.n_chunks * W;
-  const double* part = pd.part;
+  const CVG_GLOBAL double* part = gmem((const double*)pd.part);
+  const CVG_GLOBAL int32_t* chunk_begin = gmem(pd.chunk_begin);
   double s = 0.0, q = 0.0, mn = INFINITY, mx = -INFINITY;
   if (j < W) {
+    const int32_t c1 = chunk_begin[p + 1];
 #pragma unroll 4
-    for (int32_t c = pd.chunk_begin[p] + w; c < pd.chunk_begin[p + 1]; c += 4) {
+    for (int32_t c = chunk_begin[p] + w; c < c1; c += 4) {
       s += part[0 * ps + (int64_t)c * W + j];
       q += part[1 * ps + (int64_t)c * W + j];
       mn = fmin(mn, part[2 * ps + (int64_t)c * W + j]);
@@ -56,10 +58,11 @@ __global__ __launch_bounds__(256) void stats_reduce_kernel(const ProbDesc* __res
       mx = fmax(mx, sh[3][k][lane]);
     }
     const int64_t fs = (int64_t)pd.P * W;
-    pd.fold[0 * fs + (int64_t)p * W + j] = s;
-    pd.fold[1 * fs + (int64_t)p * W + j] = q;
-    pd.fold[2 * fs + (int64_t)p * W + j] = mn;
-    pd.fold[3 * fs + (int64_t)p * W + j] = mx;
+    CVG_GLOBAL double* fold = gmem(pd.fold);
+    fold[0 * fs + (int64_t)p * W + j] = s;
+    fold[1 * fs + (int64_t)p * W + j] = q;
+    fold[2 * fs + (int64_t)p * W + j] = mn;
+    fold[3 * fs + (int64_t)p * W + j] = mx;
   }
 }
 
@@ -107,7 +110,7 @@ __global__ __launch_bounds__(256) void fold_totals_kernel(const ProbDesc* __rest
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t j = (int64_t)it.a * 64 + lane;
   const int64_t fs = (int64_t)P * W;
-  const double* fold = pd.fold;
+  const CVG_GLOBAL double* fold = gmem((const double*)pd.fold);
   double S = 0.0, Q = 0.0;
   Ext mn{INFINITY, INT32_MAX, INFINITY}, mx{-INFINITY, INT32_MAX, -INFINITY};
   if (j < W) {
@@ -132,7 +135,7 @@ __global__ __launch_bounds__(256) void fold_totals_kernel(const ProbDesc* __rest
       mn = ext_min(mn, sMn[k][lane]);
       mx = ext_max(mx, sMx[k][lane]);
     }
-    double* tot = pd.tot;
+    CVG_GLOBAL double* tot = gmem(pd.tot);
     tot[0 * W + j] = S;
     tot[1 * W + j] = Q;
     tot[2 * W + j] = mn.v1;
@@ -157,12 +160,14 @@ __global__ __launch_bounds__(256) void train_stats_kernel(const ProbDesc* __rest
   if (j >= W) return;
   const int64_t fs = (int64_t)pd.P * W;
   const int64_t e = (int64_t)p * W + j;
-  const int64_t nv = pd.offsets[p + 1] - pd.offsets[p];
+  const CVG_GLOBAL int64_t* offsets = gmem(pd.offsets);
+  const int64_t nv = offsets[p + 1] - offsets[p];
   const int64_t nt = pd.N - nv;
   const double NT = (double)nt;
-  const double* tot = pd.tot;
-  const double sT = tot[0 * W + j] - pd.fold[e];          // Lemma 14
-  const double qT = tot[1 * W + j] - pd.fold[fs + e];
+  const CVG_GLOBAL double* tot = gmem((const double*)pd.tot);
+  const CVG_GLOBAL double* fold = gmem((const double*)pd.fold);
+  const double sT = tot[0 * W + j] - fold[e];             // Lemma 14
+  const double qT = tot[1 * W + j] - fold[fs + e];
   const double mu = sT / NT;                              // Lemma 7 (shifted)
   const double tmn = (int32_t)tot[3 * W + j] == p ? tot[4 * W + j] : tot[2 * W + j];
   const double tmx = (int32_t)tot[6 * W + j] == p ? tot[7 * W + j] : tot[5 * W + j];
@@ -178,12 +183,12 @@ __global__ __launch_bounds__(256) void train_stats_kernel(const ProbDesc* __rest
     sd = sqrt(var > 0.0 ? var : 0.0);
     if (sd == 0.0) sd = 1.0;
   }
-  pd.tr_sum[e] = sT;
-  pd.tr_mean[e] = constant ? 0.0 : mu;
-  pd.tr_std[e] = sd;
-  pd.tr_mu[e] = constant ? tmn : pd.pivot[j] + mu;
-  pd.tr_const[e] = constant ? 1 : 0;
-  if (j == 0) pd.ntrain[p] = nt;
+  gmem(pd.tr_sum)[e] = sT;
+  gmem(pd.tr_mean)[e] = constant ? 0.0 : mu;
+  gmem(pd.tr_std)[e] = sd;
+  gmem(pd.tr_mu)[e] = constant ? tmn : gmem((const double*)pd.pivot)[j] + mu;
+  gmem(pd.tr_const)[e] = constant ? 1 : 0;
+  if (j == 0) gmem(pd.ntrain)[p] = nt;
 }
 
 __global__ void fold_stats_kernel(const double* __restrict__ tr_mu,
