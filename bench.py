@@ -52,6 +52,9 @@ def parse():
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched block (256 independent problems, graph replay)")
     ap.add_argument("--batch-steps", type=int, default=5)
+    ap.add_argument("--c5", action="store_true",
+                    help="add the large single-problem block (N=2e6, K=4096, M=64, P=64, fp32 "
+                         "input): bf16x3 vs the FP64 form, folds streamed in chunks")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB: the "
                          "reference dispatch that scales HBM byte counters in a profile")
@@ -76,6 +79,7 @@ def cpu_legs(X, Y, fold, P, gpu_xx, gpu_xy, budget_s):
         errs.append(np.linalg.norm(gpu_xx[0, c] - oxx[c]) / np.linalg.norm(oxx[c]))
     for c in range(8):
         errs.append(np.linalg.norm(gpu_xy[0, c] - oxy[c]) / np.linalg.norm(oxy[c]))
+    errs = [float(e) for e in errs]
     cpu = {"value": 12.0 / t_or, "unit": "sets/s", "cores": int(threads), "kind": "oracle",
            "sample": f"fold 0 of {P}, all 12 distinct classes, FP64 naive baseline",
            "seconds": round(t_or, 3)}
@@ -88,7 +92,7 @@ def cpu_legs(X, Y, fold, P, gpu_xx, gpu_xy, budget_s):
         fast = {"value": P * 12.0 / t_fast, "unit": "sets/s", "cores": int(threads),
                 "kind": "paper fast algorithm (Algorithm 7, all classes), FP64 NumPy",
                 "sample": f"all {P} folds", "seconds": round(t_fast, 3)}
-    return cpu, fast, float(max(errs))
+    return cpu, fast, errs
 
 
 def measure(cv, torch, Xd, Yd, fd, P, K, M, mode, steps, warmup):
@@ -133,6 +137,83 @@ def measure(cv, torch, Xd, Yd, fd, P, K, M, mode, steps, warmup):
     return ms, stage_ms, xx, xy
 
 
+def measure_single(cv, torch, Xd, Yd, fd, P, K, M, mode, steps, warmup):
+    """The paper's own target, one combination (center and scale X and Y):
+    create + cvgram_fold for every fold + destroy.  Returns ms per step."""
+    odt = torch.float64 if mode == "fp64" else torch.float32
+    xx = torch.empty(K, K, dtype=odt, device=Xd.device)
+    xy = torch.empty(K, M, dtype=odt, device=Xd.device)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        h = cv.cvgram_create(Xd, Yd, fd, 1, 1, 1, 1, ddof=1, mode=mode, stream=stream)
+        for p in range(P):
+            cv.cvgram_fold(h, p, xx, xy)
+        cv.cvgram_destroy(h)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps
+
+
+def padded_rows(fold, P):
+    """Rows of the packed panels: every fold padded to a multiple of 32."""
+    counts = np.bincount(np.asarray(fold), minlength=P)
+    return int(((counts + 31) // 32 * 32).sum())
+
+
+def stage_bandwidth(N, K, M, P, Np, in_bytes, mode, stage_ms):
+    """Algorithmic HBM bytes and GB/s of the statistics pass (A2: read X and Y
+    once, write the packed operand panels) and of the per-fold corrections
+    (A5: read G_p, write 4 K x K + 8 K x M outputs per fold)."""
+    e = {"fp64": 8, "fp32": 4, "bf16x3": 4}[mode]
+    W = K + M
+    tile = 64 if K <= 64 else 128
+    Kp = -(-K // tile) * tile
+    Wp = Kp + (32 if 0 < M <= 32 else -(-M // tile) * tile)
+    a2 = N * W * in_bytes + Np * Wp * e
+    ob = 8 if mode == "fp64" else 4
+    a5 = P * ((4 * K * K + 8 * K * M) * ob + (K * (K + 1) // 2 + K * M) * 8) + K * W * 8
+    return {"A2_stats_pack": {"bytes": a2, "GB_per_s": a2 / (stage_ms["stats"] * 1e-3) / 1e9},
+            "A5_corrections": {"bytes": a5, "GB_per_s": a5 / (stage_ms["correct"] * 1e-3) / 1e9}}
+
+
+def source_digest():
+    """SHA-256 over the sources that decide what the Gram launch reads and
+    writes (kernels and work planning)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("gram.hip", "api.hip", "internal.h"):
+        with open(os.path.join(ROOT, "paper_2401_13185_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def profiled_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by the same
+    counter's reading for a plain copy), or None when the summary is absent,
+    covers another kernel or workload, or was taken on other sources."""
+    path = os.path.join(ROOT, "profiles", "gram_hbm_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("source_sha256") != source_digest() or kv.get("kernel") != kernel \
+            or kv.get("workload") != workload:
+        return None
+    return float(kv["fetch_bytes_scaled"]) + float(kv["write_bytes_scaled"])
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -167,7 +248,14 @@ def main():
     sets = P * 12
     flops = f_alg(N, K, M)
     gram_tflops = flops / (stage_ms["gram"] * 1e-3) / 1e12
-    kname = {"fp64": "gram_f64_kernel", "fp32": "gram_f32_kernel", "bf16x3": "gram_bf16x3_kernel"}
+    tile = 64 if K <= 64 else 128
+    kname = {"fp64": f"gram_kernel<0, {tile}>", "fp32": f"gram_kernel<1, {tile}>",
+             "bf16x3": f"gram_bf16_kernel<{tile}>"}
+    single_ms = measure_single(cv, torch, Xd, Yd, fd, P, K, M, args.mode, max(3, args.steps // 2),
+                               1)
+    print("[bench] single-combination steps done", file=sys.stderr, flush=True)
+    traffic = profiled_traffic(kname[args.mode], shape.name)
+    Np = padded_rows(fold, P)
     out = {
         "metric": "per-fold train Gram sets/s (12 distinct centering/scaling classes per fold)",
         "value": sets / (ms * 1e-3),
@@ -187,22 +275,28 @@ def main():
         "stage_ms": stage_ms,
         "roofline": {"bound": "mfma", "kernel": kname[args.mode], "achieved": gram_tflops,
                      "peak": PEAK[args.mode], "unit": "TFLOP/s",
-                     "frac": gram_tflops / PEAK[args.mode], "traffic": None},
+                     "frac": gram_tflops / PEAK[args.mode], "traffic": traffic},
+        "single_combination": {"combo": "center+scale X and Y (1111)", "sets_per_step": P,
+                               "ms_per_step": single_ms, "sets_per_s": P / (single_ms * 1e-3)},
+        "hbm": stage_bandwidth(N, K, M, P, Np, X.itemsize, args.mode, stage_ms),
     }
     if not args.no_cpu:
         torch.cuda.synchronize()
         gxx = xx.double().cpu().numpy()
         gxy = xy.double().cpu().numpy()
-        cpu, fast, err = cpu_legs(X, Y, fold, P, gxx, gxy, args.cpu_seconds)
+        cpu, fast, errs = cpu_legs(X, Y, fold, P, gxx, gxy, args.cpu_seconds)
         out["cpu_baseline"] = cpu
         if fast:
             out["cpu_fast"] = fast
-        out["max_rel_err_vs_oracle_fold0"] = err
+        out["max_rel_err_vs_oracle_fold0"] = max(errs)
+        out["median_rel_err_vs_oracle_fold0"] = float(np.median(errs))
     del xx, xy
     if not args.no_mixed:
         out["mixed"] = mixed_block(cv, torch, G, dev, args)
     if not args.no_batch:
         out["batched"] = batched_block(cv, torch, G, dev, args)
+    if args.c5:
+        out["large"] = c5_block(cv, torch, G, dev, args)
     print(json.dumps(out))
 
 
@@ -301,6 +395,70 @@ def batched_block(cv, torch, G, dev, args):
     r["speedup_vs_fp64"] = res["modes"]["fp64"]["ms_per_step"] / r["ms_per_step"]
     for b in outs.values():
         cv.cvgram_batch_destroy(b)
+    return res
+
+
+def c5_block(cv, torch, G, dev, args):
+    """One large problem (spectra N=2e6, K=4096, M=64, P=64, fp32 input,
+    Dirichlet(2) folds): bf16x3 against the FP64 form on the same inputs.
+    Folds are written in chunks of 8 (every fold's 12 classes), so only the
+    chunk's outputs are resident; sets/s per mode, and bf16x3's worst and
+    median relative Frobenius error against FP64 over every fold and class."""
+    shape = G.WORKLOADS[5]
+    N, K, M, P = shape.n, shape.k, shape.m, shape.p
+    X, Y = G.spectra_xy_torch(N, K, M, seed=5_13185, device=dev)
+    fold = G.folds_dirichlet(N, P, G._rng(5, 0, 9))
+    fd = torch.from_numpy(fold).to(dev)
+    torch.cuda.synchronize()
+    print("[bench] large workload generated", file=sys.stderr, flush=True)
+    CH = 8
+    res = {"workload": shape.name + " (torch generator)", "classes_per_fold": 12,
+           "fold_chunk": CH, "modes": {}}
+    stream = torch.cuda.current_stream()
+    handles = {}
+    for mode in ("bf16x3", "fp64"):
+        odt = torch.float64 if mode == "fp64" else torch.float32
+        xx = torch.empty(CH, 4, K, K, dtype=odt, device=dev)
+        xy = torch.empty(CH, 8, K, M, dtype=odt, device=dev)
+        cv.cvgram_set_stage_timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = cv.cvgram_create(X, Y, fd, 1, 1, 1, 1, ddof=1, mode=mode, stream=stream)
+        for p0 in range(0, P, CH):
+            cv.cvgram_folds_all(h, p0, min(P, p0 + CH), xx, xy)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        st = cv.cvgram_stage_times(h)
+        cv.cvgram_set_stage_timing(False)
+        g = f_alg(N, K, M) / (st["gram"] * 1e-3) / 1e12
+        res["modes"][mode] = {"seconds": dt, "sets_per_s": P * 12 / dt, "stage_ms": st,
+                              "gram_tflops_alg": g, "gram_frac_of_peak": g / PEAK[mode]}
+        handles[mode] = h
+        del xx, xy
+        print(f"[bench] large-block mode {mode} done", file=sys.stderr, flush=True)
+    errs = []
+    bx = torch.empty(CH, 4, K, K, dtype=torch.float32, device=dev)
+    by = torch.empty(CH, 8, K, M, dtype=torch.float32, device=dev)
+    fx = torch.empty(CH, 4, K, K, dtype=torch.float64, device=dev)
+    fy = torch.empty(CH, 8, K, M, dtype=torch.float64, device=dev)
+    for p0 in range(0, P, CH):
+        p1 = min(P, p0 + CH)
+        cv.cvgram_folds_all(handles["bf16x3"], p0, p1, bx, by)
+        cv.cvgram_folds_all(handles["fp64"], p0, p1, fx, fy)
+        for a, b in ((bx[:p1 - p0], fx[:p1 - p0]), (by[:p1 - p0], fy[:p1 - p0])):
+            num = torch.linalg.matrix_norm(a.double() - b)
+            errs.extend((num / torch.linalg.matrix_norm(b)).flatten().tolist())
+    for h in handles.values():
+        cv.cvgram_destroy(h)
+    r = res["modes"]["bf16x3"]
+    r["max_rel_err_vs_fp64"] = max(errs)
+    r["median_rel_err_vs_fp64"] = float(np.median(errs))
+    r["stated_bound"] = MIXED_BOUND["bf16x3"]
+    r["within_bound"] = max(errs) <= MIXED_BOUND["bf16x3"]
+    r["speedup_vs_fp64"] = res["modes"]["fp64"]["seconds"] / r["seconds"]
+    del X, Y, fd, bx, by, fx, fy
+    torch.cuda.empty_cache()
+    cv.cvgram_trim_cache()
     return res
 
 

@@ -23,10 +23,15 @@
 // tile every 256 rows and clear it, so FP32 rounding does not grow with the
 // fold size.
 //
-// Pipelining: LDS double buffer; the next stage's panel block is loaded into
-// registers while the current stage runs on the matrix cores; one barrier
-// per stage.  Work items are mapped XCD-aware (each of the 8 XCDs takes a
-// contiguous range of items, so tiles that read the same rows share an L2).
+// Pipelining.  FP64 / FP32: LDS double buffer; the next stage's panel block
+// is loaded into registers while the current stage runs on the matrix cores;
+// one barrier per stage.  BF16X3: the panels are already k-contiguous, so
+// stages go straight from global memory into a ring of four LDS buffers with
+// direct-to-LDS loads (no register staging, no LDS store instructions), three
+// stages ahead of the matrix cores; 16-byte chunks are XOR-swizzled per
+// column so the fragment reads are free of bank conflicts.  Work items are
+// mapped XCD-aware (each of the 8 XCDs takes a contiguous range of items, so
+// tiles that read the same rows share an L2).
 #include "internal.h"
 
 #include <type_traits>
@@ -63,8 +68,7 @@ template <>
 struct Mode<CVGRAM_MODE_BF16X3> {
   typedef __bf16 E;
   typedef float4_t Acc;
-  static constexpr int BK = 32;
-  static constexpr int LDK = BK + 8;  // 80-byte columns: conflict-free 16-byte reads
+  static constexpr int BK = 32;       // one packed panel per stage
 };
 
 // row of element e of lane l's accumulator inside a 16 x 16 MFMA block
@@ -81,15 +85,6 @@ struct Smem {
   typename Mode<MODE>::E b[2][16 * LDA];
   typename Mode<MODE>::E y[2][16 * LDY];
 };
-template <int BM>
-struct Smem<CVGRAM_MODE_BF16X3, BM> {
-  static constexpr int LDK = Mode<CVGRAM_MODE_BF16X3>::LDK;
-  // [buffer][hi/lo][column * LDK + k]
-  __bf16 a[2][2][BM * LDK];
-  __bf16 b[2][2][BM * LDK];
-  __bf16 y[2][2][kYW * LDK];
-};
-
 // ---------------------------------------------------------------------------
 // global -> register staging of one stage (BK packed rows starting at row r)
 // ---------------------------------------------------------------------------
@@ -161,60 +156,6 @@ struct Stage<CVGRAM_MODE_FP32, BM> {
   }
 };
 
-// BF16X3: a 32-row panel block of BM columns is BM * 4 16-byte chunks per
-// hi/lo array (BM / 64 per thread); the Y block (32 columns) is one chunk of
-// hi (threads 0..127) or lo (threads 128..255).
-template <int BM>
-struct Stage<CVGRAM_MODE_BF16X3, BM> {
-  static constexpr int V = BM / 64;
-  bf16x8_t ah[V], al[V], bh[V], bl[V], y;
-  __device__ void load(const CVG_GLOBAL __bf16* Zh, const CVG_GLOBAL __bf16* Zl, int64_t Wp,
-                       int64_t r, int64_t ca, int64_t cb, int64_t cy, bool ld_b, bool ld_y,
-                       int t) {
-    typedef const CVG_GLOBAL bf16x8_t* V8;
-    const int64_t panel = (r / 32) * Wp;
-    const CVG_GLOBAL __bf16* ha = Zh + (panel + ca) * 32;
-    const CVG_GLOBAL __bf16* la = Zl + (panel + ca) * 32;
-#pragma unroll
-    for (int u = 0; u < V; ++u) {
-      ah[u] = *(V8)(ha + (t + 256 * u) * 8);
-      al[u] = *(V8)(la + (t + 256 * u) * 8);
-    }
-    if (ld_b) {
-      const CVG_GLOBAL __bf16* hb = Zh + (panel + cb) * 32;
-      const CVG_GLOBAL __bf16* lb = Zl + (panel + cb) * 32;
-#pragma unroll
-      for (int u = 0; u < V; ++u) {
-        bh[u] = *(V8)(hb + (t + 256 * u) * 8);
-        bl[u] = *(V8)(lb + (t + 256 * u) * 8);
-      }
-    }
-    if (ld_y) {
-      const CVG_GLOBAL __bf16* src = (t < 128 ? Zh : Zl) + (panel + cy) * 32;
-      y = *(V8)(src + (t & 127) * 8);
-    }
-  }
-  __device__ void store(Smem<CVGRAM_MODE_BF16X3, BM>& s, int buf, bool st_b, bool st_y,
-                        int t) const {
-    constexpr int LDK = Mode<CVGRAM_MODE_BF16X3>::LDK;
-#pragma unroll
-    for (int u = 0; u < V; ++u) {
-      const int q = t + 256 * u;           // chunk: column q/4, k-group q%4
-      const int off = (q >> 2) * LDK + (q & 3) * 8;
-      *(bf16x8_t*)&s.a[buf][0][off] = ah[u];
-      *(bf16x8_t*)&s.a[buf][1][off] = al[u];
-      if (st_b) {
-        *(bf16x8_t*)&s.b[buf][0][off] = bh[u];
-        *(bf16x8_t*)&s.b[buf][1][off] = bl[u];
-      }
-    }
-    if (st_y) {
-      const int q = t & 127;
-      *(bf16x8_t*)&s.y[buf][t >> 7][(q >> 2) * LDK + (q & 3) * 8] = y;
-    }
-  }
-};
-
 // ---------------------------------------------------------------------------
 // one stage of MFMA work for a wave: NA x NB blocks of 16 x 16, A columns
 // from `acol0` of the A view, B columns from `bcol0` of the B view.
@@ -257,45 +198,96 @@ __device__ inline void mma_f32(const float* A, int lda, int acol0, const float* 
   }
 }
 
+// BF16X3 stage buffers in LDS: per array, column c of the 32-row panel is
+// 64 bytes (four 16-byte chunks of 8 rows); chunk k of column c sits at
+// position k ^ swz(c).  Sixteen lanes reading one chunk of sixteen
+// consecutive columns then hit sixteen different 16-byte bank groups (with
+// 32 or with 64 banks of 4 bytes).
+__device__ __forceinline__ int swz(int c) { return ((c >> 1) ^ (c >> 2)) & 3; }
+
+// one stage of MFMA work on the swizzled buffers: NA x NB blocks of 16 x 16,
+// A columns from `acol0`, B columns from `bcol0` (multiples of 16); `lfo` is
+// the lane's byte offset fc * 64 + ((fr ^ swz(fc)) << 4).  All fragments are
+// read first, then the three products run in passes over all blocks, so
+// consecutive MFMAs update different accumulators.
 template <int NA, int NB, int NACC>
-__device__ inline void mma_bf16x3(const __bf16* Ah, const __bf16* Al, int acol0, const __bf16* Bh,
-                                  const __bf16* Bl, int bcol0, float4_t (&acc)[NACC], int fr,
-                                  int fc) {
-  constexpr int LDK = Mode<CVGRAM_MODE_BF16X3>::LDK;
-  // every fragment of the stage first, then the three products in passes
-  // over all blocks, so consecutive MFMAs update different accumulators
+__device__ inline void mma_bf16x3(const char* Ah, const char* Al, int acol0, const char* Bh,
+                                  const char* Bl, int bcol0, int lfo, float4_t (&acc)[NACC]) {
   bf16x8_t ah[NA], al[NA], bh[NB], bl[NB];
 #pragma unroll
   for (int a = 0; a < NA; ++a) {
-    const int off = (acol0 + a * 16 + fc) * LDK + fr * 8;
-    ah[a] = *(const bf16x8_t*)&Ah[off];
-    al[a] = *(const bf16x8_t*)&Al[off];
+    const int off = (acol0 + a * 16) * 64 + lfo;
+    ah[a] = *(const bf16x8_t*)(Ah + off);
+    al[a] = *(const bf16x8_t*)(Al + off);
   }
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
-    const int off = (bcol0 + b * 16 + fc) * LDK + fr * 8;
-    bh[b] = *(const bf16x8_t*)&Bh[off];
-    bl[b] = *(const bf16x8_t*)&Bl[off];
+    const int off = (bcol0 + b * 16) * 64 + lfo;
+    bh[b] = *(const bf16x8_t*)(Bh + off);
+    bl[b] = *(const bf16x8_t*)(Bl + off);
   }
 #pragma unroll
   for (int a = 0; a < NA; ++a)
 #pragma unroll
     for (int b = 0; b < NB; ++b)
-      acc[a * NB + b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bh[b], acc[a * NB + b], 0, 0, 0);
+      acc[a * NB + b] =
+          __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bh[b], acc[a * NB + b], 0, 0, 0);
 #pragma unroll
   for (int a = 0; a < NA; ++a)
 #pragma unroll
     for (int b = 0; b < NB; ++b)
-      acc[a * NB + b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bl[b], acc[a * NB + b], 0, 0, 0);
+      acc[a * NB + b] =
+          __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bl[b], acc[a * NB + b], 0, 0, 0);
 #pragma unroll
   for (int a = 0; a < NA; ++a)
 #pragma unroll
     for (int b = 0; b < NB; ++b)
-      acc[a * NB + b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bh[b], acc[a * NB + b], 0, 0, 0);
+      acc[a * NB + b] =
+          __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bh[b], acc[a * NB + b], 0, 0, 0);
 }
 
 // ---------------------------------------------------------------------------
-// the kernel
+// epilogue shared by both kernels: the wave's FP64 results into the item's
+// slab (rows of X, columns of X or Y; entries outside K x K / K x M skipped)
+// ---------------------------------------------------------------------------
+template <int MODE, int BM, int NACC, typename V>
+__device__ inline void store_tile(CVG_GLOBAL double* out, int role, bool xy_tile, int64_t ca,
+                                  int64_t cbl, int wm, int wn, int fr, int fc, int64_t K,
+                                  int64_t M, const V& value) {
+  constexpr int WT = BM / 2, NW = WT / 16, NY = BM / 16;
+  const int64_t W = K + M;
+  if (role == 0) {
+#pragma unroll
+    for (int a = 0; a < NW; ++a)
+#pragma unroll
+      for (int b = 0; b < NW; ++b)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int64_t row = ca + wm * WT + a * 16 + acc_row<MODE>(e, fr);
+          const int64_t cl = cbl + wn * WT + b * 16 + fc;
+          if (row >= K) continue;
+          if (!xy_tile) {
+            if (cl < K) out[row * W + cl] = value(a * NW + b, e);
+          } else if (cl < M) {
+            out[row * W + K + cl] = value(a * NW + b, e);
+          }
+        }
+  } else if (role == 1) {
+#pragma unroll
+    for (int a = 0; a < NY; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int64_t row = ca + a * 16 + acc_row<MODE>(e, fr);
+          const int64_t cl = b * 16 + fc;
+          if (row < K && cl < M) out[row * W + K + cl] = value(a * 2 + b, e);
+        }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 / FP32 kernel: register-staged LDS double buffer
 // ---------------------------------------------------------------------------
 template <int MODE, int BM>
 __global__ __launch_bounds__(kThreads) void gram_kernel(const ProbDesc* __restrict__ pds,
@@ -379,10 +371,7 @@ __global__ __launch_bounds__(kThreads) void gram_kernel(const ProbDesc* __restri
     Stage<MODE, BM> st[PF];
     auto load = [&](Stage<MODE, BM>& sg, int64_t s) {
       const int64_t r = w.r0 + (s < nst ? s : nst - 1) * BK;
-      if constexpr (MODE == CVGRAM_MODE_BF16X3)
-        sg.load(packed, packed_lo, Wp, r, ca, cb, Kp, !DG, YD, t);
-      else
-        sg.load(packed, Wp, r, ca, cb, Kp, !DG, YD, t);
+      sg.load(packed, Wp, r, ca, cb, Kp, !DG, YD, t);
     };
     auto compute = [&](int buf) {
       if constexpr (MODE == CVGRAM_MODE_FP64) {
@@ -393,7 +382,7 @@ __global__ __launch_bounds__(kThreads) void gram_kernel(const ProbDesc* __restri
           mma_f64<NW, NW>(A, LDA, wm * WT, B, LDA, wn * WT, acc, fr, fc);
         else if (YD && role == 1)
           mma_f64<NY, 2>(A, LDA, 0, sm.y[buf], LDY, 0, acc, fr, fc);
-      } else if constexpr (MODE == CVGRAM_MODE_FP32) {
+      } else {
         constexpr int LDA = Smem<MODE, BM>::LDA, LDY = Smem<MODE, BM>::LDY;
         const float* A = sm.a[buf];
         const float* B = DG ? sm.a[buf] : sm.b[buf];
@@ -401,15 +390,6 @@ __global__ __launch_bounds__(kThreads) void gram_kernel(const ProbDesc* __restri
           mma_f32<NW, NW>(A, LDA, wm * WT, B, LDA, wn * WT, acc, fr, fc);
         else if (YD && role == 1)
           mma_f32<NY, 2>(A, LDA, 0, sm.y[buf], LDY, 0, acc, fr, fc);
-      } else {
-        const __bf16* Ah = sm.a[buf][0];
-        const __bf16* Al = sm.a[buf][1];
-        const __bf16* Bh = DG ? sm.a[buf][0] : sm.b[buf][0];
-        const __bf16* Bl = DG ? sm.a[buf][1] : sm.b[buf][1];
-        if (role == 0)
-          mma_bf16x3<NW, NW>(Ah, Al, wm * WT, Bh, Bl, wn * WT, acc, fr, fc);
-        else if (YD && role == 1)
-          mma_bf16x3<NY, 2>(Ah, Al, 0, sm.y[buf][0], sm.y[buf][1], 0, acc, fr, fc);
       }
     };
     load(st[0], 0);
@@ -453,53 +433,200 @@ __global__ __launch_bounds__(kThreads) void gram_kernel(const ProbDesc* __restri
   else
     main_loop(std::true_type{}, std::false_type{});
   if (role == 2) return;
-
-  const int64_t W = K + M;
-  CVG_GLOBAL double* out = slabs + (int64_t)w.slab * K * W;
+  CVG_GLOBAL double* out = slabs + (int64_t)w.slab * K * (K + M);
   auto value = [&](int i, int e) -> double {
     if constexpr (kF64)
       return acc[i][e];
     else
       return a64[i][e] + (double)acc[i][e];
   };
-  if (role == 0) {
+  store_tile<MODE, BM, NACC>(out, role, xy_tile, ca, xy_tile ? (int64_t)(w.tj - nt) * BM : cb, wm,
+                             wn, fr, fc, K, M, value);
+}
+
+// ---------------------------------------------------------------------------
+// BF16X3 kernel: direct-to-LDS loads into a ring of kStages buffers
+// ---------------------------------------------------------------------------
+constexpr int kStages = 4;
+
+template <int BM>
+struct DmaBuf {
+  // [column][32 rows] bf16, swizzled 16-byte chunks (see swz)
+  __bf16 ah[BM * 32], al[BM * 32], bh[BM * 32], bl[BM * 32], yh[kYW * 32], yl[kYW * 32];
+};
+
+// s_waitcnt with vmcnt = n and lgkmcnt = 0 (expcnt not waited on)
+template <int n>
+__device__ __forceinline__ void wait_vmcnt_lgkm0() {
+  static_assert(n >= 0 && n < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((n & 15) | ((n >> 4) << 14) | (7 << 4));
+}
+
+// workgroup barrier that orders memory operations in the compiler but adds
+// no wait of its own (the waits are explicit)
+__device__ __forceinline__ void barrier_only() { asm volatile("s_barrier" ::: "memory"); }
+
+// one 16-byte direct-to-LDS load per lane: lane l writes dst + 16 l
+__device__ __forceinline__ void dma16(const CVG_GLOBAL char* src, __bf16* dst) {
+  __builtin_amdgcn_global_load_lds((const CVG_GLOBAL void*)src,
+                                   (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
+}
+
+template <int BM>
+__global__ __launch_bounds__(kThreads) void gram_bf16_kernel(const ProbDesc* __restrict__ pds,
+                                                             const GramWork* __restrict__ work,
+                                                             int64_t n_work) {
+  constexpr int MODE = CVGRAM_MODE_BF16X3;
+  constexpr int WT = BM / 2, NW = WT / 16, NY = BM / 16;
+  constexpr int NACC = NW * NW > 2 * NY ? NW * NW : 2 * NY;
+  constexpr int IA = BM / 64;  // 1 KB direct loads per wave per array per stage
+  __shared__ __attribute__((aligned(1024))) DmaBuf<BM> sb0, sb1, sb2, sb3;
+
+  const int64_t per = (int64_t)gridDim.x / 8;
+  const int64_t item = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (item >= n_work) return;
+  const GramWork w = work[item];
+  const ProbDesc& pdr = pds[w.prob];
+  const int64_t Wp = pdr.Wp, Kp = pdr.Kp, K = pdr.K, M = pdr.M;
+  const int32_t nt = pdr.nt;
+  const CVG_GLOBAL char* const Zh = gmem((const char*)pdr.packed);
+  const CVG_GLOBAL char* const Zl = gmem((const char*)pdr.packed_lo);
+  CVG_GLOBAL double* const slabs = gmem(pdr.slabs);
+  const bool xy_diag = pdr.xy_diag != 0;
+  const int t = threadIdx.x, lane = t & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int wm = wave >> 1, wn = wave & 1;
+  const int fr = lane >> 4, fc = lane & 15;
+
+  const bool xy_tile = w.tj >= nt;
+  const bool diag = !xy_tile && w.ti == w.tj;
+  const int64_t ca = (int64_t)w.ti * BM;
+  const int64_t cb = xy_tile ? Kp + (int64_t)(w.tj - nt) * BM : (int64_t)w.tj * BM;
+  const bool ydiag = diag && xy_diag;
+  const int role = (diag && wm == 1 && wn == 0) ? (ydiag ? 1 : 2) : 0;
+
+  // byte offsets: source chunk of this lane inside a 1 KB block of 16
+  // columns (a permutation of the block's chunks: the loads stay coalesced),
+  // and this lane's fragment chunk inside a buffer
+  const int lsrc = (lane >> 2) * 64 + (((lane & 3) ^ swz(lane >> 2)) << 4);
+  const int lfo = fc * 64 + ((fr ^ swz(fc)) << 4);
+
+  float4_t acc[NACC];
+  double a64[NACC][4];
 #pragma unroll
-    for (int a = 0; a < NW; ++a)
+  for (int i = 0; i < NACC; ++i) {
+    acc[i] = float4_t{0, 0, 0, 0};
 #pragma unroll
-      for (int b = 0; b < NW; ++b)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int64_t row = ca + wm * WT + a * 16 + acc_row<MODE>(e, fr);
-          const int64_t cl = (xy_tile ? (int64_t)(w.tj - nt) * BM : cb) + wn * WT + b * 16 + fc;
-          if (row >= K) continue;
-          if (!xy_tile) {
-            if (cl < K) out[row * W + cl] = value(a * NW + b, e);
-          } else if (cl < M) {
-            out[row * W + K + cl] = value(a * NW + b, e);
-          }
-        }
-  } else {
-#pragma unroll
-    for (int a = 0; a < NY; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int64_t row = ca + a * 16 + acc_row<MODE>(e, fr);
-          const int64_t cl = b * 16 + fc;
-          if (row < K && cl < M) out[row * W + K + cl] = value(a * 2 + b, e);
-        }
+    for (int e = 0; e < 4; ++e) a64[i][e] = 0.0;
   }
+  const int64_t nst = (w.r1 - w.r0) / 32;
+  const int64_t p0 = w.r0 / 32;  // first panel
+  int since = 0;
+
+  auto main_loop = [&](auto diag_c, auto ydiag_c) {
+    constexpr bool DG = decltype(diag_c)::value;   // B is A
+    constexpr bool YD = decltype(ydiag_c)::value;  // K x M block in this tile
+    // direct loads per wave per stage (all waves issue the same number)
+    constexpr int L = IA * (DG ? 2 : 4) + (YD ? 1 : 0);
+    // stage s (clamped to the last one) into buffer b
+    auto issue = [&](DmaBuf<BM>& b, int64_t s) {
+      const int64_t panel = (p0 + (s < nst ? s : nst - 1)) * Wp;
+      const CVG_GLOBAL char* ah = Zh + (panel + ca) * 64 + lsrc;
+      const CVG_GLOBAL char* al = Zl + (panel + ca) * 64 + lsrc;
+#pragma unroll
+      for (int i = 0; i < IA; ++i) {
+        const int blk = wave * IA + i;
+        dma16(ah + blk * 1024, b.ah + blk * 512);
+        dma16(al + blk * 1024, b.al + blk * 512);
+      }
+      if constexpr (!DG) {
+        const CVG_GLOBAL char* bh = Zh + (panel + cb) * 64 + lsrc;
+        const CVG_GLOBAL char* bl = Zl + (panel + cb) * 64 + lsrc;
+#pragma unroll
+        for (int i = 0; i < IA; ++i) {
+          const int blk = wave * IA + i;
+          dma16(bh + blk * 1024, b.bh + blk * 512);
+          dma16(bl + blk * 1024, b.bl + blk * 512);
+        }
+      }
+      if constexpr (YD) {
+        // waves 0, 1: hi columns 0-15, 16-31; waves 2, 3: lo
+        const CVG_GLOBAL char* src = (wave < 2 ? Zh : Zl) + (panel + Kp) * 64 + lsrc;
+        dma16(src + (wave & 1) * 1024, (wave < 2 ? b.yh : b.yl) + (wave & 1) * 512);
+      }
+    };
+    auto compute = [&](const DmaBuf<BM>& b) {
+      const char* Ah = (const char*)b.ah;
+      const char* Al = (const char*)b.al;
+      const char* Bh = (const char*)(DG ? b.ah : b.bh);
+      const char* Bl = (const char*)(DG ? b.al : b.bl);
+      if (role == 0)
+        mma_bf16x3<NW, NW>(Ah, Al, wm * WT, Bh, Bl, wn * WT, lfo, acc);
+      else if (YD && role == 1)
+        mma_bf16x3<NY, 2>(Ah, Al, 0, (const char*)b.yh, (const char*)b.yl, 0, lfo, acc);
+      since += 32;
+      if (since >= kFlushRows) {
+        since = 0;
+#pragma unroll
+        for (int i = 0; i < NACC; ++i) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) a64[i][e] += (double)acc[i][e];
+          acc[i] = float4_t{0, 0, 0, 0};
+        }
+      }
+    };
+    // step s: stage s is complete in every wave after the wait and the
+    // barrier, which also ends every wave's reads of the previous buffer;
+    // that buffer then receives stage s + 3.  Every step issues its loads,
+    // also the steps past the end of a partial last round (they re-load the
+    // last stage and skip the compute): the compiler's wait bookkeeping for
+    // direct-to-LDS loads then stays exact across the round, and no read of
+    // one buffer waits for loads into the others.
+    auto step = [&](int64_t s, const DmaBuf<BM>& cur, DmaBuf<BM>& nxt) {
+      wait_vmcnt_lgkm0<2 * L>();
+      barrier_only();
+      issue(nxt, s + 3);
+      if (s < nst) compute(cur);
+    };
+    issue(sb0, 0);
+    issue(sb1, 1);
+    issue(sb2, 2);
+    for (int64_t s = 0; s < nst; s += kStages) {
+      step(s, sb0, sb3);
+      step(s + 1, sb1, sb0);
+      step(s + 2, sb2, sb1);
+      step(s + 3, sb3, sb2);
+    }
+    wait_vmcnt_lgkm0<0>();  // the loads past the end
+  };
+  if (!diag)
+    main_loop(std::false_type{}, std::false_type{});
+  else if (ydiag)
+    main_loop(std::true_type{}, std::true_type{});
+  else
+    main_loop(std::true_type{}, std::false_type{});
+  if (role == 2) return;
+  CVG_GLOBAL double* out = slabs + (int64_t)w.slab * K * (K + M);
+  auto value = [&](int i, int e) -> double { return a64[i][e] + (double)acc[i][e]; };
+  store_tile<MODE, BM, NACC>(out, role, xy_tile, ca, xy_tile ? (int64_t)(w.tj - nt) * BM : cb, wm,
+                             wn, fr, fc, K, M, value);
 }
 
 template <int MODE>
 void launch_mode(int tile, const ProbDesc* pd, const GramWork* work, int64_t n_work,
                  hipStream_t s) {
   const unsigned grid = (unsigned)(8 * ((n_work + 7) / 8));
-  if (tile == 64)
-    gram_kernel<MODE, 64><<<grid, kThreads, 0, s>>>(pd, work, n_work);
-  else
-    gram_kernel<MODE, 128><<<grid, kThreads, 0, s>>>(pd, work, n_work);
+  if constexpr (MODE == CVGRAM_MODE_BF16X3) {
+    if (tile == 64)
+      gram_bf16_kernel<64><<<grid, kThreads, 0, s>>>(pd, work, n_work);
+    else
+      gram_bf16_kernel<128><<<grid, kThreads, 0, s>>>(pd, work, n_work);
+  } else {
+    if (tile == 64)
+      gram_kernel<MODE, 64><<<grid, kThreads, 0, s>>>(pd, work, n_work);
+    else
+      gram_kernel<MODE, 128><<<grid, kThreads, 0, s>>>(pd, work, n_work);
+  }
   CVG_LAUNCH_CHECK();
 }
 
