@@ -55,6 +55,9 @@ def parse():
     ap.add_argument("--c5", action="store_true",
                     help="add the large single-problem block (N=2e6, K=4096, M=64, P=64, fp32 "
                          "input): bf16x3 vs the FP64 form, folds streamed in chunks")
+    ap.add_argument("--psweep", action="store_true",
+                    help="add the fold-count sweep on the spectra shape (N=1e5, K=512, M=8; "
+                         "P = 3 .. 100000, near-equal folds, FP64): Gram time flat in P")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB: the "
                          "reference dispatch that scales HBM byte counters in a profile")
@@ -297,6 +300,8 @@ def main():
         out["batched"] = batched_block(cv, torch, G, dev, args)
     if args.c5:
         out["large"] = c5_block(cv, torch, G, dev, args)
+    if args.psweep:
+        out["p_sweep"] = psweep_block(cv, torch, G, dev, args)
     print(json.dumps(out))
 
 
@@ -398,6 +403,53 @@ def batched_block(cv, torch, G, dev, args):
     return res
 
 
+def psweep_block(cv, torch, G, dev, args):
+    """Fold-count sweep on the spectra shape (N=1e5, K=512, M=8, FP64 input,
+    near-equal folds, FP64 mode): create + every fold's 12 classes, written
+    in chunks of at most 64 folds.  The Gram (A3) time should not depend on
+    P; the corrections grow with the output size (P x 12 products)."""
+    base = G.WORKLOADS[2]
+    N, K, M = base.n, base.k, base.m
+    X, Y, _ = G.make(base, 2)
+    Xd, Yd = torch.from_numpy(X).to(dev), torch.from_numpy(Y).to(dev)
+    CH = 64
+    xx = torch.empty(CH, 4, K, K, dtype=torch.float64, device=dev)
+    xy = torch.empty(CH, 8, K, M, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+    rows = []
+    for P in (3, 10, 100, 1000, 10000, 100000):
+        fold = G.folds_near_equal(N, P, G._rng(2, 0, 11, P))
+        fd = torch.from_numpy(fold).to(dev)
+        for it in range(2):  # the first pass warms the workspace cache
+            cv.cvgram_set_stage_timing(True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            h = cv.cvgram_create(Xd, Yd, fd, 1, 1, 1, 1, ddof=1, mode="fp64", stream=stream)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for p0 in range(0, P, CH):
+                p1 = min(P, p0 + CH)
+                cv.cvgram_folds_all(h, p0, p1, xx[:p1 - p0], xy[:p1 - p0])
+            e1.record(stream)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            st = cv.cvgram_stage_times(h)
+            cv.cvgram_set_stage_timing(False)
+            cv.cvgram_destroy(h)
+        out_bytes = P * (4 * K * K + 8 * K * M) * 8
+        rows.append({"P": P, "path": "fused" if P >= 64 and N // P <= 256 else "grouped",
+                     "seconds": dt, "sets_per_s": P * 12 / dt, "gram_ms": st["gram"],
+                     "stage_ms": st, "corrections_ms": e0.elapsed_time(e1),
+                     "output_GB_per_s": out_bytes / (e0.elapsed_time(e1) * 1e-3) / 1e9})
+        print(f"[bench] p-sweep P={P} done", file=sys.stderr, flush=True)
+    del xx, xy, Xd, Yd
+    torch.cuda.empty_cache()
+    cv.cvgram_trim_cache()
+    return {"workload": base.name.replace("P=10", "P swept") + ", near-equal folds",
+            "fold_chunk": CH, "rows": rows}
+
+
 def c5_block(cv, torch, G, dev, args):
     """One large problem (spectra N=2e6, K=4096, M=64, P=64, fp32 input,
     Dirichlet(2) folds): bf16x3 against the FP64 form on the same inputs.
@@ -425,7 +477,8 @@ def c5_block(cv, torch, G, dev, args):
         t0 = time.perf_counter()
         h = cv.cvgram_create(X, Y, fd, 1, 1, 1, 1, ddof=1, mode=mode, stream=stream)
         for p0 in range(0, P, CH):
-            cv.cvgram_folds_all(h, p0, min(P, p0 + CH), xx, xy)
+            p1 = min(P, p0 + CH)
+            cv.cvgram_folds_all(h, p0, p1, xx[:p1 - p0], xy[:p1 - p0])
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         st = cv.cvgram_stage_times(h)
@@ -443,8 +496,8 @@ def c5_block(cv, torch, G, dev, args):
     fy = torch.empty(CH, 8, K, M, dtype=torch.float64, device=dev)
     for p0 in range(0, P, CH):
         p1 = min(P, p0 + CH)
-        cv.cvgram_folds_all(handles["bf16x3"], p0, p1, bx, by)
-        cv.cvgram_folds_all(handles["fp64"], p0, p1, fx, fy)
+        cv.cvgram_folds_all(handles["bf16x3"], p0, p1, bx[:p1 - p0], by[:p1 - p0])
+        cv.cvgram_folds_all(handles["fp64"], p0, p1, fx[:p1 - p0], fy[:p1 - p0])
         for a, b in ((bx[:p1 - p0], fx[:p1 - p0]), (by[:p1 - p0], fy[:p1 - p0])):
             num = torch.linalg.matrix_norm(a.double() - b)
             errs.extend((num / torch.linalg.matrix_norm(b)).flatten().tolist())

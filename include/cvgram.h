@@ -104,6 +104,13 @@ typedef enum {
  * MFMA launch.  It waits on `stream` twice, for a few bytes of validation
  * results; everything after that is only enqueued.
  *
+ * Fold path: with many small folds (P >= 64 and no fold above 256 rows,
+ * e.g. leave-one-out) the rows are packed without per-fold padding, only the
+ * full Gram is contracted, and each fold's validation Gram is formed from
+ * its rows inside the per-fold corrections (it never reaches memory).  The
+ * environment variable CVGRAM_FOLD_PATH=grouped or =fused, read at each
+ * create, forces either path; results agree to rounding.
+ *
  * Ownership: X, Y and fold_id are borrowed; they must stay valid and
  * unchanged until the work this call enqueued has completed.  The handle
  * owns all its device workspace and is freed by cvgram_destroy().

@@ -256,12 +256,14 @@ struct ProbPlan {
   bool scalable = false;
   std::vector<int64_t> offsets;  // [P+1]
   Config cfg;
+  bool fused = false;         // fold path (see ProbDesc::fused)
   int64_t Kp = 0, Mp = 0, Wp = 0, Np = 0;
   bool xy_diag = false;
   int32_t nt = 0;
   std::vector<int64_t> poff;  // [P+1] packed row offsets
   std::vector<int32_t> chunk_begin, slab_begin, ctiles;
   int64_t n_chunks = 0, n_slabs = 0;
+  int32_t n_franges = 0;
   int32_t n_ctiles_xx = 0, n_ctiles_xy = 0;
   int32_t* d_perm = nullptr;
 };
@@ -288,9 +290,15 @@ struct Batch {
   int32_t max_pack_cb = 0;
   Item* d_fold_items = nullptr;
   int64_t n_fold_items = 0;
+  Item* d_sr_items = nullptr;     // folds of grouped-path problems
+  int64_t n_sr_items = 0;
+  Item* d_fs_items = nullptr;     // folds of fused-path problems
+  int64_t n_fs_items = 0;
   int32_t max_cb64 = 0, max_cb256 = 0;
   Item* d_cb_items = nullptr;
   int64_t n_cb_items = 0;
+  Item* d_range_items = nullptr;
+  int64_t n_range_items = 0;
   GramWork* d_work = nullptr;
   int64_t n_work64 = 0, n_work128 = 0;
   Item* d_red_items = nullptr;
@@ -404,10 +412,27 @@ cvgram_status bookkeeping(Batch& b) {
 
 // Layout of every problem and the flat work lists of every launch.
 struct HostLists {
-  std::vector<Item> pivot_items, fold_items, cb_items, red_items, corr_items;
+  std::vector<Item> pivot_items, fold_items, sr_items, fs_items, cb_items, range_items, red_items,
+      corr_items;
   std::vector<PackChunk> chunks;
   std::vector<GramWork> work64, work128;
 };
+
+// Fold path of a problem.  The fused path (no padding between folds, G'_p
+// formed in the corrections) is chosen for many small folds, where padding
+// every fold to whole panels and keeping one FP64 slab set per fold would
+// dominate time and memory; CVGRAM_FOLD_PATH=grouped|fused forces either.
+constexpr int64_t kFusedMaxFoldRows = 256;
+constexpr int32_t kFusedMinFolds = 64;
+
+bool choose_fused(const ProbPlan& p) {
+  const char* f = std::getenv("CVGRAM_FOLD_PATH");
+  if (f && std::strcmp(f, "fused") == 0) return true;
+  if (f && std::strcmp(f, "grouped") == 0) return false;
+  int64_t max_fold = 0;
+  for (int32_t q = 0; q < p.P; ++q) max_fold = std::max(max_fold, p.offsets[q + 1] - p.offsets[q]);
+  return p.P >= kFusedMinFolds && max_fold <= kFusedMaxFoldRows;
+}
 
 void plan_layout(Batch& b, HostLists& L) {
   const int64_t PR = kPanelRows;
@@ -416,12 +441,13 @@ void plan_layout(Batch& b, HostLists& L) {
   for (auto& p : b.pp) {
     p.cfg = b.force_cfg ? b.forced : choose_config(b.mode, b.dtype, p.K, p.M, p.N);
     const int T = p.cfg.tile;
+    p.fused = choose_fused(p);
     p.poff.assign(p.P + 1, 0);
     for (int32_t q = 0; q < p.P; ++q) {
       const int64_t n = p.offsets[q + 1] - p.offsets[q];
-      p.poff[q + 1] = p.poff[q] + (n + PR - 1) / PR * PR;
+      p.poff[q + 1] = p.poff[q] + (p.fused ? n : (n + PR - 1) / PR * PR);
     }
-    p.Np = p.poff[p.P];
+    p.Np = (p.poff[p.P] + PR - 1) / PR * PR;
     p.Kp = (p.K + T - 1) / T * T;
     p.xy_diag = p.M > 0 && p.M <= kYDiagCols;
     p.Mp = p.M == 0 ? 0 : (p.xy_diag ? kYDiagCols : (p.M + T - 1) / T * T);
@@ -441,21 +467,43 @@ void plan_layout(Batch& b, HostLists& L) {
     const int T = p.cfg.tile;
     // pivots
     for (int64_t cb = 0; cb < (p.W + 63) / 64; ++cb) L.pivot_items.push_back({pi, (int32_t)cb, 0});
-    // pack chunks: whole panels of one fold
+    // pack chunks: whole panels of one fold (grouped path), or of the whole
+    // packed row space (fused path: packed row d holds permuted row d)
     p.chunk_begin.assign(p.P + 1, 0);
     int32_t nch = 0;
-    for (int32_t q = 0; q < p.P; ++q) {
-      p.chunk_begin[q] = nch;
-      for (int64_t d = p.poff[q]; d < p.poff[q + 1]; d += chunk_rows)
-        L.chunks.push_back({pi, nch++, d, std::min(d + chunk_rows, p.poff[q + 1]),
-                            p.offsets[q] + (d - p.poff[q]), p.offsets[q + 1]});
+    if (p.fused) {
+      for (int64_t d = 0; d < p.Np; d += chunk_rows)
+        L.chunks.push_back({pi, nch++, d, std::min(d + chunk_rows, p.Np), d, p.N});
+    } else {
+      for (int32_t q = 0; q < p.P; ++q) {
+        p.chunk_begin[q] = nch;
+        for (int64_t d = p.poff[q]; d < p.poff[q + 1]; d += chunk_rows)
+          L.chunks.push_back({pi, nch++, d, std::min(d + chunk_rows, p.poff[q + 1]),
+                              p.offsets[q] + (d - p.poff[q]), p.offsets[q + 1]});
+      }
+      p.chunk_begin[p.P] = nch;
     }
-    p.chunk_begin[p.P] = nch;
     p.n_chunks = nch;
     b.max_pack_cb = std::max<int32_t>(b.max_pack_cb, (int32_t)((p.Wp + kPackCols - 1) / kPackCols));
     // statistics
-    for (int32_t q = 0; q < p.P; ++q) L.fold_items.push_back({pi, q, 0});
-    for (int64_t cb = 0; cb < (p.W + 63) / 64; ++cb) L.cb_items.push_back({pi, (int32_t)cb, 0});
+    for (int32_t q = 0; q < p.P; ++q) {
+      L.fold_items.push_back({pi, q, 0});
+      if (!p.fused) L.sr_items.push_back({pi, q, 0});
+    }
+    if (p.fused) {
+      // consecutive folds per item, up to 256 folds or 2048 rows
+      for (int32_t q = 0; q < p.P;) {
+        int32_t e = q + 1;
+        while (e < p.P && e - q < 256 && p.offsets[e + 1] - p.offsets[q] <= 2048) ++e;
+        L.fs_items.push_back({pi, q, e});
+        q = e;
+      }
+    }
+    p.n_franges = (p.P + kFoldRange - 1) / kFoldRange;
+    for (int64_t cb = 0; cb < (p.W + 63) / 64; ++cb) {
+      L.cb_items.push_back({pi, (int32_t)cb, 0});
+      for (int32_t r = 0; r < p.n_franges; ++r) L.range_items.push_back({pi, (int32_t)cb, r});
+    }
     b.max_cb64 = std::max<int32_t>(b.max_cb64, (int32_t)((p.W + 63) / 64));
     b.max_cb256 = std::max<int32_t>(b.max_cb256, (int32_t)((p.W + 255) / 256));
     // Gram work: split folds along rows so the launch has about
@@ -472,9 +520,7 @@ void plan_layout(Batch& b, HostLists& L) {
     auto& wl = T == 64 ? L.work64 : L.work128;
     p.slab_begin.assign(p.P + 1, 0);
     int32_t slab = 0;
-    for (int32_t q = 0; q < p.P; ++q) {
-      p.slab_begin[q] = slab;
-      const int64_t a = p.poff[q], e = p.poff[q + 1];
+    auto split_rows = [&](int64_t a, int64_t e) {
       const int64_t panels = (e - a) / PR;
       const int64_t splits =
           std::min(panels, std::max<int64_t>(1, (e - a + rows_per_split - 1) / rows_per_split));
@@ -483,6 +529,14 @@ void plan_layout(Batch& b, HostLists& L) {
         const int64_t r1 = a + panels * (sp + 1) / splits * PR;
         for (auto& tt : gtiles) wl.push_back({pi, slab, tt.first, tt.second, r0, r1});
         ++slab;
+      }
+    };
+    if (p.fused) {
+      split_rows(0, p.Np);  // the full Gram only
+    } else {
+      for (int32_t q = 0; q < p.P; ++q) {
+        p.slab_begin[q] = slab;
+        split_rows(p.poff[q], p.poff[q + 1]);
       }
     }
     p.slab_begin[p.P] = slab;
@@ -535,7 +589,8 @@ void allocate_and_upload(Batch& b, const HostLists& L) {
   const size_t eb = elem_bytes(b.mode);
   // arena layout per problem
   struct Off {
-    size_t pivot, packed, packed_lo, part, fold, tot, tr_sum, tr_mean, tr_std, tr_mu, tr_const,
+    size_t pivot, packed, packed_lo, part, fold, tot, tot_part, tr_sum, tr_mean, tr_std, tr_mu,
+        tr_const,
         ntrain, slabs, G;
   };
   std::vector<Off> off(b.pp.size());
@@ -554,6 +609,7 @@ void allocate_and_upload(Batch& b, const HostLists& L) {
     o.part = take_bytes((size_t)4 * p.n_chunks * p.W * 8);
     o.fold = take_bytes((size_t)4 * p.P * p.W * 8);
     o.tot = take_bytes((size_t)8 * p.W * 8);
+    o.tot_part = take_bytes((size_t)p.n_franges * 8 * p.W * 8);
     o.tr_sum = take_bytes((size_t)p.P * p.W * 8);
     o.tr_mean = take_bytes((size_t)p.P * p.W * 8);
     o.tr_std = take_bytes((size_t)p.P * p.W * 8);
@@ -567,10 +623,11 @@ void allocate_and_upload(Batch& b, const HostLists& L) {
 
   // plan blob: per-problem small arrays first, then descriptors and lists
   Blob blob;
-  std::vector<size_t> o_offsets(b.pp.size()), o_cbeg(b.pp.size()), o_sbeg(b.pp.size()),
-      o_ctiles(b.pp.size());
+  std::vector<size_t> o_offsets(b.pp.size()), o_poff(b.pp.size()), o_cbeg(b.pp.size()),
+      o_sbeg(b.pp.size()), o_ctiles(b.pp.size());
   for (size_t i = 0; i < b.pp.size(); ++i) {
     o_offsets[i] = blob.put(b.pp[i].offsets);
+    o_poff[i] = blob.put(b.pp[i].poff);
     o_cbeg[i] = blob.put(b.pp[i].chunk_begin);
     o_sbeg[i] = blob.put(b.pp[i].slab_begin);
     o_ctiles[i] = blob.put(b.pp[i].ctiles);
@@ -580,7 +637,10 @@ void allocate_and_upload(Batch& b, const HostLists& L) {
   const size_t o_pivot = blob.put(L.pivot_items);
   const size_t o_chunks = blob.put(L.chunks);
   const size_t o_fold = blob.put(L.fold_items);
+  const size_t o_sr = blob.put(L.sr_items);
+  const size_t o_fs = blob.put(L.fs_items);
   const size_t o_cb = blob.put(L.cb_items);
+  const size_t o_range = blob.put(L.range_items);
   std::vector<GramWork> work = L.work64;
   work.insert(work.end(), L.work128.begin(), L.work128.end());
   const size_t o_work = blob.put(work);
@@ -610,8 +670,12 @@ void allocate_and_upload(Batch& b, const HostLists& L) {
     d.xy_diag = p.xy_diag ? 1 : 0;
     d.ddof = b.ddof;
     d.x_vec = (p.K % 4 == 0) && ((uintptr_t)p.X % 16 == 0) ? 1 : 0;
+    d.mode = (int32_t)b.mode;
+    d.fused = p.fused ? 1 : 0;
+    d.n_slabs = (int32_t)p.n_slabs;
     d.perm = p.d_perm;
     d.offsets = (const int64_t*)(dblob + o_offsets[i]);
+    d.poff = (const int64_t*)(dblob + o_poff[i]);
     d.pivot = (double*)(arena + o.pivot);
     d.packed = arena + o.packed;
     d.packed_lo = b.mode == CVGRAM_MODE_BF16X3 ? arena + o.packed_lo : nullptr;
@@ -620,6 +684,8 @@ void allocate_and_upload(Batch& b, const HostLists& L) {
     d.chunk_begin = (const int32_t*)(dblob + o_cbeg[i]);
     d.fold = (double*)(arena + o.fold);
     d.tot = (double*)(arena + o.tot);
+    d.tot_part = (double*)(arena + o.tot_part);
+    d.n_franges = p.n_franges;
     d.tr_sum = (double*)(arena + o.tr_sum);
     d.tr_mean = (double*)(arena + o.tr_mean);
     d.tr_std = (double*)(arena + o.tr_std);
@@ -657,8 +723,14 @@ void allocate_and_upload(Batch& b, const HostLists& L) {
   b.n_chunks = (int64_t)L.chunks.size();
   b.d_fold_items = (Item*)(dblob + o_fold);
   b.n_fold_items = (int64_t)L.fold_items.size();
+  b.d_sr_items = (Item*)(dblob + o_sr);
+  b.n_sr_items = (int64_t)L.sr_items.size();
+  b.d_fs_items = (Item*)(dblob + o_fs);
+  b.n_fs_items = (int64_t)L.fs_items.size();
   b.d_cb_items = (Item*)(dblob + o_cb);
   b.n_cb_items = (int64_t)L.cb_items.size();
+  b.d_range_items = (Item*)(dblob + o_range);
+  b.n_range_items = (int64_t)L.range_items.size();
   b.d_work = (GramWork*)(dblob + o_work);
   b.n_work64 = (int64_t)L.work64.size();
   b.n_work128 = (int64_t)L.work128.size();
@@ -684,8 +756,9 @@ void run_pipeline(Batch& b, bool with_events) {
   mark(1);
   launch_pivot(b.dtype, mixed, b.d_pd, b.d_pivot_items, b.n_pivot_items, s);
   launch_pack(b.mode, b.dtype, b.d_pd, b.d_chunks, b.n_chunks, b.max_pack_cb, s);
-  launch_stats_reduce(b.d_pd, b.d_fold_items, b.n_fold_items, b.max_cb64, s);
-  launch_fold_totals(b.d_pd, b.d_cb_items, b.n_cb_items, s);
+  launch_stats_reduce(b.d_pd, b.d_sr_items, b.n_sr_items, b.max_cb64, s);
+  launch_fold_sums_rows(b.dtype, b.d_pd, b.d_fs_items, b.n_fs_items, b.max_cb64, s);
+  launch_fold_totals(b.d_pd, b.d_range_items, b.n_range_items, b.d_cb_items, b.n_cb_items, s);
   launch_train_stats(b.d_pd, b.d_fold_items, b.n_fold_items, b.max_cb256, s);
   mark(2);
   launch_gram(b.mode, 64, b.d_pd, b.d_work, b.n_work64, s);

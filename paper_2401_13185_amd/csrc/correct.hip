@@ -39,6 +39,14 @@ __global__ __launch_bounds__(256) void reduce_slabs_kernel(const ProbDesc* __res
   const int64_t i = e / W, j = e - (e / W) * W;
   if (j < K && j < i) return;
   CVG_GLOBAL double* slabs = gmem(pd.slabs) + e;
+  if (pd.fused) {
+    // fused path: the slabs are row splits of the full Gram only
+    const int32_t S = pd.n_slabs;
+    double g = slabs[0];
+    for (int32_t k = 1; k < S; ++k) g += slabs[(int64_t)k * elems];
+    gmem(pd.G)[e] = g;
+    return;
+  }
   const CVG_GLOBAL int32_t* slab_begin = gmem(pd.slab_begin);
   const int32_t P = pd.P;
   double g = 0.0;
@@ -59,6 +67,16 @@ __global__ __launch_bounds__(256) void reduce_slabs_kernel(const ProbDesc* __res
     a = b;
   }
   gmem(pd.G)[e] = g;
+}
+
+// element (row r, packed column col) of the packed panels as FP64: the
+// shifted value the Gram launch multiplied (hi + lo in the bf16 split)
+__device__ inline double packed_value(const ProbDesc& pd, int64_t r, int64_t col, int64_t Wp) {
+  if (pd.mode == CVGRAM_MODE_FP64) return gmem((const double*)pd.packed)[r * Wp + col];
+  if (pd.mode == CVGRAM_MODE_FP32) return (double)gmem((const float*)pd.packed)[r * Wp + col];
+  const int64_t k = ((r >> 5) * Wp + col) * 32 + (r & 31);
+  return (double)((float)gmem((const __bf16*)pd.packed)[k] +
+                  (float)gmem((const __bf16*)pd.packed_lo)[k]);
 }
 
 template <typename OutT>
@@ -111,8 +129,40 @@ __device__ void correct_tile(const ProbDesc& pd, const OutDesc& od, int32_t f, i
 
   const double NT = (double)gmem((const int64_t*)pd.ntrain)[p];
   const CVG_GLOBAL double* G = gmem((const double*)pd.G);
+
+  // G'_p for this thread's entries: the fold's slab sum (grouped path), or
+  // formed here from the fold's packed rows in fold order (fused path)
+  double gp[kRowsPerThread] = {0.0, 0.0, 0.0, 0.0};
+  if (pd.fused) {
+    __shared__ double zi[TS][TS + 1], zj[TS][TS + 1];
+    const int64_t r0 = gmem(pd.poff)[p], r1 = gmem(pd.poff)[p + 1];
+    const int64_t Wp = pd.Wp;
+    const int64_t pcol = is_xy ? pd.Kp : 0;  // packed column of the tile's first column
+    for (int64_t c0 = r0; c0 < r1; c0 += TS) {
+      const int nv = (int)(r1 - c0 < TS ? r1 - c0 : TS);
+      for (int idx = t; idx < TS * TS; idx += kThreads) {
+        const int v = idx / TS, c = idx % TS;
+        const int64_t i = (int64_t)bi * TS + c, j = (int64_t)bj * TS + c;
+        double a = 0.0, b = 0.0;
+        if (v < nv) {
+          if (i < K) a = packed_value(pd, c0 + v, i, Wp);
+          if (j < ncols) b = packed_value(pd, c0 + v, pcol + j, Wp);
+        }
+        zi[v][c] = a;
+        zj[v][c] = b;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < kRowsPerThread; ++r) {
+        const int il = ty + 8 * r, jl = tx;
+        for (int v = 0; v < nv; ++v) gp[r] = fma(zi[v][il], zj[v][jl], gp[r]);
+      }
+      __syncthreads();
+    }
+  }
   const CVG_GLOBAL double* gp_slab =
-      gmem((const double*)pd.slabs) + (int64_t)gmem(pd.slab_begin)[p] * K * W;  // fold sum G'_p
+      pd.fused ? nullptr
+               : gmem((const double*)pd.slabs) + (int64_t)gmem(pd.slab_begin)[p] * K * W;
 
   double raw[kRowsPerThread], cen[kRowsPerThread];
   bool ok[kRowsPerThread];
@@ -126,7 +176,7 @@ __device__ void correct_tile(const ProbDesc& pd, const OutDesc& od, int32_t f, i
     cen[r] = 0.0;
     if (!ok[r]) continue;
     const int64_t e = i * W + coff + j;
-    const double g = G[e] - gp_slab[e];
+    const double g = G[e] - (pd.fused ? gp[r] : gp_slab[e]);
     raw[r] = g + (rc[il] * ca[jl] + ra[il] * cc[jl]) + NT * (rc[il] * cc[jl]);
     cen[r] = (rcs[il] || ccs[jl]) ? 0.0 : g - NT * (rmu[il] * cmu[jl]);
   }

@@ -63,6 +63,8 @@ constexpr int kYDiagCols = 32;
 constexpr int kPackCols = 256;
 // correction tiles
 constexpr int kCorrTile = 32;
+// fold totals: folds per partial range
+constexpr int kFoldRange = 256;
 
 // ---------------------------------------------------------------------------
 // device-side description of one problem
@@ -78,8 +80,17 @@ struct ProbDesc {
   int32_t xy_diag;      // X^T Y inside diagonal tiles
   int32_t ddof;
   int32_t x_vec;        // X rows 16-byte aligned and K % 4 == 0
+  int32_t mode;         // cvgram_mode: element format of the packed panels
+  // Fold path.  0 (grouped): every fold padded to whole panels, one slab set
+  // per fold holding G'_p.  1 (fused, for many small folds): rows packed
+  // without padding between folds, the slabs hold row splits of the full
+  // Gram only, and each fold's G'_p is formed inside the corrections from
+  // the fold's packed rows.
+  int32_t fused;
+  int32_t n_slabs;
   const int32_t* perm;       // [N]
   const int64_t* offsets;    // [P+1]
+  const int64_t* poff;       // [P+1] first packed row of each fold
   double* pivot;             // [W]
   void* packed;              // packed panels (FP64 / FP32 / bf16 hi)
   void* packed_lo;           // bf16 lo panel
@@ -88,6 +99,8 @@ struct ProbDesc {
   const int32_t* chunk_begin;  // [P+1]
   double* fold;              // [4][P][W] per-fold sum, sumsq, min, max
   double* tot;               // [8][W] totals and extrema over folds
+  double* tot_part;          // [R][8][W] the same per range of kFoldRange folds
+  int32_t n_franges;         // R
   double* tr_sum;            // [P][W] shifted training sums
   double* tr_mean;           // [P][W] shifted training means
   double* tr_std;            // [P][W] training deviations (1 if constant)
@@ -165,8 +178,13 @@ void launch_pack(cvgram_mode mode, cvgram_dtype dt, const ProbDesc* pd, const Pa
 // fold_items: (prob, fold, -); colblock_items: (prob, block of 64 columns, -)
 void launch_stats_reduce(const ProbDesc* pd, const Item* fold_items, int64_t n_items,
                          int32_t max_col_blocks64, hipStream_t s);
-void launch_fold_totals(const ProbDesc* pd, const Item* colblock_items, int64_t n_items,
-                        hipStream_t s);
+// fused-path problems: per-fold sums straight from the fold's rows of X, Y;
+// items (prob, first fold, end fold)
+void launch_fold_sums_rows(cvgram_dtype dt, const ProbDesc* pd, const Item* fold_items,
+                           int64_t n_items, int32_t max_col_blocks64, hipStream_t s);
+// range_items: (prob, block of 64 columns, range of kFoldRange folds)
+void launch_fold_totals(const ProbDesc* pd, const Item* range_items, int64_t n_range_items,
+                        const Item* colblock_items, int64_t n_items, hipStream_t s);
 void launch_train_stats(const ProbDesc* pd, const Item* fold_items, int64_t n_items,
                         int32_t max_col_blocks256, hipStream_t s);
 void launch_fold_stats(const double* tr_mu, const double* tr_std, int32_t p, int64_t K,

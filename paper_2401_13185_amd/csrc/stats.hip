@@ -66,6 +66,47 @@ __global__ __launch_bounds__(256) void stats_reduce_kernel(const ProbDesc* __res
   }
 }
 
+// Fused-path problems (many small folds, no per-fold chunks): the same four
+// per-fold quantities read directly from the fold's rows, X and Y gathered
+// through the permutation and shifted by the pivot exactly as in the pack
+// pass.  items: (prob, first fold, end fold); grid.y = blocks of 64 columns.
+// Wave w takes folds f0 + w, f0 + w + 4, ... and sums each in row order.
+template <typename T>
+__global__ __launch_bounds__(256) void fold_sums_rows_kernel(const ProbDesc* __restrict__ pds,
+                                                             const Item* __restrict__ items) {
+  const Item it = items[blockIdx.x];
+  const ProbDesc& pd = pds[it.prob];
+  const int64_t W = pd.W, K = pd.K, M = pd.M;
+  if ((int64_t)blockIdx.y * 64 >= W) return;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t j = (int64_t)blockIdx.y * 64 + lane;
+  if (j >= W) return;
+  const CVG_GLOBAL T* X = gmem((const T*)pd.X);
+  const CVG_GLOBAL T* Y = gmem((const T*)pd.Y);
+  const CVG_GLOBAL int32_t* perm = gmem(pd.perm);
+  const CVG_GLOBAL int64_t* offsets = gmem(pd.offsets);
+  CVG_GLOBAL double* fold = gmem(pd.fold);
+  const int64_t fs = (int64_t)pd.P * W;
+  const double c = gmem((const double*)pd.pivot)[j];
+  for (int32_t p = it.a + w; p < it.b; p += 4) {
+    double s = 0.0, q = 0.0, mn = INFINITY, mx = -INFINITY;
+    const int64_t r1 = offsets[p + 1];
+    for (int64_t r = offsets[p]; r < r1; ++r) {
+      const int64_t row = perm[r];
+      const double x = j < K ? (double)X[row * K + j] : (double)Y[row * M + (j - K)];
+      const double d = x - c;
+      s += d;
+      q = fma(d, d, q);
+      mn = fmin(mn, x);
+      mx = fmax(mx, x);
+    }
+    fold[0 * fs + (int64_t)p * W + j] = s;
+    fold[1 * fs + (int64_t)p * W + j] = q;
+    fold[2 * fs + (int64_t)p * W + j] = mn;
+    fold[3 * fs + (int64_t)p * W + j] = mx;
+  }
+}
+
 // Column totals over all folds and, for the exact constant test, the
 // smallest and largest value of each column with the fold holding it and
 // the runner-up over the other folds: the extrema over T_p (all folds but p)
@@ -96,11 +137,13 @@ __device__ inline Ext ext_max(Ext a, Ext b) {
   return r;
 }
 
-// items: (prob, block of 64 columns).  One workgroup reduces all folds of
-// its columns in a fixed order (folds w, w + 4, ... per wave, then waves
-// 0..3), so the totals are deterministic.
-__global__ __launch_bounds__(256) void fold_totals_kernel(const ProbDesc* __restrict__ pds,
-                                                          const Item* __restrict__ items) {
+// Two levels, both in a fixed order (deterministic).  Part: items (prob,
+// block of 64 columns, range of kFoldRange folds); the 4 waves take folds
+// w, w + 4, ... of the range and are combined in wave order into tot_part.
+// Final: items (prob, block of 64 columns); the ranges are combined in
+// range order into tot (64 threads, one column each).
+__global__ __launch_bounds__(256) void fold_totals_part_kernel(const ProbDesc* __restrict__ pds,
+                                                               const Item* __restrict__ items) {
   __shared__ double sS[4][64], sQ[4][64];
   __shared__ Ext sMn[4][64], sMx[4][64];
   const Item it = items[blockIdx.x];
@@ -110,12 +153,14 @@ __global__ __launch_bounds__(256) void fold_totals_kernel(const ProbDesc* __rest
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t j = (int64_t)it.a * 64 + lane;
   const int64_t fs = (int64_t)P * W;
+  const int32_t f0 = it.b * kFoldRange;
+  const int32_t f1 = f0 + kFoldRange < P ? f0 + kFoldRange : P;
   const CVG_GLOBAL double* fold = gmem((const double*)pd.fold);
   double S = 0.0, Q = 0.0;
   Ext mn{INFINITY, INT32_MAX, INFINITY}, mx{-INFINITY, INT32_MAX, -INFINITY};
   if (j < W) {
 #pragma unroll 4
-    for (int32_t p = w; p < P; p += 4) {
+    for (int32_t p = f0 + w; p < f1; p += 4) {
       const int64_t e = (int64_t)p * W + j;
       S += fold[e];
       Q += fold[fs + e];
@@ -135,16 +180,44 @@ __global__ __launch_bounds__(256) void fold_totals_kernel(const ProbDesc* __rest
       mn = ext_min(mn, sMn[k][lane]);
       mx = ext_max(mx, sMx[k][lane]);
     }
-    CVG_GLOBAL double* tot = gmem(pd.tot);
-    tot[0 * W + j] = S;
-    tot[1 * W + j] = Q;
-    tot[2 * W + j] = mn.v1;
-    tot[3 * W + j] = (double)mn.f1;
-    tot[4 * W + j] = mn.v2;
-    tot[5 * W + j] = mx.v1;
-    tot[6 * W + j] = (double)mx.f1;
-    tot[7 * W + j] = mx.v2;
+    CVG_GLOBAL double* tp = gmem(pd.tot_part) + (int64_t)it.b * 8 * W;
+    tp[0 * W + j] = S;
+    tp[1 * W + j] = Q;
+    tp[2 * W + j] = mn.v1;
+    tp[3 * W + j] = (double)mn.f1;
+    tp[4 * W + j] = mn.v2;
+    tp[5 * W + j] = mx.v1;
+    tp[6 * W + j] = (double)mx.f1;
+    tp[7 * W + j] = mx.v2;
   }
+}
+
+__global__ __launch_bounds__(64) void fold_totals_final_kernel(const ProbDesc* __restrict__ pds,
+                                                                const Item* __restrict__ items) {
+  const Item it = items[blockIdx.x];
+  const ProbDesc& pd = pds[it.prob];
+  const int64_t W = pd.W;
+  const int64_t j = (int64_t)it.a * 64 + threadIdx.x;
+  if (j >= W) return;
+  const CVG_GLOBAL double* tp = gmem((const double*)pd.tot_part);
+  double S = 0.0, Q = 0.0;
+  Ext mn{INFINITY, INT32_MAX, INFINITY}, mx{-INFINITY, INT32_MAX, -INFINITY};
+  for (int32_t r = 0; r < pd.n_franges; ++r) {
+    const CVG_GLOBAL double* t = tp + (int64_t)r * 8 * W + j;
+    S += t[0 * W];
+    Q += t[1 * W];
+    mn = ext_min(mn, Ext{t[2 * W], (int32_t)t[3 * W], t[4 * W]});
+    mx = ext_max(mx, Ext{t[5 * W], (int32_t)t[6 * W], t[7 * W]});
+  }
+  CVG_GLOBAL double* tot = gmem(pd.tot);
+  tot[0 * W + j] = S;
+  tot[1 * W + j] = Q;
+  tot[2 * W + j] = mn.v1;
+  tot[3 * W + j] = (double)mn.f1;
+  tot[4 * W + j] = mn.v2;
+  tot[5 * W + j] = mx.v1;
+  tot[6 * W + j] = (double)mx.f1;
+  tot[7 * W + j] = mx.v2;
 }
 
 // One thread per (fold, column): Lemma 14 and Lemma 7 downdates, Lemma 12
@@ -218,10 +291,23 @@ void launch_stats_reduce(const ProbDesc* pd, const Item* fold_items, int64_t n_i
   CVG_LAUNCH_CHECK();
 }
 
-void launch_fold_totals(const ProbDesc* pd, const Item* colblock_items, int64_t n_items,
-                        hipStream_t s) {
+void launch_fold_sums_rows(cvgram_dtype dt, const ProbDesc* pd, const Item* fold_items,
+                           int64_t n_items, int32_t max_col_blocks64, hipStream_t s) {
   if (n_items <= 0) return;
-  fold_totals_kernel<<<(unsigned)n_items, 256, 0, s>>>(pd, colblock_items);
+  dim3 grid((unsigned)n_items, (unsigned)max_col_blocks64);
+  if (dt == CVGRAM_F64)
+    fold_sums_rows_kernel<double><<<grid, 256, 0, s>>>(pd, fold_items);
+  else
+    fold_sums_rows_kernel<float><<<grid, 256, 0, s>>>(pd, fold_items);
+  CVG_LAUNCH_CHECK();
+}
+
+void launch_fold_totals(const ProbDesc* pd, const Item* range_items, int64_t n_range_items,
+                        const Item* colblock_items, int64_t n_items, hipStream_t s) {
+  if (n_range_items <= 0 || n_items <= 0) return;
+  fold_totals_part_kernel<<<(unsigned)n_range_items, 256, 0, s>>>(pd, range_items);
+  CVG_LAUNCH_CHECK();
+  fold_totals_final_kernel<<<(unsigned)n_items, 64, 0, s>>>(pd, colblock_items);
   CVG_LAUNCH_CHECK();
 }
 
