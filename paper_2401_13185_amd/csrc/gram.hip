@@ -55,8 +55,8 @@ struct Mode<CVGRAM_MODE_FP64> {
   typedef double E;
   typedef double4_t Acc;
   static constexpr int BK = 16;
-  static constexpr int PAD = 4;       // doubles of padding per LDS row
-};
+  static constexpr int PAD = 16;      // rows of 144 / 80 doubles: the two rows of a
+};                                    // 32-lane half of a fragment read use disjoint banks
 template <>
 struct Mode<CVGRAM_MODE_FP32> {
   typedef float E;
@@ -82,8 +82,12 @@ struct Smem {
   static constexpr int LDA = BM + Mode<MODE>::PAD;
   static constexpr int LDY = kYW + Mode<MODE>::PAD;
   typename Mode<MODE>::E a[2][16 * LDA];
-  typename Mode<MODE>::E b[2][16 * LDA];
-  typename Mode<MODE>::E y[2][16 * LDY];
+  // B operand (off-diagonal tiles) or the Y block (diagonal tiles) share
+  // storage: a diagonal tile reuses A as B
+  union {
+    typename Mode<MODE>::E b[2][16 * LDA];
+    typename Mode<MODE>::E y[2][16 * LDY];
+  };
 };
 // ---------------------------------------------------------------------------
 // global -> register staging of one stage (BK packed rows starting at row r)
@@ -91,68 +95,43 @@ struct Smem {
 template <int MODE, int BM>
 struct Stage;
 
-// FP64: an operand block is 16 x BM doubles, BM / 16 per thread; the Y block
-// 16 x 32 doubles, one 16-byte pair per thread.
-template <int BM>
-struct Stage<CVGRAM_MODE_FP64, BM> {
-  static constexpr int V = BM / 32;  // double2 per thread per operand
-  double2_t a[V], b[V], y;
-  __device__ void load(const CVG_GLOBAL double* Z, int64_t Wp, int64_t r, int64_t ca, int64_t cb,
+// FP64 / FP32: an operand block is 16 rows x BM columns, moved in 16-byte
+// chunks; consecutive threads take consecutive chunks of a row, so both the
+// global loads and the LDS stores are contiguous.  The Y block (16 x 32) is
+// one chunk for each of the first 16 * 32 * sizeof(E) / 16 threads.
+template <int MODE, int BM>
+struct Stage {
+  typedef typename Mode<MODE>::E E;
+  typedef E V16 __attribute__((ext_vector_type(16 / sizeof(E))));
+  static constexpr int EPC = 16 / sizeof(E);        // elements per chunk
+  static constexpr int CPR = BM / EPC;              // chunks per row
+  static constexpr int RPR = kThreads / CPR;        // rows per round
+  static constexpr int V = 16 / RPR;                // chunks per thread per operand
+  static constexpr int YC = kYW / EPC;              // chunks per Y row
+  V16 a[V], b[V], y;
+  __device__ void load(const CVG_GLOBAL E* Z, int64_t Wp, int64_t r, int64_t ca, int64_t cb,
                        int64_t cy, bool ld_b, bool ld_y, int t) {
-    const int row = t >> 4, col = (t & 15) * (BM / 16);
-    const CVG_GLOBAL double* pa = Z + (r + row) * Wp + ca + col;
+    const int row0 = t / CPR, col = (t % CPR) * EPC;
 #pragma unroll
-    for (int u = 0; u < V; ++u) a[u] = *(const CVG_GLOBAL double2_t*)(pa + 2 * u);
+    for (int u = 0; u < V; ++u)
+      a[u] = *(const CVG_GLOBAL V16*)(Z + (r + row0 + RPR * u) * Wp + ca + col);
     if (ld_b) {
-      const CVG_GLOBAL double* pb = Z + (r + row) * Wp + cb + col;
 #pragma unroll
-      for (int u = 0; u < V; ++u) b[u] = *(const CVG_GLOBAL double2_t*)(pb + 2 * u);
+      for (int u = 0; u < V; ++u)
+        b[u] = *(const CVG_GLOBAL V16*)(Z + (r + row0 + RPR * u) * Wp + cb + col);
     }
-    if (ld_y) y = *(const CVG_GLOBAL double2_t*)(Z + (r + row) * Wp + cy + (t & 15) * 2);
+    if (ld_y && t < 16 * YC)
+      y = *(const CVG_GLOBAL V16*)(Z + (r + t / YC) * Wp + cy + (t % YC) * EPC);
   }
-  __device__ void store(Smem<CVGRAM_MODE_FP64, BM>& s, int buf, bool st_b, bool st_y,
-                        int t) const {
-    constexpr int LDA = Smem<CVGRAM_MODE_FP64, BM>::LDA, LDY = Smem<CVGRAM_MODE_FP64, BM>::LDY;
-    const int row = t >> 4, col = (t & 15) * (BM / 16);
+  __device__ void store(Smem<MODE, BM>& s, int buf, bool st_b, bool st_y, int t) const {
+    constexpr int LDA = Smem<MODE, BM>::LDA, LDY = Smem<MODE, BM>::LDY;
+    const int row0 = t / CPR, col = (t % CPR) * EPC;
 #pragma unroll
-    for (int u = 0; u < V; ++u) *(double2_t*)&s.a[buf][row * LDA + col + 2 * u] = a[u];
+    for (int u = 0; u < V; ++u) *(V16*)&s.a[buf][(row0 + RPR * u) * LDA + col] = a[u];
     if (st_b)
 #pragma unroll
-      for (int u = 0; u < V; ++u) *(double2_t*)&s.b[buf][row * LDA + col + 2 * u] = b[u];
-    if (st_y) *(double2_t*)&s.y[buf][row * LDY + (t & 15) * 2] = y;
-  }
-};
-
-// FP32: an operand block is 16 x BM floats, BM / 16 per thread; the Y block
-// 16 x 32 floats, 16 bytes for threads 0..127.
-template <int BM>
-struct Stage<CVGRAM_MODE_FP32, BM> {
-  static constexpr int V = BM / 64;  // float4 per thread per operand
-  float4_t a[V], b[V], y;
-  __device__ void load(const CVG_GLOBAL float* Z, int64_t Wp, int64_t r, int64_t ca, int64_t cb,
-                       int64_t cy, bool ld_b, bool ld_y, int t) {
-    const int row = t >> 4, col = (t & 15) * (BM / 16);
-    const CVG_GLOBAL float* pa = Z + (r + row) * Wp + ca + col;
-#pragma unroll
-    for (int u = 0; u < V; ++u) a[u] = *(const CVG_GLOBAL float4_t*)(pa + 4 * u);
-    if (ld_b) {
-      const CVG_GLOBAL float* pb = Z + (r + row) * Wp + cb + col;
-#pragma unroll
-      for (int u = 0; u < V; ++u) b[u] = *(const CVG_GLOBAL float4_t*)(pb + 4 * u);
-    }
-    if (ld_y && t < 128)
-      y = *(const CVG_GLOBAL float4_t*)(Z + (r + (t >> 3)) * Wp + cy + (t & 7) * 4);
-  }
-  __device__ void store(Smem<CVGRAM_MODE_FP32, BM>& s, int buf, bool st_b, bool st_y,
-                        int t) const {
-    constexpr int LDA = Smem<CVGRAM_MODE_FP32, BM>::LDA, LDY = Smem<CVGRAM_MODE_FP32, BM>::LDY;
-    const int row = t >> 4, col = (t & 15) * (BM / 16);
-#pragma unroll
-    for (int u = 0; u < V; ++u) *(float4_t*)&s.a[buf][row * LDA + col + 4 * u] = a[u];
-    if (st_b)
-#pragma unroll
-      for (int u = 0; u < V; ++u) *(float4_t*)&s.b[buf][row * LDA + col + 4 * u] = b[u];
-    if (st_y && t < 128) *(float4_t*)&s.y[buf][(t >> 3) * LDY + (t & 7) * 4] = y;
+      for (int u = 0; u < V; ++u) *(V16*)&s.b[buf][(row0 + RPR * u) * LDA + col] = b[u];
+    if (st_y && t < 16 * YC) *(V16*)&s.y[buf][(t / YC) * LDY + (t % YC) * EPC] = y;
   }
 };
 
