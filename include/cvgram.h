@@ -101,8 +101,8 @@ typedef enum {
  * fold), validates the partitioning, computes per-column pivots, the FP64
  * column sums, sums of squares, minima and maxima of every validation
  * block, and the validation-block Gram products of all folds in one grouped
- * MFMA launch.  It waits on `stream` twice, for a few bytes of validation
- * results; everything after that is only enqueued.
+ * MFMA launch.  It waits on `stream` once for the validation data and the
+ * fold sizes (twice when P > 4096); everything after that is only enqueued.
  *
  * Fold path: with many small folds (P >= 64 and no fold above 256 rows,
  * e.g. leave-one-out) the rows are packed without per-fold padding, only the

@@ -350,11 +350,15 @@ cvgram_status bookkeeping(Batch& b) {
   Owned scratch;
   scratch.device = b.device;
   int32_t* info = (int32_t*)scratch.dev(64 * sizeof(int32_t));
-  int32_t* keys = (int32_t*)scratch.dev((size_t)2 * maxN * sizeof(int32_t));
-  int32_t* perm_tmp = (int32_t*)scratch.dev((size_t)maxN * sizeof(int32_t));
-  int32_t* hist = (int32_t*)scratch.dev((size_t)radix_hist_entries(maxN) * sizeof(int32_t));
-  int64_t* offs = (int64_t*)scratch.dev((size_t)(maxN + 1) * sizeof(int64_t));
-  int32_t* hbuf = (int32_t*)scratch.pinned(64 * sizeof(int32_t));
+  // buffers of the sort stay with the batch: the sort still runs after this
+  // function returns (only the validation data is waited for)
+  int32_t* keys = (int32_t*)b.mem.dev((size_t)2 * maxN * sizeof(int32_t));
+  int32_t* perm_tmp = (int32_t*)b.mem.dev((size_t)maxN * sizeof(int32_t));
+  int32_t* hist = (int32_t*)b.mem.dev((size_t)radix_hist_entries(maxN) * sizeof(int32_t));
+  int64_t* offs = (int64_t*)b.mem.dev((size_t)(maxN + 1) * sizeof(int64_t));
+  int32_t* counts = (int32_t*)scratch.dev(kCountLabels * sizeof(int32_t));
+  int32_t* hbuf = (int32_t*)scratch.pinned((64 + kCountLabels) * sizeof(int32_t));
+  int32_t* hcounts = hbuf + 64;
   cvgram_status st = CVGRAM_OK;
   int64_t at = 0;
   try {
@@ -366,8 +370,11 @@ cvgram_status bookkeeping(Batch& b) {
       launch_fill_i32(info, 1, INT32_MAX, s);
       launch_fill_i32(info + 1, 1, INT32_MIN, s);
       launch_fill_i32(info + 2, 62, 0, s);
-      launch_label_minmax(p.fold, p.N, info, s);
+      launch_fill_i32(counts, kCountLabels, 0, s);
+      launch_label_count(p.fold, p.N, info, counts, s);
       CVG_HIP(hipMemcpyAsync(hbuf, info, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+      CVG_HIP(hipMemcpyAsync(hcounts, counts, kCountLabels * sizeof(int32_t),
+                             hipMemcpyDeviceToHost, s));
       CVG_HIP(hipStreamSynchronize(s));
       if (hbuf[0] < 0) {
         st = fail(CVGRAM_EFOLDS, tag + "fold label < 0 (Definition 1)");
@@ -386,13 +393,23 @@ cvgram_status bookkeeping(Batch& b) {
       const int32_t* sorted = nullptr;
       radix_partition(p.fold, p.N, bit_length((uint32_t)(P - 1)), keys, keys + maxN, p.d_perm,
                       perm_tmp, hist, &sorted, s);
-      launch_fold_offsets(sorted, p.N, (int32_t)P, offs, info + 2, s);
       p.offsets.assign(P + 1, 0);
-      CVG_HIP(hipMemcpyAsync(p.offsets.data(), offs, (P + 1) * sizeof(int64_t),
-                             hipMemcpyDeviceToHost, s));
-      CVG_HIP(hipMemcpyAsync(hbuf + 2, info + 2, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-      CVG_HIP(hipStreamSynchronize(s));
-      if (hbuf[2]) {
+      bool empty = false;
+      if (P <= kCountLabels) {
+        // the fold sizes came with the first wait: no second one
+        for (int64_t q = 0; q < P; ++q) {
+          empty |= hcounts[q] == 0;
+          p.offsets[q + 1] = p.offsets[q] + hcounts[q];
+        }
+      } else {
+        launch_fold_offsets(sorted, p.N, (int32_t)P, offs, info + 2, s);
+        CVG_HIP(hipMemcpyAsync(p.offsets.data(), offs, (P + 1) * sizeof(int64_t),
+                               hipMemcpyDeviceToHost, s));
+        CVG_HIP(hipMemcpyAsync(hbuf + 2, info + 2, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        CVG_HIP(hipStreamSynchronize(s));
+        empty = hbuf[2] != 0;
+      }
+      if (empty) {
         st = fail(CVGRAM_EFOLDS, tag + "a fold label in [0, P) has no rows (Definition 1)");
         break;
       }
@@ -405,7 +422,10 @@ cvgram_status bookkeeping(Batch& b) {
     scratch.release();
     throw;
   }
-  CVG_HIP(hipStreamSynchronize(s));
+  // On success nothing enqueued after the last wait reads the scratch
+  // (label counts, validation flags); on failure wait for the sorts before
+  // the batch's memory is handed back.
+  if (st != CVGRAM_OK) CVG_HIP(hipStreamSynchronize(s));
   scratch.release();
   return st;
 }

@@ -160,6 +160,10 @@ struct GramWork {
 // partition.hip (one problem at a time, at plan time)
 void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 void launch_label_minmax(const int32_t* fold, int64_t N, int32_t* info, hipStream_t s);
+// minimum, maximum and the counts of labels below kCountLabels (counts zeroed by the caller)
+constexpr int kCountLabels = 4096;
+void launch_label_count(const int32_t* fold, int64_t N, int32_t* info, int32_t* counts,
+                        hipStream_t s);
 void radix_partition(const int32_t* fold, int64_t N, int bits, int32_t* keys_a, int32_t* keys_b,
                      int32_t* perm, int32_t* perm_tmp, int32_t* hist, const int32_t** sorted_keys,
                      hipStream_t s);

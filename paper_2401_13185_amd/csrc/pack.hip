@@ -31,7 +31,9 @@ typedef float float4_t __attribute__((ext_vector_type(4)));
 typedef double double2_t __attribute__((ext_vector_type(2)));
 
 // pivot: c_j = FP64 mean of the first min(N, 256) rows of column j of [X | Y]
-// (rounded to FP32 in the mixed modes).  items: (prob, block of 64 columns)
+// (rounded to FP32 in the mixed modes).  items: (prob, block of 64 columns).
+// Wave w sums rows w, w + 4, ... with eight independent partial sums (eight
+// loads in flight per lane), combined in a fixed order.
 template <typename T>
 __global__ __launch_bounds__(256) void pivot_kernel(const ProbDesc* __restrict__ pds,
                                                     const Item* __restrict__ items,
@@ -45,11 +47,19 @@ __global__ __launch_bounds__(256) void pivot_kernel(const ProbDesc* __restrict__
   const int64_t rows = pd.N < 256 ? pd.N : 256;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t j = (int64_t)it.a * 64 + lane;
-  double s = 0.0;
-  if (j < K + M)
-    for (int64_t r = w; r < rows; r += 4)
-      s += j < K ? (double)X[r * K + j] : (double)Y[r * M + (j - K)];
-  part[w][lane] = s;
+  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (j < K + M) {
+    const CVG_GLOBAL T* base = j < K ? X + j : Y + (j - K);
+    const int64_t ld = j < K ? K : M;
+    for (int64_t r0 = w; r0 < rows; r0 += 32) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int64_t r = r0 + 4 * u;
+        if (r < rows) acc[u] += (double)base[r * ld];
+      }
+    }
+  }
+  part[w][lane] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
   __syncthreads();
   if (w == 0 && j < K + M) {
     double c = ((part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane])) / (double)rows;

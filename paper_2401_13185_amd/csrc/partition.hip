@@ -64,6 +64,46 @@ __global__ __launch_bounds__(kThreads) void label_minmax_kernel(const int32_t* _
   }
 }
 
+// Label counts for labels in [0, kCountLabels), with the minimum and maximum
+// (all integer, so the result does not depend on the order of the atomics):
+// one pass that gives the host the fold sizes together with the validation
+// data.  Each workgroup counts into LDS and adds its non-zero bins.
+__global__ __launch_bounds__(kThreads) void label_count_kernel(const int32_t* __restrict__ f,
+                                                               int64_t n, int32_t* info,
+                                                               int32_t* counts) {
+  __shared__ int h[kCountLabels];
+  for (int b = threadIdx.x; b < kCountLabels; b += kThreads) h[b] = 0;
+  __syncthreads();
+  int lo = INT_MAX, hi = INT_MIN;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) {
+    const int v = f[i];
+    lo = min(lo, v);
+    hi = max(hi, v);
+    if (v >= 0 && v < kCountLabels) atomicAdd(&h[v], 1);
+  }
+  lo = wave_min(lo);
+  hi = wave_max(hi);
+  __shared__ int slo[kWaves], shi[kWaves];
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    slo[w] = lo;
+    shi[w] = hi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int k = 1; k < kWaves; ++k) {
+      lo = min(lo, slo[k]);
+      hi = max(hi, shi[k]);
+    }
+    atomicMin(&info[0], lo);
+    atomicMax(&info[1], hi);
+  }
+  for (int b = threadIdx.x; b < kCountLabels; b += kThreads)
+    if (h[b]) atomicAdd(&counts[b], h[b]);
+}
+
 // hist is digit-major: hist[d * tiles + t]
 __global__ __launch_bounds__(kThreads) void radix_hist_kernel(const int32_t* __restrict__ keys,
                                                               int64_t n, int shift,
@@ -243,6 +283,14 @@ void launch_label_minmax(const int32_t* fold, int64_t N, int32_t* info, hipStrea
   int64_t blocks = (N + 16 * kThreads - 1) / (16 * kThreads);
   if (blocks > 512) blocks = 512;
   label_minmax_kernel<<<(unsigned)blocks, kThreads, 0, s>>>(fold, N, info);
+  CVG_LAUNCH_CHECK();
+}
+
+void launch_label_count(const int32_t* fold, int64_t N, int32_t* info, int32_t* counts,
+                        hipStream_t s) {
+  int64_t blocks = (N + 16 * kThreads - 1) / (16 * kThreads);
+  if (blocks > 512) blocks = 512;
+  label_count_kernel<<<(unsigned)blocks, kThreads, 0, s>>>(fold, N, info, counts);
   CVG_LAUNCH_CHECK();
 }
 

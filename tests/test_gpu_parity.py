@@ -257,6 +257,18 @@ def test_error_statuses():
         cv.cvgram_destroy(h)
         return 0
 
+    # more labels than the one-pass label count covers: the sort's own check
+    n = 6000
+    big = np.arange(n, dtype=np.int32) % 5001
+    big[big == 4321] = 0                                         # fold 4321 empty
+    Xb = _t(rng.standard_normal((n, 2)))
+    Yb = _t(rng.standard_normal((n, 1)))
+    with pytest.raises(cv.CVGramError) as ei:
+        cv.cvgram_create(Xb, Yb, _t(big))
+    assert ei.value.status == 2
+    big[0] = 4321                                                # every fold non-empty
+    cv.cvgram_destroy(cv.cvgram_create(Xb, Yb, _t(big)))
+
     assert status([0] * 10) == 2                                 # P = 1
     assert status([0, 1, 3, 3, 0, 1, 3, 0, 1, 3]) == 2           # fold 2 empty
     assert status([0, 1, -1, 0, 1, 0, 1, 0, 1, 0]) == 2          # negative label
