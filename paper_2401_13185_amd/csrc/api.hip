@@ -333,7 +333,7 @@ int bit_length(uint32_t v) {
   return b;
 }
 
-constexpr int64_t kPackTargetBlocks = 8192;
+constexpr int64_t kPackTargetBlocks = 1024;
 constexpr int64_t kMaxChunkRows = 1024;   // multiple of kPanelRows
 constexpr int64_t kGramMinRows = 256;
 

@@ -184,45 +184,40 @@ __device__ inline void mma_f32(const float* A, int lda, int acol0, const float* 
 // 32 or with 64 banks of 4 bytes).
 __device__ __forceinline__ int swz(int c) { return ((c >> 1) ^ (c >> 2)) & 3; }
 
-// one stage of MFMA work on the swizzled buffers: NA x NB blocks of 16 x 16,
-// A columns from `acol0`, B columns from `bcol0` (multiples of 16); `lfo` is
-// the lane's byte offset fc * 64 + ((fr ^ swz(fc)) << 4).  All fragments are
-// read first, then the three products run in passes over all blocks, so
-// consecutive MFMAs update different accumulators.
-template <int NA, int NB, int NACC>
-__device__ inline void mma_bf16x3(const char* Ah, const char* Al, int acol0, const char* Bh,
-                                  const char* Bl, int bcol0, int lfo, float4_t (&acc)[NACC]) {
+// One stage's fragments for NA x NB blocks of 16 x 16: A columns from
+// `acol0`, B columns from `bcol0` (multiples of 16) of the swizzled buffers;
+// `lfo` is the lane's byte offset fc * 64 + ((fr ^ swz(fc)) << 4).
+template <int NA, int NB>
+struct Frags {
   bf16x8_t ah[NA], al[NA], bh[NB], bl[NB];
+  __device__ void load(const __bf16* Ah, const __bf16* Al, int acol0, const __bf16* Bh,
+                       const __bf16* Bl, int bcol0, int lfo) {
 #pragma unroll
-  for (int a = 0; a < NA; ++a) {
-    const int off = (acol0 + a * 16) * 64 + lfo;
-    ah[a] = *(const bf16x8_t*)(Ah + off);
-    al[a] = *(const bf16x8_t*)(Al + off);
+    for (int a = 0; a < NA; ++a) {
+      const int off = (acol0 + a * 16) * 64 + lfo;
+      ah[a] = *(const bf16x8_t*)((const char*)Ah + off);
+      al[a] = *(const bf16x8_t*)((const char*)Al + off);
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int off = (bcol0 + b * 16) * 64 + lfo;
+      bh[b] = *(const bf16x8_t*)((const char*)Bh + off);
+      bl[b] = *(const bf16x8_t*)((const char*)Bl + off);
+    }
   }
-#pragma unroll
-  for (int b = 0; b < NB; ++b) {
-    const int off = (bcol0 + b * 16) * 64 + lfo;
-    bh[b] = *(const bf16x8_t*)(Bh + off);
-    bl[b] = *(const bf16x8_t*)(Bl + off);
-  }
-#pragma unroll
-  for (int a = 0; a < NA; ++a)
-#pragma unroll
-    for (int b = 0; b < NB; ++b)
-      acc[a * NB + b] =
-          __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bh[b], acc[a * NB + b], 0, 0, 0);
+};
+
+// One of the three products over all blocks (consecutive MFMAs update
+// different accumulators): pass 0 lo(A) hi(B), pass 1 hi(A) lo(B), pass 2
+// hi(A) hi(B).
+template <int PASS, int NA, int NB, int NACC>
+__device__ inline void mfma_pass(const Frags<NA, NB>& f, float4_t (&acc)[NACC]) {
 #pragma unroll
   for (int a = 0; a < NA; ++a)
 #pragma unroll
     for (int b = 0; b < NB; ++b)
-      acc[a * NB + b] =
-          __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bl[b], acc[a * NB + b], 0, 0, 0);
-#pragma unroll
-  for (int a = 0; a < NA; ++a)
-#pragma unroll
-    for (int b = 0; b < NB; ++b)
-      acc[a * NB + b] =
-          __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bh[b], acc[a * NB + b], 0, 0, 0);
+      acc[a * NB + b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+          PASS == 0 ? f.al[a] : f.ah[a], PASS == 1 ? f.bl[b] : f.bh[b], acc[a * NB + b], 0, 0, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -502,9 +497,27 @@ __global__ __launch_bounds__(kThreads) void gram_bf16_kernel(const ProbDesc* __r
   const int64_t p0 = w.r0 / 32;  // first panel
   int since = 0;
 
-  auto main_loop = [&](auto diag_c, auto ydiag_c) {
-    constexpr bool DG = decltype(diag_c)::value;   // B is A
-    constexpr bool YD = decltype(ydiag_c)::value;  // K x M block in this tile
+  auto flush = [&]() {
+    since += 32;
+    if (since >= kFlushRows) {
+      since = 0;
+#pragma unroll
+      for (int i = 0; i < NACC; ++i) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) a64[i][e] += (double)acc[i][e];
+        acc[i] = float4_t{0, 0, 0, 0};
+      }
+    }
+  };
+
+  // The loop is instantiated per tile kind (B is A; K x M block in the
+  // tile) and per wave role, so each wave's loop holds only its own
+  // fragment registers; every instance runs the same sequence of barriers.
+  auto main_loop = [&](auto diag_c, auto ydiag_c, auto role_c) {
+    constexpr bool DG = decltype(diag_c)::value;
+    constexpr bool YD = decltype(ydiag_c)::value;
+    constexpr int R = decltype(role_c)::value;
+    constexpr int FA = R == 1 ? NY : NW, FB = R == 1 ? 2 : NW;
     // direct loads per wave per stage (all waves issue the same number)
     constexpr int L = IA * (DG ? 2 : 4) + (YD ? 1 : 0);
     // stage s (clamped to the last one) into buffer b
@@ -534,56 +547,69 @@ __global__ __launch_bounds__(kThreads) void gram_bf16_kernel(const ProbDesc* __r
         dma16(src + (wave & 1) * 1024, (wave < 2 ? b.yh : b.yl) + (wave & 1) * 512);
       }
     };
-    auto compute = [&](const DmaBuf<BM>& b) {
-      const char* Ah = (const char*)b.ah;
-      const char* Al = (const char*)b.al;
-      const char* Bh = (const char*)(DG ? b.ah : b.bh);
-      const char* Bl = (const char*)(DG ? b.al : b.bl);
-      if (role == 0)
-        mma_bf16x3<NW, NW>(Ah, Al, wm * WT, Bh, Bl, wn * WT, lfo, acc);
-      else if (YD && role == 1)
-        mma_bf16x3<NY, 2>(Ah, Al, 0, (const char*)b.yh, (const char*)b.yl, 0, lfo, acc);
-      since += 32;
-      if (since >= kFlushRows) {
-        since = 0;
-#pragma unroll
-        for (int i = 0; i < NACC; ++i) {
-#pragma unroll
-          for (int e = 0; e < 4; ++e) a64[i][e] += (double)acc[i][e];
-          acc[i] = float4_t{0, 0, 0, 0};
+    typedef Frags<FA, FB> F;
+    auto load_frags = [&](F& f, const DmaBuf<BM>& b) {
+      if constexpr (R == 0)
+        f.load(b.ah, b.al, wm * WT, DG ? b.ah : b.bh, DG ? b.al : b.bl, wn * WT, lfo);
+      else if constexpr (R == 1)
+        f.load(b.ah, b.al, 0, b.yh, b.yl, 0, lfo);
+    };
+    // Step s: the fragments of stage s are in `cur`.  The first product pass
+    // runs; then the wait and the barrier make stage s + 1 visible in every
+    // wave and end every wave's reads of stage s's buffer, which receives
+    // stage s + 4; stage s + 1's fragments are read into `nxt` while the
+    // other two passes of stage s run.  Every step issues its loads, also
+    // past the end of a partial last round (re-loading the last stage): the
+    // compiler's wait bookkeeping for direct-to-LDS loads then stays exact,
+    // and no read of one buffer waits for loads into the others.
+    auto step = [&](int64_t s, const DmaBuf<BM>& next_buf, DmaBuf<BM>& target, F& cur, F& nxt) {
+      if constexpr (R != 2) {
+        if (s < nst) mfma_pass<0>(cur, acc);
+      }
+      wait_vmcnt_lgkm0<2 * L>();
+      barrier_only();
+      issue(target, s + 4);
+      if constexpr (R != 2) {
+        if (s + 1 < nst) load_frags(nxt, next_buf);
+        if (s < nst) {
+          mfma_pass<1>(cur, acc);
+          mfma_pass<2>(cur, acc);
+          flush();
         }
       }
     };
-    // step s: stage s is complete in every wave after the wait and the
-    // barrier, which also ends every wave's reads of the previous buffer;
-    // that buffer then receives stage s + 3.  Every step issues its loads,
-    // also the steps past the end of a partial last round (they re-load the
-    // last stage and skip the compute): the compiler's wait bookkeeping for
-    // direct-to-LDS loads then stays exact across the round, and no read of
-    // one buffer waits for loads into the others.
-    auto step = [&](int64_t s, const DmaBuf<BM>& cur, DmaBuf<BM>& nxt) {
-      wait_vmcnt_lgkm0<2 * L>();
-      barrier_only();
-      issue(nxt, s + 3);
-      if (s < nst) compute(cur);
-    };
+    F f0, f1;
     issue(sb0, 0);
     issue(sb1, 1);
     issue(sb2, 2);
+    issue(sb3, 3);
+    wait_vmcnt_lgkm0<3 * L>();
+    barrier_only();
+    if constexpr (R != 2) load_frags(f0, sb0);
     for (int64_t s = 0; s < nst; s += kStages) {
-      step(s, sb0, sb3);
-      step(s + 1, sb1, sb0);
-      step(s + 2, sb2, sb1);
-      step(s + 3, sb3, sb2);
+      step(s, sb1, sb0, f0, f1);
+      step(s + 1, sb2, sb1, f1, f0);
+      step(s + 2, sb3, sb2, f0, f1);
+      step(s + 3, sb0, sb3, f1, f0);
     }
     wait_vmcnt_lgkm0<0>();  // the loads past the end
   };
-  if (!diag)
-    main_loop(std::false_type{}, std::false_type{});
-  else if (ydiag)
-    main_loop(std::true_type{}, std::true_type{});
-  else
-    main_loop(std::true_type{}, std::false_type{});
+  typedef std::integral_constant<int, 0> R0;
+  typedef std::integral_constant<int, 1> R1;
+  typedef std::integral_constant<int, 2> R2;
+  if (!diag) {
+    main_loop(std::false_type{}, std::false_type{}, R0{});
+  } else if (ydiag) {
+    if (role == 0)
+      main_loop(std::true_type{}, std::true_type{}, R0{});
+    else
+      main_loop(std::true_type{}, std::true_type{}, R1{});
+  } else {
+    if (role == 0)
+      main_loop(std::true_type{}, std::false_type{}, R0{});
+    else
+      main_loop(std::true_type{}, std::false_type{}, R2{});
+  }
   if (role == 2) return;
   CVG_GLOBAL double* out = slabs + (int64_t)w.slab * K * (K + M);
   auto value = [&](int i, int e) -> double { return a64[i][e] + (double)acc[i][e]; };
