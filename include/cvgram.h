@@ -146,6 +146,26 @@ cvgram_status cvgram_partition(cvgram_t h, int32_t* perm, int64_t* offsets);
  */
 cvgram_status cvgram_fold(cvgram_t h, int32_t p, void* out_XtX, void* out_XtY);
 
+/* Leakage comparison -- NOT training-partition preprocessing, never the
+ * default; for demonstrating numerically what Section 4.1 shows (a
+ * validation fold's rows leak into the training products):
+ *   CVGRAM_LEAK_GLOBAL    the handle's combination, but X and Y centred and
+ *                         scaled with the means and deviations of ALL N rows
+ *                         (divisor N - ddof; a column constant over all rows
+ *                         gets deviation 1), then fold p's training rows
+ *                         multiplied.  Centering X and Y are independent here.
+ *   CVGRAM_LEAK_LINDGREN  Lindgren et al.'s centred products, Equation (20)
+ *                         as restated in the proof of Lemma 11:
+ *                         (X^T X)_ij - (X_V^T X_V)_ij - xbar_i sum_V X_nj
+ *                         - xbar_j sum_V X_ni + (N/P) xbar_i xbar_j, with
+ *                         xbar over all rows; X^T Y the same with Y on the
+ *                         right.  Needs the handle's combination
+ *                         center_x = center_y = 1, no scaling (else EINVAL).
+ * Outputs as for cvgram_fold (out_XtY ignored when M == 0).  Returns
+ * CVGRAM_ERANGE for a fold out of range, CVGRAM_EINVAL for an unknown kind. */
+typedef enum { CVGRAM_LEAK_GLOBAL = 1, CVGRAM_LEAK_LINDGREN = 2 } cvgram_leak;
+cvgram_status cvgram_fold_leaky(cvgram_t h, int32_t p, int kind, void* out_XtX, void* out_XtY);
+
 /* As cvgram_fold, for any of the 16 combinations (flags 0 or 1).  Returns
  * CVGRAM_ENOTSCALABLE if a scale flag is set on a partitioning that is not
  * scalable for the handle's ddof.  Equivalent combinations (Lemma 9) return

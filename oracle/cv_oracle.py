@@ -33,6 +33,10 @@ DESIGN.md):
     ``xtx_class`` and ``xty_class``.
 
 Precision: all arithmetic in FP64 (FP32 inputs are widened exactly first).
+
+Two leaky comparison modes (``leaky_global_fold``, ``leaky_lindgren_fold``)
+compute what Section 4.1 shows to be wrong, for numerical demonstrations of
+the leak; they are never the default.
 """
 from __future__ import annotations
 
@@ -42,7 +46,7 @@ __all__ = [
     "COMBOS", "xtx_class", "xty_class", "XTX_CLASS_COMBO", "XTY_CLASS_COMBO",
     "validation_partitions", "bookkeeping", "training_rows", "column_stats",
     "preprocess", "fold_products", "fold_all_classes", "fold_entries",
-    "fold_train_stats", "OracleError",
+    "fold_train_stats", "leaky_global_fold", "leaky_lindgren_fold", "OracleError",
 ]
 
 
@@ -242,3 +246,51 @@ def fold_train_stats(X, Y, fold_id, p: int, ddof: int = 1):
     mx, sx, _ = column_stats(np.asarray(X, dtype=np.float64)[T], ddof)
     my, sy, _ = column_stats(np.asarray(Y, dtype=np.float64)[T], ddof)
     return mx, sx, my, sy
+
+
+# ---------------------------------------------------------------------------
+# leaky comparison modes (Section 4.1): NOT training-partition preprocessing
+# ---------------------------------------------------------------------------
+
+def leaky_global_fold(X, Y, fold_id, p: int, cx: int, sx: int, cy: int, sy: int, ddof: int = 1):
+    """Fold p's training products when X and Y are centred and/or scaled once
+    with the statistics of ALL rows (the "centred and scaled over the entire
+    data set initially" approach the paper's introduction warns about): the
+    validation rows leak into the preprocessing.  Centering and scaling of X
+    and of Y are independent here (Lemma 9's equivalence needs statistics of
+    the same rows as the product).  A column constant over all rows gets
+    deviation 1 and a centred column of exact zeros, as in ``column_stats``."""
+    validation_partitions(fold_id)
+    if ddof not in (0, 1):
+        raise OracleError("ddof must be 0 or 1")
+    X = np.asarray(X, dtype=np.float64)
+    Y = np.asarray(Y, dtype=np.float64)
+    if (sx or sy) and X.shape[0] - ddof < 1:
+        raise OracleError("scaling needs N - ddof >= 1")
+    Xg = preprocess(X, bool(cx), bool(sx), ddof)
+    Yg = preprocess(Y, bool(cy), bool(sy), ddof)
+    T = training_rows(fold_id, p)
+    return Xg[T].T @ Xg[T], Xg[T].T @ Yg[T]
+
+
+def leaky_lindgren_fold(X, Y, fold_id, p: int):
+    """Lindgren et al.'s centred training products for fold p, their
+    Equation (20) as restated in the proof of Lemma 11:
+        (X^T X)_ij - (X_V^T X_V)_ij - xbar_i sum_V X_nj - xbar_j sum_V X_ni
+        + (N / P) xbar_i xbar_j
+    with xbar the mean over ALL rows (leaks, Lemma 11).  X^T Y is read the same
+    way with Y's mean and validation sums on the Y side."""
+    V = validation_partitions(fold_id)
+    X = np.asarray(X, dtype=np.float64)
+    Y = np.asarray(Y, dtype=np.float64)
+    N, P = X.shape[0], len(V)
+    v = np.asarray(V[p], dtype=np.int64)
+    xbar = X.sum(axis=0) / N
+    ybar = Y.sum(axis=0) / N if Y.shape[1] else np.zeros(0)
+    sx_v = X[v].sum(axis=0)
+    sy_v = Y[v].sum(axis=0)
+    xtx = (X.T @ X - X[v].T @ X[v] - np.outer(xbar, sx_v) - np.outer(sx_v, xbar)
+           + (N / P) * np.outer(xbar, xbar))
+    xty = (X.T @ Y - X[v].T @ Y[v] - np.outer(xbar, sy_v) - np.outer(sx_v, ybar)
+           + (N / P) * np.outer(xbar, ybar))
+    return xtx, xty

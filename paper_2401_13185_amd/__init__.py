@@ -16,7 +16,7 @@ import re
 __all__ = [
     "CVGramError", "lib_path", "load", "exported_symbols", "header_symbols",
     "cvgram_create", "cvgram_num_folds", "cvgram_partition", "cvgram_fold",
-    "cvgram_fold_combo", "cvgram_folds_all", "cvgram_fold_stats", "cvgram_set_stream",
+    "cvgram_fold_combo", "cvgram_fold_leaky", "LEAK_KINDS", "cvgram_folds_all", "cvgram_fold_stats", "cvgram_set_stream",
     "cvgram_destroy", "cvgram_status_string", "cvgram_last_error_message", "cvgram_version",
     "cvgram_set_stage_timing", "cvgram_stage_times", "cvgram_trim_cache",
     "cvgram_batch_create", "cvgram_batch_run", "cvgram_batch_run_eager",
@@ -28,6 +28,8 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 _ROOT = os.path.dirname(_PKG)
 HEADER = os.path.join(_ROOT, "include", "cvgram.h")
 MODES = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+# leakage comparison kinds of cvgram_fold_leaky (never training-partition results)
+LEAK_KINDS = {"global": 1, "lindgren": 2}
 XTX_CLASSES = 4
 XTY_CLASSES = 8
 
@@ -59,6 +61,7 @@ _SIGS = {
     "cvgram_partition": (_int, [_vp, _vp, _vp]),
     "cvgram_fold": (_int, [_vp, _i32, _vp, _vp]),
     "cvgram_fold_combo": (_int, [_vp, _i32, _int, _int, _int, _int, _vp, _vp]),
+    "cvgram_fold_leaky": (_int, [_vp, _i32, _int, _vp, _vp]),
     "cvgram_folds_all": (_int, [_vp, _i32, _i32, _vp, _vp]),
     "cvgram_fold_stats": (_int, [_vp, _i32, _vp, _vp, _vp, _vp]),
     "cvgram_set_stream": (_int, [_vp, _vp]),
@@ -238,6 +241,14 @@ def cvgram_fold_combo(h: Handle, p: int, center_x, scale_x, center_y, scale_y, o
     out_XtX, out_XtY, xp, yp = _outs(h, out_XtX, out_XtY)
     _check(load().cvgram_fold_combo(h.ptr, int(p), int(center_x), int(scale_x), int(center_y),
                                     int(scale_y), xp, yp))
+    return out_XtX, out_XtY
+
+
+def cvgram_fold_leaky(h: Handle, p: int, kind: str, out_XtX=None, out_XtY=None):
+    """Leakage comparison for fold p (kind "global" or "lindgren"); see
+    include/cvgram.h.  Not training-partition preprocessing."""
+    out_XtX, out_XtY, xp, yp = _outs(h, out_XtX, out_XtY)
+    _check(load().cvgram_fold_leaky(h.ptr, int(p), LEAK_KINDS[kind], xp, yp))
     return out_XtX, out_XtY
 
 

@@ -946,6 +946,29 @@ cvgram_status cvgram_fold_combo(cvgram_t h, int32_t p, int center_x, int scale_x
   return correct_single(h, p, p + 1, od);
 }
 
+cvgram_status cvgram_fold_leaky(cvgram_t h, int32_t p, int kind, void* out_XtX, void* out_XtY) {
+  if (!h) return fail(CVGRAM_EINVAL, "NULL handle");
+  const ProbPlan& pp = h->b.pp[0];
+  if (p < 0 || p >= pp.P) return fail(CVGRAM_ERANGE, "fold index out of range");
+  if (kind != CVGRAM_LEAK_GLOBAL && kind != CVGRAM_LEAK_LINDGREN)
+    return fail(CVGRAM_EINVAL, "unknown leakage comparison kind");
+  if (kind == CVGRAM_LEAK_LINDGREN && !(h->cx && !h->sx && h->cy && !h->sy))
+    return fail(CVGRAM_EINVAL,
+                "the Lindgren comparison needs the handle's combination center_x = center_y = 1, "
+                "no scaling");
+  OutDesc od;
+  std::memset(&od, 0, sizeof(od));
+  od.xx[0] = out_XtX;
+  if (pp.M > 0) od.xy[0] = out_XtY;
+  od.p_begin = p;
+  od.leak = kind;
+  od.lcx = h->cx;
+  od.lsx = h->sx;
+  od.lcy = h->cy;
+  od.lsy = h->sy;
+  return correct_single(h, p, p + 1, od);
+}
+
 cvgram_status cvgram_fold(cvgram_t h, int32_t p, void* out_XtX, void* out_XtY) {
   if (!h) return fail(CVGRAM_EINVAL, "NULL handle");
   return cvgram_fold_combo(h, p, h->cx, h->sx, h->cy, h->sy, out_XtX, out_XtY);

@@ -85,6 +85,9 @@ __device__ void correct_tile(const ProbDesc& pd, const OutDesc& od, int32_t f, i
   __shared__ double rc[TS], ra[TS], rmu[TS], rsd[TS];
   __shared__ double cc[TS], ca[TS], cmu[TS], csd[TS];
   __shared__ uint8_t rcs[TS], ccs[TS];
+  // leakage comparison: all-row shifted sums, deviations, constant flags
+  __shared__ double rS[TS], cS[TS], rsg[TS], csg[TS];
+  __shared__ uint8_t rgc[TS], cgc[TS];
 
   const int32_t p = od.p_begin + f;
   const bool is_xy = tile >= pd.n_ctiles_xx;
@@ -123,6 +126,26 @@ __device__ void correct_tile(const ProbDesc& pd, const OutDesc& od, int32_t f, i
       cmu[u] = tr_mean[pw + z];
       csd[u] = tr_std[pw + z];
       ccs[u] = tr_const[pw + z];
+    }
+  }
+  if (od.leak) {
+    // statistics of all N rows from the fold totals (Lemma 12 on shifted sums)
+    const CVG_GLOBAL double* tot = gmem((const double*)pd.tot);
+    const double Nd = (double)pd.N;
+    auto all_rows = [&](int64_t z, double& S, double& sd, uint8_t& cst) {
+      S = tot[0 * W + z];
+      const double var = (tot[1 * W + z] - S * (S / Nd)) / (Nd - (double)pd.ddof);
+      cst = tot[2 * W + z] == tot[5 * W + z] ? 1 : 0;
+      sd = sqrt(var > 0.0 ? var : 0.0);
+      if (cst || sd == 0.0) sd = 1.0;
+    };
+    if (t < TS) {
+      const int64_t i = (int64_t)bi * TS + t;
+      if (i < K) all_rows(i, rS[t], rsg[t], rgc[t]);
+    } else if (t < 2 * TS) {
+      const int u = t - TS;
+      const int64_t j = (int64_t)bj * TS + u;
+      if (j < ncols) all_rows(coff + j, cS[u], csg[u], cgc[u]);
     }
   }
   __syncthreads();
@@ -164,7 +187,7 @@ __device__ void correct_tile(const ProbDesc& pd, const OutDesc& od, int32_t f, i
       pd.fused ? nullptr
                : gmem((const double*)pd.slabs) + (int64_t)gmem(pd.slab_begin)[p] * K * W;
 
-  double raw[kRowsPerThread], cen[kRowsPerThread];
+  double raw[kRowsPerThread], cen[kRowsPerThread], gT[kRowsPerThread];
   bool ok[kRowsPerThread];
 #pragma unroll
   for (int r = 0; r < kRowsPerThread; ++r) {
@@ -174,11 +197,54 @@ __device__ void correct_tile(const ProbDesc& pd, const OutDesc& od, int32_t f, i
     ok[r] = i < K && j < ncols && (!diag || il <= jl);
     raw[r] = 0.0;
     cen[r] = 0.0;
+    gT[r] = 0.0;
     if (!ok[r]) continue;
     const int64_t e = i * W + coff + j;
     const double g = G[e] - (pd.fused ? gp[r] : gp_slab[e]);
+    gT[r] = g;
     raw[r] = g + (rc[il] * ca[jl] + ra[il] * cc[jl]) + NT * (rc[il] * cc[jl]);
     cen[r] = (rcs[il] || ccs[jl]) ? 0.0 : g - NT * (rmu[il] * cmu[jl]);
+  }
+
+  if (od.leak) {
+    // Leakage comparison (Section 4.1), one output pair.  Global: training
+    // rows centred by a = all-row mean (or 0) and scaled by all-row
+    // deviations: sum_T (z_i + al_i)(w_j + be_j) with al = c - a (shifted z).
+    // Lindgren et al. (Lemma 11's Equation (20)): raw products minus
+    // xbar_i (validation sum)_j + xbar_j (validation sum)_i - (N/P) xbar_i xbar_j.
+    const double Nd = (double)pd.N, Pd = (double)pd.P;
+    OutT* out = (OutT*)(is_xy ? od.xy[0] : od.xx[0]);
+    if (!out) return;
+    CVG_GLOBAL OutT* o = gmem(out);
+    const bool ci = od.lcx, cj = is_xy ? od.lcy : od.lcx;
+    const bool si = od.lsx, sj = is_xy ? od.lsy : od.lsx;
+#pragma unroll
+    for (int r = 0; r < kRowsPerThread; ++r) {
+      if (!ok[r]) continue;
+      const int il = ty + 8 * r, jl = tx;
+      const int64_t i = (int64_t)bi * TS + il;
+      const int64_t j = (int64_t)bj * TS + jl;
+      double v;
+      if (od.leak == 2) {
+        const double xi = rc[il] + rS[il] / Nd, xj = cc[jl] + cS[jl] / Nd;
+        const double vi = (rS[il] - ra[il]) + rc[il] * (Nd - NT);
+        const double vj = (cS[jl] - ca[jl]) + cc[jl] * (Nd - NT);
+        v = raw[r] - xi * vj - xj * vi + (Nd / Pd) * (xi * xj);
+      } else {
+        const double al = ci ? -rS[il] / Nd : rc[il];
+        const double be = cj ? -cS[jl] / Nd : cc[jl];
+        v = gT[r] + (al * ca[jl] + ra[il] * be) + NT * (al * be);
+        if ((ci && rgc[il]) || (cj && cgc[jl])) v = 0.0;
+        if (si || sj) v = v / ((si ? rsg[il] : 1.0) * (sj ? csg[jl] : 1.0));
+      }
+      if (is_xy) {
+        o[i * M + j] = (OutT)v;
+      } else {
+        o[i * K + j] = (OutT)v;
+        if (!diag || il != jl) o[j * K + i] = (OutT)v;
+      }
+    }
+    return;
   }
 
   if (!is_xy) {

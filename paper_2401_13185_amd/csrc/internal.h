@@ -122,6 +122,11 @@ struct OutDesc {
   int64_t fold_stride_xx;
   int64_t fold_stride_xy;
   int32_t p_begin;
+  // leakage comparison (0: off).  1: the combination (lcx, lsx, lcy, lsy)
+  // with statistics of all rows; 2: Lindgren et al.'s centred products.
+  // One output pair, in xx[0] and xy[0].
+  int32_t leak;
+  int32_t lcx, lsx, lcy, lsy;
 };
 
 // ---------------------------------------------------------------------------

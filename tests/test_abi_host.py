@@ -70,6 +70,7 @@ def test_null_handle_calls():
     assert lib.cvgram_num_folds(None, ctypes.byref(P)) == 1
     assert lib.cvgram_fold(None, 0, None, None) == 1
     assert lib.cvgram_fold_combo(None, 0, 0, 0, 0, 0, None, None) == 1
+    assert lib.cvgram_fold_leaky(None, 0, 1, None, None) == 1
     assert lib.cvgram_folds_all(None, 0, 1, None, None) == 1
     assert lib.cvgram_fold_stats(None, 0, None, None, None, None) == 1
     assert lib.cvgram_partition(None, None, None) == 1

@@ -356,3 +356,77 @@ def test_fold_entries_match_full_products():
         ex, ey = O.fold_entries(X, Y, fold, 2, *combo, 1, pairs_xx, pairs_xy)
         assert _close(ex, [xx[i, j] for i, j in pairs_xx], 1e-12)
         assert _close(ey, [xy[i, j] for i, j in pairs_xy], 1e-12)
+
+
+# ---------------------------------------------------------------------------
+# leaky comparison modes (Section 4.1)
+# ---------------------------------------------------------------------------
+
+def test_leaky_lindgren_matches_lemma11_closed_form():
+    """The oracle's Eq. (20) form equals Lemma 11's simplified form
+    (X_T^T X_T)_ij - N xbar_i xbar_j (2 - 1/P) + |T| xbar_i xbarT_j
+    + |T| xbar_j xbarT_i on uneven folds, and both leak."""
+    rng = np.random.default_rng(17)
+    N, K, M, P = 37, 4, 2, 5
+    X = rng.normal(3.0, 1.5, size=(N, K))
+    Y = rng.normal(-2.0, 0.7, size=(N, M))
+    fold = rng.integers(0, P, size=N).astype(np.int32)
+    fold[:P] = np.arange(P)
+    for p in range(P):
+        lx, ly = O.leaky_lindgren_fold(X, Y, fold, p)
+        T = fold != p
+        nt = int(T.sum())
+        xbar, ybar = X.mean(axis=0), Y.mean(axis=0)
+        xbt, ybt = X[T].mean(axis=0), Y[T].mean(axis=0)
+        lemma_xx = (X[T].T @ X[T] - N * np.outer(xbar, xbar) * (2 - 1 / P)
+                    + nt * np.outer(xbar, xbt) + nt * np.outer(xbt, xbar))
+        lemma_xy = (X[T].T @ Y[T] - N * np.outer(xbar, ybar) * (2 - 1 / P)
+                    + nt * np.outer(xbar, ybt) + nt * np.outer(xbt, ybar))
+        assert _close(lx, lemma_xx) and _close(ly, lemma_xy)
+        ours = O.fold_products(X, Y, fold, p, 1, 0, 1, 0, ddof=1)
+        assert not _close(lx, ours[0], 1e-6)
+
+
+def test_leaky_global_parallel_axis_identity():
+    """Centering the training rows with the all-row mean xbar instead of
+    their own mean xbarT adds |T| (xbarT - xbar)(xbarT - xbar)^T (and the
+    matching cross term for X^T Y): the textbook parallel-axis identity.
+    Scaling with all-row deviations divides by their outer product."""
+    rng = np.random.default_rng(23)
+    N, K, M, P = 29, 3, 2, 4
+    X = rng.normal(1.0, 2.0, size=(N, K))
+    Y = rng.normal(0.5, 1.0, size=(N, M))
+    fold = np.arange(N, dtype=np.int32) % P
+    for p in range(P):
+        T = fold != p
+        nt = int(T.sum())
+        dx = X[T].mean(axis=0) - X.mean(axis=0)
+        dy = Y[T].mean(axis=0) - Y.mean(axis=0)
+        gx, gy = O.leaky_global_fold(X, Y, fold, p, 1, 0, 1, 0, ddof=1)
+        tx, ty = O.fold_products(X, Y, fold, p, 1, 0, 1, 0, ddof=1)
+        assert _close(gx, tx + nt * np.outer(dx, dx))
+        assert _close(gy, ty + nt * np.outer(dx, dy))
+        # X centred only: (X_T - xbar)^T Y_T = X_T^T Y_T - xbar sumT(Y)
+        gx1, gy1 = O.leaky_global_fold(X, Y, fold, p, 1, 0, 0, 0, ddof=1)
+        assert _close(gy1, X[T].T @ Y[T] - np.outer(X.mean(axis=0), Y[T].sum(axis=0)))
+        # scaled with all-row deviations
+        sx = X.std(axis=0, ddof=1)
+        sy = Y.std(axis=0, ddof=1)
+        gxs, gys = O.leaky_global_fold(X, Y, fold, p, 1, 1, 1, 1, ddof=1)
+        assert _close(gxs, gx / np.outer(sx, sx)) and _close(gys, gy / np.outer(sx, sy))
+        assert not _close(gxs, O.fold_products(X, Y, fold, p, 1, 1, 1, 1, ddof=1)[0], 1e-6)
+
+
+def test_leaky_global_constant_column():
+    """A column constant over all rows: deviation 1, centred column exactly 0."""
+    rng = np.random.default_rng(3)
+    N, P = 20, 4
+    X = rng.normal(size=(N, 3))
+    X[:, 1] = 7.25
+    Y = rng.normal(size=(N, 1))
+    fold = np.arange(N, dtype=np.int32) % P
+    gx, gy = O.leaky_global_fold(X, Y, fold, 0, 1, 1, 1, 1, ddof=1)
+    assert np.all(gx[1] == 0.0) and np.all(gx[:, 1] == 0.0) and np.all(gy[1] == 0.0)
+    gx, _ = O.leaky_global_fold(X, Y, fold, 0, 0, 1, 0, 0, ddof=1)
+    T = fold != 0
+    assert _close(gx[1, 1], (X[T, 1] ** 2).sum())
