@@ -55,7 +55,8 @@ typedef enum {
                                (Definition 6, generalised to ddof)           */
   CVGRAM_ENOMEM = 4,        /* device or pinned-host allocation failed       */
   CVGRAM_EDEVICE = 5,       /* a HIP runtime call or kernel launch failed    */
-  CVGRAM_ERANGE = 6         /* fold index out of range                       */
+  CVGRAM_ERANGE = 6,        /* fold index out of range                       */
+  CVGRAM_ESINGULAR = 7      /* cvgram_ridge: a system not positive definite  */
 } cvgram_status;
 
 /* element type of X and Y */
@@ -165,6 +166,25 @@ cvgram_status cvgram_fold(cvgram_t h, int32_t p, void* out_XtX, void* out_XtY);
  * CVGRAM_ERANGE for a fold out of range, CVGRAM_EINVAL for an unknown kind. */
 typedef enum { CVGRAM_LEAK_GLOBAL = 1, CVGRAM_LEAK_LINDGREN = 2 } cvgram_leak;
 cvgram_status cvgram_fold_leaky(cvgram_t h, int32_t p, int kind, void* out_XtX, void* out_XtY);
+
+/* Per-fold ridge regression on the device -- a consumer of the training
+ * products (the paper names RR and OLS among their models, Section 1): for
+ * folds [p0, p1) and the n_lambda >= 1 penalties lambdas[] (HOST array,
+ * each >= 0; 0 is ordinary least squares) writes
+ *     B[f][l] = (X^T X_T + lambda_l I)^{-1} X^T Y_T
+ * for the handle's combination of centering and scaling, into out_B
+ * (device, FP64, [p1 - p0][n_lambda][K][M], row-major).  The products are
+ * formed in FP64 from the handle's Gram (mixed modes: from their Gram) and
+ * solved by a blocked Cholesky factorisation and two triangular solves, all
+ * on the device.  Needs M > 0.  Waits on the handle's stream for the
+ * positive-definiteness flags: CVGRAM_ESINGULAR when some X^T X_T + lambda I
+ * is not positive definite (its B is NaN; the others are written).
+ * Errors: CVGRAM_ERANGE for a bad fold range, CVGRAM_EINVAL for M == 0, a
+ * negative or non-finite lambda, n_lambda < 1 or NULL pointers,
+ * CVGRAM_ENOTSCALABLE when the combination scales and the partitioning is
+ * not scalable, CVGRAM_ENOMEM for the workspace. */
+cvgram_status cvgram_ridge(cvgram_t h, int32_t p0, int32_t p1, const double* lambdas,
+                           int32_t n_lambda, double* out_B);
 
 /* As cvgram_fold, for any of the 16 combinations (flags 0 or 1).  Returns
  * CVGRAM_ENOTSCALABLE if a scale flag is set on a partitioning that is not

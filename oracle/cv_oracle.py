@@ -46,7 +46,7 @@ __all__ = [
     "COMBOS", "xtx_class", "xty_class", "XTX_CLASS_COMBO", "XTY_CLASS_COMBO",
     "validation_partitions", "bookkeeping", "training_rows", "column_stats",
     "preprocess", "fold_products", "fold_all_classes", "fold_entries",
-    "fold_train_stats", "leaky_global_fold", "leaky_lindgren_fold", "OracleError",
+    "fold_train_stats", "leaky_global_fold", "leaky_lindgren_fold", "ridge_fold", "OracleError",
 ]
 
 
@@ -294,3 +294,15 @@ def leaky_lindgren_fold(X, Y, fold_id, p: int):
     xty = (X.T @ Y - X[v].T @ Y[v] - np.outer(xbar, sy_v) - np.outer(sx_v, ybar)
            + (N / P) * np.outer(xbar, ybar))
     return xtx, xty
+
+
+# ---------------------------------------------------------------------------
+# a consumer of the products: ridge regression per fold (Section 1 names RR
+# and OLS among the models that use X^T X and X^T Y)
+# ---------------------------------------------------------------------------
+
+def ridge_fold(X, Y, fold_id, p: int, cx: int, sx: int, cy: int, sy: int, ddof: int, lam: float):
+    """B = (X^T X_T + lam I)^{-1} X^T Y_T for fold p and one combination, from
+    the definitional products (``fold_products``) and a dense solve."""
+    xtx, xty = fold_products(X, Y, fold_id, p, cx, sx, cy, sy, ddof)
+    return np.linalg.solve(xtx + lam * np.eye(xtx.shape[0]), xty)

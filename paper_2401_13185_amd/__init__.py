@@ -16,7 +16,7 @@ import re
 __all__ = [
     "CVGramError", "lib_path", "load", "exported_symbols", "header_symbols",
     "cvgram_create", "cvgram_num_folds", "cvgram_partition", "cvgram_fold",
-    "cvgram_fold_combo", "cvgram_fold_leaky", "LEAK_KINDS", "cvgram_folds_all", "cvgram_fold_stats", "cvgram_set_stream",
+    "cvgram_fold_combo", "cvgram_fold_leaky", "LEAK_KINDS", "cvgram_ridge", "cvgram_folds_all", "cvgram_fold_stats", "cvgram_set_stream",
     "cvgram_destroy", "cvgram_status_string", "cvgram_last_error_message", "cvgram_version",
     "cvgram_set_stage_timing", "cvgram_stage_times", "cvgram_trim_cache",
     "cvgram_batch_create", "cvgram_batch_run", "cvgram_batch_run_eager",
@@ -62,6 +62,7 @@ _SIGS = {
     "cvgram_fold": (_int, [_vp, _i32, _vp, _vp]),
     "cvgram_fold_combo": (_int, [_vp, _i32, _int, _int, _int, _int, _vp, _vp]),
     "cvgram_fold_leaky": (_int, [_vp, _i32, _int, _vp, _vp]),
+    "cvgram_ridge": (_int, [_vp, _i32, _i32, ctypes.POINTER(ctypes.c_double), _i32, _vp]),
     "cvgram_folds_all": (_int, [_vp, _i32, _i32, _vp, _vp]),
     "cvgram_fold_stats": (_int, [_vp, _i32, _vp, _vp, _vp, _vp]),
     "cvgram_set_stream": (_int, [_vp, _vp]),
@@ -250,6 +251,20 @@ def cvgram_fold_leaky(h: Handle, p: int, kind: str, out_XtX=None, out_XtY=None):
     out_XtX, out_XtY, xp, yp = _outs(h, out_XtX, out_XtY)
     _check(load().cvgram_fold_leaky(h.ptr, int(p), LEAK_KINDS[kind], xp, yp))
     return out_XtX, out_XtY
+
+
+def cvgram_ridge(h: Handle, p_begin: int, p_end: int, lambdas, out_B=None):
+    """Ridge coefficients B[f][l] = (XtX_T + lambda_l I)^{-1} XtY_T for folds
+    [p_begin, p_end) and the given penalties (FP64, on the device)."""
+    torch = _torch()
+    lam = [float(v) for v in lambdas]
+    n = int(p_end) - int(p_begin)
+    if out_B is None:
+        out_B = torch.empty(max(n, 0), len(lam), h.K, h.M, dtype=torch.float64, device=h.device)
+    bp = _ptr(out_B, "out_B", torch.float64, max(n, 0) * len(lam) * h.K * h.M)
+    arr = (ctypes.c_double * max(1, len(lam)))(*lam)
+    _check(load().cvgram_ridge(h.ptr, int(p_begin), int(p_end), arr, len(lam), bp))
+    return out_B
 
 
 def cvgram_folds_all(h: Handle, p_begin: int, p_end: int, out_XtX=None, out_XtY=None):

@@ -969,6 +969,66 @@ cvgram_status cvgram_fold_leaky(cvgram_t h, int32_t p, int kind, void* out_XtX, 
   return correct_single(h, p, p + 1, od);
 }
 
+cvgram_status cvgram_ridge(cvgram_t h, int32_t p0, int32_t p1, const double* lambdas,
+                           int32_t n_lambda, double* out_B) {
+  if (!h) return fail(CVGRAM_EINVAL, "NULL handle");
+  const ProbPlan& pp = h->b.pp[0];
+  if (p0 < 0 || p1 > pp.P || p0 >= p1) return fail(CVGRAM_ERANGE, "fold range out of range");
+  if (pp.M <= 0) return fail(CVGRAM_EINVAL, "ridge regression needs M > 0");
+  if (!lambdas || !out_B || n_lambda < 1) return fail(CVGRAM_EINVAL, "lambdas / out_B / n_lambda");
+  for (int32_t l = 0; l < n_lambda; ++l)
+    if (!(lambdas[l] >= 0.0) || !std::isfinite(lambdas[l]))
+      return fail(CVGRAM_EINVAL, "lambda must be finite and >= 0");
+  if ((h->sx || h->sy) && !pp.scalable)
+    return fail(CVGRAM_ENOTSCALABLE, "partitioning is not scalable for this ddof");
+  const int32_t nf = p1 - p0;
+  const int64_t K = pp.K, M = pp.M, nmat = (int64_t)nf * n_lambda;
+  const int64_t nblk = (K + 31) / 32;
+  hipStream_t s = h->b.stream;
+  Owned ws;
+  ws.device = h->b.device;
+  cvgram_status st = CVGRAM_OK;
+  try {
+    double* xtx = (double*)ws.dev((size_t)nf * K * K * 8);
+    double* xty = (double*)ws.dev((size_t)nf * K * M * 8);
+    double* A = (double*)ws.dev((size_t)nmat * K * K * 8);
+    double* Linv = (double*)ws.dev((size_t)nmat * nblk * 32 * 32 * 8);
+    int32_t* flags = (int32_t*)ws.dev((size_t)nmat * 4);
+    double* dl = (double*)ws.dev((size_t)n_lambda * 8);
+    int32_t* hflags = (int32_t*)ws.pinned((size_t)nmat * 4);
+    double* hl = (double*)ws.pinned((size_t)n_lambda * 8);
+    std::memcpy(hl, lambdas, (size_t)n_lambda * 8);
+    CVG_HIP(hipMemcpyAsync(dl, hl, (size_t)n_lambda * 8, hipMemcpyHostToDevice, s));
+    launch_fill_i32(flags, nmat, 0, s);
+    // the handle's combination of folds [p0, p1) in FP64, fold-major
+    OutDesc od;
+    std::memset(&od, 0, sizeof(od));
+    od.xx[2 * h->cx + h->sx] = xtx;
+    od.xy[4 * (h->cx | h->cy) + 2 * h->sx + h->sy] = xty;
+    od.fold_stride_xx = K * K;
+    od.fold_stride_xy = K * M;
+    od.p_begin = p0;
+    const ProbDesc& d = h->b.h_pd[0];
+    launch_correct_single(h->b.d_pd, 0, d.n_ctiles_xx + d.n_ctiles_xy, od, nf, true, s);
+    ridge_solve(xtx, xty, dl, nf, n_lambda, K, M, A, out_B, Linv, flags, s);
+    CVG_HIP(hipMemcpyAsync(hflags, flags, (size_t)nmat * 4, hipMemcpyDeviceToHost, s));
+    CVG_HIP(hipStreamSynchronize(s));
+    for (int64_t m = 0; m < nmat; ++m)
+      if (hflags[m]) {
+        st = fail(CVGRAM_ESINGULAR, "fold " + std::to_string(p0 + m / n_lambda) + ", lambda " +
+                                        std::to_string(lambdas[m % n_lambda]) +
+                                        ": X^T X_T + lambda I is not positive definite");
+        break;
+      }
+  } catch (const Fail& f) {
+    (void)hipStreamSynchronize(s);
+    ws.release();
+    return f.st;
+  }
+  ws.release();
+  return st;
+}
+
 cvgram_status cvgram_fold(cvgram_t h, int32_t p, void* out_XtX, void* out_XtY) {
   if (!h) return fail(CVGRAM_EINVAL, "NULL handle");
   return cvgram_fold_combo(h, p, h->cx, h->sx, h->cy, h->sy, out_XtX, out_XtY);
@@ -1254,6 +1314,7 @@ const char* cvgram_status_string(cvgram_status s) {
     case CVGRAM_ENOMEM: return "out of memory";
     case CVGRAM_EDEVICE: return "HIP runtime error";
     case CVGRAM_ERANGE: return "fold index out of range";
+    case CVGRAM_ESINGULAR: return "a regularised system is not positive definite";
   }
   return "unknown status";
 }

@@ -28,7 +28,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_status_strings_and_version():
     assert cv.cvgram_version() >= 100
-    for st in range(7):
+    for st in range(8):
         assert cv.cvgram_status_string(st)
     assert cv.cvgram_status_string(99) == "unknown status"
 
@@ -71,6 +71,7 @@ def test_null_handle_calls():
     assert lib.cvgram_fold(None, 0, None, None) == 1
     assert lib.cvgram_fold_combo(None, 0, 0, 0, 0, 0, None, None) == 1
     assert lib.cvgram_fold_leaky(None, 0, 1, None, None) == 1
+    assert lib.cvgram_ridge(None, 0, 1, None, 1, None) == 1
     assert lib.cvgram_folds_all(None, 0, 1, None, None) == 1
     assert lib.cvgram_fold_stats(None, 0, None, None, None, None) == 1
     assert lib.cvgram_partition(None, None, None) == 1

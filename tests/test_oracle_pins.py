@@ -430,3 +430,29 @@ def test_leaky_global_constant_column():
     gx, _ = O.leaky_global_fold(X, Y, fold, 0, 0, 1, 0, 0, ddof=1)
     T = fold != 0
     assert _close(gx[1, 1], (X[T, 1] ** 2).sum())
+
+
+# ---------------------------------------------------------------------------
+# ridge regression consumer
+# ---------------------------------------------------------------------------
+
+def test_ridge_fold_equals_augmented_least_squares():
+    """Ridge is least squares on the training rows stacked over sqrt(lam) I
+    (a textbook identity), solved here by the SVD-based lstsq on the
+    preprocessed training data, not through the products; lam = 0 is OLS."""
+    rng = np.random.default_rng(31)
+    N, K, M, P = 60, 5, 2, 4
+    X = rng.normal(2.0, 1.0, size=(N, K))
+    Y = X @ rng.normal(size=(K, M)) + rng.normal(0, 0.3, size=(N, M))
+    fold = np.arange(N, dtype=np.int32) % P
+    for combo in [(0, 0, 0, 0), (1, 0, 1, 0), (1, 1, 1, 1), (0, 1, 0, 1)]:
+        for p in range(P):
+            T = O.training_rows(fold, p)
+            Xt = O.preprocess(X[T], bool(combo[0]), bool(combo[1]), 1)
+            Yt = O.preprocess(Y[T], bool(combo[2]), bool(combo[3]), 1)
+            for lam in (0.0, 0.5, 7.0):
+                B = O.ridge_fold(X, Y, fold, p, *combo, 1, lam)
+                Xa = np.vstack([Xt, np.sqrt(lam) * np.eye(K)])
+                Ya = np.vstack([Yt, np.zeros((K, M))])
+                ref = np.linalg.lstsq(Xa, Ya, rcond=None)[0]
+                assert _close(B, ref, 1e-9), (combo, p, lam)
