@@ -266,6 +266,7 @@ struct ProbPlan {
   int32_t n_franges = 0;
   int32_t n_ctiles_xx = 0, n_ctiles_xy = 0;
   int32_t* d_perm = nullptr;
+  double* d_pivot = nullptr;  // computed at bookkeeping time (single problems)
 };
 
 // the device pipeline of a batch (a single handle is a batch of one)
@@ -307,6 +308,7 @@ struct Batch {
   int64_t n_corr_items = 0;
   bool timing = false;
   hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t ev_wait = nullptr;   // the host's wait for the label counts
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
 
@@ -320,6 +322,8 @@ struct Batch {
         (void)hipEventDestroy(e);
         e = nullptr;
       }
+    if (ev_wait) (void)hipEventDestroy(ev_wait);
+    ev_wait = nullptr;
     mem.release();
   }
 };
@@ -349,16 +353,23 @@ cvgram_status bookkeeping(Batch& b) {
   int32_t* perm_block = (int32_t*)b.mem.dev((size_t)sumN * sizeof(int32_t));
   Owned scratch;
   scratch.device = b.device;
-  int32_t* info = (int32_t*)scratch.dev(64 * sizeof(int32_t));
+  // info[0] min label, info[1] max label, info[2 ..) counts of labels below
+  // kCountLabels, then flags: one block, one initialising launch, one copy.
+  // The block stays with the batch: the sort's scan reads the counts after
+  // this function returns.
+  constexpr int64_t kInfo = 2 + kCountLabels + 62;
+  int32_t* info = (int32_t*)b.mem.dev(kInfo * sizeof(int32_t));
+  int32_t* counts = info + 2;
+  int32_t* flag = info + 2 + kCountLabels;
   // buffers of the sort stay with the batch: the sort still runs after this
   // function returns (only the validation data is waited for)
   int32_t* keys = (int32_t*)b.mem.dev((size_t)2 * maxN * sizeof(int32_t));
   int32_t* perm_tmp = (int32_t*)b.mem.dev((size_t)maxN * sizeof(int32_t));
   int32_t* hist = (int32_t*)b.mem.dev((size_t)radix_hist_entries(maxN) * sizeof(int32_t));
   int64_t* offs = (int64_t*)b.mem.dev((size_t)(maxN + 1) * sizeof(int64_t));
-  int32_t* counts = (int32_t*)scratch.dev(kCountLabels * sizeof(int32_t));
-  int32_t* hbuf = (int32_t*)scratch.pinned((64 + kCountLabels) * sizeof(int32_t));
-  int32_t* hcounts = hbuf + 64;
+  int32_t* hbuf = (int32_t*)scratch.pinned(kInfo * sizeof(int32_t));
+  int32_t* hcounts = hbuf + 2;
+  if (!b.ev_wait) CVG_HIP(hipEventCreateWithFlags(&b.ev_wait, hipEventDisableTiming));
   cvgram_status st = CVGRAM_OK;
   int64_t at = 0;
   try {
@@ -367,15 +378,19 @@ cvgram_status bookkeeping(Batch& b) {
       const std::string tag = b.pp.size() > 1 ? "problem " + std::to_string(i) + ": " : "";
       p.d_perm = perm_block + at;
       at += p.N;
-      launch_fill_i32(info, 1, INT32_MAX, s);
-      launch_fill_i32(info + 1, 1, INT32_MIN, s);
-      launch_fill_i32(info + 2, 62, 0, s);
-      launch_fill_i32(counts, kCountLabels, 0, s);
-      launch_label_count(p.fold, p.N, info, counts, s);
-      CVG_HIP(hipMemcpyAsync(hbuf, info, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-      CVG_HIP(hipMemcpyAsync(hcounts, counts, kCountLabels * sizeof(int32_t),
+      launch_count_init(info, kInfo, s);
+      launch_label_count(p.fold, p.N, info, counts, hist, s);
+      CVG_HIP(hipMemcpyAsync(hbuf, info, (2 + kCountLabels) * sizeof(int32_t),
                              hipMemcpyDeviceToHost, s));
-      CVG_HIP(hipStreamSynchronize(s));
+      CVG_HIP(hipEventRecord(b.ev_wait, s));
+      if (!b.batched) {
+        // the pivots need only X and Y: they run while the host waits for the
+        // counts and plans (a batch computes them inside its graph instead)
+        p.d_pivot = (double*)b.mem.dev((size_t)p.W * sizeof(double));
+        launch_pivot_direct(b.dtype, b.mode != CVGRAM_MODE_FP64, p.X, p.Y, p.N, p.K, p.M,
+                            p.d_pivot, s);
+      }
+      CVG_HIP(hipEventSynchronize(b.ev_wait));
       if (hbuf[0] < 0) {
         st = fail(CVGRAM_EFOLDS, tag + "fold label < 0 (Definition 1)");
         break;
@@ -391,8 +406,8 @@ cvgram_status bookkeeping(Batch& b) {
       }
       p.P = (int32_t)P;
       const int32_t* sorted = nullptr;
-      radix_partition(p.fold, p.N, bit_length((uint32_t)(P - 1)), keys, keys + maxN, p.d_perm,
-                      perm_tmp, hist, &sorted, s);
+      radix_partition(p.fold, p.N, bit_length((uint32_t)(P - 1)), counts, keys, keys + maxN,
+                      p.d_perm, perm_tmp, hist, &sorted, s);
       p.offsets.assign(P + 1, 0);
       bool empty = false;
       if (P <= kCountLabels) {
@@ -402,12 +417,13 @@ cvgram_status bookkeeping(Batch& b) {
           p.offsets[q + 1] = p.offsets[q] + hcounts[q];
         }
       } else {
-        launch_fold_offsets(sorted, p.N, (int32_t)P, offs, info + 2, s);
+        launch_fold_offsets(sorted, p.N, (int32_t)P, offs, flag, s);
         CVG_HIP(hipMemcpyAsync(p.offsets.data(), offs, (P + 1) * sizeof(int64_t),
                                hipMemcpyDeviceToHost, s));
-        CVG_HIP(hipMemcpyAsync(hbuf + 2, info + 2, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        CVG_HIP(hipMemcpyAsync(hbuf + 2 + kCountLabels, flag, sizeof(int32_t),
+                               hipMemcpyDeviceToHost, s));
         CVG_HIP(hipStreamSynchronize(s));
-        empty = hbuf[2] != 0;
+        empty = hbuf[2 + kCountLabels] != 0;
       }
       if (empty) {
         st = fail(CVGRAM_EFOLDS, tag + "a fold label in [0, P) has no rows (Definition 1)");
@@ -623,7 +639,7 @@ void allocate_and_upload(Batch& b, const HostLists& L) {
   for (size_t i = 0; i < b.pp.size(); ++i) {
     const ProbPlan& p = b.pp[i];
     Off& o = off[i];
-    o.pivot = take_bytes(p.W * 8);
+    o.pivot = p.d_pivot ? 0 : take_bytes(p.W * 8);
     o.packed = take_bytes((size_t)p.Np * p.Wp * eb);
     o.packed_lo = b.mode == CVGRAM_MODE_BF16X3 ? take_bytes((size_t)p.Np * p.Wp * eb) : 0;
     o.part = take_bytes((size_t)4 * p.n_chunks * p.W * 8);
@@ -696,7 +712,7 @@ void allocate_and_upload(Batch& b, const HostLists& L) {
     d.perm = p.d_perm;
     d.offsets = (const int64_t*)(dblob + o_offsets[i]);
     d.poff = (const int64_t*)(dblob + o_poff[i]);
-    d.pivot = (double*)(arena + o.pivot);
+    d.pivot = p.d_pivot ? p.d_pivot : (double*)(arena + o.pivot);
     d.packed = arena + o.packed;
     d.packed_lo = b.mode == CVGRAM_MODE_BF16X3 ? arena + o.packed_lo : nullptr;
     d.part = (double*)(arena + o.part);
@@ -774,7 +790,7 @@ void run_pipeline(Batch& b, bool with_events) {
   };
   const bool mixed = b.mode != CVGRAM_MODE_FP64;
   mark(1);
-  launch_pivot(b.dtype, mixed, b.d_pd, b.d_pivot_items, b.n_pivot_items, s);
+  if (b.batched) launch_pivot(b.dtype, mixed, b.d_pd, b.d_pivot_items, b.n_pivot_items, s);
   launch_pack(b.mode, b.dtype, b.d_pd, b.d_chunks, b.n_chunks, b.max_pack_cb, s);
   launch_stats_reduce(b.d_pd, b.d_sr_items, b.n_sr_items, b.max_cb64, s);
   launch_fold_sums_rows(b.dtype, b.d_pd, b.d_fs_items, b.n_fs_items, b.max_cb64, s);

@@ -164,14 +164,19 @@ struct GramWork {
 // ---------------------------------------------------------------------------
 // partition.hip (one problem at a time, at plan time)
 void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
-void launch_label_minmax(const int32_t* fold, int64_t N, int32_t* info, hipStream_t s);
-// minimum, maximum and the counts of labels below kCountLabels (counts zeroed by the caller)
+// info[0] = INT32_MAX, info[1] = INT32_MIN, info[2 .. n) = 0
+void launch_count_init(int32_t* info, int64_t n, hipStream_t s);
+// minimum, maximum and the counts of labels below kCountLabels (starting
+// values from launch_count_init), plus the first radix pass's histogram in
+// hist (radix_hist_entries(N) entries)
 constexpr int kCountLabels = 4096;
 void launch_label_count(const int32_t* fold, int64_t N, int32_t* info, int32_t* counts,
-                        hipStream_t s);
-void radix_partition(const int32_t* fold, int64_t N, int bits, int32_t* keys_a, int32_t* keys_b,
-                     int32_t* perm, int32_t* perm_tmp, int32_t* hist, const int32_t** sorted_keys,
-                     hipStream_t s);
+                        int32_t* hist, hipStream_t s);
+// stable sort of the labels in [0, 2^bits); hist as left by launch_label_count
+// on the same labels, counts = its label counts (used when bits <= 8)
+void radix_partition(const int32_t* fold, int64_t N, int bits, const int32_t* counts,
+                     int32_t* keys_a, int32_t* keys_b, int32_t* perm, int32_t* perm_tmp,
+                     int32_t* hist, const int32_t** sorted_keys, hipStream_t s);
 int64_t radix_hist_entries(int64_t N);
 void launch_fold_offsets(const int32_t* sorted_keys, int64_t N, int32_t P, int64_t* offsets,
                          int32_t* flag, hipStream_t s);
@@ -180,6 +185,9 @@ void launch_fold_offsets(const int32_t* sorted_keys, int64_t N, int32_t P, int64
 // items: (prob, block of 64 columns of [X | Y], -)
 void launch_pivot(cvgram_dtype dt, bool round_f32, const ProbDesc* pd, const Item* items,
                   int64_t n_items, hipStream_t s);
+// the same pivots for one problem from plain arguments (Y may be null when M = 0)
+void launch_pivot_direct(cvgram_dtype dt, bool round_f32, const void* X, const void* Y,
+                         int64_t N, int64_t K, int64_t M, double* out, hipStream_t s);
 void launch_pack(cvgram_mode mode, cvgram_dtype dt, const ProbDesc* pd, const PackChunk* chunks,
                  int64_t n_chunks, int32_t max_col_blocks, hipStream_t s);
 

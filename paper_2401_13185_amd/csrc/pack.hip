@@ -31,41 +31,66 @@ typedef float float4_t __attribute__((ext_vector_type(4)));
 typedef double double2_t __attribute__((ext_vector_type(2)));
 
 // pivot: c_j = FP64 mean of the first min(N, 256) rows of column j of [X | Y]
-// (rounded to FP32 in the mixed modes).  items: (prob, block of 64 columns).
-// Wave w sums rows w, w + 4, ... with eight independent partial sums (eight
-// loads in flight per lane), combined in a fixed order.
+// (rounded to FP32 in the mixed modes).  A 1024-thread workgroup covers 64
+// columns: wave w sums rows w, w + 16, ... (at most 16 rows, every load in
+// flight at once), and the 16 wave sums are combined in a fixed order.
+constexpr int kPivotThreads = 1024;
+constexpr int kPivotWaves = kPivotThreads / 64;
+
 template <typename T>
-__global__ __launch_bounds__(256) void pivot_kernel(const ProbDesc* __restrict__ pds,
-                                                    const Item* __restrict__ items,
-                                                    int round_f32) {
-  __shared__ double part[4][64];
-  const Item it = items[blockIdx.x];
-  const ProbDesc& pd = pds[it.prob];
-  const CVG_GLOBAL T* X = gmem((const T*)pd.X);
-  const CVG_GLOBAL T* Y = gmem((const T*)pd.Y);
-  const int64_t K = pd.K, M = pd.M;
-  const int64_t rows = pd.N < 256 ? pd.N : 256;
+__device__ inline void pivot_cols(const CVG_GLOBAL T* X, const CVG_GLOBAL T* Y, int64_t N,
+                                  int64_t K, int64_t M, int64_t col_block, int round_f32,
+                                  CVG_GLOBAL double* out) {
+  __shared__ double part[kPivotWaves][64];
+  const int64_t rows = N < 256 ? N : 256;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t j = (int64_t)it.a * 64 + lane;
-  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const int64_t j = col_block * 64 + lane;
+  double v[256 / kPivotWaves];
+#pragma unroll
+  for (int u = 0; u < 256 / kPivotWaves; ++u) v[u] = 0.0;
   if (j < K + M) {
     const CVG_GLOBAL T* base = j < K ? X + j : Y + (j - K);
     const int64_t ld = j < K ? K : M;
-    for (int64_t r0 = w; r0 < rows; r0 += 32) {
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int64_t r = r0 + 4 * u;
-        if (r < rows) acc[u] += (double)base[r * ld];
-      }
+    for (int u = 0; u < 256 / kPivotWaves; ++u) {
+      const int64_t r = w + (int64_t)kPivotWaves * u;
+      if (r < rows) v[u] = (double)base[r * ld];
     }
   }
-  part[w][lane] = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+#pragma unroll
+  for (int h = 256 / kPivotWaves / 2; h > 0; h >>= 1)
+#pragma unroll
+    for (int u = 0; u < h; ++u) v[u] += v[u + h];
+  part[w][lane] = v[0];
   __syncthreads();
   if (w == 0 && j < K + M) {
-    double c = ((part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane])) / (double)rows;
+    double c = 0.0;
+#pragma unroll
+    for (int k = 0; k < kPivotWaves; ++k) c += part[k][lane];
+    c /= (double)rows;
     if (round_f32) c = (double)(float)c;
-    gmem(pd.pivot)[j] = c;
+    out[j] = c;
   }
+}
+
+// items: (prob, block of 64 columns)
+template <typename T>
+__global__ __launch_bounds__(kPivotThreads) void pivot_kernel(const ProbDesc* __restrict__ pds,
+                                                              const Item* __restrict__ items,
+                                                              int round_f32) {
+  const Item it = items[blockIdx.x];
+  const ProbDesc& pd = pds[it.prob];
+  pivot_cols<T>(gmem((const T*)pd.X), gmem((const T*)pd.Y), pd.N, pd.K, pd.M, it.a, round_f32,
+                gmem(pd.pivot));
+}
+
+// one problem, arguments by value (no descriptor yet): workgroup = block of 64 columns
+template <typename T>
+__global__ __launch_bounds__(kPivotThreads) void pivot_direct_kernel(const T* X, const T* Y,
+                                                                     int64_t N, int64_t K,
+                                                                     int64_t M, int round_f32,
+                                                                     double* out) {
+  pivot_cols<T>(gmem(X), gmem(Y), N, K, M, blockIdx.x, round_f32, gmem(out));
 }
 
 // source column (index into [X | Y], also the statistics index) of packed
@@ -299,9 +324,23 @@ void launch_pivot(cvgram_dtype dt, bool round_f32, const ProbDesc* pd, const Ite
                   int64_t n_items, hipStream_t s) {
   if (n_items <= 0) return;
   if (dt == CVGRAM_F64)
-    pivot_kernel<double><<<(unsigned)n_items, 256, 0, s>>>(pd, items, round_f32 ? 1 : 0);
+    pivot_kernel<double><<<(unsigned)n_items, kPivotThreads, 0, s>>>(pd, items,
+                                                                     round_f32 ? 1 : 0);
   else
-    pivot_kernel<float><<<(unsigned)n_items, 256, 0, s>>>(pd, items, round_f32 ? 1 : 0);
+    pivot_kernel<float><<<(unsigned)n_items, kPivotThreads, 0, s>>>(pd, items,
+                                                                    round_f32 ? 1 : 0);
+  CVG_LAUNCH_CHECK();
+}
+
+void launch_pivot_direct(cvgram_dtype dt, bool round_f32, const void* X, const void* Y,
+                         int64_t N, int64_t K, int64_t M, double* out, hipStream_t s) {
+  const unsigned blocks = (unsigned)((K + M + 63) / 64);
+  if (dt == CVGRAM_F64)
+    pivot_direct_kernel<double><<<blocks, kPivotThreads, 0, s>>>(
+        (const double*)X, (const double*)Y, N, K, M, round_f32 ? 1 : 0, out);
+  else
+    pivot_direct_kernel<float><<<blocks, kPivotThreads, 0, s>>>(
+        (const float*)X, (const float*)Y, N, K, M, round_f32 ? 1 : 0, out);
   CVG_LAUNCH_CHECK();
 }
 

@@ -7,7 +7,10 @@
 // many passes as the largest label needs (one pass for P <= 256).  Each pass
 // is: per-tile digit histogram -> exclusive scan of the digit-major
 // histogram -> stable scatter, where ranks inside a tile come from wave-wide
-// ballots (no atomics on the output, so the result is deterministic).
+// ballots (no atomics on the output, so the result is deterministic).  The
+// first pass's histogram comes with the label counts (same tiles), and a
+// single-pass sort scans it in one launch: the digit of a label below 256 is
+// the label itself, so the counts give every digit's base offset.
 #include <climits>
 
 #include "internal.h"
@@ -35,53 +38,46 @@ __device__ inline int wave_max(int v) {
   return v;
 }
 
-__global__ __launch_bounds__(kThreads) void label_minmax_kernel(const int32_t* __restrict__ f,
-                                                                int64_t n, int32_t* info) {
-  int lo = INT_MAX, hi = INT_MIN;
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (; i < n; i += stride) {
-    int v = f[i];
-    lo = min(lo, v);
-    hi = max(hi, v);
-  }
-  lo = wave_min(lo);
-  hi = wave_max(hi);
-  __shared__ int slo[kWaves], shi[kWaves];
-  int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) {
-    slo[w] = lo;
-    shi[w] = hi;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int k = 1; k < kWaves; ++k) {
-      lo = min(lo, slo[k]);
-      hi = max(hi, shi[k]);
-    }
-    atomicMin(&info[0], lo);
-    atomicMax(&info[1], hi);
-  }
+// info[0] = INT_MAX, info[1] = INT_MIN, info[2 ..) = 0: the starting values
+// of the label validation and counts (one launch for the whole block).
+__global__ void count_init_kernel(int32_t* info, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) info[i] = i == 0 ? INT_MAX : (i == 1 ? INT_MIN : 0);
 }
 
 // Label counts for labels in [0, kCountLabels), with the minimum and maximum
 // (all integer, so the result does not depend on the order of the atomics):
 // one pass that gives the host the fold sizes together with the validation
-// data.  Each workgroup counts into LDS and adds its non-zero bins.
+// data.  Workgroup t reads radix tile t, counts into LDS, adds its non-zero
+// bins, and stores the tile's histogram of the low 8 bits of the labels
+// (the first radix pass's digit) at hist[d * tiles + t].
 __global__ __launch_bounds__(kThreads) void label_count_kernel(const int32_t* __restrict__ f,
                                                                int64_t n, int32_t* info,
-                                                               int32_t* counts) {
+                                                               int32_t* counts,
+                                                               int32_t* __restrict__ hist,
+                                                               int64_t tiles) {
   __shared__ int h[kCountLabels];
+  __shared__ int dh[256];
   for (int b = threadIdx.x; b < kCountLabels; b += kThreads) h[b] = 0;
+  dh[threadIdx.x] = 0;
   __syncthreads();
   int lo = INT_MAX, hi = INT_MIN;
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (; i < n; i += stride) {
-    const int v = f[i];
-    lo = min(lo, v);
-    hi = max(hi, v);
-    if (v >= 0 && v < kCountLabels) atomicAdd(&h[v], 1);
+  const int64_t base = (int64_t)blockIdx.x * kTileElems;
+  int v[kItems];
+#pragma unroll
+  for (int it = 0; it < kItems; ++it) {
+    const int64_t idx = base + it * kThreads + threadIdx.x;
+    v[it] = idx < n ? f[idx] : -1;
+  }
+#pragma unroll
+  for (int it = 0; it < kItems; ++it) {
+    if (base + it * kThreads + threadIdx.x >= n) continue;
+    lo = min(lo, v[it]);
+    hi = max(hi, v[it]);
+    if (v[it] >= 0) {
+      if (v[it] < kCountLabels) atomicAdd(&h[v[it]], 1);
+      atomicAdd(&dh[v[it] & 255], 1);
+    }
   }
   lo = wave_min(lo);
   hi = wave_max(hi);
@@ -102,6 +98,7 @@ __global__ __launch_bounds__(kThreads) void label_count_kernel(const int32_t* __
   }
   for (int b = threadIdx.x; b < kCountLabels; b += kThreads)
     if (h[b]) atomicAdd(&counts[b], h[b]);
+  hist[(int64_t)threadIdx.x * tiles + blockIdx.x] = dh[threadIdx.x];
 }
 
 // hist is digit-major: hist[d * tiles + t]
@@ -201,6 +198,42 @@ __global__ __launch_bounds__(kThreads) void scan_apply_kernel(int32_t* __restric
   }
 }
 
+// Single-pass sort (labels below 256): workgroup d turns row d of the
+// digit-major histogram into scatter offsets, base(d) + the exclusive prefix
+// over tiles, where base(d) = counts[0] + ... + counts[d - 1].
+__global__ __launch_bounds__(kThreads) void digit_scan_kernel(int32_t* __restrict__ hist,
+                                                              int64_t tiles,
+                                                              const int32_t* __restrict__ counts) {
+  __shared__ int ws[kWaves];
+  __shared__ int carry;
+  const int d = blockIdx.x;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  int b = threadIdx.x < d ? counts[threadIdx.x] : 0;
+  for (int o = 32; o > 0; o >>= 1) b += __shfl_xor(b, o, 64);
+  if (lane == 0) ws[w] = b;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int k = 0; k < kWaves; ++k) t += ws[k];
+    carry = t;
+  }
+  __syncthreads();
+  int32_t* row = hist + (int64_t)d * tiles;
+  for (int64_t t0 = 0; t0 < tiles; t0 += kThreads) {
+    const int64_t i = t0 + threadIdx.x;
+    const int v = i < tiles ? row[i] : 0;
+    const int inc = wave_incl_scan(v, lane);
+    if (lane == 63) ws[w] = inc;
+    __syncthreads();
+    int off = carry;
+    for (int k = 0; k < w; ++k) off += ws[k];
+    if (i < tiles) row[i] = off + inc - v;
+    __syncthreads();
+    if (threadIdx.x == kThreads - 1) carry = off + inc;
+    __syncthreads();
+  }
+}
+
 __global__ __launch_bounds__(kThreads) void radix_scatter_kernel(
     const int32_t* __restrict__ keys_in, const int32_t* __restrict__ vals_in,
     int32_t* __restrict__ keys_out, int32_t* __restrict__ vals_out, int64_t n, int shift,
@@ -278,19 +311,15 @@ void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
   CVG_LAUNCH_CHECK();
 }
 
-void launch_label_minmax(const int32_t* fold, int64_t N, int32_t* info, hipStream_t s) {
-  // a few hundred blocks, each reducing many labels, then one atomic pair per block
-  int64_t blocks = (N + 16 * kThreads - 1) / (16 * kThreads);
-  if (blocks > 512) blocks = 512;
-  label_minmax_kernel<<<(unsigned)blocks, kThreads, 0, s>>>(fold, N, info);
+void launch_count_init(int32_t* info, int64_t n, hipStream_t s) {
+  count_init_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(info, n);
   CVG_LAUNCH_CHECK();
 }
 
 void launch_label_count(const int32_t* fold, int64_t N, int32_t* info, int32_t* counts,
-                        hipStream_t s) {
-  int64_t blocks = (N + 16 * kThreads - 1) / (16 * kThreads);
-  if (blocks > 512) blocks = 512;
-  label_count_kernel<<<(unsigned)blocks, kThreads, 0, s>>>(fold, N, info, counts);
+                        int32_t* hist, hipStream_t s) {
+  const int64_t tiles = (N + kTileElems - 1) / kTileElems;
+  label_count_kernel<<<(unsigned)tiles, kThreads, 0, s>>>(fold, N, info, counts, hist, tiles);
   CVG_LAUNCH_CHECK();
 }
 
@@ -310,9 +339,9 @@ void scan_exclusive(int32_t* a, int64_t n, int32_t* sums, hipStream_t s) {
   CVG_LAUNCH_CHECK();
 }
 
-void radix_partition(const int32_t* fold, int64_t N, int bits, int32_t* keys_a, int32_t* keys_b,
-                     int32_t* perm, int32_t* perm_tmp, int32_t* hist, const int32_t** sorted_keys,
-                     hipStream_t s) {
+void radix_partition(const int32_t* fold, int64_t N, int bits, const int32_t* counts,
+                     int32_t* keys_a, int32_t* keys_b, int32_t* perm, int32_t* perm_tmp,
+                     int32_t* hist, const int32_t** sorted_keys, hipStream_t s) {
   const int64_t tiles = (N + kTileElems - 1) / kTileElems;
   int passes = (bits + 7) / 8;
   if (passes < 1) passes = 1;
@@ -323,9 +352,17 @@ void radix_partition(const int32_t* fold, int64_t N, int bits, int32_t* keys_a, 
     int32_t* kout = (pass & 1) ? keys_b : keys_a;
     int32_t* vout = ((passes - 1 - pass) & 1) ? perm_tmp : perm;
     const int shift = 8 * pass;
-    radix_hist_kernel<<<(unsigned)tiles, kThreads, 0, s>>>(kin, N, shift, hist, tiles);
-    CVG_LAUNCH_CHECK();
-    scan_exclusive(hist, 256 * tiles, hist + 256 * tiles, s);
+    if (pass > 0) {
+      radix_hist_kernel<<<(unsigned)tiles, kThreads, 0, s>>>(kin, N, shift, hist, tiles);
+      CVG_LAUNCH_CHECK();
+    }
+    if (passes == 1) {
+      // labels in [0, 2^bits) with bits <= 8: one workgroup per label
+      digit_scan_kernel<<<1u << bits, kThreads, 0, s>>>(hist, tiles, counts);
+      CVG_LAUNCH_CHECK();
+    } else {
+      scan_exclusive(hist, 256 * tiles, hist + 256 * tiles, s);
+    }
     radix_scatter_kernel<<<(unsigned)tiles, kThreads, 0, s>>>(kin, vin, kout, vout, N, shift,
                                                               hist, tiles);
     CVG_LAUNCH_CHECK();
