@@ -37,15 +37,25 @@ def f_alg(n, k, m):
 
 def f_exec(n, k, m, mode, tile=None):
     """Flops the Gram launch executes (matrix-core work, not algorithmic):
-    whole tiles on and above the diagonal (three waves of four on a diagonal
-    tile, the fourth on the K x M block when M <= 32), separate K x M tiles
-    otherwise; three bf16 products per product in BF16X3."""
+    whole tiles above the diagonal; on a diagonal tile, FP64 / FP32 with
+    128-wide tiles compute the 36 upper-triangle 16 x 16 blocks of 64 and
+    one (M <= 16) or two (M <= 32) 16-column K x M blocks per block row,
+    otherwise (BF16X3, 64-wide tiles) three waves of four take the upper
+    quadrants and the fourth a 32-column K x M block; M > 32 uses separate
+    K x M tiles.  Three bf16 products per product in BF16X3."""
     T = tile or (64 if k <= 64 else 128)
     nt = -(-k // T)
-    entries = (nt * (nt + 1) // 2 - nt) * T * T + nt * (3 * T * T // 4)
-    if 0 < m <= 32:
-        entries += nt * T * 32
-    elif m > 32:
+    pairs = T == 128 and mode != "bf16x3"
+    entries = (nt * (nt + 1) // 2 - nt) * T * T
+    if pairs:
+        entries += nt * 36 * 256
+        if 0 < m <= 32:
+            entries += nt * 8 * (1 if m <= 16 else 2) * 256
+    else:
+        entries += nt * (3 * T * T // 4)
+        if 0 < m <= 32:
+            entries += nt * T * 32
+    if m > 32:
         entries += nt * (-(-m // T)) * T * T
     return 2 * n * entries * (3 if mode == "bf16x3" else 1)
 

@@ -8,9 +8,12 @@
 // are contiguous and zero-padded in the packed panels, so an item streams
 // aligned 16-byte vector loads with no gathers and no bounds checks.
 // Output tiles are BM x BM (BM = 64 or 128, chosen per problem): every tile
-// on or above the diagonal of the K x K block; the K x M block is computed
-// by the otherwise idle lower-left wave of each diagonal tile when M <= 32
-// (so no extra pass over X), else by separate tiles.  Each item writes its
+// on or above the diagonal of the K x K block.  When M <= 32 the K x M block
+// rides on the diagonal tiles (no extra pass over X), else it gets separate
+// tiles.  A 64-wide diagonal tile (and every BF16X3 one) gives its three
+// upper 32 x 32 quadrants to three waves and the K x M block to the fourth;
+// a 128-wide FP64 / FP32 diagonal tile splits its upper-triangle 16 x 16
+// blocks and K x M blocks evenly over the four waves.  Each item writes its
 // FP64 tile to its own slab (summed later in a fixed order: deterministic,
 // no floating-point atomics).
 //
@@ -139,6 +142,13 @@ struct Stage {
 // one stage of MFMA work for a wave: NA x NB blocks of 16 x 16, A columns
 // from `acol0` of the A view, B columns from `bcol0` of the B view.
 // ---------------------------------------------------------------------------
+__device__ inline double4_t mfma_step(double a, double b, double4_t c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ inline float4_t mfma_step(float a, float b, float4_t c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
 template <int NA, int NB, int NACC>
 __device__ inline void mma_f64(const double* A, int lda, int acol0, const double* B, int ldb,
                                int bcol0, double4_t (&acc)[NACC], int fr, int fc) {
@@ -218,6 +228,67 @@ __device__ inline void mfma_pass(const Frags<NA, NB>& f, float4_t (&acc)[NACC]) 
     for (int b = 0; b < NB; ++b)
       acc[a * NB + b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
           PASS == 0 ? f.al[a] : f.ah[a], PASS == 1 ? f.bl[b] : f.bh[b], acc[a * NB + b], 0, 0, 0);
+}
+
+// ---------------------------------------------------------------------------
+// diagonal 128 x 128 tiles (FP64 / FP32): only the upper triangle of its
+// 8 x 8 blocks of 16 x 16 is needed (plus the K x M blocks when the tile
+// carries them).  Wave W takes block rows W and 7 - W: (8 - W) + (W + 1) = 9
+// blocks of the triangle and NYB blocks of the K x M block per row, the same
+// count for every wave.  A block's fragment is the same register whether it
+// serves as A or as B (both are columns of the same stage), so a wave reads
+// the 8 - W fragments of blocks W .. 7 once per k-step.
+// Accumulator order: row W's blocks (columns W .. 7), row 7 - W's blocks
+// (columns 7 - W .. 7), then row W's and row 7 - W's K x M blocks.
+// ---------------------------------------------------------------------------
+template <int W, int NYB, typename E, typename Acc, int NACC>
+__device__ inline void mma_diag_pairs(const E* A, int lda, const E* Yb, int ldy,
+                                      Acc (&acc)[NACC], int fr, int fc) {
+  constexpr int R0 = W, R1 = 7 - W, N0 = 8 - R0, N1 = 8 - R1;
+  static_assert(N0 + N1 + 2 * NYB <= NACC, "accumulators");
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) {
+    E f[N0], y[NYB > 0 ? NYB : 1];
+#pragma unroll
+    for (int c = 0; c < N0; ++c) f[c] = A[(kk * 4 + fr) * lda + (R0 + c) * 16 + fc];
+#pragma unroll
+    for (int q = 0; q < NYB; ++q) y[q] = Yb[(kk * 4 + fr) * ldy + q * 16 + fc];
+#pragma unroll
+    for (int c = 0; c < N0; ++c) acc[c] = mfma_step(f[0], f[c], acc[c]);
+#pragma unroll
+    for (int c = 0; c < N1; ++c)
+      acc[N0 + c] = mfma_step(f[R1 - R0], f[R1 - R0 + c], acc[N0 + c]);
+#pragma unroll
+    for (int q = 0; q < NYB; ++q) {
+      acc[N0 + N1 + q] = mfma_step(f[0], y[q], acc[N0 + N1 + q]);
+      acc[N0 + N1 + NYB + q] = mfma_step(f[R1 - R0], y[q], acc[N0 + N1 + NYB + q]);
+    }
+  }
+}
+
+template <int MODE, int W, int NYB, typename V>
+__device__ inline void store_diag_pairs(CVG_GLOBAL double* out, int64_t ca, int fr, int fc,
+                                        int64_t K, int64_t M, const V& value) {
+  constexpr int R0 = W, R1 = 7 - W, N0 = 8 - R0, N1 = 8 - R1;
+  const int64_t Wd = K + M;
+#pragma unroll
+  for (int i = 0; i < N0 + N1 + 2 * NYB; ++i) {
+    const int rb = i < N0 ? R0 : (i < N0 + N1 ? R1 : (i < N0 + N1 + NYB ? R0 : R1));
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t row = ca + rb * 16 + acc_row<MODE>(e, fr);
+      if (row >= K) continue;
+      if (i < N0 + N1) {
+        const int cblk = i < N0 ? R0 + i : R1 + (i - N0);
+        const int64_t cl = ca + cblk * 16 + fc;
+        if (cl < K) out[row * Wd + cl] = value(i, e);
+      } else {
+        const int q = (i - N0 - N1) % (NYB > 0 ? NYB : 1);
+        const int64_t cl = q * 16 + fc;
+        if (cl < M) out[row * Wd + K + cl] = value(i, e);
+      }
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -303,7 +374,11 @@ __global__ __launch_bounds__(kThreads) void gram_kernel(const ProbDesc* __restri
   const bool ydiag = diag && xy_diag;      // K x M block inside this diagonal tile
   const bool ld_b = !diag;                  // diagonal tiles reuse A as B
   // wave roles: 0 = WT x WT sub-tile, 1 = BM x 32 K-by-M block, 2 = idle
-  const int role = (diag && wm == 1 && wn == 0) ? (ydiag ? 1 : 2) : 0;
+  // (64-wide diagonal tiles; 128-wide ones split their triangle evenly)
+  constexpr bool kPairs = BM == 128;
+  const int role = (!kPairs && diag && wm == 1 && wn == 0) ? (ydiag ? 1 : 2) : 0;
+  // K x M blocks of 16 columns a 128-wide diagonal tile computes
+  const int nyb = ydiag ? (M <= 16 ? 1 : 2) : 0;
 
   Acc acc[NACC];
   double a64[NACC][4];
@@ -339,16 +414,23 @@ __global__ __launch_bounds__(kThreads) void gram_kernel(const ProbDesc* __restri
       }
     }
   };
-  auto main_loop = [&](auto diag_c, auto ydiag_c) {
+  auto main_loop = [&](auto diag_c, auto ydiag_c, auto nyb_c, auto wave_c) {
     constexpr bool DG = decltype(diag_c)::value;   // B is A
     constexpr bool YD = decltype(ydiag_c)::value;  // K x M block in this tile
+    constexpr int NYB = decltype(nyb_c)::value;    // its blocks per row (pairs)
+    constexpr int WV = decltype(wave_c)::value;    // the wave (pairs)
     Stage<MODE, BM> st[PF];
     auto load = [&](Stage<MODE, BM>& sg, int64_t s) {
       const int64_t r = w.r0 + (s < nst ? s : nst - 1) * BK;
       sg.load(packed, Wp, r, ca, cb, Kp, !DG, YD, t);
     };
     auto compute = [&](int buf) {
-      if constexpr (MODE == CVGRAM_MODE_FP64) {
+      if constexpr (kPairs && DG) {
+        constexpr int LDA = Smem<MODE, BM>::LDA, LDY = Smem<MODE, BM>::LDY;
+        const typename Mode<MODE>::E* A = sm.a[buf];
+        const typename Mode<MODE>::E* Yb = sm.y[buf];
+        mma_diag_pairs<WV, NYB>(A, LDA, Yb, LDY, acc, fr, fc);
+      } else if constexpr (MODE == CVGRAM_MODE_FP64) {
         constexpr int LDA = Smem<MODE, BM>::LDA, LDY = Smem<MODE, BM>::LDY;
         const double* A = sm.a[buf];
         const double* B = DG ? sm.a[buf] : sm.b[buf];
@@ -400,12 +482,37 @@ __global__ __launch_bounds__(kThreads) void gram_kernel(const ProbDesc* __restri
       if (s < nst) step(s, st[1], st[0]);
     }
   };
-  if (!diag)
-    main_loop(std::false_type{}, std::false_type{});
-  else if (ydiag)
-    main_loop(std::true_type{}, std::true_type{});
-  else
-    main_loop(std::true_type{}, std::false_type{});
+  typedef std::integral_constant<int, 0> Y0;
+  typedef std::integral_constant<int, 1> Y1;
+  typedef std::integral_constant<int, 2> Y2;
+  typedef std::integral_constant<int, 0> W0;
+  typedef std::integral_constant<int, 1> W1;
+  typedef std::integral_constant<int, 2> W2;
+  typedef std::integral_constant<int, 3> W3;
+  // a 128-wide diagonal tile runs a loop specialised for the wave, so that
+  // every accumulator index is static inside it
+  auto diag_loop = [&](auto w_c) {
+    if (!ydiag)
+      main_loop(std::true_type{}, std::false_type{}, Y0{}, w_c);
+    else if (nyb == 1)
+      main_loop(std::true_type{}, std::true_type{}, Y1{}, w_c);
+    else
+      main_loop(std::true_type{}, std::true_type{}, Y2{}, w_c);
+  };
+  if (!diag) {
+    main_loop(std::false_type{}, std::false_type{}, Y0{}, W0{});
+  } else if constexpr (kPairs) {
+    switch (wave) {
+      case 0: diag_loop(W0{}); break;
+      case 1: diag_loop(W1{}); break;
+      case 2: diag_loop(W2{}); break;
+      default: diag_loop(W3{}); break;
+    }
+  } else if (!ydiag) {
+    main_loop(std::true_type{}, std::false_type{}, Y0{}, W0{});
+  } else {
+    main_loop(std::true_type{}, std::true_type{}, Y2{}, W0{});
+  }
   if (role == 2) return;
   CVG_GLOBAL double* out = slabs + (int64_t)w.slab * K * (K + M);
   auto value = [&](int i, int e) -> double {
@@ -414,6 +521,29 @@ __global__ __launch_bounds__(kThreads) void gram_kernel(const ProbDesc* __restri
     else
       return a64[i][e] + (double)acc[i][e];
   };
+  if constexpr (kPairs) {
+    if (diag) {
+      auto store = [&](auto w_c, auto y_c) {
+        store_diag_pairs<MODE, decltype(w_c)::value, decltype(y_c)::value>(out, ca, fr, fc, K, M,
+                                                                           value);
+      };
+      auto by_wave = [&](auto y_c) {
+        switch (wave) {
+          case 0: store(W0{}, y_c); break;
+          case 1: store(W1{}, y_c); break;
+          case 2: store(W2{}, y_c); break;
+          default: store(W3{}, y_c); break;
+        }
+      };
+      if (nyb == 0)
+        by_wave(Y0{});
+      else if (nyb == 1)
+        by_wave(Y1{});
+      else
+        by_wave(Y2{});
+      return;
+    }
+  }
   store_tile<MODE, BM, NACC>(out, role, xy_tile, ca, xy_tile ? (int64_t)(w.tj - nt) * BM : cb, wm,
                              wn, fr, fc, K, M, value);
 }
