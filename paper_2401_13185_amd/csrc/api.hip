@@ -452,6 +452,16 @@ struct HostLists {
       corr_items;
   std::vector<PackChunk> chunks;
   std::vector<GramWork> work64, work128;
+  // empty every list, keeping its memory (the lists are reused per thread:
+  // no allocation or first-touch page faults on the planning path)
+  void clear() {
+    for (auto* v : {&pivot_items, &fold_items, &sr_items, &fs_items, &cb_items, &range_items,
+                    &red_items, &corr_items})
+      v->clear();
+    chunks.clear();
+    work64.clear();
+    work128.clear();
+  }
 };
 
 // Fold path of a problem.  The fused path (no padding between folds, G'_p
@@ -554,6 +564,19 @@ void plan_layout(Batch& b, HostLists& L) {
     rows_per_split = std::max(rows_per_split, kGramMinRows);
     rows_per_split = (rows_per_split + PR - 1) / PR * PR;
     auto& wl = T == 64 ? L.work64 : L.work128;
+    {
+      // room for every item up front (no regrowth while appending)
+      int64_t n_splits = 0;
+      auto count_splits = [&](int64_t a, int64_t e) {
+        const int64_t panels = (e - a) / PR;
+        n_splits += std::min(panels, std::max<int64_t>(1, (e - a + rows_per_split - 1) / rows_per_split));
+      };
+      if (p.fused)
+        count_splits(0, p.Np);
+      else
+        for (int32_t q = 0; q < p.P; ++q) count_splits(p.poff[q], p.poff[q + 1]);
+      wl.reserve(wl.size() + (size_t)(n_splits * (int64_t)gtiles.size()));
+    }
     p.slab_begin.assign(p.P + 1, 0);
     int32_t slab = 0;
     auto split_rows = [&](int64_t a, int64_t e) {
@@ -578,6 +601,7 @@ void plan_layout(Batch& b, HostLists& L) {
     p.slab_begin[p.P] = slab;
     p.n_slabs = slab;
     // slab reduction
+    L.red_items.reserve(L.red_items.size() + (size_t)((p.K * p.W + 255) / 256));
     for (int64_t eb = 0; eb < (p.K * p.W + 255) / 256; ++eb) L.red_items.push_back({pi, (int32_t)eb, 0});
     // correction tiles: upper triangle of X^T X, then X^T Y
     p.ctiles.clear();
@@ -602,19 +626,22 @@ void plan_layout(Batch& b, HostLists& L) {
   }
 }
 
-// a growing plan blob with 256-byte aligned segments
+// the plan blob: segments at 256-byte aligned offsets.  Laid out twice:
+// once with dst == nullptr to measure it, then straight into the pinned
+// upload buffer (no intermediate copy).
 struct Blob {
-  std::vector<char> bytes;
+  char* dst = nullptr;
+  size_t size = 0;
   template <typename T>
-  size_t put(const T* data, size_t count) {
-    const size_t off = (bytes.size() + 255) / 256 * 256;
-    bytes.resize(off + count * sizeof(T));
-    if (count && data) std::memcpy(bytes.data() + off, data, count * sizeof(T));
+  size_t put(const T* data, size_t count, bool align = true) {
+    const size_t off = align ? (size + 255) / 256 * 256 : size;
+    size = off + count * sizeof(T);
+    if (dst && count && data) std::memcpy(dst + off, data, count * sizeof(T));
     return off;
   }
   template <typename T>
-  size_t put(const std::vector<T>& v) {
-    return put(v.data(), v.size());
+  size_t put(const std::vector<T>& v, bool align = true) {
+    return put(v.data(), v.size(), align);
   }
 };
 
@@ -658,31 +685,41 @@ void allocate_and_upload(Batch& b, const HostLists& L) {
   char* arena = (char*)b.mem.dev(total);
 
   // plan blob: per-problem small arrays first, then descriptors and lists
-  Blob blob;
   std::vector<size_t> o_offsets(b.pp.size()), o_poff(b.pp.size()), o_cbeg(b.pp.size()),
       o_sbeg(b.pp.size()), o_ctiles(b.pp.size());
-  for (size_t i = 0; i < b.pp.size(); ++i) {
-    o_offsets[i] = blob.put(b.pp[i].offsets);
-    o_poff[i] = blob.put(b.pp[i].poff);
-    o_cbeg[i] = blob.put(b.pp[i].chunk_begin);
-    o_sbeg[i] = blob.put(b.pp[i].slab_begin);
-    o_ctiles[i] = blob.put(b.pp[i].ctiles);
-  }
-  const size_t o_pd = blob.put((const ProbDesc*)nullptr, b.pp.size());
-  const size_t o_out = blob.put((const OutDesc*)nullptr, b.pp.size());
-  const size_t o_pivot = blob.put(L.pivot_items);
-  const size_t o_chunks = blob.put(L.chunks);
-  const size_t o_fold = blob.put(L.fold_items);
-  const size_t o_sr = blob.put(L.sr_items);
-  const size_t o_fs = blob.put(L.fs_items);
-  const size_t o_cb = blob.put(L.cb_items);
-  const size_t o_range = blob.put(L.range_items);
-  std::vector<GramWork> work = L.work64;
-  work.insert(work.end(), L.work128.begin(), L.work128.end());
-  const size_t o_work = blob.put(work);
-  const size_t o_red = blob.put(L.red_items);
-  const size_t o_corr = blob.put(L.corr_items);
-  char* dblob = (char*)b.mem.dev(blob.bytes.size());
+  size_t o_pd = 0, o_out = 0, o_pivot = 0, o_chunks = 0, o_fold = 0, o_sr = 0, o_fs = 0,
+         o_cb = 0, o_range = 0, o_work = 0, o_red = 0, o_corr = 0;
+  auto layout = [&](Blob& blob) {
+    for (size_t i = 0; i < b.pp.size(); ++i) {
+      o_offsets[i] = blob.put(b.pp[i].offsets);
+      o_poff[i] = blob.put(b.pp[i].poff);
+      o_cbeg[i] = blob.put(b.pp[i].chunk_begin);
+      o_sbeg[i] = blob.put(b.pp[i].slab_begin);
+      o_ctiles[i] = blob.put(b.pp[i].ctiles);
+    }
+    o_pd = blob.put((const ProbDesc*)nullptr, b.pp.size());
+    o_out = blob.put((const OutDesc*)nullptr, b.pp.size());
+    o_pivot = blob.put(L.pivot_items);
+    o_chunks = blob.put(L.chunks);
+    o_fold = blob.put(L.fold_items);
+    o_sr = blob.put(L.sr_items);
+    o_fs = blob.put(L.fs_items);
+    o_cb = blob.put(L.cb_items);
+    o_range = blob.put(L.range_items);
+    o_work = blob.put(L.work64);
+    blob.put(L.work128, false);  // right after the 64-wide items: one array
+    o_red = blob.put(L.red_items);
+    o_corr = blob.put(L.corr_items);
+  };
+  Blob measure;
+  layout(measure);
+  const size_t blob_bytes = measure.size;
+  char* dblob = (char*)b.mem.dev(blob_bytes);
+  // pinned upload buffer (kept until the batch is freed), written in place
+  char* hb = (char*)b.mem.pinned(blob_bytes);
+  Blob blob;
+  blob.dst = hb;
+  layout(blob);
 
   b.h_pd.assign(b.pp.size(), ProbDesc{});
   std::vector<OutDesc> outs(b.pp.size());
@@ -748,8 +785,8 @@ void allocate_and_upload(Batch& b, const HostLists& L) {
     od.fold_stride_xy = CVGRAM_XTY_CLASSES * KM;
     od.p_begin = 0;
   }
-  std::memcpy(blob.bytes.data() + o_pd, b.h_pd.data(), b.h_pd.size() * sizeof(ProbDesc));
-  std::memcpy(blob.bytes.data() + o_out, outs.data(), outs.size() * sizeof(OutDesc));
+  std::memcpy(hb + o_pd, b.h_pd.data(), b.h_pd.size() * sizeof(ProbDesc));
+  std::memcpy(hb + o_out, outs.data(), outs.size() * sizeof(OutDesc));
 
   b.d_pd = (ProbDesc*)(dblob + o_pd);
   b.d_out = (OutDesc*)(dblob + o_out);
@@ -775,10 +812,8 @@ void allocate_and_upload(Batch& b, const HostLists& L) {
   b.d_corr_items = (Item*)(dblob + o_corr);
   b.n_corr_items = (int64_t)L.corr_items.size();
 
-  // one asynchronous upload from pinned memory (kept until the batch is freed)
-  void* hb = b.mem.pinned(blob.bytes.size());
-  std::memcpy(hb, blob.bytes.data(), blob.bytes.size());
-  CVG_HIP(hipMemcpyAsync(dblob, hb, blob.bytes.size(), hipMemcpyHostToDevice, b.stream));
+  // one asynchronous upload from pinned memory
+  CVG_HIP(hipMemcpyAsync(dblob, hb, blob_bytes, hipMemcpyHostToDevice, b.stream));
 }
 
 // The device pipeline (Algorithm 7 steps 3-4, 8, 10, 17, 19 and, for a
@@ -815,7 +850,8 @@ cvgram_status prepare(Batch& b) {
   b.mem.device = b.device;
   cvgram_status st = bookkeeping(b);
   if (st != CVGRAM_OK) return st;
-  HostLists L;
+  thread_local HostLists L;
+  L.clear();
   plan_layout(b, L);
   allocate_and_upload(b, L);
   return CVGRAM_OK;
