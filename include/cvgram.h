@@ -214,8 +214,9 @@ cvgram_status cvgram_fold_stats(cvgram_t h, int32_t p, double* mean_x, double* s
 /* Per-stage device timing.  When enabled (process-wide; off by default),
  * cvgram_create records HIP events on its stream around its stages and
  * cvgram_stage_times() returns their durations in milliseconds, waiting for
- * them if needed: ms[0] fold bookkeeping (includes the two host waits),
- * ms[1] column statistics, ms[2] grouped Gram launch, ms[3] slab reduction.
+ * them if needed: ms[0] fold bookkeeping (includes the host's wait for the
+ * label counts and its planning), ms[1] column statistics (packing),
+ * ms[2] grouped Gram launch, ms[3] slab reduction.
  * n is the capacity of ms (at most 4 entries are written).  Returns
  * CVGRAM_EINVAL if the handle was created with timing off. */
 cvgram_status cvgram_set_stage_timing(int on);
@@ -292,6 +293,14 @@ cvgram_status cvgram_batch_destroy(cvgram_batch_t b);
 cvgram_status cvgram_autotune(const void* X, const void* Y, const int32_t* fold_id, int64_t N,
                               int64_t K, int64_t M, cvgram_dtype dtype, cvgram_mode mode,
                               void* stream, int32_t* tile, int32_t* target_items);
+
+/* The plan cvgram_create chose for this handle (host values):
+ *   info[0] tile edge of the Gram launch (64 or 128)
+ *   info[1] Gram work items (output tile x fold row range)
+ *   info[2] slabs (per-fold row splits whose partial products are summed)
+ *   info[3] 1 for the fused fold path (many small folds), else 0
+ * n is the capacity of info (at most 4 entries are written). */
+cvgram_status cvgram_plan_info(cvgram_t h, int64_t* info, int32_t n);
 
 /* Change the stream used by later calls on this handle. */
 cvgram_status cvgram_set_stream(cvgram_t h, void* stream);

@@ -15,7 +15,7 @@ import re
 
 __all__ = [
     "CVGramError", "lib_path", "load", "exported_symbols", "header_symbols",
-    "cvgram_create", "cvgram_num_folds", "cvgram_partition", "cvgram_fold",
+    "cvgram_create", "cvgram_num_folds", "cvgram_plan_info", "cvgram_partition", "cvgram_fold",
     "cvgram_fold_combo", "cvgram_fold_leaky", "LEAK_KINDS", "cvgram_ridge", "cvgram_folds_all", "cvgram_fold_stats", "cvgram_set_stream",
     "cvgram_destroy", "cvgram_status_string", "cvgram_last_error_message", "cvgram_version",
     "cvgram_set_stage_timing", "cvgram_stage_times", "cvgram_trim_cache",
@@ -34,7 +34,7 @@ XTX_CLASSES = 4
 XTY_CLASSES = 8
 
 STATUS = {0: "CVGRAM_OK", 1: "CVGRAM_EINVAL", 2: "CVGRAM_EFOLDS", 3: "CVGRAM_ENOTSCALABLE",
-          4: "CVGRAM_ENOMEM", 5: "CVGRAM_EDEVICE", 6: "CVGRAM_ERANGE"}
+          4: "CVGRAM_ENOMEM", 5: "CVGRAM_EDEVICE", 6: "CVGRAM_ERANGE", 7: "CVGRAM_ESINGULAR"}
 
 
 class CVGramError(RuntimeError):
@@ -58,6 +58,7 @@ _SIGS = {
     "cvgram_create": (_int, [_vp, _vp, _vp, _i64, _i64, _i64, _int, _int, _int, _int, _int, _int,
                              _int, _vp, ctypes.POINTER(_vp)]),
     "cvgram_num_folds": (_int, [_vp, ctypes.POINTER(_i32)]),
+    "cvgram_plan_info": (_int, [_vp, ctypes.POINTER(_i64), _i32]),
     "cvgram_partition": (_int, [_vp, _vp, _vp]),
     "cvgram_fold": (_int, [_vp, _i32, _vp, _vp]),
     "cvgram_fold_combo": (_int, [_vp, _i32, _int, _int, _int, _int, _vp, _vp]),
@@ -202,6 +203,14 @@ def cvgram_num_folds(h: Handle) -> int:
     P = _i32()
     _check(load().cvgram_num_folds(h.ptr, ctypes.byref(P)))
     return P.value
+
+
+def cvgram_plan_info(h: Handle) -> dict:
+    """The plan the handle's launch used: tile edge, Gram work items, slabs,
+    and whether the fused fold path was taken."""
+    info = (_i64 * 4)()
+    _check(load().cvgram_plan_info(h.ptr, info, 4))
+    return {"tile": info[0], "items": info[1], "slabs": info[2], "fused": bool(info[3])}
 
 
 def cvgram_partition(h: Handle, perm=None, offsets=None):

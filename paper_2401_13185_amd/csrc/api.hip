@@ -1149,6 +1149,15 @@ cvgram_status cvgram_trim_cache(void) {
   return CVGRAM_OK;
 }
 
+cvgram_status cvgram_plan_info(cvgram_t h, int64_t* info, int32_t n) {
+  if (!h || (!info && n > 0)) return fail(CVGRAM_EINVAL, "NULL argument");
+  const Batch& b = h->b;
+  const ProbPlan& p = b.pp[0];
+  const int64_t v[4] = {p.cfg.tile, b.n_work64 + b.n_work128, p.n_slabs, p.fused ? 1 : 0};
+  for (int32_t k = 0; k < n && k < 4; ++k) info[k] = v[k];
+  return CVGRAM_OK;
+}
+
 cvgram_status cvgram_set_stream(cvgram_t h, void* stream) {
   if (!h) return fail(CVGRAM_EINVAL, "NULL handle");
   h->b.stream = (hipStream_t)stream;

@@ -238,3 +238,18 @@ def test_many_folds_extrema_across_fold_ranges(path):
                     label=f"ranges-{path}")
     assert np.all(xx[611, 2][2] == 0.0)          # column 2 constant over T of fold 611
     assert np.any(xx[17, 2][5] != 0.0)           # column 5 still varies without fold 17
+
+
+def test_plan_info_reports_fold_path():
+    """cvgram_plan_info names the path the library chose (and the forced one)."""
+    X, Y = _gaussian(600, 20, 2, 3)
+    fold = np.random.default_rng(9).permutation(600).astype(np.int32) % 200  # 200 folds of 3
+    infos = {}
+    for path in (None, "grouped", "fused"):
+        with ForcedFoldPath(path):
+            h = cv.cvgram_create(_t(X), _t(Y), _t(fold), 1, 0, 1, 0, ddof=1, mode="fp64")
+        infos[path] = cv.cvgram_plan_info(h)
+        cv.cvgram_destroy(h)
+    assert infos[None]["fused"] and infos["fused"]["fused"] and not infos["grouped"]["fused"]
+    for info in infos.values():
+        assert info["tile"] == 64 and info["items"] > 0 and info["slabs"] > 0
