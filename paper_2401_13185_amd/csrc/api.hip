@@ -302,6 +302,9 @@ struct Batch {
   int64_t n_range_items = 0;
   GramWork* d_work = nullptr;
   int64_t n_work64 = 0, n_work128 = 0;
+  int32_t* d_xcd64 = nullptr;     // per-XCD item ranges of the two launches
+  int32_t* d_xcd128 = nullptr;
+  int64_t grid64 = 0, grid128 = 0;  // largest per-XCD item count
   Item* d_red_items = nullptr;
   int64_t n_red_items = 0;
   Item* d_corr_items = nullptr;
@@ -452,6 +455,8 @@ struct HostLists {
       corr_items;
   std::vector<PackChunk> chunks;
   std::vector<GramWork> work64, work128;
+  // per-XCD item ranges of each Gram launch (kXcds + 1 offsets each)
+  std::vector<int32_t> xcd64, xcd128;
   // empty every list, keeping its memory (the lists are reused per thread:
   // no allocation or first-touch page faults on the planning path)
   void clear() {
@@ -461,6 +466,8 @@ struct HostLists {
     chunks.clear();
     work64.clear();
     work128.clear();
+    xcd64.clear();
+    xcd128.clear();
   }
 };
 
@@ -478,6 +485,67 @@ bool choose_fused(const ProbPlan& p) {
   int64_t max_fold = 0;
   for (int32_t q = 0; q < p.P; ++q) max_fold = std::max(max_fold, p.offsets[q + 1] - p.offsets[q]);
   return p.P >= kFusedMinFolds && max_fold <= kFusedMaxFoldRows;
+}
+
+// Order of a Gram launch's items.  The kernel maps workgroup b to item
+// xcd[b % 8] + b / 8 of XCD b % 8's range.  A single problem keeps the list
+// order in 8 equal ranges (its items are of similar size; the tiles of one
+// fold row range are consecutive, so they run on one XCD and share its L2).
+// A batch mixes items of very different sizes: a unit is one fold row range
+// of one problem with all its output tiles, units are taken longest first
+// and each goes to the XCD with the least work so far (LPT), and an XCD runs
+// its units longest first.  Reordering is free: every item writes its own
+// slab, summed later in slab order.
+void schedule_gram(std::vector<GramWork>& wl, std::vector<int32_t>& xcd, bool balance) {
+  xcd.assign(kXcds + 1, 0);
+  if (wl.empty()) return;
+  const int32_t n = (int32_t)wl.size();
+  if (!balance) {
+    const int32_t per = (n + kXcds - 1) / kXcds;
+    for (int x = 0; x <= kXcds; ++x) xcd[x] = std::min(n, x * per);
+    return;
+  }
+  struct Unit {
+    int64_t cost;
+    int32_t begin, end;
+  };
+  // scratch kept per thread (no allocation once warm)
+  thread_local std::vector<Unit> units_tl;
+  thread_local std::vector<GramWork> out_tl;
+  std::vector<Unit>& units = units_tl;
+  std::vector<GramWork>& out = out_tl;
+  units.clear();
+  for (int32_t i = 0; i < n;) {
+    int32_t j = i + 1;
+    while (j < n && wl[j].prob == wl[i].prob && wl[j].slab == wl[i].slab) ++j;
+    // rows x tiles, plus a per-item allowance for the first stage and the
+    // tile store (about two panels)
+    units.push_back({(int64_t)(j - i) * (wl[i].r1 - wl[i].r0 + 2 * kPanelRows), i, j});
+    i = j;
+  }
+  // longest first; ties in list order (a total order: deterministic)
+  std::sort(units.begin(), units.end(), [](const Unit& a, const Unit& c) {
+    return a.cost != c.cost ? a.cost > c.cost : a.begin < c.begin;
+  });
+  int64_t load[kXcds] = {};
+  int32_t count[kXcds] = {};
+  for (Unit& u : units) {
+    int x = 0;
+    for (int y = 1; y < kXcds; ++y)
+      if (load[y] < load[x]) x = y;
+    load[x] += u.cost;
+    count[x] += u.end - u.begin;
+    u.cost = x;  // the unit's XCD from here on
+  }
+  for (int x = 0; x < kXcds; ++x) xcd[x + 1] = xcd[x] + count[x];
+  int32_t fill[kXcds];
+  for (int x = 0; x < kXcds; ++x) fill[x] = xcd[x];
+  out.resize(wl.size());
+  for (const Unit& u : units) {
+    const int x = (int)u.cost;
+    for (int32_t i = u.begin; i < u.end; ++i) out[fill[x]++] = wl[i];
+  }
+  wl.swap(out);
 }
 
 void plan_layout(Batch& b, HostLists& L) {
@@ -624,6 +692,8 @@ void plan_layout(Batch& b, HostLists& L) {
         for (int32_t tl = 0; tl < p.n_ctiles_xx + p.n_ctiles_xy; ++tl)
           L.corr_items.push_back({pi, q, tl});
   }
+  schedule_gram(L.work64, L.xcd64, b.pp.size() > 1);
+  schedule_gram(L.work128, L.xcd128, b.pp.size() > 1);
 }
 
 // the plan blob: segments at 256-byte aligned offsets.  Laid out twice:
@@ -688,7 +758,7 @@ void allocate_and_upload(Batch& b, const HostLists& L) {
   std::vector<size_t> o_offsets(b.pp.size()), o_poff(b.pp.size()), o_cbeg(b.pp.size()),
       o_sbeg(b.pp.size()), o_ctiles(b.pp.size());
   size_t o_pd = 0, o_out = 0, o_pivot = 0, o_chunks = 0, o_fold = 0, o_sr = 0, o_fs = 0,
-         o_cb = 0, o_range = 0, o_work = 0, o_red = 0, o_corr = 0;
+         o_cb = 0, o_range = 0, o_work = 0, o_red = 0, o_corr = 0, o_xcd64 = 0, o_xcd128 = 0;
   auto layout = [&](Blob& blob) {
     for (size_t i = 0; i < b.pp.size(); ++i) {
       o_offsets[i] = blob.put(b.pp[i].offsets);
@@ -710,6 +780,8 @@ void allocate_and_upload(Batch& b, const HostLists& L) {
     blob.put(L.work128, false);  // right after the 64-wide items: one array
     o_red = blob.put(L.red_items);
     o_corr = blob.put(L.corr_items);
+    o_xcd64 = blob.put(L.xcd64);
+    o_xcd128 = blob.put(L.xcd128);
   };
   Blob measure;
   layout(measure);
@@ -807,6 +879,15 @@ void allocate_and_upload(Batch& b, const HostLists& L) {
   b.d_work = (GramWork*)(dblob + o_work);
   b.n_work64 = (int64_t)L.work64.size();
   b.n_work128 = (int64_t)L.work128.size();
+  b.d_xcd64 = (int32_t*)(dblob + o_xcd64);
+  b.d_xcd128 = (int32_t*)(dblob + o_xcd128);
+  auto widest = [](const std::vector<int32_t>& x) {
+    int64_t m = 0;
+    for (size_t i = 0; i + 1 < x.size(); ++i) m = std::max<int64_t>(m, x[i + 1] - x[i]);
+    return m;
+  };
+  b.grid64 = widest(L.xcd64);
+  b.grid128 = widest(L.xcd128);
   b.d_red_items = (Item*)(dblob + o_red);
   b.n_red_items = (int64_t)L.red_items.size();
   b.d_corr_items = (Item*)(dblob + o_corr);
@@ -832,8 +913,8 @@ void run_pipeline(Batch& b, bool with_events) {
   launch_fold_totals(b.d_pd, b.d_range_items, b.n_range_items, b.d_cb_items, b.n_cb_items, s);
   launch_train_stats(b.d_pd, b.d_fold_items, b.n_fold_items, b.max_cb256, s);
   mark(2);
-  launch_gram(b.mode, 64, b.d_pd, b.d_work, b.n_work64, s);
-  launch_gram(b.mode, 128, b.d_pd, b.d_work + b.n_work64, b.n_work128, s);
+  launch_gram(b.mode, 64, b.d_pd, b.d_work, b.d_xcd64, b.grid64, s);
+  launch_gram(b.mode, 128, b.d_pd, b.d_work + b.n_work64, b.d_xcd128, b.grid128, s);
   mark(3);
   launch_reduce_slabs(b.d_pd, b.d_red_items, b.n_red_items, s);
   if (b.batched)

@@ -33,8 +33,9 @@
 // direct-to-LDS loads (no register staging, no LDS store instructions), three
 // stages ahead of the matrix cores; 16-byte chunks are XOR-swizzled per
 // column so the fragment reads are free of bank conflicts.  Work items are
-// mapped XCD-aware (each of the 8 XCDs takes a contiguous range of items, so
-// tiles that read the same rows share an L2).
+// mapped XCD-aware: each of the 8 XCDs runs its own range of the list (the
+// planner balances the ranges and keeps the tiles that read the same rows
+// in one range, where they share the XCD's L2).
 #include "internal.h"
 
 #include <type_traits>
@@ -337,7 +338,7 @@ __device__ inline void store_tile(CVG_GLOBAL double* out, int role, bool xy_tile
 template <int MODE, int BM>
 __global__ __launch_bounds__(kThreads) void gram_kernel(const ProbDesc* __restrict__ pds,
                                                         const GramWork* __restrict__ work,
-                                                        int64_t n_work) {
+                                                        const int32_t* __restrict__ xcd) {
   typedef typename Mode<MODE>::Acc Acc;
   constexpr int BK = Mode<MODE>::BK;
   constexpr bool kF64 = MODE == CVGRAM_MODE_FP64;
@@ -347,9 +348,9 @@ __global__ __launch_bounds__(kThreads) void gram_kernel(const ProbDesc* __restri
   constexpr int NACC = NW * NW > 2 * NY ? NW * NW : 2 * NY;
   __shared__ __attribute__((aligned(16))) Smem<MODE, BM> sm;
 
-  const int64_t per = (int64_t)gridDim.x / 8;
-  const int64_t item = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
-  if (item >= n_work) return;
+  const int x = (int)(blockIdx.x % kXcds);
+  const int64_t item = (int64_t)xcd[x] + blockIdx.x / kXcds;
+  if (item >= xcd[x + 1]) return;
   const GramWork w = work[item];
   // descriptor fields in registers (never re-read inside the loop)
   const ProbDesc& pdr = pds[w.prob];
@@ -579,16 +580,16 @@ __device__ __forceinline__ void dma16(const CVG_GLOBAL char* src, __bf16* dst) {
 template <int BM>
 __global__ __launch_bounds__(kThreads) void gram_bf16_kernel(const ProbDesc* __restrict__ pds,
                                                              const GramWork* __restrict__ work,
-                                                             int64_t n_work) {
+                                                             const int32_t* __restrict__ xcd) {
   constexpr int MODE = CVGRAM_MODE_BF16X3;
   constexpr int WT = BM / 2, NW = WT / 16, NY = BM / 16;
   constexpr int NACC = NW * NW > 2 * NY ? NW * NW : 2 * NY;
   constexpr int IA = BM / 64;  // 1 KB direct loads per wave per array per stage
   __shared__ __attribute__((aligned(1024))) DmaBuf<BM> sb0, sb1, sb2, sb3;
 
-  const int64_t per = (int64_t)gridDim.x / 8;
-  const int64_t item = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
-  if (item >= n_work) return;
+  const int x = (int)(blockIdx.x % kXcds);
+  const int64_t item = (int64_t)xcd[x] + blockIdx.x / kXcds;
+  if (item >= xcd[x + 1]) return;
   const GramWork w = work[item];
   const ProbDesc& pdr = pds[w.prob];
   const int64_t Wp = pdr.Wp, Kp = pdr.Kp, K = pdr.K, M = pdr.M;
@@ -748,19 +749,19 @@ __global__ __launch_bounds__(kThreads) void gram_bf16_kernel(const ProbDesc* __r
 }
 
 template <int MODE>
-void launch_mode(int tile, const ProbDesc* pd, const GramWork* work, int64_t n_work,
-                 hipStream_t s) {
-  const unsigned grid = (unsigned)(8 * ((n_work + 7) / 8));
+void launch_mode(int tile, const ProbDesc* pd, const GramWork* work, const int32_t* xcd,
+                 int64_t per_xcd, hipStream_t s) {
+  const unsigned grid = (unsigned)(kXcds * per_xcd);
   if constexpr (MODE == CVGRAM_MODE_BF16X3) {
     if (tile == 64)
-      gram_bf16_kernel<64><<<grid, kThreads, 0, s>>>(pd, work, n_work);
+      gram_bf16_kernel<64><<<grid, kThreads, 0, s>>>(pd, work, xcd);
     else
-      gram_bf16_kernel<128><<<grid, kThreads, 0, s>>>(pd, work, n_work);
+      gram_bf16_kernel<128><<<grid, kThreads, 0, s>>>(pd, work, xcd);
   } else {
     if (tile == 64)
-      gram_kernel<MODE, 64><<<grid, kThreads, 0, s>>>(pd, work, n_work);
+      gram_kernel<MODE, 64><<<grid, kThreads, 0, s>>>(pd, work, xcd);
     else
-      gram_kernel<MODE, 128><<<grid, kThreads, 0, s>>>(pd, work, n_work);
+      gram_kernel<MODE, 128><<<grid, kThreads, 0, s>>>(pd, work, xcd);
   }
   CVG_LAUNCH_CHECK();
 }
@@ -768,14 +769,14 @@ void launch_mode(int tile, const ProbDesc* pd, const GramWork* work, int64_t n_w
 }  // namespace
 
 void launch_gram(cvgram_mode mode, int tile, const ProbDesc* pd, const GramWork* work,
-                 int64_t n_work, hipStream_t s) {
-  if (n_work <= 0) return;
+                 const int32_t* xcd, int64_t per_xcd, hipStream_t s) {
+  if (per_xcd <= 0) return;
   if (mode == CVGRAM_MODE_FP64)
-    launch_mode<CVGRAM_MODE_FP64>(tile, pd, work, n_work, s);
+    launch_mode<CVGRAM_MODE_FP64>(tile, pd, work, xcd, per_xcd, s);
   else if (mode == CVGRAM_MODE_FP32)
-    launch_mode<CVGRAM_MODE_FP32>(tile, pd, work, n_work, s);
+    launch_mode<CVGRAM_MODE_FP32>(tile, pd, work, xcd, per_xcd, s);
   else
-    launch_mode<CVGRAM_MODE_BF16X3>(tile, pd, work, n_work, s);
+    launch_mode<CVGRAM_MODE_BF16X3>(tile, pd, work, xcd, per_xcd, s);
 }
 
 }  // namespace cvg

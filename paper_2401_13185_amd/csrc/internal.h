@@ -61,6 +61,9 @@ constexpr int kPanelRows = 32;
 constexpr int kYDiagCols = 32;
 // pack pass: a workgroup packs kPackCols columns of 32-row panels
 constexpr int kPackCols = 256;
+// accelerator dies (XCDs) of the part; consecutive workgroup ids go to
+// different XCDs round-robin, each XCD with its own L2
+constexpr int kXcds = 8;
 // correction tiles
 constexpr int kCorrTile = 32;
 // fold totals: folds per partial range
@@ -208,8 +211,11 @@ void launch_fold_stats(const double* tr_mu, const double* tr_std, int32_t p, int
                        int64_t M, double* mx, double* sx, double* my, double* sy, hipStream_t s);
 
 // gram.hip
+// xcd: kXcds + 1 offsets into work, the item range of each XCD; workgroup b
+// runs item xcd[b % kXcds] + b / kXcds of its range (per_xcd = the largest
+// range, so the grid is kXcds * per_xcd workgroups)
 void launch_gram(cvgram_mode mode, int tile, const ProbDesc* pd, const GramWork* work,
-                 int64_t n_work, hipStream_t s);
+                 const int32_t* xcd, int64_t per_xcd, hipStream_t s);
 
 // correct.hip
 // items: (prob, block of 256 entries of K x W, -)
