@@ -340,7 +340,7 @@ int bit_length(uint32_t v) {
   return b;
 }
 
-constexpr int64_t kPackTargetBlocks = 1024;
+constexpr int64_t kPackTargetBlocks = 4096;  // pack workgroups (one wave each) to aim for
 constexpr int64_t kMaxChunkRows = 1024;   // multiple of kPanelRows
 constexpr int64_t kGramMinRows = 256;
 

@@ -60,7 +60,7 @@ constexpr int kPanelRows = 32;
 // computed inside diagonal tiles when M <= kYDiagCols.
 constexpr int kYDiagCols = 32;
 // pack pass: a workgroup packs kPackCols columns of 32-row panels
-constexpr int kPackCols = 256;
+constexpr int kPackCols = 64;
 // accelerator dies (XCDs) of the part; consecutive workgroup ids go to
 // different XCDs round-robin, each XCD with its own L2
 constexpr int kXcds = 8;

@@ -14,11 +14,14 @@
 // with z' = z - c in FP64 (FP64 mode) or fp32(z - c) (mixed modes), and the
 // split hi = bf16(z'), lo = bf16(z' - hi).
 //
-// Work shape: a 256-thread workgroup handles one chunk (whole 32-row panels
-// of one fold) x 256 packed columns.  Each thread loads 4 consecutive
-// columns of 8 rows per panel (16-byte loads when the columns allow it);
-// the bf16 panels are transposed through LDS so that every global store is
-// a contiguous 16-byte chunk of a fully written line.
+// Work shape: a one-wave workgroup handles one chunk (whole 32-row panels
+// of one fold) x kPackCols = 64 packed columns, so that narrow problems
+// (K + M of a few dozen) and the Y columns at the end of a row keep almost
+// every lane busy.  Lane l loads columns 4 (l % 16) .. + 3 of rows
+// 8 (l / 16) .. + 7 of each panel (16-byte loads when the columns allow it:
+// eight rows x one or two loads in flight per lane); the bf16 panels are
+// transposed through LDS so that every global store is a contiguous 16-byte
+// chunk of a fully written line.
 #include <cmath>
 
 #include "internal.h"
@@ -131,14 +134,16 @@ __device__ inline void load4(const CVG_GLOBAL T* __restrict__ X, const CVG_GLOBA
 }
 
 constexpr int LDK = kPanelRows + 8;  // bf16 per column in the LDS transpose (80 B)
+constexpr int kPackThreads = kPackCols;    // one lane per 4 columns x 4 row groups
+constexpr int kColGroups = kPackCols / 4;  // lanes per row group
 
 template <typename T, int MODE>
-__global__ __launch_bounds__(256) void pack_kernel(const ProbDesc* __restrict__ pds,
-                                                   const PackChunk* __restrict__ chunks) {
+__global__ __launch_bounds__(kPackThreads) void pack_kernel(const ProbDesc* __restrict__ pds,
+                                                            const PackChunk* __restrict__ chunks) {
   constexpr int kT = MODE == CVGRAM_MODE_BF16X3 ? kPackCols * LDK : 8;
   __shared__ __attribute__((aligned(16))) __bf16 th[kT];
   __shared__ __attribute__((aligned(16))) __bf16 tl[kT];
-  __shared__ double red[256 * 4];
+  __shared__ double red[kPackThreads * 4];
 
   const PackChunk ch = chunks[blockIdx.x];
   // descriptor fields in registers (the loops below store through other
@@ -157,7 +162,7 @@ __global__ __launch_bounds__(256) void pack_kernel(const ProbDesc* __restrict__ 
   const int64_t n_chunks = pdr.n_chunks;
   const int x_vec = pdr.x_vec;
   const int64_t K = pdr.K, M = pdr.M, Kp = pdr.Kp, W = pdr.W;
-  const int t = threadIdx.x, cg = t & 63, rg = t >> 6;
+  const int t = threadIdx.x, cg = t % kColGroups, rg = t / kColGroups;
   const int64_t jp0 = cb0 + 4 * cg;
 
   int64_t js[4];
@@ -240,7 +245,7 @@ __global__ __launch_bounds__(256) void pack_kernel(const ProbDesc* __restrict__ 
       const int64_t base = ((d0 / kPanelRows) * Wp + cb0) * kPanelRows;
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
-        const int qc = t + 256 * k;  // 16-byte chunk: column qc / 4, rows 8 (qc % 4) ..
+        const int qc = t + kPackThreads * k;  // 16-byte chunk: column qc / 4, rows 8 (qc % 4) ..
         if (cb0 + (qc >> 2) < Wp) {
           *(CVG_GLOBAL bf16x8_t*)&hi[base + qc * 8] =
               *(const bf16x8_t*)&th[(qc >> 2) * LDK + (qc & 3) * 8];
@@ -282,7 +287,7 @@ __global__ __launch_bounds__(256) void pack_kernel(const ProbDesc* __restrict__ 
     }
   }
 
-  // combine the 4 row groups (waves) of each column, in wave order
+  // combine the 4 row groups of each column, in row-group order
   const int64_t stride = n_chunks * W;
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
@@ -295,7 +300,7 @@ __global__ __launch_bounds__(256) void pack_kernel(const ProbDesc* __restrict__ 
       for (int u = 0; u < 4; ++u) {
         double r = red[cg * 4 + u];
         for (int g = 1; g < 4; ++g) {
-          const double o = red[(g * 64 + cg) * 4 + u];
+          const double o = red[(g * kColGroups + cg) * 4 + u];
           r = k < 2 ? r + o : (k == 2 ? fmin(r, o) : fmax(r, o));
         }
         if (js[u] >= 0) part[k * stride + (int64_t)ch.chunk * W + js[u]] = r;
@@ -310,11 +315,11 @@ void launch_pack_typed(cvgram_mode mode, const ProbDesc* pd, const PackChunk* ch
                        int64_t n_chunks, int32_t max_col_blocks, hipStream_t s) {
   dim3 grid((unsigned)n_chunks, (unsigned)max_col_blocks);
   if (mode == CVGRAM_MODE_FP64)
-    pack_kernel<T, CVGRAM_MODE_FP64><<<grid, 256, 0, s>>>(pd, chunks);
+    pack_kernel<T, CVGRAM_MODE_FP64><<<grid, kPackThreads, 0, s>>>(pd, chunks);
   else if (mode == CVGRAM_MODE_FP32)
-    pack_kernel<T, CVGRAM_MODE_FP32><<<grid, 256, 0, s>>>(pd, chunks);
+    pack_kernel<T, CVGRAM_MODE_FP32><<<grid, kPackThreads, 0, s>>>(pd, chunks);
   else
-    pack_kernel<T, CVGRAM_MODE_BF16X3><<<grid, 256, 0, s>>>(pd, chunks);
+    pack_kernel<T, CVGRAM_MODE_BF16X3><<<grid, kPackThreads, 0, s>>>(pd, chunks);
   CVG_LAUNCH_CHECK();
 }
 
