@@ -10,7 +10,8 @@
 //     panel:  L_ij = A_ij L_jj^{-T} for every block row i > j
 //     update: A_ik -= L_ij L_kj^T for every j < k <= i (lower triangle)
 // then R is overwritten by L^{-T} L^{-1} R with the same blocks (forward and
-// backward substitution through the stored inverses of the diagonal blocks).
+// backward substitution through the stored inverses of the diagonal blocks,
+// one launch for both).
 // A matrix whose pivot is not positive (A + lambda I not positive definite)
 // sets its flag and continues with NaN.
 //
@@ -79,16 +80,19 @@ __global__ __launch_bounds__(kThreads) void chol_diag_kernel(double* __restrict_
       if (r > c && tx > c && tx <= r) L[r][tx] = fma(-L[r][c], L[tx][c], L[r][tx]);
     __syncthreads();
   }
-  // inverse of the lower factor, one column per thread: L X = I
-  if (t < NB) {
-    const int col = t;
-    for (int r = 0; r < NB; ++r) {
-      double s = r == col ? 1.0 : 0.0;
-      for (int k = col; k < r; ++k) s = fma(-L[r][k], I[k][col], s);
-      I[r][col] = r < col ? 0.0 : s / L[r][r];
-    }
-  }
+  // inverse of the lower factor, L X = I, by right-looking elimination over
+  // the rows of X: at step c row c is divided by the pivot and then removed
+  // from the rows below, all 32 x 32 entries in parallel (each entry sums in
+  // increasing c, the order of plain forward substitution)
+  for (int r = ty; r < NB; r += kThreads / NB) I[r][tx] = r == tx ? 1.0 : 0.0;
   __syncthreads();
+  for (int c = 0; c < NB; ++c) {
+    if (t < NB) I[c][t] = I[c][t] / L[c][c];
+    __syncthreads();
+    for (int r = ty; r < NB; r += kThreads / NB)
+      if (r > c) I[r][tx] = fma(-L[r][c], I[c][tx], I[r][tx]);
+    __syncthreads();
+  }
   CVG_GLOBAL double* li = gmem(Linv) + (mat * nblk + j) * NB * NB;
   for (int r = ty; r < NB; r += kThreads / NB) {
     const int64_t i = r0 + r, c = r0 + tx;
@@ -155,62 +159,69 @@ __global__ __launch_bounds__(kThreads) void chol_update_kernel(double* __restric
   }
 }
 
-// forward step j: Z_j = Linv_jj R_j; then R_i -= L_ij Z_j for i > j.
-// backward step j: W_j = Linv_jj^T R_j; then R_i -= L_ji^T W_j for i < j.
-// grid (matrices, column blocks of R of 32); one workgroup walks the rows.
-__global__ __launch_bounds__(kThreads) void tri_solve_step_kernel(const double* __restrict__ A,
-                                                                  const double* __restrict__ Linv,
-                                                                  double* __restrict__ R,
-                                                                  int64_t K, int64_t M, int32_t j,
-                                                                  int32_t nblk, int backward) {
+// Both substitutions in one launch: workgroup (matrix, block of 32 columns
+// of R) walks the block steps itself.
+//   forward step j:  Z_j = Linv_jj R_j;    R_i -= L_ij Z_j     for i > j
+//   backward step j: W_j = Linv_jj^T R_j;  R_i -= L_ji^T W_j   for i < j
+// The updates run over (row, column) pairs of the other block rows, so a
+// narrow R (M of a few columns) keeps every lane busy.  Each workgroup owns
+// its rows x columns of R: its own writes are the only ones it reads back
+// (ordered by the barrier between steps).
+__global__ __launch_bounds__(kThreads) void tri_solve_kernel(const double* __restrict__ A,
+                                                             const double* __restrict__ Linv,
+                                                             double* __restrict__ R, int64_t K,
+                                                             int64_t M, int32_t nblk) {
   __shared__ double Z[NB][NB + 1];
   __shared__ double Li[NB][NB + 1];
   __shared__ double Rb[NB][NB + 1];
   const int64_t mat = blockIdx.x;
   const int64_t m0 = (int64_t)blockIdx.y * NB;
+  const int64_t mw = M - m0 < NB ? M - m0 : NB;  // columns of R in this block
   const CVG_GLOBAL double* a = gmem(A) + mat * K * K;
-  const CVG_GLOBAL double* li = gmem(Linv) + (mat * nblk + j) * NB * NB;
   CVG_GLOBAL double* rr = gmem(R) + mat * K * M;
   const int t = threadIdx.x, tx = t % NB, ty = t / NB;
-  const int64_t r0 = (int64_t)j * NB;
-  for (int r = ty; r < NB; r += kThreads / NB) {
-    const int64_t i = r0 + r, m = m0 + tx;
-    Rb[r][tx] = (i < K && m < M) ? rr[i * M + m] : 0.0;
-    Li[r][tx] = li[r * NB + tx];
-  }
-  __syncthreads();
-  for (int r = ty; r < NB; r += kThreads / NB) {
-    double s = 0.0;
-    if (!backward)
-      for (int k = 0; k <= r; ++k) s = fma(Li[r][k], Rb[k][tx], s);
-    else
-      for (int k = r; k < NB; ++k) s = fma(Li[k][r], Rb[k][tx], s);
-    Z[r][tx] = s;
-    const int64_t i = r0 + r, m = m0 + tx;
-    if (i < K && m < M) rr[i * M + m] = s;
-  }
-  __syncthreads();
-  // propagate to the other block rows (one block row per pass of the loop)
-  const int32_t lo = backward ? 0 : j + 1, hi = backward ? j : nblk;
-  for (int32_t ib = lo; ib < hi; ++ib) {
-    for (int r = ty; r < NB; r += kThreads / NB) {
-      const int64_t i = (int64_t)ib * NB + r, m = m0 + tx;
-      if (i >= K || m >= M) continue;
-      double s = 0.0;
-      if (!backward) {
-        // L_ij = A[i][r0 + c]
-        for (int c = 0; c < NB; ++c) {
-          const int64_t cc = r0 + c;
-          if (cc < K) s = fma(a[i * K + cc], Z[c][tx], s);
-        }
-      } else {
-        // (L_ji)^T[r][c] = A[r0 + c][i]
-        for (int c = 0; c < NB; ++c) {
-          const int64_t cc = r0 + c;
-          if (cc < K) s = fma(a[cc * K + i], Z[c][tx], s);
-        }
+  for (int pass = 0; pass < 2; ++pass) {
+    const bool backward = pass == 1;
+    for (int32_t jj = 0; jj < nblk; ++jj) {
+      const int32_t j = backward ? nblk - 1 - jj : jj;
+      const int64_t r0 = (int64_t)j * NB;
+      const CVG_GLOBAL double* li = gmem(Linv) + (mat * nblk + j) * NB * NB;
+      for (int r = ty; r < NB; r += kThreads / NB) {
+        const int64_t i = r0 + r;
+        Rb[r][tx] = (i < K && tx < mw) ? rr[i * M + m0 + tx] : 0.0;
+        Li[r][tx] = li[r * NB + tx];
       }
-      rr[i * M + m] -= s;
+      __syncthreads();
+      for (int r = ty; r < NB; r += kThreads / NB) {
+        double sum = 0.0;
+        if (!backward)
+          for (int k = 0; k <= r; ++k) sum = fma(Li[r][k], Rb[k][tx], sum);
+        else
+          for (int k = r; k < NB; ++k) sum = fma(Li[k][r], Rb[k][tx], sum);
+        Z[r][tx] = sum;
+        const int64_t i = r0 + r;
+        if (i < K && tx < mw) rr[i * M + m0 + tx] = sum;
+      }
+      __syncthreads();
+      // the other block rows: forward i >= r0 + NB, backward i < r0
+      const int64_t lo = backward ? 0 : r0 + NB, hi = backward ? r0 : K;
+      const int64_t cnt = hi > lo ? (hi - lo) * mw : 0;
+      const int64_t cmax = K - r0 < NB ? K - r0 : NB;  // columns of the block inside K
+      for (int64_t e = t; e < cnt; e += kThreads) {
+        const int64_t i = lo + e / mw;
+        const int mm = (int)(e % mw);
+        double sum = 0.0;
+        if (!backward) {
+          // L_ij = A[i][r0 + c]
+          const CVG_GLOBAL double* row = a + i * K + r0;
+          for (int c = 0; c < cmax; ++c) sum = fma(row[c], Z[c][mm], sum);
+        } else {
+          // (L_ji)^T[i][c] = A[r0 + c][i]
+          for (int c = 0; c < cmax; ++c) sum = fma(a[(r0 + c) * K + i], Z[c][mm], sum);
+        }
+        rr[i * M + m0 + mm] -= sum;
+      }
+      __syncthreads();
     }
   }
 }
@@ -244,16 +255,8 @@ void ridge_solve(const double* xtx, const double* xty, const double* lambdas, in
   }
   if (M <= 0) return;
   const unsigned mb = (unsigned)((M + NB - 1) / NB);
-  for (int32_t j = 0; j < nblk; ++j) {
-    tri_solve_step_kernel<<<dim3((unsigned)n_mat, mb), kThreads, 0, s>>>(A, Linv, R, K, M, j, nblk,
-                                                                         0);
-    CVG_LAUNCH_CHECK();
-  }
-  for (int32_t j = nblk - 1; j >= 0; --j) {
-    tri_solve_step_kernel<<<dim3((unsigned)n_mat, mb), kThreads, 0, s>>>(A, Linv, R, K, M, j, nblk,
-                                                                         1);
-    CVG_LAUNCH_CHECK();
-  }
+  tri_solve_kernel<<<dim3((unsigned)n_mat, mb), kThreads, 0, s>>>(A, Linv, R, K, M, nblk);
+  CVG_LAUNCH_CHECK();
 }
 
 }  // namespace cvg
