@@ -21,6 +21,14 @@ namespace cvg {
 namespace {
 
 constexpr int TS = kCorrTile;  // 32
+
+// workgroup barrier for LDS reuse only: waits for this wave's LDS accesses,
+// not for its global stores (__syncthreads' fence would wait for those too)
+__device__ __forceinline__ void lds_barrier() {
+  // s_waitcnt fields: vmcnt 63 and expcnt 7 (no wait), lgkmcnt 0
+  __builtin_amdgcn_s_waitcnt(0xc07f);
+  asm volatile("s_barrier" ::: "memory");
+}
 constexpr int kThreads = 256;
 constexpr int kRowsPerThread = TS * TS / kThreads;  // 4
 
@@ -107,6 +115,27 @@ __device__ void correct_tile(const ProbDesc& pd, const OutDesc& od, int32_t f, i
   const int t = threadIdx.x;
   const int tx = t % TS, ty = t / TS;
   const int64_t pw = (int64_t)p * W;
+  // this thread's entries; their full-data and (grouped path) fold Gram
+  // values are loaded first, so that these loads and the statistics' loads
+  // below are in flight together
+  bool ok[kRowsPerThread];
+  double gfull[kRowsPerThread], gfold[kRowsPerThread];
+  {
+    const CVG_GLOBAL double* G = gmem((const double*)pd.G);
+    const CVG_GLOBAL double* gp_slab =
+        pd.fused ? nullptr
+                 : gmem((const double*)pd.slabs) + (int64_t)gmem(pd.slab_begin)[p] * K * W;
+#pragma unroll
+    for (int r = 0; r < kRowsPerThread; ++r) {
+      const int il = ty + 8 * r, jl = tx;
+      const int64_t i = (int64_t)bi * TS + il;
+      const int64_t j = (int64_t)bj * TS + jl;
+      ok[r] = i < K && j < ncols && (!diag || il <= jl);
+      const int64_t e = i * W + coff + j;
+      gfull[r] = ok[r] ? G[e] : 0.0;
+      gfold[r] = ok[r] && gp_slab ? gp_slab[e] : 0.0;
+    }
+  }
   if (t < TS) {
     const int64_t i = (int64_t)bi * TS + t;
     if (i < K) {
@@ -151,7 +180,6 @@ __device__ void correct_tile(const ProbDesc& pd, const OutDesc& od, int32_t f, i
   __syncthreads();
 
   const double NT = (double)gmem((const int64_t*)pd.ntrain)[p];
-  const CVG_GLOBAL double* G = gmem((const double*)pd.G);
 
   // G'_p for this thread's entries: the fold's slab sum (grouped path), or
   // formed here from the fold's packed rows in fold order (fused path)
@@ -183,24 +211,15 @@ __device__ void correct_tile(const ProbDesc& pd, const OutDesc& od, int32_t f, i
       __syncthreads();
     }
   }
-  const CVG_GLOBAL double* gp_slab =
-      pd.fused ? nullptr
-               : gmem((const double*)pd.slabs) + (int64_t)gmem(pd.slab_begin)[p] * K * W;
-
   double raw[kRowsPerThread], cen[kRowsPerThread], gT[kRowsPerThread];
-  bool ok[kRowsPerThread];
 #pragma unroll
   for (int r = 0; r < kRowsPerThread; ++r) {
     const int il = ty + 8 * r, jl = tx;
-    const int64_t i = (int64_t)bi * TS + il;
-    const int64_t j = (int64_t)bj * TS + jl;
-    ok[r] = i < K && j < ncols && (!diag || il <= jl);
     raw[r] = 0.0;
     cen[r] = 0.0;
     gT[r] = 0.0;
     if (!ok[r]) continue;
-    const int64_t e = i * W + coff + j;
-    const double g = G[e] - (pd.fused ? gp[r] : gp_slab[e]);
+    const double g = gfull[r] - (pd.fused ? gp[r] : gfold[r]);
     gT[r] = g;
     raw[r] = g + (rc[il] * ca[jl] + ra[il] * cc[jl]) + NT * (rc[il] * cc[jl]);
     cen[r] = (rcs[il] || ccs[jl]) ? 0.0 : g - NT * (rmu[il] * cmu[jl]);
@@ -260,7 +279,7 @@ __device__ void correct_tile(const ProbDesc& pd, const OutDesc& od, int32_t f, i
         if (scaled && ok[r]) v[r] = v[r] / (rsd[il] * csd[jl]);
         if (ok[r]) T[il][jl] = v[r];
       }
-      __syncthreads();
+      lds_barrier();
 #pragma unroll
       for (int r = 0; r < kRowsPerThread; ++r) {
         const int il = ty + 8 * r, jl = tx;
@@ -276,7 +295,7 @@ __device__ void correct_tile(const ProbDesc& pd, const OutDesc& od, int32_t f, i
           if (ti < K && tj < K) out[ti * K + tj] = (OutT)T[jl][il];
         }
       }
-      __syncthreads();
+      lds_barrier();
     }
   } else {
     for (int c = 0; c < CVGRAM_XTY_CLASSES; ++c) {
@@ -306,7 +325,7 @@ __global__ __launch_bounds__(kThreads) void correct_single_kernel(const ProbDesc
   const ProbDesc& pd = pds[prob];
   for (int32_t f = blockIdx.y; f < n_folds; f += gridDim.y) {
     correct_tile<OutT>(pd, od, f, blockIdx.x);
-    __syncthreads();
+    lds_barrier();  // the next fold reuses the LDS arrays
   }
 }
 
