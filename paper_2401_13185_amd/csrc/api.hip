@@ -341,7 +341,6 @@ int bit_length(uint32_t v) {
 }
 
 constexpr int64_t kPackTargetBlocks = 4096;  // pack workgroups (one wave each) to aim for
-constexpr int64_t kMaxChunkRows = 1024;   // multiple of kPanelRows
 constexpr int64_t kGramMinRows = 256;
 
 // Algorithm 1 on the device for every problem, with the checks of
@@ -573,7 +572,7 @@ void plan_layout(Batch& b, HostLists& L) {
     gram_rows += p.Np * ntile;
   }
   int64_t chunk_rows = (pack_cols_rows + kPackTargetBlocks - 1) / kPackTargetBlocks;
-  chunk_rows = std::min(kMaxChunkRows, std::max(PR, (chunk_rows + PR - 1) / PR * PR));
+  chunk_rows = std::min((int64_t)kMaxChunkRows, std::max(PR, (chunk_rows + PR - 1) / PR * PR));
 
   for (size_t i = 0; i < b.pp.size(); ++i) {
     ProbPlan& p = b.pp[i];

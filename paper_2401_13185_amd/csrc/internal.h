@@ -59,8 +59,10 @@ constexpr int kPanelRows = 32;
 // problem's Gram tile), Y columns [Kp, Kp + M), zeros up to Wp.  X^T Y is
 // computed inside diagonal tiles when M <= kYDiagCols.
 constexpr int kYDiagCols = 32;
-// pack pass: a workgroup packs kPackCols columns of 32-row panels
+// pack pass: a workgroup packs kPackCols columns of 32-row panels of one
+// chunk of at most kMaxChunkRows rows (a multiple of kPanelRows)
 constexpr int kPackCols = 64;
+constexpr int kMaxChunkRows = 1024;
 // accelerator dies (XCDs) of the part; consecutive workgroup ids go to
 // different XCDs round-robin, each XCD with its own L2
 constexpr int kXcds = 8;

@@ -23,6 +23,7 @@
 // transposed through LDS so that every global store is a contiguous 16-byte
 // chunk of a fully written line.
 #include <cmath>
+#include <type_traits>
 
 #include "internal.h"
 
@@ -133,6 +134,26 @@ __device__ inline void load4(const CVG_GLOBAL T* __restrict__ X, const CVG_GLOBA
   }
 }
 
+// four consecutive X columns of one row, 16-byte aligned
+template <typename T>
+__device__ inline void load_vec(const CVG_GLOBAL T* __restrict__ X, int64_t K, int64_t row,
+                                int64_t col, double (&x)[4]) {
+  if constexpr (sizeof(T) == 4) {
+    const float4_t v = *(const CVG_GLOBAL float4_t*)&X[row * K + col];
+    x[0] = v.x;
+    x[1] = v.y;
+    x[2] = v.z;
+    x[3] = v.w;
+  } else {
+    const double2_t a = *(const CVG_GLOBAL double2_t*)&X[row * K + col];
+    const double2_t b = *(const CVG_GLOBAL double2_t*)&X[row * K + col + 2];
+    x[0] = a.x;
+    x[1] = a.y;
+    x[2] = b.x;
+    x[3] = b.y;
+  }
+}
+
 constexpr int LDK = kPanelRows + 8;  // bf16 per column in the LDS transpose (80 B)
 constexpr int kPackThreads = kPackCols;    // one lane per 4 columns x 4 row groups
 constexpr int kColGroups = kPackCols / 4;  // lanes per row group
@@ -181,111 +202,135 @@ __global__ __launch_bounds__(kPackThreads) void pack_kernel(const ProbDesc* __re
   double mn[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
   double mx[4] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
 
-  // permutation indices of this thread's 8 rows, one panel ahead
-  int32_t rows_next[8];
-  auto fetch_rows = [&](int64_t d0, int32_t (&r)[8]) {
+  // the chunk's permutation indices (source rows; -1 for padding rows),
+  // staged in LDS once: the panel loop then waits on no global load but its
+  // own data (loads and stores share one counter on this architecture)
+  __shared__ int32_t prow[kMaxChunkRows];
+  const int64_t nrows = ch.d1 - ch.d0;
+  for (int64_t k = t; k < nrows; k += kPackThreads) {
+    const int64_t src = ch.src0 + k;
+    prow[k] = src < ch.src1 ? perm[src] : -1;
+  }
+  __syncthreads();
+  // The panel loop, instantiated twice: a workgroup whose 64 columns are all
+  // X columns (16-byte loads allowed) runs the branch-free load path; the
+  // others (the block that reaches into Y or the padding, unaligned X) run
+  // the general one.  Separate loops keep the general path's loads from
+  // holding up the fast path's.
+  auto panel_loop = [&](auto fast_c) {
+    constexpr bool FAST = decltype(fast_c)::value;
+    for (int64_t d0 = ch.d0; d0 < ch.d1; d0 += kPanelRows) {
+      int32_t rows[8];
 #pragma unroll
-    for (int g = 0; g < 8; ++g) {
-      const int64_t src = ch.src0 + (d0 - ch.d0) + rg * 8 + g;
-      r[g] = (d0 < ch.d1 && src < ch.src1) ? perm[src] : -1;
-    }
-  };
-  fetch_rows(ch.d0, rows_next);
-  for (int64_t d0 = ch.d0; d0 < ch.d1; d0 += kPanelRows) {
-    int32_t rows[8];
+      for (int g = 0; g < 8; ++g) rows[g] = prow[d0 - ch.d0 + rg * 8 + g];
+      double x[8][4];
+      bool v[8];
 #pragma unroll
-    for (int g = 0; g < 8; ++g) rows[g] = rows_next[g];
-    fetch_rows(d0 + kPanelRows, rows_next);
-    double x[8][4];
-    bool v[8];
+      for (int g = 0; g < 8; ++g) v[g] = any && rows[g] >= 0;
+      if (FAST) {
+        // all four columns are X columns: the eight rows' loads are issued
+        // back to back with no branch between them (a padding row reads row 0
+        // and is zeroed), so they are all in flight at once
 #pragma unroll
-    for (int g = 0; g < 8; ++g) {
-      v[g] = any && rows[g] >= 0;
-      if (v[g]) {
-        load4(X, Y, K, M, (int64_t)rows[g], js, vec, x[g]);
+        for (int g = 0; g < 8; ++g) load_vec(X, K, rows[g] >= 0 ? (int64_t)rows[g] : 0, js[0], x[g]);
+#pragma unroll
+        for (int g = 0; g < 8; ++g)
+#pragma unroll
+          for (int u = 0; u < 4; ++u) x[g][u] = v[g] ? x[g][u] : 0.0;
       } else {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) x[g][u] = 0.0;
-      }
-    }
-#pragma unroll
-    for (int g = 0; g < 8; ++g) {
-      if (!v[g]) continue;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        if (js[u] < 0) continue;
-        const double d = x[g][u] - piv[u];
-        s[u] += d;
-        q[u] = fma(d, d, q[u]);
-        mn[u] = fmin(mn[u], x[g][u]);
-        mx[u] = fmax(mx[u], x[g][u]);
-      }
-    }
-    if constexpr (MODE == CVGRAM_MODE_BF16X3) {
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        bf16x8_t h, l;
-#pragma unroll
         for (int g = 0; g < 8; ++g) {
-          const bool ok = v[g] && js[u] >= 0;
-          // z' = fp32(z - c): an exact FP32 subtraction for FP32 input
-          const float zf = !ok ? 0.f
-                           : (sizeof(T) == 4 ? (float)x[g][u] - pivf[u]
-                                             : (float)(x[g][u] - (double)pivf[u]));
-          const __bf16 hh = (__bf16)zf;
-          h[g] = hh;
-          l[g] = (__bf16)(zf - (float)hh);
-        }
-        *(bf16x8_t*)&th[(4 * cg + u) * LDK + rg * 8] = h;
-        *(bf16x8_t*)&tl[(4 * cg + u) * LDK + rg * 8] = l;
-      }
-      __syncthreads();
-      CVG_GLOBAL __bf16* hi = gmem((__bf16*)packed);
-      CVG_GLOBAL __bf16* lo = gmem((__bf16*)packed_lo);
-      const int64_t base = ((d0 / kPanelRows) * Wp + cb0) * kPanelRows;
+          if (v[g]) {
+            load4(X, Y, K, M, (int64_t)rows[g], js, vec, x[g]);
+          } else {
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        const int qc = t + kPackThreads * k;  // 16-byte chunk: column qc / 4, rows 8 (qc % 4) ..
-        if (cb0 + (qc >> 2) < Wp) {
-          *(CVG_GLOBAL bf16x8_t*)&hi[base + qc * 8] =
-              *(const bf16x8_t*)&th[(qc >> 2) * LDK + (qc & 3) * 8];
-          *(CVG_GLOBAL bf16x8_t*)&lo[base + qc * 8] =
-              *(const bf16x8_t*)&tl[(qc >> 2) * LDK + (qc & 3) * 8];
-        }
-      }
-      __syncthreads();
-    } else if constexpr (MODE == CVGRAM_MODE_FP32) {
-      if (jp0 < Wp) {
-        CVG_GLOBAL float* out = gmem((float*)packed);
-#pragma unroll
-        for (int g = 0; g < 8; ++g) {
-          float4_t z;
-#pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const bool ok = v[g] && js[u] >= 0;
-            z[u] = !ok ? 0.f
-                   : (sizeof(T) == 4 ? (float)x[g][u] - pivf[u]
-                                     : (float)(x[g][u] - (double)pivf[u]));
+            for (int u = 0; u < 4; ++u) x[g][u] = 0.0;
           }
-          *(CVG_GLOBAL float4_t*)&out[(d0 + rg * 8 + g) * Wp + jp0] = z;
         }
       }
-    } else {
-      if (jp0 < Wp) {
-        CVG_GLOBAL double* out = gmem((double*)packed);
 #pragma unroll
-        for (int g = 0; g < 8; ++g) {
-          double2_t a, b;
-          a.x = (v[g] && js[0] >= 0) ? x[g][0] - piv[0] : 0.0;
-          a.y = (v[g] && js[1] >= 0) ? x[g][1] - piv[1] : 0.0;
-          b.x = (v[g] && js[2] >= 0) ? x[g][2] - piv[2] : 0.0;
-          b.y = (v[g] && js[3] >= 0) ? x[g][3] - piv[3] : 0.0;
-          *(CVG_GLOBAL double2_t*)&out[(d0 + rg * 8 + g) * Wp + jp0] = a;
-          *(CVG_GLOBAL double2_t*)&out[(d0 + rg * 8 + g) * Wp + jp0 + 2] = b;
+      for (int g = 0; g < 8; ++g) {
+        if (!v[g]) continue;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (js[u] < 0) continue;
+          const double d = x[g][u] - piv[u];
+          s[u] += d;
+          q[u] = fma(d, d, q[u]);
+          mn[u] = fmin(mn[u], x[g][u]);
+          mx[u] = fmax(mx[u], x[g][u]);
+        }
+      }
+      if constexpr (MODE == CVGRAM_MODE_BF16X3) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          bf16x8_t h, l;
+#pragma unroll
+          for (int g = 0; g < 8; ++g) {
+            const bool ok = v[g] && js[u] >= 0;
+            // z' = fp32(z - c): an exact FP32 subtraction for FP32 input
+            const float zf = !ok ? 0.f
+                             : (sizeof(T) == 4 ? (float)x[g][u] - pivf[u]
+                                               : (float)(x[g][u] - (double)pivf[u]));
+            const __bf16 hh = (__bf16)zf;
+            h[g] = hh;
+            l[g] = (__bf16)(zf - (float)hh);
+          }
+          *(bf16x8_t*)&th[(4 * cg + u) * LDK + rg * 8] = h;
+          *(bf16x8_t*)&tl[(4 * cg + u) * LDK + rg * 8] = l;
+        }
+        __syncthreads();
+        CVG_GLOBAL __bf16* hi = gmem((__bf16*)packed);
+        CVG_GLOBAL __bf16* lo = gmem((__bf16*)packed_lo);
+        const int64_t base = ((d0 / kPanelRows) * Wp + cb0) * kPanelRows;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int qc = t + kPackThreads * k;  // 16-byte chunk: column qc / 4, rows 8 (qc % 4) ..
+          if (cb0 + (qc >> 2) < Wp) {
+            *(CVG_GLOBAL bf16x8_t*)&hi[base + qc * 8] =
+                *(const bf16x8_t*)&th[(qc >> 2) * LDK + (qc & 3) * 8];
+            *(CVG_GLOBAL bf16x8_t*)&lo[base + qc * 8] =
+                *(const bf16x8_t*)&tl[(qc >> 2) * LDK + (qc & 3) * 8];
+          }
+        }
+        __syncthreads();
+      } else if constexpr (MODE == CVGRAM_MODE_FP32) {
+        if (jp0 < Wp) {
+          CVG_GLOBAL float* out = gmem((float*)packed);
+#pragma unroll
+          for (int g = 0; g < 8; ++g) {
+            float4_t z;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const bool ok = v[g] && js[u] >= 0;
+              z[u] = !ok ? 0.f
+                     : (sizeof(T) == 4 ? (float)x[g][u] - pivf[u]
+                                       : (float)(x[g][u] - (double)pivf[u]));
+            }
+            *(CVG_GLOBAL float4_t*)&out[(d0 + rg * 8 + g) * Wp + jp0] = z;
+          }
+        }
+      } else {
+        if (jp0 < Wp) {
+          CVG_GLOBAL double* out = gmem((double*)packed);
+#pragma unroll
+          for (int g = 0; g < 8; ++g) {
+            double2_t a, b;
+            a.x = (v[g] && js[0] >= 0) ? x[g][0] - piv[0] : 0.0;
+            a.y = (v[g] && js[1] >= 0) ? x[g][1] - piv[1] : 0.0;
+            b.x = (v[g] && js[2] >= 0) ? x[g][2] - piv[2] : 0.0;
+            b.y = (v[g] && js[3] >= 0) ? x[g][3] - piv[3] : 0.0;
+            *(CVG_GLOBAL double2_t*)&out[(d0 + rg * 8 + g) * Wp + jp0] = a;
+            *(CVG_GLOBAL double2_t*)&out[(d0 + rg * 8 + g) * Wp + jp0 + 2] = b;
+          }
         }
       }
     }
-  }
+  };
+  if (x_vec && cb0 + kPackCols <= K)
+    panel_loop(std::true_type{});
+  else
+    panel_loop(std::false_type{});
 
   // combine the 4 row groups of each column, in row-group order
   const int64_t stride = n_chunks * W;
