@@ -212,125 +212,141 @@ __global__ __launch_bounds__(kPackThreads) void pack_kernel(const ProbDesc* __re
     prow[k] = src < ch.src1 ? perm[src] : -1;
   }
   __syncthreads();
-  // The panel loop, instantiated twice: a workgroup whose 64 columns are all
-  // X columns (16-byte loads allowed) runs the branch-free load path; the
-  // others (the block that reaches into Y or the padding, unaligned X) run
-  // the general one.  Separate loops keep the general path's loads from
-  // holding up the fast path's.
-  auto panel_loop = [&](auto fast_c) {
-    constexpr bool FAST = decltype(fast_c)::value;
-    for (int64_t d0 = ch.d0; d0 < ch.d1; d0 += kPanelRows) {
-      int32_t rows[8];
+  // panel d0: this lane's 8 rows x 4 columns (zero for padding rows)
+  auto load_panel = [&](auto fast_c, int64_t d0, double (&x)[8][4], bool (&v)[8]) {
+    int32_t rows[8];
 #pragma unroll
-      for (int g = 0; g < 8; ++g) rows[g] = prow[d0 - ch.d0 + rg * 8 + g];
-      double x[8][4];
-      bool v[8];
+    for (int g = 0; g < 8; ++g) rows[g] = prow[d0 - ch.d0 + rg * 8 + g];
 #pragma unroll
-      for (int g = 0; g < 8; ++g) v[g] = any && rows[g] >= 0;
-      if (FAST) {
-        // all four columns are X columns: the eight rows' loads are issued
-        // back to back with no branch between them (a padding row reads row 0
-        // and is zeroed), so they are all in flight at once
+    for (int g = 0; g < 8; ++g) v[g] = any && rows[g] >= 0;
+    if constexpr (decltype(fast_c)::value) {
+      // all four columns are X columns: the eight rows' loads are issued
+      // back to back with no branch between them (a padding row reads row 0
+      // and is zeroed), so they are all in flight at once
 #pragma unroll
-        for (int g = 0; g < 8; ++g) load_vec(X, K, rows[g] >= 0 ? (int64_t)rows[g] : 0, js[0], x[g]);
+      for (int g = 0; g < 8; ++g) load_vec(X, K, rows[g] >= 0 ? (int64_t)rows[g] : 0, js[0], x[g]);
 #pragma unroll
-        for (int g = 0; g < 8; ++g)
+      for (int g = 0; g < 8; ++g)
 #pragma unroll
-          for (int u = 0; u < 4; ++u) x[g][u] = v[g] ? x[g][u] : 0.0;
-      } else {
-#pragma unroll
-        for (int g = 0; g < 8; ++g) {
-          if (v[g]) {
-            load4(X, Y, K, M, (int64_t)rows[g], js, vec, x[g]);
-          } else {
-#pragma unroll
-            for (int u = 0; u < 4; ++u) x[g][u] = 0.0;
-          }
-        }
-      }
+        for (int u = 0; u < 4; ++u) x[g][u] = v[g] ? x[g][u] : 0.0;
+    } else {
 #pragma unroll
       for (int g = 0; g < 8; ++g) {
-        if (!v[g]) continue;
+        if (v[g]) {
+          load4(X, Y, K, M, (int64_t)rows[g], js, vec, x[g]);
+        } else {
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          if (js[u] < 0) continue;
-          const double d = x[g][u] - piv[u];
-          s[u] += d;
-          q[u] = fma(d, d, q[u]);
-          mn[u] = fmin(mn[u], x[g][u]);
-          mx[u] = fmax(mx[u], x[g][u]);
-        }
-      }
-      if constexpr (MODE == CVGRAM_MODE_BF16X3) {
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          bf16x8_t h, l;
-#pragma unroll
-          for (int g = 0; g < 8; ++g) {
-            const bool ok = v[g] && js[u] >= 0;
-            // z' = fp32(z - c): an exact FP32 subtraction for FP32 input
-            const float zf = !ok ? 0.f
-                             : (sizeof(T) == 4 ? (float)x[g][u] - pivf[u]
-                                               : (float)(x[g][u] - (double)pivf[u]));
-            const __bf16 hh = (__bf16)zf;
-            h[g] = hh;
-            l[g] = (__bf16)(zf - (float)hh);
-          }
-          *(bf16x8_t*)&th[(4 * cg + u) * LDK + rg * 8] = h;
-          *(bf16x8_t*)&tl[(4 * cg + u) * LDK + rg * 8] = l;
-        }
-        __syncthreads();
-        CVG_GLOBAL __bf16* hi = gmem((__bf16*)packed);
-        CVG_GLOBAL __bf16* lo = gmem((__bf16*)packed_lo);
-        const int64_t base = ((d0 / kPanelRows) * Wp + cb0) * kPanelRows;
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const int qc = t + kPackThreads * k;  // 16-byte chunk: column qc / 4, rows 8 (qc % 4) ..
-          if (cb0 + (qc >> 2) < Wp) {
-            *(CVG_GLOBAL bf16x8_t*)&hi[base + qc * 8] =
-                *(const bf16x8_t*)&th[(qc >> 2) * LDK + (qc & 3) * 8];
-            *(CVG_GLOBAL bf16x8_t*)&lo[base + qc * 8] =
-                *(const bf16x8_t*)&tl[(qc >> 2) * LDK + (qc & 3) * 8];
-          }
-        }
-        __syncthreads();
-      } else if constexpr (MODE == CVGRAM_MODE_FP32) {
-        if (jp0 < Wp) {
-          CVG_GLOBAL float* out = gmem((float*)packed);
-#pragma unroll
-          for (int g = 0; g < 8; ++g) {
-            float4_t z;
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-              const bool ok = v[g] && js[u] >= 0;
-              z[u] = !ok ? 0.f
-                     : (sizeof(T) == 4 ? (float)x[g][u] - pivf[u]
-                                       : (float)(x[g][u] - (double)pivf[u]));
-            }
-            *(CVG_GLOBAL float4_t*)&out[(d0 + rg * 8 + g) * Wp + jp0] = z;
-          }
-        }
-      } else {
-        if (jp0 < Wp) {
-          CVG_GLOBAL double* out = gmem((double*)packed);
-#pragma unroll
-          for (int g = 0; g < 8; ++g) {
-            double2_t a, b;
-            a.x = (v[g] && js[0] >= 0) ? x[g][0] - piv[0] : 0.0;
-            a.y = (v[g] && js[1] >= 0) ? x[g][1] - piv[1] : 0.0;
-            b.x = (v[g] && js[2] >= 0) ? x[g][2] - piv[2] : 0.0;
-            b.y = (v[g] && js[3] >= 0) ? x[g][3] - piv[3] : 0.0;
-            *(CVG_GLOBAL double2_t*)&out[(d0 + rg * 8 + g) * Wp + jp0] = a;
-            *(CVG_GLOBAL double2_t*)&out[(d0 + rg * 8 + g) * Wp + jp0 + 2] = b;
-          }
+          for (int u = 0; u < 4; ++u) x[g][u] = 0.0;
         }
       }
     }
   };
-  if (x_vec && cb0 + kPackCols <= K)
-    panel_loop(std::true_type{});
-  else
-    panel_loop(std::false_type{});
+  // statistics and packed output of panel d0
+  auto consume = [&](int64_t d0, const double (&x)[8][4], const bool (&v)[8]) {
+#pragma unroll
+    for (int g = 0; g < 8; ++g) {
+      if (!v[g]) continue;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (js[u] < 0) continue;
+        const double d = x[g][u] - piv[u];
+        s[u] += d;
+        q[u] = fma(d, d, q[u]);
+        mn[u] = fmin(mn[u], x[g][u]);
+        mx[u] = fmax(mx[u], x[g][u]);
+      }
+    }
+    if constexpr (MODE == CVGRAM_MODE_BF16X3) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        bf16x8_t h, l;
+#pragma unroll
+        for (int g = 0; g < 8; ++g) {
+          const bool ok = v[g] && js[u] >= 0;
+          // z' = fp32(z - c): an exact FP32 subtraction for FP32 input
+          const float zf = !ok ? 0.f
+                           : (sizeof(T) == 4 ? (float)x[g][u] - pivf[u]
+                                             : (float)(x[g][u] - (double)pivf[u]));
+          const __bf16 hh = (__bf16)zf;
+          h[g] = hh;
+          l[g] = (__bf16)(zf - (float)hh);
+        }
+        *(bf16x8_t*)&th[(4 * cg + u) * LDK + rg * 8] = h;
+        *(bf16x8_t*)&tl[(4 * cg + u) * LDK + rg * 8] = l;
+      }
+      __syncthreads();
+      CVG_GLOBAL __bf16* hi = gmem((__bf16*)packed);
+      CVG_GLOBAL __bf16* lo = gmem((__bf16*)packed_lo);
+      const int64_t base = ((d0 / kPanelRows) * Wp + cb0) * kPanelRows;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int qc = t + kPackThreads * k;  // 16-byte chunk: column qc / 4, rows 8 (qc % 4) ..
+        if (cb0 + (qc >> 2) < Wp) {
+          *(CVG_GLOBAL bf16x8_t*)&hi[base + qc * 8] =
+              *(const bf16x8_t*)&th[(qc >> 2) * LDK + (qc & 3) * 8];
+          *(CVG_GLOBAL bf16x8_t*)&lo[base + qc * 8] =
+              *(const bf16x8_t*)&tl[(qc >> 2) * LDK + (qc & 3) * 8];
+        }
+      }
+      __syncthreads();
+    } else if constexpr (MODE == CVGRAM_MODE_FP32) {
+      if (jp0 < Wp) {
+        CVG_GLOBAL float* out = gmem((float*)packed);
+#pragma unroll
+        for (int g = 0; g < 8; ++g) {
+          float4_t z;
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const bool ok = v[g] && js[u] >= 0;
+            z[u] = !ok ? 0.f
+                   : (sizeof(T) == 4 ? (float)x[g][u] - pivf[u]
+                                     : (float)(x[g][u] - (double)pivf[u]));
+          }
+          *(CVG_GLOBAL float4_t*)&out[(d0 + rg * 8 + g) * Wp + jp0] = z;
+        }
+      }
+    } else {
+      if (jp0 < Wp) {
+        CVG_GLOBAL double* out = gmem((double*)packed);
+#pragma unroll
+        for (int g = 0; g < 8; ++g) {
+          double2_t a, b;
+          a.x = (v[g] && js[0] >= 0) ? x[g][0] - piv[0] : 0.0;
+          a.y = (v[g] && js[1] >= 0) ? x[g][1] - piv[1] : 0.0;
+          b.x = (v[g] && js[2] >= 0) ? x[g][2] - piv[2] : 0.0;
+          b.y = (v[g] && js[3] >= 0) ? x[g][3] - piv[3] : 0.0;
+          *(CVG_GLOBAL double2_t*)&out[(d0 + rg * 8 + g) * Wp + jp0] = a;
+          *(CVG_GLOBAL double2_t*)&out[(d0 + rg * 8 + g) * Wp + jp0 + 2] = b;
+        }
+      }
+    }
+  };
+  if (x_vec && cb0 + kPackCols <= K) {
+    // a block of X columns only (16-byte loads): two register sets, so the
+    // next panel's loads are issued before this panel's stores and are not
+    // held up by them (loads and stores share one wait counter)
+    double xa[8][4], xb[8][4];
+    bool va[8], vb[8];
+    load_panel(std::true_type{}, ch.d0, xa, va);
+    for (int64_t d0 = ch.d0;; d0 += 2 * kPanelRows) {
+      const int64_t n1 = d0 + kPanelRows;
+      load_panel(std::true_type{}, n1 < ch.d1 ? n1 : d0, xb, vb);
+      consume(d0, xa, va);
+      if (n1 >= ch.d1) break;
+      const int64_t n2 = n1 + kPanelRows;
+      load_panel(std::true_type{}, n2 < ch.d1 ? n2 : n1, xa, va);
+      consume(n1, xb, vb);
+      if (n2 >= ch.d1) break;
+    }
+  } else {
+    // the block that reaches into Y or the padding, or unaligned X
+    for (int64_t d0 = ch.d0; d0 < ch.d1; d0 += kPanelRows) {
+      double x[8][4];
+      bool v[8];
+      load_panel(std::false_type{}, d0, x, v);
+      consume(d0, x, v);
+    }
+  }
 
   // combine the 4 row groups of each column, in row-group order
   const int64_t stride = n_chunks * W;
