@@ -51,7 +51,15 @@ __global__ __launch_bounds__(256) void reduce_slabs_kernel(const ProbDesc* __res
     // fused path: the slabs are row splits of the full Gram only
     const int32_t S = pd.n_slabs;
     double g = slabs[0];
-    for (int32_t k = 1; k < S; ++k) g += slabs[(int64_t)k * elems];
+    int32_t k = 1;
+    for (; k + 7 < S; k += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = slabs[(int64_t)(k + u) * elems];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) g += v[u];
+    }
+    for (; k < S; ++k) g += slabs[(int64_t)k * elems];
     gmem(pd.G)[e] = g;
     return;
   }
@@ -63,11 +71,13 @@ __global__ __launch_bounds__(256) void reduce_slabs_kernel(const ProbDesc* __res
     const int32_t b = slab_begin[p + 1];
     double f = slabs[(int64_t)a * elems];
     int32_t k = a + 1;
-    // four independent loads in flight per step; the sum keeps slab order
-    for (; k + 3 < b; k += 4) {
-      const double v0 = slabs[(int64_t)k * elems], v1 = slabs[(int64_t)(k + 1) * elems];
-      const double v2 = slabs[(int64_t)(k + 2) * elems], v3 = slabs[(int64_t)(k + 3) * elems];
-      f = (((f + v0) + v1) + v2) + v3;
+    // eight independent loads in flight per step; the sum keeps slab order
+    for (; k + 7 < b; k += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = slabs[(int64_t)(k + u) * elems];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) f += v[u];
     }
     for (; k < b; ++k) f += slabs[(int64_t)k * elems];
     if (b > a + 1) slabs[(int64_t)a * elems] = f;
