@@ -471,7 +471,7 @@ def psweep_block(cv, torch, G, dev, args):
     xy = torch.empty(CH, 8, K, M, dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
     rows = []
-    for P in (3, 10, 100, 1000, 10000, 100000):
+    for P in (3, 10, 100, 1000, 3000, 10000, 100000):
         fold = G.folds_near_equal(N, P, G._rng(2, 0, 11, P))
         fd = torch.from_numpy(fold).to(dev)
         for it in range(2):  # the first pass warms the workspace cache
@@ -490,9 +490,10 @@ def psweep_block(cv, torch, G, dev, args):
             dt = time.perf_counter() - t0
             st = cv.cvgram_stage_times(h)
             cv.cvgram_set_stage_timing(False)
+            fused = cv.cvgram_plan_info(h)["fused"]
             cv.cvgram_destroy(h)
         out_bytes = P * (4 * K * K + 8 * K * M) * 8
-        rows.append({"P": P, "path": "fused" if P >= 64 and N // P <= 256 else "grouped",
+        rows.append({"P": P, "path": "fused" if fused else "grouped",
                      "seconds": dt, "sets_per_s": P * 12 / dt, "gram_ms": st["gram"],
                      "stage_ms": st, "corrections_ms": e0.elapsed_time(e1),
                      "output_GB_per_s": out_bytes / (e0.elapsed_time(e1) * 1e-3) / 1e9})

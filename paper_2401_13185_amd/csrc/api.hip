@@ -470,12 +470,19 @@ struct HostLists {
   }
 };
 
-// Fold path of a problem.  The fused path (no padding between folds, G'_p
-// formed in the corrections) is chosen for many small folds, where padding
-// every fold to whole panels and keeping one FP64 slab set per fold would
-// dominate time and memory; CVGRAM_FOLD_PATH=grouped|fused forces either.
-constexpr int64_t kFusedMaxFoldRows = 256;
+// Fold path of a problem.  The grouped path pads every fold to whole panels
+// and keeps at least one K x (K + M) FP64 slab per fold; the fused path (no
+// padding between folds) forms each G'_p inside the corrections instead,
+// re-reading the fold's rows for every output tile (a cost that does not
+// shrink with the folds).  Measured on N=1e5, K=512 (create + all folds):
+// grouped is faster down to folds of 33 rows (P=3000: 10.3 vs 12.5 ms), the
+// fused path from folds of about 20 rows on, where padding and per-fold
+// slabs dominate.  The fused path is also taken when the per-fold slabs
+// would not fit a memory budget.  CVGRAM_FOLD_PATH=grouped|fused forces
+// either.
+constexpr int64_t kFusedMaxFoldRows = 24;
 constexpr int32_t kFusedMinFolds = 64;
+constexpr double kGroupedSlabBudget = 16e9;  // bytes
 
 bool choose_fused(const ProbPlan& p) {
   const char* f = std::getenv("CVGRAM_FOLD_PATH");
@@ -483,7 +490,8 @@ bool choose_fused(const ProbPlan& p) {
   if (f && std::strcmp(f, "grouped") == 0) return false;
   int64_t max_fold = 0;
   for (int32_t q = 0; q < p.P; ++q) max_fold = std::max(max_fold, p.offsets[q + 1] - p.offsets[q]);
-  return p.P >= kFusedMinFolds && max_fold <= kFusedMaxFoldRows;
+  if (p.P >= kFusedMinFolds && max_fold <= kFusedMaxFoldRows) return true;
+  return (double)p.P * (double)p.K * (double)p.W * 8.0 > kGroupedSlabBudget;
 }
 
 // Order of a Gram launch's items.  The kernel maps workgroup b to item

@@ -180,14 +180,18 @@ def test_batch_mixing_fold_paths_equals_single_handles():
     cv.cvgram_batch_destroy(b)
 
 
-def test_large_P_spectra_full_size_sampled():
+@pytest.mark.parametrize("path", [None, "fused"])
+def test_large_P_spectra_full_size_sampled(path):
     """The spectra workload's shape (N=100000, K=512, M=8) with P=1000
-    near-equal folds of 100 rows: folds written in chunks; sampled entries
-    of three folds against the oracle, properties on every written fold."""
+    near-equal folds of 100 rows (the chosen path, and the fused one forced):
+    folds written in chunks; sampled entries of three folds against the
+    oracle, properties on every written fold."""
     shape = G.Shape("spectra P=1000", 100_000, 512, 8, 1000, "f64", "spectra", "near_equal")
     X, Y, fold = G.make(shape, 2, problem=1)
-    print(f"[fused] {shape.name}", flush=True)
-    h = cv.cvgram_create(_t(X), _t(Y), _t(fold), 1, 1, 1, 1, ddof=1, mode="fp64")
+    print(f"[fused] {shape.name} path={path}", flush=True)
+    with ForcedFoldPath(path):
+        h = cv.cvgram_create(_t(X), _t(Y), _t(fold), 1, 1, 1, 1, ddof=1, mode="fp64")
+    assert cv.cvgram_plan_info(h)["fused"] == (path == "fused")
     P = cv.cvgram_num_folds(h)
     assert P == 1000
     K, M = 512, 8
