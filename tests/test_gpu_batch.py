@@ -180,3 +180,58 @@ def test_autotune_returns_valid_choice_and_results_stay_correct():
     for c in range(4):
         assert _relerr(xx[2, c].cpu().numpy(), oxx[c]) <= BF16X3_BOUND
     cv.cvgram_destroy(h)
+
+
+def test_batch_full_size_sampled():
+    """The batched workload at full size, as the bench runs it: 256 problems
+    (N log-uniform in [1e3, 2e5], K in {64, 128, 256, 512}, M 1..16, P 3..20,
+    values drawn on the device, graph replay).  FP64 mode against the
+    oracle on sampled entries of every 16th problem (each entry from the two
+    columns it needs, copied to the host); bf16x3 against FP64 on every
+    problem, fold and class within the stated bound."""
+    shapes = G.batch_shapes(256)
+    probs = [G.batch_problem_device(s, i, _dev()) for i, s in enumerate(shapes)]
+    torch.cuda.synchronize()
+    print("[batch] full-size workload generated", flush=True)
+    outs = {}
+    for mode in ("fp64", "bf16x3"):
+        b = cv.cvgram_batch_create(probs, ddof=1, mode=mode)
+        cv.cvgram_batch_run(b)
+        torch.cuda.synchronize()
+        outs[mode] = b
+    worst = 0.0
+    for (xa, ya), (xb, yb) in zip(outs["bf16x3"].outs, outs["fp64"].outs):
+        for a, r in ((xa, xb), (ya, yb)):
+            num = torch.linalg.matrix_norm(a.double() - r)
+            worst = max(worst, (num / torch.linalg.matrix_norm(r)).max().item())
+    assert worst <= BF16X3_BOUND, worst
+    rng = np.random.default_rng(256)
+    for i in range(0, 256, 16):
+        X, Y, fd = probs[i]
+        K, M = X.shape[1], Y.shape[1]
+        fold = fd.cpu().numpy()
+        P, _ = cv.cvgram_batch_problem_info(outs["fp64"], i)
+        pairs_xx = [(int(a), int(c)) for a, c in rng.integers(0, K, size=(6, 2))] + [(K - 1, K - 1)]
+        pairs_xy = [(int(a), int(c)) for a, c in zip(rng.integers(0, K, 4), rng.integers(0, M, 4))]
+        xcols = sorted({c for pr in pairs_xx for c in pr} | {a for a, _ in pairs_xy})
+        ycols = sorted({c for _, c in pairs_xy})
+        xm = {c: n for n, c in enumerate(xcols)}
+        ym = {c: n for n, c in enumerate(ycols)}
+        Xs = X[:, xcols].double().cpu().numpy()
+        Ys = Y[:, ycols].double().cpu().numpy()
+        sxx = [(xm[a], xm[c]) for a, c in pairs_xx]
+        sxy = [(xm[a], ym[c]) for a, c in pairs_xy]
+        gx, gy = outs["fp64"].outs[i]
+        for q in (0, P - 1):
+            for c in range(4):
+                ref, _ = O.fold_entries(Xs, Ys, fold, q, *O.XTX_CLASS_COMBO[c], 1, sxx, [])
+                got = np.array([gx[q, c, a, d].item() for a, d in pairs_xx])
+                scale = gx[q, c].abs().max().item()
+                assert np.max(np.abs(got - ref)) <= FP64_TOL * scale, (i, q, c)
+            for c in range(8):
+                _, ref = O.fold_entries(Xs, Ys, fold, q, *O.XTY_CLASS_COMBO[c], 1, [], sxy)
+                got = np.array([gy[q, c, a, d].item() for a, d in pairs_xy])
+                scale = gy[q, c].abs().max().item()
+                assert np.max(np.abs(got - ref)) <= FP64_TOL * scale, (i, q, c)
+    for b in outs.values():
+        cv.cvgram_batch_destroy(b)
