@@ -25,6 +25,7 @@ namespace cvg {
 namespace {
 
 constexpr int NB = 32;         // block edge
+constexpr int kSolveRows = 128;  // rows of L staged per pass of a substitution update
 constexpr int kThreads = 256;  // 8 rows x 32 columns per pass, 4 passes per block
 
 // A + lambda I and a copy of R from the products (p-major, lambda-minor)
@@ -174,6 +175,7 @@ __global__ __launch_bounds__(kThreads) void tri_solve_kernel(const double* __res
   __shared__ double Z[NB][NB + 1];
   __shared__ double Li[NB][NB + 1];
   __shared__ double Rb[NB][NB + 1];
+  __shared__ double Ls[kSolveRows][NB + 1];
   const int64_t mat = blockIdx.x;
   const int64_t m0 = (int64_t)blockIdx.y * NB;
   const int64_t mw = M - m0 < NB ? M - m0 : NB;  // columns of R in this block
@@ -203,25 +205,34 @@ __global__ __launch_bounds__(kThreads) void tri_solve_kernel(const double* __res
         if (i < K && tx < mw) rr[i * M + m0 + tx] = sum;
       }
       __syncthreads();
-      // the other block rows: forward i >= r0 + NB, backward i < r0
+      // the other block rows: forward i >= r0 + NB, backward i < r0; the
+      // block column of L they need is staged in LDS kSolveRows rows at a
+      // time (coalesced loads, all in flight), the dot products then read LDS
       const int64_t lo = backward ? 0 : r0 + NB, hi = backward ? r0 : K;
-      const int64_t cnt = hi > lo ? (hi - lo) * mw : 0;
       const int64_t cmax = K - r0 < NB ? K - r0 : NB;  // columns of the block inside K
-      for (int64_t e = t; e < cnt; e += kThreads) {
-        const int64_t i = lo + e / mw;
-        const int mm = (int)(e % mw);
-        double sum = 0.0;
-        if (!backward) {
-          // L_ij = A[i][r0 + c]
-          const CVG_GLOBAL double* row = a + i * K + r0;
-          for (int c = 0; c < cmax; ++c) sum = fma(row[c], Z[c][mm], sum);
-        } else {
-          // (L_ji)^T[i][c] = A[r0 + c][i]
-          for (int c = 0; c < cmax; ++c) sum = fma(a[(r0 + c) * K + i], Z[c][mm], sum);
+      for (int64_t i0 = lo; i0 < hi; i0 += kSolveRows) {
+        const int64_t nr = hi - i0 < kSolveRows ? hi - i0 : kSolveRows;
+        for (int e = t; e < kSolveRows * NB; e += kThreads) {
+          // forward: Ls[ri][c] = L_ij = A[i0 + ri][r0 + c]
+          // backward: Ls[ri][c] = (L_ji)^T = A[r0 + c][i0 + ri]
+          const int ri = backward ? e % kSolveRows : e / NB;
+          const int c = backward ? e / kSolveRows : e % NB;
+          double v = 0.0;
+          if (ri < nr && c < cmax)
+            v = backward ? a[(r0 + c) * K + i0 + ri] : a[(i0 + ri) * K + r0 + c];
+          Ls[ri][c] = v;
         }
-        rr[i * M + m0 + mm] -= sum;
+        __syncthreads();
+        for (int64_t e = t; e < nr * mw; e += kThreads) {
+          const int ri = (int)(e / mw);
+          const int mm = (int)(e % mw);
+          double sum = 0.0;
+#pragma unroll
+          for (int c = 0; c < NB; ++c) sum = fma(Ls[ri][c], Z[c][mm], sum);
+          rr[(i0 + ri) * M + m0 + mm] -= sum;
+        }
+        __syncthreads();
       }
-      __syncthreads();
     }
   }
 }
