@@ -269,6 +269,48 @@ struct ProbPlan {
   double* d_pivot = nullptr;  // computed at bookkeeping time (single problems)
 };
 
+// Events of released handles, kept per device and reused by later handles
+// (a handle per call is the common pattern; creating its events each time
+// would sit on the host path between two steps).  Only events whose work
+// has completed are returned here: a handle's stream is synchronised before
+// it is released.
+struct EventPool {
+  std::mutex mu;
+  std::vector<hipEvent_t> timed[kMaxDev], plain[kMaxDev];
+};
+EventPool& event_pool() {
+  static EventPool* e = new EventPool();  // never destroyed: outlives static teardown
+  return *e;
+}
+hipEvent_t event_get(int device, bool timed) {
+  if (device >= 0 && device < kMaxDev) {
+    EventPool& ep = event_pool();
+    std::lock_guard<std::mutex> g(ep.mu);
+    auto& v = timed ? ep.timed[device] : ep.plain[device];
+    if (!v.empty()) {
+      hipEvent_t e = v.back();
+      v.pop_back();
+      return e;
+    }
+  }
+  hipEvent_t e = nullptr;
+  CVG_HIP(hipEventCreateWithFlags(&e, timed ? hipEventDefault : hipEventDisableTiming));
+  return e;
+}
+void event_put(int device, bool timed, hipEvent_t e) {
+  if (!e) return;
+  if (device >= 0 && device < kMaxDev) {
+    EventPool& ep = event_pool();
+    std::lock_guard<std::mutex> g(ep.mu);
+    auto& v = timed ? ep.timed[device] : ep.plain[device];
+    if (v.size() < 64) {
+      v.push_back(e);
+      return;
+    }
+  }
+  (void)hipEventDestroy(e);
+}
+
 // the device pipeline of a batch (a single handle is a batch of one)
 struct Batch {
   int device = 0;
@@ -320,12 +362,11 @@ struct Batch {
     if (graph) (void)hipGraphDestroy(graph);
     gexec = nullptr;
     graph = nullptr;
-    for (auto& e : ev)
-      if (e) {
-        (void)hipEventDestroy(e);
-        e = nullptr;
-      }
-    if (ev_wait) (void)hipEventDestroy(ev_wait);
+    for (auto& e : ev) {
+      event_put(device, true, e);
+      e = nullptr;
+    }
+    event_put(device, false, ev_wait);
     ev_wait = nullptr;
     mem.release();
   }
@@ -371,7 +412,7 @@ cvgram_status bookkeeping(Batch& b) {
   int64_t* offs = (int64_t*)b.mem.dev((size_t)(maxN + 1) * sizeof(int64_t));
   int32_t* hbuf = (int32_t*)scratch.pinned(kInfo * sizeof(int32_t));
   int32_t* hcounts = hbuf + 2;
-  if (!b.ev_wait) CVG_HIP(hipEventCreateWithFlags(&b.ev_wait, hipEventDisableTiming));
+  if (!b.ev_wait) b.ev_wait = event_get(b.device, false);
   cvgram_status st = CVGRAM_OK;
   int64_t at = 0;
   try {
@@ -933,7 +974,8 @@ void run_pipeline(Batch& b, bool with_events) {
 // bookkeeping + plan + workspace for a batch whose problems are filled in
 cvgram_status prepare(Batch& b) {
   if (b.timing)
-    for (auto& e : b.ev) CVG_HIP(hipEventCreate(&e));
+    for (auto& e : b.ev)
+      if (!e) e = event_get(b.device, true);
   if (b.timing) CVG_HIP(hipEventRecord(b.ev[0], b.stream));
   b.mem.device = b.device;
   cvgram_status st = bookkeeping(b);
