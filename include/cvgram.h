@@ -105,10 +105,11 @@ typedef enum {
  * MFMA launch.  It waits on `stream` once for the validation data and the
  * fold sizes (twice when P > 4096); everything after that is only enqueued.
  *
- * Fold path: with many small folds (P >= 64 and no fold above 256 rows,
- * e.g. leave-one-out) the rows are packed without per-fold padding, only the
- * full Gram is contracted, and each fold's validation Gram is formed from
- * its rows inside the per-fold corrections (it never reaches memory).  The
+ * Fold path: with many small folds (P >= 64 and no fold above 24 rows,
+ * e.g. leave-one-out), or when one FP64 K x (K + M) slab per fold would
+ * exceed 16 GB, the rows are packed without per-fold padding, only the full
+ * Gram is contracted, and each fold's validation Gram is formed from its
+ * rows inside the per-fold corrections (it never reaches memory).  The
  * environment variable CVGRAM_FOLD_PATH=grouped or =fused, read at each
  * create, forces either path; results agree to rounding.
  *
