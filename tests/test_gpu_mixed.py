@@ -58,6 +58,7 @@ CASES = [
     (3001, 130, 5, 7, "spectra", "f64"),       # ragged rows/tiles, FP64 input
     (900, 40, 0, 4, "gaussian", "f64"),        # no Y, K below one tile
     (5000, 300, 130, 5, "gaussian", "f32"),    # Y wider than one tile
+    (6000, 160, 30, 5, "offset", "f32"),       # 16 < M <= 32 inside diagonal tiles
 ]
 
 

@@ -125,6 +125,7 @@ def test_fp64_gaussian_workload_all_classes(ddof):
     (777, 1, 1, 3, "gaussian", "f64"),        # K = 1
     (900, 33, 0, 6, "gaussian", "f64"),       # no Y
     (5000, 200, 40, 12, "spectra", "f64"),    # several XtY tiles
+    (4000, 150, 24, 6, "spectra", "f64"),     # 16 < M <= 32: two XtY blocks per diagonal row
 ])
 def test_fp64_ragged_shapes(n, k, m, p, values, dtype):
     shape = G.Shape(f"{values} N={n} K={k} M={m} P={p}", n, k, m, p, dtype, values, "dirichlet")
