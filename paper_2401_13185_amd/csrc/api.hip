@@ -599,7 +599,9 @@ void schedule_gram(std::vector<GramWork>& wl, std::vector<int32_t>& xcd, bool ba
 void plan_layout(Batch& b, HostLists& L) {
   const int64_t PR = kPanelRows;
   int64_t pack_cols_rows = 0;  // sum over problems of Np * column blocks
-  int64_t gram_rows = 0;       // sum over problems of Np * tiles
+  // sum over problems of Np * tiles, per Gram launch (64- and 128-wide tiles
+  // are launched apart, so each launch is split for its own work)
+  int64_t gram_rows64 = 0, gram_rows128 = 0;
   for (auto& p : b.pp) {
     p.cfg = b.force_cfg ? b.forced : choose_config(b.mode, b.dtype, p.K, p.M, p.N);
     const int T = p.cfg.tile;
@@ -618,7 +620,7 @@ void plan_layout(Batch& b, HostLists& L) {
     const int64_t nyt = p.xy_diag ? 0 : p.Mp / T;
     const int64_t ntile = (int64_t)p.nt * (p.nt + 1) / 2 + (int64_t)p.nt * nyt;
     pack_cols_rows += p.Np * ((p.Wp + kPackCols - 1) / kPackCols);
-    gram_rows += p.Np * ntile;
+    (T == 64 ? gram_rows64 : gram_rows128) += p.Np * ntile;
   }
   int64_t chunk_rows = (pack_cols_rows + kPackTargetBlocks - 1) / kPackTargetBlocks;
   chunk_rows = std::min((int64_t)kMaxChunkRows, std::max(PR, (chunk_rows + PR - 1) / PR * PR));
@@ -668,14 +670,16 @@ void plan_layout(Batch& b, HostLists& L) {
     }
     b.max_cb64 = std::max<int32_t>(b.max_cb64, (int32_t)((p.W + 63) / 64));
     b.max_cb256 = std::max<int32_t>(b.max_cb256, (int32_t)((p.W + 255) / 256));
-    // Gram work: split folds along rows so the launch has about
-    // target_items items (shared over the batch)
+    // Gram work: split folds along rows so the launch this problem joins
+    // has about target_items items (shared over the problems of the batch
+    // with the same tile width)
     std::vector<std::pair<int32_t, int32_t>> gtiles;
     const int64_t nyt = p.xy_diag ? 0 : p.Mp / T;
     for (int32_t ti = 0; ti < p.nt; ++ti) {
       for (int32_t tj = ti; tj < p.nt; ++tj) gtiles.push_back({ti, tj});
       for (int64_t y = 0; y < nyt; ++y) gtiles.push_back({ti, (int32_t)(p.nt + y)});
     }
+    const int64_t gram_rows = T == 64 ? gram_rows64 : gram_rows128;
     int64_t rows_per_split = (gram_rows + p.cfg.target_items - 1) / p.cfg.target_items;
     rows_per_split = std::max(rows_per_split, kGramMinRows);
     rows_per_split = (rows_per_split + PR - 1) / PR * PR;
