@@ -99,17 +99,25 @@ def cpu_legs(X, Y, fold, P, gpu_xx, gpu_xy, budget_s):
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count()])
     except Exception:
         threads = os.cpu_count()
+    # the oracle on folds 0, 1, ... until about half the budget is spent
+    # (at least one fold); the GPU result is checked on every fold it covers
     t0 = time.perf_counter()
-    oxx, oxy = O.fold_all_classes(X, Y, fold, 0, ddof=1)
-    t_or = time.perf_counter() - t0
     errs = []
-    for c in range(4):
-        errs.append(np.linalg.norm(gpu_xx[0, c] - oxx[c]) / np.linalg.norm(oxx[c]))
-    for c in range(8):
-        errs.append(np.linalg.norm(gpu_xy[0, c] - oxy[c]) / np.linalg.norm(oxy[c]))
+    n_or = 0
+    while n_or < P:
+        oxx, oxy = O.fold_all_classes(X, Y, fold, n_or, ddof=1)
+        for c in range(4):
+            errs.append(np.linalg.norm(gpu_xx[n_or, c] - oxx[c]) / np.linalg.norm(oxx[c]))
+        for c in range(8):
+            errs.append(np.linalg.norm(gpu_xy[n_or, c] - oxy[c]) / np.linalg.norm(oxy[c]))
+        n_or += 1
+        if time.perf_counter() - t0 >= 0.5 * budget_s:
+            break
+    t_or = time.perf_counter() - t0
     errs = [float(e) for e in errs]
-    cpu = {"value": 12.0 / t_or, "unit": "sets/s", "cores": int(threads), "kind": "oracle",
-           "sample": f"fold 0 of {P}, all 12 distinct classes, FP64 naive baseline",
+    cpu = {"value": 12.0 * n_or / t_or, "unit": "sets/s", "cores": int(threads), "kind": "oracle",
+           "sample": f"folds 0..{n_or - 1} of {P}, all 12 distinct classes each, FP64 naive "
+                     f"baseline",
            "seconds": round(t_or, 3)}
     fast = None
     if t_or < budget_s:
@@ -317,8 +325,8 @@ def main():
         out["cpu_baseline"] = cpu
         if fast:
             out["cpu_fast"] = fast
-        out["max_rel_err_vs_oracle_fold0"] = max(errs)
-        out["median_rel_err_vs_oracle_fold0"] = float(np.median(errs))
+        out["max_rel_err_vs_oracle"] = max(errs)  # over the folds the oracle sample covers
+        out["median_rel_err_vs_oracle"] = float(np.median(errs))
     del xx, xy
     out["ridge"] = ridge_block(cv, torch, Xd, Yd, fd, P, K, M, args.mode)
     print("[bench] ridge block done", file=sys.stderr, flush=True)

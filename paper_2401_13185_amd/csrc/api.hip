@@ -1169,7 +1169,7 @@ cvgram_status cvgram_ridge(cvgram_t h, int32_t p0, int32_t p1, const double* lam
     return fail(CVGRAM_ENOTSCALABLE, "partitioning is not scalable for this ddof");
   const int32_t nf = p1 - p0;
   const int64_t K = pp.K, M = pp.M, nmat = (int64_t)nf * n_lambda;
-  const int64_t nblk = (K + 31) / 32;
+  const int64_t nblk = (K + 31) / 32, Kp = nblk * 32, Mp = (M + 31) / 32 * 32;
   hipStream_t s = h->b.stream;
   Owned ws;
   ws.device = h->b.device;
@@ -1177,7 +1177,8 @@ cvgram_status cvgram_ridge(cvgram_t h, int32_t p0, int32_t p1, const double* lam
   try {
     double* xtx = (double*)ws.dev((size_t)nf * K * K * 8);
     double* xty = (double*)ws.dev((size_t)nf * K * M * 8);
-    double* A = (double*)ws.dev((size_t)nmat * K * K * 8);
+    double* A = (double*)ws.dev((size_t)nmat * Kp * Kp * 8);
+    double* R = (double*)ws.dev((size_t)nmat * Kp * Mp * 8);
     double* Linv = (double*)ws.dev((size_t)nmat * nblk * 32 * 32 * 8);
     int32_t* flags = (int32_t*)ws.dev((size_t)nmat * 4);
     double* dl = (double*)ws.dev((size_t)n_lambda * 8);
@@ -1196,7 +1197,7 @@ cvgram_status cvgram_ridge(cvgram_t h, int32_t p0, int32_t p1, const double* lam
     od.p_begin = p0;
     const ProbDesc& d = h->b.h_pd[0];
     launch_correct_single(h->b.d_pd, 0, d.n_ctiles_xx + d.n_ctiles_xy, od, nf, true, s);
-    ridge_solve(xtx, xty, dl, nf, n_lambda, K, M, A, out_B, Linv, flags, s);
+    ridge_solve(xtx, xty, dl, nf, n_lambda, K, M, A, R, Linv, flags, out_B, s);
     CVG_HIP(hipMemcpyAsync(hflags, flags, (size_t)nmat * 4, hipMemcpyDeviceToHost, s));
     CVG_HIP(hipStreamSynchronize(s));
     for (int64_t m = 0; m < nmat; ++m)

@@ -230,11 +230,12 @@ void launch_correct_batch(const ProbDesc* pd, const OutDesc* outs, const Item* i
                           int64_t n_items, bool out_f64, hipStream_t s);
 
 // solve.hip: B = (xtx_f + lambda_l I)^{-1} xty_f for every (fold f, lambda l),
-// matrices p-major; R receives B.  A: [n_folds n_lambda][K][K] workspace,
-// Linv: [n_folds n_lambda][ceil(K/32)][32][32], flags: [n_folds n_lambda]
-// (zeroed by the caller; set on a non-positive pivot).
+// matrices p-major, into B: [n_folds n_lambda][K][M].  Workspaces, with Kp and
+// Mp the multiples of 32 at or above K and M: A [n_folds n_lambda][Kp][Kp],
+// R [n_folds n_lambda][Kp][Mp], Linv [n_folds n_lambda][Kp/32][32][32];
+// flags: [n_folds n_lambda] (zeroed by the caller; set on a non-positive pivot).
 void ridge_solve(const double* xtx, const double* xty, const double* lambdas, int32_t n_folds,
                  int32_t n_lambda, int64_t K, int64_t M, double* A, double* R, double* Linv,
-                 int32_t* flags, hipStream_t s);
+                 int32_t* flags, double* B, hipStream_t s);
 
 }  // namespace cvg

@@ -4,14 +4,20 @@
 // the training products directly (the models the paper names for them,
 // Section 1: RR, and OLS for lambda = 0).
 //
+// The systems are copied into padded workspaces first: A to Kp x Kp with the
+// identity in the padding, R to Kp x Mp with zeros (Kp, Mp multiples of 32),
+// so no kernel below needs a bounds check and every load can be issued
+// without waiting for the one before it.
+//
 // Blocked right-looking Cholesky A = L L^T with 32 x 32 blocks:
 //   for each block column j
-//     diag:   L_jj = chol(A_jj) and its inverse, in LDS (one workgroup per matrix)
-//     panel:  L_ij = A_ij L_jj^{-T} for every block row i > j
+//     diag:   L_jj = chol(A_jj) and its inverse, in registers (one wave per matrix)
+//     panel:  L_ij = A_ij L_jj^{-T} for every block row i > j (also stored
+//             transposed in the upper triangle)
 //     update: A_ik -= L_ij L_kj^T for every j < k <= i (lower triangle)
 // then R is overwritten by L^{-T} L^{-1} R with the same blocks (forward and
 // backward substitution through the stored inverses of the diagonal blocks,
-// one launch for both).
+// one launch for both), and copied out.
 // A matrix whose pivot is not positive (A + lambda I not positive definite)
 // sets its flag and continues with NaN.
 //
@@ -24,113 +30,168 @@
 namespace cvg {
 namespace {
 
-constexpr int NB = 32;         // block edge
-constexpr int kSolveRows = 128;  // rows of L staged per pass of a substitution update
-constexpr int kThreads = 256;  // 8 rows x 32 columns per pass, 4 passes per block
+constexpr int NB = 32;                         // block edge
+constexpr int kThreads = 256;                  // 8 rows x 32 columns per pass
+constexpr int kRowStep = kThreads / NB;        // rows a pass covers
+constexpr int kRowsPerThread = NB / kRowStep;  // passes per block
+constexpr int kWave = 64;
 
-// A + lambda I and a copy of R from the products (p-major, lambda-minor)
+// padded systems: A + lambda I in Kp x Kp (identity in the padding) and R in
+// Kp x Mp (zeros in the padding), from the products (p-major, lambda-minor)
 __global__ __launch_bounds__(kThreads) void ridge_setup_kernel(
     const double* __restrict__ xtx, const double* __restrict__ xty,
-    const double* __restrict__ lambdas, int32_t n_lambda, int64_t K, int64_t M,
-    double* __restrict__ A, double* __restrict__ R) {
+    const double* __restrict__ lambdas, int32_t n_lambda, int64_t K, int64_t M, int64_t Kp,
+    int64_t Mp, double* __restrict__ A, double* __restrict__ R) {
   const int64_t mat = blockIdx.y;  // fold * n_lambda + lambda
   const int64_t f = mat / n_lambda;
   const double lam = lambdas[mat % n_lambda];
-  const int64_t KK = K * K, KM = K * M;
-  const CVG_GLOBAL double* src = gmem(xtx) + f * KK;
-  CVG_GLOBAL double* dst = gmem(A) + mat * KK;
-  for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < KK; e += (int64_t)gridDim.x * kThreads) {
-    const int64_t i = e / K, j = e - i * K;
-    dst[e] = src[e] + (i == j ? lam : 0.0);
+  const CVG_GLOBAL double* src = gmem(xtx) + f * K * K;
+  CVG_GLOBAL double* dst = gmem(A) + mat * Kp * Kp;
+  for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < Kp * Kp;
+       e += (int64_t)gridDim.x * kThreads) {
+    const int64_t i = e / Kp, j = e - i * Kp;
+    dst[e] = (i < K && j < K) ? src[i * K + j] + (i == j ? lam : 0.0) : (i == j ? 1.0 : 0.0);
   }
-  const CVG_GLOBAL double* rs = gmem(xty) + f * KM;
-  CVG_GLOBAL double* rd = gmem(R) + mat * KM;
-  for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < KM; e += (int64_t)gridDim.x * kThreads)
-    rd[e] = rs[e];
+  const CVG_GLOBAL double* rs = gmem(xty) + f * K * M;
+  CVG_GLOBAL double* rd = gmem(R) + mat * Kp * Mp;
+  for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < Kp * Mp;
+       e += (int64_t)gridDim.x * kThreads) {
+    const int64_t i = e / Mp, m = e - i * Mp;
+    rd[e] = (i < K && m < M) ? rs[i * M + m] : 0.0;
+  }
 }
 
-// diagonal block j of every matrix: Cholesky in LDS (column by column), the
-// inverse of the factor by forward substitution, both written back; blocks
-// past K are padded with the identity.  flags[mat] = 1 on a non-positive pivot.
-__global__ __launch_bounds__(kThreads) void chol_diag_kernel(double* __restrict__ A,
-                                                             double* __restrict__ Linv,
-                                                             int32_t* __restrict__ flags,
-                                                             int64_t K, int32_t j, int32_t nblk) {
-  __shared__ double L[NB][NB + 1];
-  __shared__ double I[NB][NB + 1];
+// B[mat] = the first K x M of the padded R[mat]
+__global__ __launch_bounds__(kThreads) void ridge_store_kernel(const double* __restrict__ R,
+                                                               int64_t K, int64_t M, int64_t Kp,
+                                                               int64_t Mp, double* __restrict__ B) {
+  const int64_t mat = blockIdx.y;
+  const CVG_GLOBAL double* rs = gmem(R) + mat * Kp * Mp;
+  CVG_GLOBAL double* bd = gmem(B) + mat * K * M;
+  for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < K * M;
+       e += (int64_t)gridDim.x * kThreads) {
+    const int64_t i = e / M, m = e - i * M;
+    bd[e] = rs[i * Mp + m];
+  }
+}
+
+// the value that lane `lane` holds in x, in every lane (a wave-wide
+// broadcast through the scalar registers)
+__device__ __forceinline__ double from_lane(double x, int lane) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), lane);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// diagonal block j of every matrix, one wave per matrix, all in registers:
+// lanes 0..31 hold the rows of the block and factor it column by column
+// (right-looking); lanes 32..63 hold the columns of the factor's inverse and
+// run the forward substitution L X = I in the same steps, since step c of
+// the substitution needs only column c of L, final once step c of the
+// factorisation has divided it.  Both updates are one FMA with a broadcast
+// operand: the factor rows take L[r][k] -= L[r][c] L[k][c] (c < k <= r), the
+// inverse columns X[k][t] -= L[k][c] X[c][t] (k > c); every entry sums in
+// increasing c.  The factor goes to the lower triangle of the block (zeros
+// above), its inverse to Linv; flags[mat] = 1 on a non-positive pivot.
+__global__ __launch_bounds__(kWave) void chol_diag_kernel(double* __restrict__ A,
+                                                          double* __restrict__ Linv,
+                                                          int32_t* __restrict__ flags, int64_t Kp,
+                                                          int32_t j, int32_t nblk) {
   const int64_t mat = blockIdx.x;
-  CVG_GLOBAL double* a = gmem(A) + mat * K * K;
-  const int t = threadIdx.x, tx = t % NB, ty = t / NB;
+  const int l = threadIdx.x;
+  const bool fac = l < NB;  // a factor row, else an inverse column
+  const int q = l % NB;     // its row / column index
   const int64_t r0 = (int64_t)j * NB;
-  for (int r = ty; r < NB; r += kThreads / NB) {
-    const int64_t i = r0 + r, c = r0 + tx;
-    L[r][tx] = (i < K && c < K) ? a[i * K + c] : (r == tx ? 1.0 : 0.0);
+  CVG_GLOBAL double* arow = gmem(A) + mat * Kp * Kp + (r0 + q) * Kp + r0;
+  double u[NB];
+#pragma unroll
+  for (int k = 0; k < NB; ++k) {
+    const double v = arow[k];
+    u[k] = (fac && k <= q) ? v : (q == k ? 1.0 : 0.0);
   }
-  __syncthreads();
-  // right-looking on the block: column c finishes, then updates the rest
+  bool bad = false;
+#pragma unroll
   for (int c = 0; c < NB; ++c) {
-    if (t == 0) {
-      const double d = L[c][c];
-      if (!(d > 0.0)) flags[mat] = 1;
-      L[c][c] = d > 0.0 ? sqrt(d) : NAN;
+    const double d = from_lane(u[c], c);  // pivot: A[c][c] after the earlier steps
+    bad = bad || !(d > 0.0);
+    const double piv = d > 0.0 ? sqrt(d) : NAN;
+    // L[q][c] below the pivot, X[c][q] in an inverse column (a factor row
+    // above the pivot divides a value that is never read)
+    u[c] = fac && q == c ? piv : u[c] / piv;
+#pragma unroll
+    for (int k = c + 1; k < NB; ++k) {
+      const double lkc = from_lane(u[c], k);  // L[k][c]
+      // factor rows with q < k update entries above the diagonal: never read
+      u[k] = fma(-u[c], lkc, u[k]);
     }
-    __syncthreads();
-    if (t > c && t < NB) L[t][c] = L[t][c] / L[c][c];
-    __syncthreads();
-    for (int r = ty; r < NB; r += kThreads / NB)
-      if (r > c && tx > c && tx <= r) L[r][tx] = fma(-L[r][c], L[tx][c], L[r][tx]);
-    __syncthreads();
   }
-  // inverse of the lower factor, L X = I, by right-looking elimination over
-  // the rows of X: at step c row c is divided by the pivot and then removed
-  // from the rows below, all 32 x 32 entries in parallel (each entry sums in
-  // increasing c, the order of plain forward substitution)
-  for (int r = ty; r < NB; r += kThreads / NB) I[r][tx] = r == tx ? 1.0 : 0.0;
-  __syncthreads();
-  for (int c = 0; c < NB; ++c) {
-    if (t < NB) I[c][t] = I[c][t] / L[c][c];
-    __syncthreads();
-    for (int r = ty; r < NB; r += kThreads / NB)
-      if (r > c) I[r][tx] = fma(-L[r][c], I[c][tx], I[r][tx]);
-    __syncthreads();
-  }
-  CVG_GLOBAL double* li = gmem(Linv) + (mat * nblk + j) * NB * NB;
-  for (int r = ty; r < NB; r += kThreads / NB) {
-    const int64_t i = r0 + r, c = r0 + tx;
-    if (i < K && c < K) a[i * K + c] = tx <= r ? L[r][tx] : 0.0;
-    li[r * NB + tx] = I[r][tx];
+  if (l == 0 && bad) flags[mat] = 1;
+  if (fac) {
+#pragma unroll
+    for (int k = 0; k < NB; ++k) arow[k] = k <= q ? u[k] : 0.0;
+  } else {
+    CVG_GLOBAL double* li = gmem(Linv) + (mat * nblk + j) * NB * NB;
+#pragma unroll
+    for (int r = 0; r < NB; ++r) li[r * NB + q] = u[r];
   }
 }
 
-// panel: L_ij = A_ij Linv_jj^T for block rows i > j.  grid (matrices, rows below)
+// panel: L_ij = A_ij Linv_jj^T for block rows i > j, written to the lower
+// triangle and, transposed, to block (j, i) of the upper triangle (which the
+// factorisation never reads; the substitutions read the factor along rows of
+// A from there).  grid (matrices, rows below)
 __global__ __launch_bounds__(kThreads) void chol_panel_kernel(double* __restrict__ A,
                                                               const double* __restrict__ Linv,
-                                                              int64_t K, int32_t j, int32_t nblk) {
+                                                              int64_t Kp, int32_t j, int32_t nblk) {
   __shared__ double Ab[NB][NB + 1];
   __shared__ double Li[NB][NB + 1];
+  __shared__ double Lt[NB][NB + 1];
   const int64_t mat = blockIdx.x;
   const int32_t ib = j + 1 + (int32_t)blockIdx.y;
-  CVG_GLOBAL double* a = gmem(A) + mat * K * K;
+  CVG_GLOBAL double* a = gmem(A) + mat * Kp * Kp;
   const CVG_GLOBAL double* li = gmem(Linv) + (mat * nblk + j) * NB * NB;
   const int t = threadIdx.x, tx = t % NB, ty = t / NB;
   const int64_t r0 = (int64_t)ib * NB, c0 = (int64_t)j * NB;
-  for (int r = ty; r < NB; r += kThreads / NB) {
-    const int64_t i = r0 + r, c = c0 + tx;
-    Ab[r][tx] = (i < K && c < K) ? a[i * K + c] : 0.0;
-    Li[r][tx] = li[r * NB + tx];
+  double va[kRowsPerThread], vl[kRowsPerThread];
+#pragma unroll
+  for (int q = 0; q < kRowsPerThread; ++q) {
+    const int r = ty + kRowStep * q;
+    va[q] = a[(r0 + r) * Kp + c0 + tx];
+    vl[q] = li[r * NB + tx];
+  }
+#pragma unroll
+  for (int q = 0; q < kRowsPerThread; ++q) {
+    Ab[ty + kRowStep * q][tx] = va[q];
+    Li[ty + kRowStep * q][tx] = vl[q];
   }
   __syncthreads();
-  for (int r = ty; r < NB; r += kThreads / NB) {
-    double s = 0.0;
-    for (int k = 0; k <= tx; ++k) s = fma(Ab[r][k], Li[tx][k], s);  // (A Linv^T)[r][tx]
-    const int64_t i = r0 + r, c = c0 + tx;
-    if (i < K && c < K) a[i * K + c] = s;
+  // rows ty + kRowStep * q of (A Linv^T)[.][tx], sharing Linv's row tx
+  double s[kRowsPerThread];
+#pragma unroll
+  for (int q = 0; q < kRowsPerThread; ++q) s[q] = 0.0;
+  for (int k = 0; k <= tx; ++k) {
+    const double b = Li[tx][k];
+#pragma unroll
+    for (int q = 0; q < kRowsPerThread; ++q) s[q] = fma(Ab[ty + kRowStep * q][k], b, s[q]);
+  }
+#pragma unroll
+  for (int q = 0; q < kRowsPerThread; ++q) {
+    const int r = ty + kRowStep * q;
+    a[(r0 + r) * Kp + c0 + tx] = s[q];
+    Lt[r][tx] = s[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kRowsPerThread; ++q) {  // A[c0 + c][r0 + tx] = L[r0 + tx][c0 + c]
+    const int c = ty + kRowStep * q;
+    a[(c0 + c) * Kp + r0 + tx] = Lt[tx][c];
   }
 }
 
 // trailing update A_ik -= L_ij L_kj^T for j < k <= i.  grid (matrices, lower
 // triangle of the remaining blocks)
-__global__ __launch_bounds__(kThreads) void chol_update_kernel(double* __restrict__ A, int64_t K,
+__global__ __launch_bounds__(kThreads) void chol_update_kernel(double* __restrict__ A, int64_t Kp,
                                                                int32_t j) {
   __shared__ double Li[NB][NB + 1];
   __shared__ double Lk[NB][NB + 1];
@@ -142,21 +203,38 @@ __global__ __launch_bounds__(kThreads) void chol_update_kernel(double* __restric
     ++ii;
   }
   const int32_t ib = j + 1 + ii, kb = j + 1 + q;
-  CVG_GLOBAL double* a = gmem(A) + mat * K * K;
+  CVG_GLOBAL double* a = gmem(A) + mat * Kp * Kp;
   const int t = threadIdx.x, tx = t % NB, ty = t / NB;
   const int64_t c0 = (int64_t)j * NB;
-  for (int r = ty; r < NB; r += kThreads / NB) {
-    const int64_t i = (int64_t)ib * NB + r, k = (int64_t)kb * NB + r, c = c0 + tx;
-    Li[r][tx] = (i < K && c < K) ? a[i * K + c] : 0.0;
-    Lk[r][tx] = (k < K && c < K) ? a[k * K + c] : 0.0;
+  CVG_GLOBAL double* out = a + (int64_t)ib * NB * Kp + (int64_t)kb * NB + tx;  // A_ik[0][tx]
+  double vi[kRowsPerThread], vk[kRowsPerThread], vo[kRowsPerThread];
+#pragma unroll
+  for (int p = 0; p < kRowsPerThread; ++p) {
+    const int r = ty + kRowStep * p;
+    vi[p] = a[((int64_t)ib * NB + r) * Kp + c0 + tx];
+    vk[p] = a[((int64_t)kb * NB + r) * Kp + c0 + tx];
+    vo[p] = out[r * Kp];
+  }
+#pragma unroll
+  for (int p = 0; p < kRowsPerThread; ++p) {
+    Li[ty + kRowStep * p][tx] = vi[p];
+    Lk[ty + kRowStep * p][tx] = vk[p];
   }
   __syncthreads();
-  for (int r = ty; r < NB; r += kThreads / NB) {
-    const int64_t i = (int64_t)ib * NB + r, k = (int64_t)kb * NB + tx;
-    if (i >= K || k >= K || k > i) continue;
-    double s = 0.0;
-    for (int c = 0; c < NB; ++c) s = fma(Li[r][c], Lk[tx][c], s);
-    a[i * K + k] -= s;
+  // rows ty + kRowStep * p of the product, sharing L_kj's row tx
+  double s[kRowsPerThread];
+#pragma unroll
+  for (int p = 0; p < kRowsPerThread; ++p) s[p] = 0.0;
+#pragma unroll 8
+  for (int c = 0; c < NB; ++c) {
+    const double b = Lk[tx][c];
+#pragma unroll
+    for (int p = 0; p < kRowsPerThread; ++p) s[p] = fma(Li[ty + kRowStep * p][c], b, s[p]);
+  }
+#pragma unroll
+  for (int p = 0; p < kRowsPerThread; ++p) {
+    const int r = ty + kRowStep * p;
+    if (ib != kb || tx <= r) out[r * Kp] = vo[p] - s[p];
   }
 }
 
@@ -164,23 +242,29 @@ __global__ __launch_bounds__(kThreads) void chol_update_kernel(double* __restric
 // of R) walks the block steps itself.
 //   forward step j:  Z_j = Linv_jj R_j;    R_i -= L_ij Z_j     for i > j
 //   backward step j: W_j = Linv_jj^T R_j;  R_i -= L_ji^T W_j   for i < j
-// The updates run over (row, column) pairs of the other block rows, so a
-// narrow R (M of a few columns) keeps every lane busy.  Each workgroup owns
-// its rows x columns of R: its own writes are the only ones it reads back
-// (ordered by the barrier between steps).
+// In both passes the coefficient of Z[c] in row i is A[r0 + c][i]: the
+// factor's block row j in the lower triangle (backward, i < r0) or the
+// transposed copy of its block column j in the upper triangle (forward,
+// i >= r0 + 32).  One thread per row of R reads those 32 values down a column
+// of A, consecutive threads consecutive columns, all loads in flight.  Each
+// workgroup owns its rows x columns of R: its own writes are the only ones it
+// reads back (ordered by the barrier between steps).  Rows past K are not
+// updated (they hold zeros throughout).  MW (8, 16 or 32) is the width of R
+// each row update carries in registers: at least the block's columns of B,
+// the rest padding zeros that stay zero.
+template <int MW>
 __global__ __launch_bounds__(kThreads) void tri_solve_kernel(const double* __restrict__ A,
                                                              const double* __restrict__ Linv,
                                                              double* __restrict__ R, int64_t K,
-                                                             int64_t M, int32_t nblk) {
+                                                             int64_t M, int64_t Kp, int64_t Mp,
+                                                             int32_t nblk) {
   __shared__ double Z[NB][NB + 1];
   __shared__ double Li[NB][NB + 1];
   __shared__ double Rb[NB][NB + 1];
-  __shared__ double Ls[kSolveRows][NB + 1];
   const int64_t mat = blockIdx.x;
   const int64_t m0 = (int64_t)blockIdx.y * NB;
-  const int64_t mw = M - m0 < NB ? M - m0 : NB;  // columns of R in this block
-  const CVG_GLOBAL double* a = gmem(A) + mat * K * K;
-  CVG_GLOBAL double* rr = gmem(R) + mat * K * M;
+  const CVG_GLOBAL double* a = gmem(A) + mat * Kp * Kp;
+  CVG_GLOBAL double* rr = gmem(R) + mat * Kp * Mp + m0;
   const int t = threadIdx.x, tx = t % NB, ty = t / NB;
   for (int pass = 0; pass < 2; ++pass) {
     const bool backward = pass == 1;
@@ -188,51 +272,52 @@ __global__ __launch_bounds__(kThreads) void tri_solve_kernel(const double* __res
       const int32_t j = backward ? nblk - 1 - jj : jj;
       const int64_t r0 = (int64_t)j * NB;
       const CVG_GLOBAL double* li = gmem(Linv) + (mat * nblk + j) * NB * NB;
-      for (int r = ty; r < NB; r += kThreads / NB) {
-        const int64_t i = r0 + r;
-        Rb[r][tx] = (i < K && tx < mw) ? rr[i * M + m0 + tx] : 0.0;
-        Li[r][tx] = li[r * NB + tx];
+      double vr[kRowsPerThread], vl[kRowsPerThread];
+#pragma unroll
+      for (int q = 0; q < kRowsPerThread; ++q) {
+        const int r = ty + kRowStep * q;
+        vr[q] = rr[(r0 + r) * Mp + tx];
+        vl[q] = li[r * NB + tx];
+      }
+#pragma unroll
+      for (int q = 0; q < kRowsPerThread; ++q) {
+        Rb[ty + kRowStep * q][tx] = vr[q];
+        Li[ty + kRowStep * q][tx] = vl[q];
       }
       __syncthreads();
-      for (int r = ty; r < NB; r += kThreads / NB) {
+#pragma unroll
+      for (int q = 0; q < kRowsPerThread; ++q) {
+        const int r = ty + kRowStep * q;
         double sum = 0.0;
         if (!backward)
           for (int k = 0; k <= r; ++k) sum = fma(Li[r][k], Rb[k][tx], sum);
         else
           for (int k = r; k < NB; ++k) sum = fma(Li[k][r], Rb[k][tx], sum);
         Z[r][tx] = sum;
-        const int64_t i = r0 + r;
-        if (i < K && tx < mw) rr[i * M + m0 + tx] = sum;
+        rr[(r0 + r) * Mp + tx] = sum;
       }
       __syncthreads();
-      // the other block rows: forward i >= r0 + NB, backward i < r0; the
-      // block column of L they need is staged in LDS kSolveRows rows at a
-      // time (coalesced loads, all in flight), the dot products then read LDS
       const int64_t lo = backward ? 0 : r0 + NB, hi = backward ? r0 : K;
-      const int64_t cmax = K - r0 < NB ? K - r0 : NB;  // columns of the block inside K
-      for (int64_t i0 = lo; i0 < hi; i0 += kSolveRows) {
-        const int64_t nr = hi - i0 < kSolveRows ? hi - i0 : kSolveRows;
-        for (int e = t; e < kSolveRows * NB; e += kThreads) {
-          // forward: Ls[ri][c] = L_ij = A[i0 + ri][r0 + c]
-          // backward: Ls[ri][c] = (L_ji)^T = A[r0 + c][i0 + ri]
-          const int ri = backward ? e % kSolveRows : e / NB;
-          const int c = backward ? e / kSolveRows : e % NB;
-          double v = 0.0;
-          if (ri < nr && c < cmax)
-            v = backward ? a[(r0 + c) * K + i0 + ri] : a[(i0 + ri) * K + r0 + c];
-          Ls[ri][c] = v;
-        }
-        __syncthreads();
-        for (int64_t e = t; e < nr * mw; e += kThreads) {
-          const int ri = (int)(e / mw);
-          const int mm = (int)(e % mw);
-          double sum = 0.0;
+      for (int64_t i = lo + t; i < hi; i += kThreads) {
+        double lc[NB], rv[MW];
 #pragma unroll
-          for (int c = 0; c < NB; ++c) sum = fma(Ls[ri][c], Z[c][mm], sum);
-          rr[(i0 + ri) * M + m0 + mm] -= sum;
+        for (int c = 0; c < NB; ++c) lc[c] = a[(r0 + c) * Kp + i];
+#pragma unroll
+        for (int mm = 0; mm < MW; ++mm) rv[mm] = rr[i * Mp + mm];
+        double sum[MW];
+#pragma unroll
+        for (int mm = 0; mm < MW; ++mm) sum[mm] = 0.0;
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+#pragma unroll
+          for (int mm = 0; mm < MW; ++mm) sum[mm] = fma(lc[c], Z[c][mm], sum[mm]);
+          // keep the scheduler from hoisting every row of Z into registers
+          if (c % 4 == 3) __builtin_amdgcn_sched_barrier(0);
         }
-        __syncthreads();
+#pragma unroll
+        for (int mm = 0; mm < MW; ++mm) rr[i * Mp + mm] = rv[mm] - sum[mm];
       }
+      __syncthreads();
     }
   }
 }
@@ -241,33 +326,45 @@ __global__ __launch_bounds__(kThreads) void tri_solve_kernel(const double* __res
 
 void ridge_solve(const double* xtx, const double* xty, const double* lambdas, int32_t n_folds,
                  int32_t n_lambda, int64_t K, int64_t M, double* A, double* R, double* Linv,
-                 int32_t* flags, hipStream_t s) {
+                 int32_t* flags, double* B, hipStream_t s) {
   const int64_t n_mat = (int64_t)n_folds * n_lambda;
-  if (n_mat <= 0) return;
+  if (n_mat <= 0 || K <= 0) return;
   const int32_t nblk = (int32_t)((K + NB - 1) / NB);
+  const int64_t Kp = (int64_t)nblk * NB, Mp = (M + NB - 1) / NB * NB;
   {
-    const int64_t per = (K * K + kThreads - 1) / kThreads;
+    const int64_t per = (Kp * Kp + kThreads - 1) / kThreads;
     dim3 grid((unsigned)(per < 1024 ? per : 1024), (unsigned)n_mat);
-    ridge_setup_kernel<<<grid, kThreads, 0, s>>>(xtx, xty, lambdas, n_lambda, K, M, A, R);
+    ridge_setup_kernel<<<grid, kThreads, 0, s>>>(xtx, xty, lambdas, n_lambda, K, M, Kp, Mp, A, R);
     CVG_LAUNCH_CHECK();
   }
   for (int32_t j = 0; j < nblk; ++j) {
-    chol_diag_kernel<<<(unsigned)n_mat, kThreads, 0, s>>>(A, Linv, flags, K, j, nblk);
+    chol_diag_kernel<<<(unsigned)n_mat, kWave, 0, s>>>(A, Linv, flags, Kp, j, nblk);
     CVG_LAUNCH_CHECK();
     const int32_t below = nblk - j - 1;
     if (below > 0) {
-      chol_panel_kernel<<<dim3((unsigned)n_mat, (unsigned)below), kThreads, 0, s>>>(A, Linv, K, j,
-                                                                                    nblk);
+      chol_panel_kernel<<<dim3((unsigned)n_mat, (unsigned)below), kThreads, 0, s>>>(A, Linv, Kp,
+                                                                                    j, nblk);
       CVG_LAUNCH_CHECK();
       chol_update_kernel<<<dim3((unsigned)n_mat, (unsigned)(below * (below + 1) / 2)), kThreads,
-                           0, s>>>(A, K, j);
+                           0, s>>>(A, Kp, j);
       CVG_LAUNCH_CHECK();
     }
   }
   if (M <= 0) return;
-  const unsigned mb = (unsigned)((M + NB - 1) / NB);
-  tri_solve_kernel<<<dim3((unsigned)n_mat, mb), kThreads, 0, s>>>(A, Linv, R, K, M, nblk);
+  const dim3 grid((unsigned)n_mat, (unsigned)(Mp / NB));
+  if (M <= 8)
+    tri_solve_kernel<8><<<grid, kThreads, 0, s>>>(A, Linv, R, K, M, Kp, Mp, nblk);
+  else if (M <= 16)
+    tri_solve_kernel<16><<<grid, kThreads, 0, s>>>(A, Linv, R, K, M, Kp, Mp, nblk);
+  else
+    tri_solve_kernel<NB><<<grid, kThreads, 0, s>>>(A, Linv, R, K, M, Kp, Mp, nblk);
   CVG_LAUNCH_CHECK();
+  {
+    const int64_t per = (K * M + kThreads - 1) / kThreads;
+    dim3 grid((unsigned)(per < 1024 ? per : 1024), (unsigned)n_mat);
+    ridge_store_kernel<<<grid, kThreads, 0, s>>>(R, K, M, Kp, Mp, B);
+    CVG_LAUNCH_CHECK();
+  }
 }
 
 }  // namespace cvg
