@@ -133,7 +133,9 @@ def cpu_legs(X, Y, fold, P, gpu_xx, gpu_xy, budget_s):
 
 def measure(cv, torch, Xd, Yd, fd, P, K, M, mode, steps, warmup):
     """Time `steps` whole steps (after `warmup`): create + all folds x 12
-    classes + destroy.  Stage times come from HIP events on the same stream."""
+    classes + destroy, back to back with no host synchronisation between
+    them.  Stage times come from a separate pass of steps with the library's
+    HIP events on (those steps wait for their events)."""
     odt = torch.float64 if mode == "fp64" else torch.float32
     dev = Xd.device
     xx = torch.empty(P, 4, K, K, dtype=odt, device=dev)
@@ -153,22 +155,24 @@ def measure(cv, torch, Xd, Yd, fd, P, K, M, mode, steps, warmup):
             st = cv.cvgram_stage_times(h)
         cv.cvgram_destroy(h)
         if timing:
+            e1.synchronize()
             st["correct"] = e0.elapsed_time(e1)
         return st
 
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    cv.cvgram_set_stage_timing(True)
-    stages = []
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        stages.append(step(timing=True))
+        step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    cv.cvgram_set_stage_timing(False)
     ms = (t1 - t0) * 1e3 / steps
+    # stage breakdown (and the Gram launch time behind the roofline)
+    cv.cvgram_set_stage_timing(True)
+    stages = [step(timing=True) for _ in range(max(3, min(steps, 20)))]
+    torch.cuda.synchronize()
+    cv.cvgram_set_stage_timing(False)
     stage_ms = {k: float(np.mean([s[k] for s in stages])) for k in stages[0]}
     return ms, stage_ms, xx, xy
 

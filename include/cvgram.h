@@ -225,8 +225,8 @@ cvgram_status cvgram_stage_times(cvgram_t h, double* ms, int32_t n);
 
 /* Device workspace released by cvgram_destroy() is kept in a per-device
  * cache and reused by later handles of similar size (bounded to 32 GiB per
- * device).  cvgram_trim_cache() frees every cached block of the current
- * device. */
+ * device).  cvgram_trim_cache() waits for the work still using cached blocks
+ * of the current device, then frees them. */
 cvgram_status cvgram_trim_cache(void);
 
 /* ---------------------------------------------------------------------------
@@ -303,10 +303,19 @@ cvgram_status cvgram_autotune(const void* X, const void* Y, const int32_t* fold_
  * n is the capacity of info (at most 4 entries are written). */
 cvgram_status cvgram_plan_info(cvgram_t h, int64_t* info, int32_t n);
 
-/* Change the stream used by later calls on this handle. */
+/* Change the stream used by later calls on this handle.  Work queued on the
+ * new stream from then on runs after everything already queued on the old
+ * one (an event recorded there is waited for on the device, not the host). */
 cvgram_status cvgram_set_stream(cvgram_t h, void* stream);
 
-/* Wait for the handle's outstanding work, then free it (NULL is a no-op). */
+/* Free the handle (NULL is a no-op) without waiting for its queued work:
+ * its workspace goes back to the per-device cache in stream order, tagged
+ * with an event recorded on the handle's stream now.  Later work on the same
+ * stream reuses it at once (stream order puts that work behind this
+ * handle's); other streams, and the host for pinned blocks, reuse it only
+ * once that event has completed.  Outputs of the handle's calls are complete
+ * when the stream reaches this point; device errors of that work surface at
+ * the caller's next synchronisation. */
 cvgram_status cvgram_destroy(cvgram_t h);
 
 /* Static description of a status code. */

@@ -35,16 +35,38 @@ cvgram_status fail(cvgram_status st, const std::string& msg) {
 // workspace caches.  Device blocks (per device) and pinned host blocks
 // released by a handle are reused by later handles when a cached block is at
 // least as large as the request and at most about twice as large.
+//
+// Release is stream-ordered: a handle released with work still queued tags
+// its blocks with an event recorded on its stream at that point.  A tagged
+// device block is reused at once by work on the same stream (stream order
+// puts the new work behind the old); by another stream, and a pinned block by
+// the host, only once the event has completed.
 // ---------------------------------------------------------------------------
 constexpr size_t kCacheCap = (size_t)32 << 30;
 constexpr size_t kHostCacheCap = (size_t)1 << 30;
 constexpr int kMaxDev = 64;
 
+hipEvent_t event_get(int device, bool timed);
+void event_put(int device, bool timed, hipEvent_t e);
+
+// the event of one stream-ordered release, shared by the blocks it tags;
+// back to the event pool when the last of them leaves the cache
+struct ReleaseMark {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev = nullptr;
+  ~ReleaseMark() { event_put(device, false, ev); }
+};
+struct Cached {
+  void* ptr = nullptr;
+  std::shared_ptr<ReleaseMark> mark;  // null: released with no work queued
+};
+
 struct Cache {
   std::mutex mu;
-  std::multimap<size_t, void*> dev[kMaxDev];
+  std::multimap<size_t, Cached> dev[kMaxDev];
   size_t dev_total[kMaxDev] = {};
-  std::multimap<size_t, void*> host;
+  std::multimap<size_t, Cached> host;
   size_t host_total = 0;
 };
 Cache& cache() {
@@ -52,23 +74,62 @@ Cache& cache() {
   return *c;
 }
 
-void cache_trim_dev(int dev) {
-  Cache& c = cache();
-  std::lock_guard<std::mutex> g(c.mu);
-  if (dev < 0 || dev >= kMaxDev) return;
-  for (auto& kv : c.dev[dev]) (void)hipFree(kv.second);
-  c.dev[dev].clear();
-  c.dev_total[dev] = 0;
+// true once the work before the mark has completed (no mark: nothing queued)
+bool mark_done(const std::shared_ptr<ReleaseMark>& mk) {
+  if (!mk) return true;
+  const hipError_t e = hipEventQuery(mk->ev);
+  if (e == hipSuccess) return true;
+  (void)hipGetLastError();  // "not ready" is an answer, not an error to keep
+  return false;
 }
 
-void* take(std::multimap<size_t, void*>& m, size_t& total, size_t want, size_t* got) {
-  auto it = m.lower_bound(want);
-  if (it == m.end() || it->first > 2 * want + 4096) return nullptr;
-  void* p = it->second;
-  *got = it->first;
-  total -= it->first;
-  m.erase(it);
-  return p;
+void cache_trim_dev(int dev) {
+  std::multimap<size_t, Cached> gone;
+  {
+    Cache& c = cache();
+    std::lock_guard<std::mutex> g(c.mu);
+    if (dev < 0 || dev >= kMaxDev) return;
+    gone.swap(c.dev[dev]);
+    c.dev_total[dev] = 0;
+  }
+  for (auto& kv : gone) {
+    if (kv.second.mark) (void)hipEventSynchronize(kv.second.mark->ev);
+    (void)hipFree(kv.second.ptr);
+  }
+}
+
+// a cached block of at least `want` bytes and at most about twice that.  A
+// block that is free now (idle, or a device block last released on `stream`)
+// is preferred; else the first that fits is returned with the mark the caller
+// must wait for before using it.
+struct Taken {
+  void* p = nullptr;
+  std::shared_ptr<ReleaseMark> wait;
+};
+Taken take(std::multimap<size_t, Cached>& m, size_t& total, size_t want, size_t* got,
+           hipStream_t stream, bool host) {
+  Taken r;
+  auto pick = m.end(), first = m.end();
+  int looked = 0;
+  for (auto it = m.lower_bound(want); it != m.end() && it->first <= 2 * want + 4096 && looked < 8;
+       ++it, ++looked) {
+    const auto& mk = it->second.mark;
+    if ((!host && mk && mk->stream == stream) || mark_done(mk)) {
+      pick = it;
+      break;
+    }
+    if (first == m.end()) first = it;
+  }
+  if (pick == m.end()) {
+    if (first == m.end()) return r;
+    pick = first;
+    r.wait = pick->second.mark;
+  }
+  r.p = pick->second.ptr;
+  *got = pick->first;
+  total -= pick->first;
+  m.erase(pick);
+  return r;
 }
 
 // one owned block: device or pinned host
@@ -80,17 +141,24 @@ struct Block {
 
 struct Owned {
   int device = 0;
+  hipStream_t stream = nullptr;  // the stream the owner's work runs on
   std::vector<Block> blocks;
 
   void* dev(size_t want) {
     want = (want + 255) / 256 * 256;
     if (want == 0) want = 256;
     size_t got = want;
-    void* p = nullptr;
+    Taken tk;
     {
       Cache& c = cache();
       std::lock_guard<std::mutex> g(c.mu);
-      if (device >= 0 && device < kMaxDev) p = take(c.dev[device], c.dev_total[device], want, &got);
+      if (device >= 0 && device < kMaxDev)
+        tk = take(c.dev[device], c.dev_total[device], want, &got, stream, false);
+    }
+    void* p = tk.p;
+    if (tk.wait && hipEventSynchronize(tk.wait->ev) != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hipDeviceSynchronize();
     }
     if (!p) {
       hipError_t e = hipMalloc(&p, want);
@@ -114,11 +182,16 @@ struct Owned {
     want = (want + 4095) / 4096 * 4096;
     if (want == 0) want = 4096;
     size_t got = want;
-    void* p = nullptr;
+    Taken tk;
     {
       Cache& c = cache();
       std::lock_guard<std::mutex> g(c.mu);
-      p = take(c.host, c.host_total, want, &got);
+      tk = take(c.host, c.host_total, want, &got, stream, true);
+    }
+    void* p = tk.p;
+    if (tk.wait && hipEventSynchronize(tk.wait->ev) != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hipDeviceSynchronize();
     }
     if (!p) {
       hipError_t e = hipHostMalloc(&p, want, hipHostMallocDefault);
@@ -143,30 +216,55 @@ struct Owned {
       }
   }
 
-  void release_one(const Block& b) {
+  void release_one(const Block& b, const std::shared_ptr<ReleaseMark>& mark = nullptr) {
     Cache& c = cache();
     {
       std::lock_guard<std::mutex> g(c.mu);
       if (b.host) {
         if (c.host_total + b.bytes <= kHostCacheCap) {
-          c.host.insert({b.bytes, b.ptr});
+          c.host.insert({b.bytes, Cached{b.ptr, mark}});
           c.host_total += b.bytes;
           return;
         }
       } else if (device >= 0 && device < kMaxDev && c.dev_total[device] + b.bytes <= kCacheCap) {
-        c.dev[device].insert({b.bytes, b.ptr});
+        c.dev[device].insert({b.bytes, Cached{b.ptr, mark}});
         c.dev_total[device] += b.bytes;
         return;
       }
     }
+    if (mark) (void)hipEventSynchronize(mark->ev);
     if (b.host)
       (void)hipHostFree(b.ptr);
     else
       (void)hipFree(b.ptr);
   }
 
+  // every block back to the cache; no work that uses them may be queued
   void release() {
     for (auto& b : blocks) release_one(b);
+    blocks.clear();
+  }
+
+  // every block back to the cache while work that uses them may still be
+  // queued on `s`: they are tagged with an event recorded there now
+  void release_async(hipStream_t s) {
+    if (blocks.empty()) return;
+    auto mark = std::make_shared<ReleaseMark>();
+    mark->device = device;
+    mark->stream = s;
+    bool ok = false;
+    try {
+      mark->ev = event_get(device, false);
+      ok = hipEventRecord(mark->ev, s) == hipSuccess;
+    } catch (const Fail&) {
+    }
+    if (!ok) {
+      (void)hipGetLastError();
+      (void)hipStreamSynchronize(s);
+      release();
+      return;
+    }
+    for (auto& b : blocks) release_one(b, mark);
     blocks.clear();
   }
 };
@@ -271,9 +369,9 @@ struct ProbPlan {
 
 // Events of released handles, kept per device and reused by later handles
 // (a handle per call is the common pattern; creating its events each time
-// would sit on the host path between two steps).  Only events whose work
-// has completed are returned here: a handle's stream is synchronised before
-// it is released.
+// would sit on the host path between two steps).  An event may come back
+// with its last record still pending: its next user records it again, and
+// nothing waits on the old record any more.
 struct EventPool {
   std::mutex mu;
   std::vector<hipEvent_t> timed[kMaxDev], plain[kMaxDev];
@@ -370,6 +468,22 @@ struct Batch {
     ev_wait = nullptr;
     mem.release();
   }
+  // as release(), with work still queued on the stream (stream-ordered; a
+  // captured graph is waited for first)
+  void release_async() {
+    if (gexec || graph) {
+      (void)hipStreamSynchronize(stream);
+      release();
+      return;
+    }
+    for (auto& e : ev) {
+      event_put(device, true, e);
+      e = nullptr;
+    }
+    event_put(device, false, ev_wait);
+    ev_wait = nullptr;
+    mem.release_async(stream);
+  }
 };
 
 int bit_length(uint32_t v) {
@@ -396,6 +510,7 @@ cvgram_status bookkeeping(Batch& b) {
   int32_t* perm_block = (int32_t*)b.mem.dev((size_t)sumN * sizeof(int32_t));
   Owned scratch;
   scratch.device = b.device;
+  scratch.stream = s;
   // info[0] min label, info[1] max label, info[2 ..) counts of labels below
   // kCountLabels, then flags: one block, one initialising launch, one copy.
   // The block stays with the batch: the sort's scan reads the counts after
@@ -433,6 +548,14 @@ cvgram_status bookkeeping(Batch& b) {
         launch_pivot_direct(b.dtype, b.mode != CVGRAM_MODE_FP64, p.X, p.Y, p.N, p.K, p.M,
                             p.d_pivot, s);
       }
+      // the sort starts before the wait on the guess that the labels fit in
+      // one 8-bit pass (P <= 256, where its result is exact); labels that
+      // turn out wider are sorted again below.  Any label values keep the
+      // early pass inside its buffers (it sorts by the low 8 bits).
+      const int32_t* sorted = nullptr;
+      constexpr int kEarlyBits = 8;
+      radix_partition(p.fold, p.N, kEarlyBits, counts, keys, keys + maxN, p.d_perm, perm_tmp,
+                      hist, true, &sorted, s);
       CVG_HIP(hipEventSynchronize(b.ev_wait));
       if (hbuf[0] < 0) {
         st = fail(CVGRAM_EFOLDS, tag + "fold label < 0 (Definition 1)");
@@ -448,9 +571,11 @@ cvgram_status bookkeeping(Batch& b) {
         break;
       }
       p.P = (int32_t)P;
-      const int32_t* sorted = nullptr;
-      radix_partition(p.fold, p.N, bit_length((uint32_t)(P - 1)), counts, keys, keys + maxN,
-                      p.d_perm, perm_tmp, hist, &sorted, s);
+      const int bits = bit_length((uint32_t)(P - 1));
+      if (bits > kEarlyBits)
+        // the early pass scanned the histogram in place: count it again
+        radix_partition(p.fold, p.N, bits, counts, keys, keys + maxN, p.d_perm, perm_tmp, hist,
+                        false, &sorted, s);
       p.offsets.assign(P + 1, 0);
       bool empty = false;
       if (P <= kCountLabels) {
@@ -982,6 +1107,7 @@ cvgram_status prepare(Batch& b) {
       if (!e) e = event_get(b.device, true);
   if (b.timing) CVG_HIP(hipEventRecord(b.ev[0], b.stream));
   b.mem.device = b.device;
+  b.mem.stream = b.stream;
   cvgram_status st = bookkeeping(b);
   if (st != CVGRAM_OK) return st;
   thread_local HostLists L;
@@ -1173,6 +1299,7 @@ cvgram_status cvgram_ridge(cvgram_t h, int32_t p0, int32_t p1, const double* lam
   hipStream_t s = h->b.stream;
   Owned ws;
   ws.device = h->b.device;
+  ws.stream = h->b.stream;
   cvgram_status st = CVGRAM_OK;
   try {
     double* xtx = (double*)ws.dev((size_t)nf * K * K * 8);
@@ -1295,16 +1422,29 @@ cvgram_status cvgram_plan_info(cvgram_t h, int64_t* info, int32_t n) {
 
 cvgram_status cvgram_set_stream(cvgram_t h, void* stream) {
   if (!h) return fail(CVGRAM_EINVAL, "NULL handle");
-  h->b.stream = (hipStream_t)stream;
+  hipStream_t ns = (hipStream_t)stream;
+  if (ns != h->b.stream) {
+    // later work on the new stream (and the stream-ordered release at
+    // destroy) comes after everything queued on the old one
+    try {
+      hipEvent_t e = event_get(h->b.device, false);
+      const hipError_t r1 = hipEventRecord(e, h->b.stream);
+      const hipError_t r2 = r1 == hipSuccess ? hipStreamWaitEvent(ns, e, 0) : r1;
+      event_put(h->b.device, false, e);
+      if (r2 != hipSuccess) return fail(CVGRAM_EDEVICE, hipGetErrorString(r2));
+    } catch (const Fail& f) {
+      return f.st;
+    }
+    h->b.stream = ns;
+    h->b.mem.stream = ns;
+  }
   return CVGRAM_OK;
 }
 
 cvgram_status cvgram_destroy(cvgram_t h) {
   if (!h) return CVGRAM_OK;
-  hipError_t e = hipStreamSynchronize(h->b.stream);
-  h->b.release();
+  h->b.release_async();
   delete h;
-  if (e != hipSuccess) return fail(CVGRAM_EDEVICE, hipGetErrorString(e));
   return CVGRAM_OK;
 }
 

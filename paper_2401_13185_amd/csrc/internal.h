@@ -178,10 +178,11 @@ constexpr int kCountLabels = 4096;
 void launch_label_count(const int32_t* fold, int64_t N, int32_t* info, int32_t* counts,
                         int32_t* hist, hipStream_t s);
 // stable sort of the labels in [0, 2^bits); hist as left by launch_label_count
-// on the same labels, counts = its label counts (used when bits <= 8)
+// on the same labels when hist_ready (else the first pass recounts it),
+// counts = its label counts (used when bits <= 8)
 void radix_partition(const int32_t* fold, int64_t N, int bits, const int32_t* counts,
                      int32_t* keys_a, int32_t* keys_b, int32_t* perm, int32_t* perm_tmp,
-                     int32_t* hist, const int32_t** sorted_keys, hipStream_t s);
+                     int32_t* hist, bool hist_ready, const int32_t** sorted_keys, hipStream_t s);
 int64_t radix_hist_entries(int64_t N);
 void launch_fold_offsets(const int32_t* sorted_keys, int64_t N, int32_t P, int64_t* offsets,
                          int32_t* flag, hipStream_t s);

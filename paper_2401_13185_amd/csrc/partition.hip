@@ -341,7 +341,8 @@ void scan_exclusive(int32_t* a, int64_t n, int32_t* sums, hipStream_t s) {
 
 void radix_partition(const int32_t* fold, int64_t N, int bits, const int32_t* counts,
                      int32_t* keys_a, int32_t* keys_b, int32_t* perm, int32_t* perm_tmp,
-                     int32_t* hist, const int32_t** sorted_keys, hipStream_t s) {
+                     int32_t* hist, bool hist_ready, const int32_t** sorted_keys,
+                     hipStream_t s) {
   const int64_t tiles = (N + kTileElems - 1) / kTileElems;
   int passes = (bits + 7) / 8;
   if (passes < 1) passes = 1;
@@ -352,7 +353,7 @@ void radix_partition(const int32_t* fold, int64_t N, int bits, const int32_t* co
     int32_t* kout = (pass & 1) ? keys_b : keys_a;
     int32_t* vout = ((passes - 1 - pass) & 1) ? perm_tmp : perm;
     const int shift = 8 * pass;
-    if (pass > 0) {
+    if (pass > 0 || !hist_ready) {
       radix_hist_kernel<<<(unsigned)tiles, kThreads, 0, s>>>(kin, N, shift, hist, tiles);
       CVG_LAUNCH_CHECK();
     }
