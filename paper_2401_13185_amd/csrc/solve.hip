@@ -246,12 +246,14 @@ __global__ __launch_bounds__(kThreads) void chol_update_kernel(double* __restric
 // factor's block row j in the lower triangle (backward, i < r0) or the
 // transposed copy of its block column j in the upper triangle (forward,
 // i >= r0 + 32).  One thread per row of R reads those 32 values down a column
-// of A, consecutive threads consecutive columns, all loads in flight.  Each
-// workgroup owns its rows x columns of R: its own writes are the only ones it
-// reads back (ordered by the barrier between steps).  Rows past K are not
-// updated (they hold zeros throughout).  MW (8, 16 or 32) is the width of R
-// each row update carries in registers: at least the block's columns of B,
-// the rest padding zeros that stay zero.
+// of A, consecutive threads consecutive columns, all loads in flight.  The
+// rows of the next step's block go on to it through LDS as they are updated,
+// and the next diagonal inverse is loaded during the update, so a step waits
+// on memory once.  Each workgroup owns its rows x columns of R: its own
+// writes are the only ones it reads back (ordered by the barriers between
+// steps).  Padding rows of the last block (past K) stay zero.  MW (8, 16 or
+// 32) is the width of R each row update carries in registers: at least the
+// block's columns of B, the rest padding zeros that stay zero.
 template <int MW>
 __global__ __launch_bounds__(kThreads) void tri_solve_kernel(const double* __restrict__ A,
                                                              const double* __restrict__ Linv,
@@ -259,45 +261,57 @@ __global__ __launch_bounds__(kThreads) void tri_solve_kernel(const double* __res
                                                              int64_t M, int64_t Kp, int64_t Mp,
                                                              int32_t nblk) {
   __shared__ double Z[NB][NB + 1];
-  __shared__ double Li[NB][NB + 1];
+  __shared__ double Li[2][NB][NB + 1];
   __shared__ double Rb[NB][NB + 1];
   const int64_t mat = blockIdx.x;
   const int64_t m0 = (int64_t)blockIdx.y * NB;
   const CVG_GLOBAL double* a = gmem(A) + mat * Kp * Kp;
   CVG_GLOBAL double* rr = gmem(R) + mat * Kp * Mp + m0;
   const int t = threadIdx.x, tx = t % NB, ty = t / NB;
+  auto load_li = [&](int32_t j, double* vl) {
+    const CVG_GLOBAL double* li = gmem(Linv) + (mat * nblk + j) * NB * NB;
+#pragma unroll
+    for (int q = 0; q < kRowsPerThread; ++q) vl[q] = li[(ty + kRowStep * q) * NB + tx];
+  };
+  int buf = 0;
   for (int pass = 0; pass < 2; ++pass) {
     const bool backward = pass == 1;
-    for (int32_t jj = 0; jj < nblk; ++jj) {
-      const int32_t j = backward ? nblk - 1 - jj : jj;
+    {
+      // the pass's first block: its rows of R and its inverse from memory
+      const int32_t j = backward ? nblk - 1 : 0;
       const int64_t r0 = (int64_t)j * NB;
-      const CVG_GLOBAL double* li = gmem(Linv) + (mat * nblk + j) * NB * NB;
       double vr[kRowsPerThread], vl[kRowsPerThread];
 #pragma unroll
-      for (int q = 0; q < kRowsPerThread; ++q) {
-        const int r = ty + kRowStep * q;
-        vr[q] = rr[(r0 + r) * Mp + tx];
-        vl[q] = li[r * NB + tx];
-      }
+      for (int q = 0; q < kRowsPerThread; ++q) vr[q] = rr[(r0 + ty + kRowStep * q) * Mp + tx];
+      load_li(j, vl);
 #pragma unroll
       for (int q = 0; q < kRowsPerThread; ++q) {
         Rb[ty + kRowStep * q][tx] = vr[q];
-        Li[ty + kRowStep * q][tx] = vl[q];
+        Li[buf][ty + kRowStep * q][tx] = vl[q];
       }
       __syncthreads();
+    }
+    for (int32_t jj = 0; jj < nblk; ++jj) {
+      const int32_t j = backward ? nblk - 1 - jj : jj;
+      const int64_t r0 = (int64_t)j * NB;
+      const bool last = jj + 1 == nblk;
+      const int32_t jn = backward ? j - 1 : j + 1;  // the next step's block
+      const int64_t n0 = (int64_t)jn * NB;
 #pragma unroll
       for (int q = 0; q < kRowsPerThread; ++q) {
         const int r = ty + kRowStep * q;
         double sum = 0.0;
         if (!backward)
-          for (int k = 0; k <= r; ++k) sum = fma(Li[r][k], Rb[k][tx], sum);
+          for (int k = 0; k <= r; ++k) sum = fma(Li[buf][r][k], Rb[k][tx], sum);
         else
-          for (int k = r; k < NB; ++k) sum = fma(Li[k][r], Rb[k][tx], sum);
+          for (int k = r; k < NB; ++k) sum = fma(Li[buf][k][r], Rb[k][tx], sum);
         Z[r][tx] = sum;
         rr[(r0 + r) * Mp + tx] = sum;
       }
       __syncthreads();
-      const int64_t lo = backward ? 0 : r0 + NB, hi = backward ? r0 : K;
+      double vl[kRowsPerThread];
+      if (!last) load_li(jn, vl);
+      const int64_t lo = backward ? 0 : r0 + NB, hi = backward ? r0 : Kp;
       for (int64_t i = lo + t; i < hi; i += kThreads) {
         double lc[NB], rv[MW];
 #pragma unroll
@@ -315,9 +329,21 @@ __global__ __launch_bounds__(kThreads) void tri_solve_kernel(const double* __res
           if (c % 4 == 3) __builtin_amdgcn_sched_barrier(0);
         }
 #pragma unroll
-        for (int mm = 0; mm < MW; ++mm) rr[i * Mp + mm] = rv[mm] - sum[mm];
+        for (int mm = 0; mm < MW; ++mm) {
+          rv[mm] -= sum[mm];
+          rr[i * Mp + mm] = rv[mm];
+        }
+        if (!last && i >= n0 && i < n0 + NB) {
+#pragma unroll
+          for (int mm = 0; mm < MW; ++mm) Rb[i - n0][mm] = rv[mm];
+        }
+      }
+      if (!last) {
+#pragma unroll
+        for (int q = 0; q < kRowsPerThread; ++q) Li[buf ^ 1][ty + kRowStep * q][tx] = vl[q];
       }
       __syncthreads();
+      buf ^= 1;
     }
   }
 }
