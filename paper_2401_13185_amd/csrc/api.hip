@@ -669,13 +669,43 @@ bool choose_fused(const ProbPlan& p) {
 // and each goes to the XCD with the least work so far (LPT), and an XCD runs
 // its units longest first.  Reordering is free: every item writes its own
 // slab, summed later in slab order.
-void schedule_gram(std::vector<GramWork>& wl, std::vector<int32_t>& xcd, bool balance) {
+// Estimated cost of one Gram item: its rows (plus about two panels for the
+// first stage and the tile store) times the 16 x 16 blocks each wave
+// computes per row step: 16 on a full tile; on a 128-wide diagonal tile 9 of
+// the triangle plus the wave's X^T Y blocks.
+int64_t gram_item_cost(const GramWork& w, const std::vector<ProbPlan>& pp) {
+  const ProbPlan& p = pp[w.prob];
+  int64_t blocks = 16;
+  if (p.cfg.tile == 128 && w.ti == w.tj && w.tj < p.nt)
+    blocks = 9 + 2 * (p.xy_diag ? (p.M <= 16 ? 1 : 2) : 0);
+  return (w.r1 - w.r0 + 2 * kPanelRows) * blocks;
+}
+
+// The last items an XCD starts decide when the launch ends: the final
+// kTailPercent of every XCD's range run longest first, so that the launch
+// ends on short items.  The rest keep list order (the tiles of one fold row
+// range stay together and share the XCD's L2).
+constexpr int kTailPercent = 30;
+void order_tails(std::vector<GramWork>& wl, const std::vector<int32_t>& xcd,
+                 const std::vector<ProbPlan>& pp) {
+  for (int x = 0; x < kXcds; ++x) {
+    const int32_t b = xcd[x], e = xcd[x + 1];
+    const int32_t k = e - (e - b) * kTailPercent / 100;
+    std::stable_sort(wl.begin() + k, wl.begin() + e, [&](const GramWork& u, const GramWork& v) {
+      return gram_item_cost(u, pp) > gram_item_cost(v, pp);
+    });
+  }
+}
+
+void schedule_gram(std::vector<GramWork>& wl, std::vector<int32_t>& xcd, bool balance,
+                   const std::vector<ProbPlan>& pp) {
   xcd.assign(kXcds + 1, 0);
   if (wl.empty()) return;
   const int32_t n = (int32_t)wl.size();
   if (!balance) {
     const int32_t per = (n + kXcds - 1) / kXcds;
     for (int x = 0; x <= kXcds; ++x) xcd[x] = std::min(n, x * per);
+    order_tails(wl, xcd, pp);
     return;
   }
   struct Unit {
@@ -719,6 +749,7 @@ void schedule_gram(std::vector<GramWork>& wl, std::vector<int32_t>& xcd, bool ba
     for (int32_t i = u.begin; i < u.end; ++i) out[fill[x]++] = wl[i];
   }
   wl.swap(out);
+  order_tails(wl, xcd, pp);
 }
 
 void plan_layout(Batch& b, HostLists& L) {
@@ -869,8 +900,8 @@ void plan_layout(Batch& b, HostLists& L) {
         for (int32_t tl = 0; tl < p.n_ctiles_xx + p.n_ctiles_xy; ++tl)
           L.corr_items.push_back({pi, q, tl});
   }
-  schedule_gram(L.work64, L.xcd64, b.pp.size() > 1);
-  schedule_gram(L.work128, L.xcd128, b.pp.size() > 1);
+  schedule_gram(L.work64, L.xcd64, b.pp.size() > 1, b.pp);
+  schedule_gram(L.work128, L.xcd128, b.pp.size() > 1, b.pp);
 }
 
 // the plan blob: segments at 256-byte aligned offsets.  Laid out twice:
