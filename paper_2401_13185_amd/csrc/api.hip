@@ -327,7 +327,7 @@ void tune_save_locked(TuneTable& tt) {
 Config default_config(cvgram_mode mode, int64_t K) {
   Config c;
   c.tile = K <= 64 ? 64 : 128;
-  c.target_items = mode == CVGRAM_MODE_FP64 ? 2048 : 1024;
+  c.target_items = mode == CVGRAM_MODE_FP64 ? 1536 : 1024;
   return c;
 }
 
