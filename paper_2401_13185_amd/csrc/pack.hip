@@ -160,18 +160,24 @@ constexpr int kColGroups = kPackCols / 4;  // lanes per row group
 
 template <typename T, int MODE>
 __global__ __launch_bounds__(kPackThreads) void pack_kernel(const ProbDesc* __restrict__ pds,
-                                                            const PackChunk* __restrict__ chunks) {
+                                                            const PackChunk* __restrict__ chunks,
+                                                            int32_t ncb) {
   constexpr int kT = MODE == CVGRAM_MODE_BF16X3 ? kPackCols * LDK : 8;
   __shared__ __attribute__((aligned(16))) __bf16 th[kT];
   __shared__ __attribute__((aligned(16))) __bf16 tl[kT];
   __shared__ double red[kPackThreads * 4];
 
-  const PackChunk ch = chunks[blockIdx.x];
+  // workgroup = (chunk, column block), column blocks fastest: the workgroups
+  // reading one chunk's rows start together and take whole rows between
+  // them (better DRAM page locality than column-block-major order)
+  const int64_t chunk = (int64_t)blockIdx.x / ncb;
+  const int32_t cbi = (int32_t)(blockIdx.x - chunk * ncb);
+  const PackChunk ch = chunks[chunk];
   // descriptor fields in registers (the loops below store through other
   // pointers; no field is re-read from memory)
   const ProbDesc& pdr = pds[ch.prob];
   const int64_t Wp = pdr.Wp;
-  const int64_t cb0 = (int64_t)blockIdx.y * kPackCols;
+  const int64_t cb0 = (int64_t)cbi * kPackCols;
   if (cb0 >= Wp) return;  // uniform over the workgroup
   const CVG_GLOBAL T* __restrict__ X = gmem((const T*)pdr.X);
   const CVG_GLOBAL T* __restrict__ Y = gmem((const T*)pdr.Y);
@@ -374,13 +380,19 @@ __global__ __launch_bounds__(kPackThreads) void pack_kernel(const ProbDesc* __re
 template <typename T>
 void launch_pack_typed(cvgram_mode mode, const ProbDesc* pd, const PackChunk* chunks,
                        int64_t n_chunks, int32_t max_col_blocks, hipStream_t s) {
-  dim3 grid((unsigned)n_chunks, (unsigned)max_col_blocks);
+  const int64_t blocks = n_chunks * max_col_blocks;
+  if (blocks > INT32_MAX) {
+    set_error("pack: too many chunks for one launch");
+    throw Fail{CVGRAM_EINVAL};
+  }
+  const unsigned grid = (unsigned)blocks;
+  const int32_t ncb = max_col_blocks;
   if (mode == CVGRAM_MODE_FP64)
-    pack_kernel<T, CVGRAM_MODE_FP64><<<grid, kPackThreads, 0, s>>>(pd, chunks);
+    pack_kernel<T, CVGRAM_MODE_FP64><<<grid, kPackThreads, 0, s>>>(pd, chunks, ncb);
   else if (mode == CVGRAM_MODE_FP32)
-    pack_kernel<T, CVGRAM_MODE_FP32><<<grid, kPackThreads, 0, s>>>(pd, chunks);
+    pack_kernel<T, CVGRAM_MODE_FP32><<<grid, kPackThreads, 0, s>>>(pd, chunks, ncb);
   else
-    pack_kernel<T, CVGRAM_MODE_BF16X3><<<grid, kPackThreads, 0, s>>>(pd, chunks);
+    pack_kernel<T, CVGRAM_MODE_BF16X3><<<grid, kPackThreads, 0, s>>>(pd, chunks, ncb);
   CVG_LAUNCH_CHECK();
 }
 
