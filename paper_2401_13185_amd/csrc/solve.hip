@@ -35,6 +35,13 @@ constexpr int kThreads = 256;                  // 8 rows x 32 columns per pass
 constexpr int kRowStep = kThreads / NB;        // rows a pass covers
 constexpr int kRowsPerThread = NB / kRowStep;  // passes per block
 constexpr int kWave = 64;
+// the substitutions: the first kThreads threads handle the 32 x 32 blocks,
+// all of them one row each of the update; 512 threads (up to 512 rows in one
+// pass) where a row's registers allow two waves per SIMD, else 256
+template <int MW>
+constexpr int solve_threads() {
+  return MW <= 16 ? 512 : kThreads;
+}
 
 // padded systems: A + lambda I in Kp x Kp (identity in the padding) and R in
 // Kp x Mp (zeros in the padding), from the products (p-major, lambda-minor)
@@ -255,7 +262,7 @@ __global__ __launch_bounds__(kThreads) void chol_update_kernel(double* __restric
 // 32) is the width of R each row update carries in registers: at least the
 // block's columns of B, the rest padding zeros that stay zero.
 template <int MW>
-__global__ __launch_bounds__(kThreads) void tri_solve_kernel(const double* __restrict__ A,
+__global__ __launch_bounds__(solve_threads<MW>()) void tri_solve_kernel(const double* __restrict__ A,
                                                              const double* __restrict__ Linv,
                                                              double* __restrict__ R, int64_t K,
                                                              int64_t M, int64_t Kp, int64_t Mp,
@@ -268,6 +275,7 @@ __global__ __launch_bounds__(kThreads) void tri_solve_kernel(const double* __res
   const CVG_GLOBAL double* a = gmem(A) + mat * Kp * Kp;
   CVG_GLOBAL double* rr = gmem(R) + mat * Kp * Mp + m0;
   const int t = threadIdx.x, tx = t % NB, ty = t / NB;
+  const bool blk = t < kThreads;  // one of the threads that handle a 32 x 32 block
   auto load_li = [&](int32_t j, double* vl) {
     const CVG_GLOBAL double* li = gmem(Linv) + (mat * nblk + j) * NB * NB;
 #pragma unroll
@@ -280,14 +288,16 @@ __global__ __launch_bounds__(kThreads) void tri_solve_kernel(const double* __res
       // the pass's first block: its rows of R and its inverse from memory
       const int32_t j = backward ? nblk - 1 : 0;
       const int64_t r0 = (int64_t)j * NB;
-      double vr[kRowsPerThread], vl[kRowsPerThread];
+      if (blk) {
+        double vr[kRowsPerThread], vl[kRowsPerThread];
 #pragma unroll
-      for (int q = 0; q < kRowsPerThread; ++q) vr[q] = rr[(r0 + ty + kRowStep * q) * Mp + tx];
-      load_li(j, vl);
+        for (int q = 0; q < kRowsPerThread; ++q) vr[q] = rr[(r0 + ty + kRowStep * q) * Mp + tx];
+        load_li(j, vl);
 #pragma unroll
-      for (int q = 0; q < kRowsPerThread; ++q) {
-        Rb[ty + kRowStep * q][tx] = vr[q];
-        Li[buf][ty + kRowStep * q][tx] = vl[q];
+        for (int q = 0; q < kRowsPerThread; ++q) {
+          Rb[ty + kRowStep * q][tx] = vr[q];
+          Li[buf][ty + kRowStep * q][tx] = vl[q];
+        }
       }
       __syncthreads();
     }
@@ -297,22 +307,24 @@ __global__ __launch_bounds__(kThreads) void tri_solve_kernel(const double* __res
       const bool last = jj + 1 == nblk;
       const int32_t jn = backward ? j - 1 : j + 1;  // the next step's block
       const int64_t n0 = (int64_t)jn * NB;
+      if (blk) {
 #pragma unroll
-      for (int q = 0; q < kRowsPerThread; ++q) {
-        const int r = ty + kRowStep * q;
-        double sum = 0.0;
-        if (!backward)
-          for (int k = 0; k <= r; ++k) sum = fma(Li[buf][r][k], Rb[k][tx], sum);
-        else
-          for (int k = r; k < NB; ++k) sum = fma(Li[buf][k][r], Rb[k][tx], sum);
-        Z[r][tx] = sum;
-        rr[(r0 + r) * Mp + tx] = sum;
+        for (int q = 0; q < kRowsPerThread; ++q) {
+          const int r = ty + kRowStep * q;
+          double sum = 0.0;
+          if (!backward)
+            for (int k = 0; k <= r; ++k) sum = fma(Li[buf][r][k], Rb[k][tx], sum);
+          else
+            for (int k = r; k < NB; ++k) sum = fma(Li[buf][k][r], Rb[k][tx], sum);
+          Z[r][tx] = sum;
+          rr[(r0 + r) * Mp + tx] = sum;
+        }
       }
       __syncthreads();
       double vl[kRowsPerThread];
-      if (!last) load_li(jn, vl);
+      if (!last && blk) load_li(jn, vl);
       const int64_t lo = backward ? 0 : r0 + NB, hi = backward ? r0 : Kp;
-      for (int64_t i = lo + t; i < hi; i += kThreads) {
+      for (int64_t i = lo + t; i < hi; i += solve_threads<MW>()) {
         double lc[NB], rv[MW];
 #pragma unroll
         for (int c = 0; c < NB; ++c) lc[c] = a[(r0 + c) * Kp + i];
@@ -338,7 +350,7 @@ __global__ __launch_bounds__(kThreads) void tri_solve_kernel(const double* __res
           for (int mm = 0; mm < MW; ++mm) Rb[i - n0][mm] = rv[mm];
         }
       }
-      if (!last) {
+      if (!last && blk) {
 #pragma unroll
         for (int q = 0; q < kRowsPerThread; ++q) Li[buf ^ 1][ty + kRowStep * q][tx] = vl[q];
       }
@@ -379,11 +391,11 @@ void ridge_solve(const double* xtx, const double* xty, const double* lambdas, in
   if (M <= 0) return;
   const dim3 grid((unsigned)n_mat, (unsigned)(Mp / NB));
   if (M <= 8)
-    tri_solve_kernel<8><<<grid, kThreads, 0, s>>>(A, Linv, R, K, M, Kp, Mp, nblk);
+    tri_solve_kernel<8><<<grid, solve_threads<8>(), 0, s>>>(A, Linv, R, K, M, Kp, Mp, nblk);
   else if (M <= 16)
-    tri_solve_kernel<16><<<grid, kThreads, 0, s>>>(A, Linv, R, K, M, Kp, Mp, nblk);
+    tri_solve_kernel<16><<<grid, solve_threads<16>(), 0, s>>>(A, Linv, R, K, M, Kp, Mp, nblk);
   else
-    tri_solve_kernel<NB><<<grid, kThreads, 0, s>>>(A, Linv, R, K, M, Kp, Mp, nblk);
+    tri_solve_kernel<NB><<<grid, solve_threads<NB>(), 0, s>>>(A, Linv, R, K, M, Kp, Mp, nblk);
   CVG_LAUNCH_CHECK();
   {
     const int64_t per = (K * M + kThreads - 1) / kThreads;
