@@ -105,35 +105,6 @@ __device__ inline int64_t src_col(int64_t jp, int64_t K, int64_t Kp, int64_t M) 
   return -1;
 }
 
-template <typename T>
-__device__ inline void load4(const CVG_GLOBAL T* __restrict__ X, const CVG_GLOBAL T* __restrict__ Y, int64_t K,
-                             int64_t M, int64_t row, const int64_t (&js)[4], bool vec,
-                             double (&x)[4]) {
-  if (vec) {
-    // four consecutive X columns, 16-byte aligned
-    if constexpr (sizeof(T) == 4) {
-      const float4_t v = *(const CVG_GLOBAL float4_t*)&X[row * K + js[0]];
-      x[0] = v.x;
-      x[1] = v.y;
-      x[2] = v.z;
-      x[3] = v.w;
-    } else {
-      const double2_t a = *(const CVG_GLOBAL double2_t*)&X[row * K + js[0]];
-      const double2_t b = *(const CVG_GLOBAL double2_t*)&X[row * K + js[0] + 2];
-      x[0] = a.x;
-      x[1] = a.y;
-      x[2] = b.x;
-      x[3] = b.y;
-    }
-  } else {
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-      x[u] = js[u] < 0 ? 0.0
-             : js[u] < K ? (double)X[row * K + js[u]]
-                         : (double)Y[row * M + (js[u] - K)];
-  }
-}
-
 // four consecutive X columns of one row, 16-byte aligned
 template <typename T>
 __device__ inline void load_vec(const CVG_GLOBAL T* __restrict__ X, int64_t K, int64_t row,
@@ -204,6 +175,19 @@ __global__ __launch_bounds__(kPackThreads) void pack_kernel(const ProbDesc* __re
     any |= js[u] >= 0;
   }
   const bool vec = x_vec && jp0 + 3 < K;
+  // per column: the source array and its row stride
+  const CVG_GLOBAL T* src[4];
+  int64_t ld[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    if (js[u] >= K) {
+      src[u] = Y + (js[u] - K);
+      ld[u] = M;
+    } else {
+      src[u] = X + (js[u] >= 0 ? js[u] : 0);
+      ld[u] = K;
+    }
+  }
   double s[4] = {0, 0, 0, 0}, q[4] = {0, 0, 0, 0};
   double mn[4] = {INFINITY, INFINITY, INFINITY, INFINITY};
   double mx[4] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
@@ -236,15 +220,25 @@ __global__ __launch_bounds__(kPackThreads) void pack_kernel(const ProbDesc* __re
 #pragma unroll
         for (int u = 0; u < 4; ++u) x[g][u] = v[g] ? x[g][u] : 0.0;
     } else {
+      // a block reaching into Y or the padding, or unaligned X: each lane
+      // reads its four columns from fixed sources (X, Y, or X column 0 for a
+      // padding column), all eight rows' loads issued with no branch between
+      // them (padding rows read row 0); what is not data is zeroed after
+      if (vec) {
 #pragma unroll
-      for (int g = 0; g < 8; ++g) {
-        if (v[g]) {
-          load4(X, Y, K, M, (int64_t)rows[g], js, vec, x[g]);
-        } else {
+        for (int g = 0; g < 8; ++g) load_vec(X, K, rows[g] >= 0 ? (int64_t)rows[g] : 0, js[0], x[g]);
+      } else {
 #pragma unroll
-          for (int u = 0; u < 4; ++u) x[g][u] = 0.0;
+        for (int g = 0; g < 8; ++g) {
+          const int64_t r = rows[g] >= 0 ? (int64_t)rows[g] : 0;
+#pragma unroll
+          for (int u = 0; u < 4; ++u) x[g][u] = (double)src[u][r * ld[u]];
         }
       }
+#pragma unroll
+      for (int g = 0; g < 8; ++g)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) x[g][u] = (v[g] && js[u] >= 0) ? x[g][u] : 0.0;
     }
   };
   // statistics and packed output of panel d0
@@ -327,32 +321,28 @@ __global__ __launch_bounds__(kPackThreads) void pack_kernel(const ProbDesc* __re
       }
     }
   };
-  if (x_vec && cb0 + kPackCols <= K) {
-    // a block of X columns only (16-byte loads): two register sets, so the
-    // next panel's loads are issued before this panel's stores and are not
-    // held up by them (loads and stores share one wait counter)
+  // two register sets, so the next panel's loads are issued before this
+  // panel's stores and are not held up by them (loads and stores share one
+  // wait counter)
+  auto panels = [&](auto fast_c) {
     double xa[8][4], xb[8][4];
     bool va[8], vb[8];
-    load_panel(std::true_type{}, ch.d0, xa, va);
+    load_panel(fast_c, ch.d0, xa, va);
     for (int64_t d0 = ch.d0;; d0 += 2 * kPanelRows) {
       const int64_t n1 = d0 + kPanelRows;
-      load_panel(std::true_type{}, n1 < ch.d1 ? n1 : d0, xb, vb);
+      load_panel(fast_c, n1 < ch.d1 ? n1 : d0, xb, vb);
       consume(d0, xa, va);
       if (n1 >= ch.d1) break;
       const int64_t n2 = n1 + kPanelRows;
-      load_panel(std::true_type{}, n2 < ch.d1 ? n2 : n1, xa, va);
+      load_panel(fast_c, n2 < ch.d1 ? n2 : n1, xa, va);
       consume(n1, xb, vb);
       if (n2 >= ch.d1) break;
     }
-  } else {
-    // the block that reaches into Y or the padding, or unaligned X
-    for (int64_t d0 = ch.d0; d0 < ch.d1; d0 += kPanelRows) {
-      double x[8][4];
-      bool v[8];
-      load_panel(std::false_type{}, d0, x, v);
-      consume(d0, x, v);
-    }
-  }
+  };
+  if (x_vec && cb0 + kPackCols <= K)
+    panels(std::true_type{});  // a block of X columns only (16-byte loads)
+  else
+    panels(std::false_type{});  // reaches into Y or the padding, or unaligned X
 
   // combine the 4 row groups of each column, in row-group order
   const int64_t stride = n_chunks * W;
