@@ -686,6 +686,10 @@ int64_t gram_item_cost(const GramWork& w, const std::vector<ProbPlan>& pp) {
 // ends on short items.  The rest keep list order (the tiles of one fold row
 // range stay together and share the XCD's L2).
 constexpr int kTailPercent = 30;
+// problems with at least kTileGroupMinNt tile columns visit their tiles in
+// square groups and spread the list over the XCDs round-robin
+constexpr int32_t kTileGroup = 8;
+constexpr int32_t kTileGroupMinNt = 16;
 void order_tails(std::vector<GramWork>& wl, const std::vector<int32_t>& xcd,
                  const std::vector<ProbPlan>& pp) {
   for (int x = 0; x < kXcds; ++x) {
@@ -705,6 +709,18 @@ void schedule_gram(std::vector<GramWork>& wl, std::vector<int32_t>& xcd, bool ba
   if (!balance) {
     const int32_t per = (n + kXcds - 1) / kXcds;
     for (int x = 0; x <= kXcds; ++x) xcd[x] = std::min(n, x * per);
+    if (pp[0].nt >= kTileGroupMinNt) {
+      // list order round-robin over the XCDs: workgroup b runs list item b,
+      // so all XCDs work on the same tile groups of the same rows at once
+      // and share them through the memory-side cache.  Range x holds the
+      // items i with i % kXcds == x.
+      for (int x = 0; x < kXcds; ++x) xcd[x + 1] = xcd[x] + (n > x ? (n - x + kXcds - 1) / kXcds : 0);
+      thread_local std::vector<GramWork> rr_tl;
+      std::vector<GramWork>& out = rr_tl;
+      out.resize(wl.size());
+      for (int32_t i = 0; i < n; ++i) out[xcd[i % kXcds] + i / kXcds] = wl[i];
+      wl.swap(out);
+    }
     order_tails(wl, xcd, pp);
     return;
   }
@@ -831,9 +847,26 @@ void plan_layout(Batch& b, HostLists& L) {
     // with the same tile width)
     std::vector<std::pair<int32_t, int32_t>> gtiles;
     const int64_t nyt = p.xy_diag ? 0 : p.Mp / T;
-    for (int32_t ti = 0; ti < p.nt; ++ti) {
-      for (int32_t tj = ti; tj < p.nt; ++tj) gtiles.push_back({ti, tj});
-      for (int64_t y = 0; y < nyt; ++y) gtiles.push_back({ti, (int32_t)(p.nt + y)});
+    if (p.nt < kTileGroupMinNt) {
+      for (int32_t ti = 0; ti < p.nt; ++ti) {
+        for (int32_t tj = ti; tj < p.nt; ++tj) gtiles.push_back({ti, tj});
+        for (int64_t y = 0; y < nyt; ++y) gtiles.push_back({ti, (int32_t)(p.nt + y)});
+      }
+    } else {
+      // many tiles per fold row range: square groups of kTileGroup x
+      // kTileGroup tiles, so that the items running together read few
+      // distinct column blocks (2 kTileGroup for 64 tiles)
+      const int32_t ng = (p.nt + kTileGroup - 1) / kTileGroup;
+      for (int32_t bi = 0; bi < ng; ++bi) {
+        const int32_t i0 = bi * kTileGroup, i1 = std::min(p.nt, i0 + kTileGroup);
+        for (int32_t bj = bi; bj < ng; ++bj) {
+          const int32_t j0 = bj * kTileGroup, j1 = std::min(p.nt, j0 + kTileGroup);
+          for (int32_t ti = i0; ti < i1; ++ti)
+            for (int32_t tj = std::max(ti, j0); tj < j1; ++tj) gtiles.push_back({ti, tj});
+        }
+        for (int64_t y = 0; y < nyt; ++y)
+          for (int32_t ti = i0; ti < i1; ++ti) gtiles.push_back({ti, (int32_t)(p.nt + y)});
+      }
     }
     const int64_t gram_rows = T == 64 ? gram_rows64 : gram_rows128;
     int64_t rows_per_split = (gram_rows + p.cfg.target_items - 1) / p.cfg.target_items;
