@@ -307,10 +307,26 @@ def cvgram_set_stream(h: Handle, stream):
     h.stream = s
 
 
+def _record_on_stream(tensors, stream_ptr):
+    """Mark tensors as in use on the stream `stream_ptr` (torch's allocator
+    then keeps their memory until the work queued there has run)."""
+    torch = _torch()
+    for t in tensors:
+        if t is None:
+            continue
+        st = (torch.cuda.default_stream(t.device) if not stream_ptr
+              else torch.cuda.ExternalStream(stream_ptr, device=t.device))
+        t.record_stream(st)
+
+
 def cvgram_destroy(h: Handle):
     if h.ptr:
         ptr, h.ptr = h.ptr, None
         _check(load().cvgram_destroy(ptr))
+        # the library does not wait for the handle's queued work: the inputs
+        # stay reserved for that work in torch's allocator
+        if h._keep is not None:
+            _record_on_stream(h._keep, h.stream)
         h._keep = None
 
 
