@@ -126,6 +126,8 @@ def test_fp64_gaussian_workload_all_classes(ddof):
     (900, 33, 0, 6, "gaussian", "f64"),       # no Y
     (5000, 200, 40, 12, "spectra", "f64"),    # several XtY tiles
     (4000, 150, 24, 6, "spectra", "f64"),     # 16 < M <= 32: two XtY blocks per diagonal row
+    (1500, 2100, 3, 3, "spectra", "f64"),     # 17 tile columns: tiles in 8 x 8 groups, dealt
+                                              # round-robin over the XCDs; ragged last group
 ])
 def test_fp64_ragged_shapes(n, k, m, p, values, dtype):
     shape = G.Shape(f"{values} N={n} K={k} M={m} P={p}", n, k, m, p, dtype, values, "dirichlet")
