@@ -910,8 +910,9 @@ void plan_layout(Batch& b, HostLists& L) {
     p.slab_begin[p.P] = slab;
     p.n_slabs = slab;
     // slab reduction
-    L.red_items.reserve(L.red_items.size() + (size_t)((p.K * p.W + 255) / 256));
-    for (int64_t eb = 0; eb < (p.K * p.W + 255) / 256; ++eb) L.red_items.push_back({pi, (int32_t)eb, 0});
+    const int64_t n_red = (p.K * p.W + kReduceElems - 1) / kReduceElems;
+    L.red_items.reserve(L.red_items.size() + (size_t)n_red);
+    for (int64_t eb = 0; eb < n_red; ++eb) L.red_items.push_back({pi, (int32_t)eb, 0});
     // correction tiles: upper triangle of X^T X, then X^T Y
     p.ctiles.clear();
     const int64_t nct = (p.K + kCorrTile - 1) / kCorrTile;

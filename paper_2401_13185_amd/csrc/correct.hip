@@ -36,55 +36,99 @@ constexpr int kRowsPerThread = TS * TS / kThreads;  // 4
 // into the fold's first slab; G' = sum over folds in fold order.  Entries
 // below the diagonal of the K x K block are never read (mirror image) and
 // are skipped.  Fixed summation order: deterministic.
-// items: (prob, block of 256 entries of the K x W slab)
+// items: (prob, block of kReduceElems entries of the K x W slab); each thread
+// sums two neighbouring entries, with one 16-byte load per slab when the
+// slab stride keeps the pair aligned (K W even).
+typedef double double2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void load_pair(const CVG_GLOBAL double* p, bool vec, bool second,
+                                          double& a, double& b) {
+  if (vec) {
+    const double2_t v = *(const CVG_GLOBAL double2_t*)p;
+    a = v.x;
+    b = v.y;
+  } else {
+    a = p[0];
+    b = second ? p[1] : 0.0;
+  }
+}
 __global__ __launch_bounds__(256) void reduce_slabs_kernel(const ProbDesc* __restrict__ pds,
                                                            const Item* __restrict__ items) {
   const Item it = items[blockIdx.x];
   const ProbDesc& pd = pds[it.prob];
   const int64_t K = pd.K, W = pd.W, elems = K * W;
-  const int64_t e = (int64_t)it.a * 256 + threadIdx.x;
+  const int64_t e = (int64_t)it.a * kReduceElems + 2 * threadIdx.x;
   if (e >= elems) return;
-  const int64_t i = e / W, j = e - (e / W) * W;
-  if (j < K && j < i) return;
+  const bool second = e + 1 < elems;
+  auto needed = [&](int64_t x) {
+    const int64_t i = x / W, j = x - i * W;
+    return !(j < K && j < i);
+  };
+  const bool n0 = needed(e), n1 = second && needed(e + 1);
+  if (!n0 && !n1) return;
+  const bool vec = (elems & 1) == 0;  // then e is even and the pair 16-byte aligned
   CVG_GLOBAL double* slabs = gmem(pd.slabs) + e;
+  CVG_GLOBAL double* G = gmem(pd.G) + e;
+  auto store = [&](CVG_GLOBAL double* q, double a, double b) {
+    if (n0) q[0] = a;
+    if (n1) q[1] = b;
+  };
   if (pd.fused) {
     // fused path: the slabs are row splits of the full Gram only
     const int32_t S = pd.n_slabs;
-    double g = slabs[0];
+    double g0, g1;
+    load_pair(slabs, vec, second, g0, g1);
     int32_t k = 1;
     for (; k + 7 < S; k += 8) {
-      double v[8];
+      double v0[8], v1[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = slabs[(int64_t)(k + u) * elems];
+      for (int u = 0; u < 8; ++u) load_pair(slabs + (int64_t)(k + u) * elems, vec, second, v0[u], v1[u]);
 #pragma unroll
-      for (int u = 0; u < 8; ++u) g += v[u];
+      for (int u = 0; u < 8; ++u) {
+        g0 += v0[u];
+        g1 += v1[u];
+      }
     }
-    for (; k < S; ++k) g += slabs[(int64_t)k * elems];
-    gmem(pd.G)[e] = g;
+    for (; k < S; ++k) {
+      double v0, v1;
+      load_pair(slabs + (int64_t)k * elems, vec, second, v0, v1);
+      g0 += v0;
+      g1 += v1;
+    }
+    store(G, g0, g1);
     return;
   }
   const CVG_GLOBAL int32_t* slab_begin = gmem(pd.slab_begin);
   const int32_t P = pd.P;
-  double g = 0.0;
+  double g0 = 0.0, g1 = 0.0;
   int32_t a = slab_begin[0];
   for (int32_t p = 0; p < P; ++p) {
     const int32_t b = slab_begin[p + 1];
-    double f = slabs[(int64_t)a * elems];
+    double f0, f1;
+    load_pair(slabs + (int64_t)a * elems, vec, second, f0, f1);
     int32_t k = a + 1;
     // eight independent loads in flight per step; the sum keeps slab order
     for (; k + 7 < b; k += 8) {
-      double v[8];
+      double v0[8], v1[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = slabs[(int64_t)(k + u) * elems];
+      for (int u = 0; u < 8; ++u) load_pair(slabs + (int64_t)(k + u) * elems, vec, second, v0[u], v1[u]);
 #pragma unroll
-      for (int u = 0; u < 8; ++u) f += v[u];
+      for (int u = 0; u < 8; ++u) {
+        f0 += v0[u];
+        f1 += v1[u];
+      }
     }
-    for (; k < b; ++k) f += slabs[(int64_t)k * elems];
-    if (b > a + 1) slabs[(int64_t)a * elems] = f;
-    g += f;
+    for (; k < b; ++k) {
+      double v0, v1;
+      load_pair(slabs + (int64_t)k * elems, vec, second, v0, v1);
+      f0 += v0;
+      f1 += v1;
+    }
+    if (b > a + 1) store(slabs + (int64_t)a * elems, f0, f1);
+    g0 += f0;
+    g1 += f1;
     a = b;
   }
-  gmem(pd.G)[e] = g;
+  store(G, g0, g1);
 }
 
 // element (row r, packed column col) of the packed panels as FP64: the
@@ -352,7 +396,7 @@ __global__ __launch_bounds__(kThreads) void correct_batch_kernel(const ProbDesc*
 
 void launch_reduce_slabs(const ProbDesc* pd, const Item* items, int64_t n_items, hipStream_t s) {
   if (n_items <= 0) return;
-  reduce_slabs_kernel<<<(unsigned)n_items, 256, 0, s>>>(pd, items);
+  reduce_slabs_kernel<<<(unsigned)n_items, kReduceElems / 2, 0, s>>>(pd, items);
   CVG_LAUNCH_CHECK();
 }
 

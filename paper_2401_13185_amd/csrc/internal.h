@@ -68,6 +68,8 @@ constexpr int kMaxChunkRows = 1024;
 constexpr int kXcds = 8;
 // correction tiles
 constexpr int kCorrTile = 32;
+// slab reduction: entries of the K x W slab per workgroup (two per thread)
+constexpr int kReduceElems = 512;
 // fold totals: folds per partial range
 constexpr int kFoldRange = 256;
 
