@@ -358,6 +358,7 @@ struct ProbPlan {
   int64_t Kp = 0, Mp = 0, Wp = 0, Np = 0;
   bool xy_diag = false;
   int32_t nt = 0;
+  bool tile_groups = false;   // tile order and XCD spread (see kTileGroup)
   std::vector<int64_t> poff;  // [P+1] packed row offsets
   std::vector<int32_t> chunk_begin, slab_begin, ctiles;
   int64_t n_chunks = 0, n_slabs = 0;
@@ -686,8 +687,12 @@ int64_t gram_item_cost(const GramWork& w, const std::vector<ProbPlan>& pp) {
 // ends on short items.  The rest keep list order (the tiles of one fold row
 // range stay together and share the XCD's L2).
 constexpr int kTailPercent = 30;
-// problems with at least kTileGroupMinNt tile columns visit their tiles in
-// square groups and spread the list over the XCDs round-robin
+// single problems with at least kTileGroupMinNt tile columns visit their
+// tiles in square groups and spread the list over the XCDs round-robin
+// (ProbPlan::tile_groups).  Below that the per-XCD ranges keep a fold row
+// range's tiles in one L2: measured, the BF16X3 launch on K = 1024 slows
+// from 3.8 to 4.5 ms with groups, and the FP64 launch on K = 512 gains 1 %
+// while its L2 misses double (served by the memory-side cache).
 constexpr int32_t kTileGroup = 8;
 constexpr int32_t kTileGroupMinNt = 16;
 void order_tails(std::vector<GramWork>& wl, const std::vector<int32_t>& xcd,
@@ -709,7 +714,7 @@ void schedule_gram(std::vector<GramWork>& wl, std::vector<int32_t>& xcd, bool ba
   if (!balance) {
     const int32_t per = (n + kXcds - 1) / kXcds;
     for (int x = 0; x <= kXcds; ++x) xcd[x] = std::min(n, x * per);
-    if (pp[0].nt >= kTileGroupMinNt) {
+    if (pp[0].tile_groups) {
       // list order round-robin over the XCDs: workgroup b runs list item b,
       // so all XCDs work on the same tile groups of the same rows at once
       // and share them through the memory-side cache.  Range x holds the
@@ -789,6 +794,7 @@ void plan_layout(Batch& b, HostLists& L) {
     p.Mp = p.M == 0 ? 0 : (p.xy_diag ? kYDiagCols : (p.M + T - 1) / T * T);
     p.Wp = p.Kp + p.Mp;
     p.nt = (int32_t)(p.Kp / T);
+    p.tile_groups = b.pp.size() == 1 && p.nt >= kTileGroupMinNt;
     const int64_t nyt = p.xy_diag ? 0 : p.Mp / T;
     const int64_t ntile = (int64_t)p.nt * (p.nt + 1) / 2 + (int64_t)p.nt * nyt;
     pack_cols_rows += p.Np * ((p.Wp + kPackCols - 1) / kPackCols);
@@ -847,7 +853,7 @@ void plan_layout(Batch& b, HostLists& L) {
     // with the same tile width)
     std::vector<std::pair<int32_t, int32_t>> gtiles;
     const int64_t nyt = p.xy_diag ? 0 : p.Mp / T;
-    if (p.nt < kTileGroupMinNt) {
+    if (!p.tile_groups) {
       for (int32_t ti = 0; ti < p.nt; ++ti) {
         for (int32_t tj = ti; tj < p.nt; ++tj) gtiles.push_back({ti, tj});
         for (int64_t y = 0; y < nyt; ++y) gtiles.push_back({ti, (int32_t)(p.nt + y)});
