@@ -51,6 +51,8 @@ typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 constexpr int kThreads = 256;
 constexpr int kYW = kYDiagCols;    // Y columns handled inside diagonal tiles (32)
 constexpr int kFlushRows = 256;
+// row steps of 4 rows each wave keeps in flight in the direct FP64 loop
+constexpr int kDirectDepth = 4;
 
 template <int MODE>
 struct Mode;
@@ -500,8 +502,51 @@ __global__ __launch_bounds__(kThreads) void gram_kernel(const ProbDesc* __restri
     else
       main_loop(std::true_type{}, std::true_type{}, Y2{}, w_c);
   };
+  // FP64 off-diagonal tiles of 128: every wave reads its MFMA fragments
+  // straight from the panels, kDirectDepth row steps (4 rows each) ahead,
+  // with no LDS staging and no workgroup barrier; the two waves that share
+  // an operand half meet in the L1 cache.  Same products in the same order
+  // as the staged loop (row steps in increasing row order).
+  auto direct_loop = [&]() {
+    constexpr int D = kDirectDepth;
+    const CVG_GLOBAL double* za = gmem((const double*)pdr.packed) + ca + wm * WT + fc;
+    const CVG_GLOBAL double* zb = gmem((const double*)pdr.packed) + cb + wn * WT + fc;
+    const int64_t nk = (w.r1 - w.r0) / 4;  // a multiple of 8: items are whole panels
+    double fa[D][NW], fb[D][NW];
+    auto load_k = [&](int d, int64_t k) {
+      const int64_t off = (w.r0 + 4 * k + fr) * Wp;
+#pragma unroll
+      for (int a = 0; a < NW; ++a) fa[d][a] = za[off + 16 * a];
+#pragma unroll
+      for (int b = 0; b < NW; ++b) fb[d][b] = zb[off + 16 * b];
+    };
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      load_k(d, d < nk ? d : nk - 1);
+      __builtin_amdgcn_sched_barrier(0);  // the loop's order: its waits count from it
+    }
+    for (int64_t k = 0; k < nk; k += D) {
+#pragma unroll
+      for (int d = 0; d < D; ++d) {
+#pragma unroll
+        for (int a = 0; a < NW; ++a)
+#pragma unroll
+          for (int b = 0; b < NW; ++b)
+            acc[a * NW + b] = mfma_step(fa[d][a], fb[d][b], acc[a * NW + b]);
+        // the step D ahead (past the end: the last step again, unused),
+        // issued here and not moved: its registers are free only now, and
+        // it has the next D - 1 steps' MFMAs to arrive
+        const int64_t kn = k + d + D;
+        load_k(d, kn < nk ? kn : nk - 1);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+  };
   if (!diag) {
-    main_loop(std::false_type{}, std::false_type{}, Y0{}, W0{});
+    if constexpr (kF64 && kPairs)
+      direct_loop();
+    else
+      main_loop(std::false_type{}, std::false_type{}, Y0{}, W0{});
   } else if constexpr (kPairs) {
     switch (wave) {
       case 0: diag_loop(W0{}); break;
