@@ -15,6 +15,8 @@
 // Work decomposition: one workgroup per (32 x 32 output tile, fold).  X^T X
 // tiles cover the upper triangle only; the lower triangle is written from
 // the same values through an LDS transpose, so X^T X is bit-symmetric.
+#include <type_traits>
+
 #include "internal.h"
 
 namespace cvg {
@@ -72,63 +74,60 @@ __global__ __launch_bounds__(256) void reduce_slabs_kernel(const ProbDesc* __res
     if (n0) q[0] = a;
     if (n1) q[1] = b;
   };
-  if (pd.fused) {
-    // fused path: the slabs are row splits of the full Gram only
-    const int32_t S = pd.n_slabs;
-    double g0, g1;
-    load_pair(slabs, vec, second, g0, g1);
-    int32_t k = 1;
-    for (; k + 7 < S; k += 8) {
-      double v0[8], v1[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) load_pair(slabs + (int64_t)(k + u) * elems, vec, second, v0[u], v1[u]);
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        g0 += v0[u];
-        g1 += v1[u];
+  // slabs [s0, s1) summed in slab order, eight loads in flight per group
+  // (indices past the range read its last slab again and are not added)
+  auto run = [&](auto vec_c) {
+    constexpr bool V = decltype(vec_c)::value;
+    auto sum_range = [&](int32_t s0, int32_t s1, double& f0, double& f1) {
+      if (s1 - s0 == 1) {  // one slab (many small folds): nothing to add
+        load_pair(slabs + (int64_t)s0 * elems, V, second, f0, f1);
+        return;
       }
+      for (int32_t k = s0; k < s1; k += 8) {
+        double v0[8], v1[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int32_t ks = k + u < s1 ? k + u : s1 - 1;
+          load_pair(slabs + (int64_t)ks * elems, V, second, v0[u], v1[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          if (k + u == s0) {
+            f0 = v0[u];
+            f1 = v1[u];
+          } else if (k + u < s1) {
+            f0 += v0[u];
+            f1 += v1[u];
+          }
+        }
+      }
+    };
+    if (pd.fused) {
+      // fused path: the slabs are row splits of the full Gram only
+      double g0 = 0.0, g1 = 0.0;
+      sum_range(0, pd.n_slabs, g0, g1);
+      store(G, g0, g1);
+      return;
     }
-    for (; k < S; ++k) {
-      double v0, v1;
-      load_pair(slabs + (int64_t)k * elems, vec, second, v0, v1);
-      g0 += v0;
-      g1 += v1;
+    const CVG_GLOBAL int32_t* slab_begin = gmem(pd.slab_begin);
+    const int32_t P = pd.P;
+    double g0 = 0.0, g1 = 0.0;
+    int32_t a = slab_begin[0];
+    for (int32_t p = 0; p < P; ++p) {
+      const int32_t b = slab_begin[p + 1];
+      double f0 = 0.0, f1 = 0.0;
+      sum_range(a, b, f0, f1);
+      if (b > a + 1) store(slabs + (int64_t)a * elems, f0, f1);
+      g0 += f0;
+      g1 += f1;
+      a = b;
     }
     store(G, g0, g1);
-    return;
-  }
-  const CVG_GLOBAL int32_t* slab_begin = gmem(pd.slab_begin);
-  const int32_t P = pd.P;
-  double g0 = 0.0, g1 = 0.0;
-  int32_t a = slab_begin[0];
-  for (int32_t p = 0; p < P; ++p) {
-    const int32_t b = slab_begin[p + 1];
-    double f0, f1;
-    load_pair(slabs + (int64_t)a * elems, vec, second, f0, f1);
-    int32_t k = a + 1;
-    // eight independent loads in flight per step; the sum keeps slab order
-    for (; k + 7 < b; k += 8) {
-      double v0[8], v1[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) load_pair(slabs + (int64_t)(k + u) * elems, vec, second, v0[u], v1[u]);
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        f0 += v0[u];
-        f1 += v1[u];
-      }
-    }
-    for (; k < b; ++k) {
-      double v0, v1;
-      load_pair(slabs + (int64_t)k * elems, vec, second, v0, v1);
-      f0 += v0;
-      f1 += v1;
-    }
-    if (b > a + 1) store(slabs + (int64_t)a * elems, f0, f1);
-    g0 += f0;
-    g1 += f1;
-    a = b;
-  }
-  store(G, g0, g1);
+  };
+  if (vec)
+    run(std::true_type{});
+  else
+    run(std::false_type{});
 }
 
 // element (row r, packed column col) of the packed panels as FP64: the
