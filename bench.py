@@ -258,7 +258,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1 "
-                          "(the multi-GPU sharding is described in DESIGN.md, not built)"}))
+                          "(multi-GPU sharding is a design, not built)"}))
         sys.exit(2)
     import torch
     import paper_2401_13185_amd as cv

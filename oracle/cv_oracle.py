@@ -13,15 +13,14 @@ combination of Section 6 and Table 1).  The fast algorithm reaches exactly the
 same result (Propositions 1, 9 and 17), so this plain definition is the
 reference it must match.
 
-Readings where the paper is silent or only implicit (each is listed in
-DESIGN.md):
+Readings where the paper is silent or only implicit:
   * fold labels are 0-based ints; label p is the paper's partition p+1, and
     P = max(label)+1 with every label in [0, P) used and 2 <= P <= N
     (Definition 1);
   * the deviation divisor is |T| - ddof with ddof in {0, 1}; ddof = 1 is the
     paper's Bessel correction (Definition 4).  Scaling needs |T| - ddof >= 1
     for every fold (Definition 6 generalised);
-  * "a deviation that is 0 is replaced by 1" (Algorithm 6 step 10, Algorithm 7
+  * the rule that a zero deviation becomes 1 (Algorithm 6 step 10, Algorithm 7
     step 24) is read as: column j is constant over T.  Such a column keeps
     deviation 1, and its mean is the constant itself, so a centred constant
     column is exactly zero;

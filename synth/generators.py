@@ -11,8 +11,8 @@ fixed-size chunks with one generator per chunk, so any row range can be
 regenerated on its own and the result does not depend on how many threads
 drew it.  Values are drawn in FP64 and cast to the requested dtype at the end.
 
-Workloads (shapes follow the paper's benchmark setting in Section 7 and the
-value models stated in the design doc):
+Workloads (shapes follow the paper's benchmark setting in Section 7; the value
+models are these):
   * ``gaussian``   -- per-column Gaussian X, column mean ~ N(5, 2^2), column
                       std ~ LogNormal(0, 0.5); Y = X W + N(0, 0.1^2).
   * ``spectra``    -- smooth spectra: per row a baseline ~ U(0.5, 2) plus five
