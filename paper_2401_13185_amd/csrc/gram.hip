@@ -53,6 +53,9 @@ constexpr int kYW = kYDiagCols;    // Y columns handled inside diagonal tiles (3
 constexpr int kFlushRows = 256;
 // row steps of 4 rows each wave keeps in flight in the direct FP64 loop
 constexpr int kDirectDepth = 4;
+// the loop runs kDirectDepth steps per pass over an item's kPanelRows / 4
+// steps per panel, so the depth must divide them
+static_assert((kPanelRows / 4) % kDirectDepth == 0, "direct depth must divide a panel's steps");
 
 template <int MODE>
 struct Mode;
