@@ -261,7 +261,7 @@ __global__ __launch_bounds__(kThreads) void chol_update_kernel(double* __restric
 // steps).  Padding rows of the last block (past K) stay zero.  MW (8, 16 or
 // 32) is the width of R each row update carries in registers: at least the
 // block's columns of B, the rest padding zeros that stay zero.
-template <int MW>
+template <int MW, bool FAST>
 __global__ __launch_bounds__(solve_threads<MW>()) void tri_solve_kernel(const double* __restrict__ A,
                                                              const double* __restrict__ Linv,
                                                              double* __restrict__ R, int64_t K,
@@ -276,6 +276,8 @@ __global__ __launch_bounds__(solve_threads<MW>()) void tri_solve_kernel(const do
   CVG_GLOBAL double* rr = gmem(R) + mat * Kp * Mp + m0;
   const int t = threadIdx.x, tx = t % NB, ty = t / NB;
   const bool blk = t < kThreads;  // one of the threads that handle a 32 x 32 block
+  // FAST: Kp <= the thread count and MW <= 16 (the launch checks)
+  constexpr bool fast = FAST;
   auto load_li = [&](int32_t j, double* vl) {
     const CVG_GLOBAL double* li = gmem(Linv) + (mat * nblk + j) * NB * NB;
 #pragma unroll
@@ -301,6 +303,23 @@ __global__ __launch_bounds__(solve_threads<MW>()) void tri_solve_kernel(const do
       }
       __syncthreads();
     }
+    // Rows of R in registers (Kp <= the thread count, MW <= 16): thread t
+    // keeps row t for the whole pass, so an update reads no R from memory,
+    // and the coefficients of its next step are loaded at the end of this
+    // one, while the barrier and the next block's Z are in progress.
+    double rv[MW], lc[NB];
+    if (fast) {
+      const int32_t j = backward ? nblk - 1 : 0;
+      const int64_t lo = backward ? 0 : (int64_t)(j + 1) * NB, hi = backward ? (int64_t)j * NB : Kp;
+      if (t < Kp) {
+#pragma unroll
+        for (int mm = 0; mm < MW; ++mm) rv[mm] = rr[(int64_t)t * Mp + mm];
+      }
+      if (t >= lo && t < hi) {
+#pragma unroll
+        for (int c = 0; c < NB; ++c) lc[c] = a[((int64_t)j * NB + c) * Kp + t];
+      }
+    }
     for (int32_t jj = 0; jj < nblk; ++jj) {
       const int32_t j = backward ? nblk - 1 - jj : jj;
       const int64_t r0 = (int64_t)j * NB;
@@ -311,11 +330,17 @@ __global__ __launch_bounds__(solve_threads<MW>()) void tri_solve_kernel(const do
 #pragma unroll
         for (int q = 0; q < kRowsPerThread; ++q) {
           const int r = ty + kRowStep * q;
+          // all 32 terms, unrolled: the inverse block holds exact zeros
+          // above its diagonal, so the terms outside the triangle add zero
+          // and the sum is that of the triangle, in the same order
           double sum = 0.0;
-          if (!backward)
-            for (int k = 0; k <= r; ++k) sum = fma(Li[buf][r][k], Rb[k][tx], sum);
-          else
-            for (int k = r; k < NB; ++k) sum = fma(Li[buf][k][r], Rb[k][tx], sum);
+          if (!backward) {
+#pragma unroll
+            for (int k = 0; k < NB; ++k) sum = fma(Li[buf][r][k], Rb[k][tx], sum);
+          } else {
+#pragma unroll
+            for (int k = 0; k < NB; ++k) sum = fma(Li[buf][k][r], Rb[k][tx], sum);
+          }
           Z[r][tx] = sum;
           rr[(r0 + r) * Mp + tx] = sum;
         }
@@ -324,7 +349,32 @@ __global__ __launch_bounds__(solve_threads<MW>()) void tri_solve_kernel(const do
       double vl[kRowsPerThread];
       if (!last && blk) load_li(jn, vl);
       const int64_t lo = backward ? 0 : r0 + NB, hi = backward ? r0 : Kp;
-      for (int64_t i = lo + t; i < hi; i += solve_threads<MW>()) {
+      if (fast) {
+        if (t >= lo && t < hi) {
+          double sum[MW];
+#pragma unroll
+          for (int mm = 0; mm < MW; ++mm) sum[mm] = 0.0;
+#pragma unroll
+          for (int c = 0; c < NB; ++c) {
+#pragma unroll
+            for (int mm = 0; mm < MW; ++mm) sum[mm] = fma(lc[c], Z[c][mm], sum[mm]);
+            if (c % 4 == 3) __builtin_amdgcn_sched_barrier(0);
+          }
+#pragma unroll
+          for (int mm = 0; mm < MW; ++mm) rv[mm] -= sum[mm];
+          if (!last && t >= n0 && t < n0 + NB) {
+#pragma unroll
+            for (int mm = 0; mm < MW; ++mm) Rb[t - n0][mm] = rv[mm];
+          }
+        }
+        // the next step's rows of the update: forward [n0 + 32, Kp), backward [0, n0)
+        const int64_t lo_n = backward ? 0 : n0 + NB, hi_n = backward ? n0 : Kp;
+        if (!last && t >= lo_n && t < hi_n) {
+#pragma unroll
+          for (int c = 0; c < NB; ++c) lc[c] = a[(n0 + c) * Kp + t];
+        }
+      }
+      for (int64_t i = lo + t; !fast && i < hi; i += solve_threads<MW>()) {
         double lc[NB], rv[MW];
 #pragma unroll
         for (int c = 0; c < NB; ++c) lc[c] = a[(r0 + c) * Kp + i];
@@ -390,12 +440,17 @@ void ridge_solve(const double* xtx, const double* xty, const double* lambdas, in
   }
   if (M <= 0) return;
   const dim3 grid((unsigned)n_mat, (unsigned)(Mp / NB));
-  if (M <= 8)
-    tri_solve_kernel<8><<<grid, solve_threads<8>(), 0, s>>>(A, Linv, R, K, M, Kp, Mp, nblk);
+  const bool fast = Kp <= solve_threads<16>();  // one row of R per thread
+  if (M <= 8 && fast)
+    tri_solve_kernel<8, true><<<grid, solve_threads<8>(), 0, s>>>(A, Linv, R, K, M, Kp, Mp, nblk);
+  else if (M <= 8)
+    tri_solve_kernel<8, false><<<grid, solve_threads<8>(), 0, s>>>(A, Linv, R, K, M, Kp, Mp, nblk);
+  else if (M <= 16 && fast)
+    tri_solve_kernel<16, true><<<grid, solve_threads<16>(), 0, s>>>(A, Linv, R, K, M, Kp, Mp, nblk);
   else if (M <= 16)
-    tri_solve_kernel<16><<<grid, solve_threads<16>(), 0, s>>>(A, Linv, R, K, M, Kp, Mp, nblk);
+    tri_solve_kernel<16, false><<<grid, solve_threads<16>(), 0, s>>>(A, Linv, R, K, M, Kp, Mp, nblk);
   else
-    tri_solve_kernel<NB><<<grid, solve_threads<NB>(), 0, s>>>(A, Linv, R, K, M, Kp, Mp, nblk);
+    tri_solve_kernel<NB, false><<<grid, solve_threads<NB>(), 0, s>>>(A, Linv, R, K, M, Kp, Mp, nblk);
   CVG_LAUNCH_CHECK();
   {
     const int64_t per = (K * M + kThreads - 1) / kThreads;

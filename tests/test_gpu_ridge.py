@@ -32,7 +32,10 @@ def _data(n, k, m, seed):
     return X, Y
 
 
-@pytest.mark.parametrize("n,k,m,P", [(600, 40, 3, 5), (900, 45, 40, 4), (1500, 70, 1, 3)])
+# K <= 512 with M <= 16 keeps R's rows in registers in the substitutions;
+# M > 16 and K > 512 take the general path
+@pytest.mark.parametrize("n,k,m,P", [(600, 40, 3, 5), (900, 45, 40, 4), (1500, 70, 1, 3),
+                                     (1200, 100, 12, 4), (2500, 600, 4, 3)])
 def test_ridge_matches_oracle(n, k, m, P):
     X, Y = _data(n, k, m, k)
     fold = np.random.default_rng(k).integers(0, P, size=n).astype(np.int32)
