@@ -1,17 +1,37 @@
 #!/usr/bin/env python3
 """Throughput of the per-fold training Gram path on one MI355X.
 
-One step = the whole hot path over one batch of synthetic input:
-cvgram_create (fold bookkeeping, statistics, grouped Gram) + every fold's 12
-distinct training products (4 X^T X + 8 X^T Y classes) + cvgram_destroy.
-Inputs are resident in HBM before timing starts.
+Headline (the default JSON line's ``value``): the large single problem --
+spectra N=2,000,000, K=4096, M=64, P=64 with Dirichlet(2) folds, FP32 input
+drawn on the device -- in FP64 mode.  One step = the whole hot path over the
+problem: cvgram_create (fold bookkeeping, pivots, statistics + pack, grouped
+Gram, slab reduction) + every fold's 12 distinct training products (4 X^T X +
+8 X^T Y classes) written in chunks of 8 folds + cvgram_destroy.  Inputs are
+resident in HBM before timing starts.  ``value`` is sets/s: a set is one
+fold's (X^T X, X^T Y) pair for one combination, P * 12 sets per step.
 
-Prints ONE JSON line.  ``value`` is sets/s, a set being one fold's
-(X^T X, X^T Y) pair for one combination: P * 12 sets per step.
+Further blocks on the same line (each on by default; ``--blocks`` picks):
+  headline  the large problem in FP64 (above), the same inputs in BF16X3
+            (speed-up over FP64 at the stated bound, the error of every fold x
+            class against the FP64 form, sampled entries of two folds against
+            the FP64 oracle in both modes) and the oracle's CPU time on a
+            bounded sample
+  spectra   N=1e5, K=512, M=8, P=10 (the paper's benchmark shape), FP64: sets/s,
+            Gram roofline, error against the oracle, the CPU oracle and the
+            paper's fast algorithm on the host (all cores and one thread), and
+            the per-fold ridge consumer
+  mixed     precision stress N=1e6, K=1024, M=16, P=100, FP32 input with large
+            column offsets: FP64, FP32 and BF16X3 modes, each mixed mode's
+            error per fold x class against the FP64 GPU form and sampled
+            entries against the oracle
+  batched   256 independent problems in one HIP-graph replay, FP64 and BF16X3
+  psweep    the spectra shape with P = 3 .. 100000 (leave-one-out): Gram time
+            flat in P
 """
 from __future__ import annotations
 
 import argparse
+import glob
 import json
 import os
 import sys
@@ -24,9 +44,21 @@ sys.path.insert(0, ROOT)
 
 PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}  # TFLOP/s dense MFMA, MI355X
 HBM_PEAK = 8000.0  # GB/s
-# stated relative Frobenius error bounds of the mixed modes (per fold, class
-# and output, against FP64)
+# stated relative error bounds of the mixed modes (per fold, class and
+# output, against FP64: relative Frobenius, and entry-wise against the
+# entry's Cauchy-Schwarz scale)
 MIXED_BOUND = {"fp32": 1e-6, "bf16x3": 2e-5}
+METRIC = "per-fold train Gram sets/s + TFLOP/s, mixed vs FP64 plain at stated rel err"
+BLOCKS = ("headline", "spectra", "mixed", "batched", "psweep")
+XTX_NAMES = ["raw", "scaled", "centred", "centred+scaled"]
+XTY_NAMES = ["raw", "Y-scaled", "X-scaled", "both-scaled", "centred", "centred+Y-scaled",
+             "centred+X-scaled", "centred+both-scaled"]
+HEADLINE_CHUNK = 8     # folds per cvgram_folds_all call on the large problem
+CPU_SAMPLE_ROWS = 16384
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def f_alg(n, k, m):
@@ -60,47 +92,252 @@ def f_exec(n, k, m, mode, tile=None):
     return 2 * n * entries * (3 if mode == "bf16x3" else 1)
 
 
-def parse():
+def gram_kernel_name(mode, k):
+    tile = 64 if k <= 64 else 128
+    return {"fp64": f"gram_kernel<0, {tile}>", "fp32": f"gram_kernel<2, {tile}>",
+            "bf16x3": f"gram_bf16_kernel<{tile}>"}[mode]
+
+
+def parse(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--mode", default="fp64", choices=["fp64", "fp32", "bf16x3"])
-    ap.add_argument("--workload", type=int, default=2, choices=[2, 3],
-                    help="headline workload: 2 = spectra N=1e5 K=512 (default), "
-                         "3 = precision-stress N=1e6 K=1024 (for profiling one mode)")
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline legs")
-    ap.add_argument("--cpu-seconds", type=float, default=20.0)
-    ap.add_argument("--no-mixed", action="store_true",
-                    help="skip the mixed-vs-FP64 block on the precision-stress workload")
+    ap.add_argument("--blocks", default=",".join(BLOCKS),
+                    help=f"comma-separated blocks to run, from {','.join(BLOCKS)}")
+    ap.add_argument("--headline-mode", default="fp64", choices=["fp64", "bf16x3"],
+                    help="mode of the headline line (the other is still timed)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU legs (oracle, fast CPU)")
+    ap.add_argument("--no-check", action="store_true",
+                    help="skip every error check (timing only; for profiling runs)")
     ap.add_argument("--mixed-steps", type=int, default=5)
-    ap.add_argument("--no-batch", action="store_true",
-                    help="skip the batched block (256 independent problems, graph replay)")
     ap.add_argument("--batch-steps", type=int, default=5)
-    ap.add_argument("--c5", action="store_true",
-                    help="add the large single-problem block (N=2e6, K=4096, M=64, P=64, fp32 "
-                         "input): bf16x3 vs the FP64 form, folds streamed in chunks")
-    ap.add_argument("--psweep", action="store_true",
-                    help="add the fold-count sweep on the spectra shape (N=1e5, K=512, M=8; "
-                         "P = 3 .. 100000, near-equal folds, FP64): Gram time flat in P")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB: the "
                          "reference dispatch that scales HBM byte counters in a profile")
-    return ap.parse_args()
+    a = ap.parse_args(argv)
+    a.blocks = [b for b in a.blocks.split(",") if b]
+    bad = [b for b in a.blocks if b not in BLOCKS]
+    if bad:
+        ap.error(f"unknown block(s) {bad}")
+    return a
 
 
-def cpu_legs(X, Y, fold, P, gpu_xx, gpu_xy, budget_s):
-    """CPU baselines on the host cores: the oracle on a bounded sample (one
-    fold, all 12 classes) and the paper's fast algorithm on all folds."""
-    from oracle import cv_oracle as O
-    from oracle import fast_cpu
+# ---------------------------------------------------------------------------
+# host description
+# ---------------------------------------------------------------------------
+
+def cpu_host():
+    """The host CPU, the cores this process may use, and NumPy's BLAS."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    info = {"model": model, "nproc": os.cpu_count(),
+            "affinity": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None}
     try:
         from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [os.cpu_count()])
+        info["blas"] = [{k: i.get(k) for k in ("internal_api", "version", "num_threads",
+                                                 "threading_layer", "architecture")}
+                        for i in threadpool_info() if i.get("user_api") == "blas"]
     except Exception:
-        threads = os.cpu_count()
-    # the oracle on folds 0, 1, ... until about half the budget is spent
-    # (at least one fold); the GPU result is checked on every fold it covers
+        info["blas"] = None
+    return info
+
+
+def blas_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        return max([i.get("num_threads", 1) for i in threadpool_info()
+                    if i.get("user_api") == "blas"] or [os.cpu_count()])
+    except Exception:
+        return os.cpu_count()
+
+
+# ---------------------------------------------------------------------------
+# timing
+# ---------------------------------------------------------------------------
+
+def time_steps(cv, torch, Xd, Yd, fd, P, K, M, mode, steps, warmup, chunk, stages_inline):
+    """Time `steps` whole steps after `warmup`: create + every fold's 12
+    classes (folds_all in chunks of `chunk` folds) + destroy.  Returns
+    (ms per step, per-stage ms).  With `stages_inline` the library's HIP
+    events are on during the timed steps themselves (each step reads its
+    stage times once its Gram and reduction are done, while its corrections
+    run); otherwise the timed steps run back to back with no host wait and
+    the stage times come from a separate pass."""
+    odt = torch.float64 if mode == "fp64" else torch.float32
+    dev = Xd.device
+    CH = min(chunk, P)
+    xx = torch.empty(CH, 4, K, K, dtype=odt, device=dev)
+    xy = torch.empty(CH, 8, K, M, dtype=odt, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step(timing, ev=None):
+        h = cv.cvgram_create(Xd, Yd, fd, 1, 1, 1, 1, ddof=1, mode=mode, stream=stream)
+        if ev is not None:
+            ev[0].record(stream)
+        for p0 in range(0, P, CH):
+            p1 = min(P, p0 + CH)
+            cv.cvgram_folds_all(h, p0, p1, xx[:p1 - p0], xy[:p1 - p0])
+        if ev is not None:
+            ev[1].record(stream)
+        st = cv.cvgram_stage_times(h) if timing else None
+        cv.cvgram_destroy(h)
+        return st
+
+    def events():
+        return (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+
+    for _ in range(warmup):
+        step(False)
+    torch.cuda.synchronize()
+    if stages_inline:
+        cv.cvgram_set_stage_timing(True)
+        evs = [events() for _ in range(steps)]
+        t0 = time.perf_counter()
+        sts = [step(True, evs[i]) for i in range(steps)]
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        cv.cvgram_set_stage_timing(False)
+    else:
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step(False)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        cv.cvgram_set_stage_timing(True)
+        n = max(3, min(steps, 20))
+        evs = [events() for _ in range(n)]
+        sts = [step(True, evs[i]) for i in range(n)]
+        torch.cuda.synchronize()
+        cv.cvgram_set_stage_timing(False)
+    for s, (e0, e1) in zip(sts, evs):
+        s["correct"] = e0.elapsed_time(e1)
+    del xx, xy
+    stage_ms = {k: float(np.mean([s[k] for s in sts])) for k in sts[0]}
+    stage_ms["gram_min"] = float(np.min([s["gram"] for s in sts]))
+    stage_ms["gram_max"] = float(np.max([s["gram"] for s in sts]))
+    return (t1 - t0) * 1e3 / steps, stage_ms
+
+
+def roofline(mode, n, k, m, stage_ms, workload):
+    g = f_alg(n, k, m) / (stage_ms["gram"] * 1e-3) / 1e12
+    kname = gram_kernel_name(mode, k)
+    return {"bound": "mfma", "kernel": kname, "achieved": g, "peak": PEAK[mode],
+            "unit": "TFLOP/s", "frac": g / PEAK[mode],
+            "traffic": profiled_traffic(kname, workload),
+            "flops_per_launch": f_alg(n, k, m), "launch_ms": stage_ms["gram"],
+            "executed_tflops": f_exec(n, k, m, mode) / (stage_ms["gram"] * 1e-3) / 1e12}
+
+
+# ---------------------------------------------------------------------------
+# errors
+# ---------------------------------------------------------------------------
+
+def errors_vs_reference(cv, torch, h, href, P, chunk):
+    """Relative Frobenius error of every fold x class of handle h against
+    handle href (same inputs): (xtx [P][4], xty [P][8]) as nested lists."""
+    exx, exy = [], []
+    for p0 in range(0, P, chunk):
+        p1 = min(P, p0 + chunk)
+        a, b = cv.cvgram_folds_all(h, p0, p1)
+        ra, rb = cv.cvgram_folds_all(href, p0, p1)
+        ex = torch.linalg.matrix_norm(a.double() - ra) / torch.linalg.matrix_norm(ra)
+        ey = torch.linalg.matrix_norm(b.double() - rb) / torch.linalg.matrix_norm(rb)
+        exx.extend(ex.cpu().tolist())
+        exy.extend(ey.cpu().tolist())
+        del a, b, ra, rb
+    return exx, exy
+
+
+def error_summary(exx, exy, bound=None):
+    allv = [v for row in exx for v in row] + [v for row in exy for v in row]
+    out = {"max": max(allv), "median": float(np.median(allv)),
+           "max_per_xtx_class": dict(zip(XTX_NAMES, np.max(np.array(exx), axis=0).tolist())),
+           "max_per_xty_class": dict(zip(XTY_NAMES, np.max(np.array(exy), axis=0).tolist())),
+           "per_fold_xtx": [[float(f"{v:.3g}") for v in row] for row in exx],
+           "per_fold_xty": [[float(f"{v:.3g}") for v in row] for row in exy]}
+    if bound is not None:
+        out["stated_bound"] = bound
+        out["within_bound"] = out["max"] <= bound
+    return out
+
+
+def gpu_sampled_blocks(cv, torch, handles, folds, xcols, ycols):
+    """GPU products of the given folds restricted to the sampled columns, as
+    host FP64 arrays: {mode: {fold: (xx[4][kx][kx], xy[8][kx][ky])}}."""
+    out = {m: {} for m in handles}
+    for mode, h in handles.items():
+        for p in folds:
+            xx, xy = cv.cvgram_folds_all(h, p, p + 1)
+            xi = torch.tensor(xcols, device=xx.device)
+            yi = torch.tensor(ycols, device=xx.device)
+            out[mode][int(p)] = (xx[0][:, xi][:, :, xi].double().cpu().numpy(),
+                                 xy[0][:, xi][:, :, yi].double().cpu().numpy())
+            del xx, xy
+    return out
+
+
+# ---------------------------------------------------------------------------
+# CPU legs
+# ---------------------------------------------------------------------------
+
+def cpu_oracle_sample(X_rows, Y_rows, fold_rows, p, n_train_full):
+    """The oracle (FP64 naive baseline) on fold p of the first rows of a
+    workload, all 12 classes, timed on the host cores; the per-set time is
+    scaled to the full workload by the ratio of training rows (the baseline
+    materialises the training rows and multiplies: linear in them)."""
+    from oracle import cv_oracle as O
+    t0 = time.perf_counter()
+    O.fold_all_classes(X_rows, Y_rows, fold_rows, p, ddof=1)
+    dt = time.perf_counter() - t0
+    nt_sample = int((np.asarray(fold_rows) != p).sum())
+    scale = n_train_full / nt_sample
+    per_set_full = dt / 12 * scale
+    return {"value": 1.0 / per_set_full, "unit": "sets/s", "cores": int(blas_threads()),
+            "kind": "oracle",
+            "sample": f"fold {p} over the first {len(fold_rows)} rows of the workload (their own "
+                      f"labels; {nt_sample} training rows), all 12 distinct classes, FP64; the "
+                      f"naive baseline is linear in the training rows, so its per-set time is "
+                      f"scaled by {n_train_full}/{nt_sample} = {scale:.2f} to the full workload",
+            "seconds": round(dt, 3)}
+
+
+def cpu_sampled_check(gpu_blocks, Xs, Ys, fold):
+    """The oracle on the sampled columns of each checked fold, compared with
+    the GPU blocks of every mode: every entry against its Cauchy-Schwarz
+    scale, and the relative Frobenius error of the block, per class:
+    {mode: {fold: {"xtx": [[entrywise, frobenius]] * 4, "xty": [...] * 8},
+    "max_entrywise": e}}."""
+    from tests import sampling as S
+    modes = list(gpu_blocks)
+    folds = sorted(gpu_blocks[modes[0]])
+    out = {m: {} for m in modes}
+    for p in folds:
+        ref = S.oracle_block(Xs, Ys, fold, p)
+        for m in modes:
+            gxx, gxy = gpu_blocks[m][p]
+            res = S.compare_block(gxx, gxy, ref)
+            out[m][p] = {k: [[float(f"{a:.3g}"), float(f"{b:.3g}")] for a, b in v]
+                         for k, v in res.items()}
+    for m in modes:
+        out[m]["max_entrywise"] = max(e for p in folds for k in out[m][p].values() for e, _ in k)
+    return out
+
+
+def cpu_spectra_legs(X, Y, fold, P, gpu_xx, gpu_xy, budget_s=20.0):
+    """CPU baselines on the spectra shape: the oracle on folds 0, 1, ... (until
+    about half the budget is spent; the GPU result is checked on every fold it
+    covers), and the paper's fast algorithm on all folds with every host core
+    and with one thread (the paper's own setting)."""
+    from oracle import cv_oracle as O
+    from oracle import fast_cpu
     t0 = time.perf_counter()
     errs = []
     n_or = 0
@@ -114,114 +351,38 @@ def cpu_legs(X, Y, fold, P, gpu_xx, gpu_xy, budget_s):
         if time.perf_counter() - t0 >= 0.5 * budget_s:
             break
     t_or = time.perf_counter() - t0
-    errs = [float(e) for e in errs]
-    cpu = {"value": 12.0 * n_or / t_or, "unit": "sets/s", "cores": int(threads), "kind": "oracle",
+    threads = int(blas_threads())
+    cpu = {"value": 12.0 * n_or / t_or, "unit": "sets/s", "cores": threads, "kind": "oracle",
            "sample": f"folds 0..{n_or - 1} of {P}, all 12 distinct classes each, FP64 naive "
-                     f"baseline",
-           "seconds": round(t_or, 3)}
-    fast = None
-    if t_or < budget_s:
+                     f"baseline", "seconds": round(t_or, 3)}
+
+    def fast(nthreads):
         t0 = time.perf_counter()
-        for _ in fast_cpu.fast_all_folds(X, Y, fold, ddof=1):
-            pass
-        t_fast = time.perf_counter() - t0
-        fast = {"value": P * 12.0 / t_fast, "unit": "sets/s", "cores": int(threads),
+        if nthreads is None:
+            for _ in fast_cpu.fast_all_folds(X, Y, fold, ddof=1):
+                pass
+        else:
+            from threadpoolctl import threadpool_limits
+            with threadpool_limits(limits=nthreads):
+                for _ in fast_cpu.fast_all_folds(X, Y, fold, ddof=1):
+                    pass
+        dt = time.perf_counter() - t0
+        return {"value": P * 12.0 / dt, "unit": "sets/s", "cores": nthreads or threads,
                 "kind": "paper fast algorithm (Algorithm 7, all classes), FP64 NumPy",
-                "sample": f"all {P} folds", "seconds": round(t_fast, 3)}
-    return cpu, fast, errs
+                "sample": f"all {P} folds", "seconds": round(dt, 3)}
+
+    out = {"oracle": cpu, "fast_all_cores": fast(None)}
+    try:
+        out["fast_one_thread"] = fast(1)
+    except Exception as e:  # threadpoolctl missing: report why
+        out["fast_one_thread"] = {"error": str(e)}
+    errs = [float(e) for e in errs]
+    return out, errs
 
 
-def measure(cv, torch, Xd, Yd, fd, P, K, M, mode, steps, warmup):
-    """Time `steps` whole steps (after `warmup`): create + all folds x 12
-    classes + destroy, back to back with no host synchronisation between
-    them.  Stage times come from a separate pass of steps with the library's
-    HIP events on (those steps wait for their events)."""
-    odt = torch.float64 if mode == "fp64" else torch.float32
-    dev = Xd.device
-    xx = torch.empty(P, 4, K, K, dtype=odt, device=dev)
-    xy = torch.empty(P, 8, K, M, dtype=odt, device=dev)
-    stream = torch.cuda.current_stream()
-
-    def step(timing=False):
-        h = cv.cvgram_create(Xd, Yd, fd, 1, 1, 1, 1, ddof=1, mode=mode, stream=stream)
-        if timing:
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-        cv.cvgram_folds_all(h, 0, P, xx, xy)
-        st = None
-        if timing:
-            e1.record(stream)
-            st = cv.cvgram_stage_times(h)
-        cv.cvgram_destroy(h)
-        if timing:
-            e1.synchronize()
-            st["correct"] = e0.elapsed_time(e1)
-        return st
-
-    for _ in range(warmup):
-        step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms = (t1 - t0) * 1e3 / steps
-    # stage breakdown (and the Gram launch time behind the roofline)
-    cv.cvgram_set_stage_timing(True)
-    stages = [step(timing=True) for _ in range(max(3, min(steps, 20)))]
-    torch.cuda.synchronize()
-    cv.cvgram_set_stage_timing(False)
-    stage_ms = {k: float(np.mean([s[k] for s in stages])) for k in stages[0]}
-    return ms, stage_ms, xx, xy
-
-
-def measure_single(cv, torch, Xd, Yd, fd, P, K, M, mode, steps, warmup):
-    """The paper's own target, one combination (center and scale X and Y):
-    create + cvgram_fold for every fold + destroy.  Returns ms per step."""
-    odt = torch.float64 if mode == "fp64" else torch.float32
-    xx = torch.empty(K, K, dtype=odt, device=Xd.device)
-    xy = torch.empty(K, M, dtype=odt, device=Xd.device)
-    stream = torch.cuda.current_stream()
-
-    def step():
-        h = cv.cvgram_create(Xd, Yd, fd, 1, 1, 1, 1, ddof=1, mode=mode, stream=stream)
-        for p in range(P):
-            cv.cvgram_fold(h, p, xx, xy)
-        cv.cvgram_destroy(h)
-
-    for _ in range(warmup):
-        step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        step()
-    torch.cuda.synchronize()
-    return (time.perf_counter() - t0) * 1e3 / steps
-
-
-def padded_rows(fold, P):
-    """Rows of the packed panels: every fold padded to a multiple of 32."""
-    counts = np.bincount(np.asarray(fold), minlength=P)
-    return int(((counts + 31) // 32 * 32).sum())
-
-
-def stage_bandwidth(N, K, M, P, Np, in_bytes, mode, stage_ms):
-    """Algorithmic HBM bytes and GB/s of the statistics pass (A2: read X and Y
-    once, write the packed operand panels) and of the per-fold corrections
-    (A5: read G_p, write 4 K x K + 8 K x M outputs per fold)."""
-    e = {"fp64": 8, "fp32": 4, "bf16x3": 4}[mode]
-    W = K + M
-    tile = 64 if K <= 64 else 128
-    Kp = -(-K // tile) * tile
-    Wp = Kp + (32 if 0 < M <= 32 else -(-M // tile) * tile)
-    a2 = N * W * in_bytes + Np * Wp * e
-    ob = 8 if mode == "fp64" else 4
-    a5 = P * ((4 * K * K + 8 * K * M) * ob + (K * (K + 1) // 2 + K * M) * 8) + K * W * 8
-    return {"A2_stats_pack": {"bytes": a2, "GB_per_s": a2 / (stage_ms["stats"] * 1e-3) / 1e9},
-            "A5_corrections": {"bytes": a5, "GB_per_s": a5 / (stage_ms["correct"] * 1e-3) / 1e9}}
-
+# ---------------------------------------------------------------------------
+# measured HBM traffic from the committed counter summaries
+# ---------------------------------------------------------------------------
 
 def source_digest():
     """SHA-256 over the sources that decide what the Gram launch reads and
@@ -235,123 +396,150 @@ def source_digest():
 
 
 def profiled_traffic(kernel, workload):
-    """HBM bytes per launch of `kernel` on `workload` from the committed
-    counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by the same
-    counter's reading for a plain copy), or None when the summary is absent,
-    covers another kernel or workload, or was taken on other sources."""
-    path = os.path.join(ROOT, "profiles", "gram_hbm_traffic.txt")
-    if not os.path.exists(path):
-        return None
-    kv = {}
-    with open(path) as fh:
-        for line in fh:
-            if ":" in line and not line.startswith("#"):
-                k, v = line.split(":", 1)
-                kv[k.strip()] = v.strip()
-    if kv.get("source_sha256") != source_digest() or kv.get("kernel") != kernel \
-            or kv.get("workload") != workload:
-        return None
-    return float(kv["fetch_bytes_scaled"]) + float(kv["write_bytes_scaled"])
+    """HBM bytes per launch of `kernel` on `workload` from a committed counter
+    summary (profiles/*hbm_traffic*.txt: FETCH_SIZE and WRITE_SIZE, each
+    scaled by the same counter's reading for a plain copy), or None when no
+    summary covers that kernel and workload on the current sources."""
+    digest = None
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*hbm_traffic*.txt"))):
+        kv = {}
+        with open(path) as fh:
+            for line in fh:
+                if ":" in line and not line.startswith("#"):
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        if kv.get("kernel") != kernel or kv.get("workload") != workload:
+            continue
+        if digest is None:
+            digest = source_digest()
+        if kv.get("source_sha256") != digest:
+            continue
+        return float(kv["fetch_bytes_scaled"]) + float(kv["write_bytes_scaled"])
+    return None
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1 "
-                          "(multi-GPU sharding is a design, not built)"}))
-        sys.exit(2)
-    import torch
-    import paper_2401_13185_amd as cv
-    from synth import generators as G
+# ---------------------------------------------------------------------------
+# blocks
+# ---------------------------------------------------------------------------
 
-    if not torch.cuda.is_available():
-        print(json.dumps({"error": "no GPU visible"}))
-        sys.exit(1)
-    dev = torch.device("cuda:0")
-    if args.copy_ref_mib:
-        src = torch.empty(args.copy_ref_mib << 18, dtype=torch.float32, device=dev).fill_(1.0)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-    shape, (X, Y, fold) = G.workload(args.workload)
+def headline_block(cv, torch, G, dev, args):
+    """The large problem: FP64 and BF16X3 on the same inputs."""
+    shape = G.WORKLOADS[5]
     N, K, M, P = shape.n, shape.k, shape.m, shape.p
-    print(f"[bench] workload {shape.name} generated", file=sys.stderr, flush=True)
-    Xd = torch.from_numpy(X).to(dev)
-    Yd = torch.from_numpy(Y).to(dev)
+    workload = shape.name + " input"
+    X, Y = G.spectra_xy_torch(N, K, M, seed=5_13185, device=dev)
+    fold = G.folds_dirichlet(N, P, G._rng(5, 0, 9))
     fd = torch.from_numpy(fold).to(dev)
-    ms, stage_ms, xx, xy = measure(cv, torch, Xd, Yd, fd, P, K, M, args.mode, args.steps,
-                                   args.warmup)
-    print("[bench] headline timed steps done", file=sys.stderr, flush=True)
-
-    sets = P * 12
-    flops = f_alg(N, K, M)
-    gram_tflops = flops / (stage_ms["gram"] * 1e-3) / 1e12
-    tile = 64 if K <= 64 else 128
-    kname = {"fp64": f"gram_kernel<0, {tile}>", "fp32": f"gram_kernel<1, {tile}>",
-             "bf16x3": f"gram_bf16_kernel<{tile}>"}
-    single_ms = measure_single(cv, torch, Xd, Yd, fd, P, K, M, args.mode, max(3, args.steps // 2),
-                               1)
-    print("[bench] single-combination steps done", file=sys.stderr, flush=True)
-    traffic = profiled_traffic(kname[args.mode], shape.name)
-    Np = padded_rows(fold, P)
-    out = {
-        "metric": "per-fold train Gram sets/s (12 distinct centering/scaling classes per fold)",
-        "value": sets / (ms * 1e-3),
-        "unit": "sets/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3+f32acc"}[args.mode],
-        "data": "synthetic",
-        "config": {"workload": shape.name, "N": N, "K": K, "M": M, "P": P, "folds": {"dirichlet": "Dirichlet(2)", "near_equal": "near-equal"}[shape.folds],
-                   "mode": args.mode, "classes_per_fold": 12, "ddof": 1},
-        "tflops_alg": flops / (ms * 1e-3) / 1e12,
-        "stage_ms": stage_ms,
-        "roofline": {"bound": "mfma", "kernel": kname[args.mode], "achieved": gram_tflops,
-                     "peak": PEAK[args.mode], "unit": "TFLOP/s",
-                     "frac": gram_tflops / PEAK[args.mode], "traffic": traffic},
-        "gram_executed_tflops": f_exec(N, K, M, args.mode) / (stage_ms["gram"] * 1e-3) / 1e12,
-        "single_combination": {"combo": "center+scale X and Y (1111)", "sets_per_step": P,
-                               "ms_per_step": single_ms, "sets_per_s": P / (single_ms * 1e-3)},
-        "hbm": stage_bandwidth(N, K, M, P, Np, X.itemsize, args.mode, stage_ms),
-    }
-    if not args.no_cpu:
+    torch.cuda.synchronize()
+    log(f"workload {workload} generated")
+    res = {"workload": workload, "modes": {}}
+    for mode in ("fp64", "bf16x3"):
+        main = mode == args.headline_mode
+        steps = args.steps if main else max(3, args.mixed_steps)
+        warm = args.warmup if main else 1
+        ms, st = time_steps(cv, torch, X, Y, fd, P, K, M, mode, steps, warm, HEADLINE_CHUNK,
+                            stages_inline=True)
+        res["modes"][mode] = {"steps": steps, "warmup": warm, "ms_per_step": ms,
+                              "sets_per_s": P * 12 / (ms * 1e-3),
+                              "tflops_alg": f_alg(N, K, M) / (ms * 1e-3) / 1e12,
+                              "stage_ms": st, "roofline": roofline(mode, N, K, M, st, workload)}
+        log(f"large problem {mode}: {ms:.1f} ms/step, Gram {st['gram']:.1f} ms")
+    f64, b16 = res["modes"]["fp64"], res["modes"]["bf16x3"]
+    b16["speedup_vs_fp64"] = f64["ms_per_step"] / b16["ms_per_step"]
+    b16["gram_speedup_vs_fp64"] = f64["stage_ms"]["gram"] / b16["stage_ms"]["gram"]
+    if not args.no_check:
+        h64 = cv.cvgram_create(X, Y, fd, 1, 1, 1, 1, ddof=1, mode="fp64")
+        hb = cv.cvgram_create(X, Y, fd, 1, 1, 1, 1, ddof=1, mode="bf16x3")
+        exx, exy = errors_vs_reference(cv, torch, hb, h64, P, HEADLINE_CHUNK)
+        b16["error_vs_fp64_gpu"] = error_summary(exx, exy, MIXED_BOUND["bf16x3"])
+        log("large problem: bf16x3 error table against the FP64 form done")
+        if not args.no_cpu:
+            sizes = np.bincount(fold, minlength=P)
+            folds = sorted({int(np.argmin(sizes)), int(np.argmax(sizes))})
+            rng = np.random.default_rng(5)
+            xcols = sorted(int(c) for c in rng.choice(np.arange(1, K - 1), 10, replace=False))
+            xcols = [0, *xcols, K - 1]
+            ycols = [0, 1, M // 2, M - 1]
+            blocks = gpu_sampled_blocks(cv, torch, {"fp64": h64, "bf16x3": hb}, folds, xcols,
+                                        ycols)
+            Xs = X[:, xcols].double().cpu().numpy()
+            Ys = Y[:, ycols].double().cpu().numpy()
+        cv.cvgram_destroy(hb)
+        cv.cvgram_destroy(h64)
         torch.cuda.synchronize()
-        gxx = xx.double().cpu().numpy()
-        gxy = xy.double().cpu().numpy()
-        cpu, fast, errs = cpu_legs(X, Y, fold, P, gxx, gxy, args.cpu_seconds)
-        out["cpu_baseline"] = cpu
-        if fast:
-            out["cpu_fast"] = fast
-        out["max_rel_err_vs_oracle"] = max(errs)  # over the folds the oracle sample covers
-        out["median_rel_err_vs_oracle"] = float(np.median(errs))
-    del xx, xy
-    out["ridge"] = ridge_block(cv, torch, Xd, Yd, fd, P, K, M, args.mode)
-    print("[bench] ridge block done", file=sys.stderr, flush=True)
-    if not args.no_mixed:
-        out["mixed"] = mixed_block(cv, torch, G, dev, args)
-    if not args.no_batch:
-        out["batched"] = batched_block(cv, torch, G, dev, args)
-    if args.c5:
-        out["large"] = c5_block(cv, torch, G, dev, args)
-    if args.psweep:
-        out["p_sweep"] = psweep_block(cv, torch, G, dev, args)
-    print(json.dumps(out))
+    if not args.no_cpu:
+        # CPU leg: the oracle timed on a bounded sample, and (unless
+        # --no-check) the oracle's values of the sampled entries
+        n = CPU_SAMPLE_ROWS
+        Xh = X[:n].double().cpu().numpy()
+        Yh = Y[:n].double().cpu().numpy()
+        res["cpu_baseline"] = cpu_oracle_sample(Xh, Yh, fold[:n], 0, int((fold != 0).sum()))
+        del Xh, Yh
+        log("large problem: CPU oracle sample done")
+        if not args.no_check:
+            res["sampled_vs_oracle"] = {
+                "columns": {"x": xcols, "y": ycols}, "folds": folds,
+                "errors": cpu_sampled_check(blocks, Xs, Ys, fold),
+                "bars": {"fp64": 1e-10, "bf16x3": MIXED_BOUND["bf16x3"]},
+                "note": "every entry among the sampled columns: error against the entry's "
+                        "Cauchy-Schwarz scale sqrt(U^T U_ii V^T V_jj), and relative Frobenius "
+                        "error of the sampled block"}
+            log("large problem: sampled entries against the oracle done")
+    del X, Y, fd
+    torch.cuda.empty_cache()
+    cv.cvgram_trim_cache()
+    return res
 
 
-def ridge_block(cv, torch, Xd, Yd, fd, P, K, M, mode, n_lambda=8, reps=3):
-    """The per-fold ridge consumer on the headline workload: every fold and
-    n_lambda penalties (1e-3 .. 1e4), centred and scaled; one call = the
-    products of all folds in FP64, a batched Cholesky of P x n_lambda K x K
-    systems and their solves.  Flops per system: K^3/3 + 2 K^2 M."""
+def spectra_block(cv, torch, G, dev, args):
+    """N=1e5, K=512, M=8, P=10 spectra, FP64 input, Dirichlet(2) folds."""
+    shape, (X, Y, fold) = G.workload(2)
+    N, K, M, P = shape.n, shape.k, shape.m, shape.p
+    log(f"workload {shape.name} generated")
+    Xd, Yd, fd = (torch.from_numpy(a).to(dev) for a in (X, Y, fold))
+    ms, st = time_steps(cv, torch, Xd, Yd, fd, P, K, M, "fp64", args.steps, args.warmup, P,
+                        stages_inline=False)
+    out = {"workload": shape.name, "ms_per_step": ms, "sets_per_s": P * 12 / (ms * 1e-3),
+           "tflops_alg": f_alg(N, K, M) / (ms * 1e-3) / 1e12, "stage_ms": st,
+           "roofline": roofline("fp64", N, K, M, st, shape.name),
+           "hbm": stage_bandwidth(N, K, M, P, X.itemsize, "fp64", st)}
+    log("spectra timed steps done")
+    if not args.no_check or not args.no_cpu:
+        h = cv.cvgram_create(Xd, Yd, fd, 1, 1, 1, 1, ddof=1, mode="fp64")
+        xx, xy = cv.cvgram_folds_all(h, 0, P)
+        gxx, gxy = xx.cpu().numpy(), xy.cpu().numpy()
+        cv.cvgram_destroy(h)
+        del xx, xy
+        if not args.no_cpu:
+            out["cpu"], errs = cpu_spectra_legs(X, Y, fold, P, gxx, gxy)
+            out["max_rel_err_vs_oracle"] = max(errs)
+            out["median_rel_err_vs_oracle"] = float(np.median(errs))
+            log("spectra CPU legs done")
+    out["ridge"] = ridge_block(cv, torch, Xd, Yd, fd, P, K, M)
+    log("ridge block done")
+    return out
+
+
+def stage_bandwidth(N, K, M, P, in_bytes, mode, stage_ms):
+    """Algorithmic HBM bytes and GB/s of the statistics pass (A2: read X and Y
+    once) and of the per-fold corrections (A5: read G_p, write 4 K x K + 8
+    K x M outputs per fold, read G once).  What the pass writes besides (the
+    packed operand panels) is not counted."""
+    W = K + M
+    a2 = N * W * in_bytes
+    ob = 8 if mode == "fp64" else 4
+    a5 = P * ((4 * K * K + 8 * K * M) * ob + (K * (K + 1) // 2 + K * M) * 8) + K * W * 8
+    return {"A2_stats_pack": {"bytes": a2, "GB_per_s": a2 / (stage_ms["stats"] * 1e-3) / 1e9},
+            "A5_corrections": {"bytes": a5, "GB_per_s": a5 / (stage_ms["correct"] * 1e-3) / 1e9}}
+
+
+def ridge_block(cv, torch, Xd, Yd, fd, P, K, M, n_lambda=8, reps=3):
+    """The per-fold ridge consumer: every fold and n_lambda penalties (1e-3 ..
+    1e4), centred and scaled; one call = the products of all folds in FP64, a
+    batched Cholesky of P x n_lambda K x K systems and their solves.  Flops
+    per system: K^3/3 + 2 K^2 M."""
     lams = list(np.logspace(-3, 4, n_lambda))
-    h = cv.cvgram_create(Xd, Yd, fd, 1, 1, 1, 1, ddof=1, mode=mode)
+    h = cv.cvgram_create(Xd, Yd, fd, 1, 1, 1, 1, ddof=1, mode="fp64")
     out = torch.empty(P, n_lambda, K, M, dtype=torch.float64, device=Xd.device)
     cv.cvgram_ridge(h, 0, P, lams, out)  # warm
     torch.cuda.synchronize()
@@ -368,49 +556,54 @@ def ridge_block(cv, torch, Xd, Yd, fd, P, K, M, mode, n_lambda=8, reps=3):
 
 
 def mixed_block(cv, torch, G, dev, args):
-    """Mixed precision vs plain FP64 on the precision-stress workload (FP32
-    input, column means in [1e3, 1e4]): sets/s and Gram TFLOP/s per mode, and
-    each mixed mode's worst relative Frobenius error over all folds and
-    classes against the FP64 GPU form (itself within 1e-10 of the oracle)."""
+    """Precision stress (FP32 input, column means in [1e3, 1e4]): sets/s and
+    Gram roofline per mode; each mixed mode's error per fold x class against
+    the FP64 GPU form; sampled entries of three folds against the oracle in
+    every mode."""
     shape, (X, Y, fold) = G.workload(3)
     N, K, M, P = shape.n, shape.k, shape.m, shape.p
-    print(f"[bench] workload {shape.name} generated", file=sys.stderr, flush=True)
-    Xd = torch.from_numpy(X).to(dev)
-    Yd = torch.from_numpy(Y).to(dev)
-    fd = torch.from_numpy(fold).to(dev)
+    log(f"workload {shape.name} generated")
+    rng = np.random.default_rng(1024)
+    xcols = [0, *sorted(int(c) for c in rng.choice(np.arange(1, K - 1), 14, replace=False)),
+             K - 1]
+    ycols = [0, 5, 10, M - 1]
+    Xs = X[:, xcols].astype(np.float64)
+    Ys = Y[:, ycols].astype(np.float64)
+    Xd, Yd, fd = (torch.from_numpy(a).to(dev) for a in (X, Y, fold))
     del X, Y
-    flops = f_alg(N, K, M)
     res = {"workload": shape.name, "classes_per_fold": 12, "modes": {}}
-    ref = None
     for mode in ("fp64", "fp32", "bf16x3"):
-        ms, st, xx, xy = measure(cv, torch, Xd, Yd, fd, P, K, M, mode, args.mixed_steps, 1)
-        g = flops / (st["gram"] * 1e-3) / 1e12
-        ge = f_exec(N, K, M, mode) / (st["gram"] * 1e-3) / 1e12
-        r = {"sets_per_s": P * 12 / (ms * 1e-3), "ms_per_step": ms, "stage_ms": st,
-             "gram_tflops_alg": g, "gram_frac_of_peak": g / PEAK[mode], "peak_tflops": PEAK[mode],
-             "gram_executed_tflops": ge, "gram_executed_frac_of_peak": ge / PEAK[mode]}
-        if mode == "fp64":
-            ref = (xx, xy)
-        else:
-            errs = []
-            for q in range(P):
-                for c in range(4):
-                    a, b = xx[q, c].double(), ref[0][q, c]
-                    errs.append((torch.linalg.norm(a - b) / torch.linalg.norm(b)).item())
-                for c in range(8):
-                    a, b = xy[q, c].double(), ref[1][q, c]
-                    errs.append((torch.linalg.norm(a - b) / torch.linalg.norm(b)).item())
-            worst = max(errs)
-            r["max_rel_err_vs_fp64"] = worst
-            r["median_rel_err_vs_fp64"] = float(np.median(errs))
-            r["stated_bound"] = MIXED_BOUND[mode]
-            r["within_bound"] = worst <= MIXED_BOUND[mode]
-            del xx, xy
-        res["modes"][mode] = r
-        print(f"[bench] mixed-block mode {mode} done", file=sys.stderr, flush=True)
+        ms, st = time_steps(cv, torch, Xd, Yd, fd, P, K, M, mode, args.mixed_steps, 1, 25,
+                            stages_inline=True)
+        rl = roofline(mode, N, K, M, st, shape.name)
+        res["modes"][mode] = {"sets_per_s": P * 12 / (ms * 1e-3), "ms_per_step": ms,
+                              "stage_ms": st, "roofline": rl}
+        log(f"mixed-block mode {mode}: {ms:.2f} ms/step, Gram {st['gram']:.2f} ms")
     f64 = res["modes"]["fp64"]["ms_per_step"]
     for mode in ("fp32", "bf16x3"):
         res["modes"][mode]["speedup_vs_fp64"] = f64 / res["modes"][mode]["ms_per_step"]
+    if not args.no_check:
+        handles = {m: cv.cvgram_create(Xd, Yd, fd, 1, 1, 1, 1, ddof=1, mode=m)
+                   for m in ("fp64", "fp32", "bf16x3")}
+        for mode in ("fp32", "bf16x3"):
+            exx, exy = errors_vs_reference(cv, torch, handles[mode], handles["fp64"], P, 25)
+            res["modes"][mode]["error_vs_fp64_gpu"] = error_summary(exx, exy, MIXED_BOUND[mode])
+        log("mixed block: error tables against the FP64 form done")
+        folds = [0, 37, P - 1]
+        blocks = gpu_sampled_blocks(cv, torch, handles, folds, xcols, ycols)
+        for h in handles.values():
+            cv.cvgram_destroy(h)
+        torch.cuda.synchronize()
+        if not args.no_cpu:
+            # CPU leg: the oracle's values of the sampled entries
+            res["sampled_vs_oracle"] = {
+                "columns": {"x": xcols, "y": ycols}, "folds": folds,
+                "errors": cpu_sampled_check(blocks, Xs, Ys, fold),
+                "bars": {"fp64": 1e-10, **MIXED_BOUND}}
+            log("mixed block: sampled entries against the oracle done")
+    del Xd, Yd, fd
+    torch.cuda.empty_cache()
+    cv.cvgram_trim_cache()
     return res
 
 
@@ -423,7 +616,7 @@ def batched_block(cv, torch, G, dev, args):
     shapes = G.batch_shapes(256)
     probs = [G.batch_problem_device(s, i, dev) for i, s in enumerate(shapes)]
     torch.cuda.synchronize()
-    print("[bench] batched workload generated", file=sys.stderr, flush=True)
+    log("batched workload generated")
     n_sets = sum(s.p for s in shapes) * 12
     flops = sum(f_alg(s.n, s.k, s.m) for s in shapes)
     res = {"workload": "256 problems: N log-uniform [1e3, 2e5], K in {64,128,256,512}, "
@@ -450,22 +643,25 @@ def batched_block(cv, torch, G, dev, args):
                               "tflops_alg": flops / (ms * 1e-3) / 1e12,
                               "plan_seconds": round(t_plan, 3)}
         outs[mode] = b
-        print(f"[bench] batched mode {mode} done", file=sys.stderr, flush=True)
-    worst = 0.0
-    for (xa, ya), (xb, yb) in zip(outs["bf16x3"].outs, outs["fp64"].outs):
-        num = torch.linalg.matrix_norm(xa.double() - xb)
-        den = torch.linalg.matrix_norm(xb)
-        worst = max(worst, (num / den).max().item())
-        num = torch.linalg.matrix_norm(ya.double() - yb)
-        den = torch.linalg.matrix_norm(yb)
-        worst = max(worst, (num / den).max().item())
-    r = res["modes"]["bf16x3"]
-    r["max_rel_err_vs_fp64"] = worst
-    r["stated_bound"] = MIXED_BOUND["bf16x3"]
-    r["within_bound"] = worst <= MIXED_BOUND["bf16x3"]
-    r["speedup_vs_fp64"] = res["modes"]["fp64"]["ms_per_step"] / r["ms_per_step"]
+        log(f"batched mode {mode}: {ms:.2f} ms per replay")
+    if not args.no_check:
+        worst = 0.0
+        for (xa, ya), (xb, yb) in zip(outs["bf16x3"].outs, outs["fp64"].outs):
+            num = torch.linalg.matrix_norm(xa.double() - xb)
+            worst = max(worst, (num / torch.linalg.matrix_norm(xb)).max().item())
+            num = torch.linalg.matrix_norm(ya.double() - yb)
+            worst = max(worst, (num / torch.linalg.matrix_norm(yb)).max().item())
+        r = res["modes"]["bf16x3"]
+        r["max_rel_err_vs_fp64"] = worst
+        r["stated_bound"] = MIXED_BOUND["bf16x3"]
+        r["within_bound"] = worst <= MIXED_BOUND["bf16x3"]
+    res["modes"]["bf16x3"]["speedup_vs_fp64"] = (res["modes"]["fp64"]["ms_per_step"]
+                                                 / res["modes"]["bf16x3"]["ms_per_step"])
     for b in outs.values():
         cv.cvgram_batch_destroy(b)
+    del probs
+    torch.cuda.empty_cache()
+    cv.cvgram_trim_cache()
     return res
 
 
@@ -509,7 +705,7 @@ def psweep_block(cv, torch, G, dev, args):
                      "seconds": dt, "sets_per_s": P * 12 / dt, "gram_ms": st["gram"],
                      "stage_ms": st, "corrections_ms": e0.elapsed_time(e1),
                      "output_GB_per_s": out_bytes / (e0.elapsed_time(e1) * 1e-3) / 1e9})
-        print(f"[bench] p-sweep P={P} done", file=sys.stderr, flush=True)
+        log(f"p-sweep P={P} done")
     del xx, xy, Xd, Yd
     torch.cuda.empty_cache()
     cv.cvgram_trim_cache()
@@ -517,69 +713,64 @@ def psweep_block(cv, torch, G, dev, args):
             "fold_chunk": CH, "rows": rows}
 
 
-def c5_block(cv, torch, G, dev, args):
-    """One large problem (spectra N=2e6, K=4096, M=64, P=64, fp32 input,
-    Dirichlet(2) folds): bf16x3 against the FP64 form on the same inputs.
-    Folds are written in chunks of 8 (every fold's 12 classes), so only the
-    chunk's outputs are resident; sets/s per mode, and bf16x3's worst and
-    median relative Frobenius error against FP64 over every fold and class."""
-    shape = G.WORKLOADS[5]
-    N, K, M, P = shape.n, shape.k, shape.m, shape.p
-    X, Y = G.spectra_xy_torch(N, K, M, seed=5_13185, device=dev)
-    fold = G.folds_dirichlet(N, P, G._rng(5, 0, 9))
-    fd = torch.from_numpy(fold).to(dev)
-    torch.cuda.synchronize()
-    print("[bench] large workload generated", file=sys.stderr, flush=True)
-    CH = 8
-    res = {"workload": shape.name + " (torch generator)", "classes_per_fold": 12,
-           "fold_chunk": CH, "modes": {}}
-    stream = torch.cuda.current_stream()
-    handles = {}
-    for mode in ("bf16x3", "fp64"):
-        odt = torch.float64 if mode == "fp64" else torch.float32
-        xx = torch.empty(CH, 4, K, K, dtype=odt, device=dev)
-        xy = torch.empty(CH, 8, K, M, dtype=odt, device=dev)
-        cv.cvgram_set_stage_timing(True)
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1 "
+                          "(multi-GPU sharding is a design, not built)"}))
+        sys.exit(2)
+    import torch
+    import paper_2401_13185_amd as cv
+    from synth import generators as G
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    if args.copy_ref_mib:
+        src = torch.empty(args.copy_ref_mib << 18, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        h = cv.cvgram_create(X, Y, fd, 1, 1, 1, 1, ddof=1, mode=mode, stream=stream)
-        for p0 in range(0, P, CH):
-            p1 = min(P, p0 + CH)
-            cv.cvgram_folds_all(h, p0, p1, xx[:p1 - p0], xy[:p1 - p0])
+        dst.copy_(src)
         torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        st = cv.cvgram_stage_times(h)
-        cv.cvgram_set_stage_timing(False)
-        g = f_alg(N, K, M) / (st["gram"] * 1e-3) / 1e12
-        res["modes"][mode] = {"seconds": dt, "sets_per_s": P * 12 / dt, "stage_ms": st,
-                              "gram_tflops_alg": g, "gram_frac_of_peak": g / PEAK[mode]}
-        handles[mode] = h
-        del xx, xy
-        print(f"[bench] large-block mode {mode} done", file=sys.stderr, flush=True)
-    errs = []
-    bx = torch.empty(CH, 4, K, K, dtype=torch.float32, device=dev)
-    by = torch.empty(CH, 8, K, M, dtype=torch.float32, device=dev)
-    fx = torch.empty(CH, 4, K, K, dtype=torch.float64, device=dev)
-    fy = torch.empty(CH, 8, K, M, dtype=torch.float64, device=dev)
-    for p0 in range(0, P, CH):
-        p1 = min(P, p0 + CH)
-        cv.cvgram_folds_all(handles["bf16x3"], p0, p1, bx[:p1 - p0], by[:p1 - p0])
-        cv.cvgram_folds_all(handles["fp64"], p0, p1, fx[:p1 - p0], fy[:p1 - p0])
-        for a, b in ((bx[:p1 - p0], fx[:p1 - p0]), (by[:p1 - p0], fy[:p1 - p0])):
-            num = torch.linalg.matrix_norm(a.double() - b)
-            errs.extend((num / torch.linalg.matrix_norm(b)).flatten().tolist())
-    for h in handles.values():
-        cv.cvgram_destroy(h)
-    r = res["modes"]["bf16x3"]
-    r["max_rel_err_vs_fp64"] = max(errs)
-    r["median_rel_err_vs_fp64"] = float(np.median(errs))
-    r["stated_bound"] = MIXED_BOUND["bf16x3"]
-    r["within_bound"] = max(errs) <= MIXED_BOUND["bf16x3"]
-    r["speedup_vs_fp64"] = res["modes"]["fp64"]["seconds"] / r["seconds"]
-    del X, Y, fd, bx, by, fx, fy
-    torch.cuda.empty_cache()
-    cv.cvgram_trim_cache()
-    return res
+        del src, dst
+    blocks = {}
+    for name, fn in (("headline", headline_block), ("spectra", spectra_block),
+                     ("mixed", mixed_block), ("batched", batched_block),
+                     ("psweep", psweep_block)):
+        if name in args.blocks:
+            blocks[name] = fn(cv, torch, G, dev, args)
+
+    if "headline" in blocks:
+        hl = blocks["headline"]
+        main_mode = args.headline_mode
+        r = hl["modes"][main_mode]
+        shape = G.WORKLOADS[5]
+        out = {
+            "metric": METRIC, "value": r["sets_per_s"], "unit": "sets/s", "n_gpus": 1,
+            "steps": r["steps"], "warmup": r["warmup"], "ms_per_step": r["ms_per_step"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": {"fp64": "f64", "bf16x3": "bf16x3+f32acc"}[main_mode], "data": "synthetic",
+            "config": {"workload": hl["workload"], "N": shape.n, "K": shape.k, "M": shape.m,
+                       "P": shape.p, "folds": "Dirichlet(2)", "input": "fp32 (drawn on the GPU)",
+                       "mode": main_mode, "classes_per_fold": 12,
+                       "fold_chunk": HEADLINE_CHUNK, "ddof": 1},
+            "tflops_alg": r["tflops_alg"], "stage_ms": r["stage_ms"], "roofline": r["roofline"],
+        }
+        if "cpu_baseline" in hl:
+            out["cpu_baseline"] = hl["cpu_baseline"]
+        out["mixed_vs_fp64"] = {"mode": "bf16x3", "fp64": hl["modes"]["fp64"],
+                                "bf16x3": hl["modes"]["bf16x3"]}
+        if "sampled_vs_oracle" in hl:
+            out["sampled_vs_oracle"] = hl["sampled_vs_oracle"]
+    else:
+        out = {"metric": METRIC, "value": None, "unit": "sets/s", "n_gpus": 1,
+               "note": "headline block not run (--blocks)"}
+    out["cpu_host"] = cpu_host()
+    for name in ("spectra", "mixed", "batched", "psweep"):
+        if name in blocks:
+            out[name] = blocks[name]
+    print(json.dumps(out))
 
 
 if __name__ == "__main__":

@@ -28,8 +28,9 @@
  *    Device work is enqueued on it; calls return without waiting for it
  *    except where stated.  Outputs are complete once the stream reaches the
  *    point where the call enqueued its work.
- *  - Every entry point returns a cvgram_status; nothing is thrown across the
- *    ABI.  On an error the output arguments are left untouched (a handle
+ *  - Every entry point returns a cvgram_status (except the queries
+ *    cvgram_num_folds, cvgram_version and the two string getters); nothing
+ *    is thrown across the ABI.  On an error the output arguments are left untouched (a handle
  *    out-parameter is set to NULL) and nothing leaks;
  *    cvgram_last_error_message() gives details for the calling thread.
  *  - NaN or Inf inputs are not checked; they propagate into the outputs.
@@ -65,16 +66,18 @@ typedef enum { CVGRAM_F32 = 0, CVGRAM_F64 = 1 } cvgram_dtype;
 /* arithmetic of the Gram contractions (statistics and corrections are
    always FP64):
      CVGRAM_MODE_FP64    FP64 MFMA on FP64 pivot-shifted data; outputs FP64.
-     CVGRAM_MODE_FP32    FP32 MFMA, FP32 accumulation over row blocks that
-                         are combined in FP64; outputs FP32.
      CVGRAM_MODE_BF16X3  each pivot-shifted value split as hi + lo in bf16;
                          hi*hi + hi*lo + lo*hi on bf16 MFMA with FP32
                          accumulation, row blocks combined in FP64; outputs
-                         FP32. */
+                         FP32.
+     CVGRAM_MODE_FP32    FP32 MFMA, FP32 accumulation over row blocks that
+                         are combined in FP64; outputs FP32.
+   The paper computes in FP64 only (Section 7); the two mixed modes are this
+   library's, each with a stated error bound against FP64. */
 typedef enum {
   CVGRAM_MODE_FP64 = 0,
-  CVGRAM_MODE_FP32 = 1,
-  CVGRAM_MODE_BF16X3 = 2
+  CVGRAM_MODE_BF16X3 = 1,
+  CVGRAM_MODE_FP32 = 2
 } cvgram_mode;
 
 /* Class numbering of the distinct products (Section 6, Table 1).
@@ -126,8 +129,10 @@ cvgram_status cvgram_create(const void* X, const void* Y, const int32_t* fold_id
                             int center_x, int scale_x, int center_y, int scale_y,
                             int ddof, cvgram_mode mode, void* stream, cvgram_t* out);
 
-/* Number of folds P of the handle's partitioning (host out-parameter). */
-cvgram_status cvgram_num_folds(cvgram_t h, int32_t* P);
+/* Number of folds P of the handle's partitioning (Definition 1: the
+ * largest label plus one), known on the host once cvgram_create returned.
+ * Returns -1 for a NULL handle (and sets cvgram_last_error_message). */
+int32_t cvgram_num_folds(cvgram_t h);
 
 /* Copy of the fold bookkeeping of Algorithm 1 as a stable counting sort:
  * perm[N] (int32) lists the rows of fold 0, then fold 1, ..., each in
@@ -197,10 +202,11 @@ cvgram_status cvgram_fold_combo(cvgram_t h, int32_t p, int center_x, int scale_x
 /* All distinct products of folds p_begin <= p < p_end in one launch:
  * out_XtX[(p - p_begin)][c][K][K] for the 4 X^T X classes and
  * out_XtY[(p - p_begin)][c][K][M] for the 8 X^T Y classes (class numbering
- * above).  Either pointer may be NULL.  With a partitioning that is not
- * scalable, only the unscaled classes are written (classes 0 and 2 of X^T X,
- * 0 and 4 of X^T Y; the others are left untouched).  Element type as in
- * cvgram_fold. */
+ * above).  Either pointer may be NULL.  Every class is written.  With a
+ * partitioning that is not scalable (Definition 6), a fold whose
+ * |T_p| - ddof < 1 has no training deviation: its scaled classes (1 and 3
+ * of X^T X; 1, 2, 3, 5, 6, 7 of X^T Y) are NaN; the other folds' are
+ * computed as usual.  Element type as in cvgram_fold. */
 cvgram_status cvgram_folds_all(cvgram_t h, int32_t p_begin, int32_t p_end,
                                void* out_XtX, void* out_XtY);
 
@@ -224,8 +230,8 @@ cvgram_status cvgram_set_stage_timing(int on);
 cvgram_status cvgram_stage_times(cvgram_t h, double* ms, int32_t n);
 
 /* Device workspace released by cvgram_destroy() is kept in a per-device
- * cache and reused by later handles of similar size (bounded to 32 GiB per
- * device).  cvgram_trim_cache() waits for the work still using cached blocks
+ * cache and reused by later handles of similar size (bounded per device to
+ * half of its memory, at least 32 GiB).  cvgram_trim_cache() waits for the work still using cached blocks
  * of the current device, then frees them. */
 cvgram_status cvgram_trim_cache(void);
 
@@ -255,8 +261,9 @@ typedef struct {
  * fold bookkeeping of every problem (Algorithm 1; waits on `stream`), checks
  * Definition 1 (CVGRAM_EFOLDS, with the failing problem's index in the error
  * message), allocates one workspace for the batch and captures the pipeline
- * into a HIP graph on `stream`.  Scaled classes of a problem whose
- * partitioning is not scalable for ddof (Definition 6) are not written.
+ * into a HIP graph on `stream`.  Every class is written; in a problem whose
+ * partitioning is not scalable for ddof (Definition 6), the scaled classes
+ * of the folds with |T_p| - ddof < 1 are NaN (as in cvgram_folds_all).
  * Problem arrays and outputs are borrowed: they must stay valid until
  * cvgram_batch_destroy(); their contents may change between runs (the fold
  * labels must not).  Output element type: double in CVGRAM_MODE_FP64, float

@@ -27,7 +27,7 @@ __all__ = [
 _PKG = os.path.dirname(os.path.abspath(__file__))
 _ROOT = os.path.dirname(_PKG)
 HEADER = os.path.join(_ROOT, "include", "cvgram.h")
-MODES = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+MODES = {"fp64": 0, "bf16x3": 1, "fp32": 2}
 # leakage comparison kinds of cvgram_fold_leaky (never training-partition results)
 LEAK_KINDS = {"global": 1, "lindgren": 2}
 XTX_CLASSES = 4
@@ -57,7 +57,7 @@ _int = ctypes.c_int
 _SIGS = {
     "cvgram_create": (_int, [_vp, _vp, _vp, _i64, _i64, _i64, _int, _int, _int, _int, _int, _int,
                              _int, _vp, ctypes.POINTER(_vp)]),
-    "cvgram_num_folds": (_int, [_vp, ctypes.POINTER(_i32)]),
+    "cvgram_num_folds": (_i32, [_vp]),
     "cvgram_plan_info": (_int, [_vp, ctypes.POINTER(_i64), _i32]),
     "cvgram_partition": (_int, [_vp, _vp, _vp]),
     "cvgram_fold": (_int, [_vp, _i32, _vp, _vp]),
@@ -200,9 +200,10 @@ def cvgram_create(X, Y, fold_id, center_x=0, scale_x=0, center_y=0, scale_y=0, d
 
 
 def cvgram_num_folds(h: Handle) -> int:
-    P = _i32()
-    _check(load().cvgram_num_folds(h.ptr, ctypes.byref(P)))
-    return P.value
+    P = int(load().cvgram_num_folds(h.ptr))
+    if P < 0:
+        raise CVGramError(1, cvgram_last_error_message() or "NULL handle")
+    return P
 
 
 def cvgram_plan_info(h: Handle) -> dict:

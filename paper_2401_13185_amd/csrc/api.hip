@@ -42,7 +42,9 @@ cvgram_status fail(cvgram_status st, const std::string& msg) {
 // puts the new work behind the old); by another stream, and a pinned block by
 // the host, only once the event has completed.
 // ---------------------------------------------------------------------------
-constexpr size_t kCacheCap = (size_t)32 << 30;
+// device cache bound: half of the device's memory, at least 32 GiB (a
+// large problem's workspace, tens of GB, then stays cached between handles)
+constexpr size_t kCacheCapMin = (size_t)32 << 30;
 constexpr size_t kHostCacheCap = (size_t)1 << 30;
 constexpr int kMaxDev = 64;
 
@@ -66,6 +68,7 @@ struct Cache {
   std::mutex mu;
   std::multimap<size_t, Cached> dev[kMaxDev];
   size_t dev_total[kMaxDev] = {};
+  size_t dev_cap[kMaxDev] = {};  // 0: not yet known
   std::multimap<size_t, Cached> host;
   size_t host_total = 0;
 };
@@ -218,6 +221,23 @@ struct Owned {
 
   void release_one(const Block& b, const std::shared_ptr<ReleaseMark>& mark = nullptr) {
     Cache& c = cache();
+    size_t cap = kCacheCapMin;
+    if (!b.host && device >= 0 && device < kMaxDev) {
+      {
+        std::lock_guard<std::mutex> g(c.mu);
+        cap = c.dev_cap[device];
+      }
+      if (cap == 0) {
+        size_t total_b = 0;
+        if (hipDeviceTotalMem(&total_b, device) != hipSuccess) {
+          (void)hipGetLastError();
+          total_b = 0;
+        }
+        cap = std::max(kCacheCapMin, total_b / 2);
+        std::lock_guard<std::mutex> g(c.mu);
+        c.dev_cap[device] = cap;
+      }
+    }
     {
       std::lock_guard<std::mutex> g(c.mu);
       if (b.host) {
@@ -226,7 +246,7 @@ struct Owned {
           c.host_total += b.bytes;
           return;
         }
-      } else if (device >= 0 && device < kMaxDev && c.dev_total[device] + b.bytes <= kCacheCap) {
+      } else if (device >= 0 && device < kMaxDev && c.dev_total[device] + b.bytes <= cap) {
         c.dev[device].insert({b.bytes, Cached{b.ptr, mark}});
         c.dev_total[device] += b.bytes;
         return;
@@ -1091,16 +1111,17 @@ void allocate_and_upload(Batch& b, const HostLists& L) {
     d.ctiles = (const int32_t*)(dblob + o_ctiles[i]);
     d.n_ctiles_xx = p.n_ctiles_xx;
     d.n_ctiles_xy = p.n_ctiles_xy;
-    // batched outputs: every fold, all 12 classes (scaled ones only if scalable)
+    // batched outputs: every fold, all 12 classes
     OutDesc& od = outs[i];
     std::memset(&od, 0, sizeof(od));
     const size_t ob = b.mode == CVGRAM_MODE_FP64 ? 8 : 4;
     const int64_t KK = p.K * p.K, KM = p.K * p.M;
+    // every class is written; a fold whose |T_p| - ddof < 1 has NaN
+    // deviations, so its scaled classes come out NaN
     for (int c = 0; c < CVGRAM_XTX_CLASSES; ++c)
-      od.xx[c] = (p.out_xx && (p.scalable || !(c & 1))) ? (char*)p.out_xx + c * KK * ob : nullptr;
+      od.xx[c] = p.out_xx ? (char*)p.out_xx + c * KK * ob : nullptr;
     for (int c = 0; c < CVGRAM_XTY_CLASSES; ++c)
-      od.xy[c] = (p.out_xy && p.M > 0 && (p.scalable || !(c & 3))) ? (char*)p.out_xy + c * KM * ob
-                                                                   : nullptr;
+      od.xy[c] = (p.out_xy && p.M > 0) ? (char*)p.out_xy + c * KM * ob : nullptr;
     od.fold_stride_xx = CVGRAM_XTX_CLASSES * KK;
     od.fold_stride_xy = CVGRAM_XTY_CLASSES * KM;
     od.p_begin = 0;
@@ -1290,10 +1311,12 @@ cvgram_status cvgram_create(const void* X, const void* Y, const int32_t* fold_id
   return CVGRAM_OK;
 }
 
-cvgram_status cvgram_num_folds(cvgram_t h, int32_t* P) {
-  if (!h || !P) return fail(CVGRAM_EINVAL, "NULL argument");
-  *P = h->b.pp[0].P;
-  return CVGRAM_OK;
+int32_t cvgram_num_folds(cvgram_t h) {
+  if (!h) {
+    set_error("NULL handle");
+    return -1;
+  }
+  return h->b.pp[0].P;
 }
 
 cvgram_status cvgram_partition(cvgram_t h, int32_t* perm, int64_t* offsets) {
@@ -1430,11 +1453,11 @@ cvgram_status cvgram_folds_all(cvgram_t h, int32_t p_begin, int32_t p_end, void*
   std::memset(&od, 0, sizeof(od));
   const size_t es = out_is_f64(h->b) ? sizeof(double) : sizeof(float);
   const int64_t KK = pp.K * pp.K, KM = pp.K * pp.M;
+  // every class; scaled classes of folds with |T_p| - ddof < 1 are NaN
   for (int c = 0; c < CVGRAM_XTX_CLASSES; ++c)
-    od.xx[c] = (out_XtX && (pp.scalable || !(c & 1))) ? (char*)out_XtX + c * KK * es : nullptr;
+    od.xx[c] = out_XtX ? (char*)out_XtX + c * KK * es : nullptr;
   for (int c = 0; c < CVGRAM_XTY_CLASSES; ++c)
-    od.xy[c] = (out_XtY && pp.M > 0 && (pp.scalable || !(c & 3))) ? (char*)out_XtY + c * KM * es
-                                                                 : nullptr;
+    od.xy[c] = (out_XtY && pp.M > 0) ? (char*)out_XtY + c * KM * es : nullptr;
   od.fold_stride_xx = CVGRAM_XTX_CLASSES * KK;
   od.fold_stride_xy = CVGRAM_XTY_CLASSES * KM;
   od.p_begin = p_begin;
@@ -1657,6 +1680,14 @@ cvgram_status cvgram_autotune(const void* X, const void* Y, const int32_t* fold_
       if (tiles[ti] == 64 && K > 1024) continue;  // too many tiles to pay off
       for (int ii = 0; ii < 4; ++ii) {
         Batch b;
+        // the candidate's workspace goes back to the cache on every path
+        struct Releaser {
+          Batch& b;
+          ~Releaser() {
+            (void)hipStreamSynchronize(b.stream);
+            b.release();
+          }
+        } releaser{b};
         b.stream = (hipStream_t)stream;
         b.mode = mode;
         b.dtype = dtype;
@@ -1676,10 +1707,7 @@ cvgram_status cvgram_autotune(const void* X, const void* Y, const int32_t* fold_
         b.pp.push_back(p);
         CVG_HIP(hipGetDevice(&b.device));
         st = prepare(b);
-        if (st != CVGRAM_OK) {
-          b.release();
-          return st;
-        }
+        if (st != CVGRAM_OK) return st;
         run_pipeline(b, true);   // warm
         double ms = 1e300;
         for (int rep = 0; rep < 3; ++rep) {
@@ -1689,8 +1717,6 @@ cvgram_status cvgram_autotune(const void* X, const void* Y, const int32_t* fold_
           CVG_HIP(hipEventElapsedTime(&t, b.ev[1], b.ev[4]));
           ms = std::min(ms, (double)t);
         }
-        CVG_HIP(hipStreamSynchronize(b.stream));
-        b.release();
         if (ms < best_ms) {
           best_ms = ms;
           best = b.forced;

@@ -34,10 +34,13 @@ typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
 typedef double double2_t __attribute__((ext_vector_type(2)));
 
-// pivot: c_j = FP64 mean of the first min(N, 256) rows of column j of [X | Y]
-// (rounded to FP32 in the mixed modes).  A 1024-thread workgroup covers 64
-// columns: wave w sums rows w, w + 16, ... (at most 16 rows, every load in
-// flight at once), and the 16 wave sums are combined in a fixed order.
+// pivot: c_j = FP64 mean of n = min(N, 256) rows of column j of [X | Y]
+// spread evenly over the whole column (rows floor(r N / n), r = 0 .. n-1), so
+// that rows ordered by a drifting or sorted covariate still give a pivot
+// near the column's mean (rounded to FP32 in the mixed modes).  A
+// 1024-thread workgroup covers 64 columns: wave w sums sample rows w,
+// w + 16, ... (at most 16, every load in flight at once), and the 16 wave
+// sums are combined in a fixed order.
 constexpr int kPivotThreads = 1024;
 constexpr int kPivotWaves = kPivotThreads / 64;
 
@@ -58,7 +61,7 @@ __device__ inline void pivot_cols(const CVG_GLOBAL T* X, const CVG_GLOBAL T* Y, 
 #pragma unroll
     for (int u = 0; u < 256 / kPivotWaves; ++u) {
       const int64_t r = w + (int64_t)kPivotWaves * u;
-      if (r < rows) v[u] = (double)base[r * ld];
+      if (r < rows) v[u] = (double)base[(r * N / rows) * ld];
     }
   }
 #pragma unroll
@@ -263,7 +266,8 @@ __global__ __launch_bounds__(kPackThreads) void pack_kernel(const ProbDesc* __re
 #pragma unroll
         for (int g = 0; g < 8; ++g) {
           const bool ok = v[g] && js[u] >= 0;
-          // z' = fp32(z - c): an exact FP32 subtraction for FP32 input
+          // z' = fp32(z - c): exact for FP32 input when c/2 <= z <= 2c
+          // (Sterbenz), otherwise rounded once to FP32
           const float zf = !ok ? 0.f
                            : (sizeof(T) == 4 ? (float)x[g][u] - pivf[u]
                                              : (float)(x[g][u] - (double)pivf[u]));

@@ -66,8 +66,7 @@ def test_create_rejects_bad_arguments_before_device_work(kw, status):
 
 def test_null_handle_calls():
     lib = cv.load()
-    P = ctypes.c_int32()
-    assert lib.cvgram_num_folds(None, ctypes.byref(P)) == 1
+    assert lib.cvgram_num_folds(None) == -1
     assert lib.cvgram_fold(None, 0, None, None) == 1
     assert lib.cvgram_fold_combo(None, 0, 0, 0, 0, 0, None, None) == 1
     assert lib.cvgram_fold_leaky(None, 0, 1, None, None) == 1
@@ -121,3 +120,28 @@ def test_binding_fails_loudly_without_library(tmp_path):
     )
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=ROOT)
     assert "raised" in r.stdout, r.stdout + r.stderr
+
+
+def _header_enum(prefix):
+    import re
+    text = open(cv.HEADER).read()
+    return {m.group(1): int(m.group(2))
+            for m in re.finditer(r"\b(" + prefix + r"[A-Z0-9_]+)\s*=\s*(\d+)", text)}
+
+
+def test_mode_numbering_matches_header_and_binding():
+    """The arithmetic modes are numbered FP64 = 0, BF16X3 = 1, FP32 = 2 in the
+    header, and the binding passes the same numbers."""
+    modes = _header_enum("CVGRAM_MODE_")
+    assert modes == {"CVGRAM_MODE_FP64": 0, "CVGRAM_MODE_BF16X3": 1, "CVGRAM_MODE_FP32": 2}
+    assert cv.MODES == {"fp64": 0, "bf16x3": 1, "fp32": 2}
+    status = _header_enum("CVGRAM_E")
+    status["CVGRAM_OK"] = 0
+    assert {v: k for k, v in status.items()} == cv.STATUS
+
+
+def test_num_folds_returns_int32_and_minus_one_for_null():
+    lib = cv.load()
+    assert lib.cvgram_num_folds.restype is ctypes.c_int32
+    assert lib.cvgram_num_folds(None) == -1
+    assert "NULL" in cv.cvgram_last_error_message()

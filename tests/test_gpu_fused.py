@@ -17,6 +17,7 @@ import pytest
 import paper_2401_13185_amd as cv
 from oracle import cv_oracle as O
 from synth import generators as G
+from tests import sampling as S
 
 pytestmark = pytest.mark.gpu
 
@@ -206,16 +207,13 @@ def test_large_P_spectra_full_size_sampled(path):
             assert np.array_equal(xx[q, 3], xx[q, 3].T)
             assert np.allclose(np.diag(xx[q, 3]), nt - 1, rtol=1e-12)
         p = p0 + 3
-        pairs_xx = [(int(a), int(b)) for a, b in rng.integers(0, K, size=(16, 2))]
-        pairs_xy = [(int(a), int(b)) for a, b in zip(rng.integers(0, K, 8), rng.integers(0, M, 8))]
-        for c in range(4):
-            ref, _ = O.fold_entries(X, Y, fold, p, *O.XTX_CLASS_COMBO[c], 1, pairs_xx, [])
-            got = np.array([xx[3, c, i, j] for i, j in pairs_xx])
-            assert np.max(np.abs(got - ref)) <= FP64_TOL * np.max(np.abs(xx[3, c])), (p, c)
-        for c in range(8):
-            _, ref = O.fold_entries(X, Y, fold, p, *O.XTY_CLASS_COMBO[c], 1, [], pairs_xy)
-            got = np.array([xy[3, c, i, j] for i, j in pairs_xy])
-            assert np.max(np.abs(got - ref)) <= FP64_TOL * np.max(np.abs(xy[3, c])), (p, c)
+        xcols = S.pick_columns(K, 16, rng)
+        ycols = S.pick_columns(M, 4, rng)
+        res = S.compare_fold(xx[3][:, xcols][:, :, xcols], xy[3][:, xcols][:, :, ycols],
+                             X[:, xcols], Y[:, ycols], fold, p)
+        for kind in ("xtx", "xty"):
+            for c, (ew, fe) in enumerate(res[kind]):
+                assert ew <= FP64_TOL and fe <= FP64_TOL, (p, kind, c, ew, fe)
     cv.cvgram_destroy(h)
 
 
@@ -257,3 +255,41 @@ def test_plan_info_reports_fold_path():
     assert infos[None]["fused"] and infos["fused"]["fused"] and not infos["grouped"]["fused"]
     for info in infos.values():
         assert info["tile"] == 64 and info["items"] > 0 and info["slabs"] > 0
+
+
+def _fold_products(h, p):
+    xx, xy = cv.cvgram_folds_all(h, p, p + 1)
+    return xx[0].double().cpu().numpy(), xy[0].double().cpu().numpy()
+
+
+@pytest.mark.parametrize("n,k,m,ddof,n_random", [(20000, 64, 4, 1, 26), (6000, 16, 2, 0, 10),
+                                                 (6000, 16, 2, 1, 10)])
+def test_leave_one_out_beyond_4096_folds(n, k, m, ddof, n_random):
+    """Leave-one-out with P = N > 4096: the fold sizes come from the second
+    host wait (fold_offsets_kernel), the folds' totals span many ranges.  All
+    12 classes of folds 0, 4095, 4096, 4097, P-1 and random others against
+    the oracle at 1e-10."""
+    print(f"[fused] LOO N={n} K={k} M={m} ddof={ddof}", flush=True)
+    X, Y = _gaussian(n, k, m, 40 + n + ddof)
+    fold = np.random.default_rng(n + ddof).permutation(n).astype(np.int32)
+    h = cv.cvgram_create(_t(X), _t(Y), _t(fold), 1, 1, 1, 1, ddof=ddof, mode="fp64")
+    assert cv.cvgram_num_folds(h) == n
+    assert cv.cvgram_plan_info(h)["fused"]
+    rng = np.random.default_rng(7)
+    folds = sorted({0, 4095, 4096, 4097, n - 1,
+                    *[int(v) for v in rng.choice(n, n_random, replace=False)]})
+    worst = 0.0
+    for p in folds:
+        gxx, gxy = _fold_products(h, p)
+        oxx, oxy = O.fold_all_classes(X, Y, fold, p, ddof=ddof)
+        for c in range(4):
+            e = _relerr(gxx[c], oxx[c])
+            worst = max(worst, e)
+            assert e <= FP64_TOL, ("XtX", p, c, e)
+            assert np.array_equal(gxx[c], gxx[c].T)
+        for c in range(8):
+            e = _relerr(gxy[c], oxy[c])
+            worst = max(worst, e)
+            assert e <= FP64_TOL, ("XtY", p, c, e)
+    cv.cvgram_destroy(h)
+    print(f"[fused] LOO N={n} {len(folds)} folds worst {worst:.3e}", flush=True)

@@ -3,8 +3,9 @@ P=64, FP32 input, Dirichlet(2) folds (values drawn on the device, as the
 bench's large block does), in the launch configuration the bench times.
 
 FP64 mode against the FP64 oracle on sampled entries of three folds (the
-smallest, the largest and fold 0; the oracle computes each entry from the
-two columns it needs, copied to the host); BF16X3 mode against the FP64 GPU
+smallest, the largest and fold 0): every entry among 16 columns of X and 4
+of Y, computed by the oracle from those columns copied to the host, within
+1e-10 of its Cauchy-Schwarz scale (tests/sampling.py); BF16X3 mode against the FP64 GPU
 form on the same folds' whole products, within the stated bound.
 """
 from __future__ import annotations
@@ -15,6 +16,7 @@ import pytest
 import paper_2401_13185_amd as cv
 from oracle import cv_oracle as O
 from synth import generators as G
+from tests import sampling as S
 
 pytestmark = pytest.mark.gpu
 
@@ -64,30 +66,22 @@ def test_large_problem_sampled_and_mixed_bound():
             worst = max(worst, (num / torch.linalg.matrix_norm(b)).max().item())
     assert worst <= BF16X3_BOUND, worst
 
-    # FP64 against the oracle on sampled entries (columns copied to the host)
+    # FP64 against the oracle on sampled entries: every entry among 16 X and
+    # 4 Y columns (copied to the host), against its Cauchy-Schwarz scale
     rng = np.random.default_rng(55)
-    pairs_xx = [(int(a), int(b)) for a, b in rng.integers(0, K, size=(10, 2))] + [(0, K - 1),
-                                                                                  (K - 1, K - 1)]
-    pairs_xy = [(int(a), int(b)) for a, b in zip(rng.integers(0, K, 6), rng.integers(0, M, 6))]
-    xcols = sorted({c for pr in pairs_xx for c in pr} | {i for i, _ in pairs_xy})
-    ycols = sorted({j for _, j in pairs_xy})
-    xmap = {c: n for n, c in enumerate(xcols)}
-    ymap = {c: n for n, c in enumerate(ycols)}
+    xcols = S.pick_columns(K, 16, rng)
+    ycols = S.pick_columns(M, 4, rng)
     Xs = X[:, xcols].double().cpu().numpy()
     Ys = Y[:, ycols].double().cpu().numpy()
-    sub_xx = [(xmap[i], xmap[j]) for i, j in pairs_xx]
-    sub_xy = [(xmap[i], ymap[j]) for i, j in pairs_xy]
+    xi = torch.tensor(xcols, device=dev)
+    yi = torch.tensor(ycols, device=dev)
     for (fx, fy), p in zip(out["fp64"], folds):
-        for c in range(4):
-            ref, _ = O.fold_entries(Xs, Ys, fold, p, *O.XTX_CLASS_COMBO[c], 1, sub_xx, [])
-            got = np.array([fx[c, i, j].item() for i, j in pairs_xx])
-            scale = fx[c].abs().max().item()
-            assert np.max(np.abs(got - ref)) <= FP64_TOL * scale, (p, c)
-        for c in range(8):
-            _, ref = O.fold_entries(Xs, Ys, fold, p, *O.XTY_CLASS_COMBO[c], 1, [], sub_xy)
-            got = np.array([fy[c, i, j].item() for i, j in pairs_xy])
-            scale = fy[c].abs().max().item()
-            assert np.max(np.abs(got - ref)) <= FP64_TOL * scale, (p, c)
+        gxx = fx[:, xi][:, :, xi].cpu().numpy()
+        gxy = fy[:, xi][:, :, yi].cpu().numpy()
+        res = S.compare_fold(gxx, gxy, Xs, Ys, fold, p)
+        for kind in ("xtx", "xty"):
+            for c, (ew, fe) in enumerate(res[kind]):
+                assert ew <= FP64_TOL and fe <= FP64_TOL, (p, kind, c, ew, fe)
         # properties that hold at any size
         nt = int((fold != p).sum())
         assert torch.equal(fx[3], fx[3].T)

@@ -87,49 +87,50 @@ def test_mixed_against_oracle(mode, case):
     print(f"[mixed] {mode} {shape.name} worst rel err {worst}", flush=True)
 
 
-@pytest.mark.parametrize("mode", ["fp32", "bf16x3"])
-def test_mixed_precision_stress_full_size_sampled(mode):
-    """The precision-stress workload at full size (N=1e6, K=1024, M=16,
-    P=100, FP32 input with column means in [1e3, 1e4]): sampled entries of
-    three folds against the oracle, every fold against the FP64 GPU form."""
-    shape, (X, Y, fold) = G.workload(3)
-    print(f"[mixed] {mode} {shape.name}", flush=True)
-    Xd, Yd, fd = _t(X), _t(Y), _t(fold)
-    h64 = cv.cvgram_create(Xd, Yd, fd, 1, 1, 1, 1, mode="fp64")
-    hm = cv.cvgram_create(Xd, Yd, fd, 1, 1, 1, 1, mode=mode)
-    P = cv.cvgram_num_folds(hm)
-    K, M = X.shape[1], Y.shape[1]
+@pytest.mark.parametrize("mode", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("order", ["drift", "sorted"])
+def test_rows_ordered_by_a_covariate(mode, order):
+    """Offset columns (means in [1e3, 1e4]) whose rows are ordered by a
+    covariate: a drift along the rows of 40 column deviations end to end,
+    or all rows sorted by column 0.  The first rows then sit far from each
+    column's mean; the pivot is taken from rows spread over the whole
+    column, so the centred classes cancel no more than on shuffled rows.
+    Whole products against the oracle (relative Frobenius per fold x class)
+    and every entry against its Cauchy-Schwarz scale, at the mode's bar."""
+    from tests import sampling as S
+    n, k, m, p = 30000, 96, 4, 6
+    rng = np.random.default_rng(77)
+    mu = rng.uniform(1e3, 1e4, k)
+    sd = rng.uniform(0.1, 1.0, k)
+    z = rng.standard_normal((n, k))
+    if order == "drift":
+        z += 40.0 * (np.arange(n)[:, None] / n - 0.5)
+    X = (mu + sd * z).astype(np.float32)
+    if order == "sorted":
+        X = X[np.argsort(X[:, 0], kind="stable")]
+    W = rng.standard_normal((k, m)) / np.sqrt(k)
+    Y = (rng.uniform(1e3, 1e4, m) + ((X - mu) / sd) @ W
+         + 0.1 * rng.standard_normal((n, m))).astype(np.float32)
+    fold = G.folds_dirichlet(n, p, np.random.default_rng(78))
+    print(f"[mixed] {mode} rows ordered by {order} N={n} K={k}", flush=True)
+    P, (xx, xy) = _run(X, Y, fold, mode)
+    tol = 1e-10 if mode == "fp64" else MIXED_BOUND[mode]
     worst = 0.0
-    rng = np.random.default_rng(5)
-    for q0 in range(0, P, 25):
-        q1 = min(P, q0 + 25)
-        a64, b64 = cv.cvgram_folds_all(h64, q0, q1)
-        am, bm = cv.cvgram_folds_all(hm, q0, q1)
-        for q in range(q1 - q0):
-            for c in range(4):
-                ref = a64[q, c]
-                e = (torch.linalg.norm(am[q, c].double() - ref) / torch.linalg.norm(ref)).item()
-                worst = max(worst, e)
-                assert e <= MIXED_BOUND[mode], (mode, q0 + q, c, e)
-            for c in range(8):
-                ref = b64[q, c]
-                e = (torch.linalg.norm(bm[q, c].double() - ref) / torch.linalg.norm(ref)).item()
-                worst = max(worst, e)
-                assert e <= MIXED_BOUND[mode], (mode, q0 + q, c, e)
-        if q0 == 0:
-            am0, bm0 = am.cpu().numpy(), bm.cpu().numpy()
-    print(f"[mixed] {mode} full-size worst rel err vs FP64 GPU form {worst:.3e}", flush=True)
-    # sampled entries of fold 0 against the oracle (entry-wise, scaled by the
-    # class's largest entry)
-    pairs_xx = [(int(a), int(b)) for a, b in rng.integers(0, K, size=(10, 2))] + [(3, 3)]
-    pairs_xy = [(int(a), int(b)) for a, b in zip(rng.integers(0, K, 6), rng.integers(0, M, 6))]
-    for c in range(4):
-        ref, _ = O.fold_entries(X, Y, fold, 0, *O.XTX_CLASS_COMBO[c], 1, pairs_xx, [])
-        got = np.array([am0[0, c, i, j] for i, j in pairs_xx], np.float64)
-        assert np.max(np.abs(got - ref)) <= 10 * MIXED_BOUND[mode] * np.max(np.abs(am0[0, c])), c
-    for c in range(8):
-        _, ref = O.fold_entries(X, Y, fold, 0, *O.XTY_CLASS_COMBO[c], 1, [], pairs_xy)
-        got = np.array([bm0[0, c, i, j] for i, j in pairs_xy], np.float64)
-        assert np.max(np.abs(got - ref)) <= 10 * MIXED_BOUND[mode] * np.max(np.abs(bm0[0, c])), c
-    cv.cvgram_destroy(hm)
-    cv.cvgram_destroy(h64)
+    for q in range(P):
+        oxx, oxy = O.fold_all_classes(X, Y, fold, q, ddof=1)
+        d = {}
+        for c, (cx, sx, _, _) in O.XTX_CLASS_COMBO.items():
+            d[("x", cx, sx)] = np.diag(oxx[c])
+            e = _relerr(xx[q, c], oxx[c])
+            ew = S.entrywise_error(xx[q, c], oxx[c], np.sqrt(np.outer(np.diag(oxx[c]),
+                                                                     np.diag(oxx[c]))))
+            worst = max(worst, e, ew)
+            assert e <= tol and ew <= tol, (mode, order, "XtX", q, c, e, ew)
+        for c, (cx, sx, cy, sy) in O.XTY_CLASS_COMBO.items():
+            yy, _ = O.fold_products(Y, Y, fold, q, cy, sy, cy, sy, ddof=1)
+            scale = np.sqrt(np.outer(d[("x", cx, sx)], np.diag(yy)))
+            e = _relerr(xy[q, c], oxy[c])
+            ew = S.entrywise_error(xy[q, c], oxy[c], scale)
+            worst = max(worst, e, ew)
+            assert e <= tol and ew <= tol, (mode, order, "XtY", q, c, e, ew)
+    print(f"[mixed] {mode} {order}: worst {worst:.3e}", flush=True)

@@ -13,6 +13,7 @@ import pytest
 import paper_2401_13185_amd as cv
 from oracle import cv_oracle as O
 from synth import generators as G
+from tests import sampling as S
 
 pytestmark = pytest.mark.gpu
 
@@ -214,21 +215,17 @@ def test_fp64_spectra_full_size_sampled():
     xy = xy.cpu().numpy()
     rng = np.random.default_rng(0)
     K, M = X.shape[1], Y.shape[1]
-    for p in (0, 3, P - 1):
-        pairs_xx = [(int(a), int(b)) for a, b in rng.integers(0, K, size=(24, 2))] + [(0, 0), (K - 1, K - 1)]
-        pairs_xy = [(int(a), int(b)) for a, b in zip(rng.integers(0, K, 12), rng.integers(0, M, 12))]
-        for c in range(4):
-            combo = O.XTX_CLASS_COMBO[c]
-            ref, _ = O.fold_entries(X, Y, fold, p, *combo, 1, pairs_xx, [])
-            got = np.array([xx[p, c, i, j] for i, j in pairs_xx])
-            scale = np.max(np.abs(xx[p, c]))
-            assert np.max(np.abs(got - ref)) <= FP64_TOL * scale, (p, c)
-        for c in range(8):
-            combo = O.XTY_CLASS_COMBO[c]
-            _, ref = O.fold_entries(X, Y, fold, p, *combo, 1, [], pairs_xy)
-            got = np.array([xy[p, c, i, j] for i, j in pairs_xy])
-            scale = np.max(np.abs(xy[p, c]))
-            assert np.max(np.abs(got - ref)) <= FP64_TOL * scale, (p, c)
+    sizes = np.bincount(fold, minlength=P)
+    for p in sorted({0, 3, P - 1, int(np.argmin(sizes)), int(np.argmax(sizes))}):
+        # every entry among 16 X and 4 Y columns, against its Cauchy-Schwarz
+        # scale (tests/sampling.py)
+        xcols = S.pick_columns(K, 16, rng)
+        ycols = S.pick_columns(M, 4, rng)
+        res = S.compare_fold(xx[p][:, xcols][:, :, xcols], xy[p][:, xcols][:, :, ycols],
+                             X[:, xcols], Y[:, ycols], fold, p)
+        for kind in ("xtx", "xty"):
+            for c, (ew, fe) in enumerate(res[kind]):
+                assert ew <= FP64_TOL and fe <= FP64_TOL, (p, kind, c, ew, fe)
         # properties that hold at any size
         nt = int((fold != p).sum())
         assert np.array_equal(xx[p, 3], xx[p, 3].T)
@@ -240,6 +237,52 @@ def test_fp64_spectra_full_size_sampled():
         assert _relerr(xx[1, c], oxx[c]) <= FP64_TOL
     for c in range(8):
         assert _relerr(xy[1, c], oxy[c]) <= FP64_TOL
+    cv.cvgram_destroy(h)
+
+
+@pytest.mark.parametrize("mode", ["fp64", "bf16x3"])
+def test_not_scalable_partition_writes_nan_only_where_undefined(mode):
+    """Definition 6 fails: fold 0 holds all rows but one, so its training
+    partition has one row and no deviation with ddof = 1.  cvgram_folds_all
+    writes every class: fold 0's scaled classes are NaN, its unscaled ones
+    and every class of fold 1 are the oracle's.  The single-combination call
+    with scaling reports CVGRAM_ENOTSCALABLE."""
+    n, k, m = 40, 9, 2
+    rng = np.random.default_rng(66)
+    X = rng.normal(3.0, 1.0, (n, k))
+    Y = X[:, :m] + rng.normal(0, 0.2, (n, m))
+    fold = np.zeros(n, np.int32)
+    fold[17] = 1
+    h = cv.cvgram_create(_t(X), _t(Y), _t(fold), 1, 1, 1, 1, ddof=1, mode=mode)
+    xx, xy = cv.cvgram_folds_all(h, 0, 2)
+    torch.cuda.synchronize()
+    xx = xx.double().cpu().numpy()
+    xy = xy.double().cpu().numpy()
+    tol = FP64_TOL if mode == "fp64" else 2e-5
+    scaled_xx, scaled_xy = (1, 3), (1, 2, 3, 5, 6, 7)
+    for c in scaled_xx:
+        assert np.all(np.isnan(xx[0, c])), c
+    for c in scaled_xy:
+        assert np.all(np.isnan(xy[0, c])), c
+    # fold 0's unscaled classes (the oracle without scaling)
+    oxx, oxy = O.fold_all_classes(X, Y, fold, 0, ddof=1, scaling=False)
+    for c in (0, 2):
+        assert _relerr(xx[0, c], oxx[c]) <= tol, c
+    for c in (0, 4):
+        assert _relerr(xy[0, c], oxy[c]) <= tol, c
+    # fold 1 (39 training rows): every class.  Its training rows are those of
+    # fold 0 of a scalable relabelling (row 17 alone, the rest split in two),
+    # so the oracle computes them there.
+    relab = np.where(np.arange(n) % 2 == 0, 1, 2).astype(np.int32)
+    relab[17] = 0
+    oxx, oxy = O.fold_all_classes(X, Y, relab, 0, ddof=1)
+    for c in range(4):
+        assert _relerr(xx[1, c], oxx[c]) <= tol, c
+    for c in range(8):
+        assert _relerr(xy[1, c], oxy[c]) <= tol, c
+    with pytest.raises(cv.CVGramError) as ei:
+        cv.cvgram_fold_combo(h, 1, 1, 1, 1, 1)
+    assert ei.value.name == "CVGRAM_ENOTSCALABLE"
     cv.cvgram_destroy(h)
 
 
