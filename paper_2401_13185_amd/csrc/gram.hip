@@ -23,8 +23,14 @@
 //   BF16X3  v_mfma_f32_16x16x32_bf16, three products hi*hi + hi*lo + lo*hi
 //           per FP32 product from the hi/lo bf16 panels.
 // The FP32-accumulating modes add their FP32 tile into an FP64 register
-// tile every 256 rows and clear it, so FP32 rounding does not grow with the
-// fold size.
+// tile and clear it every 64 rows (FP32: 16 accumulating MFMAs) or 256 rows
+// (BF16X3: 24, each summing 32 products), so FP32 rounding does not grow
+// with the fold size.  The accumulated rounding error of a block is about
+// half an FP32 ulp per accumulating step, and it does not average out on
+// entries that sum positive products (the diagonal).  On the offset data
+// of the precision-stress workload (N=1e6, K=1024) the FP32 mode's worst
+// entry against its Cauchy-Schwarz scale was 1.9e-6 with a flush every 256
+// rows and is 4.9e-7 with one every 64 (the Gram 6 % slower).
 //
 // Pipelining.  FP64 / FP32: LDS double buffer; the next stage's panel block
 // is loaded into registers while the current stage runs on the matrix cores;
@@ -50,7 +56,7 @@ typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 
 constexpr int kThreads = 256;
 constexpr int kYW = kYDiagCols;    // Y columns handled inside diagonal tiles (32)
-constexpr int kFlushRows = 256;
+constexpr int kFlushRowsBf16 = 256;   // rows between FP64 flushes (BF16X3)
 // row steps of 4 rows each wave keeps in flight in the direct FP64 loop
 constexpr int kDirectDepth = 4;
 // the loop runs kDirectDepth steps per pass over an item's kPanelRows / 4
@@ -72,7 +78,9 @@ struct Mode<CVGRAM_MODE_FP32> {
   typedef float4_t Acc;
   static constexpr int BK = 16;
   static constexpr int PAD = 16;      // rows of 144 / 80 floats: the 4 row groups of a
-};                                    // fragment read fall in different banks
+                                      // fragment read fall in different banks
+  static constexpr int FLUSH = 64;    // rows between FP64 flushes
+};
 template <>
 struct Mode<CVGRAM_MODE_BF16X3> {
   typedef __bf16 E;
@@ -409,7 +417,7 @@ __global__ __launch_bounds__(kThreads) void gram_kernel(const ProbDesc* __restri
   auto flush = [&]() {
     if constexpr (!kF64) {
       since += BK;
-      if (since >= kFlushRows) {
+      if (since >= Mode<CVGRAM_MODE_FP32>::FLUSH) {
         since = 0;
 #pragma unroll
         for (int i = 0; i < NACC; ++i) {
@@ -678,7 +686,7 @@ __global__ __launch_bounds__(kThreads) void gram_bf16_kernel(const ProbDesc* __r
 
   auto flush = [&]() {
     since += 32;
-    if (since >= kFlushRows) {
+    if (since >= kFlushRowsBf16) {
       since = 0;
 #pragma unroll
       for (int i = 0; i < NACC; ++i) {

@@ -253,7 +253,11 @@ def test_not_scalable_partition_writes_nan_only_where_undefined(mode):
     Y = X[:, :m] + rng.normal(0, 0.2, (n, m))
     fold = np.zeros(n, np.int32)
     fold[17] = 1
-    h = cv.cvgram_create(_t(X), _t(Y), _t(fold), 1, 1, 1, 1, ddof=1, mode=mode)
+    # a handle asked for a scaled combination is refused (Definition 6)
+    with pytest.raises(cv.CVGramError) as ei:
+        cv.cvgram_create(_t(X), _t(Y), _t(fold), 1, 1, 1, 1, ddof=1, mode=mode)
+    assert ei.value.name == "CVGRAM_ENOTSCALABLE"
+    h = cv.cvgram_create(_t(X), _t(Y), _t(fold), 1, 0, 1, 0, ddof=1, mode=mode)
     xx, xy = cv.cvgram_folds_all(h, 0, 2)
     torch.cuda.synchronize()
     xx = xx.double().cpu().numpy()
