@@ -210,6 +210,35 @@ cvgram_status cvgram_fold_combo(cvgram_t h, int32_t p, int center_x, int scale_x
 cvgram_status cvgram_folds_all(cvgram_t h, int32_t p_begin, int32_t p_end,
                                void* out_XtX, void* out_XtY);
 
+/* For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc): cvgram_create + cvgram_folds_all(h, 0, P)
+ * + cvgram_destroy in one call whose workspace is a fixed scratch array of
+ * CVGRAM_NOALLOC_SCRATCH_BYTES that every device the library runs on holds
+ * from module load until the process ends; host staging (label counts, the
+ * launch plan) is a fixed 16 MiB host buffer.  It calls no hipMalloc,
+ * hipHostMalloc, hipFree and creates no event.
+ *   X, Y, fold_id, N, K, M, dtype, ddof, mode: as cvgram_create (every class
+ *            is computed, so there are no centering/scaling flags).
+ *   P        the number of folds the labels give (largest label + 1);
+ *            CVGRAM_EFOLDS if they give another (or violate Definition 1).
+ *   out_XtX  device [P][4][K][K], out_XtY device [P][8][K][M] (either may be
+ *            NULL): every fold's classes as cvgram_folds_all(h, 0, P) writes
+ *            them, bit-identical to it.
+ * Waits once for the label counts (as cvgram_create does), then returns with
+ * the pipeline queued on `stream`.  A problem whose workspace does not fit
+ * the scratch (or whose plan exceeds the host staging) returns
+ * CVGRAM_EINVAL, with the sizes in cvgram_last_error_message(), before any
+ * Gram work is queued.  Every call on a device shares that device's scratch:
+ * calls are serialised on the host, and calls on one device whose device
+ * work may overlap (different streams without ordering between them) race;
+ * calls on one stream are ordered.  The pipeline initialises every scratch
+ * location it reads, so nothing has to start at zero. */
+#define CVGRAM_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+cvgram_status cvgram_folds_all_noalloc(const void* X, const void* Y, const int32_t* fold_id,
+                                       int64_t N, int64_t K, int64_t M, cvgram_dtype dtype,
+                                       int ddof, cvgram_mode mode, int32_t P, void* stream,
+                                       void* out_XtX, void* out_XtY);
+
 /* Training-partition statistics of fold p in FP64: column means
  * (Definition 2) and deviations with divisor |T_p| - ddof (Definition 4);
  * a column constant over T_p reports deviation 1 (Algorithm 7 step 24).

@@ -16,7 +16,8 @@ import re
 __all__ = [
     "CVGramError", "lib_path", "load", "exported_symbols", "header_symbols",
     "cvgram_create", "cvgram_num_folds", "cvgram_plan_info", "cvgram_partition", "cvgram_fold",
-    "cvgram_fold_combo", "cvgram_fold_leaky", "LEAK_KINDS", "cvgram_ridge", "cvgram_folds_all", "cvgram_fold_stats", "cvgram_set_stream",
+    "cvgram_fold_combo", "cvgram_fold_leaky", "LEAK_KINDS", "cvgram_ridge", "cvgram_folds_all",
+    "cvgram_folds_all_noalloc", "cvgram_fold_stats", "cvgram_set_stream",
     "cvgram_destroy", "cvgram_status_string", "cvgram_last_error_message", "cvgram_version",
     "cvgram_set_stage_timing", "cvgram_stage_times", "cvgram_trim_cache",
     "cvgram_batch_create", "cvgram_batch_run", "cvgram_batch_run_eager",
@@ -65,6 +66,8 @@ _SIGS = {
     "cvgram_fold_leaky": (_int, [_vp, _i32, _int, _vp, _vp]),
     "cvgram_ridge": (_int, [_vp, _i32, _i32, ctypes.POINTER(ctypes.c_double), _i32, _vp]),
     "cvgram_folds_all": (_int, [_vp, _i32, _i32, _vp, _vp]),
+    "cvgram_folds_all_noalloc": (_int, [_vp, _vp, _vp, _i64, _i64, _i64, _int, _int, _int, _i32,
+                                        _vp, _vp, _vp]),
     "cvgram_fold_stats": (_int, [_vp, _i32, _vp, _vp, _vp, _vp]),
     "cvgram_set_stream": (_int, [_vp, _vp]),
     "cvgram_destroy": (_int, [_vp]),
@@ -288,6 +291,33 @@ def cvgram_folds_all(h: Handle, p_begin: int, p_end: int, out_XtX=None, out_XtY=
     yp = (_ptr(out_XtY, "out_XtY", h.out_dtype, n * XTY_CLASSES * h.K * h.M)
           if (out_XtY is not None and out_XtY is not False) else None)
     _check(load().cvgram_folds_all(h.ptr, int(p_begin), int(p_end), xp, yp))
+    return out_XtX, out_XtY
+
+
+def cvgram_folds_all_noalloc(X, Y, fold_id, P, out_XtX, out_XtY, ddof=1, mode="fp64",
+                             stream=None):
+    """Every fold's 12 classes into caller-owned outputs, with the library's
+    fixed scratch as workspace (no device allocation by the library).
+    out_XtX: [P][4][K][K], out_XtY: [P][8][K][M] (or None), FP64 in mode
+    fp64 and FP32 otherwise."""
+    torch = _torch()
+    if X.dim() != 2:
+        raise ValueError("X must be N x K")
+    N, K = X.shape
+    M = 0 if Y is None else Y.shape[1]
+    if Y is not None and (Y.dim() != 2 or Y.shape[0] != N or Y.dtype != X.dtype):
+        raise ValueError("Y must be N x M with X's dtype")
+    if X.dtype not in (torch.float32, torch.float64):
+        raise TypeError("X must be float32 or float64")
+    if mode not in MODES:
+        raise ValueError(f"mode must be one of {sorted(MODES)}")
+    od = torch.float64 if mode == "fp64" else torch.float32
+    xp = _ptr(out_XtX, "out_XtX", od, int(P) * XTX_CLASSES * K * K)
+    yp = _ptr(out_XtY, "out_XtY", od, int(P) * XTY_CLASSES * K * M) if M > 0 else None
+    _check(load().cvgram_folds_all_noalloc(
+        _ptr(X, "X"), _ptr(Y, "Y") if M > 0 else None, _ptr(fold_id, "fold_id", torch.int32, N),
+        N, K, M, 1 if X.dtype == torch.float64 else 0, int(ddof), MODES[mode], int(P),
+        _stream_ptr(stream), xp, yp))
     return out_XtX, out_XtY
 
 

@@ -142,14 +142,43 @@ struct Block {
   bool host = false;
 };
 
+// Fixed memory of the allocation-free entry point: device blocks are carved
+// in order from the library's static scratch array (through its device
+// address), host staging from a static host buffer.  Nothing is allocated,
+// and giving blocks back is a no-op; a request beyond either region fails.
+struct Arena {
+  char* dev = nullptr;
+  size_t dev_cap = 0, dev_used = 0;
+  char* host = nullptr;
+  size_t host_cap = 0, host_used = 0;
+
+  void* take(bool on_host, size_t want) {
+    char* base = on_host ? host : dev;
+    size_t& used = on_host ? host_used : dev_used;
+    const size_t cap = on_host ? host_cap : dev_cap;
+    if (want > cap - used) {
+      set_error(std::string("the allocation-free entry point needs more ") +
+                (on_host ? "host staging" : "device workspace") + " than its fixed " +
+                std::to_string(cap >> 20) + " MiB (" + std::to_string(used + want) +
+                " bytes asked for): use cvgram_create for this problem");
+      throw Fail{CVGRAM_EINVAL};
+    }
+    void* p = base + used;
+    used += want;
+    return p;
+  }
+};
+
 struct Owned {
   int device = 0;
   hipStream_t stream = nullptr;  // the stream the owner's work runs on
   std::vector<Block> blocks;
+  Arena* arena = nullptr;        // set: every block comes from it
 
   void* dev(size_t want) {
     want = (want + 255) / 256 * 256;
     if (want == 0) want = 256;
+    if (arena) return arena->take(false, want);
     size_t got = want;
     Taken tk;
     {
@@ -184,6 +213,7 @@ struct Owned {
   void* pinned(size_t want) {
     want = (want + 4095) / 4096 * 4096;
     if (want == 0) want = 4096;
+    if (arena) return arena->take(true, want);
     size_t got = want;
     Taken tk;
     {
@@ -532,6 +562,10 @@ cvgram_status bookkeeping(Batch& b) {
   Owned scratch;
   scratch.device = b.device;
   scratch.stream = s;
+  scratch.arena = b.mem.arena;
+  // the host's wait for the label counts: an event, or (fixed memory, where
+  // no event is created) the whole stream
+  const bool wait_stream = b.mem.arena != nullptr;
   // info[0] min label, info[1] max label, info[2 ..) counts of labels below
   // kCountLabels, then flags: one block, one initialising launch, one copy.
   // The block stays with the batch: the sort's scan reads the counts after
@@ -548,7 +582,7 @@ cvgram_status bookkeeping(Batch& b) {
   int64_t* offs = (int64_t*)b.mem.dev((size_t)(maxN + 1) * sizeof(int64_t));
   int32_t* hbuf = (int32_t*)scratch.pinned(kInfo * sizeof(int32_t));
   int32_t* hcounts = hbuf + 2;
-  if (!b.ev_wait) b.ev_wait = event_get(b.device, false);
+  if (!b.ev_wait && !wait_stream) b.ev_wait = event_get(b.device, false);
   cvgram_status st = CVGRAM_OK;
   int64_t at = 0;
   try {
@@ -561,7 +595,7 @@ cvgram_status bookkeeping(Batch& b) {
       launch_label_count(p.fold, p.N, info, counts, hist, s);
       CVG_HIP(hipMemcpyAsync(hbuf, info, (2 + kCountLabels) * sizeof(int32_t),
                              hipMemcpyDeviceToHost, s));
-      CVG_HIP(hipEventRecord(b.ev_wait, s));
+      if (!wait_stream) CVG_HIP(hipEventRecord(b.ev_wait, s));
       if (!b.batched) {
         // the pivots need only X and Y: they run while the host waits for the
         // counts and plans (a batch computes them inside its graph instead)
@@ -577,7 +611,10 @@ cvgram_status bookkeeping(Batch& b) {
       constexpr int kEarlyBits = 8;
       radix_partition(p.fold, p.N, kEarlyBits, counts, keys, keys + maxN, p.d_perm, perm_tmp,
                       hist, true, &sorted, s);
-      CVG_HIP(hipEventSynchronize(b.ev_wait));
+      if (wait_stream)
+        CVG_HIP(hipStreamSynchronize(s));
+      else
+        CVG_HIP(hipEventSynchronize(b.ev_wait));
       if (hbuf[0] < 0) {
         st = fail(CVGRAM_EFOLDS, tag + "fold label < 0 (Definition 1)");
         break;
@@ -1240,15 +1277,37 @@ namespace {
 
 bool out_is_f64(const Batch& b) { return b.mode == CVGRAM_MODE_FP64; }
 
-cvgram_status correct_single(cvgram_t h, int32_t p0, int32_t p1, const OutDesc& od) {
-  const ProbDesc& d = h->b.h_pd[0];
+cvgram_status correct_single(const Batch& b, int32_t p0, int32_t p1, const OutDesc& od) {
+  const ProbDesc& d = b.h_pd[0];
   try {
-    launch_correct_single(h->b.d_pd, 0, d.n_ctiles_xx + d.n_ctiles_xy, od, p1 - p0,
-                          out_is_f64(h->b), h->b.stream);
+    launch_correct_single(b.d_pd, 0, d.n_ctiles_xx + d.n_ctiles_xy, od, p1 - p0,
+                          out_is_f64(b), b.stream);
   } catch (const Fail& f) {
     return f.st;
   }
   return CVGRAM_OK;
+}
+cvgram_status correct_single(cvgram_t h, int32_t p0, int32_t p1, const OutDesc& od) {
+  return correct_single(h->b, p0, p1, od);
+}
+
+// outputs of every class of folds p_begin, p_begin + 1, ...:
+// [fold][class][K][K] and [fold][class][K][M]; scaled classes of folds with
+// |T_p| - ddof < 1 come out NaN
+OutDesc all_classes_out(const Batch& b, int32_t p_begin, void* out_XtX, void* out_XtY) {
+  const ProbPlan& pp = b.pp[0];
+  OutDesc od;
+  std::memset(&od, 0, sizeof(od));
+  const size_t es = out_is_f64(b) ? sizeof(double) : sizeof(float);
+  const int64_t KK = pp.K * pp.K, KM = pp.K * pp.M;
+  for (int c = 0; c < CVGRAM_XTX_CLASSES; ++c)
+    od.xx[c] = out_XtX ? (char*)out_XtX + c * KK * es : nullptr;
+  for (int c = 0; c < CVGRAM_XTY_CLASSES; ++c)
+    od.xy[c] = (out_XtY && pp.M > 0) ? (char*)out_XtY + c * KM * es : nullptr;
+  od.fold_stride_xx = CVGRAM_XTX_CLASSES * KK;
+  od.fold_stride_xy = CVGRAM_XTY_CLASSES * KM;
+  od.p_begin = p_begin;
+  return od;
 }
 
 }  // namespace
@@ -1449,19 +1508,7 @@ cvgram_status cvgram_folds_all(cvgram_t h, int32_t p_begin, int32_t p_end, void*
   if (p_begin < 0 || p_end > pp.P || p_begin > p_end)
     return fail(CVGRAM_ERANGE, "fold range out of bounds");
   if (p_begin == p_end) return CVGRAM_OK;
-  OutDesc od;
-  std::memset(&od, 0, sizeof(od));
-  const size_t es = out_is_f64(h->b) ? sizeof(double) : sizeof(float);
-  const int64_t KK = pp.K * pp.K, KM = pp.K * pp.M;
-  // every class; scaled classes of folds with |T_p| - ddof < 1 are NaN
-  for (int c = 0; c < CVGRAM_XTX_CLASSES; ++c)
-    od.xx[c] = out_XtX ? (char*)out_XtX + c * KK * es : nullptr;
-  for (int c = 0; c < CVGRAM_XTY_CLASSES; ++c)
-    od.xy[c] = (out_XtY && pp.M > 0) ? (char*)out_XtY + c * KM * es : nullptr;
-  od.fold_stride_xx = CVGRAM_XTX_CLASSES * KK;
-  od.fold_stride_xy = CVGRAM_XTY_CLASSES * KM;
-  od.p_begin = p_begin;
-  return correct_single(h, p_begin, p_end, od);
+  return correct_single(h->b, p_begin, p_end, all_classes_out(h->b, p_begin, out_XtX, out_XtY));
 }
 
 cvgram_status cvgram_fold_stats(cvgram_t h, int32_t p, double* mean_x, double* std_x,
@@ -1736,6 +1783,105 @@ cvgram_status cvgram_autotune(const void* X, const void* Y, const int32_t* fold_
   if (tile) *tile = best.tile;
   if (target_items) *target_items = (int32_t)best.target_items;
   return CVGRAM_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// allocation-free form: fixed device scratch and host staging
+// ---------------------------------------------------------------------------
+// The device scratch is a file-scope array: each device the library runs on
+// holds its own copy from module load until the process ends.  In host code
+// its name is only a stand-in; its device address comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+static __device__ __align__(256) unsigned char scratch[CVGRAM_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr size_t kNoallocHostBytes = (size_t)16 << 20;
+alignas(4096) unsigned char g_noalloc_host[kNoallocHostBytes];
+// one call at a time uses the host staging (device work of calls on one
+// device still races unless stream-ordered; see the header)
+std::mutex g_noalloc_mu;
+void* g_scratch_ptr[kMaxDev] = {};
+
+// device address of this device's scratch array (device current)
+void* scratch_address(int device) {
+  if (device < 0 || device >= kMaxDev) {
+    set_error("device index out of range");
+    throw Fail{CVGRAM_EDEVICE};
+  }
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      set_error(std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+      throw Fail{CVGRAM_EDEVICE};
+    }
+    g_scratch_ptr[device] = ptr;
+  }
+  return g_scratch_ptr[device];
+}
+
+}  // namespace
+
+extern "C" {
+
+cvgram_status cvgram_folds_all_noalloc(const void* X, const void* Y, const int32_t* fold_id,
+                                       int64_t N, int64_t K, int64_t M, cvgram_dtype dtype,
+                                       int ddof, cvgram_mode mode, int32_t P, void* stream,
+                                       void* out_XtX, void* out_XtY) {
+  set_error("");
+  cvgram_status st = check_problem(X, Y, fold_id, N, K, M);
+  if (st != CVGRAM_OK) return st;
+  if (dtype != CVGRAM_F32 && dtype != CVGRAM_F64) return fail(CVGRAM_EINVAL, "bad dtype");
+  if (mode != CVGRAM_MODE_FP64 && mode != CVGRAM_MODE_FP32 && mode != CVGRAM_MODE_BF16X3)
+    return fail(CVGRAM_EINVAL, "bad mode");
+  if (ddof != 0 && ddof != 1) return fail(CVGRAM_EINVAL, "ddof must be 0 or 1");
+  if (P < 2 || P > N) return fail(CVGRAM_EINVAL, "need 2 <= P <= N");
+  std::lock_guard<std::mutex> g(g_noalloc_mu);
+  Arena arena;
+  Batch b;
+  b.stream = (hipStream_t)stream;
+  b.mode = mode;
+  b.dtype = dtype;
+  b.ddof = ddof;
+  b.batched = false;
+  b.timing = false;
+  b.mem.arena = &arena;
+  ProbPlan p;
+  p.X = X;
+  p.Y = M > 0 ? Y : nullptr;
+  p.fold = fold_id;
+  p.N = N;
+  p.K = K;
+  p.M = M;
+  p.W = K + M;
+  b.pp.push_back(p);
+  try {
+    CVG_HIP(hipGetDevice(&b.device));
+    arena.dev = (char*)scratch_address(b.device);
+    arena.dev_cap = CVGRAM_NOALLOC_SCRATCH_BYTES;
+    arena.host = (char*)g_noalloc_host;
+    arena.host_cap = kNoallocHostBytes;
+    st = prepare(b);
+    if (st == CVGRAM_OK && b.pp[0].P != P)
+      st = fail(CVGRAM_EFOLDS, "the labels give " + std::to_string(b.pp[0].P) +
+                                   " folds, not the P passed");
+    if (st == CVGRAM_OK) {
+      run_pipeline(b, false);
+      st = correct_single(b, 0, P, all_classes_out(b, 0, out_XtX, out_XtY));
+    }
+  } catch (const Fail& f) {
+    st = f.st;
+  }
+  // the staging buffer is reused by the next call: every copy that reads it
+  // has been consumed (pageable uploads are staged before the call
+  // returns); on an error the device work is waited for
+  if (st != CVGRAM_OK) (void)hipStreamSynchronize(b.stream);
+  b.release();
+  return st;
 }
 
 const char* cvgram_status_string(cvgram_status s) {
