@@ -72,10 +72,23 @@ def f_exec(n, k, m, mode, tile=None):
     whole tiles above the diagonal; on a diagonal tile, FP64 / FP32 with
     128-wide tiles compute the 36 upper-triangle 16 x 16 blocks of 64 and
     one (M <= 16) or two (M <= 32) 16-column K x M blocks per block row,
-    otherwise (BF16X3, 64-wide tiles) three waves of four take the upper
-    quadrants and the fourth a 32-column K x M block; M > 32 uses separate
-    K x M tiles.  Three bf16 products per product in BF16X3."""
+    otherwise (BF16X3, 64- and 128-wide tiles) three waves of four take the
+    upper quadrants and the fourth a 32-column K x M block; M > 32 uses
+    separate K x M tiles.  BF16X3 256 x 128 tiles (pairs of 128-wide row
+    blocks over a 128-wide column block): full pairs off the diagonal, the
+    upper 128 x 128 plus a 256 x 32 K x M block (M <= 32) on the pairs whose
+    lower half is below it, 256 x 128 K x M tiles for M > 32.  Three bf16
+    products per product in BF16X3."""
     T = tile or (64 if k <= 64 else 128)
+    rep = 3 if mode == "bf16x3" else 1
+    if T == 256:
+        na = -(-k // 256)
+        entries = na * na * 256 * 128 + na * 128 * 128
+        if 0 < m <= 32:
+            entries += na * 256 * 32
+        if m > 32:
+            entries += na * (-(-m // 128)) * 256 * 128
+        return 2 * n * entries * rep
     nt = -(-k // T)
     pairs = T == 128 and mode != "bf16x3"
     entries = (nt * (nt + 1) // 2 - nt) * T * T
@@ -89,13 +102,17 @@ def f_exec(n, k, m, mode, tile=None):
             entries += nt * T * 32
     if m > 32:
         entries += nt * (-(-m // T)) * T * T
-    return 2 * n * entries * (3 if mode == "bf16x3" else 1)
+    return 2 * n * entries * rep
 
 
-def gram_kernel_name(mode, k):
-    tile = 64 if k <= 64 else 128
-    return {"fp64": f"gram_kernel<0, {tile}>", "fp32": f"gram_kernel<2, {tile}>",
-            "bf16x3": f"gram_bf16_kernel<{tile}>"}[mode]
+def gram_kernel_name(mode, tile, f32_input):
+    """The Gram kernel the library launches (as rocprofv3 names it): FP64
+    mode keeps FP32 input in FP32 panels (third template argument)."""
+    if mode == "bf16x3":
+        return "gram_bf16_wide_kernel" if tile == 256 else f"gram_bf16_kernel<{tile}>"
+    if mode == "fp64":
+        return f"gram_kernel<0, {tile}, {'true' if f32_input else 'false'}>"
+    return f"gram_kernel<2, {tile}, false>"
 
 
 def parse(argv=None):
@@ -166,7 +183,8 @@ def blas_threads():
 def time_steps(cv, torch, Xd, Yd, fd, P, K, M, mode, steps, warmup, chunk, stages_inline):
     """Time `steps` whole steps after `warmup`: create + every fold's 12
     classes (folds_all in chunks of `chunk` folds) + destroy.  Returns
-    (ms per step, per-stage ms).  With `stages_inline` the library's HIP
+    (ms per step, per-stage ms, the plan of cvgram_plan_info).  With
+    `stages_inline` the library's HIP
     events are on during the timed steps themselves (each step reads its
     stage times once its Gram and reduction are done, while its corrections
     run); otherwise the timed steps run back to back with no host wait and
@@ -178,8 +196,12 @@ def time_steps(cv, torch, Xd, Yd, fd, P, K, M, mode, steps, warmup, chunk, stage
     xy = torch.empty(CH, 8, K, M, dtype=odt, device=dev)
     stream = torch.cuda.current_stream()
 
+    plan = {}
+
     def step(timing, ev=None):
         h = cv.cvgram_create(Xd, Yd, fd, 1, 1, 1, 1, ddof=1, mode=mode, stream=stream)
+        if timing and not plan:
+            plan.update(cv.cvgram_plan_info(h))
         if ev is not None:
             ev[0].record(stream)
         for p0 in range(0, P, CH):
@@ -223,17 +245,17 @@ def time_steps(cv, torch, Xd, Yd, fd, P, K, M, mode, steps, warmup, chunk, stage
     stage_ms = {k: float(np.mean([s[k] for s in sts])) for k in sts[0]}
     stage_ms["gram_min"] = float(np.min([s["gram"] for s in sts]))
     stage_ms["gram_max"] = float(np.max([s["gram"] for s in sts]))
-    return (t1 - t0) * 1e3 / steps, stage_ms
+    return (t1 - t0) * 1e3 / steps, stage_ms, plan
 
 
-def roofline(mode, n, k, m, stage_ms, workload):
+def roofline(mode, n, k, m, stage_ms, workload, tile, f32_input):
     g = f_alg(n, k, m) / (stage_ms["gram"] * 1e-3) / 1e12
-    kname = gram_kernel_name(mode, k)
+    kname = gram_kernel_name(mode, tile, f32_input)
     return {"bound": "mfma", "kernel": kname, "achieved": g, "peak": PEAK[mode],
             "unit": "TFLOP/s", "frac": g / PEAK[mode],
             "traffic": profiled_traffic(kname, workload),
             "flops_per_launch": f_alg(n, k, m), "launch_ms": stage_ms["gram"],
-            "executed_tflops": f_exec(n, k, m, mode) / (stage_ms["gram"] * 1e-3) / 1e12}
+            "executed_tflops": f_exec(n, k, m, mode, tile) / (stage_ms["gram"] * 1e-3) / 1e12}
 
 
 # ---------------------------------------------------------------------------
@@ -437,12 +459,14 @@ def headline_block(cv, torch, G, dev, args):
         main = mode == args.headline_mode
         steps = args.steps if main else max(3, args.mixed_steps)
         warm = args.warmup if main else 1
-        ms, st = time_steps(cv, torch, X, Y, fd, P, K, M, mode, steps, warm, HEADLINE_CHUNK,
-                            stages_inline=True)
+        ms, st, plan = time_steps(cv, torch, X, Y, fd, P, K, M, mode, steps, warm,
+                                  HEADLINE_CHUNK, stages_inline=True)
         res["modes"][mode] = {"steps": steps, "warmup": warm, "ms_per_step": ms,
                               "sets_per_s": P * 12 / (ms * 1e-3),
                               "tflops_alg": f_alg(N, K, M) / (ms * 1e-3) / 1e12,
-                              "stage_ms": st, "roofline": roofline(mode, N, K, M, st, workload)}
+                              "stage_ms": st, "plan": plan,
+                              "roofline": roofline(mode, N, K, M, st, workload, plan["tile"],
+                                                   True)}
         log(f"large problem {mode}: {ms:.1f} ms/step, Gram {st['gram']:.1f} ms")
     f64, b16 = res["modes"]["fp64"], res["modes"]["bf16x3"]
     b16["speedup_vs_fp64"] = f64["ms_per_step"] / b16["ms_per_step"]
@@ -497,11 +521,12 @@ def spectra_block(cv, torch, G, dev, args):
     N, K, M, P = shape.n, shape.k, shape.m, shape.p
     log(f"workload {shape.name} generated")
     Xd, Yd, fd = (torch.from_numpy(a).to(dev) for a in (X, Y, fold))
-    ms, st = time_steps(cv, torch, Xd, Yd, fd, P, K, M, "fp64", args.steps, args.warmup, P,
-                        stages_inline=False)
+    ms, st, plan = time_steps(cv, torch, Xd, Yd, fd, P, K, M, "fp64", args.steps, args.warmup, P,
+                              stages_inline=False)
     out = {"workload": shape.name, "ms_per_step": ms, "sets_per_s": P * 12 / (ms * 1e-3),
-           "tflops_alg": f_alg(N, K, M) / (ms * 1e-3) / 1e12, "stage_ms": st,
-           "roofline": roofline("fp64", N, K, M, st, shape.name),
+           "tflops_alg": f_alg(N, K, M) / (ms * 1e-3) / 1e12, "stage_ms": st, "plan": plan,
+           "roofline": roofline("fp64", N, K, M, st, shape.name, plan["tile"],
+                                Xd.dtype == torch.float32),
            "hbm": stage_bandwidth(N, K, M, P, X.itemsize, "fp64", st)}
     log("spectra timed steps done")
     if not args.no_check or not args.no_cpu:
@@ -573,11 +598,11 @@ def mixed_block(cv, torch, G, dev, args):
     del X, Y
     res = {"workload": shape.name, "classes_per_fold": 12, "modes": {}}
     for mode in ("fp64", "fp32", "bf16x3"):
-        ms, st = time_steps(cv, torch, Xd, Yd, fd, P, K, M, mode, args.mixed_steps, 1, 25,
-                            stages_inline=True)
-        rl = roofline(mode, N, K, M, st, shape.name)
+        ms, st, plan = time_steps(cv, torch, Xd, Yd, fd, P, K, M, mode, args.mixed_steps, 1, 25,
+                                  stages_inline=True)
+        rl = roofline(mode, N, K, M, st, shape.name, plan["tile"], Xd.dtype == torch.float32)
         res["modes"][mode] = {"sets_per_s": P * 12 / (ms * 1e-3), "ms_per_step": ms,
-                              "stage_ms": st, "roofline": rl}
+                              "stage_ms": st, "plan": plan, "roofline": rl}
         log(f"mixed-block mode {mode}: {ms:.2f} ms/step, Gram {st['gram']:.2f} ms")
     f64 = res["modes"]["fp64"]["ms_per_step"]
     for mode in ("fp32", "bf16x3"):
@@ -607,12 +632,43 @@ def mixed_block(cv, torch, G, dev, args):
     return res
 
 
+def log2_bucket(v):
+    """Smallest b with 2**b >= v (the autotuning table's rounding)."""
+    b = 0
+    while (1 << b) < v and b < 62:
+        b += 1
+    return b
+
+
+def autotune_batch(cv, torch, probs, shapes, mode):
+    """cvgram_autotune on the first problem of every shape bucket the batch's
+    problems fall in (the tuning table's key: mode, dtype, and K, M + 1 and N
+    rounded up to powers of two); cvgram_batch_create then takes each
+    problem's Gram tile edge and work-list size from the table."""
+    t0 = time.perf_counter()
+    tuned = {}
+    per_problem = []
+    for (X, Y, f), s in zip(probs, shapes):
+        key = (log2_bucket(s.k), log2_bucket(s.m + 1), log2_bucket(s.n))
+        if key not in tuned:
+            tuned[key] = cv.cvgram_autotune(X, Y, f, mode=mode)
+        per_problem.append(tuned[key])
+    torch.cuda.synchronize()
+    tiles, items = {}, {}
+    for tile, it in per_problem:
+        tiles[str(tile)] = tiles.get(str(tile), 0) + 1
+        items[str(it)] = items.get(str(it), 0) + 1
+    return {"buckets": len(tuned), "seconds": round(time.perf_counter() - t0, 2),
+            "problems_by_tile": tiles, "problems_by_target_items": items}
+
+
 def batched_block(cv, torch, G, dev, args):
     """256 independent problems of different N, K, M, P (spectra, FP32,
-    Dirichlet(2) folds) in one batch: the whole pipeline (12 classes per
-    fold) captured in a HIP graph, replayed `batch_steps` times, FP64 and
-    bf16x3 on the same inputs; bf16x3's worst relative Frobenius error
-    against FP64 over every problem, fold and class."""
+    Dirichlet(2) folds) in one batch: the Gram launch autotuned per shape
+    bucket, the whole pipeline (12 classes per fold) captured in a HIP graph,
+    replayed `batch_steps` times, FP64 and bf16x3 on the same inputs;
+    bf16x3's worst relative Frobenius error against FP64 over every problem,
+    fold and class."""
     shapes = G.batch_shapes(256)
     probs = [G.batch_problem_device(s, i, dev) for i, s in enumerate(shapes)]
     torch.cuda.synchronize()
@@ -625,6 +681,8 @@ def batched_block(cv, torch, G, dev, args):
            "f_alg_total": flops, "modes": {}}
     outs = {}
     for mode in ("fp64", "bf16x3"):
+        tune = autotune_batch(cv, torch, probs, shapes, mode)
+        log(f"batched mode {mode}: autotuned {tune['buckets']} shape buckets in {tune['seconds']} s")
         t0 = time.perf_counter()
         b = cv.cvgram_batch_create(probs, ddof=1, mode=mode)
         torch.cuda.synchronize()
@@ -641,7 +699,7 @@ def batched_block(cv, torch, G, dev, args):
         ms = e0.elapsed_time(e1) / args.batch_steps
         res["modes"][mode] = {"ms_per_step": ms, "sets_per_s": n_sets / (ms * 1e-3),
                               "tflops_alg": flops / (ms * 1e-3) / 1e12,
-                              "plan_seconds": round(t_plan, 3)}
+                              "plan_seconds": round(t_plan, 3), "autotune": tune}
         outs[mode] = b
         log(f"batched mode {mode}: {ms:.2f} ms per replay")
     if not args.no_check:

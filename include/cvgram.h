@@ -318,8 +318,9 @@ cvgram_status cvgram_batch_problem_info(cvgram_batch_t b, int32_t i, int32_t* P,
 cvgram_status cvgram_batch_destroy(cvgram_batch_t b);
 
 /* ---------------------------------------------------------------------------
- * Autotuner of the grouped Gram launch.  Times the candidate tile edges (64,
- * 128) and work-list sizes on the given problem (device data as in
+ * Autotuner of the grouped Gram launch.  Times the candidate tile widths (64,
+ * 128, and in CVGRAM_MODE_BF16X3 the 256 x 128 tiles when K > 128) and
+ * work-list sizes on the given problem (device data as in
  * cvgram_create), records the fastest in a process-wide table keyed by
  * (mode, dtype, K, M and N rounded to powers of two), and returns it.  Later
  * cvgram_create / cvgram_batch_create calls whose problem falls in a tuned
@@ -332,7 +333,7 @@ cvgram_status cvgram_autotune(const void* X, const void* Y, const int32_t* fold_
                               void* stream, int32_t* tile, int32_t* target_items);
 
 /* The plan cvgram_create chose for this handle (host values):
- *   info[0] tile edge of the Gram launch (64 or 128)
+ *   info[0] tile width of the Gram launch (64, 128, or 256: 256 x 128 tiles)
  *   info[1] Gram work items (output tile x fold row range)
  *   info[2] slabs (per-fold row splits whose partial products are summed)
  *   info[3] 1 for the fused fold path (many small folds), else 0

@@ -358,7 +358,8 @@ void tune_load_locked(TuneTable& tt) {
   int a, b, c, d, e, tile;
   long long items;
   while (std::fscanf(f, "%d %d %d %d %d %d %lld", &a, &b, &c, &d, &e, &tile, &items) == 7)
-    if ((tile == 64 || tile == 128) && items > 0) tt.t[std::make_tuple(a, b, c, d, e)] = {tile, items};
+    if ((tile == 64 || tile == 128 || tile == 256) && items > 0)
+      tt.t[std::make_tuple(a, b, c, d, e)] = {tile, items};
   std::fclose(f);
 }
 
@@ -374,9 +375,20 @@ void tune_save_locked(TuneTable& tt) {
   std::fclose(f);
 }
 
+// Built-in tile rule: 64 for K <= 64, else 128, and in BF16X3 mode 256 x 128
+// tiles from K > 128 (half the panel bytes per product of the 128-wide
+// tiles; narrower problems would pad to 256 columns).  CVGRAM_BF16_TILE
+// (64, 128 or 256) overrides the BF16X3 choice.
 Config default_config(cvgram_mode mode, int64_t K) {
   Config c;
   c.tile = K <= 64 ? 64 : 128;
+  if (mode == CVGRAM_MODE_BF16X3) {
+    if (K > 128) c.tile = 256;
+    if (const char* e = std::getenv("CVGRAM_BF16_TILE")) {
+      const int v = std::atoi(e);
+      if (v == 64 || v == 128 || v == 256) c.tile = v;
+    }
+  }
   c.target_items = mode == CVGRAM_MODE_FP64 ? 1536 : 1024;
   return c;
 }
@@ -491,11 +503,10 @@ struct Batch {
   int64_t n_cb_items = 0;
   Item* d_range_items = nullptr;
   int64_t n_range_items = 0;
-  GramWork* d_work = nullptr;
-  int64_t n_work64 = 0, n_work128 = 0;
-  int32_t* d_xcd64 = nullptr;     // per-XCD item ranges of the two launches
-  int32_t* d_xcd128 = nullptr;
-  int64_t grid64 = 0, grid128 = 0;  // largest per-XCD item count
+  GramWork* d_work = nullptr;     // the items of the three launches, one array
+  int64_t n_work[kWidths] = {};
+  int32_t* d_xcd[kWidths] = {};   // per-XCD item ranges of each launch
+  int64_t grid[kWidths] = {};     // largest per-XCD item count
   Item* d_red_items = nullptr;
   int64_t n_red_items = 0;
   Item* d_corr_items = nullptr;
@@ -536,6 +547,13 @@ struct Batch {
     mem.release_async(stream);
   }
 };
+
+// FP64 mode on FP32 input keeps the panels in FP32 (ProbDesc::panel_f32)
+bool panel_f32(const Batch& b) { return b.mode == CVGRAM_MODE_FP64 && b.dtype == CVGRAM_F32; }
+// pivots are FP32 values in the mixed modes (the FP32 shift is then exact
+// for inputs within a factor 2 of it) and with FP32 panels (a padding row
+// holds the pivot and shifts to exactly 0)
+bool pivot_f32(const Batch& b) { return b.mode != CVGRAM_MODE_FP64 || panel_f32(b); }
 
 int bit_length(uint32_t v) {
   int b = 0;
@@ -600,7 +618,7 @@ cvgram_status bookkeeping(Batch& b) {
         // the pivots need only X and Y: they run while the host waits for the
         // counts and plans (a batch computes them inside its graph instead)
         p.d_pivot = (double*)b.mem.dev((size_t)p.W * sizeof(double));
-        launch_pivot_direct(b.dtype, b.mode != CVGRAM_MODE_FP64, p.X, p.Y, p.N, p.K, p.M,
+        launch_pivot_direct(b.dtype, pivot_f32(b), p.X, p.Y, p.N, p.K, p.M,
                             p.d_pivot, s);
       }
       // the sort starts before the wait on the guess that the labels fit in
@@ -677,9 +695,9 @@ struct HostLists {
   std::vector<Item> pivot_items, fold_items, sr_items, fs_items, cb_items, range_items, red_items,
       corr_items;
   std::vector<PackChunk> chunks;
-  std::vector<GramWork> work64, work128;
+  std::vector<GramWork> work[kWidths];
   // per-XCD item ranges of each Gram launch (kXcds + 1 offsets each)
-  std::vector<int32_t> xcd64, xcd128;
+  std::vector<int32_t> xcd[kWidths];
   // empty every list, keeping its memory (the lists are reused per thread:
   // no allocation or first-touch page faults on the planning path)
   void clear() {
@@ -687,10 +705,10 @@ struct HostLists {
                     &red_items, &corr_items})
       v->clear();
     chunks.clear();
-    work64.clear();
-    work128.clear();
-    xcd64.clear();
-    xcd128.clear();
+    for (int k = 0; k < kWidths; ++k) {
+      work[k].clear();
+      xcd[k].clear();
+    }
   }
 };
 
@@ -736,6 +754,7 @@ int64_t gram_item_cost(const GramWork& w, const std::vector<ProbPlan>& pp) {
   int64_t blocks = 16;
   if (p.cfg.tile == 128 && w.ti == w.tj && w.tj < p.nt)
     blocks = 9 + 2 * (p.xy_diag ? (p.M <= 16 ? 1 : 2) : 0);
+  if (p.cfg.tile == 256) blocks = 32;  // a 128 x 64 wave tile
   return (w.r1 - w.r0 + 2 * kPanelRows) * blocks;
 }
 
@@ -833,9 +852,9 @@ void schedule_gram(std::vector<GramWork>& wl, std::vector<int32_t>& xcd, bool ba
 void plan_layout(Batch& b, HostLists& L) {
   const int64_t PR = kPanelRows;
   int64_t pack_cols_rows = 0;  // sum over problems of Np * column blocks
-  // sum over problems of Np * tiles, per Gram launch (64- and 128-wide tiles
-  // are launched apart, so each launch is split for its own work)
-  int64_t gram_rows64 = 0, gram_rows128 = 0;
+  // sum over problems of Np * items per row range, per Gram launch (each
+  // tile width is launched apart, so each launch is split for its own work)
+  int64_t gram_rows[kWidths] = {};
   for (auto& p : b.pp) {
     p.cfg = b.force_cfg ? b.forced : choose_config(b.mode, b.dtype, p.K, p.M, p.N);
     const int T = p.cfg.tile;
@@ -846,16 +865,21 @@ void plan_layout(Batch& b, HostLists& L) {
       p.poff[q + 1] = p.poff[q] + (p.fused ? n : (n + PR - 1) / PR * PR);
     }
     p.Np = (p.poff[p.P] + PR - 1) / PR * PR;
+    // TB: width of a B block (the tile's columns); tile 256 pairs two
+    // 128-wide row blocks (A 256 columns, B 128)
+    const int TB = T == 256 ? 128 : T;
     p.Kp = (p.K + T - 1) / T * T;
     p.xy_diag = p.M > 0 && p.M <= kYDiagCols;
-    p.Mp = p.M == 0 ? 0 : (p.xy_diag ? kYDiagCols : (p.M + T - 1) / T * T);
+    p.Mp = p.M == 0 ? 0 : (p.xy_diag ? kYDiagCols : (p.M + TB - 1) / TB * TB);
     p.Wp = p.Kp + p.Mp;
-    p.nt = (int32_t)(p.Kp / T);
+    p.nt = (int32_t)(p.Kp / TB);
     p.tile_groups = b.pp.size() == 1 && p.nt >= kTileGroupMinNt;
-    const int64_t nyt = p.xy_diag ? 0 : p.Mp / T;
-    const int64_t ntile = (int64_t)p.nt * (p.nt + 1) / 2 + (int64_t)p.nt * nyt;
+    const int64_t nyt = p.xy_diag ? 0 : p.Mp / TB;
+    const int64_t na = p.Kp / T;  // A blocks
+    const int64_t ntile = T == 256 ? na * p.nt - na * (na - 1) + na * nyt
+                                   : (int64_t)p.nt * (p.nt + 1) / 2 + (int64_t)p.nt * nyt;
     pack_cols_rows += p.Np * ((p.Wp + kPackCols - 1) / kPackCols);
-    (T == 64 ? gram_rows64 : gram_rows128) += p.Np * ntile;
+    gram_rows[width_index(T)] += p.Np * ntile;
   }
   int64_t chunk_rows = (pack_cols_rows + kPackTargetBlocks - 1) / kPackTargetBlocks;
   chunk_rows = std::min((int64_t)kMaxChunkRows, std::max(PR, (chunk_rows + PR - 1) / PR * PR));
@@ -909,8 +933,25 @@ void plan_layout(Batch& b, HostLists& L) {
     // has about target_items items (shared over the problems of the batch
     // with the same tile width)
     std::vector<std::pair<int32_t, int32_t>> gtiles;
-    const int64_t nyt = p.xy_diag ? 0 : p.Mp / T;
-    if (!p.tile_groups) {
+    const int64_t nyt = p.xy_diag ? 0 : p.Mp / (T == 256 ? 128 : T);
+    if (T == 256) {
+      // (A block ti of 256 columns, B block tj of 128) for tj >= 2 ti; with
+      // many tiles in groups of 4 A blocks x 8 B blocks (the same column
+      // span as the 8 x 8 groups of 128-wide tiles)
+      const int32_t na = (int32_t)(p.Kp / 256);
+      const int32_t ga = p.tile_groups ? kTileGroup / 2 : na;
+      const int32_t gb = p.tile_groups ? kTileGroup : p.nt;
+      for (int32_t ba = 0; ba * ga < na; ++ba) {
+        const int32_t i0 = ba * ga, i1 = std::min(na, i0 + ga);
+        for (int32_t bb = 0; bb * gb < p.nt; ++bb) {
+          const int32_t j0 = bb * gb, j1 = std::min(p.nt, j0 + gb);
+          for (int32_t ti = i0; ti < i1; ++ti)
+            for (int32_t tj = std::max(2 * ti, j0); tj < j1; ++tj) gtiles.push_back({ti, tj});
+        }
+        for (int64_t y = 0; y < nyt; ++y)
+          for (int32_t ti = i0; ti < i1; ++ti) gtiles.push_back({ti, (int32_t)(p.nt + y)});
+      }
+    } else if (!p.tile_groups) {
       for (int32_t ti = 0; ti < p.nt; ++ti) {
         for (int32_t tj = ti; tj < p.nt; ++tj) gtiles.push_back({ti, tj});
         for (int64_t y = 0; y < nyt; ++y) gtiles.push_back({ti, (int32_t)(p.nt + y)});
@@ -931,11 +972,11 @@ void plan_layout(Batch& b, HostLists& L) {
           for (int32_t ti = i0; ti < i1; ++ti) gtiles.push_back({ti, (int32_t)(p.nt + y)});
       }
     }
-    const int64_t gram_rows = T == 64 ? gram_rows64 : gram_rows128;
-    int64_t rows_per_split = (gram_rows + p.cfg.target_items - 1) / p.cfg.target_items;
+    const int64_t grows = gram_rows[width_index(T)];
+    int64_t rows_per_split = (grows + p.cfg.target_items - 1) / p.cfg.target_items;
     rows_per_split = std::max(rows_per_split, kGramMinRows);
     rows_per_split = (rows_per_split + PR - 1) / PR * PR;
-    auto& wl = T == 64 ? L.work64 : L.work128;
+    auto& wl = L.work[width_index(T)];
     {
       // room for every item up front (no regrowth while appending)
       int64_t n_splits = 0;
@@ -997,8 +1038,7 @@ void plan_layout(Batch& b, HostLists& L) {
         for (int32_t tl = 0; tl < p.n_ctiles_xx + p.n_ctiles_xy; ++tl)
           L.corr_items.push_back({pi, q, tl});
   }
-  schedule_gram(L.work64, L.xcd64, b.pp.size() > 1, b.pp);
-  schedule_gram(L.work128, L.xcd128, b.pp.size() > 1, b.pp);
+  for (int k = 0; k < kWidths; ++k) schedule_gram(L.work[k], L.xcd[k], b.pp.size() > 1, b.pp);
 }
 
 // the plan blob: segments at 256-byte aligned offsets.  Laid out twice:
@@ -1020,11 +1060,16 @@ struct Blob {
   }
 };
 
-size_t elem_bytes(cvgram_mode m) { return m == CVGRAM_MODE_FP64 ? 8 : (m == CVGRAM_MODE_FP32 ? 4 : 2); }
+// bytes of one packed panel element: FP64 mode keeps FP32 input as FP32
+// (ProbDesc::panel_f32)
+size_t elem_bytes(cvgram_mode m, cvgram_dtype dt) {
+  if (m == CVGRAM_MODE_FP64) return dt == CVGRAM_F32 ? 4 : 8;
+  return m == CVGRAM_MODE_FP32 ? 4 : 2;
+}
 
 // Workspace arena + device descriptors + one upload of every plan.
 void allocate_and_upload(Batch& b, const HostLists& L) {
-  const size_t eb = elem_bytes(b.mode);
+  const size_t eb = elem_bytes(b.mode, b.dtype);
   // arena layout per problem
   struct Off {
     size_t pivot, packed, packed_lo, part, fold, tot, tot_part, tr_sum, tr_mean, tr_std, tr_mu,
@@ -1063,7 +1108,8 @@ void allocate_and_upload(Batch& b, const HostLists& L) {
   std::vector<size_t> o_offsets(b.pp.size()), o_poff(b.pp.size()), o_cbeg(b.pp.size()),
       o_sbeg(b.pp.size()), o_ctiles(b.pp.size());
   size_t o_pd = 0, o_out = 0, o_pivot = 0, o_chunks = 0, o_fold = 0, o_sr = 0, o_fs = 0,
-         o_cb = 0, o_range = 0, o_work = 0, o_red = 0, o_corr = 0, o_xcd64 = 0, o_xcd128 = 0;
+         o_cb = 0, o_range = 0, o_work = 0, o_red = 0, o_corr = 0;
+  size_t o_xcd[kWidths] = {};
   auto layout = [&](Blob& blob) {
     for (size_t i = 0; i < b.pp.size(); ++i) {
       o_offsets[i] = blob.put(b.pp[i].offsets);
@@ -1081,12 +1127,11 @@ void allocate_and_upload(Batch& b, const HostLists& L) {
     o_fs = blob.put(L.fs_items);
     o_cb = blob.put(L.cb_items);
     o_range = blob.put(L.range_items);
-    o_work = blob.put(L.work64);
-    blob.put(L.work128, false);  // right after the 64-wide items: one array
+    o_work = blob.put(L.work[0]);
+    for (int k = 1; k < kWidths; ++k) blob.put(L.work[k], false);  // one array
     o_red = blob.put(L.red_items);
     o_corr = blob.put(L.corr_items);
-    o_xcd64 = blob.put(L.xcd64);
-    o_xcd128 = blob.put(L.xcd128);
+    for (int k = 0; k < kWidths; ++k) o_xcd[k] = blob.put(L.xcd[k]);
   };
   Blob measure;
   layout(measure);
@@ -1121,6 +1166,7 @@ void allocate_and_upload(Batch& b, const HostLists& L) {
     d.ddof = b.ddof;
     d.x_vec = (p.K % 4 == 0) && ((uintptr_t)p.X % 16 == 0) ? 1 : 0;
     d.mode = (int32_t)b.mode;
+    d.panel_f32 = panel_f32(b) ? 1 : 0;
     d.fused = p.fused ? 1 : 0;
     d.n_slabs = (int32_t)p.n_slabs;
     d.perm = p.d_perm;
@@ -1183,17 +1229,16 @@ void allocate_and_upload(Batch& b, const HostLists& L) {
   b.d_range_items = (Item*)(dblob + o_range);
   b.n_range_items = (int64_t)L.range_items.size();
   b.d_work = (GramWork*)(dblob + o_work);
-  b.n_work64 = (int64_t)L.work64.size();
-  b.n_work128 = (int64_t)L.work128.size();
-  b.d_xcd64 = (int32_t*)(dblob + o_xcd64);
-  b.d_xcd128 = (int32_t*)(dblob + o_xcd128);
+  for (int k = 0; k < kWidths; ++k) {
+    b.n_work[k] = (int64_t)L.work[k].size();
+    b.d_xcd[k] = (int32_t*)(dblob + o_xcd[k]);
+  }
   auto widest = [](const std::vector<int32_t>& x) {
     int64_t m = 0;
     for (size_t i = 0; i + 1 < x.size(); ++i) m = std::max<int64_t>(m, x[i + 1] - x[i]);
     return m;
   };
-  b.grid64 = widest(L.xcd64);
-  b.grid128 = widest(L.xcd128);
+  for (int k = 0; k < kWidths; ++k) b.grid[k] = widest(L.xcd[k]);
   b.d_red_items = (Item*)(dblob + o_red);
   b.n_red_items = (int64_t)L.red_items.size();
   b.d_corr_items = (Item*)(dblob + o_corr);
@@ -1210,17 +1255,20 @@ void run_pipeline(Batch& b, bool with_events) {
   auto mark = [&](int k) {
     if (with_events && b.timing) CVG_HIP(hipEventRecord(b.ev[k], s));
   };
-  const bool mixed = b.mode != CVGRAM_MODE_FP64;
   mark(1);
-  if (b.batched) launch_pivot(b.dtype, mixed, b.d_pd, b.d_pivot_items, b.n_pivot_items, s);
+  if (b.batched) launch_pivot(b.dtype, pivot_f32(b), b.d_pd, b.d_pivot_items, b.n_pivot_items, s);
   launch_pack(b.mode, b.dtype, b.d_pd, b.d_chunks, b.n_chunks, b.max_pack_cb, s);
   launch_stats_reduce(b.d_pd, b.d_sr_items, b.n_sr_items, b.max_cb64, s);
   launch_fold_sums_rows(b.dtype, b.d_pd, b.d_fs_items, b.n_fs_items, b.max_cb64, s);
   launch_fold_totals(b.d_pd, b.d_range_items, b.n_range_items, b.d_cb_items, b.n_cb_items, s);
   launch_train_stats(b.d_pd, b.d_fold_items, b.n_fold_items, b.max_cb256, s);
   mark(2);
-  launch_gram(b.mode, 64, b.d_pd, b.d_work, b.d_xcd64, b.grid64, s);
-  launch_gram(b.mode, 128, b.d_pd, b.d_work + b.n_work64, b.d_xcd128, b.grid128, s);
+  int64_t first = 0;
+  for (int k = 0; k < kWidths; ++k) {
+    launch_gram(b.mode, panel_f32(b), kWidth[k], b.d_pd, b.d_work + first, b.d_xcd[k], b.grid[k],
+                s);
+    first += b.n_work[k];
+  }
   mark(3);
   launch_reduce_slabs(b.d_pd, b.d_red_items, b.n_red_items, s);
   if (b.batched)
@@ -1556,7 +1604,8 @@ cvgram_status cvgram_plan_info(cvgram_t h, int64_t* info, int32_t n) {
   if (!h || (!info && n > 0)) return fail(CVGRAM_EINVAL, "NULL argument");
   const Batch& b = h->b;
   const ProbPlan& p = b.pp[0];
-  const int64_t v[4] = {p.cfg.tile, b.n_work64 + b.n_work128, p.n_slabs, p.fused ? 1 : 0};
+  const int64_t v[4] = {p.cfg.tile, b.n_work[0] + b.n_work[1] + b.n_work[2], p.n_slabs,
+                        p.fused ? 1 : 0};
   for (int32_t k = 0; k < n && k < 4; ++k) info[k] = v[k];
   return CVGRAM_OK;
 }
@@ -1718,13 +1767,15 @@ cvgram_status cvgram_autotune(const void* X, const void* Y, const int32_t* fold_
   if (dtype != CVGRAM_F32 && dtype != CVGRAM_F64) return fail(CVGRAM_EINVAL, "bad dtype");
   if (mode != CVGRAM_MODE_FP64 && mode != CVGRAM_MODE_FP32 && mode != CVGRAM_MODE_BF16X3)
     return fail(CVGRAM_EINVAL, "bad mode");
-  const int tiles[2] = {64, 128};
+  const int tiles[3] = {64, 128, 256};
   const int64_t items[4] = {512, 1024, 2048, 4096};
   Config best;
   double best_ms = 1e300;
   try {
-    for (int ti = 0; ti < 2; ++ti) {
+    for (int ti = 0; ti < 3; ++ti) {
       if (tiles[ti] == 64 && K > 1024) continue;  // too many tiles to pay off
+      // 256 x 128 tiles: BF16X3 only, and not where they would pad K to 256
+      if (tiles[ti] == 256 && (mode != CVGRAM_MODE_BF16X3 || K <= 128)) continue;
       for (int ii = 0; ii < 4; ++ii) {
         Batch b;
         // the candidate's workspace goes back to the cache on every path

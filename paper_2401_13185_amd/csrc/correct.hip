@@ -133,6 +133,13 @@ __global__ __launch_bounds__(256) void reduce_slabs_kernel(const ProbDesc* __res
 // element (row r, packed column col) of the packed panels as FP64: the
 // shifted value the Gram launch multiplied (hi + lo in the bf16 split)
 __device__ inline double packed_value(const ProbDesc& pd, int64_t r, int64_t col, int64_t Wp) {
+  if (pd.panel_f32) {
+    // raw FP32 values, shifted here (padding columns: 0)
+    const int64_t sc = col < pd.Kp ? (col < pd.K ? col : -1)
+                                   : (col - pd.Kp < pd.M ? pd.K + (col - pd.Kp) : -1);
+    if (sc < 0) return 0.0;
+    return (double)gmem((const float*)pd.packed)[r * Wp + col] - gmem(pd.pivot)[sc];
+  }
   if (pd.mode == CVGRAM_MODE_FP64) return gmem((const double*)pd.packed)[r * Wp + col];
   if (pd.mode == CVGRAM_MODE_FP32) return (double)gmem((const float*)pd.packed)[r * Wp + col];
   const int64_t k = ((r >> 5) * Wp + col) * 32 + (r & 31);

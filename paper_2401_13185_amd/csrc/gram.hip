@@ -109,24 +109,33 @@ struct Smem {
 // ---------------------------------------------------------------------------
 // global -> register staging of one stage (BK packed rows starting at row r)
 // ---------------------------------------------------------------------------
-template <int MODE, int BM>
-struct Stage;
+// pivot of packed column pc (0 for a padding column): the shift FP32 panels
+// of the FP64 mode get as they are loaded
+__device__ inline double panel_pivot(const CVG_GLOBAL double* pivot, int64_t pc, int64_t K,
+                                     int64_t Kp, int64_t M) {
+  if (pc < Kp) return pc < K ? pivot[pc] : 0.0;
+  return pc - Kp < M ? pivot[K + (pc - Kp)] : 0.0;
+}
 
 // FP64 / FP32: an operand block is 16 rows x BM columns, moved in 16-byte
 // chunks; consecutive threads take consecutive chunks of a row, so both the
 // global loads and the LDS stores are contiguous.  The Y block (16 x 32) is
-// one chunk for each of the first 16 * 32 * sizeof(E) / 16 threads.
-template <int MODE, int BM>
+// one chunk for each of the first 16 * 32 * sizeof(E) / 16 threads.  F32P
+// (FP64 mode on FP32 panels): the chunks hold four FP32 values, stored to
+// LDS as FP64 minus their columns' pivots (a thread's columns are the same
+// in every stage, so their pivots are read once).
+template <int MODE, int BM, bool F32P = false>
 struct Stage {
-  typedef typename Mode<MODE>::E E;
-  typedef E V16 __attribute__((ext_vector_type(16 / sizeof(E))));
-  static constexpr int EPC = 16 / sizeof(E);        // elements per chunk
+  typedef typename Mode<MODE>::E E;                  // LDS element
+  typedef typename std::conditional<F32P, float, E>::type LE;  // panel element
+  typedef LE V16 __attribute__((ext_vector_type(16 / sizeof(LE))));
+  static constexpr int EPC = 16 / sizeof(LE);       // elements per chunk
   static constexpr int CPR = BM / EPC;              // chunks per row
   static constexpr int RPR = kThreads / CPR;        // rows per round
   static constexpr int V = 16 / RPR;                // chunks per thread per operand
   static constexpr int YC = kYW / EPC;              // chunks per Y row
   V16 a[V], b[V], y;
-  __device__ void load(const CVG_GLOBAL E* Z, int64_t Wp, int64_t r, int64_t ca, int64_t cb,
+  __device__ void load(const CVG_GLOBAL LE* Z, int64_t Wp, int64_t r, int64_t ca, int64_t cb,
                        int64_t cy, bool ld_b, bool ld_y, int t) {
     const int row0 = t / CPR, col = (t % CPR) * EPC;
 #pragma unroll
@@ -140,17 +149,46 @@ struct Stage {
     if (ld_y && t < 16 * YC)
       y = *(const CVG_GLOBAL V16*)(Z + (r + t / YC) * Wp + cy + (t % YC) * EPC);
   }
-  __device__ void store(Smem<MODE, BM>& s, int buf, bool st_b, bool st_y, int t) const {
+  template <typename Piv>
+  __device__ void store(Smem<MODE, BM>& s, int buf, bool st_b, bool st_y, int t,
+                        const Piv& pv) const {
     constexpr int LDA = Smem<MODE, BM>::LDA, LDY = Smem<MODE, BM>::LDY;
     const int row0 = t / CPR, col = (t % CPR) * EPC;
+    if constexpr (!F32P) {
 #pragma unroll
-    for (int u = 0; u < V; ++u) *(V16*)&s.a[buf][(row0 + RPR * u) * LDA + col] = a[u];
-    if (st_b)
+      for (int u = 0; u < V; ++u) *(V16*)&s.a[buf][(row0 + RPR * u) * LDA + col] = a[u];
+      if (st_b)
 #pragma unroll
-      for (int u = 0; u < V; ++u) *(V16*)&s.b[buf][(row0 + RPR * u) * LDA + col] = b[u];
-    if (st_y && t < 16 * YC) *(V16*)&s.y[buf][(t / YC) * LDY + (t % YC) * EPC] = y;
+        for (int u = 0; u < V; ++u) *(V16*)&s.b[buf][(row0 + RPR * u) * LDA + col] = b[u];
+      if (st_y && t < 16 * YC) *(V16*)&s.y[buf][(t / YC) * LDY + (t % YC) * EPC] = y;
+    } else {
+      // four FP32 values -> four shifted FP64 values (two 16-byte stores)
+      auto put = [&](double* dst, const V16& v, const double* piv) {
+        double2_t lo, hi;
+        lo.x = (double)v[0] - piv[0];
+        lo.y = (double)v[1] - piv[1];
+        hi.x = (double)v[2] - piv[2];
+        hi.y = (double)v[3] - piv[3];
+        *(double2_t*)dst = lo;
+        *(double2_t*)(dst + 2) = hi;
+      };
+#pragma unroll
+      for (int u = 0; u < V; ++u) put(&s.a[buf][(row0 + RPR * u) * LDA + col], a[u], pv.a);
+      if (st_b)
+#pragma unroll
+        for (int u = 0; u < V; ++u) put(&s.b[buf][(row0 + RPR * u) * LDA + col], b[u], pv.b);
+      if (st_y && t < 16 * YC) put(&s.y[buf][(t / YC) * LDY + (t % YC) * EPC], y, pv.y);
+    }
   }
 };
+// the pivots of one thread's stage columns (F32P) or nothing
+template <bool F32P>
+struct StagePivots {
+  double a[4], b[4], y[4];
+};
+template <>
+struct StagePivots<false> {};
+
 
 // ---------------------------------------------------------------------------
 // one stage of MFMA work for a wave: NA x NB blocks of 16 x 16, A columns
@@ -208,40 +246,52 @@ __device__ inline void mma_f32(const float* A, int lda, int acol0, const float* 
 // 32 or with 64 banks of 4 bytes).
 __device__ __forceinline__ int swz(int c) { return ((c >> 1) ^ (c >> 2)) & 3; }
 
-// One stage's fragments for NA x NB blocks of 16 x 16: A columns from
-// `acol0`, B columns from `bcol0` (multiples of 16) of the swizzled buffers;
-// `lfo` is the lane's byte offset fc * 64 + ((fr ^ swz(fc)) << 4).
+// One stage's fragments for NA x NB output blocks of 32 x 32 (the operands
+// of v_mfma_f32_32x32x16_bf16: per lane one column of a 32-column block and
+// 8 consecutive rows of a 16-row slice; a 32-row stage is two slices).
+// A columns from `acol0`, B columns from `bcol0` (multiples of 32) of the
+// swizzled buffers; lfo[ks] is the lane's byte offset for slice ks:
+// (lane % 32) * 64 + (((2 ks + lane / 32) ^ swz(lane % 32)) << 4).  The 32
+// lanes of a half-wave read one 16-byte chunk of 32 consecutive columns:
+// every 16 of them fall in 16 different bank groups.
+typedef float float16_t __attribute__((ext_vector_type(16)));
 template <int NA, int NB>
 struct Frags {
-  bf16x8_t ah[NA], al[NA], bh[NB], bl[NB];
+  bf16x8_t ah[NA][2], al[NA][2], bh[NB][2], bl[NB][2];
   __device__ void load(const __bf16* Ah, const __bf16* Al, int acol0, const __bf16* Bh,
-                       const __bf16* Bl, int bcol0, int lfo) {
+                       const __bf16* Bl, int bcol0, const int (&lfo)[2]) {
 #pragma unroll
-    for (int a = 0; a < NA; ++a) {
-      const int off = (acol0 + a * 16) * 64 + lfo;
-      ah[a] = *(const bf16x8_t*)((const char*)Ah + off);
-      al[a] = *(const bf16x8_t*)((const char*)Al + off);
-    }
+    for (int ks = 0; ks < 2; ++ks) {
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      const int off = (bcol0 + b * 16) * 64 + lfo;
-      bh[b] = *(const bf16x8_t*)((const char*)Bh + off);
-      bl[b] = *(const bf16x8_t*)((const char*)Bl + off);
+      for (int a = 0; a < NA; ++a) {
+        const int off = (acol0 + a * 32) * 64 + lfo[ks];
+        ah[a][ks] = *(const bf16x8_t*)((const char*)Ah + off);
+        al[a][ks] = *(const bf16x8_t*)((const char*)Al + off);
+      }
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const int off = (bcol0 + b * 32) * 64 + lfo[ks];
+        bh[b][ks] = *(const bf16x8_t*)((const char*)Bh + off);
+        bl[b][ks] = *(const bf16x8_t*)((const char*)Bl + off);
+      }
     }
   }
 };
 
-// One of the three products over all blocks (consecutive MFMAs update
-// different accumulators): pass 0 lo(A) hi(B), pass 1 hi(A) lo(B), pass 2
-// hi(A) hi(B).
+// One of the three products over all blocks and both slices (consecutive
+// MFMAs update different accumulators): pass 0 lo(A) hi(B), pass 1 hi(A)
+// lo(B), pass 2 hi(A) hi(B).
 template <int PASS, int NA, int NB, int NACC>
-__device__ inline void mfma_pass(const Frags<NA, NB>& f, float4_t (&acc)[NACC]) {
+__device__ inline void mfma_pass(const Frags<NA, NB>& f, float16_t (&acc)[NACC]) {
 #pragma unroll
-  for (int a = 0; a < NA; ++a)
+  for (int ks = 0; ks < 2; ++ks)
 #pragma unroll
-    for (int b = 0; b < NB; ++b)
-      acc[a * NB + b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-          PASS == 0 ? f.al[a] : f.ah[a], PASS == 1 ? f.bl[b] : f.bh[b], acc[a * NB + b], 0, 0, 0);
+    for (int a = 0; a < NA; ++a)
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+        acc[a * NB + b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+            PASS == 0 ? f.al[a][ks] : f.ah[a][ks], PASS == 1 ? f.bl[b][ks] : f.bh[b][ks],
+            acc[a * NB + b], 0, 0, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -348,8 +398,11 @@ __device__ inline void store_tile(CVG_GLOBAL double* out, int role, bool xy_tile
 // ---------------------------------------------------------------------------
 // FP64 / FP32 kernel: register-staged LDS double buffer
 // ---------------------------------------------------------------------------
-template <int MODE, int BM>
-__global__ __launch_bounds__(kThreads) void gram_kernel(const ProbDesc* __restrict__ pds,
+// FP32 panels in FP64 mode: held to two workgroups per CU (at most 256
+// registers per lane), as the FP64 panels fit by themselves
+template <int MODE, int BM, bool F32P>
+__global__ __launch_bounds__(kThreads, F32P ? 2 : 1) void gram_kernel(
+    const ProbDesc* __restrict__ pds,
                                                         const GramWork* __restrict__ work,
                                                         const int32_t* __restrict__ xcd) {
   typedef typename Mode<MODE>::Acc Acc;
@@ -369,9 +422,8 @@ __global__ __launch_bounds__(kThreads) void gram_kernel(const ProbDesc* __restri
   const ProbDesc& pdr = pds[w.prob];
   const int64_t Wp = pdr.Wp, Kp = pdr.Kp, K = pdr.K, M = pdr.M;
   const int32_t nt = pdr.nt;
-  typedef typename Mode<MODE>::E E;
-  const CVG_GLOBAL E* const packed = gmem((const E*)pdr.packed);
-  const CVG_GLOBAL E* const packed_lo = gmem((const E*)pdr.packed_lo);
+  typedef typename Stage<MODE, BM, F32P>::LE PE;  // panel element
+  const CVG_GLOBAL PE* const packed = gmem((const PE*)pdr.packed);
   CVG_GLOBAL double* const slabs = gmem(pdr.slabs);
   const bool xy_diag = pdr.xy_diag != 0;
   const int t = threadIdx.x, lane = t & 63;
@@ -428,13 +480,26 @@ __global__ __launch_bounds__(kThreads) void gram_kernel(const ProbDesc* __restri
       }
     }
   };
+  // FP32 panels: the pivots of this thread's stage columns
+  StagePivots<F32P> pv;
+  if constexpr (F32P) {
+    typedef Stage<MODE, BM, true> S;
+    const CVG_GLOBAL double* pivot = gmem((const double*)pdr.pivot);
+    const int64_t col = (t % S::CPR) * S::EPC, ycol = (t % S::YC) * S::EPC;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      pv.a[e] = panel_pivot(pivot, ca + col + e, K, Kp, M);
+      pv.b[e] = panel_pivot(pivot, cb + col + e, K, Kp, M);
+      pv.y[e] = panel_pivot(pivot, Kp + ycol + e, K, Kp, M);
+    }
+  }
   auto main_loop = [&](auto diag_c, auto ydiag_c, auto nyb_c, auto wave_c) {
     constexpr bool DG = decltype(diag_c)::value;   // B is A
     constexpr bool YD = decltype(ydiag_c)::value;  // K x M block in this tile
     constexpr int NYB = decltype(nyb_c)::value;    // its blocks per row (pairs)
     constexpr int WV = decltype(wave_c)::value;    // the wave (pairs)
-    Stage<MODE, BM> st[PF];
-    auto load = [&](Stage<MODE, BM>& sg, int64_t s) {
+    Stage<MODE, BM, F32P> st[PF];
+    auto load = [&](Stage<MODE, BM, F32P>& sg, int64_t s) {
       const int64_t r = w.r0 + (s < nst ? s : nst - 1) * BK;
       sg.load(packed, Wp, r, ca, cb, Kp, !DG, YD, t);
     };
@@ -463,7 +528,7 @@ __global__ __launch_bounds__(kThreads) void gram_kernel(const ProbDesc* __restri
       }
     };
     load(st[0], 0);
-    st[0].store(sm, 0, !DG, YD, t);
+    st[0].store(sm, 0, !DG, YD, t, pv);
     if constexpr (PF == 2) load(st[1], 1);
     __syncthreads();
     if constexpr (PF == 1) {
@@ -473,19 +538,19 @@ __global__ __launch_bounds__(kThreads) void gram_kernel(const ProbDesc* __restri
         if (more) load(st[0], s + 1);
         compute(buf);
         flush();
-        if (more) st[0].store(sm, buf ^ 1, !DG, YD, t);
+        if (more) st[0].store(sm, buf ^ 1, !DG, YD, t, pv);
         __syncthreads();
       }
     } else {
       // stage s is in LDS buffer s & 1 and stage s+1 in registers; stage s+2
       // is loaded while stage s computes.  Unrolled by two so that the two
       // register sets keep fixed roles.
-      auto step = [&](int64_t s, Stage<MODE, BM>& next, Stage<MODE, BM>& far) {
+      auto step = [&](int64_t s, Stage<MODE, BM, F32P>& next, Stage<MODE, BM, F32P>& far) {
         const int buf = (int)(s & 1);
         load(far, s + 2);
         compute(buf);
         flush();
-        if (s + 1 < nst) next.store(sm, buf ^ 1, !DG, YD, t);
+        if (s + 1 < nst) next.store(sm, buf ^ 1, !DG, YD, t, pv);
         __syncthreads();
       };
       int64_t s = 0;
@@ -518,12 +583,26 @@ __global__ __launch_bounds__(kThreads) void gram_kernel(const ProbDesc* __restri
   // with no LDS staging and no workgroup barrier; the two waves that share
   // an operand half meet in the L1 cache.  Same products in the same order
   // as the staged loop (row steps in increasing row order).
+  // FP32 panels: the values are loaded as FP32 (half the bytes) and shifted
+  // to FP64 right before the MFMAs that use them, so the loads stay
+  // kDirectDepth steps ahead
   auto direct_loop = [&]() {
     constexpr int D = kDirectDepth;
-    const CVG_GLOBAL double* za = gmem((const double*)pdr.packed) + ca + wm * WT + fc;
-    const CVG_GLOBAL double* zb = gmem((const double*)pdr.packed) + cb + wn * WT + fc;
+    const CVG_GLOBAL PE* za = packed + ca + wm * WT + fc;
+    const CVG_GLOBAL PE* zb = packed + cb + wn * WT + fc;
     const int64_t nk = (w.r1 - w.r0) / 4;  // a multiple of 8: items are whole panels
-    double fa[D][NW], fb[D][NW];
+    PE fa[D][NW], fb[D][NW];
+    double pa[NW], pb[NW];
+#pragma unroll
+    for (int a = 0; a < NW; ++a) {
+      pa[a] = 0.0;
+      pb[a] = 0.0;
+      if constexpr (F32P) {
+        const CVG_GLOBAL double* pivot = gmem((const double*)pdr.pivot);
+        pa[a] = panel_pivot(pivot, ca + wm * WT + fc + 16 * a, K, Kp, M);
+        pb[a] = panel_pivot(pivot, cb + wn * WT + fc + 16 * a, K, Kp, M);
+      }
+    }
     auto load_k = [&](int d, int64_t k) {
       const int64_t off = (w.r0 + 4 * k + fr) * Wp;
 #pragma unroll
@@ -536,14 +615,35 @@ __global__ __launch_bounds__(kThreads) void gram_kernel(const ProbDesc* __restri
       load_k(d, d < nk ? d : nk - 1);
       __builtin_amdgcn_sched_barrier(0);  // the loop's order: its waits count from it
     }
+    // FP32 panels: step k's operands are converted and shifted while step
+    // k - 1's MFMAs run (two sets, alternating; D is even)
+    static_assert(kDirectDepth % 2 == 0, "operand sets alternate per step");
+    double xa[2][NW], xb[2][NW];
+    auto convert = [&](int d, int slot) {
+#pragma unroll
+      for (int a = 0; a < NW; ++a) {
+        xa[slot][a] = (double)fa[d][a] - pa[a];
+        xb[slot][a] = (double)fb[d][a] - pb[a];
+      }
+    };
+    if constexpr (F32P) convert(0, 0);
     for (int64_t k = 0; k < nk; k += D) {
 #pragma unroll
       for (int d = 0; d < D; ++d) {
+        if constexpr (F32P) {
 #pragma unroll
-        for (int a = 0; a < NW; ++a)
+          for (int a = 0; a < NW; ++a)
 #pragma unroll
-          for (int b = 0; b < NW; ++b)
-            acc[a * NW + b] = mfma_step(fa[d][a], fb[d][b], acc[a * NW + b]);
+            for (int b = 0; b < NW; ++b)
+              acc[a * NW + b] = mfma_step(xa[d & 1][a], xb[d & 1][b], acc[a * NW + b]);
+          convert((d + 1) % D, (d + 1) & 1);  // step k + d + 1 (past the end: unused)
+        } else {
+#pragma unroll
+          for (int a = 0; a < NW; ++a)
+#pragma unroll
+            for (int b = 0; b < NW; ++b)
+              acc[a * NW + b] = mfma_step((double)fa[d][a], (double)fb[d][b], acc[a * NW + b]);
+        }
         // the step D ahead (past the end: the last step again, unused),
         // issued here and not moved: its registers are free only now, and
         // it has the next D - 1 steps' MFMAs to arrive
@@ -637,9 +737,11 @@ template <int BM>
 __global__ __launch_bounds__(kThreads) void gram_bf16_kernel(const ProbDesc* __restrict__ pds,
                                                              const GramWork* __restrict__ work,
                                                              const int32_t* __restrict__ xcd) {
-  constexpr int MODE = CVGRAM_MODE_BF16X3;
-  constexpr int WT = BM / 2, NW = WT / 16, NY = BM / 16;
-  constexpr int NACC = NW * NW > 2 * NY ? NW * NW : 2 * NY;
+  constexpr int WT = BM / 2;
+  // 32 x 32 output blocks: a wave's WT x WT sub-tile (role 0) is NW x NW of
+  // them, the BM x 32 K-by-M block of a diagonal tile (role 1) NY x 1
+  constexpr int NW = WT / 32, NY = BM / 32;
+  constexpr int NACC = NW * NW > NY ? NW * NW : NY;
   constexpr int IA = BM / 64;  // 1 KB direct loads per wave per array per stage
   __shared__ __attribute__((aligned(1024))) DmaBuf<BM> sb0, sb1, sb2, sb3;
 
@@ -657,7 +759,6 @@ __global__ __launch_bounds__(kThreads) void gram_bf16_kernel(const ProbDesc* __r
   const int t = threadIdx.x, lane = t & 63;
   const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
   const int wm = wave >> 1, wn = wave & 1;
-  const int fr = lane >> 4, fc = lane & 15;
 
   const bool xy_tile = w.tj >= nt;
   const bool diag = !xy_tile && w.ti == w.tj;
@@ -670,15 +771,18 @@ __global__ __launch_bounds__(kThreads) void gram_bf16_kernel(const ProbDesc* __r
   // columns (a permutation of the block's chunks: the loads stay coalesced),
   // and this lane's fragment chunk inside a buffer
   const int lsrc = (lane >> 2) * 64 + (((lane & 3) ^ swz(lane >> 2)) << 4);
-  const int lfo = fc * 64 + ((fr ^ swz(fc)) << 4);
+  const int lc = lane & 31, lh = lane >> 5;
+  const int lfo[2] = {lc * 64 + ((lh ^ swz(lc)) << 4), lc * 64 + (((2 + lh) ^ swz(lc)) << 4)};
 
-  float4_t acc[NACC];
-  double a64[NACC][4];
+  float16_t acc[NACC];
+  double a64[NACC][16];
 #pragma unroll
   for (int i = 0; i < NACC; ++i) {
-    acc[i] = float4_t{0, 0, 0, 0};
 #pragma unroll
-    for (int e = 0; e < 4; ++e) a64[i][e] = 0.0;
+    for (int e = 0; e < 16; ++e) {
+      acc[i][e] = 0.f;
+      a64[i][e] = 0.0;
+    }
   }
   const int64_t nst = (w.r1 - w.r0) / 32;
   const int64_t p0 = w.r0 / 32;  // first panel
@@ -691,8 +795,10 @@ __global__ __launch_bounds__(kThreads) void gram_bf16_kernel(const ProbDesc* __r
 #pragma unroll
       for (int i = 0; i < NACC; ++i) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) a64[i][e] += (double)acc[i][e];
-        acc[i] = float4_t{0, 0, 0, 0};
+        for (int e = 0; e < 16; ++e) {
+          a64[i][e] += (double)acc[i][e];
+          acc[i][e] = 0.f;
+        }
       }
     }
   };
@@ -704,7 +810,7 @@ __global__ __launch_bounds__(kThreads) void gram_bf16_kernel(const ProbDesc* __r
     constexpr bool DG = decltype(diag_c)::value;
     constexpr bool YD = decltype(ydiag_c)::value;
     constexpr int R = decltype(role_c)::value;
-    constexpr int FA = R == 1 ? NY : NW, FB = R == 1 ? 2 : NW;
+    constexpr int FA = R == 1 ? NY : NW, FB = R == 1 ? 1 : NW;
     // direct loads per wave per stage (all waves issue the same number)
     constexpr int L = IA * (DG ? 2 : 4) + (YD ? 1 : 0);
     // stage s (clamped to the last one) into buffer b
@@ -799,40 +905,348 @@ __global__ __launch_bounds__(kThreads) void gram_bf16_kernel(const ProbDesc* __r
   }
   if (role == 2) return;
   CVG_GLOBAL double* out = slabs + (int64_t)w.slab * K * (K + M);
-  auto value = [&](int i, int e) -> double { return a64[i][e] + (double)acc[i][e]; };
-  store_tile<MODE, BM, NACC>(out, role, xy_tile, ca, xy_tile ? (int64_t)(w.tj - nt) * BM : cb, wm,
-                             wn, fr, fc, K, M, value);
+  // lane's entries of block (a, b): column b * 32 + lane % 32, rows
+  // a * 32 + 8 (e / 4) + 4 (lane / 32) + e % 4 for e = 0 .. 15
+  const int64_t W = K + M;
+  if (role == 0) {
+    const int64_t r0 = ca + wm * WT;
+    const int64_t c0 = (xy_tile ? (int64_t)(w.tj - nt) * BM : cb) + wn * WT;
+#pragma unroll
+    for (int a = 0; a < NW; ++a)
+#pragma unroll
+      for (int b = 0; b < NW; ++b)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          const int64_t row = r0 + a * 32 + 8 * (e >> 2) + 4 * lh + (e & 3);
+          const int64_t cl = c0 + b * 32 + lc;
+          const double v = a64[a * NW + b][e] + (double)acc[a * NW + b][e];
+          if (row >= K) continue;
+          if (!xy_tile) {
+            if (cl < K) out[row * W + cl] = v;
+          } else if (cl < M) {
+            out[row * W + K + cl] = v;
+          }
+        }
+  } else {
+#pragma unroll
+    for (int a = 0; a < NY; ++a)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int64_t row = ca + a * 32 + 8 * (e >> 2) + 4 * lh + (e & 3);
+        if (row < K && lc < M) out[row * W + K + lc] = a64[a][e] + (double)acc[a][e];
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// BF16X3 wide kernel: 256 x 128 workgroup tiles (tile code 256)
+// ---------------------------------------------------------------------------
+// Item (ti, tj): A = packed columns [256 ti, 256 ti + 256) (two 128-wide
+// tiles of the K x K block stacked), B = the 128 columns of B block tj
+// (tj < nt: X columns [128 tj, +128); tj >= nt: Y columns [128 (tj - nt),
+// +128)).  Items exist for tj >= 2 ti.  Pairs with tj = 2 ti or 2 ti + 1
+// straddle the diagonal: their B columns lie inside A's (no B loads); in
+// tj = 2 ti the lower half of A is below the diagonal, and those two waves
+// compute the 256 x 32 K-by-M block instead (M <= 32) or idle.
+// Four waves, wave (wm, wn) = A columns 128 wm, B columns 64 wn: 4 x 2
+// output blocks of 32 x 32.  Per 32-row stage each wave reads 96 KB... of
+// fragments in three parts streamed around the three products
+// (lo(A) hi(B), hi(A) hi(B), hi(A) lo(B)): a part is re-read for the next
+// stage as soon as the product that used it last is issued, so one register
+// set serves.  The ring has three stages of 52 KB; the barrier after each
+// stage's first product frees that stage's buffer for the stage three ahead.
+// Accumulation: FP32 MFMA accumulators added into FP32 running totals every
+// 256 rows (VALU adds round to nearest) -- the totals take the place of the
+// FP64 copies, which leave no room for a 128 x 64 wave tile.
+constexpr int kWStages = 3;
+constexpr int kWFlushRows = 256;
+struct DmaBufW {
+  // [column][32 rows] bf16, swizzled 16-byte chunks (see swz)
+  __bf16 ah[256 * 32], al[256 * 32], bh[128 * 32], bl[128 * 32], yh[kYW * 32], yl[kYW * 32];
+};
+
+__global__ __launch_bounds__(kThreads) void gram_bf16_wide_kernel(
+    const ProbDesc* __restrict__ pds, const GramWork* __restrict__ work,
+    const int32_t* __restrict__ xcd) {
+  __shared__ __attribute__((aligned(1024))) DmaBufW sb0, sb1, sb2;
+  const int x = (int)(blockIdx.x % kXcds);
+  const int64_t item = (int64_t)xcd[x] + blockIdx.x / kXcds;
+  if (item >= xcd[x + 1]) return;
+  const GramWork w = work[item];
+  const ProbDesc& pdr = pds[w.prob];
+  const int64_t Wp = pdr.Wp, Kp = pdr.Kp, K = pdr.K, M = pdr.M;
+  const int32_t nt = pdr.nt;  // B blocks of 128 along X's columns
+  const CVG_GLOBAL char* const Zh = gmem((const char*)pdr.packed);
+  const CVG_GLOBAL char* const Zl = gmem((const char*)pdr.packed_lo);
+  CVG_GLOBAL double* const slabs = gmem(pdr.slabs);
+  const bool xy_diag = pdr.xy_diag != 0;
+  const int t = threadIdx.x, lane = t & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int wm = wave >> 1, wn = wave & 1;
+
+  const bool xy_tile = w.tj >= nt;
+  const int dq = w.tj - 2 * w.ti;               // 0 or 1 on the diagonal pairs
+  const bool diag = !xy_tile && (dq == 0 || dq == 1);
+  const int64_t ca = (int64_t)w.ti * 256;
+  const int64_t cb = xy_tile ? Kp + (int64_t)(w.tj - nt) * 128 : (int64_t)w.tj * 128;
+  const bool ydiag = diag && dq == 0 && xy_diag;
+  // 0: 128 x 64 sub-tile; 1: 128 x 32 K-by-M block; 2: idle
+  const int role = (diag && dq == 0 && wm == 1) ? (ydiag ? 1 : 2) : 0;
+
+  const int lsrc = (lane >> 2) * 64 + (((lane & 3) ^ swz(lane >> 2)) << 4);
+  const int lc = lane & 31, lh = lane >> 5;
+  const int lfo[2] = {lc * 64 + ((lh ^ swz(lc)) << 4), lc * 64 + (((2 + lh) ^ swz(lc)) << 4)};
+
+  constexpr int NACC = 8;
+  float16_t acc[NACC], tot[NACC];
+#pragma unroll
+  for (int i = 0; i < NACC; ++i)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      acc[i][e] = 0.f;
+      tot[i][e] = 0.f;
+    }
+  const int64_t nst = (w.r1 - w.r0) / 32;
+  const int64_t p0 = w.r0 / 32;  // first panel
+  int since = 0;
+
+  auto main_loop = [&](auto dg_c, auto yd_c, auto role_c) {
+    constexpr bool DG = decltype(dg_c)::value;   // B inside A
+    constexpr bool YD = decltype(yd_c)::value;   // K x M block in this tile
+    constexpr int R = decltype(role_c)::value;
+    constexpr int FA = 4, FB = R == 1 ? 1 : 2;
+    constexpr int NA = R == 2 ? 0 : FA;
+    // direct loads per wave per stage (the same in every wave)
+    constexpr int L = 8 + (DG ? 0 : 4) + (YD ? 1 : 0);
+    // B columns inside the A buffer (diagonal pairs) or the B buffer
+    const int bcol = (DG ? dq * 128 : 0) + wn * 64;
+    auto issue = [&](DmaBufW& b, int64_t s) {
+      const int64_t panel = (p0 + (s < nst ? s : nst - 1)) * Wp;
+      const CVG_GLOBAL char* ah = Zh + (panel + ca) * 64 + lsrc;
+      const CVG_GLOBAL char* al = Zl + (panel + ca) * 64 + lsrc;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int blk = wave * 4 + i;
+        dma16(ah + blk * 1024, b.ah + blk * 512);
+        dma16(al + blk * 1024, b.al + blk * 512);
+      }
+      if constexpr (!DG) {
+        const CVG_GLOBAL char* bh = Zh + (panel + cb) * 64 + lsrc;
+        const CVG_GLOBAL char* bl = Zl + (panel + cb) * 64 + lsrc;
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          const int blk = wave * 2 + i;
+          dma16(bh + blk * 1024, b.bh + blk * 512);
+          dma16(bl + blk * 1024, b.bl + blk * 512);
+        }
+      }
+      if constexpr (YD) {
+        // waves 0, 1: hi columns 0-15, 16-31; waves 2, 3: lo
+        const CVG_GLOBAL char* src = (wave < 2 ? Zh : Zl) + (panel + Kp) * 64 + lsrc;
+        dma16(src + (wave & 1) * 1024, (wave < 2 ? b.yh : b.yl) + (wave & 1) * 512);
+      }
+    };
+    // fragment parts of one stage: lo(A), hi(A), hi(B), lo(B)
+    bf16x8_t fal[NA > 0 ? NA : 1][2], fah[NA > 0 ? NA : 1][2], fbh[FB][2], fbl[FB][2];
+    const int acol = R == 1 ? wn * 128 : wm * 128;
+    auto rd = [&](const __bf16* base, int col0, int ks) -> bf16x8_t {
+      return *(const bf16x8_t*)((const char*)base + col0 * 64 + lfo[ks]);
+    };
+    auto load_al = [&](const DmaBufW& b) {
+#pragma unroll
+      for (int a = 0; a < NA; ++a)
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) fal[a][ks] = rd(b.al, acol + a * 32, ks);
+    };
+    auto load_ah = [&](const DmaBufW& b) {
+#pragma unroll
+      for (int a = 0; a < NA; ++a)
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) fah[a][ks] = rd(b.ah, acol + a * 32, ks);
+    };
+    auto load_bh = [&](const DmaBufW& b) {
+#pragma unroll
+      for (int c = 0; c < FB; ++c)
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks)
+          fbh[c][ks] = R == 1 ? rd(b.yh, c * 32, ks) : rd(DG ? b.ah : b.bh, bcol + c * 32, ks);
+    };
+    auto load_bl = [&](const DmaBufW& b) {
+#pragma unroll
+      for (int c = 0; c < FB; ++c)
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks)
+          fbl[c][ks] = R == 1 ? rd(b.yl, c * 32, ks) : rd(DG ? b.al : b.bl, bcol + c * 32, ks);
+    };
+    // one product over the wave's blocks and both slices
+    auto product = [&](const bf16x8_t (&fa)[NA > 0 ? NA : 1][2], const bf16x8_t (&fb)[FB][2]) {
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+        for (int a = 0; a < NA; ++a)
+#pragma unroll
+          for (int c = 0; c < FB; ++c)
+            acc[a * FB + c] =
+                __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[a][ks], fb[c][ks], acc[a * FB + c], 0, 0, 0);
+    };
+    auto flush = [&]() {
+      since += 32;
+      if (since >= kWFlushRows) {
+        since = 0;
+#pragma unroll
+        for (int i = 0; i < NA * FB; ++i)
+#pragma unroll
+          for (int e = 0; e < 16; ++e) {
+            tot[i][e] += acc[i][e];
+            acc[i][e] = 0.f;
+          }
+      }
+    };
+    // stage s: al, bh of stage s are in registers; `cur` holds stage s,
+    // `next` stage s + 1 (complete after the wait), `cur` receives s + 3
+    // Stage s: lo(A) and hi(B) of stage s are in registers (read during
+    // stage s - 1).  Its hi(A) and lo(B) are read, then the wait and the
+    // barrier: every wave's reads of `cur` are done (it receives stage
+    // s + 3) and stage s + 1 has landed in `next`.  The products follow with
+    // no further wait -- all their operands were complete at the barrier --
+    // while the next stage's parts are read into the registers each product
+    // frees: lo(A) after the first, hi(B) after the second.  The last
+    // product of stage s - 1 is still running on the matrix cores across the
+    // reads and the barrier.  Scheduling barriers keep this order.  The reads
+    // run also past the end (the buffer holds a re-loaded stage).
+    auto step = [&](int64_t s, DmaBufW& cur, const DmaBufW& next) {
+      if constexpr (R != 2) {
+        load_ah(cur);
+        load_bl(cur);
+      }
+      wait_vmcnt_lgkm0<L>();
+      barrier_only();
+      issue(cur, s + kWStages);
+      if constexpr (R != 2) {
+        __builtin_amdgcn_sched_barrier(0);
+        if (s < nst) product(fal, fbh);
+        __builtin_amdgcn_sched_barrier(0);
+        load_al(next);
+        __builtin_amdgcn_sched_barrier(0);
+        if (s < nst) product(fah, fbh);
+        __builtin_amdgcn_sched_barrier(0);
+        load_bh(next);
+        __builtin_amdgcn_sched_barrier(0);
+        if (s < nst) {
+          product(fah, fbl);
+          flush();
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    };
+    issue(sb0, 0);
+    issue(sb1, 1);
+    issue(sb2, 2);
+    wait_vmcnt_lgkm0<2 * L>();
+    barrier_only();
+    if constexpr (R != 2) {
+      load_al(sb0);
+      load_bh(sb0);
+    }
+    for (int64_t s = 0; s < nst; s += kWStages) {
+      step(s, sb0, sb1);
+      step(s + 1, sb1, sb2);
+      step(s + 2, sb2, sb0);
+    }
+    wait_vmcnt_lgkm0<0>();  // the loads past the end
+  };
+  typedef std::integral_constant<int, 0> R0;
+  typedef std::integral_constant<int, 1> R1;
+  typedef std::integral_constant<int, 2> R2;
+  if (!diag) {
+    main_loop(std::false_type{}, std::false_type{}, R0{});
+  } else if (ydiag) {
+    if (role == 0)
+      main_loop(std::true_type{}, std::true_type{}, R0{});
+    else
+      main_loop(std::true_type{}, std::true_type{}, R1{});
+  } else {
+    if (role == 0)
+      main_loop(std::true_type{}, std::false_type{}, R0{});
+    else
+      main_loop(std::true_type{}, std::false_type{}, R2{});
+  }
+  if (role == 2) return;
+  CVG_GLOBAL double* out = slabs + (int64_t)w.slab * K * (K + M);
+  const int64_t W = K + M;
+  if (role == 0) {
+    const int64_t r0 = ca + wm * 128;
+    const int64_t c0 = (xy_tile ? (int64_t)(w.tj - nt) * 128 : cb) + wn * 64;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          const int64_t row = r0 + a * 32 + 8 * (e >> 2) + 4 * lh + (e & 3);
+          const int64_t cl = c0 + b * 32 + lc;
+          const double v = (double)tot[a * 2 + b][e] + (double)acc[a * 2 + b][e];
+          if (row >= K) continue;
+          if (!xy_tile) {
+            if (cl < K) out[row * W + cl] = v;
+          } else if (cl < M) {
+            out[row * W + K + cl] = v;
+          }
+        }
+  } else {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int64_t row = ca + wn * 128 + a * 32 + 8 * (e >> 2) + 4 * lh + (e & 3);
+        if (row < K && lc < M) out[row * W + K + lc] = (double)tot[a][e] + (double)acc[a][e];
+      }
+  }
 }
 
 template <int MODE>
-void launch_mode(int tile, const ProbDesc* pd, const GramWork* work, const int32_t* xcd,
-                 int64_t per_xcd, hipStream_t s) {
+void launch_mode(bool panel_f32, int tile, const ProbDesc* pd, const GramWork* work,
+                 const int32_t* xcd, int64_t per_xcd, hipStream_t s) {
   const unsigned grid = (unsigned)(kXcds * per_xcd);
   if constexpr (MODE == CVGRAM_MODE_BF16X3) {
     if (tile == 64)
       gram_bf16_kernel<64><<<grid, kThreads, 0, s>>>(pd, work, xcd);
-    else
+    else if (tile == 128)
       gram_bf16_kernel<128><<<grid, kThreads, 0, s>>>(pd, work, xcd);
+    else
+      gram_bf16_wide_kernel<<<grid, kThreads, 0, s>>>(pd, work, xcd);
+  } else if constexpr (MODE == CVGRAM_MODE_FP64) {
+    if (panel_f32) {
+      if (tile == 64)
+        gram_kernel<MODE, 64, true><<<grid, kThreads, 0, s>>>(pd, work, xcd);
+      else
+        gram_kernel<MODE, 128, true><<<grid, kThreads, 0, s>>>(pd, work, xcd);
+    } else {
+      if (tile == 64)
+        gram_kernel<MODE, 64, false><<<grid, kThreads, 0, s>>>(pd, work, xcd);
+      else
+        gram_kernel<MODE, 128, false><<<grid, kThreads, 0, s>>>(pd, work, xcd);
+    }
   } else {
     if (tile == 64)
-      gram_kernel<MODE, 64><<<grid, kThreads, 0, s>>>(pd, work, xcd);
+      gram_kernel<MODE, 64, false><<<grid, kThreads, 0, s>>>(pd, work, xcd);
     else
-      gram_kernel<MODE, 128><<<grid, kThreads, 0, s>>>(pd, work, xcd);
+      gram_kernel<MODE, 128, false><<<grid, kThreads, 0, s>>>(pd, work, xcd);
   }
   CVG_LAUNCH_CHECK();
 }
 
 }  // namespace
 
-void launch_gram(cvgram_mode mode, int tile, const ProbDesc* pd, const GramWork* work,
-                 const int32_t* xcd, int64_t per_xcd, hipStream_t s) {
+void launch_gram(cvgram_mode mode, bool panel_f32, int tile, const ProbDesc* pd,
+                 const GramWork* work, const int32_t* xcd, int64_t per_xcd, hipStream_t s) {
   if (per_xcd <= 0) return;
   if (mode == CVGRAM_MODE_FP64)
-    launch_mode<CVGRAM_MODE_FP64>(tile, pd, work, xcd, per_xcd, s);
+    launch_mode<CVGRAM_MODE_FP64>(panel_f32, tile, pd, work, xcd, per_xcd, s);
   else if (mode == CVGRAM_MODE_FP32)
-    launch_mode<CVGRAM_MODE_FP32>(tile, pd, work, xcd, per_xcd, s);
+    launch_mode<CVGRAM_MODE_FP32>(false, tile, pd, work, xcd, per_xcd, s);
   else
-    launch_mode<CVGRAM_MODE_BF16X3>(tile, pd, work, xcd, per_xcd, s);
+    launch_mode<CVGRAM_MODE_BF16X3>(false, tile, pd, work, xcd, per_xcd, s);
 }
 
 }  // namespace cvg

@@ -66,6 +66,11 @@ constexpr int kMaxChunkRows = 1024;
 // accelerator dies (XCDs) of the part; consecutive workgroup ids go to
 // different XCDs round-robin, each XCD with its own L2
 constexpr int kXcds = 8;
+// Gram tile widths, one launch each: 64, 128, and 256 (BF16X3 only: a
+// 256 x 128 tile, two 128-wide row blocks over one 128-wide column block)
+constexpr int kWidths = 3;
+constexpr int kWidth[kWidths] = {64, 128, 256};
+inline int width_index(int tile) { return tile == 64 ? 0 : (tile == 128 ? 1 : 2); }
 // correction tiles
 constexpr int kCorrTile = 32;
 // slab reduction: entries of the K x W slab per workgroup (two per thread)
@@ -82,12 +87,17 @@ struct ProbDesc {
   int64_t N, K, M, W;   // W = K + M
   int64_t Kp, Wp, Np;   // packed widths / padded row count
   int32_t P;            // folds
-  int32_t tile;         // Gram tile edge (64 or 128)
-  int32_t nt;           // Gram tiles along X's columns (Kp / tile)
+  int32_t tile;         // Gram tile width (64, 128 or 256)
+  int32_t nt;           // Gram tile columns along X's columns (Kp / 128 for tile 256)
   int32_t xy_diag;      // X^T Y inside diagonal tiles
   int32_t ddof;
   int32_t x_vec;        // X rows 16-byte aligned and K % 4 == 0
   int32_t mode;         // cvgram_mode: element format of the packed panels
+  // FP64 mode with FP32 input: the panels hold the input's FP32 values as
+  // they are (padding rows: the column's pivot, an FP32 value; padding
+  // columns: 0 with pivot 0), and every reader shifts them in FP64,
+  // z' = (double)x - c, an exact subtraction of two FP32 values
+  int32_t panel_f32;
   // Fold path.  0 (grouped): every fold padded to whole panels, one slab set
   // per fold holding G'_p.  1 (fused, for many small folds): rows packed
   // without padding between folds, the slabs hold row splits of the full
@@ -218,9 +228,10 @@ void launch_fold_stats(const double* tr_mu, const double* tr_std, int32_t p, int
 // gram.hip
 // xcd: kXcds + 1 offsets into work, the item range of each XCD; workgroup b
 // runs item xcd[b % kXcds] + b / kXcds of its range (per_xcd = the largest
-// range, so the grid is kXcds * per_xcd workgroups)
-void launch_gram(cvgram_mode mode, int tile, const ProbDesc* pd, const GramWork* work,
-                 const int32_t* xcd, int64_t per_xcd, hipStream_t s);
+// range, so the grid is kXcds * per_xcd workgroups).  panel_f32: FP64 mode
+// on FP32 panels (ProbDesc::panel_f32, the same for every problem).
+void launch_gram(cvgram_mode mode, bool panel_f32, int tile, const ProbDesc* pd,
+                 const GramWork* work, const int32_t* xcd, int64_t per_xcd, hipStream_t s);
 
 // correct.hip
 // items: (prob, block of 256 entries of K x W, -)

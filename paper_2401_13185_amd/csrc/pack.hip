@@ -309,6 +309,20 @@ __global__ __launch_bounds__(kPackThreads) void pack_kernel(const ProbDesc* __re
           *(CVG_GLOBAL float4_t*)&out[(d0 + rg * 8 + g) * Wp + jp0] = z;
         }
       }
+    } else if constexpr (sizeof(T) == 4) {
+      // FP64 mode on FP32 input: the raw FP32 values, shifted by the Gram
+      // launch as it loads them; a padding row holds the column's pivot (an
+      // FP32 value in this mode) so that it shifts to 0, a padding column 0
+      if (jp0 < Wp) {
+        CVG_GLOBAL float* out = gmem((float*)packed);
+#pragma unroll
+        for (int g = 0; g < 8; ++g) {
+          float4_t z;
+#pragma unroll
+          for (int u = 0; u < 4; ++u) z[u] = js[u] < 0 ? 0.f : (v[g] ? (float)x[g][u] : pivf[u]);
+          *(CVG_GLOBAL float4_t*)&out[(d0 + rg * 8 + g) * Wp + jp0] = z;
+        }
+      }
     } else {
       if (jp0 < Wp) {
         CVG_GLOBAL double* out = gmem((double*)packed);

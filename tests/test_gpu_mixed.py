@@ -1,8 +1,9 @@
 """GPU parity of the mixed-precision modes against the FP64 oracle.
 
 The Gram contraction runs in FP32 MFMA or split-bf16 (bf16x3) MFMA with FP32
-accumulation over row blocks of at most 256 rows combined in FP64; the
-statistics and corrections are FP64.  Bars (relative Frobenius error per
+accumulation over row blocks of at most 256 rows, combined in FP64 (or, on
+bf16x3's 256 x 128 tiles, in FP32 running totals); the statistics and
+corrections are FP64.  Bars (relative Frobenius error per
 fold x class x output, against the oracle):
     fp32    <= MIXED_BOUND["fp32"]
     bf16x3  <= MIXED_BOUND["bf16x3"]
@@ -59,6 +60,8 @@ CASES = [
     (900, 40, 0, 4, "gaussian", "f64"),        # no Y, K below one tile
     (5000, 300, 130, 5, "gaussian", "f32"),    # Y wider than one tile
     (6000, 160, 30, 5, "offset", "f32"),       # 16 < M <= 32 inside diagonal tiles
+    (4000, 700, 0, 4, "spectra", "f32"),       # three 256-column blocks, ragged, no Y
+    (2000, 2100, 7, 3, "offset", "f32"),       # tiles visited in groups (K > 1920)
 ]
 
 
