@@ -548,8 +548,20 @@ struct Batch {
   }
 };
 
-// FP64 mode on FP32 input keeps the panels in FP32 (ProbDesc::panel_f32)
-bool panel_f32(const Batch& b) { return b.mode == CVGRAM_MODE_FP64 && b.dtype == CVGRAM_F32; }
+// FP64 mode on FP32 input keeps the panels in FP32 (ProbDesc::panel_f32):
+// half the pack's writes and the Gram's panel reads, for an FP64 shift per
+// loaded value on the vector units beside the FP64 MFMAs (the Gram launch
+// measured 4.5 % slower, at K = 1024 and K = 4096 alike).  The pack is
+// linear in K, the Gram quadratic, so FP32 panels pay up to about K = 2300
+// (measured: K = 1024 gains 0.9 ms of 19.9, K = 4096 loses 10 ms of 537);
+// they are taken while every problem has K <= kPanelF32MaxK.
+constexpr int64_t kPanelF32MaxK = 2048;
+bool panel_f32(const Batch& b) {
+  if (b.mode != CVGRAM_MODE_FP64 || b.dtype != CVGRAM_F32) return false;
+  for (const auto& p : b.pp)
+    if (p.K > kPanelF32MaxK) return false;
+  return true;
+}
 // pivots are FP32 values in the mixed modes (the FP32 shift is then exact
 // for inputs within a factor 2 of it) and with FP32 panels (a padding row
 // holds the pivot and shifts to exactly 0)
@@ -1060,16 +1072,16 @@ struct Blob {
   }
 };
 
-// bytes of one packed panel element: FP64 mode keeps FP32 input as FP32
-// (ProbDesc::panel_f32)
-size_t elem_bytes(cvgram_mode m, cvgram_dtype dt) {
-  if (m == CVGRAM_MODE_FP64) return dt == CVGRAM_F32 ? 4 : 8;
-  return m == CVGRAM_MODE_FP32 ? 4 : 2;
+// bytes of one packed panel element; FP64 mode on FP32 panels (panel_f32,
+// the same decision the pack and the Gram launch take) uses 4
+size_t elem_bytes(const Batch& b) {
+  if (b.mode == CVGRAM_MODE_FP64) return panel_f32(b) ? 4 : 8;
+  return b.mode == CVGRAM_MODE_FP32 ? 4 : 2;
 }
 
 // Workspace arena + device descriptors + one upload of every plan.
 void allocate_and_upload(Batch& b, const HostLists& L) {
-  const size_t eb = elem_bytes(b.mode, b.dtype);
+  const size_t eb = elem_bytes(b);
   // arena layout per problem
   struct Off {
     size_t pivot, packed, packed_lo, part, fold, tot, tot_part, tr_sum, tr_mean, tr_std, tr_mu,

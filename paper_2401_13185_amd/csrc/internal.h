@@ -93,10 +93,10 @@ struct ProbDesc {
   int32_t ddof;
   int32_t x_vec;        // X rows 16-byte aligned and K % 4 == 0
   int32_t mode;         // cvgram_mode: element format of the packed panels
-  // FP64 mode with FP32 input: the panels hold the input's FP32 values as
-  // they are (padding rows: the column's pivot, an FP32 value; padding
-  // columns: 0 with pivot 0), and every reader shifts them in FP64,
-  // z' = (double)x - c, an exact subtraction of two FP32 values
+  // FP64 mode with FP32 input (and K up to 2048): the panels hold the
+  // input's FP32 values as they are (padding rows: the column's pivot, an
+  // FP32 value; padding columns: 0 with pivot 0), and every reader shifts
+  // them in FP64, z' = (double)x - c, an exact subtraction of two FP32 values
   int32_t panel_f32;
   // Fold path.  0 (grouped): every fold padded to whole panels, one slab set
   // per fold holding G'_p.  1 (fused, for many small folds): rows packed

@@ -162,6 +162,7 @@ __global__ __launch_bounds__(kPackThreads) void pack_kernel(const ProbDesc* __re
   CVG_GLOBAL double* const part = gmem(pdr.part);
   const int64_t n_chunks = pdr.n_chunks;
   const int x_vec = pdr.x_vec;
+  const bool panel_f32 = pdr.panel_f32 != 0;
   const int64_t K = pdr.K, M = pdr.M, Kp = pdr.Kp, W = pdr.W;
   const int t = threadIdx.x, cg = t % kColGroups, rg = t / kColGroups;
   const int64_t jp0 = cb0 + 4 * cg;
@@ -309,10 +310,11 @@ __global__ __launch_bounds__(kPackThreads) void pack_kernel(const ProbDesc* __re
           *(CVG_GLOBAL float4_t*)&out[(d0 + rg * 8 + g) * Wp + jp0] = z;
         }
       }
-    } else if constexpr (sizeof(T) == 4) {
-      // FP64 mode on FP32 input: the raw FP32 values, shifted by the Gram
-      // launch as it loads them; a padding row holds the column's pivot (an
-      // FP32 value in this mode) so that it shifts to 0, a padding column 0
+    } else if (sizeof(T) == 4 && panel_f32) {
+      // FP64 mode on FP32 panels (FP32 input, ProbDesc::panel_f32): the raw
+      // FP32 values, shifted by the Gram launch as it loads them; a padding
+      // row holds the column's pivot (an FP32 value in this mode) so that it
+      // shifts to 0, a padding column 0
       if (jp0 < Wp) {
         CVG_GLOBAL float* out = gmem((float*)packed);
 #pragma unroll

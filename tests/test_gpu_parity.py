@@ -129,6 +129,9 @@ def test_fp64_gaussian_workload_all_classes(ddof):
     (4000, 150, 24, 6, "spectra", "f64"),     # 16 < M <= 32: two XtY blocks per diagonal row
     (1500, 2100, 3, 3, "spectra", "f64"),     # 17 tile columns: tiles in 8 x 8 groups, dealt
                                               # round-robin over the XCDs; ragged last group
+    (1500, 2048, 3, 3, "offset", "f32"),      # FP32 input: FP32 panels up to K = 2048 ...
+    (1500, 2049, 3, 3, "offset", "f32"),      # ... FP64 panels beyond (pack, allocation and
+                                              # Gram agree on the element type)
 ])
 def test_fp64_ragged_shapes(n, k, m, p, values, dtype):
     shape = G.Shape(f"{values} N={n} K={k} M={m} P={p}", n, k, m, p, dtype, values, "dirichlet")
