@@ -632,40 +632,11 @@ def mixed_block(cv, torch, G, dev, args):
     return res
 
 
-def log2_bucket(v):
-    """Smallest b with 2**b >= v (the autotuning table's rounding)."""
-    b = 0
-    while (1 << b) < v and b < 62:
-        b += 1
-    return b
-
-
-def autotune_batch(cv, torch, probs, shapes, mode):
-    """cvgram_autotune on the first problem of every shape bucket the batch's
-    problems fall in (the tuning table's key: mode, dtype, and K, M + 1 and N
-    rounded up to powers of two); cvgram_batch_create then takes each
-    problem's Gram tile edge and work-list size from the table."""
-    t0 = time.perf_counter()
-    tuned = {}
-    per_problem = []
-    for (X, Y, f), s in zip(probs, shapes):
-        key = (log2_bucket(s.k), log2_bucket(s.m + 1), log2_bucket(s.n))
-        if key not in tuned:
-            tuned[key] = cv.cvgram_autotune(X, Y, f, mode=mode)
-        per_problem.append(tuned[key])
-    torch.cuda.synchronize()
-    tiles, items = {}, {}
-    for tile, it in per_problem:
-        tiles[str(tile)] = tiles.get(str(tile), 0) + 1
-        items[str(it)] = items.get(str(it), 0) + 1
-    return {"buckets": len(tuned), "seconds": round(time.perf_counter() - t0, 2),
-            "problems_by_tile": tiles, "problems_by_target_items": items}
-
-
 def batched_block(cv, torch, G, dev, args):
     """256 independent problems of different N, K, M, P (spectra, FP32,
-    Dirichlet(2) folds) in one batch: the Gram launch autotuned per shape
-    bucket, the whole pipeline (12 classes per fold) captured in a HIP graph,
+    Dirichlet(2) folds) in one batch: the Gram launches autotuned in the
+    batch (cvgram_batch_autotune), the whole pipeline (12 classes per fold)
+    captured in a HIP graph,
     replayed `batch_steps` times, FP64 and bf16x3 on the same inputs;
     bf16x3's worst relative Frobenius error against FP64 over every problem,
     fold and class."""
@@ -681,8 +652,12 @@ def batched_block(cv, torch, G, dev, args):
            "f_alg_total": flops, "modes": {}}
     outs = {}
     for mode in ("fp64", "bf16x3"):
-        tune = autotune_batch(cv, torch, probs, shapes, mode)
-        log(f"batched mode {mode}: autotuned {tune['buckets']} shape buckets in {tune['seconds']} s")
+        t0 = time.perf_counter()
+        tile, items, tms = cv.cvgram_batch_autotune(probs, mode=mode)
+        tune = {"max_tile": tile, "target_items": items, "gram_stage_ms": tms,
+                "seconds": round(time.perf_counter() - t0, 2)}
+        log(f"batched mode {mode}: autotuned in the batch: tile <= {tile}, {items} items "
+            f"({tune['seconds']} s)")
         t0 = time.perf_counter()
         b = cv.cvgram_batch_create(probs, ddof=1, mode=mode)
         torch.cuda.synchronize()

@@ -21,7 +21,8 @@ __all__ = [
     "cvgram_destroy", "cvgram_status_string", "cvgram_last_error_message", "cvgram_version",
     "cvgram_set_stage_timing", "cvgram_stage_times", "cvgram_trim_cache",
     "cvgram_batch_create", "cvgram_batch_run", "cvgram_batch_run_eager",
-    "cvgram_batch_problem_info", "cvgram_batch_destroy", "cvgram_autotune", "Batch",
+    "cvgram_batch_problem_info", "cvgram_batch_destroy", "cvgram_autotune",
+    "cvgram_batch_autotune", "Batch",
     "CVGram", "MODES", "XTX_CLASSES", "XTY_CLASSES",
 ]
 
@@ -82,6 +83,8 @@ _SIGS = {
     "cvgram_batch_destroy": (_int, [_vp]),
     "cvgram_autotune": (_int, [_vp, _vp, _vp, _i64, _i64, _i64, _int, _int, _vp,
                                ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
+    "cvgram_batch_autotune": (_int, [_vp, _i32, _int, _int, _vp, ctypes.POINTER(_i32),
+                                     ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_double)]),
     "cvgram_stage_times": (_int, [_vp, ctypes.POINTER(ctypes.c_double), _i32]),
     "cvgram_trim_cache": (_int, []),
 }
@@ -448,6 +451,31 @@ def cvgram_batch_create(problems, ddof=1, mode="fp64", stream=None) -> Batch:
     _check(lib.cvgram_batch_create(arr, len(problems), 1 if dt == torch.float64 else 0, int(ddof),
                                    MODES[mode], s, ctypes.byref(out)))
     return Batch(out.value, keep, outs, mode, s)
+
+
+def cvgram_batch_autotune(problems, mode="fp64", stream=None):
+    """Tune the Gram launches of a batch of (X, Y, fold_id) problems in the
+    batch itself; returns (widest tile, target items, Gram-stage ms).  A
+    following cvgram_batch_create of these problems uses the choice."""
+    torch = _torch()
+    if not problems:
+        raise ValueError("need at least one problem")
+    dt = problems[0][0].dtype
+    if dt not in (torch.float32, torch.float64):
+        raise TypeError("X must be float32 or float64")
+    if mode not in MODES:
+        raise ValueError(f"mode must be one of {sorted(MODES)}")
+    arr = (_Problem * len(problems))()
+    for i, (X, Y, f) in enumerate(problems):
+        N, K = X.shape
+        M = 0 if Y is None else Y.shape[1]
+        arr[i] = _Problem(_ptr(X, "X"), _ptr(Y, "Y") if M else None,
+                          _ptr(f, "fold_id", torch.int32, N), N, K, M, None, None)
+    tile, items, ms = _i32(), _i32(), ctypes.c_double()
+    _check(load().cvgram_batch_autotune(arr, len(problems), 1 if dt == torch.float64 else 0,
+                                        MODES[mode], _stream_ptr(stream), ctypes.byref(tile),
+                                        ctypes.byref(items), ctypes.byref(ms)))
+    return tile.value, items.value, ms.value
 
 
 def cvgram_batch_run(b: Batch):

@@ -393,6 +393,12 @@ Config default_config(cvgram_mode mode, int64_t K) {
   return c;
 }
 
+// the widest tile the built-in rule gives a problem of this K (no override)
+int natural_tile(cvgram_mode mode, int64_t K) {
+  if (K <= 64) return 64;
+  return (mode == CVGRAM_MODE_BF16X3 && K > 128) ? 256 : 128;
+}
+
 Config choose_config(cvgram_mode mode, cvgram_dtype dt, int64_t K, int64_t M, int64_t N) {
   TuneTable& tt = tune_table();
   std::lock_guard<std::mutex> g(tt.mu);
@@ -868,7 +874,13 @@ void plan_layout(Batch& b, HostLists& L) {
   // tile width is launched apart, so each launch is split for its own work)
   int64_t gram_rows[kWidths] = {};
   for (auto& p : b.pp) {
-    p.cfg = b.force_cfg ? b.forced : choose_config(b.mode, b.dtype, p.K, p.M, p.N);
+    if (b.force_cfg) {
+      // a candidate's tile width caps each problem's own widest one
+      p.cfg = b.forced;
+      p.cfg.tile = std::min(b.forced.tile, natural_tile(b.mode, p.K));
+    } else {
+      p.cfg = choose_config(b.mode, b.dtype, p.K, p.M, p.N);
+    }
     const int T = p.cfg.tile;
     p.fused = choose_fused(p);
     p.poff.assign(p.P + 1, 0);
@@ -1770,6 +1782,54 @@ cvgram_status cvgram_batch_destroy(cvgram_batch_t bb) {
 // ---------------------------------------------------------------------------
 // autotuner
 // ---------------------------------------------------------------------------
+}  // extern "C"
+
+namespace {
+
+// Gram-stage time (pack through slab reduction, the best of three eager
+// runs after a warm one) of the problems `pp` planned with the forced
+// configuration `cfg` (each problem's tile capped by its own widest).  The
+// candidate's workspace goes back to the cache on every path.
+double time_candidate(const std::vector<ProbPlan>& pp, cvgram_dtype dtype, cvgram_mode mode,
+                      hipStream_t stream, const Config& cfg, cvgram_status& st) {
+  Batch b;
+  struct Releaser {
+    Batch& b;
+    ~Releaser() {
+      (void)hipStreamSynchronize(b.stream);
+      b.release();
+    }
+  } releaser{b};
+  b.stream = stream;
+  b.mode = mode;
+  b.dtype = dtype;
+  b.ddof = 1;
+  b.timing = true;
+  b.force_cfg = true;
+  b.forced = cfg;
+  b.pp = pp;
+  CVG_HIP(hipGetDevice(&b.device));
+  st = prepare(b);
+  if (st != CVGRAM_OK) return 1e300;
+  run_pipeline(b, true);  // warm
+  double ms = 1e300;
+  for (int rep = 0; rep < 3; ++rep) {
+    run_pipeline(b, true);
+    CVG_HIP(hipEventSynchronize(b.ev[4]));
+    float t = 0.f;
+    CVG_HIP(hipEventElapsedTime(&t, b.ev[1], b.ev[4]));
+    ms = std::min(ms, (double)t);
+  }
+  return ms;
+}
+
+const int kTuneTiles[3] = {64, 128, 256};
+const int64_t kTuneItems[4] = {512, 1024, 2048, 4096};
+
+}  // namespace
+
+extern "C" {
+
 cvgram_status cvgram_autotune(const void* X, const void* Y, const int32_t* fold_id, int64_t N,
                               int64_t K, int64_t M, cvgram_dtype dtype, cvgram_mode mode,
                               void* stream, int32_t* tile, int32_t* target_items) {
@@ -1779,57 +1839,30 @@ cvgram_status cvgram_autotune(const void* X, const void* Y, const int32_t* fold_
   if (dtype != CVGRAM_F32 && dtype != CVGRAM_F64) return fail(CVGRAM_EINVAL, "bad dtype");
   if (mode != CVGRAM_MODE_FP64 && mode != CVGRAM_MODE_FP32 && mode != CVGRAM_MODE_BF16X3)
     return fail(CVGRAM_EINVAL, "bad mode");
-  const int tiles[3] = {64, 128, 256};
-  const int64_t items[4] = {512, 1024, 2048, 4096};
+  ProbPlan p;
+  p.X = X;
+  p.Y = M > 0 ? Y : nullptr;
+  p.fold = fold_id;
+  p.N = N;
+  p.K = K;
+  p.M = M;
+  p.W = K + M;
+  const std::vector<ProbPlan> pp{p};
   Config best;
   double best_ms = 1e300;
   try {
-    for (int ti = 0; ti < 3; ++ti) {
-      if (tiles[ti] == 64 && K > 1024) continue;  // too many tiles to pay off
-      // 256 x 128 tiles: BF16X3 only, and not where they would pad K to 256
-      if (tiles[ti] == 256 && (mode != CVGRAM_MODE_BF16X3 || K <= 128)) continue;
-      for (int ii = 0; ii < 4; ++ii) {
-        Batch b;
-        // the candidate's workspace goes back to the cache on every path
-        struct Releaser {
-          Batch& b;
-          ~Releaser() {
-            (void)hipStreamSynchronize(b.stream);
-            b.release();
-          }
-        } releaser{b};
-        b.stream = (hipStream_t)stream;
-        b.mode = mode;
-        b.dtype = dtype;
-        b.ddof = 1;
-        b.timing = true;
-        b.force_cfg = true;
-        b.forced.tile = tiles[ti];
-        b.forced.target_items = items[ii];
-        ProbPlan p;
-        p.X = X;
-        p.Y = M > 0 ? Y : nullptr;
-        p.fold = fold_id;
-        p.N = N;
-        p.K = K;
-        p.M = M;
-        p.W = K + M;
-        b.pp.push_back(p);
-        CVG_HIP(hipGetDevice(&b.device));
-        st = prepare(b);
+    for (int t : kTuneTiles) {
+      if (t == 64 && K > 1024) continue;   // too many tiles to pay off
+      if (t > natural_tile(mode, K)) continue;  // wider than the problem takes
+      for (int64_t it : kTuneItems) {
+        Config c;
+        c.tile = t;
+        c.target_items = it;
+        const double ms = time_candidate(pp, dtype, mode, (hipStream_t)stream, c, st);
         if (st != CVGRAM_OK) return st;
-        run_pipeline(b, true);   // warm
-        double ms = 1e300;
-        for (int rep = 0; rep < 3; ++rep) {
-          run_pipeline(b, true);
-          CVG_HIP(hipEventSynchronize(b.ev[4]));
-          float t = 0.f;
-          CVG_HIP(hipEventElapsedTime(&t, b.ev[1], b.ev[4]));
-          ms = std::min(ms, (double)t);
-        }
         if (ms < best_ms) {
           best_ms = ms;
-          best = b.forced;
+          best = c;
         }
       }
     }
@@ -1845,6 +1878,71 @@ cvgram_status cvgram_autotune(const void* X, const void* Y, const int32_t* fold_
   }
   if (tile) *tile = best.tile;
   if (target_items) *target_items = (int32_t)best.target_items;
+  return CVGRAM_OK;
+}
+
+cvgram_status cvgram_batch_autotune(const cvgram_problem* problems, int32_t n, cvgram_dtype dtype,
+                                    cvgram_mode mode, void* stream, int32_t* max_tile,
+                                    int32_t* target_items, double* gram_ms) {
+  set_error("");
+  if (!problems || n < 1) return fail(CVGRAM_EINVAL, "need at least one problem");
+  if (dtype != CVGRAM_F32 && dtype != CVGRAM_F64) return fail(CVGRAM_EINVAL, "bad dtype");
+  if (mode != CVGRAM_MODE_FP64 && mode != CVGRAM_MODE_FP32 && mode != CVGRAM_MODE_BF16X3)
+    return fail(CVGRAM_EINVAL, "bad mode");
+  std::vector<ProbPlan> pp;
+  int widest = 64;
+  for (int32_t i = 0; i < n; ++i) {
+    const cvgram_problem& q = problems[i];
+    cvgram_status st = check_problem(q.X, q.Y, q.fold_id, q.N, q.K, q.M);
+    if (st != CVGRAM_OK) return fail(st, "problem " + std::to_string(i) + ": " + g_last_error);
+    ProbPlan p;
+    p.X = q.X;
+    p.Y = q.M > 0 ? q.Y : nullptr;
+    p.fold = q.fold_id;
+    p.N = q.N;
+    p.K = q.K;
+    p.M = q.M;
+    p.W = q.K + q.M;
+    pp.push_back(p);
+    widest = std::max(widest, natural_tile(mode, q.K));
+  }
+  Config best;
+  double best_ms = 1e300;
+  cvgram_status st = CVGRAM_OK;
+  try {
+    for (int t : kTuneTiles) {
+      if (t > widest) continue;
+      for (int64_t it : kTuneItems) {
+        Config c;
+        c.tile = t;
+        c.target_items = it;
+        const double ms = time_candidate(pp, dtype, mode, (hipStream_t)stream, c, st);
+        if (st != CVGRAM_OK) return st;
+        if (ms < best_ms) {
+          best_ms = ms;
+          best = c;
+        }
+      }
+    }
+  } catch (const Fail& f) {
+    return f.st;
+  }
+  {
+    // every problem's bucket takes the batch's choice (its tile capped by
+    // the problem's widest)
+    TuneTable& tt = tune_table();
+    std::lock_guard<std::mutex> g(tt.mu);
+    tune_load_locked(tt);
+    for (const ProbPlan& p : pp) {
+      Config c = best;
+      c.tile = std::min(best.tile, natural_tile(mode, p.K));
+      tt.t[tune_key(mode, dtype, p.K, p.M, p.N)] = c;
+    }
+    tune_save_locked(tt);
+  }
+  if (max_tile) *max_tile = best.tile;
+  if (target_items) *target_items = (int32_t)best.target_items;
+  if (gram_ms) *gram_ms = best_ms;
   return CVGRAM_OK;
 }
 

@@ -18,14 +18,19 @@
 // no floating-point atomics).
 //
 // Arithmetic per mode:
-//   FP64    v_mfma_f64_16x16x4_f64 on FP64 panels, FP64 accumulation.
+//   FP64    v_mfma_f64_16x16x4_f64 on FP64 panels (or on FP32 panels of
+//           FP32 input, shifted to FP64 as they are loaded), FP64
+//           accumulation.
 //   FP32    v_mfma_f32_16x16x4_f32 on FP32 panels.
-//   BF16X3  v_mfma_f32_16x16x32_bf16, three products hi*hi + hi*lo + lo*hi
-//           per FP32 product from the hi/lo bf16 panels.
+//   BF16X3  three products hi*hi + hi*lo + lo*hi per FP32 product from the
+//           hi/lo bf16 panels: v_mfma_f32_16x16x32_bf16 on 64- and 128-wide
+//           tiles, v_mfma_f32_32x32x16_bf16 on 256 x 128 tiles (the kernel
+//           at the end of this file).
 // The FP32-accumulating modes add their FP32 tile into an FP64 register
 // tile and clear it every 64 rows (FP32: 16 accumulating MFMAs) or 256 rows
-// (BF16X3: 24, each summing 32 products), so FP32 rounding does not grow
-// with the fold size.  The accumulated rounding error of a block is about
+// (BF16X3: 24, each summing 32 products; on 256 x 128 tiles into FP32
+// totals every 512 rows), so FP32 rounding does not grow with the fold
+// size.  The accumulated rounding error of a block is about
 // half an FP32 ulp per accumulating step, and it does not average out on
 // entries that sum positive products (the diagonal).  On the offset data
 // of the precision-stress workload (N=1e6, K=1024) the FP32 mode's worst
@@ -246,52 +251,44 @@ __device__ inline void mma_f32(const float* A, int lda, int acol0, const float* 
 // 32 or with 64 banks of 4 bytes).
 __device__ __forceinline__ int swz(int c) { return ((c >> 1) ^ (c >> 2)) & 3; }
 
-// One stage's fragments for NA x NB output blocks of 32 x 32 (the operands
-// of v_mfma_f32_32x32x16_bf16: per lane one column of a 32-column block and
-// 8 consecutive rows of a 16-row slice; a 32-row stage is two slices).
-// A columns from `acol0`, B columns from `bcol0` (multiples of 32) of the
-// swizzled buffers; lfo[ks] is the lane's byte offset for slice ks:
-// (lane % 32) * 64 + (((2 ks + lane / 32) ^ swz(lane % 32)) << 4).  The 32
-// lanes of a half-wave read one 16-byte chunk of 32 consecutive columns:
-// every 16 of them fall in 16 different bank groups.
+// accumulator of a 32 x 32 output block (v_mfma_f32_32x32x16_bf16, the
+// 256 x 128 kernel)
 typedef float float16_t __attribute__((ext_vector_type(16)));
+
+// One stage's fragments for NA x NB blocks of 16 x 16: A columns from
+// `acol0`, B columns from `bcol0` (multiples of 16) of the swizzled buffers;
+// `lfo` is the lane's byte offset fc * 64 + ((fr ^ swz(fc)) << 4).
 template <int NA, int NB>
 struct Frags {
-  bf16x8_t ah[NA][2], al[NA][2], bh[NB][2], bl[NB][2];
+  bf16x8_t ah[NA], al[NA], bh[NB], bl[NB];
   __device__ void load(const __bf16* Ah, const __bf16* Al, int acol0, const __bf16* Bh,
-                       const __bf16* Bl, int bcol0, const int (&lfo)[2]) {
+                       const __bf16* Bl, int bcol0, int lfo) {
 #pragma unroll
-    for (int ks = 0; ks < 2; ++ks) {
+    for (int a = 0; a < NA; ++a) {
+      const int off = (acol0 + a * 16) * 64 + lfo;
+      ah[a] = *(const bf16x8_t*)((const char*)Ah + off);
+      al[a] = *(const bf16x8_t*)((const char*)Al + off);
+    }
 #pragma unroll
-      for (int a = 0; a < NA; ++a) {
-        const int off = (acol0 + a * 32) * 64 + lfo[ks];
-        ah[a][ks] = *(const bf16x8_t*)((const char*)Ah + off);
-        al[a][ks] = *(const bf16x8_t*)((const char*)Al + off);
-      }
-#pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        const int off = (bcol0 + b * 32) * 64 + lfo[ks];
-        bh[b][ks] = *(const bf16x8_t*)((const char*)Bh + off);
-        bl[b][ks] = *(const bf16x8_t*)((const char*)Bl + off);
-      }
+    for (int b = 0; b < NB; ++b) {
+      const int off = (bcol0 + b * 16) * 64 + lfo;
+      bh[b] = *(const bf16x8_t*)((const char*)Bh + off);
+      bl[b] = *(const bf16x8_t*)((const char*)Bl + off);
     }
   }
 };
 
-// One of the three products over all blocks and both slices (consecutive
-// MFMAs update different accumulators): pass 0 lo(A) hi(B), pass 1 hi(A)
-// lo(B), pass 2 hi(A) hi(B).
+// One of the three products over all blocks (consecutive MFMAs update
+// different accumulators): pass 0 lo(A) hi(B), pass 1 hi(A) lo(B), pass 2
+// hi(A) hi(B).
 template <int PASS, int NA, int NB, int NACC>
-__device__ inline void mfma_pass(const Frags<NA, NB>& f, float16_t (&acc)[NACC]) {
+__device__ inline void mfma_pass(const Frags<NA, NB>& f, float4_t (&acc)[NACC]) {
 #pragma unroll
-  for (int ks = 0; ks < 2; ++ks)
+  for (int a = 0; a < NA; ++a)
 #pragma unroll
-    for (int a = 0; a < NA; ++a)
-#pragma unroll
-      for (int b = 0; b < NB; ++b)
-        acc[a * NB + b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-            PASS == 0 ? f.al[a][ks] : f.ah[a][ks], PASS == 1 ? f.bl[b][ks] : f.bh[b][ks],
-            acc[a * NB + b], 0, 0, 0);
+    for (int b = 0; b < NB; ++b)
+      acc[a * NB + b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+          PASS == 0 ? f.al[a] : f.ah[a], PASS == 1 ? f.bl[b] : f.bh[b], acc[a * NB + b], 0, 0, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -737,11 +734,9 @@ template <int BM>
 __global__ __launch_bounds__(kThreads) void gram_bf16_kernel(const ProbDesc* __restrict__ pds,
                                                              const GramWork* __restrict__ work,
                                                              const int32_t* __restrict__ xcd) {
-  constexpr int WT = BM / 2;
-  // 32 x 32 output blocks: a wave's WT x WT sub-tile (role 0) is NW x NW of
-  // them, the BM x 32 K-by-M block of a diagonal tile (role 1) NY x 1
-  constexpr int NW = WT / 32, NY = BM / 32;
-  constexpr int NACC = NW * NW > NY ? NW * NW : NY;
+  constexpr int MODE = CVGRAM_MODE_BF16X3;
+  constexpr int WT = BM / 2, NW = WT / 16, NY = BM / 16;
+  constexpr int NACC = NW * NW > 2 * NY ? NW * NW : 2 * NY;
   constexpr int IA = BM / 64;  // 1 KB direct loads per wave per array per stage
   __shared__ __attribute__((aligned(1024))) DmaBuf<BM> sb0, sb1, sb2, sb3;
 
@@ -759,6 +754,7 @@ __global__ __launch_bounds__(kThreads) void gram_bf16_kernel(const ProbDesc* __r
   const int t = threadIdx.x, lane = t & 63;
   const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
   const int wm = wave >> 1, wn = wave & 1;
+  const int fr = lane >> 4, fc = lane & 15;
 
   const bool xy_tile = w.tj >= nt;
   const bool diag = !xy_tile && w.ti == w.tj;
@@ -771,18 +767,15 @@ __global__ __launch_bounds__(kThreads) void gram_bf16_kernel(const ProbDesc* __r
   // columns (a permutation of the block's chunks: the loads stay coalesced),
   // and this lane's fragment chunk inside a buffer
   const int lsrc = (lane >> 2) * 64 + (((lane & 3) ^ swz(lane >> 2)) << 4);
-  const int lc = lane & 31, lh = lane >> 5;
-  const int lfo[2] = {lc * 64 + ((lh ^ swz(lc)) << 4), lc * 64 + (((2 + lh) ^ swz(lc)) << 4)};
+  const int lfo = fc * 64 + ((fr ^ swz(fc)) << 4);
 
-  float16_t acc[NACC];
-  double a64[NACC][16];
+  float4_t acc[NACC];
+  double a64[NACC][4];
 #pragma unroll
   for (int i = 0; i < NACC; ++i) {
+    acc[i] = float4_t{0, 0, 0, 0};
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      acc[i][e] = 0.f;
-      a64[i][e] = 0.0;
-    }
+    for (int e = 0; e < 4; ++e) a64[i][e] = 0.0;
   }
   const int64_t nst = (w.r1 - w.r0) / 32;
   const int64_t p0 = w.r0 / 32;  // first panel
@@ -795,10 +788,8 @@ __global__ __launch_bounds__(kThreads) void gram_bf16_kernel(const ProbDesc* __r
 #pragma unroll
       for (int i = 0; i < NACC; ++i) {
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-          a64[i][e] += (double)acc[i][e];
-          acc[i][e] = 0.f;
-        }
+        for (int e = 0; e < 4; ++e) a64[i][e] += (double)acc[i][e];
+        acc[i] = float4_t{0, 0, 0, 0};
       }
     }
   };
@@ -810,7 +801,7 @@ __global__ __launch_bounds__(kThreads) void gram_bf16_kernel(const ProbDesc* __r
     constexpr bool DG = decltype(diag_c)::value;
     constexpr bool YD = decltype(ydiag_c)::value;
     constexpr int R = decltype(role_c)::value;
-    constexpr int FA = R == 1 ? NY : NW, FB = R == 1 ? 1 : NW;
+    constexpr int FA = R == 1 ? NY : NW, FB = R == 1 ? 2 : NW;
     // direct loads per wave per stage (all waves issue the same number)
     constexpr int L = IA * (DG ? 2 : 4) + (YD ? 1 : 0);
     // stage s (clamped to the last one) into buffer b
@@ -905,37 +896,9 @@ __global__ __launch_bounds__(kThreads) void gram_bf16_kernel(const ProbDesc* __r
   }
   if (role == 2) return;
   CVG_GLOBAL double* out = slabs + (int64_t)w.slab * K * (K + M);
-  // lane's entries of block (a, b): column b * 32 + lane % 32, rows
-  // a * 32 + 8 (e / 4) + 4 (lane / 32) + e % 4 for e = 0 .. 15
-  const int64_t W = K + M;
-  if (role == 0) {
-    const int64_t r0 = ca + wm * WT;
-    const int64_t c0 = (xy_tile ? (int64_t)(w.tj - nt) * BM : cb) + wn * WT;
-#pragma unroll
-    for (int a = 0; a < NW; ++a)
-#pragma unroll
-      for (int b = 0; b < NW; ++b)
-#pragma unroll
-        for (int e = 0; e < 16; ++e) {
-          const int64_t row = r0 + a * 32 + 8 * (e >> 2) + 4 * lh + (e & 3);
-          const int64_t cl = c0 + b * 32 + lc;
-          const double v = a64[a * NW + b][e] + (double)acc[a * NW + b][e];
-          if (row >= K) continue;
-          if (!xy_tile) {
-            if (cl < K) out[row * W + cl] = v;
-          } else if (cl < M) {
-            out[row * W + K + cl] = v;
-          }
-        }
-  } else {
-#pragma unroll
-    for (int a = 0; a < NY; ++a)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const int64_t row = ca + a * 32 + 8 * (e >> 2) + 4 * lh + (e & 3);
-        if (row < K && lc < M) out[row * W + K + lc] = a64[a][e] + (double)acc[a][e];
-      }
-  }
+  auto value = [&](int i, int e) -> double { return a64[i][e] + (double)acc[i][e]; };
+  store_tile<MODE, BM, NACC>(out, role, xy_tile, ca, xy_tile ? (int64_t)(w.tj - nt) * BM : cb, wm,
+                             wn, fr, fc, K, M, value);
 }
 
 // ---------------------------------------------------------------------------
@@ -949,17 +912,23 @@ __global__ __launch_bounds__(kThreads) void gram_bf16_kernel(const ProbDesc* __r
 // tj = 2 ti the lower half of A is below the diagonal, and those two waves
 // compute the 256 x 32 K-by-M block instead (M <= 32) or idle.
 // Four waves, wave (wm, wn) = A columns 128 wm, B columns 64 wn: 4 x 2
-// output blocks of 32 x 32.  Per 32-row stage each wave reads 96 KB... of
-// fragments in three parts streamed around the three products
-// (lo(A) hi(B), hi(A) hi(B), hi(A) lo(B)): a part is re-read for the next
-// stage as soon as the product that used it last is issued, so one register
-// set serves.  The ring has three stages of 52 KB; the barrier after each
-// stage's first product frees that stage's buffer for the stage three ahead.
+// output blocks of 32 x 32 (v_mfma_f32_32x32x16_bf16).  Per 32-row stage
+// each wave reads 24 KB of fragments from LDS, in four parts around the
+// three products (lo(A) hi(B), hi(A) hi(B), hi(A) lo(B)): a part is re-read
+// for the next stage as soon as the product that used it last is issued,
+// so one register set serves.  The ring has three stages of 52 KB; the
+// barrier at each stage frees the previous stage's buffer for the stage
+// three ahead.  Per fragment byte read from LDS the 128 x 64 wave tile does
+// 4/3 the MFMA work of a 64 x 64 one, and per panel byte loaded the
+// 256 x 128 workgroup tile 4/3 that of a 128 x 128 one.
 // Accumulation: FP32 MFMA accumulators added into FP32 running totals every
-// 256 rows (VALU adds round to nearest) -- the totals take the place of the
-// FP64 copies, which leave no room for a 128 x 64 wave tile.
+// 512 rows (VALU adds round to nearest) -- the totals take the place of the
+// FP64 copies, which leave no room for a 128 x 64 wave tile.  A block of
+// 512 rows is 96 accumulating MFMAs; the accumulator's rounding is about
+// half an FP32 ulp per step and does not average out on sums of positive
+// products, so a block's worst relative error is about 48 ulp (3e-6).
 constexpr int kWStages = 3;
-constexpr int kWFlushRows = 256;
+constexpr int kWFlushRows = 512;
 struct DmaBufW {
   // [column][32 rows] bf16, swizzled 16-byte chunks (see swz)
   __bf16 ah[256 * 32], al[256 * 32], bh[128 * 32], bl[128 * 32], yh[kYW * 32], yl[kYW * 32];
@@ -1102,8 +1071,6 @@ __global__ __launch_bounds__(kThreads) void gram_bf16_wide_kernel(
           }
       }
     };
-    // stage s: al, bh of stage s are in registers; `cur` holds stage s,
-    // `next` stage s + 1 (complete after the wait), `cur` receives s + 3
     // Stage s: lo(A) and hi(B) of stage s are in registers (read during
     // stage s - 1).  Its hi(A) and lo(B) are read, then the wait and the
     // barrier: every wave's reads of `cur` are done (it receives stage

@@ -5,7 +5,8 @@ N, K, M and P in one pipeline (one launch per stage), captured in a HIP graph.
   relative Frobenius; bf16x3: the stated bound);
 * graph replays against eager runs of the same pipeline, bit for bit, with
   the inputs changed between replays and eager work in between;
-* the autotuner returns a valid choice that later plans use.
+* the autotuners (one problem, a whole batch) return valid choices that
+  later plans use, with results that stay within the mode's bound.
 """
 from __future__ import annotations
 
@@ -173,13 +174,36 @@ def test_autotune_returns_valid_choice_and_results_stay_correct():
     Xd, Yd, fd = _t(X), _t(Y), _t(f)
     tile, items = cv.cvgram_autotune(Xd, Yd, fd, mode="bf16x3")
     print(f"[autotune] tile={tile} items={items}", flush=True)
-    assert tile in (64, 128) and items in (512, 1024, 2048, 4096)
+    assert tile in (64, 128, 256) and items in (512, 1024, 2048, 4096)
     h = cv.cvgram_create(Xd, Yd, fd, 1, 1, 1, 1, mode="bf16x3")   # uses the tuned bucket
     xx, xy = cv.cvgram_folds_all(h, 0, 6)
     oxx, oxy = O.fold_all_classes(X, Y, f, 2, ddof=1)
     for c in range(4):
         assert _relerr(xx[2, c].cpu().numpy(), oxx[c]) <= BF16X3_BOUND
     cv.cvgram_destroy(h)
+
+
+@pytest.mark.parametrize("mode", ["fp64", "bf16x3"])
+def test_batch_autotune_choice_used_and_correct(mode):
+    probs = _problems("f32")
+    dev_probs = [(_t(X), _t(Y) if Y.shape[1] else None, _t(f)) for X, Y, f in probs]
+    tile, items, ms = cv.cvgram_batch_autotune(dev_probs, mode=mode)
+    print(f"[batch autotune] mode={mode} tile={tile} items={items} gram_ms={ms:.4f}", flush=True)
+    assert tile in (64, 128, 256) and items in (512, 1024, 2048, 4096) and ms > 0
+    if mode == "fp64":
+        assert tile <= 128          # FP64 tiles stop at 128
+    b = cv.cvgram_batch_create(dev_probs, ddof=1, mode=mode)
+    cv.cvgram_batch_run(b)
+    torch.cuda.synchronize()
+    bound = FP64_TOL if mode == "fp64" else BF16X3_BOUND
+    for i, (X, Y, f) in enumerate(probs):
+        P, _ = cv.cvgram_batch_problem_info(b, i)
+        xx = b.outs[i][0].cpu().numpy()
+        for q in (0, P - 1):
+            oxx, _ = O.fold_all_classes(X, Y, f, q, ddof=1)
+            for c in range(4):
+                assert _relerr(xx[q, c], oxx[c]) <= bound, (mode, i, q, c)
+    cv.cvgram_batch_destroy(b)
 
 
 def test_batch_full_size_sampled():
