@@ -1520,7 +1520,7 @@ cvgram_status cvgram_ridge(cvgram_t h, int32_t p0, int32_t p1, const double* lam
     return fail(CVGRAM_ENOTSCALABLE, "partitioning is not scalable for this ddof");
   const int32_t nf = p1 - p0;
   const int64_t K = pp.K, M = pp.M, nmat = (int64_t)nf * n_lambda;
-  const int64_t nblk = (K + 31) / 32, Kp = nblk * 32, Mp = (M + 31) / 32 * 32;
+  const int64_t Kp = ridge_padded_k(K), Mp = (M + 31) / 32 * 32;
   hipStream_t s = h->b.stream;
   Owned ws;
   ws.device = h->b.device;
@@ -1531,7 +1531,7 @@ cvgram_status cvgram_ridge(cvgram_t h, int32_t p0, int32_t p1, const double* lam
     double* xty = (double*)ws.dev((size_t)nf * K * M * 8);
     double* A = (double*)ws.dev((size_t)nmat * Kp * Kp * 8);
     double* R = (double*)ws.dev((size_t)nmat * Kp * Mp * 8);
-    double* Linv = (double*)ws.dev((size_t)nmat * nblk * 32 * 32 * 8);
+    double* Linv = (double*)ws.dev((size_t)nmat * Kp * 96 * 8);
     int32_t* flags = (int32_t*)ws.dev((size_t)nmat * 4);
     double* dl = (double*)ws.dev((size_t)n_lambda * 8);
     int32_t* hflags = (int32_t*)ws.pinned((size_t)nmat * 4);

@@ -5,24 +5,29 @@
 // Section 1: RR, and OLS for lambda = 0).
 //
 // The systems are copied into padded workspaces first: A to Kp x Kp with the
-// identity in the padding, R to Kp x Mp with zeros (Kp, Mp multiples of 32),
-// so no kernel below needs a bounds check and every load can be issued
-// without waiting for the one before it.
+// identity in the padding (Kp a multiple of 64), R to Kp x Mp with zeros (Mp
+// a multiple of 32), so no kernel below needs a bounds check and every load
+// can be issued without waiting for the one before it.
 //
-// Blocked right-looking Cholesky A = L L^T with 32 x 32 blocks:
-//   for each block column j
-//     diag:   L_jj = chol(A_jj) and its inverse, in registers (one wave per matrix)
-//     panel:  L_ij = A_ij L_jj^{-T} for every block row i > j (also stored
+// Blocked right-looking Cholesky A = L L^T with 64 x 64 blocks:
+//   for each block column s
+//     diag:   L_ss = chol(A_ss) and its inverse (one workgroup per matrix,
+//             two 32 x 32 factorisations in registers joined by small
+//             products); for s > 0 done inside the previous step's update
+//             by the workgroup that finishes A_ss
+//     panel:  L_is = A_is L_ss^{-T} for every block row i > s (also stored
 //             transposed in the upper triangle)
-//     update: A_ik -= L_ij L_kj^T for every j < k <= i (lower triangle)
-// then R is overwritten by L^{-T} L^{-1} R with the same blocks (forward and
-// backward substitution through the stored inverses of the diagonal blocks,
-// one launch for both), and copied out.
+//     update: A_ik -= L_is L_ks^T for every s < k <= i (lower triangle)
+// then R is overwritten by L^{-T} L^{-1} R with 32 x 32 blocks (forward and
+// backward substitution through the stored inverses of the factor's 32 x 32
+// diagonal blocks, one launch for both), and copied out.
 // A matrix whose pivot is not positive (A + lambda I not positive definite)
 // sets its flag and continues with NaN.
 //
-// Arithmetic: FP64 FMA on the vector units; every sum runs in a fixed order
-// (deterministic).
+// Arithmetic: FP64 throughout; the panel and the trailing update (nearly all
+// of the factorisation's flops) on the FP64 matrix cores
+// (v_mfma_f64_16x16x4f64), the rest FP64 FMA on the vector units.  Every sum
+// runs in a fixed order (deterministic).
 #include <cmath>
 
 #include "internal.h"
@@ -30,7 +35,12 @@
 namespace cvg {
 namespace {
 
-constexpr int NB = 32;                         // block edge
+typedef double double2_t __attribute__((ext_vector_type(2)));
+typedef double double4_t __attribute__((ext_vector_type(4)));
+
+constexpr int NB = 32;                         // block edge of the substitutions
+constexpr int NB2 = 64;                        // block edge of the factorisation
+constexpr int LDB = NB2 + 2;                   // LDS row stride of a 64 x 64 block
 constexpr int kThreads = 256;                  // 8 rows x 32 columns per pass
 constexpr int kRowStep = kThreads / NB;        // rows a pass covers
 constexpr int kRowsPerThread = NB / kRowStep;  // passes per block
@@ -44,7 +54,13 @@ constexpr int solve_threads() {
 }
 
 // padded systems: A + lambda I in Kp x Kp (identity in the padding) and R in
-// Kp x Mp (zeros in the padding), from the products (p-major, lambda-minor)
+// Kp x Mp (zeros in the padding), from the products (p-major, lambda-minor).
+// Only the 64 x 64 blocks on and below the diagonal of A are written: the
+// factorisation reads nothing else, and the blocks above are written by it
+// (the transposed panels) before the substitutions read them.
+// grid (Kp / kSetupRows, matrices): a workgroup fills kSetupRows rows,
+// two neighbouring columns per thread
+constexpr int kSetupRows = 8;
 __global__ __launch_bounds__(kThreads) void ridge_setup_kernel(
     const double* __restrict__ xtx, const double* __restrict__ xty,
     const double* __restrict__ lambdas, int32_t n_lambda, int64_t K, int64_t M, int64_t Kp,
@@ -54,17 +70,25 @@ __global__ __launch_bounds__(kThreads) void ridge_setup_kernel(
   const double lam = lambdas[mat % n_lambda];
   const CVG_GLOBAL double* src = gmem(xtx) + f * K * K;
   CVG_GLOBAL double* dst = gmem(A) + mat * Kp * Kp;
-  for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < Kp * Kp;
-       e += (int64_t)gridDim.x * kThreads) {
-    const int64_t i = e / Kp, j = e - i * Kp;
-    dst[e] = (i < K && j < K) ? src[i * K + j] + (i == j ? lam : 0.0) : (i == j ? 1.0 : 0.0);
+  const int64_t i0 = (int64_t)blockIdx.x * kSetupRows;
+  auto value = [&](int64_t i, int64_t j) {
+    return (i < K && j < K) ? src[i * K + j] + (i == j ? lam : 0.0) : (i == j ? 1.0 : 0.0);
+  };
+  for (int rr = 0; rr < kSetupRows; ++rr) {
+    const int64_t i = i0 + rr;
+    const int64_t jend = (i / NB2 + 1) * NB2;
+    for (int64_t j = 2 * (int64_t)threadIdx.x; j < jend; j += 2 * kThreads) {
+      double2_t v;
+      v.x = value(i, j);
+      v.y = value(i, j + 1);
+      *(CVG_GLOBAL double2_t*)&dst[i * Kp + j] = v;
+    }
   }
   const CVG_GLOBAL double* rs = gmem(xty) + f * K * M;
   CVG_GLOBAL double* rd = gmem(R) + mat * Kp * Mp;
-  for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < Kp * Mp;
-       e += (int64_t)gridDim.x * kThreads) {
-    const int64_t i = e / Mp, m = e - i * Mp;
-    rd[e] = (i < K && m < M) ? rs[i * M + m] : 0.0;
+  for (int64_t e = threadIdx.x; e < kSetupRows * Mp; e += kThreads) {
+    const int64_t i = i0 + e / Mp, m = e % Mp;
+    rd[i * Mp + m] = (i < K && m < M) ? rs[i * M + m] : 0.0;
   }
 }
 
@@ -91,33 +115,30 @@ __device__ __forceinline__ double from_lane(double x, int lane) {
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-// diagonal block j of every matrix, one wave per matrix, all in registers:
-// lanes 0..31 hold the rows of the block and factor it column by column
-// (right-looking); lanes 32..63 hold the columns of the factor's inverse and
-// run the forward substitution L X = I in the same steps, since step c of
-// the substitution needs only column c of L, final once step c of the
-// factorisation has divided it.  Both updates are one FMA with a broadcast
-// operand: the factor rows take L[r][k] -= L[r][c] L[k][c] (c < k <= r), the
-// inverse columns X[k][t] -= L[k][c] X[c][t] (k > c); every entry sums in
-// increasing c.  The factor goes to the lower triangle of the block (zeros
-// above), its inverse to Linv; flags[mat] = 1 on a non-positive pivot.
-__global__ __launch_bounds__(kWave) void chol_diag_kernel(double* __restrict__ A,
-                                                          double* __restrict__ Linv,
-                                                          int32_t* __restrict__ flags, int64_t Kp,
-                                                          int32_t j, int32_t nblk) {
-  const int64_t mat = blockIdx.x;
-  const int l = threadIdx.x;
+// One wave factors a 32 x 32 block held in LDS (rows q of S, lower triangle
+// read) and inverts the factor, all in registers: lanes 0..31 hold the rows
+// of the block and factor it column by column (right-looking); lanes 32..63
+// hold the columns of the factor's inverse and run the forward substitution
+// L X = I in the same steps, since step c of the substitution needs only
+// column c of L, final once step c of the factorisation has divided it.
+// Step c: with the pivot p = sqrt(A[c][c]) a factor row takes
+// L[q][c] = A[q][c] / p, an inverse column X[c][t] = X[c][t] / p; then both
+// updates are one FMA with a broadcast operand (v_readlane): the factor rows
+// L[q][k] -= L[q][c] L[k][c] (c < k <= q), the inverse columns
+// X[k][t] -= L[k][c] X[c][t] (k > c); every entry sums in increasing c.  The
+// factor goes back to S (lower triangle, zeros above), its inverse to Li
+// (row-major, zeros above the diagonal); bad is set on a non-positive pivot
+// (the factorisation then continues with NaN).
+__device__ __forceinline__ void factor32_wave(double* S, int ld, double* Li, int ldi, int l,
+                                              bool& bad) {
   const bool fac = l < NB;  // a factor row, else an inverse column
   const int q = l % NB;     // its row / column index
-  const int64_t r0 = (int64_t)j * NB;
-  CVG_GLOBAL double* arow = gmem(A) + mat * Kp * Kp + (r0 + q) * Kp + r0;
   double u[NB];
 #pragma unroll
   for (int k = 0; k < NB; ++k) {
-    const double v = arow[k];
+    const double v = S[q * ld + k];
     u[k] = (fac && k <= q) ? v : (q == k ? 1.0 : 0.0);
   }
-  bool bad = false;
 #pragma unroll
   for (int c = 0; c < NB; ++c) {
     const double d = from_lane(u[c], c);  // pivot: A[c][c] after the earlier steps
@@ -133,116 +154,293 @@ __global__ __launch_bounds__(kWave) void chol_diag_kernel(double* __restrict__ A
       u[k] = fma(-u[c], lkc, u[k]);
     }
   }
-  if (l == 0 && bad) flags[mat] = 1;
   if (fac) {
 #pragma unroll
-    for (int k = 0; k < NB; ++k) arow[k] = k <= q ? u[k] : 0.0;
+    for (int k = 0; k < NB; ++k) S[q * ld + k] = k <= q ? u[k] : 0.0;
   } else {
-    CVG_GLOBAL double* li = gmem(Linv) + (mat * nblk + j) * NB * NB;
 #pragma unroll
-    for (int r = 0; r < NB; ++r) li[r * NB + q] = u[r];
+    for (int r = 0; r < NB; ++r) Li[r * ldi + q] = u[r];
   }
 }
 
-// panel: L_ij = A_ij Linv_jj^T for block rows i > j, written to the lower
-// triangle and, transposed, to block (j, i) of the upper triangle (which the
-// factorisation never reads; the substitutions read the factor along rows of
-// A from there).  grid (matrices, rows below)
-__global__ __launch_bounds__(kThreads) void chol_panel_kernel(double* __restrict__ A,
-                                                              const double* __restrict__ Linv,
-                                                              int64_t Kp, int32_t j, int32_t nblk) {
-  __shared__ double Ab[NB][NB + 1];
-  __shared__ double Li[NB][NB + 1];
-  __shared__ double Lt[NB][NB + 1];
-  const int64_t mat = blockIdx.x;
-  const int32_t ib = j + 1 + (int32_t)blockIdx.y;
-  CVG_GLOBAL double* a = gmem(A) + mat * Kp * Kp;
-  const CVG_GLOBAL double* li = gmem(Linv) + (mat * nblk + j) * NB * NB;
-  const int t = threadIdx.x, tx = t % NB, ty = t / NB;
-  const int64_t r0 = (int64_t)ib * NB, c0 = (int64_t)j * NB;
-  double va[kRowsPerThread], vl[kRowsPerThread];
+// 64 x 64 blocks between global memory (row stride ld, even) and LDS (row
+// stride LDB): thread t moves columns 2 (t % 32), +1 of rows t / 32 + 8 p,
+// so each wave instruction moves two whole 512-byte rows in 16-byte pieces
+__device__ inline void load_block64(const CVG_GLOBAL double* g, int64_t ld, double* S, int t) {
+  const int r0 = t >> 5, c = (t & 31) * 2;
+  double2_t v[8];
 #pragma unroll
-  for (int q = 0; q < kRowsPerThread; ++q) {
-    const int r = ty + kRowStep * q;
-    va[q] = a[(r0 + r) * Kp + c0 + tx];
-    vl[q] = li[r * NB + tx];
-  }
+  for (int p = 0; p < 8; ++p) v[p] = *(const CVG_GLOBAL double2_t*)&g[(r0 + 8 * p) * ld + c];
 #pragma unroll
-  for (int q = 0; q < kRowsPerThread; ++q) {
-    Ab[ty + kRowStep * q][tx] = va[q];
-    Li[ty + kRowStep * q][tx] = vl[q];
-  }
-  __syncthreads();
-  // rows ty + kRowStep * q of (A Linv^T)[.][tx], sharing Linv's row tx
-  double s[kRowsPerThread];
+  for (int p = 0; p < 8; ++p) *(double2_t*)&S[(r0 + 8 * p) * LDB + c] = v[p];
+}
+// g = S (transpose = false) or S^T (true)
+template <bool TRANSPOSE>
+__device__ inline void store_block64(CVG_GLOBAL double* g, int64_t ld, const double* S, int t) {
+  const int r0 = t >> 5, c = (t & 31) * 2;
 #pragma unroll
-  for (int q = 0; q < kRowsPerThread; ++q) s[q] = 0.0;
-  for (int k = 0; k <= tx; ++k) {
-    const double b = Li[tx][k];
-#pragma unroll
-    for (int q = 0; q < kRowsPerThread; ++q) s[q] = fma(Ab[ty + kRowStep * q][k], b, s[q]);
-  }
-#pragma unroll
-  for (int q = 0; q < kRowsPerThread; ++q) {
-    const int r = ty + kRowStep * q;
-    a[(r0 + r) * Kp + c0 + tx] = s[q];
-    Lt[r][tx] = s[q];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int q = 0; q < kRowsPerThread; ++q) {  // A[c0 + c][r0 + tx] = L[r0 + tx][c0 + c]
-    const int c = ty + kRowStep * q;
-    a[(c0 + c) * Kp + r0 + tx] = Lt[tx][c];
+  for (int p = 0; p < 8; ++p) {
+    const int r = r0 + 8 * p;
+    double2_t v;
+    if (TRANSPOSE) {
+      v.x = S[c * LDB + r];
+      v.y = S[(c + 1) * LDB + r];
+    } else {
+      v = *(const double2_t*)&S[r * LDB + c];
+    }
+    *(CVG_GLOBAL double2_t*)&g[r * ld + c] = v;
   }
 }
 
-// trailing update A_ik -= L_ij L_kj^T for j < k <= i.  grid (matrices, lower
-// triangle of the remaining blocks)
-__global__ __launch_bounds__(kThreads) void chol_update_kernel(double* __restrict__ A, int64_t Kp,
-                                                               int32_t j) {
-  __shared__ double Li[NB][NB + 1];
-  __shared__ double Lk[NB][NB + 1];
-  const int64_t mat = blockIdx.x;
-  // blockIdx.y -> (ii, kk) with 0 <= kk <= ii, counted row by row
-  int32_t q = (int32_t)blockIdx.y, ii = 0;
-  while (q > ii) {
-    q -= ii + 1;
-    ++ii;
-  }
-  const int32_t ib = j + 1 + ii, kb = j + 1 + q;
-  CVG_GLOBAL double* a = gmem(A) + mat * Kp * Kp;
-  const int t = threadIdx.x, tx = t % NB, ty = t / NB;
-  const int64_t c0 = (int64_t)j * NB;
-  CVG_GLOBAL double* out = a + (int64_t)ib * NB * Kp + (int64_t)kb * NB + tx;  // A_ik[0][tx]
-  double vi[kRowsPerThread], vk[kRowsPerThread], vo[kRowsPerThread];
-#pragma unroll
-  for (int p = 0; p < kRowsPerThread; ++p) {
-    const int r = ty + kRowStep * p;
-    vi[p] = a[((int64_t)ib * NB + r) * Kp + c0 + tx];
-    vk[p] = a[((int64_t)kb * NB + r) * Kp + c0 + tx];
-    vo[p] = out[r * Kp];
-  }
-#pragma unroll
-  for (int p = 0; p < kRowsPerThread; ++p) {
-    Li[ty + kRowStep * p][tx] = vi[p];
-    Lk[ty + kRowStep * p][tx] = vk[p];
-  }
+// Diagonal block s (64 x 64) of matrix mat by one 256-thread workgroup, the
+// block already in S (LDS, lower triangle valid; I1, I2, T: LDS scratch of
+// 32 x 33 doubles each).  The block is the 2 x 2 arrangement of 32 x 32 blocks
+//   [A11 .; A21 A22] = [L11 0; L21 L22] [L11 0; L21 L22]^T
+// so L11 = chol(A11) (one wave, above), L21 = A21 L11^{-T},
+// L22 = chol(A22 - L21 L21^T) (one wave), and the inverse of the factor is
+//   [L11^{-1} 0; -L22^{-1} L21 L11^{-1}  L22^{-1}].
+// Written back: the factor to the block's lower triangle and, transposed, L21
+// to its upper right quadrant (the substitutions read the factor's 32-column
+// blocks along rows from the upper triangle); the 64 x 64 inverse to Linv64
+// (the panel step's operand) and the two 32 x 32 diagonal inverses to Linv32
+// (the substitutions').  Small products on the vector ALU in increasing c.
+__device__ __forceinline__ void diag64_body(double* S, double* I1, double* I2, double* T,
+                                            CVG_GLOBAL double* a,
+                            double* __restrict__ Linv64, double* __restrict__ Linv32,
+                            int32_t* __restrict__ flags, int64_t Kp, int64_t mat, int32_t s,
+                            int32_t nb64, int t) {
+  constexpr int LI = NB + 1;
+  CVG_GLOBAL double* blk = a + (int64_t)s * NB2 * Kp + (int64_t)s * NB2;
+  bool bad = false;  // meaningful in wave 0
+  if (t < kWave) factor32_wave(S, LDB, I1, LI, t, bad);
   __syncthreads();
-  // rows ty + kRowStep * p of the product, sharing L_kj's row tx
-  double s[kRowsPerThread];
+  const int q = t % NB, rb = t / NB;  // this thread: column q of rows rb + 8 p
+  // the four rows' sums run interleaved (independent FMA chains)
+  double v[kRowsPerThread];
+  // L21[r][q] = sum_c A21[r][c] L11^{-1}[q][c]
 #pragma unroll
-  for (int p = 0; p < kRowsPerThread; ++p) s[p] = 0.0;
+  for (int p = 0; p < kRowsPerThread; ++p) v[p] = 0.0;
 #pragma unroll 8
   for (int c = 0; c < NB; ++c) {
-    const double b = Lk[tx][c];
+    const double b = I1[q * LI + c];
 #pragma unroll
-    for (int p = 0; p < kRowsPerThread; ++p) s[p] = fma(Li[ty + kRowStep * p][c], b, s[p]);
+    for (int p = 0; p < kRowsPerThread; ++p)
+      v[p] = fma(S[(NB + rb + kRowStep * p) * LDB + c], b, v[p]);
   }
+  __syncthreads();
+#pragma unroll
+  for (int p = 0; p < kRowsPerThread; ++p) S[(NB + rb + kRowStep * p) * LDB + q] = v[p];
+  __syncthreads();
+  // A22 -= L21 L21^T (reads columns 0..31, writes 32..63)
+#pragma unroll
+  for (int p = 0; p < kRowsPerThread; ++p) v[p] = S[(NB + rb + kRowStep * p) * LDB + NB + q];
+#pragma unroll 8
+  for (int c = 0; c < NB; ++c) {
+    const double b = S[(NB + q) * LDB + c];
+#pragma unroll
+    for (int p = 0; p < kRowsPerThread; ++p)
+      v[p] = fma(-S[(NB + rb + kRowStep * p) * LDB + c], b, v[p]);
+  }
+#pragma unroll
+  for (int p = 0; p < kRowsPerThread; ++p) S[(NB + rb + kRowStep * p) * LDB + NB + q] = v[p];
+  __syncthreads();
+  if (t < kWave) factor32_wave(S + NB * LDB + NB, LDB, I2, LI, t, bad);
+  // T = L21 L11^{-1}
+#pragma unroll
+  for (int p = 0; p < kRowsPerThread; ++p) v[p] = 0.0;
+#pragma unroll 8
+  for (int c = 0; c < NB; ++c) {
+    const double b = I1[c * LI + q];
+#pragma unroll
+    for (int p = 0; p < kRowsPerThread; ++p)
+      v[p] = fma(S[(NB + rb + kRowStep * p) * LDB + c], b, v[p]);
+  }
+#pragma unroll
+  for (int p = 0; p < kRowsPerThread; ++p) T[(rb + kRowStep * p) * LI + q] = v[p];
+  __syncthreads();
+  // the inverse's lower left quadrant: -L22^{-1} T
+#pragma unroll
+  for (int p = 0; p < kRowsPerThread; ++p) v[p] = 0.0;
+#pragma unroll 8
+  for (int c = 0; c < NB; ++c) {
+    const double b = T[c * LI + q];
+#pragma unroll
+    for (int p = 0; p < kRowsPerThread; ++p)
+      v[p] = fma(I2[(rb + kRowStep * p) * LI + c], b, v[p]);
+  }
+#pragma unroll
+  for (int p = 0; p < kRowsPerThread; ++p) v[p] = -v[p];
+  CVG_GLOBAL double* li = gmem(Linv64) + (mat * nb64 + s) * NB2 * NB2;
+  CVG_GLOBAL double* l32 = gmem(Linv32) + (mat * 2 * nb64 + 2 * s) * NB * NB;
 #pragma unroll
   for (int p = 0; p < kRowsPerThread; ++p) {
-    const int r = ty + kRowStep * p;
-    if (ib != kb || tx <= r) out[r * Kp] = vo[p] - s[p];
+    const int r = rb + kRowStep * p;
+    li[r * NB2 + q] = I1[r * LI + q];
+    li[r * NB2 + NB + q] = 0.0;
+    li[(NB + r) * NB2 + q] = v[p];
+    li[(NB + r) * NB2 + NB + q] = I2[r * LI + q];
+    l32[r * NB + q] = I1[r * LI + q];
+    l32[NB * NB + r * NB + q] = I2[r * LI + q];
+    blk[r * Kp + q] = S[r * LDB + q];                      // L11
+    blk[r * Kp + NB + q] = S[(NB + q) * LDB + r];          // L21^T
+    blk[(NB + r) * Kp + q] = S[(NB + r) * LDB + q];        // L21
+    blk[(NB + r) * Kp + NB + q] = S[(NB + r) * LDB + NB + q];  // L22
   }
+  if (t == 0 && bad) flags[mat] = 1;
+}
+
+// diagonal block 0 of every matrix (the later ones are factored by the
+// trailing update that finishes them); grid: matrices
+__global__ __launch_bounds__(kThreads) void chol_diag64_kernel(double* __restrict__ A,
+                                                               double* __restrict__ Linv64,
+                                                               double* __restrict__ Linv32,
+                                                               int32_t* __restrict__ flags,
+                                                               int64_t Kp, int32_t nb64) {
+  __shared__ double S[NB2 * LDB];
+  __shared__ double I1[NB * (NB + 1)], I2[NB * (NB + 1)], T[NB * (NB + 1)];
+  const int64_t mat = blockIdx.x;
+  const int t = threadIdx.x;
+  CVG_GLOBAL double* a = gmem(A) + mat * Kp * Kp;
+  load_block64(a, Kp, S, t);
+  __syncthreads();
+  diag64_body(S, I1, I2, T, a, Linv64, Linv32, flags, Kp, mat, 0, nb64, t);
+}
+
+// C[r][q] += sum_c sign * X[r][c] Y[q][c] over a 64 x 64 tile, X and Y 64 x 64
+// in LDS: wave w computes rows 32 (w / 2) .., columns 32 (w % 2) .. as 2 x 2
+// blocks of v_mfma_f64_16x16x4f64 over 16 steps of 4 c.  Element e of
+// acc[a][b] in lane (fr = lane / 16, fc = lane % 16) is
+//   C[32 wm + 16 a + 4 e + fr][32 wn + 16 b + fc].
+template <bool NEG>
+__device__ inline void mma64(const double* X, const double* Y, double4_t (&acc)[2][2], int wm,
+                             int wn, int fr, int fc) {
+#pragma unroll 4
+  for (int kk = 0; kk < NB2 / 4; ++kk) {
+    double af[2], bf[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const double x = X[(32 * wm + 16 * u + fc) * LDB + 4 * kk + fr];
+      af[u] = NEG ? -x : x;
+      bf[u] = Y[(32 * wn + 16 * u + fc) * LDB + 4 * kk + fr];
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int w = 0; w < 2; ++w)
+        acc[u][w] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[u], bf[w], acc[u][w], 0, 0, 0);
+  }
+}
+
+// panel: L_is = A_is Linv_ss^T for block rows i > s (64 x 64 blocks, FP64
+// MFMA), written to the lower triangle and, transposed, to block (s, i) of
+// the upper triangle (which the factorisation never reads; the
+// substitutions read the factor along rows of A from there).
+// grid (matrices, block rows below s)
+__global__ __launch_bounds__(kThreads) void chol_panel64_kernel(double* __restrict__ A,
+                                                                const double* __restrict__ Linv64,
+                                                                int64_t Kp, int32_t s,
+                                                                int32_t nb64) {
+  __shared__ double Xs[NB2 * LDB], Ys[NB2 * LDB];
+  const int64_t mat = blockIdx.x;
+  const int32_t ib = s + 1 + (int32_t)blockIdx.y;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int fr = lane >> 4, fc = lane & 15, wm = w >> 1, wn = w & 1;
+  CVG_GLOBAL double* a = gmem(A) + mat * Kp * Kp;
+  CVG_GLOBAL double* blk = a + (int64_t)ib * NB2 * Kp + (int64_t)s * NB2;  // block (ib, s)
+  const CVG_GLOBAL double* li = gmem(Linv64) + (mat * nb64 + s) * NB2 * NB2;
+  load_block64(blk, Kp, Xs, t);
+  load_block64(li, NB2, Ys, t);
+  __syncthreads();
+  double4_t acc[2][2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v) acc[u][v] = double4_t{0.0, 0.0, 0.0, 0.0};
+  mma64<false>(Xs, Ys, acc, wm, wn, fr, fc);
+  __syncthreads();  // every wave's reads of Xs are done
+#pragma unroll
+  for (int u = 0; u < 2; ++u)
+#pragma unroll
+    for (int v = 0; v < 2; ++v)
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        Xs[(32 * wm + 16 * u + 4 * e + fr) * LDB + 32 * wn + 16 * v + fc] = acc[u][v][e];
+  __syncthreads();
+  store_block64<false>(blk, Kp, Xs, t);
+  store_block64<true>(a + (int64_t)s * NB2 * Kp + (int64_t)ib * NB2, Kp, Xs, t);  // block (s, ib)
+}
+
+// trailing update A_ik -= L_is L_ks^T for s < k <= i (64 x 64 blocks, FP64
+// MFMA accumulating onto A_ik: the negated L_is is the first operand).
+// grid (matrices, lower triangle of the remaining blocks, counted row by
+// row).  Workgroup 0 of a matrix owns block (s + 1, s + 1), the next
+// diagonal block: once its update is complete (no other workgroup writes
+// it), it keeps the block in LDS and factors it (diag64_body), so the next
+// step's diagonal work runs beside the rest of this update instead of in a
+// launch of its own.  On a diagonal block the wave of the upper right
+// quadrant has nothing to compute.
+__global__ __launch_bounds__(kThreads) void chol_update64_kernel(double* __restrict__ A,
+                                                                 double* __restrict__ Linv64,
+                                                                 double* __restrict__ Linv32,
+                                                                 int32_t* __restrict__ flags,
+                                                                 int64_t Kp, int32_t s,
+                                                                 int32_t nb64) {
+  __shared__ double Xs[NB2 * LDB], Ys[NB2 * LDB];
+  const int64_t mat = blockIdx.x;
+  int32_t kk = (int32_t)blockIdx.y, ii = 0;
+  while (kk > ii) {
+    kk -= ii + 1;
+    ++ii;
+  }
+  const int32_t ib = s + 1 + ii, kb = s + 1 + kk;
+  const bool owner = blockIdx.y == 0;  // block (s + 1, s + 1)
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int fr = lane >> 4, fc = lane & 15, wm = w >> 1, wn = w & 1;
+  CVG_GLOBAL double* a = gmem(A) + mat * Kp * Kp;
+  CVG_GLOBAL double* out = a + (int64_t)ib * NB2 * Kp + (int64_t)kb * NB2;
+  const bool idle = ib == kb && wm < wn;
+  double4_t acc[2][2];
+  if (!idle) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int v = 0; v < 2; ++v)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          acc[u][v][e] = out[(32 * wm + 16 * u + 4 * e + fr) * Kp + 32 * wn + 16 * v + fc];
+  }
+  load_block64(a + (int64_t)ib * NB2 * Kp + (int64_t)s * NB2, Kp, Xs, t);
+  if (kb != ib) load_block64(a + (int64_t)kb * NB2 * Kp + (int64_t)s * NB2, Kp, Ys, t);
+  __syncthreads();
+  if (!idle) mma64<true>(Xs, kb != ib ? Ys : Xs, acc, wm, wn, fr, fc);
+  if (!owner) {
+    if (idle) return;
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int v = 0; v < 2; ++v)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          out[(32 * wm + 16 * u + 4 * e + fr) * Kp + 32 * wn + 16 * v + fc] = acc[u][v][e];
+    return;
+  }
+  // the owner: the updated block to LDS (its lower triangle; the idle
+  // wave's quadrant is above the diagonal), then the factorisation of it,
+  // with the diagonal step's scratch in Ys (unused on a diagonal block)
+  __syncthreads();  // every wave's reads of Xs are done
+  if (!idle) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int v = 0; v < 2; ++v)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          Xs[(32 * wm + 16 * u + 4 * e + fr) * LDB + 32 * wn + 16 * v + fc] = acc[u][v][e];
+  }
+  __syncthreads();
+  constexpr int kI = NB * (NB + 1);
+  static_assert(3 * kI <= NB2 * LDB, "diagonal scratch must fit in the second block buffer");
+  diag64_body(Xs, Ys, Ys + kI, Ys + 2 * kI, a, Linv64, Linv32, flags, Kp, mat, s + 1, nb64, t);
 }
 
 // Both substitutions in one launch: workgroup (matrix, block of 32 columns
@@ -417,40 +615,42 @@ void ridge_solve(const double* xtx, const double* xty, const double* lambdas, in
                  int32_t* flags, double* B, hipStream_t s) {
   const int64_t n_mat = (int64_t)n_folds * n_lambda;
   if (n_mat <= 0 || K <= 0) return;
-  const int32_t nblk = (int32_t)((K + NB - 1) / NB);
-  const int64_t Kp = (int64_t)nblk * NB, Mp = (M + NB - 1) / NB * NB;
-  {
-    const int64_t per = (Kp * Kp + kThreads - 1) / kThreads;
-    dim3 grid((unsigned)(per < 1024 ? per : 1024), (unsigned)n_mat);
-    ridge_setup_kernel<<<grid, kThreads, 0, s>>>(xtx, xty, lambdas, n_lambda, K, M, Kp, Mp, A, R);
+  const int64_t Kp = ridge_padded_k(K), Mp = (M + NB - 1) / NB * NB;
+  const int32_t nb64 = (int32_t)(Kp / NB2), nblk = (int32_t)(Kp / NB);
+  double* Linv64 = Linv;                                // [n_mat][nb64][64][64]
+  double* Linv32 = Linv + n_mat * nb64 * NB2 * NB2;     // [n_mat][nblk][32][32]
+  ridge_setup_kernel<<<dim3((unsigned)(Kp / kSetupRows), (unsigned)n_mat), kThreads, 0, s>>>(
+      xtx, xty, lambdas, n_lambda, K, M, Kp, Mp, A, R);
+  CVG_LAUNCH_CHECK();
+  // diagonal block 0, then per block column s: the panel below it and the
+  // trailing update, which also factors diagonal block s + 1
+  chol_diag64_kernel<<<(unsigned)n_mat, kThreads, 0, s>>>(A, Linv64, Linv32, flags, Kp, nb64);
+  CVG_LAUNCH_CHECK();
+  for (int32_t j = 0; j + 1 < nb64; ++j) {
+    const int32_t below = nb64 - j - 1;
+    chol_panel64_kernel<<<dim3((unsigned)n_mat, (unsigned)below), kThreads, 0, s>>>(A, Linv64,
+                                                                                  Kp, j, nb64);
     CVG_LAUNCH_CHECK();
-  }
-  for (int32_t j = 0; j < nblk; ++j) {
-    chol_diag_kernel<<<(unsigned)n_mat, kWave, 0, s>>>(A, Linv, flags, Kp, j, nblk);
+    chol_update64_kernel<<<dim3((unsigned)n_mat, (unsigned)(below * (below + 1) / 2)), kThreads,
+                           0, s>>>(A, Linv64, Linv32, flags, Kp, j, nb64);
     CVG_LAUNCH_CHECK();
-    const int32_t below = nblk - j - 1;
-    if (below > 0) {
-      chol_panel_kernel<<<dim3((unsigned)n_mat, (unsigned)below), kThreads, 0, s>>>(A, Linv, Kp,
-                                                                                    j, nblk);
-      CVG_LAUNCH_CHECK();
-      chol_update_kernel<<<dim3((unsigned)n_mat, (unsigned)(below * (below + 1) / 2)), kThreads,
-                           0, s>>>(A, Kp, j);
-      CVG_LAUNCH_CHECK();
-    }
   }
   if (M <= 0) return;
   const dim3 grid((unsigned)n_mat, (unsigned)(Mp / NB));
   const bool fast = Kp <= solve_threads<16>();  // one row of R per thread
   if (M <= 8 && fast)
-    tri_solve_kernel<8, true><<<grid, solve_threads<8>(), 0, s>>>(A, Linv, R, K, M, Kp, Mp, nblk);
+    tri_solve_kernel<8, true><<<grid, solve_threads<8>(), 0, s>>>(A, Linv32, R, K, M, Kp, Mp, nblk);
   else if (M <= 8)
-    tri_solve_kernel<8, false><<<grid, solve_threads<8>(), 0, s>>>(A, Linv, R, K, M, Kp, Mp, nblk);
+    tri_solve_kernel<8, false><<<grid, solve_threads<8>(), 0, s>>>(A, Linv32, R, K, M, Kp, Mp, nblk);
   else if (M <= 16 && fast)
-    tri_solve_kernel<16, true><<<grid, solve_threads<16>(), 0, s>>>(A, Linv, R, K, M, Kp, Mp, nblk);
+    tri_solve_kernel<16, true><<<grid, solve_threads<16>(), 0, s>>>(A, Linv32, R, K, M, Kp, Mp,
+                                                                      nblk);
   else if (M <= 16)
-    tri_solve_kernel<16, false><<<grid, solve_threads<16>(), 0, s>>>(A, Linv, R, K, M, Kp, Mp, nblk);
+    tri_solve_kernel<16, false><<<grid, solve_threads<16>(), 0, s>>>(A, Linv32, R, K, M, Kp, Mp,
+                                                                       nblk);
   else
-    tri_solve_kernel<NB, false><<<grid, solve_threads<NB>(), 0, s>>>(A, Linv, R, K, M, Kp, Mp, nblk);
+    tri_solve_kernel<NB, false><<<grid, solve_threads<NB>(), 0, s>>>(A, Linv32, R, K, M, Kp, Mp,
+                                                                       nblk);
   CVG_LAUNCH_CHECK();
   {
     const int64_t per = (K * M + kThreads - 1) / kThreads;
