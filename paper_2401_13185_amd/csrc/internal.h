@@ -245,12 +245,14 @@ void launch_correct_batch(const ProbDesc* pd, const OutDesc* outs, const Item* i
 
 // solve.hip: B = (xtx_f + lambda_l I)^{-1} xty_f for every (fold f, lambda l),
 // matrices p-major, into B: [n_folds n_lambda][K][M].  Workspaces, with
-// Kp = ridge_padded_k(K) and Mp the multiple of 32 at or above M:
-// A [n_folds n_lambda][Kp][Kp], R [n_folds n_lambda][Kp][Mp],
+// Kp = ridge_padded_k(K), Ma = ridge_aug_rows(M) and Mp the multiple of 32
+// at or above M: A [n_folds n_lambda][Kp + Ma][Kp] (the matrix, then R^T),
+// R [n_folds n_lambda][Kp][Mp],
 // Linv: n_folds n_lambda Kp 96 doubles (the 64 x 64 inverses of the diagonal
 // blocks of the factor, then their 32 x 32 diagonal blocks);
 // flags: [n_folds n_lambda] (zeroed by the caller; set on a non-positive pivot).
 inline int64_t ridge_padded_k(int64_t K) { return (K + 63) / 64 * 64; }
+inline int64_t ridge_aug_rows(int64_t M) { return (M + 63) / 64 * 64; }
 void ridge_solve(const double* xtx, const double* xty, const double* lambdas, int32_t n_folds,
                  int32_t n_lambda, int64_t K, int64_t M, double* A, double* R, double* Linv,
                  int32_t* flags, double* B, hipStream_t s);

@@ -15,12 +15,13 @@
 //             two 32 x 32 factorisations in registers joined by small
 //             products); for s > 0 done inside the previous step's update
 //             by the workgroup that finishes A_ss
-//     panel:  L_is = A_is L_ss^{-T} for every block row i > s (also stored
-//             transposed in the upper triangle)
+//     panel:  L_is = A_is L_ss^{-T} for every block row i > s
 //     update: A_ik -= L_is L_ks^T for every s < k <= i (lower triangle)
-// then R is overwritten by L^{-T} L^{-1} R with 32 x 32 blocks (forward and
-// backward substitution through the stored inverses of the factor's 32 x 32
-// diagonal blocks, one launch for both), and copied out.
+// R^T sits in extra block rows below A and takes the panel and update steps
+// with it, so it leaves the factorisation as (L^{-1} R)^T (the forward
+// substitution); the backward substitution L^{-T} then runs with 32 x 32
+// blocks through the stored inverses of the factor's 32 x 32 diagonal
+// blocks, and the result is copied out.
 // A matrix whose pivot is not positive (A + lambda I not positive definite)
 // sets its flag and continues with NaN.
 //
@@ -53,30 +54,37 @@ constexpr int solve_threads() {
   return MW <= 16 ? 512 : kThreads;
 }
 
-// padded systems: A + lambda I in Kp x Kp (identity in the padding) and R in
-// Kp x Mp (zeros in the padding), from the products (p-major, lambda-minor).
-// Only the 64 x 64 blocks on and below the diagonal of A are written: the
-// factorisation reads nothing else, and the blocks above are written by it
-// (the transposed panels) before the substitutions read them.
-// grid (Kp / kSetupRows, matrices): a workgroup fills kSetupRows rows,
-// two neighbouring columns per thread
+// padded systems: A + lambda I in Kp x Kp (identity in the padding) and,
+// below it, R^T in Ma rows of Kp (zeros in the padding), from the products
+// (p-major, lambda-minor).  Of the square part only the 64 x 64 blocks on and
+// below the diagonal are written: the factorisation reads nothing else, and
+// the blocks above are written by it (the transposed panels) before the
+// substitution reads them.  The rows of R^T are factored with the matrix
+// (they become (L^{-1} R)^T: the forward substitution).
+// grid (Kr / kSetupRows, matrices), Kr = Kp + Ma: a workgroup fills
+// kSetupRows rows, two neighbouring columns per thread
 constexpr int kSetupRows = 8;
 __global__ __launch_bounds__(kThreads) void ridge_setup_kernel(
     const double* __restrict__ xtx, const double* __restrict__ xty,
     const double* __restrict__ lambdas, int32_t n_lambda, int64_t K, int64_t M, int64_t Kp,
-    int64_t Mp, double* __restrict__ A, double* __restrict__ R) {
+    int64_t Kr, double* __restrict__ A) {
   const int64_t mat = blockIdx.y;  // fold * n_lambda + lambda
   const int64_t f = mat / n_lambda;
   const double lam = lambdas[mat % n_lambda];
   const CVG_GLOBAL double* src = gmem(xtx) + f * K * K;
-  CVG_GLOBAL double* dst = gmem(A) + mat * Kp * Kp;
+  const CVG_GLOBAL double* rs = gmem(xty) + f * K * M;
+  CVG_GLOBAL double* dst = gmem(A) + mat * Kr * Kp;
   const int64_t i0 = (int64_t)blockIdx.x * kSetupRows;
   auto value = [&](int64_t i, int64_t j) {
+    if (i >= Kp) {  // R^T
+      const int64_t m = i - Kp;
+      return (m < M && j < K) ? rs[j * M + m] : 0.0;
+    }
     return (i < K && j < K) ? src[i * K + j] + (i == j ? lam : 0.0) : (i == j ? 1.0 : 0.0);
   };
   for (int rr = 0; rr < kSetupRows; ++rr) {
     const int64_t i = i0 + rr;
-    const int64_t jend = (i / NB2 + 1) * NB2;
+    const int64_t jend = i >= Kp ? Kp : (i / NB2 + 1) * NB2;
     for (int64_t j = 2 * (int64_t)threadIdx.x; j < jend; j += 2 * kThreads) {
       double2_t v;
       v.x = value(i, j);
@@ -84,11 +92,20 @@ __global__ __launch_bounds__(kThreads) void ridge_setup_kernel(
       *(CVG_GLOBAL double2_t*)&dst[i * Kp + j] = v;
     }
   }
-  const CVG_GLOBAL double* rs = gmem(xty) + f * K * M;
+}
+
+// R[mat] (Kp x Mp) = the first Mp rows of (L^{-1} R)^T below the factor,
+// transposed: the backward substitution's input.  grid (Kp / 8, matrices)
+__global__ __launch_bounds__(kThreads) void ridge_z_kernel(const double* __restrict__ A, int64_t Kp,
+                                                           int64_t Kr, int64_t Mp,
+                                                           double* __restrict__ R) {
+  const int64_t mat = blockIdx.y;
+  const CVG_GLOBAL double* z = gmem(A) + mat * Kr * Kp + Kp * Kp;  // row m: Z^T[m][.]
   CVG_GLOBAL double* rd = gmem(R) + mat * Kp * Mp;
-  for (int64_t e = threadIdx.x; e < kSetupRows * Mp; e += kThreads) {
-    const int64_t i = i0 + e / Mp, m = e % Mp;
-    rd[i * Mp + m] = (i < K && m < M) ? rs[i * M + m] : 0.0;
+  const int64_t j0 = (int64_t)blockIdx.x * 8;
+  for (int64_t e = threadIdx.x; e < 8 * Mp; e += kThreads) {
+    const int64_t m = e / 8, j = j0 + e % 8;
+    rd[j * Mp + m] = z[m * Kp + j];
   }
 }
 
@@ -174,21 +191,12 @@ __device__ inline void load_block64(const CVG_GLOBAL double* g, int64_t ld, doub
 #pragma unroll
   for (int p = 0; p < 8; ++p) *(double2_t*)&S[(r0 + 8 * p) * LDB + c] = v[p];
 }
-// g = S (transpose = false) or S^T (true)
-template <bool TRANSPOSE>
 __device__ inline void store_block64(CVG_GLOBAL double* g, int64_t ld, const double* S, int t) {
   const int r0 = t >> 5, c = (t & 31) * 2;
 #pragma unroll
   for (int p = 0; p < 8; ++p) {
     const int r = r0 + 8 * p;
-    double2_t v;
-    if (TRANSPOSE) {
-      v.x = S[c * LDB + r];
-      v.y = S[(c + 1) * LDB + r];
-    } else {
-      v = *(const double2_t*)&S[r * LDB + c];
-    }
-    *(CVG_GLOBAL double2_t*)&g[r * ld + c] = v;
+    *(CVG_GLOBAL double2_t*)&g[r * ld + c] = *(const double2_t*)&S[r * LDB + c];
   }
 }
 
@@ -199,11 +207,10 @@ __device__ inline void store_block64(CVG_GLOBAL double* g, int64_t ld, const dou
 // so L11 = chol(A11) (one wave, above), L21 = A21 L11^{-T},
 // L22 = chol(A22 - L21 L21^T) (one wave), and the inverse of the factor is
 //   [L11^{-1} 0; -L22^{-1} L21 L11^{-1}  L22^{-1}].
-// Written back: the factor to the block's lower triangle and, transposed, L21
-// to its upper right quadrant (the substitutions read the factor's 32-column
-// blocks along rows from the upper triangle); the 64 x 64 inverse to Linv64
-// (the panel step's operand) and the two 32 x 32 diagonal inverses to Linv32
-// (the substitutions').  Small products on the vector ALU in increasing c.
+// Written back: the factor to the block's lower triangle; the 64 x 64
+// inverse to Linv64 (the panel step's operand) and the two 32 x 32 diagonal
+// inverses to Linv32 (the backward substitution's).  Small products on the
+// vector ALU in increasing c.
 __device__ __forceinline__ void diag64_body(double* S, double* I1, double* I2, double* T,
                                             CVG_GLOBAL double* a,
                             double* __restrict__ Linv64, double* __restrict__ Linv32,
@@ -282,7 +289,6 @@ __device__ __forceinline__ void diag64_body(double* S, double* I1, double* I2, d
     l32[r * NB + q] = I1[r * LI + q];
     l32[NB * NB + r * NB + q] = I2[r * LI + q];
     blk[r * Kp + q] = S[r * LDB + q];                      // L11
-    blk[r * Kp + NB + q] = S[(NB + q) * LDB + r];          // L21^T
     blk[(NB + r) * Kp + q] = S[(NB + r) * LDB + q];        // L21
     blk[(NB + r) * Kp + NB + q] = S[(NB + r) * LDB + NB + q];  // L22
   }
@@ -295,12 +301,13 @@ __global__ __launch_bounds__(kThreads) void chol_diag64_kernel(double* __restric
                                                                double* __restrict__ Linv64,
                                                                double* __restrict__ Linv32,
                                                                int32_t* __restrict__ flags,
-                                                               int64_t Kp, int32_t nb64) {
+                                                               int64_t Kp, int64_t Kr,
+                                                               int32_t nb64) {
   __shared__ double S[NB2 * LDB];
   __shared__ double I1[NB * (NB + 1)], I2[NB * (NB + 1)], T[NB * (NB + 1)];
   const int64_t mat = blockIdx.x;
   const int t = threadIdx.x;
-  CVG_GLOBAL double* a = gmem(A) + mat * Kp * Kp;
+  CVG_GLOBAL double* a = gmem(A) + mat * Kr * Kp;
   load_block64(a, Kp, S, t);
   __syncthreads();
   diag64_body(S, I1, I2, T, a, Linv64, Linv32, flags, Kp, mat, 0, nb64, t);
@@ -332,20 +339,19 @@ __device__ inline void mma64(const double* X, const double* Y, double4_t (&acc)[
 }
 
 // panel: L_is = A_is Linv_ss^T for block rows i > s (64 x 64 blocks, FP64
-// MFMA), written to the lower triangle and, transposed, to block (s, i) of
-// the upper triangle (which the factorisation never reads; the
-// substitutions read the factor along rows of A from there).
-// grid (matrices, block rows below s)
+// MFMA), in place; the naug block rows below the matrix (R^T) take the same
+// step.  grid (matrices, block rows below s: nb64 - 1 - s of the matrix, then
+// naug)
 __global__ __launch_bounds__(kThreads) void chol_panel64_kernel(double* __restrict__ A,
                                                                 const double* __restrict__ Linv64,
-                                                                int64_t Kp, int32_t s,
+                                                                int64_t Kp, int64_t Kr, int32_t s,
                                                                 int32_t nb64) {
   __shared__ double Xs[NB2 * LDB], Ys[NB2 * LDB];
   const int64_t mat = blockIdx.x;
-  const int32_t ib = s + 1 + (int32_t)blockIdx.y;
+  const int32_t ib = s + 1 + (int32_t)blockIdx.y;  // >= nb64: a row block of R^T
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int fr = lane >> 4, fc = lane & 15, wm = w >> 1, wn = w & 1;
-  CVG_GLOBAL double* a = gmem(A) + mat * Kp * Kp;
+  CVG_GLOBAL double* a = gmem(A) + mat * Kr * Kp;
   CVG_GLOBAL double* blk = a + (int64_t)ib * NB2 * Kp + (int64_t)s * NB2;  // block (ib, s)
   const CVG_GLOBAL double* li = gmem(Linv64) + (mat * nb64 + s) * NB2 * NB2;
   load_block64(blk, Kp, Xs, t);
@@ -366,14 +372,14 @@ __global__ __launch_bounds__(kThreads) void chol_panel64_kernel(double* __restri
       for (int e = 0; e < 4; ++e)
         Xs[(32 * wm + 16 * u + 4 * e + fr) * LDB + 32 * wn + 16 * v + fc] = acc[u][v][e];
   __syncthreads();
-  store_block64<false>(blk, Kp, Xs, t);
-  store_block64<true>(a + (int64_t)s * NB2 * Kp + (int64_t)ib * NB2, Kp, Xs, t);  // block (s, ib)
+  store_block64(blk, Kp, Xs, t);
 }
 
 // trailing update A_ik -= L_is L_ks^T for s < k <= i (64 x 64 blocks, FP64
 // MFMA accumulating onto A_ik: the negated L_is is the first operand).
-// grid (matrices, lower triangle of the remaining blocks, counted row by
-// row).  Workgroup 0 of a matrix owns block (s + 1, s + 1), the next
+// grid (matrices, lower triangle of the remaining blocks counted row by row,
+// then naug x (nb64 - 1 - s) blocks of the R^T rows below the matrix).
+// Workgroup 0 of a matrix owns block (s + 1, s + 1), the next
 // diagonal block: once its update is complete (no other workgroup writes
 // it), it keeps the block in LDS and factors it (diag64_body), so the next
 // step's diagonal work runs beside the rest of this update instead of in a
@@ -383,20 +389,30 @@ __global__ __launch_bounds__(kThreads) void chol_update64_kernel(double* __restr
                                                                  double* __restrict__ Linv64,
                                                                  double* __restrict__ Linv32,
                                                                  int32_t* __restrict__ flags,
-                                                                 int64_t Kp, int32_t s,
+                                                                 int64_t Kp, int64_t Kr, int32_t s,
                                                                  int32_t nb64) {
   __shared__ double Xs[NB2 * LDB], Ys[NB2 * LDB];
   const int64_t mat = blockIdx.x;
-  int32_t kk = (int32_t)blockIdx.y, ii = 0;
-  while (kk > ii) {
-    kk -= ii + 1;
-    ++ii;
+  const int32_t below = nb64 - 1 - s;
+  const int32_t tri = below * (below + 1) / 2;
+  int32_t ib, kb;
+  if ((int32_t)blockIdx.y < tri) {
+    int32_t kk = (int32_t)blockIdx.y, ii = 0;
+    while (kk > ii) {
+      kk -= ii + 1;
+      ++ii;
+    }
+    ib = s + 1 + ii;
+    kb = s + 1 + kk;
+  } else {  // a block of the R^T rows
+    const int32_t r = (int32_t)blockIdx.y - tri, ia = r / below;
+    ib = nb64 + ia;
+    kb = s + 1 + (r - ia * below);
   }
-  const int32_t ib = s + 1 + ii, kb = s + 1 + kk;
   const bool owner = blockIdx.y == 0;  // block (s + 1, s + 1)
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int fr = lane >> 4, fc = lane & 15, wm = w >> 1, wn = w & 1;
-  CVG_GLOBAL double* a = gmem(A) + mat * Kp * Kp;
+  CVG_GLOBAL double* a = gmem(A) + mat * Kr * Kp;
   CVG_GLOBAL double* out = a + (int64_t)ib * NB2 * Kp + (int64_t)kb * NB2;
   const bool idle = ib == kb && wm < wn;
   double4_t acc[2][2];
@@ -443,34 +459,32 @@ __global__ __launch_bounds__(kThreads) void chol_update64_kernel(double* __restr
   diag64_body(Xs, Ys, Ys + kI, Ys + 2 * kI, a, Linv64, Linv32, flags, Kp, mat, s + 1, nb64, t);
 }
 
-// Both substitutions in one launch: workgroup (matrix, block of 32 columns
-// of R) walks the block steps itself.
-//   forward step j:  Z_j = Linv_jj R_j;    R_i -= L_ij Z_j     for i > j
-//   backward step j: W_j = Linv_jj^T R_j;  R_i -= L_ji^T W_j   for i < j
-// In both passes the coefficient of Z[c] in row i is A[r0 + c][i]: the
-// factor's block row j in the lower triangle (backward, i < r0) or the
-// transposed copy of its block column j in the upper triangle (forward,
-// i >= r0 + 32).  One thread per row of R reads those 32 values down a column
-// of A, consecutive threads consecutive columns, all loads in flight.  The
-// rows of the next step's block go on to it through LDS as they are updated,
-// and the next diagonal inverse is loaded during the update, so a step waits
-// on memory once.  Each workgroup owns its rows x columns of R: its own
-// writes are the only ones it reads back (ordered by the barriers between
-// steps).  Padding rows of the last block (past K) stay zero.  MW (8, 16 or
-// 32) is the width of R each row update carries in registers: at least the
-// block's columns of B, the rest padding zeros that stay zero.
+// The backward substitution W = L^{-T} Z in one launch (Z = L^{-1} R, from
+// the factorisation): workgroup (matrix, block of 32 columns of R) walks the
+// block steps itself, last block first:
+//   step j:  W_j = Linv_jj^T R_j;  R_i -= L_ji^T W_j   for i < j
+// The coefficient of W[c] in row i is A[r0 + c][i], the factor's block row j
+// in the lower triangle.  One thread per row of R reads those 32 values along
+// a row of A, consecutive threads consecutive columns, all loads in flight.
+// The rows of the next step's block go on to it through LDS as they are
+// updated, and the next diagonal inverse is loaded during the update, so a
+// step waits on memory once.  Each workgroup owns its rows x columns of R:
+// its own writes are the only ones it reads back (ordered by the barriers
+// between steps).  Padding rows of the last block (past K) stay zero.  MW
+// (8, 16 or 32) is the width of R each row update carries in registers: at
+// least the block's columns of B, the rest padding zeros that stay zero.
 template <int MW, bool FAST>
 __global__ __launch_bounds__(solve_threads<MW>()) void tri_solve_kernel(const double* __restrict__ A,
                                                              const double* __restrict__ Linv,
                                                              double* __restrict__ R, int64_t K,
-                                                             int64_t M, int64_t Kp, int64_t Mp,
-                                                             int32_t nblk) {
+                                                             int64_t M, int64_t Kp, int64_t Kr,
+                                                             int64_t Mp, int32_t nblk) {
   __shared__ double Z[NB][NB + 1];
   __shared__ double Li[2][NB][NB + 1];
   __shared__ double Rb[NB][NB + 1];
   const int64_t mat = blockIdx.x;
   const int64_t m0 = (int64_t)blockIdx.y * NB;
-  const CVG_GLOBAL double* a = gmem(A) + mat * Kp * Kp;
+  const CVG_GLOBAL double* a = gmem(A) + mat * Kr * Kp;
   CVG_GLOBAL double* rr = gmem(R) + mat * Kp * Mp + m0;
   const int t = threadIdx.x, tx = t % NB, ty = t / NB;
   const bool blk = t < kThreads;  // one of the threads that handle a 32 x 32 block
@@ -482,11 +496,10 @@ __global__ __launch_bounds__(solve_threads<MW>()) void tri_solve_kernel(const do
     for (int q = 0; q < kRowsPerThread; ++q) vl[q] = li[(ty + kRowStep * q) * NB + tx];
   };
   int buf = 0;
-  for (int pass = 0; pass < 2; ++pass) {
-    const bool backward = pass == 1;
+  {
     {
-      // the pass's first block: its rows of R and its inverse from memory
-      const int32_t j = backward ? nblk - 1 : 0;
+      // the first block (the last one): its rows of R and its inverse
+      const int32_t j = nblk - 1;
       const int64_t r0 = (int64_t)j * NB;
       if (blk) {
         double vr[kRowsPerThread], vl[kRowsPerThread];
@@ -502,13 +515,13 @@ __global__ __launch_bounds__(solve_threads<MW>()) void tri_solve_kernel(const do
       __syncthreads();
     }
     // Rows of R in registers (Kp <= the thread count, MW <= 16): thread t
-    // keeps row t for the whole pass, so an update reads no R from memory,
+    // keeps row t for the whole walk, so an update reads no R from memory,
     // and the coefficients of its next step are loaded at the end of this
     // one, while the barrier and the next block's Z are in progress.
     double rv[MW], lc[NB];
     if (fast) {
-      const int32_t j = backward ? nblk - 1 : 0;
-      const int64_t lo = backward ? 0 : (int64_t)(j + 1) * NB, hi = backward ? (int64_t)j * NB : Kp;
+      const int32_t j = nblk - 1;
+      const int64_t lo = 0, hi = (int64_t)j * NB;
       if (t < Kp) {
 #pragma unroll
         for (int mm = 0; mm < MW; ++mm) rv[mm] = rr[(int64_t)t * Mp + mm];
@@ -518,11 +531,12 @@ __global__ __launch_bounds__(solve_threads<MW>()) void tri_solve_kernel(const do
         for (int c = 0; c < NB; ++c) lc[c] = a[((int64_t)j * NB + c) * Kp + t];
       }
     }
+#pragma unroll 1
     for (int32_t jj = 0; jj < nblk; ++jj) {
-      const int32_t j = backward ? nblk - 1 - jj : jj;
+      const int32_t j = nblk - 1 - jj;
       const int64_t r0 = (int64_t)j * NB;
       const bool last = jj + 1 == nblk;
-      const int32_t jn = backward ? j - 1 : j + 1;  // the next step's block
+      const int32_t jn = j - 1;  // the next step's block
       const int64_t n0 = (int64_t)jn * NB;
       if (blk) {
 #pragma unroll
@@ -532,21 +546,22 @@ __global__ __launch_bounds__(solve_threads<MW>()) void tri_solve_kernel(const do
           // above its diagonal, so the terms outside the triangle add zero
           // and the sum is that of the triangle, in the same order
           double sum = 0.0;
-          if (!backward) {
 #pragma unroll
-            for (int k = 0; k < NB; ++k) sum = fma(Li[buf][r][k], Rb[k][tx], sum);
-          } else {
-#pragma unroll
-            for (int k = 0; k < NB; ++k) sum = fma(Li[buf][k][r], Rb[k][tx], sum);
+          for (int k = 0; k < NB; ++k) {
+            sum = fma(Li[buf][k][r], Rb[k][tx], sum);
+            if (k % 8 == 7) __builtin_amdgcn_sched_barrier(0);
           }
           Z[r][tx] = sum;
           rr[(r0 + r) * Mp + tx] = sum;
         }
       }
+      // the stages below stay in order: the next coefficients' loads are
+      // not hoisted above this step's sums (both sets would be live)
+      __builtin_amdgcn_sched_barrier(0);
       __syncthreads();
       double vl[kRowsPerThread];
       if (!last && blk) load_li(jn, vl);
-      const int64_t lo = backward ? 0 : r0 + NB, hi = backward ? r0 : Kp;
+      const int64_t lo = 0, hi = r0;
       if (fast) {
         if (t >= lo && t < hi) {
           double sum[MW];
@@ -565,8 +580,9 @@ __global__ __launch_bounds__(solve_threads<MW>()) void tri_solve_kernel(const do
             for (int mm = 0; mm < MW; ++mm) Rb[t - n0][mm] = rv[mm];
           }
         }
-        // the next step's rows of the update: forward [n0 + 32, Kp), backward [0, n0)
-        const int64_t lo_n = backward ? 0 : n0 + NB, hi_n = backward ? n0 : Kp;
+        // the next step's rows of the update: [0, n0)
+        __builtin_amdgcn_sched_barrier(0);
+        const int64_t lo_n = 0, hi_n = n0;
         if (!last && t >= lo_n && t < hi_n) {
 #pragma unroll
           for (int c = 0; c < NB; ++c) lc[c] = a[(n0 + c) * Kp + t];
@@ -619,38 +635,51 @@ void ridge_solve(const double* xtx, const double* xty, const double* lambdas, in
   const int32_t nb64 = (int32_t)(Kp / NB2), nblk = (int32_t)(Kp / NB);
   double* Linv64 = Linv;                                // [n_mat][nb64][64][64]
   double* Linv32 = Linv + n_mat * nb64 * NB2 * NB2;     // [n_mat][nblk][32][32]
-  ridge_setup_kernel<<<dim3((unsigned)(Kp / kSetupRows), (unsigned)n_mat), kThreads, 0, s>>>(
-      xtx, xty, lambdas, n_lambda, K, M, Kp, Mp, A, R);
+  const int64_t Ma = ridge_aug_rows(M), Kr = Kp + Ma;
+  const int32_t naug = (int32_t)(Ma / NB2);
+  ridge_setup_kernel<<<dim3((unsigned)(Kr / kSetupRows), (unsigned)n_mat), kThreads, 0, s>>>(
+      xtx, xty, lambdas, n_lambda, K, M, Kp, Kr, A);
   CVG_LAUNCH_CHECK();
-  // diagonal block 0, then per block column s: the panel below it and the
-  // trailing update, which also factors diagonal block s + 1
-  chol_diag64_kernel<<<(unsigned)n_mat, kThreads, 0, s>>>(A, Linv64, Linv32, flags, Kp, nb64);
+  // diagonal block 0, then per block column s: the panel below it (the
+  // matrix's block rows and the R^T rows) and the trailing update, which
+  // also factors diagonal block s + 1
+  chol_diag64_kernel<<<(unsigned)n_mat, kThreads, 0, s>>>(A, Linv64, Linv32, flags, Kp, Kr, nb64);
   CVG_LAUNCH_CHECK();
-  for (int32_t j = 0; j + 1 < nb64; ++j) {
+  for (int32_t j = 0; j < nb64; ++j) {
     const int32_t below = nb64 - j - 1;
-    chol_panel64_kernel<<<dim3((unsigned)n_mat, (unsigned)below), kThreads, 0, s>>>(A, Linv64,
-                                                                                  Kp, j, nb64);
-    CVG_LAUNCH_CHECK();
-    chol_update64_kernel<<<dim3((unsigned)n_mat, (unsigned)(below * (below + 1) / 2)), kThreads,
-                           0, s>>>(A, Linv64, Linv32, flags, Kp, j, nb64);
-    CVG_LAUNCH_CHECK();
+    if (below + naug > 0) {
+      chol_panel64_kernel<<<dim3((unsigned)n_mat, (unsigned)(below + naug)), kThreads, 0, s>>>(
+          A, Linv64, Kp, Kr, j, nb64);
+      CVG_LAUNCH_CHECK();
+    }
+    if (below > 0) {
+      const int32_t blocks = below * (below + 1) / 2 + naug * below;
+      chol_update64_kernel<<<dim3((unsigned)n_mat, (unsigned)blocks), kThreads, 0, s>>>(
+          A, Linv64, Linv32, flags, Kp, Kr, j, nb64);
+      CVG_LAUNCH_CHECK();
+    }
   }
   if (M <= 0) return;
+  // the forward substitution is done ((L^{-1} R)^T below the factor)
+  ridge_z_kernel<<<dim3((unsigned)(Kp / 8), (unsigned)n_mat), kThreads, 0, s>>>(A, Kp, Kr, Mp, R);
+  CVG_LAUNCH_CHECK();
   const dim3 grid((unsigned)n_mat, (unsigned)(Mp / NB));
   const bool fast = Kp <= solve_threads<16>();  // one row of R per thread
   if (M <= 8 && fast)
-    tri_solve_kernel<8, true><<<grid, solve_threads<8>(), 0, s>>>(A, Linv32, R, K, M, Kp, Mp, nblk);
+    tri_solve_kernel<8, true><<<grid, solve_threads<8>(), 0, s>>>(A, Linv32, R, K, M, Kp, Kr, Mp,
+                                                                    nblk);
   else if (M <= 8)
-    tri_solve_kernel<8, false><<<grid, solve_threads<8>(), 0, s>>>(A, Linv32, R, K, M, Kp, Mp, nblk);
+    tri_solve_kernel<8, false><<<grid, solve_threads<8>(), 0, s>>>(A, Linv32, R, K, M, Kp, Kr, Mp,
+                                                                     nblk);
   else if (M <= 16 && fast)
-    tri_solve_kernel<16, true><<<grid, solve_threads<16>(), 0, s>>>(A, Linv32, R, K, M, Kp, Mp,
-                                                                      nblk);
+    tri_solve_kernel<16, true><<<grid, solve_threads<16>(), 0, s>>>(A, Linv32, R, K, M, Kp, Kr,
+                                                                      Mp, nblk);
   else if (M <= 16)
-    tri_solve_kernel<16, false><<<grid, solve_threads<16>(), 0, s>>>(A, Linv32, R, K, M, Kp, Mp,
-                                                                       nblk);
+    tri_solve_kernel<16, false><<<grid, solve_threads<16>(), 0, s>>>(A, Linv32, R, K, M, Kp, Kr,
+                                                                       Mp, nblk);
   else
-    tri_solve_kernel<NB, false><<<grid, solve_threads<NB>(), 0, s>>>(A, Linv32, R, K, M, Kp, Mp,
-                                                                       nblk);
+    tri_solve_kernel<NB, false><<<grid, solve_threads<NB>(), 0, s>>>(A, Linv32, R, K, M, Kp, Kr,
+                                                                       Mp, nblk);
   CVG_LAUNCH_CHECK();
   {
     const int64_t per = (K * M + kThreads - 1) / kThreads;
