@@ -105,13 +105,15 @@ def f_exec(n, k, m, mode, tile=None):
     return 2 * n * entries * rep
 
 
-def gram_kernel_name(mode, tile, f32_input):
-    """The Gram kernel the library launches (as rocprofv3 names it): FP64
-    mode keeps FP32 input in FP32 panels (third template argument)."""
+def gram_kernel_name(mode, plan):
+    """The Gram kernel the library launched (as rocprofv3 names it), from the
+    handle's plan: FP64 mode on FP32 panels (4 bytes per element) is the
+    third template argument."""
+    tile = plan["tile"]
     if mode == "bf16x3":
         return "gram_bf16_wide_kernel" if tile == 256 else f"gram_bf16_kernel<{tile}>"
     if mode == "fp64":
-        return f"gram_kernel<0, {tile}, {'true' if f32_input else 'false'}>"
+        return f"gram_kernel<0, {tile}, {'true' if plan['panel_bytes'] == 4 else 'false'}>"
     return f"gram_kernel<2, {tile}, false>"
 
 
@@ -248,9 +250,10 @@ def time_steps(cv, torch, Xd, Yd, fd, P, K, M, mode, steps, warmup, chunk, stage
     return (t1 - t0) * 1e3 / steps, stage_ms, plan
 
 
-def roofline(mode, n, k, m, stage_ms, workload, tile, f32_input):
+def roofline(mode, n, k, m, stage_ms, workload, plan):
     g = f_alg(n, k, m) / (stage_ms["gram"] * 1e-3) / 1e12
-    kname = gram_kernel_name(mode, tile, f32_input)
+    tile = plan["tile"]
+    kname = gram_kernel_name(mode, plan)
     return {"bound": "mfma", "kernel": kname, "achieved": g, "peak": PEAK[mode],
             "unit": "TFLOP/s", "frac": g / PEAK[mode],
             "traffic": profiled_traffic(kname, workload),
@@ -465,8 +468,7 @@ def headline_block(cv, torch, G, dev, args):
                               "sets_per_s": P * 12 / (ms * 1e-3),
                               "tflops_alg": f_alg(N, K, M) / (ms * 1e-3) / 1e12,
                               "stage_ms": st, "plan": plan,
-                              "roofline": roofline(mode, N, K, M, st, workload, plan["tile"],
-                                                   True)}
+                              "roofline": roofline(mode, N, K, M, st, workload, plan)}
         log(f"large problem {mode}: {ms:.1f} ms/step, Gram {st['gram']:.1f} ms")
     f64, b16 = res["modes"]["fp64"], res["modes"]["bf16x3"]
     b16["speedup_vs_fp64"] = f64["ms_per_step"] / b16["ms_per_step"]
@@ -525,8 +527,7 @@ def spectra_block(cv, torch, G, dev, args):
                               stages_inline=False)
     out = {"workload": shape.name, "ms_per_step": ms, "sets_per_s": P * 12 / (ms * 1e-3),
            "tflops_alg": f_alg(N, K, M) / (ms * 1e-3) / 1e12, "stage_ms": st, "plan": plan,
-           "roofline": roofline("fp64", N, K, M, st, shape.name, plan["tile"],
-                                Xd.dtype == torch.float32),
+           "roofline": roofline("fp64", N, K, M, st, shape.name, plan),
            "hbm": stage_bandwidth(N, K, M, P, X.itemsize, "fp64", st)}
     log("spectra timed steps done")
     if not args.no_check or not args.no_cpu:
@@ -600,7 +601,7 @@ def mixed_block(cv, torch, G, dev, args):
     for mode in ("fp64", "fp32", "bf16x3"):
         ms, st, plan = time_steps(cv, torch, Xd, Yd, fd, P, K, M, mode, args.mixed_steps, 1, 25,
                                   stages_inline=True)
-        rl = roofline(mode, N, K, M, st, shape.name, plan["tile"], Xd.dtype == torch.float32)
+        rl = roofline(mode, N, K, M, st, shape.name, plan)
         res["modes"][mode] = {"sets_per_s": P * 12 / (ms * 1e-3), "ms_per_step": ms,
                               "stage_ms": st, "plan": plan, "roofline": rl}
         log(f"mixed-block mode {mode}: {ms:.2f} ms/step, Gram {st['gram']:.2f} ms")

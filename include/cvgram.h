@@ -354,7 +354,10 @@ cvgram_status cvgram_batch_autotune(const cvgram_problem* problems, int32_t n,
  *   info[1] Gram work items (output tile x fold row range)
  *   info[2] slabs (per-fold row splits whose partial products are summed)
  *   info[3] 1 for the fused fold path (many small folds), else 0
- * n is the capacity of info (at most 4 entries are written). */
+ *   info[4] bytes per element of the packed panels the Gram launch reads
+ *           (FP64 mode: 8, or 4 when FP32 input is kept in FP32 panels; FP32
+ *           mode: 4; BF16X3: 2 per panel, hi and lo)
+ * n is the capacity of info (at most 5 entries are written). */
 cvgram_status cvgram_plan_info(cvgram_t h, int64_t* info, int32_t n);
 
 /* Change the stream used by later calls on this handle.  Work queued on the

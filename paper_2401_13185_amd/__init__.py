@@ -214,10 +214,12 @@ def cvgram_num_folds(h: Handle) -> int:
 
 def cvgram_plan_info(h: Handle) -> dict:
     """The plan the handle's launch used: tile edge, Gram work items, slabs,
-    and whether the fused fold path was taken."""
-    info = (_i64 * 4)()
-    _check(load().cvgram_plan_info(h.ptr, info, 4))
-    return {"tile": info[0], "items": info[1], "slabs": info[2], "fused": bool(info[3])}
+    whether the fused fold path was taken, and the packed panels' bytes per
+    element."""
+    info = (_i64 * 5)()
+    _check(load().cvgram_plan_info(h.ptr, info, 5))
+    return {"tile": info[0], "items": info[1], "slabs": info[2], "fused": bool(info[3]),
+            "panel_bytes": info[4]}
 
 
 def cvgram_partition(h: Handle, perm=None, offsets=None):

@@ -1628,9 +1628,9 @@ cvgram_status cvgram_plan_info(cvgram_t h, int64_t* info, int32_t n) {
   if (!h || (!info && n > 0)) return fail(CVGRAM_EINVAL, "NULL argument");
   const Batch& b = h->b;
   const ProbPlan& p = b.pp[0];
-  const int64_t v[4] = {p.cfg.tile, b.n_work[0] + b.n_work[1] + b.n_work[2], p.n_slabs,
-                        p.fused ? 1 : 0};
-  for (int32_t k = 0; k < n && k < 4; ++k) info[k] = v[k];
+  const int64_t v[5] = {p.cfg.tile, b.n_work[0] + b.n_work[1] + b.n_work[2], p.n_slabs,
+                        p.fused ? 1 : 0, (int64_t)elem_bytes(b)};
+  for (int32_t k = 0; k < n && k < 5; ++k) info[k] = v[k];
   return CVGRAM_OK;
 }
 

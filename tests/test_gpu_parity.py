@@ -52,6 +52,10 @@ def _check_all_folds(X, Y, fold, ddof, mode="fp64", tol=FP64_TOL, folds=None, la
     h = cv.cvgram_create(Xd, Yd, fd, 1, 1, 1, 1, ddof=ddof, mode=mode)
     P = cv.cvgram_num_folds(h)
     assert P == int(fold.max()) + 1
+    if mode == "fp64":
+        # FP32 input keeps FP32 panels up to K = 2048, FP64 panels otherwise
+        f32_panels = X.dtype == np.float32 and X.shape[1] <= 2048
+        assert cv.cvgram_plan_info(h)["panel_bytes"] == (4 if f32_panels else 8), label
     xx, xy = cv.cvgram_folds_all(h, 0, P)
     torch.cuda.synchronize()
     xx = xx.cpu().numpy()
