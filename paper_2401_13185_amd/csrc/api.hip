@@ -782,11 +782,12 @@ int64_t gram_item_cost(const GramWork& w, const std::vector<ProbPlan>& pp) {
 // range stay together and share the XCD's L2).
 constexpr int kTailPercent = 30;
 // single problems with at least kTileGroupMinNt tile columns visit their
-// tiles in square groups and spread the list over the XCDs round-robin
-// (ProbPlan::tile_groups).  Below that the per-XCD ranges keep a fold row
-// range's tiles in one L2: measured, the BF16X3 launch on K = 1024 slows
-// from 3.8 to 4.5 ms with groups, and the FP64 launch on K = 512 gains 1 %
-// while its L2 misses double (served by the memory-side cache).
+// tiles in square groups, each group on one XCD (ProbPlan::tile_groups).
+// Below that the per-XCD ranges keep a fold row range's tiles in one L2:
+// measured with groups dealt item by item round-robin over the XCDs, the
+// BF16X3 launch on K = 1024 slowed from 3.8 to 4.5 ms, and the FP64 launch
+// on K = 512 gained 1 % while its L2 misses doubled (served by the
+// memory-side cache).
 constexpr int32_t kTileGroup = 8;
 constexpr int32_t kTileGroupMinNt = 16;
 void order_tails(std::vector<GramWork>& wl, const std::vector<int32_t>& xcd,
@@ -809,15 +810,44 @@ void schedule_gram(std::vector<GramWork>& wl, std::vector<int32_t>& xcd, bool ba
     const int32_t per = (n + kXcds - 1) / kXcds;
     for (int x = 0; x <= kXcds; ++x) xcd[x] = std::min(n, x * per);
     if (pp[0].tile_groups) {
-      // list order round-robin over the XCDs: workgroup b runs list item b,
-      // so all XCDs work on the same tile groups of the same rows at once
-      // and share them through the memory-side cache.  Range x holds the
-      // items i with i % kXcds == x.
-      for (int x = 0; x < kXcds; ++x) xcd[x + 1] = xcd[x] + (n > x ? (n - x + kXcds - 1) / kXcds : 0);
-      thread_local std::vector<GramWork> rr_tl;
-      std::vector<GramWork>& out = rr_tl;
+      // whole tile groups per XCD: the items of one group (one fold row
+      // range, at most 2 x 8 column blocks) run together on one XCD and
+      // read their column blocks through its L2 once per group instead of
+      // once per item.  Groups go in list order to the XCD with the least
+      // work so far, so the XCDs stay on neighbouring groups of the same
+      // rows (shared through the memory-side cache).
+      const ProbPlan& p = pp[0];
+      const int32_t ga = p.cfg.tile == 256 ? kTileGroup / 2 : kTileGroup;
+      auto same_group = [&](const GramWork& u, const GramWork& v) {
+        const int32_t gu = u.tj < p.nt ? u.tj / kTileGroup : -1;
+        const int32_t gv = v.tj < p.nt ? v.tj / kTileGroup : -1;
+        return u.slab == v.slab && u.ti / ga == v.ti / ga && gu == gv;
+      };
+      thread_local std::vector<int32_t> owner_tl;
+      thread_local std::vector<GramWork> out_tl;
+      std::vector<int32_t>& owner = owner_tl;
+      owner.assign(wl.size(), 0);
+      int64_t load[kXcds] = {};
+      int32_t count[kXcds] = {};
+      for (int32_t i = 0; i < n;) {
+        int32_t j = i + 1;
+        while (j < n && same_group(wl[j], wl[i])) ++j;
+        int x = 0;
+        for (int y = 1; y < kXcds; ++y)
+          if (load[y] < load[x]) x = y;
+        for (int32_t k = i; k < j; ++k) {
+          owner[k] = x;
+          load[x] += gram_item_cost(wl[k], pp);
+        }
+        count[x] += j - i;
+        i = j;
+      }
+      for (int x = 0; x < kXcds; ++x) xcd[x + 1] = xcd[x] + count[x];
+      std::vector<GramWork>& out = out_tl;
       out.resize(wl.size());
-      for (int32_t i = 0; i < n; ++i) out[xcd[i % kXcds] + i / kXcds] = wl[i];
+      int32_t fill[kXcds];
+      for (int x = 0; x < kXcds; ++x) fill[x] = xcd[x];
+      for (int32_t i = 0; i < n; ++i) out[fill[owner[i]]++] = wl[i];
       wl.swap(out);
     }
     order_tails(wl, xcd, pp);
