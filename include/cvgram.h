@@ -321,12 +321,15 @@ cvgram_status cvgram_batch_destroy(cvgram_batch_t b);
  * Autotuner of the grouped Gram launch.  Times the candidate tile widths (64,
  * 128, and in CVGRAM_MODE_BF16X3 the 256 x 128 tiles when K > 128) and
  * work-list sizes on the given problem (device data as in
- * cvgram_create), records the fastest in a process-wide table keyed by
- * (mode, dtype, K, M and N rounded to powers of two), and returns it.  Later
- * cvgram_create / cvgram_batch_create calls whose problem falls in a tuned
- * bucket use the recorded choice.  With the environment variable
- * CVGRAM_TUNE_FILE set, the table is loaded from that file at first use and
- * rewritten after each tuning.  Waits on `stream`.
+ * cvgram_create), records the fastest in a process-wide table keyed by the
+ * device (architecture name and compute-unit count), mode, dtype and K,
+ * M + 1, N and the mean fold size N / P rounded up to powers of two, and
+ * returns it.  Later cvgram_create / cvgram_batch_create calls on the same
+ * kind of device whose problem falls in a tuned bucket use the recorded
+ * choice.  With the environment variable CVGRAM_TUNE_FILE set, the table is
+ * loaded from that file at first use (one entry per line: device key, the
+ * six bucket numbers, tile, work-list size; entries of other devices are
+ * kept and ignored) and rewritten after each tuning.  Waits on `stream`.
  * ------------------------------------------------------------------------- */
 cvgram_status cvgram_autotune(const void* X, const void* Y, const int32_t* fold_id, int64_t N,
                               int64_t K, int64_t M, cvgram_dtype dtype, cvgram_mode mode,

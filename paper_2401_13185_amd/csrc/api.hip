@@ -333,9 +333,15 @@ int log2_bucket(int64_t v) {
   return b;
 }
 
+// Tuned choices, keyed by the device (architecture name and compute-unit
+// count: a table written on another part is kept but not used), the mode,
+// the input type and log2 buckets of K, M + 1, N and the mean fold size
+// N / P (which sets how many row splits fill the chip).
+using TuneKey = std::tuple<std::string, int, int, int, int, int, int>;
 struct TuneTable {
   std::mutex mu;
-  std::map<std::tuple<int, int, int, int, int>, Config> t;
+  std::map<TuneKey, Config> t;
+  std::map<int, std::string> arch;  // device ordinal -> key of its part
   bool loaded = false;
 };
 TuneTable& tune_table() {
@@ -343,9 +349,25 @@ TuneTable& tune_table() {
   return *t;
 }
 
-std::tuple<int, int, int, int, int> tune_key(cvgram_mode mode, cvgram_dtype dt, int64_t K,
-                                             int64_t M, int64_t N) {
-  return std::make_tuple((int)mode, (int)dt, log2_bucket(K), log2_bucket(M + 1), log2_bucket(N));
+// "<gcnArchName>/<CUs>" of the current device, with no spaces (call with the
+// table's mutex held)
+const std::string& device_arch_locked(TuneTable& tt) {
+  int dev = 0;
+  CVG_HIP(hipGetDevice(&dev));
+  auto it = tt.arch.find(dev);
+  if (it != tt.arch.end()) return it->second;
+  hipDeviceProp_t prop;
+  CVG_HIP(hipGetDeviceProperties(&prop, dev));
+  std::string a = std::string(prop.gcnArchName) + "/" + std::to_string(prop.multiProcessorCount);
+  for (char& ch : a)
+    if (ch == ' ') ch = '_';
+  return tt.arch[dev] = a;
+}
+
+TuneKey tune_key_locked(TuneTable& tt, cvgram_mode mode, cvgram_dtype dt, int64_t K, int64_t M,
+                        int64_t N, int64_t P) {
+  return TuneKey(device_arch_locked(tt), (int)mode, (int)dt, log2_bucket(K), log2_bucket(M + 1),
+                 log2_bucket(N), log2_bucket(std::max<int64_t>(1, N / std::max<int64_t>(1, P))));
 }
 
 void tune_load_locked(TuneTable& tt) {
@@ -355,11 +377,13 @@ void tune_load_locked(TuneTable& tt) {
   if (!path) return;
   FILE* f = std::fopen(path, "r");
   if (!f) return;
-  int a, b, c, d, e, tile;
+  char arch[128];
+  int a, b, c, d, e, v, tile;
   long long items;
-  while (std::fscanf(f, "%d %d %d %d %d %d %lld", &a, &b, &c, &d, &e, &tile, &items) == 7)
+  while (std::fscanf(f, "%127s %d %d %d %d %d %d %d %lld", arch, &a, &b, &c, &d, &e, &v, &tile,
+                     &items) == 9)
     if ((tile == 64 || tile == 128 || tile == 256) && items > 0)
-      tt.t[std::make_tuple(a, b, c, d, e)] = {tile, items};
+      tt.t[TuneKey(arch, a, b, c, d, e, v)] = {tile, items};
   std::fclose(f);
 }
 
@@ -369,8 +393,9 @@ void tune_save_locked(TuneTable& tt) {
   FILE* f = std::fopen(path, "w");
   if (!f) return;
   for (auto& kv : tt.t)
-    std::fprintf(f, "%d %d %d %d %d %d %lld\n", std::get<0>(kv.first), std::get<1>(kv.first),
-                 std::get<2>(kv.first), std::get<3>(kv.first), std::get<4>(kv.first),
+    std::fprintf(f, "%s %d %d %d %d %d %d %d %lld\n", std::get<0>(kv.first).c_str(),
+                 std::get<1>(kv.first), std::get<2>(kv.first), std::get<3>(kv.first),
+                 std::get<4>(kv.first), std::get<5>(kv.first), std::get<6>(kv.first),
                  kv.second.tile, (long long)kv.second.target_items);
   std::fclose(f);
 }
@@ -399,11 +424,12 @@ int natural_tile(cvgram_mode mode, int64_t K) {
   return (mode == CVGRAM_MODE_BF16X3 && K > 128) ? 256 : 128;
 }
 
-Config choose_config(cvgram_mode mode, cvgram_dtype dt, int64_t K, int64_t M, int64_t N) {
+Config choose_config(cvgram_mode mode, cvgram_dtype dt, int64_t K, int64_t M, int64_t N,
+                     int64_t P) {
   TuneTable& tt = tune_table();
   std::lock_guard<std::mutex> g(tt.mu);
   tune_load_locked(tt);
-  auto it = tt.t.find(tune_key(mode, dt, K, M, N));
+  auto it = tt.t.find(tune_key_locked(tt, mode, dt, K, M, N, P));
   if (it != tt.t.end()) return it->second;
   return default_config(mode, K);
 }
@@ -909,7 +935,7 @@ void plan_layout(Batch& b, HostLists& L) {
       p.cfg = b.forced;
       p.cfg.tile = std::min(b.forced.tile, natural_tile(b.mode, p.K));
     } else {
-      p.cfg = choose_config(b.mode, b.dtype, p.K, p.M, p.N);
+      p.cfg = choose_config(b.mode, b.dtype, p.K, p.M, p.N, p.P);
     }
     const int T = p.cfg.tile;
     p.fused = choose_fused(p);
@@ -1821,7 +1847,8 @@ namespace {
 // configuration `cfg` (each problem's tile capped by its own widest).  The
 // candidate's workspace goes back to the cache on every path.
 double time_candidate(const std::vector<ProbPlan>& pp, cvgram_dtype dtype, cvgram_mode mode,
-                      hipStream_t stream, const Config& cfg, cvgram_status& st) {
+                      hipStream_t stream, const Config& cfg, cvgram_status& st,
+                      std::vector<int32_t>* folds = nullptr) {
   Batch b;
   struct Releaser {
     Batch& b;
@@ -1841,6 +1868,10 @@ double time_candidate(const std::vector<ProbPlan>& pp, cvgram_dtype dtype, cvgra
   CVG_HIP(hipGetDevice(&b.device));
   st = prepare(b);
   if (st != CVGRAM_OK) return 1e300;
+  if (folds) {
+    folds->clear();
+    for (const ProbPlan& q : b.pp) folds->push_back(q.P);
+  }
   run_pipeline(b, true);  // warm
   double ms = 1e300;
   for (int rep = 0; rep < 3; ++rep) {
@@ -1880,6 +1911,7 @@ cvgram_status cvgram_autotune(const void* X, const void* Y, const int32_t* fold_
   const std::vector<ProbPlan> pp{p};
   Config best;
   double best_ms = 1e300;
+  std::vector<int32_t> folds;
   try {
     for (int t : kTuneTiles) {
       if (t == 64 && K > 1024) continue;   // too many tiles to pay off
@@ -1888,7 +1920,7 @@ cvgram_status cvgram_autotune(const void* X, const void* Y, const int32_t* fold_
         Config c;
         c.tile = t;
         c.target_items = it;
-        const double ms = time_candidate(pp, dtype, mode, (hipStream_t)stream, c, st);
+        const double ms = time_candidate(pp, dtype, mode, (hipStream_t)stream, c, st, &folds);
         if (st != CVGRAM_OK) return st;
         if (ms < best_ms) {
           best_ms = ms;
@@ -1903,7 +1935,7 @@ cvgram_status cvgram_autotune(const void* X, const void* Y, const int32_t* fold_
     TuneTable& tt = tune_table();
     std::lock_guard<std::mutex> g(tt.mu);
     tune_load_locked(tt);
-    tt.t[tune_key(mode, dtype, K, M, N)] = best;
+    tt.t[tune_key_locked(tt, mode, dtype, K, M, N, folds.empty() ? 1 : folds[0])] = best;
     tune_save_locked(tt);
   }
   if (tile) *tile = best.tile;
@@ -1938,6 +1970,7 @@ cvgram_status cvgram_batch_autotune(const cvgram_problem* problems, int32_t n, c
   }
   Config best;
   double best_ms = 1e300;
+  std::vector<int32_t> folds;
   cvgram_status st = CVGRAM_OK;
   try {
     for (int t : kTuneTiles) {
@@ -1946,7 +1979,7 @@ cvgram_status cvgram_batch_autotune(const cvgram_problem* problems, int32_t n, c
         Config c;
         c.tile = t;
         c.target_items = it;
-        const double ms = time_candidate(pp, dtype, mode, (hipStream_t)stream, c, st);
+        const double ms = time_candidate(pp, dtype, mode, (hipStream_t)stream, c, st, &folds);
         if (st != CVGRAM_OK) return st;
         if (ms < best_ms) {
           best_ms = ms;
@@ -1963,10 +1996,11 @@ cvgram_status cvgram_batch_autotune(const cvgram_problem* problems, int32_t n, c
     TuneTable& tt = tune_table();
     std::lock_guard<std::mutex> g(tt.mu);
     tune_load_locked(tt);
-    for (const ProbPlan& p : pp) {
+    for (size_t i = 0; i < pp.size(); ++i) {
+      const ProbPlan& p = pp[i];
       Config c = best;
       c.tile = std::min(best.tile, natural_tile(mode, p.K));
-      tt.t[tune_key(mode, dtype, p.K, p.M, p.N)] = c;
+      tt.t[tune_key_locked(tt, mode, dtype, p.K, p.M, p.N, i < folds.size() ? folds[i] : 1)] = c;
     }
     tune_save_locked(tt);
   }

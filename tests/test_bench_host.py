@@ -56,7 +56,7 @@ def test_traffic_follows_the_source_hash(tmp_path, monkeypatch):
 def test_committed_summary_names_its_sources():
     # the committed summary carries a hash of the three sources it covers
     kv = {}
-    with open(os.path.join(ROOT, "profiles", "gram_hbm_traffic.txt")) as fh:
+    with open(os.path.join(ROOT, "profiles", "gram_fp64_large_hbm_traffic.txt")) as fh:
         for line in fh:
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)

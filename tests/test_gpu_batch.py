@@ -259,3 +259,46 @@ def test_batch_full_size_sampled():
                 assert np.max(np.abs(got - ref)) <= FP64_TOL * scale, (i, q, c)
     for b in outs.values():
         cv.cvgram_batch_destroy(b)
+
+
+_TUNE_CHILD = r"""
+import sys, numpy as np, torch
+sys.path.insert(0, sys.argv[1])
+import paper_2401_13185_amd as cv
+from synth import generators as G
+shape = G.Shape("tune file", 6000, 160, 4, 5, "f32", "spectra", "dirichlet")
+X, Y, f = G.make(shape, 91, 0)
+dev = torch.device("cuda:0")
+Xd, Yd, fd = (torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (X, Y, f))
+if sys.argv[2] == "tune":
+    tile, items = cv.cvgram_autotune(Xd, Yd, fd, mode="bf16x3")
+    print("CHOICE", tile, items, flush=True)
+else:
+    h = cv.cvgram_create(Xd, Yd, fd, 1, 1, 1, 1, mode="bf16x3")
+    print("PLAN", cv.cvgram_plan_info(h)["tile"], flush=True)
+    cv.cvgram_destroy(h)
+"""
+
+
+def test_tune_file_round_trip(tmp_path):
+    """An autotuned choice written to CVGRAM_TUNE_FILE (keyed by the device)
+    is the plan a later process takes for the same problem."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, CVGRAM_TUNE_FILE=str(tmp_path / "tune.txt"))
+    script = tmp_path / "child.py"
+    script.write_text(_TUNE_CHILD)
+    out = subprocess.run([sys.executable, str(script), root, "tune"], env=env, capture_output=True,
+                         text=True, timeout=240)
+    assert out.returncode == 0, out.stderr[-2000:]
+    tile = int(out.stdout.split("CHOICE")[1].split()[0])
+    lines = (tmp_path / "tune.txt").read_text().splitlines()
+    print("[tune file]", lines, flush=True)
+    assert lines and all(len(ln.split()) == 9 for ln in lines)
+    assert all(ln.split()[0].startswith("gfx") for ln in lines)
+    out = subprocess.run([sys.executable, str(script), root, "plan"], env=env, capture_output=True,
+                         text=True, timeout=240)
+    assert out.returncode == 0, out.stderr[-2000:]
+    assert int(out.stdout.split("PLAN")[1].split()[0]) == tile
