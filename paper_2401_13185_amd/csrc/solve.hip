@@ -5,9 +5,10 @@
 // Section 1: RR, and OLS for lambda = 0).
 //
 // The systems are copied into padded workspaces first: A to Kp x Kp with the
-// identity in the padding (Kp a multiple of 64), R to Kp x Mp with zeros (Mp
-// a multiple of 32), so no kernel below needs a bounds check and every load
-// can be issued without waiting for the one before it.
+// identity in the padding (Kp a multiple of 64) and R^T below it in
+// Ma = ceil(M / 64) 64 rows with zeros in the padding, so no kernel below
+// needs a bounds check and every load can be issued without waiting for the
+// one before it.
 //
 // Blocked right-looking Cholesky A = L L^T with 64 x 64 blocks:
 //   for each block column s
@@ -57,10 +58,9 @@ constexpr int solve_threads() {
 // padded systems: A + lambda I in Kp x Kp (identity in the padding) and,
 // below it, R^T in Ma rows of Kp (zeros in the padding), from the products
 // (p-major, lambda-minor).  Of the square part only the 64 x 64 blocks on and
-// below the diagonal are written: the factorisation reads nothing else, and
-// the blocks above are written by it (the transposed panels) before the
-// substitution reads them.  The rows of R^T are factored with the matrix
-// (they become (L^{-1} R)^T: the forward substitution).
+// below the diagonal are written: nothing reads the blocks above.  The rows
+// of R^T are factored with the matrix (they become (L^{-1} R)^T: the forward
+// substitution).
 // grid (Kr / kSetupRows, matrices), Kr = Kp + Ma: a workgroup fills
 // kSetupRows rows, two neighbouring columns per thread
 constexpr int kSetupRows = 8;
