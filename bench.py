@@ -654,11 +654,11 @@ def batched_block(cv, torch, G, dev, args):
     outs = {}
     for mode in ("fp64", "bf16x3"):
         t0 = time.perf_counter()
-        tile, items, tms = cv.cvgram_batch_autotune(probs, mode=mode)
-        tune = {"max_tile": tile, "target_items": items, "gram_stage_ms": tms,
-                "seconds": round(time.perf_counter() - t0, 2)}
-        log(f"batched mode {mode}: autotuned in the batch: tile <= {tile}, {items} items "
-            f"({tune['seconds']} s)")
+        tile, wide_k, items, tms = cv.cvgram_batch_autotune(probs, mode=mode)
+        tune = {"max_tile": tile, "wide_min_k": wide_k, "target_items": items,
+                "gram_stage_ms": tms, "seconds": round(time.perf_counter() - t0, 2)}
+        log(f"batched mode {mode}: autotuned in the batch: tile <= {tile} "
+            f"(256 x 128 from K >= {wide_k}), {items} items ({tune['seconds']} s)")
         t0 = time.perf_counter()
         b = cv.cvgram_batch_create(probs, ddof=1, mode=mode)
         torch.cuda.synchronize()

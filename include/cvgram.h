@@ -338,19 +338,24 @@ cvgram_status cvgram_autotune(const void* X, const void* Y, const int32_t* fold_
 /* Autotuner of a batch's Gram launches, in the batch itself: times the
  * batch's problems (as cvgram_batch_create would plan them, pack through
  * slab reduction, eager) under each candidate widest tile (64, 128, and in
- * CVGRAM_MODE_BF16X3 256; every problem's tile is capped by its own widest
- * under the built-in rule) and work-list size, and records the fastest for
+ * CVGRAM_MODE_BF16X3 256 x 128 tiles, for every problem the built-in rule
+ * gives them or only for K >= 512; every problem's tile is capped by its own
+ * widest under the built-in rule) and work-list size (512 .. 16384 items),
+ * and records the fastest for
  * every problem's bucket of the table above, so that a following
  * cvgram_batch_create of these problems uses it.  Tuning each problem alone
  * (cvgram_autotune) can choose narrow tiles that give a lone small problem
  * enough work items but lose inside a batch, where the problems share the
  * launch.  problems[i]: as for cvgram_batch_create (outputs are not
  * touched); ddof does not change the timing and is taken as 1.  Outputs
- * (host, each may be NULL): the widest tile and work-list size chosen, and
- * their Gram-stage time in ms.  Waits on `stream`. */
+ * (host, each may be NULL): the widest tile chosen, the smallest K that
+ * takes 256 x 128 tiles under it (0: every problem the built-in rule gives
+ * them), the work-list size, and their Gram-stage time in ms.  Waits on
+ * `stream`. */
 cvgram_status cvgram_batch_autotune(const cvgram_problem* problems, int32_t n,
                                     cvgram_dtype dtype, cvgram_mode mode, void* stream,
-                                    int32_t* max_tile, int32_t* target_items, double* gram_ms);
+                                    int32_t* max_tile, int32_t* wide_min_k,
+                                    int32_t* target_items, double* gram_ms);
 
 /* The plan cvgram_create chose for this handle (host values):
  *   info[0] tile width of the Gram launch (64, 128, or 256: 256 x 128 tiles)

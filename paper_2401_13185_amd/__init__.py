@@ -84,7 +84,8 @@ _SIGS = {
     "cvgram_autotune": (_int, [_vp, _vp, _vp, _i64, _i64, _i64, _int, _int, _vp,
                                ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "cvgram_batch_autotune": (_int, [_vp, _i32, _int, _int, _vp, ctypes.POINTER(_i32),
-                                     ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_double)]),
+                                     ctypes.POINTER(_i32), ctypes.POINTER(_i32),
+                                     ctypes.POINTER(ctypes.c_double)]),
     "cvgram_stage_times": (_int, [_vp, ctypes.POINTER(ctypes.c_double), _i32]),
     "cvgram_trim_cache": (_int, []),
 }
@@ -457,8 +458,9 @@ def cvgram_batch_create(problems, ddof=1, mode="fp64", stream=None) -> Batch:
 
 def cvgram_batch_autotune(problems, mode="fp64", stream=None):
     """Tune the Gram launches of a batch of (X, Y, fold_id) problems in the
-    batch itself; returns (widest tile, target items, Gram-stage ms).  A
-    following cvgram_batch_create of these problems uses the choice."""
+    batch itself; returns (widest tile, smallest K on 256 x 128 tiles (0: the
+    built-in rule), target items, Gram-stage ms).  A following
+    cvgram_batch_create of these problems uses the choice."""
     torch = _torch()
     if not problems:
         raise ValueError("need at least one problem")
@@ -473,11 +475,12 @@ def cvgram_batch_autotune(problems, mode="fp64", stream=None):
         M = 0 if Y is None else Y.shape[1]
         arr[i] = _Problem(_ptr(X, "X"), _ptr(Y, "Y") if M else None,
                           _ptr(f, "fold_id", torch.int32, N), N, K, M, None, None)
-    tile, items, ms = _i32(), _i32(), ctypes.c_double()
+    tile, wide_k, items, ms = _i32(), _i32(), _i32(), ctypes.c_double()
     _check(load().cvgram_batch_autotune(arr, len(problems), 1 if dt == torch.float64 else 0,
                                         MODES[mode], _stream_ptr(stream), ctypes.byref(tile),
-                                        ctypes.byref(items), ctypes.byref(ms)))
-    return tile.value, items.value, ms.value
+                                        ctypes.byref(wide_k), ctypes.byref(items),
+                                        ctypes.byref(ms)))
+    return tile.value, wide_k.value, items.value, ms.value
 
 
 def cvgram_batch_run(b: Batch):

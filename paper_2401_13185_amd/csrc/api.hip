@@ -325,6 +325,9 @@ struct Owned {
 struct Config {
   int tile = 128;
   int64_t target_items = 1024;  // Gram work items to aim for
+  // a tuned batch rule: 256 x 128 tiles only for K >= wide_min_k (0: every
+  // problem the built-in rule gives them)
+  int64_t wide_min_k = 0;
 };
 
 int log2_bucket(int64_t v) {
@@ -934,6 +937,7 @@ void plan_layout(Batch& b, HostLists& L) {
       // a candidate's tile width caps each problem's own widest one
       p.cfg = b.forced;
       p.cfg.tile = std::min(b.forced.tile, natural_tile(b.mode, p.K));
+      if (p.cfg.tile == 256 && p.K < b.forced.wide_min_k) p.cfg.tile = 128;
     } else {
       p.cfg = choose_config(b.mode, b.dtype, p.K, p.M, p.N, p.P);
     }
@@ -1885,7 +1889,9 @@ double time_candidate(const std::vector<ProbPlan>& pp, cvgram_dtype dtype, cvgra
 }
 
 const int kTuneTiles[3] = {64, 128, 256};
-const int64_t kTuneItems[4] = {512, 1024, 2048, 4096};
+const int64_t kTuneItems[6] = {512, 1024, 2048, 4096, 8192, 16384};
+// a batch also tries 256 x 128 tiles for its widest problems only
+const int64_t kTuneWideMinK[2] = {0, 512};
 
 }  // namespace
 
@@ -1945,7 +1951,7 @@ cvgram_status cvgram_autotune(const void* X, const void* Y, const int32_t* fold_
 
 cvgram_status cvgram_batch_autotune(const cvgram_problem* problems, int32_t n, cvgram_dtype dtype,
                                     cvgram_mode mode, void* stream, int32_t* max_tile,
-                                    int32_t* target_items, double* gram_ms) {
+                                    int32_t* wide_min_k, int32_t* target_items, double* gram_ms) {
   set_error("");
   if (!problems || n < 1) return fail(CVGRAM_EINVAL, "need at least one problem");
   if (dtype != CVGRAM_F32 && dtype != CVGRAM_F64) return fail(CVGRAM_EINVAL, "bad dtype");
@@ -1975,15 +1981,19 @@ cvgram_status cvgram_batch_autotune(const cvgram_problem* problems, int32_t n, c
   try {
     for (int t : kTuneTiles) {
       if (t > widest) continue;
-      for (int64_t it : kTuneItems) {
-        Config c;
-        c.tile = t;
-        c.target_items = it;
-        const double ms = time_candidate(pp, dtype, mode, (hipStream_t)stream, c, st, &folds);
-        if (st != CVGRAM_OK) return st;
-        if (ms < best_ms) {
-          best_ms = ms;
-          best = c;
+      for (int64_t wk : kTuneWideMinK) {
+        if (wk > 0 && t != 256) continue;
+        for (int64_t it : kTuneItems) {
+          Config c;
+          c.tile = t;
+          c.target_items = it;
+          c.wide_min_k = wk;
+          const double ms = time_candidate(pp, dtype, mode, (hipStream_t)stream, c, st, &folds);
+          if (st != CVGRAM_OK) return st;
+          if (ms < best_ms) {
+            best_ms = ms;
+            best = c;
+          }
         }
       }
     }
@@ -2000,11 +2010,14 @@ cvgram_status cvgram_batch_autotune(const cvgram_problem* problems, int32_t n, c
       const ProbPlan& p = pp[i];
       Config c = best;
       c.tile = std::min(best.tile, natural_tile(mode, p.K));
+      if (c.tile == 256 && p.K < best.wide_min_k) c.tile = 128;
+      c.wide_min_k = 0;
       tt.t[tune_key_locked(tt, mode, dtype, p.K, p.M, p.N, i < folds.size() ? folds[i] : 1)] = c;
     }
     tune_save_locked(tt);
   }
   if (max_tile) *max_tile = best.tile;
+  if (wide_min_k) *wide_min_k = (int32_t)best.wide_min_k;
   if (target_items) *target_items = (int32_t)best.target_items;
   if (gram_ms) *gram_ms = best_ms;
   return CVGRAM_OK;

@@ -97,6 +97,17 @@ def test_batch_and_autotune_reject_bad_arguments():
     t, i = ctypes.c_int32(), ctypes.c_int32()
     assert lib.cvgram_autotune(None, None, FAKE, 10, 3, 0, 1, 0, None, ctypes.byref(t),
                                ctypes.byref(i)) == 1
+    # the batch tuner validates before any device work
+    w, ms = ctypes.c_int32(), ctypes.c_double()
+    outs = (ctypes.byref(t), ctypes.byref(w), ctypes.byref(i), ctypes.byref(ms))
+    probs[0] = cv._Problem(FAKE, FAKE, FAKE, 10, 3, 1, None, None)
+    assert lib.cvgram_batch_autotune(None, 1, 1, 0, None, *outs) == 1
+    assert lib.cvgram_batch_autotune(probs, 0, 1, 0, None, *outs) == 1
+    assert lib.cvgram_batch_autotune(probs, 1, 5, 0, None, *outs) == 1
+    assert lib.cvgram_batch_autotune(probs, 1, 1, 7, None, *outs) == 1
+    probs[0] = cv._Problem(FAKE, None, FAKE, 10, 3, 2, None, None)   # Y NULL with M > 0
+    assert lib.cvgram_batch_autotune(probs, 1, 1, 0, None, *outs) == 1
+    assert "problem 0" in cv.cvgram_last_error_message()
 
 
 def test_product_path_has_no_oracle_or_cpu_fallback():

@@ -174,7 +174,7 @@ def test_autotune_returns_valid_choice_and_results_stay_correct():
     Xd, Yd, fd = _t(X), _t(Y), _t(f)
     tile, items = cv.cvgram_autotune(Xd, Yd, fd, mode="bf16x3")
     print(f"[autotune] tile={tile} items={items}", flush=True)
-    assert tile in (64, 128, 256) and items in (512, 1024, 2048, 4096)
+    assert tile in (64, 128, 256) and items in (512, 1024, 2048, 4096, 8192, 16384)
     h = cv.cvgram_create(Xd, Yd, fd, 1, 1, 1, 1, mode="bf16x3")   # uses the tuned bucket
     xx, xy = cv.cvgram_folds_all(h, 0, 6)
     oxx, oxy = O.fold_all_classes(X, Y, f, 2, ddof=1)
@@ -187,9 +187,12 @@ def test_autotune_returns_valid_choice_and_results_stay_correct():
 def test_batch_autotune_choice_used_and_correct(mode):
     probs = _problems("f32")
     dev_probs = [(_t(X), _t(Y) if Y.shape[1] else None, _t(f)) for X, Y, f in probs]
-    tile, items, ms = cv.cvgram_batch_autotune(dev_probs, mode=mode)
-    print(f"[batch autotune] mode={mode} tile={tile} items={items} gram_ms={ms:.4f}", flush=True)
-    assert tile in (64, 128, 256) and items in (512, 1024, 2048, 4096) and ms > 0
+    tile, wide_k, items, ms = cv.cvgram_batch_autotune(dev_probs, mode=mode)
+    print(f"[batch autotune] mode={mode} tile={tile} wide_min_k={wide_k} items={items} "
+          f"gram_ms={ms:.4f}", flush=True)
+    assert tile in (64, 128, 256) and wide_k in (0, 512) and ms > 0
+    assert items in (512, 1024, 2048, 4096, 8192, 16384)
+    assert wide_k == 0 or tile == 256
     if mode == "fp64":
         assert tile <= 128          # FP64 tiles stop at 128
     b = cv.cvgram_batch_create(dev_probs, ddof=1, mode=mode)
