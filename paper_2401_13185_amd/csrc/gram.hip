@@ -909,22 +909,25 @@ __global__ __launch_bounds__(kThreads) void gram_bf16_kernel(const ProbDesc* __r
 // (tj < nt: X columns [128 tj, +128); tj >= nt: Y columns [128 (tj - nt),
 // +128)).  Items exist for tj >= 2 ti.  Pairs with tj = 2 ti or 2 ti + 1
 // straddle the diagonal: their B columns lie inside A's (no B loads); in
-// tj = 2 ti the lower half of A is below the diagonal, and those two waves
+// tj = 2 ti the lower half of A is below the diagonal, and the waves on it
 // compute the 256 x 32 K-by-M block instead (M <= 32) or idle.
-// Four waves, wave (wm, wn) = A columns 128 wm, B columns 64 wn: 4 x 2
-// output blocks of 32 x 32 (v_mfma_f32_32x32x16_bf16).  Per 32-row stage
-// each wave reads 24 KB of fragments from LDS, in four parts around the
-// three products (lo(A) hi(B), hi(A) hi(B), hi(A) lo(B)): a part is re-read
-// for the next stage as soon as the product that used it last is issued,
-// so one register set serves.  The ring has three stages of 52 KB; the
-// barrier at each stage frees the previous stage's buffer for the stage
-// three ahead.  Per fragment byte read from LDS the 128 x 64 wave tile does
-// 4/3 the MFMA work of a 64 x 64 one, and per panel byte loaded the
-// 256 x 128 workgroup tile 4/3 that of a 128 x 128 one.
+// Eight waves, two per SIMD: wave (wm, wn), wm = 0..3, wn = 0..1, computes A
+// columns 64 wm .. + 64 against B columns 64 wn .. + 64 as 2 x 2 output
+// blocks of 32 x 32 (v_mfma_f32_32x32x16_bf16); on a diagonal pair with
+// tj = 2 ti the waves wm = 2, 3 take 64 rows each of the K-by-M block.  While
+// one wave of a SIMD waits on LDS or the stage barrier, the other issues its
+// MFMAs (with one 128 x 64 wave tile per SIMD the kernel ran 6 % slower).
+// Per 32-row stage each wave reads 16 KB of fragments from LDS, in four
+// parts around the three products (lo(A) hi(B), hi(A) hi(B), hi(A) lo(B)):
+// a part is re-read for the next stage as soon as the product that used it
+// last is issued, so one register set serves.  The ring has three stages of
+// 52 KB; the barrier at each stage frees the previous stage's buffer for the
+// stage three ahead.  Per panel byte loaded the 256 x 128 workgroup tile
+// does 4/3 the MFMA work of a 128 x 128 one.
 // Accumulation: FP32 MFMA accumulators added into FP32 running totals every
-// 512 rows (VALU adds round to nearest) -- the totals take the place of the
-// FP64 copies, which leave no room for a 128 x 64 wave tile.  A block of
-// 512 rows is 96 accumulating MFMAs; the accumulator's rounding is about
+// 512 rows (VALU adds round to nearest) -- the totals take the place of
+// FP64 copies, which would leave room for one wave per SIMD only.  A block
+// of 512 rows is 96 accumulating MFMAs; the accumulator's rounding is about
 // half an FP32 ulp per step and does not average out on sums of positive
 // products, so a block's worst relative error is about 48 ulp (3e-6).
 constexpr int kWStages = 3;
@@ -934,7 +937,8 @@ struct DmaBufW {
   __bf16 ah[256 * 32], al[256 * 32], bh[128 * 32], bl[128 * 32], yh[kYW * 32], yl[kYW * 32];
 };
 
-__global__ __launch_bounds__(kThreads) void gram_bf16_wide_kernel(
+constexpr int kThreads8 = 512;  // eight waves
+__global__ __launch_bounds__(kThreads8) void gram_bf16_wide_kernel(
     const ProbDesc* __restrict__ pds, const GramWork* __restrict__ work,
     const int32_t* __restrict__ xcd) {
   __shared__ __attribute__((aligned(1024))) DmaBufW sb0, sb1, sb2;
@@ -959,14 +963,14 @@ __global__ __launch_bounds__(kThreads) void gram_bf16_wide_kernel(
   const int64_t ca = (int64_t)w.ti * 256;
   const int64_t cb = xy_tile ? Kp + (int64_t)(w.tj - nt) * 128 : (int64_t)w.tj * 128;
   const bool ydiag = diag && dq == 0 && xy_diag;
-  // 0: 128 x 64 sub-tile; 1: 128 x 32 K-by-M block; 2: idle
-  const int role = (diag && dq == 0 && wm == 1) ? (ydiag ? 1 : 2) : 0;
+  // 0: 64 x 64 sub-tile; 1: 64 x 32 of the K-by-M block; 2: idle
+  const int role = (diag && dq == 0 && wm >= 2) ? (ydiag ? 1 : 2) : 0;
 
   const int lsrc = (lane >> 2) * 64 + (((lane & 3) ^ swz(lane >> 2)) << 4);
   const int lc = lane & 31, lh = lane >> 5;
   const int lfo[2] = {lc * 64 + ((lh ^ swz(lc)) << 4), lc * 64 + (((2 + lh) ^ swz(lc)) << 4)};
 
-  constexpr int NACC = 8;
+  constexpr int NACC = 4;
   float16_t acc[NACC], tot[NACC];
 #pragma unroll
   for (int i = 0; i < NACC; ++i)
@@ -978,46 +982,51 @@ __global__ __launch_bounds__(kThreads) void gram_bf16_wide_kernel(
   const int64_t nst = (w.r1 - w.r0) / 32;
   const int64_t p0 = w.r0 / 32;  // first panel
   int since = 0;
+  // the Y block's four 1 KB loads (hi and lo, two column halves each) go to
+  // waves 0 .. 3
+  const bool yload = wave < 4;
 
   auto main_loop = [&](auto dg_c, auto yd_c, auto role_c) {
     constexpr bool DG = decltype(dg_c)::value;   // B inside A
     constexpr bool YD = decltype(yd_c)::value;   // K x M block in this tile
     constexpr int R = decltype(role_c)::value;
-    constexpr int FA = 4, FB = R == 1 ? 1 : 2;
+    constexpr int FA = 2, FB = R == 1 ? 1 : 2;
     constexpr int NA = R == 2 ? 0 : FA;
-    // direct loads per wave per stage (the same in every wave)
-    constexpr int L = 8 + (DG ? 0 : 4) + (YD ? 1 : 0);
-    // B columns inside the A buffer (diagonal pairs) or the B buffer
+    // direct loads per wave per stage (waves 0 .. 3 one more with the Y block)
+    constexpr int L = 4 + (DG ? 0 : 2);
     const int bcol = (DG ? dq * 128 : 0) + wn * 64;
+    auto wait_one_stage = [&]() {
+      if (YD && yload)
+        wait_vmcnt_lgkm0<L + 1>();
+      else
+        wait_vmcnt_lgkm0<L>();
+    };
     auto issue = [&](DmaBufW& b, int64_t s) {
       const int64_t panel = (p0 + (s < nst ? s : nst - 1)) * Wp;
       const CVG_GLOBAL char* ah = Zh + (panel + ca) * 64 + lsrc;
       const CVG_GLOBAL char* al = Zl + (panel + ca) * 64 + lsrc;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int blk = wave * 4 + i;
+      for (int i = 0; i < 2; ++i) {
+        const int blk = wave * 2 + i;
         dma16(ah + blk * 1024, b.ah + blk * 512);
         dma16(al + blk * 1024, b.al + blk * 512);
       }
       if constexpr (!DG) {
         const CVG_GLOBAL char* bh = Zh + (panel + cb) * 64 + lsrc;
         const CVG_GLOBAL char* bl = Zl + (panel + cb) * 64 + lsrc;
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-          const int blk = wave * 2 + i;
-          dma16(bh + blk * 1024, b.bh + blk * 512);
-          dma16(bl + blk * 1024, b.bl + blk * 512);
-        }
+        dma16(bh + wave * 1024, b.bh + wave * 512);
+        dma16(bl + wave * 1024, b.bl + wave * 512);
       }
       if constexpr (YD) {
         // waves 0, 1: hi columns 0-15, 16-31; waves 2, 3: lo
-        const CVG_GLOBAL char* src = (wave < 2 ? Zh : Zl) + (panel + Kp) * 64 + lsrc;
-        dma16(src + (wave & 1) * 1024, (wave < 2 ? b.yh : b.yl) + (wave & 1) * 512);
+        if (yload) {
+          const CVG_GLOBAL char* src = (wave < 2 ? Zh : Zl) + (panel + Kp) * 64 + lsrc;
+          dma16(src + (wave & 1) * 1024, (wave < 2 ? b.yh : b.yl) + (wave & 1) * 512);
+        }
       }
     };
-    // fragment parts of one stage: lo(A), hi(A), hi(B), lo(B)
     bf16x8_t fal[NA > 0 ? NA : 1][2], fah[NA > 0 ? NA : 1][2], fbh[FB][2], fbl[FB][2];
-    const int acol = R == 1 ? wn * 128 : wm * 128;
+    const int acol = R == 1 ? (2 * (wm - 2) + wn) * 64 : wm * 64;
     auto rd = [&](const __bf16* base, int col0, int ks) -> bf16x8_t {
       return *(const bf16x8_t*)((const char*)base + col0 * 64 + lfo[ks]);
     };
@@ -1047,7 +1056,6 @@ __global__ __launch_bounds__(kThreads) void gram_bf16_wide_kernel(
         for (int ks = 0; ks < 2; ++ks)
           fbl[c][ks] = R == 1 ? rd(b.yl, c * 32, ks) : rd(DG ? b.al : b.bl, bcol + c * 32, ks);
     };
-    // one product over the wave's blocks and both slices
     auto product = [&](const bf16x8_t (&fa)[NA > 0 ? NA : 1][2], const bf16x8_t (&fb)[FB][2]) {
 #pragma unroll
       for (int ks = 0; ks < 2; ++ks)
@@ -1086,7 +1094,7 @@ __global__ __launch_bounds__(kThreads) void gram_bf16_wide_kernel(
         load_ah(cur);
         load_bl(cur);
       }
-      wait_vmcnt_lgkm0<L>();
+      wait_one_stage();
       barrier_only();
       issue(cur, s + kWStages);
       if constexpr (R != 2) {
@@ -1109,7 +1117,10 @@ __global__ __launch_bounds__(kThreads) void gram_bf16_wide_kernel(
     issue(sb0, 0);
     issue(sb1, 1);
     issue(sb2, 2);
-    wait_vmcnt_lgkm0<2 * L>();
+    if (YD && yload)
+      wait_vmcnt_lgkm0<2 * (L + 1)>();
+    else
+      wait_vmcnt_lgkm0<2 * L>();
     barrier_only();
     if constexpr (R != 2) {
       load_al(sb0);
@@ -1142,10 +1153,10 @@ __global__ __launch_bounds__(kThreads) void gram_bf16_wide_kernel(
   CVG_GLOBAL double* out = slabs + (int64_t)w.slab * K * (K + M);
   const int64_t W = K + M;
   if (role == 0) {
-    const int64_t r0 = ca + wm * 128;
+    const int64_t r0 = ca + wm * 64;
     const int64_t c0 = (xy_tile ? (int64_t)(w.tj - nt) * 128 : cb) + wn * 64;
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
       for (int b = 0; b < 2; ++b)
 #pragma unroll
@@ -1161,11 +1172,12 @@ __global__ __launch_bounds__(kThreads) void gram_bf16_wide_kernel(
           }
         }
   } else {
+    const int64_t r0 = ca + (2 * (wm - 2) + wn) * 64;
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
-        const int64_t row = ca + wn * 128 + a * 32 + 8 * (e >> 2) + 4 * lh + (e & 3);
+        const int64_t row = r0 + a * 32 + 8 * (e >> 2) + 4 * lh + (e & 3);
         if (row < K && lc < M) out[row * W + K + lc] = (double)tot[a][e] + (double)acc[a][e];
       }
   }
@@ -1181,7 +1193,7 @@ void launch_mode(bool panel_f32, int tile, const ProbDesc* pd, const GramWork* w
     else if (tile == 128)
       gram_bf16_kernel<128><<<grid, kThreads, 0, s>>>(pd, work, xcd);
     else
-      gram_bf16_wide_kernel<<<grid, kThreads, 0, s>>>(pd, work, xcd);
+      gram_bf16_wide_kernel<<<grid, kThreads8, 0, s>>>(pd, work, xcd);
   } else if constexpr (MODE == CVGRAM_MODE_FP64) {
     if (panel_f32) {
       if (tile == 64)
