@@ -368,6 +368,23 @@ cvgram_status cvgram_batch_autotune(const cvgram_problem* problems, int32_t n,
  * n is the capacity of info (at most 5 entries are written). */
 cvgram_status cvgram_plan_info(cvgram_t h, int64_t* info, int32_t n);
 
+/* Host-side preview of the plan cvgram_create would make for a problem of
+ * this shape whose fold p has fold_sizes[p] rows (Definition 1: each >= 1,
+ * summing to N), with no device work and no device allocation; the tuned
+ * choice of the current device applies (none on a host without a device).
+ *   info[0..4] as cvgram_plan_info
+ *   info[5] bytes of device workspace cvgram_create would allocate (packed
+ *           panels, statistics, slabs, the full Gram; not the plan upload of
+ *           a few MB or the caller's outputs)
+ *   info[6], info[7] the most and the fewest Gram work items one XCD runs in
+ *           the Gram launch with the most items
+ * n is the capacity of info (at most 8 entries are written).  Errors:
+ * CVGRAM_EINVAL for a bad shape, dtype or mode, or sizes not summing to N;
+ * CVGRAM_EFOLDS for an empty fold. */
+cvgram_status cvgram_plan_query(int64_t N, int64_t K, int64_t M, const int64_t* fold_sizes,
+                                int32_t P, cvgram_dtype dtype, cvgram_mode mode, int64_t* info,
+                                int32_t n);
+
 /* Change the stream used by later calls on this handle.  Work queued on the
  * new stream from then on runs after everything already queued on the old
  * one (an event recorded there is waited for on the device, not the host). */

@@ -15,7 +15,8 @@ import re
 
 __all__ = [
     "CVGramError", "lib_path", "load", "exported_symbols", "header_symbols",
-    "cvgram_create", "cvgram_num_folds", "cvgram_plan_info", "cvgram_partition", "cvgram_fold",
+    "cvgram_create", "cvgram_num_folds", "cvgram_plan_info", "cvgram_plan_query",
+    "cvgram_partition", "cvgram_fold",
     "cvgram_fold_combo", "cvgram_fold_leaky", "LEAK_KINDS", "cvgram_ridge", "cvgram_folds_all",
     "cvgram_folds_all_noalloc", "cvgram_fold_stats", "cvgram_set_stream",
     "cvgram_destroy", "cvgram_status_string", "cvgram_last_error_message", "cvgram_version",
@@ -61,6 +62,8 @@ _SIGS = {
                              _int, _vp, ctypes.POINTER(_vp)]),
     "cvgram_num_folds": (_i32, [_vp]),
     "cvgram_plan_info": (_int, [_vp, ctypes.POINTER(_i64), _i32]),
+    "cvgram_plan_query": (_int, [_i64, _i64, _i64, ctypes.POINTER(_i64), _i32, _int, _int,
+                                 ctypes.POINTER(_i64), _i32]),
     "cvgram_partition": (_int, [_vp, _vp, _vp]),
     "cvgram_fold": (_int, [_vp, _i32, _vp, _vp]),
     "cvgram_fold_combo": (_int, [_vp, _i32, _int, _int, _int, _int, _vp, _vp]),
@@ -221,6 +224,23 @@ def cvgram_plan_info(h: Handle) -> dict:
     _check(load().cvgram_plan_info(h.ptr, info, 5))
     return {"tile": info[0], "items": info[1], "slabs": info[2], "fused": bool(info[3]),
             "panel_bytes": info[4]}
+
+
+def cvgram_plan_query(N, K, M, fold_sizes, dtype="f32", mode="fp64") -> dict:
+    """The plan cvgram_create would make for this shape and these fold sizes,
+    computed on the host (no device work): the cvgram_plan_info fields, the
+    device workspace bytes, and the most and fewest Gram items per XCD."""
+    if mode not in MODES:
+        raise ValueError(f"mode must be one of {sorted(MODES)}")
+    if dtype not in ("f32", "f64"):
+        raise ValueError("dtype must be 'f32' or 'f64'")
+    sizes = (_i64 * len(fold_sizes))(*[int(v) for v in fold_sizes])
+    info = (_i64 * 8)()
+    _check(load().cvgram_plan_query(N, K, M, sizes, len(fold_sizes), 1 if dtype == "f64" else 0,
+                                    MODES[mode], info, 8))
+    return {"tile": info[0], "items": info[1], "slabs": info[2], "fused": bool(info[3]),
+            "panel_bytes": info[4], "workspace_bytes": info[5], "xcd_items_max": info[6],
+            "xcd_items_min": info[7]}
 
 
 def cvgram_partition(h: Handle, perm=None, offsets=None):

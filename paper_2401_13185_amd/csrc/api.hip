@@ -355,8 +355,12 @@ TuneTable& tune_table() {
 // "<gcnArchName>/<CUs>" of the current device, with no spaces (call with the
 // table's mutex held)
 const std::string& device_arch_locked(TuneTable& tt) {
+  static const std::string none = "none";
   int dev = 0;
-  CVG_HIP(hipGetDevice(&dev));
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return none;  // planning on a host without a device: no tuned entry applies
+  }
   auto it = tt.arch.find(dev);
   if (it != tt.arch.end()) return it->second;
   hipDeviceProp_t prop;
@@ -1151,16 +1155,15 @@ size_t elem_bytes(const Batch& b) {
   return b.mode == CVGRAM_MODE_FP32 ? 4 : 2;
 }
 
-// Workspace arena + device descriptors + one upload of every plan.
-void allocate_and_upload(Batch& b, const HostLists& L) {
+// Workspace arena of a planned batch: byte offsets of every problem's
+// buffers (256-byte aligned) and the total.
+struct ArenaOff {
+  size_t pivot, packed, packed_lo, part, fold, tot, tot_part, tr_sum, tr_mean, tr_std, tr_mu,
+      tr_const, ntrain, slabs, G;
+};
+size_t arena_layout(const Batch& b, std::vector<ArenaOff>& off) {
   const size_t eb = elem_bytes(b);
-  // arena layout per problem
-  struct Off {
-    size_t pivot, packed, packed_lo, part, fold, tot, tot_part, tr_sum, tr_mean, tr_std, tr_mu,
-        tr_const,
-        ntrain, slabs, G;
-  };
-  std::vector<Off> off(b.pp.size());
+  off.assign(b.pp.size(), ArenaOff{});
   size_t total = 0;
   auto take_bytes = [&](size_t bytes) {
     const size_t o = total;
@@ -1169,7 +1172,7 @@ void allocate_and_upload(Batch& b, const HostLists& L) {
   };
   for (size_t i = 0; i < b.pp.size(); ++i) {
     const ProbPlan& p = b.pp[i];
-    Off& o = off[i];
+    ArenaOff& o = off[i];
     o.pivot = p.d_pivot ? 0 : take_bytes(p.W * 8);
     o.packed = take_bytes((size_t)p.Np * p.Wp * eb);
     o.packed_lo = b.mode == CVGRAM_MODE_BF16X3 ? take_bytes((size_t)p.Np * p.Wp * eb) : 0;
@@ -1186,6 +1189,13 @@ void allocate_and_upload(Batch& b, const HostLists& L) {
     o.slabs = take_bytes((size_t)p.n_slabs * p.K * p.W * 8);
     o.G = take_bytes((size_t)p.K * p.W * 8);
   }
+  return total;
+}
+
+// Workspace arena + device descriptors + one upload of every plan.
+void allocate_and_upload(Batch& b, const HostLists& L) {
+  std::vector<ArenaOff> off;
+  const size_t total = arena_layout(b, off);
   char* arena = (char*)b.mem.dev(total);
 
   // plan blob: per-problem small arrays first, then descriptors and lists
@@ -1231,7 +1241,7 @@ void allocate_and_upload(Batch& b, const HostLists& L) {
   std::vector<OutDesc> outs(b.pp.size());
   for (size_t i = 0; i < b.pp.size(); ++i) {
     const ProbPlan& p = b.pp[i];
-    const Off& o = off[i];
+    const ArenaOff& o = off[i];
     ProbDesc& d = b.h_pd[i];
     std::memset(&d, 0, sizeof(d));
     d.X = p.X;
@@ -1379,6 +1389,13 @@ cvgram_status prepare(Batch& b) {
 }
 
 bool flag01(int v) { return v == 0 || v == 1; }
+
+cvgram_status check_shape(int64_t N, int64_t K, int64_t M) {
+  if (N < 2 || K < 1 || M < 0) return fail(CVGRAM_EINVAL, "need N >= 2, K >= 1, M >= 0");
+  if (N > (int64_t)INT32_MAX - 1) return fail(CVGRAM_EINVAL, "N must fit in int32");
+  if (K > (int64_t)1 << 24 || M > (int64_t)1 << 24) return fail(CVGRAM_EINVAL, "K or M too large");
+  return CVGRAM_OK;
+}
 
 cvgram_status check_problem(const void* X, const void* Y, const int32_t* fold, int64_t N,
                             int64_t K, int64_t M) {
@@ -1691,6 +1708,66 @@ cvgram_status cvgram_plan_info(cvgram_t h, int64_t* info, int32_t n) {
   const int64_t v[5] = {p.cfg.tile, b.n_work[0] + b.n_work[1] + b.n_work[2], p.n_slabs,
                         p.fused ? 1 : 0, (int64_t)elem_bytes(b)};
   for (int32_t k = 0; k < n && k < 5; ++k) info[k] = v[k];
+  return CVGRAM_OK;
+}
+
+cvgram_status cvgram_plan_query(int64_t N, int64_t K, int64_t M, const int64_t* fold_sizes,
+                                int32_t P, cvgram_dtype dtype, cvgram_mode mode, int64_t* info,
+                                int32_t n) {
+  set_error("");
+  if (!info && n > 0) return fail(CVGRAM_EINVAL, "NULL info");
+  cvgram_status st = check_shape(N, K, M);
+  if (st != CVGRAM_OK) return st;
+  if (dtype != CVGRAM_F32 && dtype != CVGRAM_F64) return fail(CVGRAM_EINVAL, "bad dtype");
+  if (mode != CVGRAM_MODE_FP64 && mode != CVGRAM_MODE_FP32 && mode != CVGRAM_MODE_BF16X3)
+    return fail(CVGRAM_EINVAL, "bad mode");
+  if (!fold_sizes || P < 1) return fail(CVGRAM_EINVAL, "need fold sizes and P >= 1");
+  Batch b;
+  b.mode = mode;
+  b.dtype = dtype;
+  b.ddof = 1;
+  ProbPlan p;
+  p.N = N;
+  p.K = K;
+  p.M = M;
+  p.W = K + M;
+  p.P = P;
+  p.offsets.assign((size_t)P + 1, 0);
+  for (int32_t q = 0; q < P; ++q) {
+    if (fold_sizes[q] < 1)
+      return fail(CVGRAM_EFOLDS, "fold " + std::to_string(q) + " is empty (Definition 1)");
+    p.offsets[q + 1] = p.offsets[q] + fold_sizes[q];
+  }
+  if (p.offsets[P] != N) return fail(CVGRAM_EINVAL, "fold sizes do not sum to N");
+  b.pp.push_back(std::move(p));
+  try {
+    HostLists L;
+    L.clear();
+    plan_layout(b, L);
+    std::vector<ArenaOff> off;
+    const size_t bytes = arena_layout(b, off);
+    int64_t items = 0, most = -1, xmax = 0, xmin = 0;
+    for (int k = 0; k < kWidths; ++k) {
+      const int64_t nk = (int64_t)L.work[k].size();
+      items += nk;
+      if (nk > most && (int)L.xcd[k].size() == kXcds + 1) {
+        most = nk;
+        xmax = 0;
+        xmin = INT64_MAX;
+        for (int x = 0; x < kXcds; ++x) {
+          const int64_t c = L.xcd[k][x + 1] - L.xcd[k][x];
+          xmax = std::max(xmax, c);
+          xmin = std::min(xmin, c);
+        }
+      }
+    }
+    const ProbPlan& q = b.pp[0];
+    const int64_t v[8] = {q.cfg.tile, items, q.n_slabs, q.fused ? 1 : 0, (int64_t)elem_bytes(b),
+                          (int64_t)bytes, xmax, xmin};
+    for (int32_t k = 0; k < n && k < 8; ++k) info[k] = v[k];
+  } catch (const Fail& f) {
+    return f.st;
+  }
   return CVGRAM_OK;
 }
 

@@ -342,3 +342,24 @@ def test_error_statuses():
         cv.cvgram_fold(h, 2)
     assert ei.value.status == 6
     cv.cvgram_destroy(h)
+
+
+@pytest.mark.parametrize("n,k,m,p,dtype,mode", [
+    (3001, 130, 5, 7, "f64", "fp64"), (1500, 2048, 3, 3, "f32", "fp64"),
+    (1500, 2049, 3, 3, "f32", "fp64"), (6000, 300, 40, 5, "f32", "bf16x3"),
+    (20000, 64, 4, 20000, "f64", "fp64"), (9000, 100, 2, 9, "f32", "fp32"),
+])
+def test_plan_query_matches_created_plan(n, k, m, p, dtype, mode):
+    """cvgram_plan_query (host only) returns the plan cvgram_create makes."""
+    values = "gaussian" if dtype == "f64" else "offset"
+    kind = "dirichlet" if p < n else "near_equal"   # p = n: leave-one-out
+    shape = G.Shape(f"plan N={n} K={k}", n, k, m, p, dtype, values, kind)
+    X, Y, fold = G.make(shape, 17 + k, 0)
+    sizes = np.bincount(fold, minlength=int(fold.max()) + 1)
+    q = cv.cvgram_plan_query(n, k, m, sizes, dtype, mode)
+    h = cv.cvgram_create(_t(X), _t(Y), _t(fold.astype(np.int32)), 1, 1, 1, 1, ddof=1, mode=mode)
+    info = cv.cvgram_plan_info(h)
+    cv.cvgram_destroy(h)
+    print(f"[plan] {shape.name} {mode}: {info}", flush=True)
+    for key in ("tile", "items", "slabs", "fused", "panel_bytes"):
+        assert q[key] == info[key], (key, q, info)
