@@ -326,6 +326,10 @@ __device__ void correct_tile(const ProbDesc& pd, const OutDesc& od, int32_t f, i
     return;
   }
 
+  // The classes are written once and not read back here: non-temporal
+  // stores keep them from displacing G and the statistics, which every fold
+  // re-reads, from the caches (leave-one-out N = 1e5, K = 512: 203 -> 194 ms
+  // for all folds' classes).
   if (!is_xy) {
     for (int c = 0; c < CVGRAM_XTX_CLASSES; ++c) {
       if (!od.xx[c]) continue;
@@ -346,13 +350,14 @@ __device__ void correct_tile(const ProbDesc& pd, const OutDesc& od, int32_t f, i
         const int64_t i = (int64_t)bi * TS + il;
         const int64_t j = (int64_t)bj * TS + jl;
         if (diag) {
-          if (i < K && j < K) out[i * K + j] = (OutT)(il <= jl ? T[il][jl] : T[jl][il]);
+          if (i < K && j < K)
+            __builtin_nontemporal_store((OutT)(il <= jl ? T[il][jl] : T[jl][il]), &out[i * K + j]);
         } else {
-          if (ok[r]) out[i * K + j] = (OutT)v[r];
+          if (ok[r]) __builtin_nontemporal_store((OutT)v[r], &out[i * K + j]);
           // transposed block: rows of bj, columns of bi
           const int64_t ti = (int64_t)bj * TS + il;
           const int64_t tj = (int64_t)bi * TS + jl;
-          if (ti < K && tj < K) out[ti * K + tj] = (OutT)T[jl][il];
+          if (ti < K && tj < K) __builtin_nontemporal_store((OutT)T[jl][il], &out[ti * K + tj]);
         }
       }
       lds_barrier();
@@ -370,7 +375,7 @@ __device__ void correct_tile(const ProbDesc& pd, const OutDesc& od, int32_t f, i
         if (scx || scy) v = v / ((scx ? rsd[il] : 1.0) * (scy ? csd[jl] : 1.0));
         const int64_t i = (int64_t)bi * TS + il;
         const int64_t j = (int64_t)bj * TS + jl;
-        out[i * M + j] = (OutT)v;
+        __builtin_nontemporal_store((OutT)v, &out[i * M + j]);
       }
     }
   }
