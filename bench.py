@@ -8,7 +8,10 @@ problem: cvgram_create (fold bookkeeping, pivots, statistics + pack, grouped
 Gram, slab reduction) + every fold's 12 distinct training products (4 X^T X +
 8 X^T Y classes) written in chunks of 8 folds + cvgram_destroy.  Inputs are
 resident in HBM before timing starts.  ``value`` is sets/s: a set is one
-fold's (X^T X, X^T Y) pair for one combination, P * 12 sets per step.
+fold's (X^T X, X^T Y) pair for one combination, P * 12 sets per step.  The
+single-combination form (create + cvgram_fold of every fold for the centred
+and scaled combination, P sets per step) is reported beside it
+(``one_combination``), on this problem and on the spectra shape.
 
 Further blocks on the same line (each on by default; ``--blocks`` picks):
   headline  the large problem in FP64 (above), the same inputs in BF16X3
@@ -250,6 +253,33 @@ def time_steps(cv, torch, Xd, Yd, fd, P, K, M, mode, steps, warmup, chunk, stage
     return (t1 - t0) * 1e3 / steps, stage_ms, plan
 
 
+def time_one_combination(cv, torch, Xd, Yd, fd, P, K, M, mode, steps, warmup):
+    """The single-combination form (centred and scaled X and Y, the
+    combination the paper's Algorithm 7 computes): create + cvgram_fold for
+    every fold + destroy, back to back.  Returns (ms per step, sets/s)."""
+    odt = torch.float64 if mode == "fp64" else torch.float32
+    xx = torch.empty(K, K, dtype=odt, device=Xd.device)
+    xy = torch.empty(K, M, dtype=odt, device=Xd.device)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        h = cv.cvgram_create(Xd, Yd, fd, 1, 1, 1, 1, ddof=1, mode=mode, stream=stream)
+        for p in range(P):
+            cv.cvgram_fold(h, p, xx, xy)
+        cv.cvgram_destroy(h)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    del xx, xy
+    return ms, P / (ms * 1e-3)
+
+
 def roofline(mode, n, k, m, stage_ms, workload, plan):
     g = f_alg(n, k, m) / (stage_ms["gram"] * 1e-3) / 1e12
     tile = plan["tile"]
@@ -470,6 +500,12 @@ def headline_block(cv, torch, G, dev, args):
                               "stage_ms": st, "plan": plan,
                               "roofline": roofline(mode, N, K, M, st, workload, plan)}
         log(f"large problem {mode}: {ms:.1f} ms/step, Gram {st['gram']:.1f} ms")
+    ms1, sps1 = time_one_combination(cv, torch, X, Y, fd, P, K, M, args.headline_mode,
+                                     min(3, args.steps), min(1, args.warmup))
+    res["one_combination"] = {"mode": args.headline_mode,
+                              "combination": "1111 (X and Y centred and scaled)",
+                              "ms_per_step": ms1, "sets_per_s": sps1}
+    log(f"large problem, one combination: {ms1:.1f} ms/step")
     f64, b16 = res["modes"]["fp64"], res["modes"]["bf16x3"]
     b16["speedup_vs_fp64"] = f64["ms_per_step"] / b16["ms_per_step"]
     b16["gram_speedup_vs_fp64"] = f64["stage_ms"]["gram"] / b16["stage_ms"]["gram"]
@@ -529,6 +565,10 @@ def spectra_block(cv, torch, G, dev, args):
            "tflops_alg": f_alg(N, K, M) / (ms * 1e-3) / 1e12, "stage_ms": st, "plan": plan,
            "roofline": roofline("fp64", N, K, M, st, shape.name, plan),
            "hbm": stage_bandwidth(N, K, M, P, X.itemsize, "fp64", st)}
+    ms1, sps1 = time_one_combination(cv, torch, Xd, Yd, fd, P, K, M, "fp64", args.steps,
+                                     args.warmup)
+    out["one_combination"] = {"combination": "1111 (X and Y centred and scaled)",
+                              "ms_per_step": ms1, "sets_per_s": sps1}
     log("spectra timed steps done")
     if not args.no_check or not args.no_cpu:
         h = cv.cvgram_create(Xd, Yd, fd, 1, 1, 1, 1, ddof=1, mode="fp64")
@@ -793,6 +833,7 @@ def main():
         }
         if "cpu_baseline" in hl:
             out["cpu_baseline"] = hl["cpu_baseline"]
+        out["one_combination"] = hl["one_combination"]
         out["mixed_vs_fp64"] = {"mode": "bf16x3", "fp64": hl["modes"]["fp64"],
                                 "bf16x3": hl["modes"]["bf16x3"]}
         if "sampled_vs_oracle" in hl:
