@@ -11,6 +11,8 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <new>
+#include <stdexcept>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -1461,12 +1463,26 @@ OutDesc all_classes_out(const Batch& b, int32_t p_begin, void* out_XtX, void* ou
 
 }  // namespace
 
+// C++ exceptions never cross the C ABI: the body of every entry point that
+// returns a status is a function-try-block ending in these handlers (a
+// failure inside the library's own try blocks is reported there first).
+#define CVG_ABI_CATCH                                                           \
+  catch (const Fail& f) {                                                       \
+    return f.st;                                                                \
+  }                                                                             \
+  catch (const std::bad_alloc&) {                                               \
+    return fail(CVGRAM_ENOMEM, "host memory allocation failed");               \
+  }                                                                             \
+  catch (const std::exception& e) {                                             \
+    return fail(CVGRAM_EINVAL, std::string("internal error: ") + e.what());    \
+  }
+
 extern "C" {
 
 cvgram_status cvgram_create(const void* X, const void* Y, const int32_t* fold_id, int64_t N,
                             int64_t K, int64_t M, cvgram_dtype dtype, int center_x, int scale_x,
                             int center_y, int scale_y, int ddof, cvgram_mode mode, void* stream,
-                            cvgram_t* out) {
+                            cvgram_t* out) try {
   set_error("");
   if (!out) return fail(CVGRAM_EINVAL, "out is NULL");
   *out = nullptr;
@@ -1517,7 +1533,7 @@ cvgram_status cvgram_create(const void* X, const void* Y, const int32_t* fold_id
   }
   *out = h.release();
   return CVGRAM_OK;
-}
+} CVG_ABI_CATCH
 
 int32_t cvgram_num_folds(cvgram_t h) {
   if (!h) {
@@ -1527,7 +1543,7 @@ int32_t cvgram_num_folds(cvgram_t h) {
   return h->b.pp[0].P;
 }
 
-cvgram_status cvgram_partition(cvgram_t h, int32_t* perm, int64_t* offsets) {
+cvgram_status cvgram_partition(cvgram_t h, int32_t* perm, int64_t* offsets) try {
   if (!h) return fail(CVGRAM_EINVAL, "NULL handle");
   const ProbPlan& p = h->b.pp[0];
   try {
@@ -1541,10 +1557,10 @@ cvgram_status cvgram_partition(cvgram_t h, int32_t* perm, int64_t* offsets) {
     return f.st;
   }
   return CVGRAM_OK;
-}
+} CVG_ABI_CATCH
 
 cvgram_status cvgram_fold_combo(cvgram_t h, int32_t p, int center_x, int scale_x, int center_y,
-                                int scale_y, void* out_XtX, void* out_XtY) {
+                                int scale_y, void* out_XtX, void* out_XtY) try {
   if (!h) return fail(CVGRAM_EINVAL, "NULL handle");
   const ProbPlan& pp = h->b.pp[0];
   if (p < 0 || p >= pp.P) return fail(CVGRAM_ERANGE, "fold index out of range");
@@ -1558,9 +1574,9 @@ cvgram_status cvgram_fold_combo(cvgram_t h, int32_t p, int center_x, int scale_x
   if (pp.M > 0) od.xy[4 * (center_x | center_y) + 2 * scale_x + scale_y] = out_XtY;
   od.p_begin = p;
   return correct_single(h, p, p + 1, od);
-}
+} CVG_ABI_CATCH
 
-cvgram_status cvgram_fold_leaky(cvgram_t h, int32_t p, int kind, void* out_XtX, void* out_XtY) {
+cvgram_status cvgram_fold_leaky(cvgram_t h, int32_t p, int kind, void* out_XtX, void* out_XtY) try {
   if (!h) return fail(CVGRAM_EINVAL, "NULL handle");
   const ProbPlan& pp = h->b.pp[0];
   if (p < 0 || p >= pp.P) return fail(CVGRAM_ERANGE, "fold index out of range");
@@ -1581,10 +1597,10 @@ cvgram_status cvgram_fold_leaky(cvgram_t h, int32_t p, int kind, void* out_XtX, 
   od.lcy = h->cy;
   od.lsy = h->sy;
   return correct_single(h, p, p + 1, od);
-}
+} CVG_ABI_CATCH
 
 cvgram_status cvgram_ridge(cvgram_t h, int32_t p0, int32_t p1, const double* lambdas,
-                           int32_t n_lambda, double* out_B) {
+                           int32_t n_lambda, double* out_B) try {
   if (!h) return fail(CVGRAM_EINVAL, "NULL handle");
   const ProbPlan& pp = h->b.pp[0];
   if (p0 < 0 || p1 > pp.P || p0 >= p1) return fail(CVGRAM_ERANGE, "fold range out of range");
@@ -1643,25 +1659,25 @@ cvgram_status cvgram_ridge(cvgram_t h, int32_t p0, int32_t p1, const double* lam
   }
   ws.release();
   return st;
-}
+} CVG_ABI_CATCH
 
-cvgram_status cvgram_fold(cvgram_t h, int32_t p, void* out_XtX, void* out_XtY) {
+cvgram_status cvgram_fold(cvgram_t h, int32_t p, void* out_XtX, void* out_XtY) try {
   if (!h) return fail(CVGRAM_EINVAL, "NULL handle");
   return cvgram_fold_combo(h, p, h->cx, h->sx, h->cy, h->sy, out_XtX, out_XtY);
-}
+} CVG_ABI_CATCH
 
 cvgram_status cvgram_folds_all(cvgram_t h, int32_t p_begin, int32_t p_end, void* out_XtX,
-                               void* out_XtY) {
+                               void* out_XtY) try {
   if (!h) return fail(CVGRAM_EINVAL, "NULL handle");
   const ProbPlan& pp = h->b.pp[0];
   if (p_begin < 0 || p_end > pp.P || p_begin > p_end)
     return fail(CVGRAM_ERANGE, "fold range out of bounds");
   if (p_begin == p_end) return CVGRAM_OK;
   return correct_single(h->b, p_begin, p_end, all_classes_out(h->b, p_begin, out_XtX, out_XtY));
-}
+} CVG_ABI_CATCH
 
 cvgram_status cvgram_fold_stats(cvgram_t h, int32_t p, double* mean_x, double* std_x,
-                                double* mean_y, double* std_y) {
+                                double* mean_y, double* std_y) try {
   if (!h) return fail(CVGRAM_EINVAL, "NULL handle");
   const ProbDesc& d = h->b.h_pd[0];
   if (p < 0 || p >= d.P) return fail(CVGRAM_ERANGE, "fold index out of range");
@@ -1671,14 +1687,14 @@ cvgram_status cvgram_fold_stats(cvgram_t h, int32_t p, double* mean_x, double* s
     return f.st;
   }
   return CVGRAM_OK;
-}
+} CVG_ABI_CATCH
 
-cvgram_status cvgram_set_stage_timing(int on) {
+cvgram_status cvgram_set_stage_timing(int on) try {
   g_stage_timing.store(on ? 1 : 0);
   return CVGRAM_OK;
-}
+} CVG_ABI_CATCH
 
-cvgram_status cvgram_stage_times(cvgram_t h, double* ms, int32_t n) {
+cvgram_status cvgram_stage_times(cvgram_t h, double* ms, int32_t n) try {
   if (!h || (!ms && n > 0)) return fail(CVGRAM_EINVAL, "NULL argument");
   if (!h->b.timing) return fail(CVGRAM_EINVAL, "handle created without stage timing");
   try {
@@ -1692,16 +1708,16 @@ cvgram_status cvgram_stage_times(cvgram_t h, double* ms, int32_t n) {
     return f.st;
   }
   return CVGRAM_OK;
-}
+} CVG_ABI_CATCH
 
-cvgram_status cvgram_trim_cache(void) {
+cvgram_status cvgram_trim_cache(void) try {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return fail(CVGRAM_EDEVICE, "hipGetDevice failed");
   cache_trim_dev(dev);
   return CVGRAM_OK;
-}
+} CVG_ABI_CATCH
 
-cvgram_status cvgram_plan_info(cvgram_t h, int64_t* info, int32_t n) {
+cvgram_status cvgram_plan_info(cvgram_t h, int64_t* info, int32_t n) try {
   if (!h || (!info && n > 0)) return fail(CVGRAM_EINVAL, "NULL argument");
   const Batch& b = h->b;
   const ProbPlan& p = b.pp[0];
@@ -1709,11 +1725,11 @@ cvgram_status cvgram_plan_info(cvgram_t h, int64_t* info, int32_t n) {
                         p.fused ? 1 : 0, (int64_t)elem_bytes(b)};
   for (int32_t k = 0; k < n && k < 5; ++k) info[k] = v[k];
   return CVGRAM_OK;
-}
+} CVG_ABI_CATCH
 
 cvgram_status cvgram_plan_query(int64_t N, int64_t K, int64_t M, const int64_t* fold_sizes,
                                 int32_t P, cvgram_dtype dtype, cvgram_mode mode, int64_t* info,
-                                int32_t n) {
+                                int32_t n) try {
   set_error("");
   if (!info && n > 0) return fail(CVGRAM_EINVAL, "NULL info");
   cvgram_status st = check_shape(N, K, M);
@@ -1769,9 +1785,9 @@ cvgram_status cvgram_plan_query(int64_t N, int64_t K, int64_t M, const int64_t* 
     return f.st;
   }
   return CVGRAM_OK;
-}
+} CVG_ABI_CATCH
 
-cvgram_status cvgram_set_stream(cvgram_t h, void* stream) {
+cvgram_status cvgram_set_stream(cvgram_t h, void* stream) try {
   if (!h) return fail(CVGRAM_EINVAL, "NULL handle");
   hipStream_t ns = (hipStream_t)stream;
   if (ns != h->b.stream) {
@@ -1790,20 +1806,20 @@ cvgram_status cvgram_set_stream(cvgram_t h, void* stream) {
     h->b.mem.stream = ns;
   }
   return CVGRAM_OK;
-}
+} CVG_ABI_CATCH
 
-cvgram_status cvgram_destroy(cvgram_t h) {
+cvgram_status cvgram_destroy(cvgram_t h) try {
   if (!h) return CVGRAM_OK;
   h->b.release_async();
   delete h;
   return CVGRAM_OK;
-}
+} CVG_ABI_CATCH
 
 // ---------------------------------------------------------------------------
 // batched form
 // ---------------------------------------------------------------------------
 cvgram_status cvgram_batch_create(const cvgram_problem* problems, int32_t n, cvgram_dtype dtype,
-                                  int ddof, cvgram_mode mode, void* stream, cvgram_batch_t* out) {
+                                  int ddof, cvgram_mode mode, void* stream, cvgram_batch_t* out) try {
   set_error("");
   if (!out) return fail(CVGRAM_EINVAL, "out is NULL");
   *out = nullptr;
@@ -1879,16 +1895,16 @@ cvgram_status cvgram_batch_create(const cvgram_problem* problems, int32_t n, cvg
   }
   *out = bb.release();
   return CVGRAM_OK;
-}
+} CVG_ABI_CATCH
 
-cvgram_status cvgram_batch_run(cvgram_batch_t bb) {
+cvgram_status cvgram_batch_run(cvgram_batch_t bb) try {
   if (!bb) return fail(CVGRAM_EINVAL, "NULL batch");
   hipError_t e = hipGraphLaunch(bb->b.gexec, bb->b.stream);
   if (e != hipSuccess) return fail(CVGRAM_EDEVICE, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
   return CVGRAM_OK;
-}
+} CVG_ABI_CATCH
 
-cvgram_status cvgram_batch_run_eager(cvgram_batch_t bb) {
+cvgram_status cvgram_batch_run_eager(cvgram_batch_t bb) try {
   if (!bb) return fail(CVGRAM_EINVAL, "NULL batch");
   try {
     run_pipeline(bb->b, false);
@@ -1896,25 +1912,25 @@ cvgram_status cvgram_batch_run_eager(cvgram_batch_t bb) {
     return f.st;
   }
   return CVGRAM_OK;
-}
+} CVG_ABI_CATCH
 
 cvgram_status cvgram_batch_problem_info(cvgram_batch_t bb, int32_t i, int32_t* P,
-                                        int32_t* scalable) {
+                                        int32_t* scalable) try {
   if (!bb) return fail(CVGRAM_EINVAL, "NULL batch");
   if (i < 0 || i >= (int32_t)bb->b.pp.size()) return fail(CVGRAM_ERANGE, "problem index out of range");
   if (P) *P = bb->b.pp[i].P;
   if (scalable) *scalable = bb->b.pp[i].scalable ? 1 : 0;
   return CVGRAM_OK;
-}
+} CVG_ABI_CATCH
 
-cvgram_status cvgram_batch_destroy(cvgram_batch_t bb) {
+cvgram_status cvgram_batch_destroy(cvgram_batch_t bb) try {
   if (!bb) return CVGRAM_OK;
   hipError_t e = hipStreamSynchronize(bb->b.stream);
   bb->b.release();
   delete bb;
   if (e != hipSuccess) return fail(CVGRAM_EDEVICE, hipGetErrorString(e));
   return CVGRAM_OK;
-}
+} CVG_ABI_CATCH
 
 // ---------------------------------------------------------------------------
 // autotuner
@@ -1976,7 +1992,7 @@ extern "C" {
 
 cvgram_status cvgram_autotune(const void* X, const void* Y, const int32_t* fold_id, int64_t N,
                               int64_t K, int64_t M, cvgram_dtype dtype, cvgram_mode mode,
-                              void* stream, int32_t* tile, int32_t* target_items) {
+                              void* stream, int32_t* tile, int32_t* target_items) try {
   set_error("");
   cvgram_status st = check_problem(X, Y, fold_id, N, K, M);
   if (st != CVGRAM_OK) return st;
@@ -2024,11 +2040,11 @@ cvgram_status cvgram_autotune(const void* X, const void* Y, const int32_t* fold_
   if (tile) *tile = best.tile;
   if (target_items) *target_items = (int32_t)best.target_items;
   return CVGRAM_OK;
-}
+} CVG_ABI_CATCH
 
 cvgram_status cvgram_batch_autotune(const cvgram_problem* problems, int32_t n, cvgram_dtype dtype,
                                     cvgram_mode mode, void* stream, int32_t* max_tile,
-                                    int32_t* wide_min_k, int32_t* target_items, double* gram_ms) {
+                                    int32_t* wide_min_k, int32_t* target_items, double* gram_ms) try {
   set_error("");
   if (!problems || n < 1) return fail(CVGRAM_EINVAL, "need at least one problem");
   if (dtype != CVGRAM_F32 && dtype != CVGRAM_F64) return fail(CVGRAM_EINVAL, "bad dtype");
@@ -2098,7 +2114,7 @@ cvgram_status cvgram_batch_autotune(const cvgram_problem* problems, int32_t n, c
   if (target_items) *target_items = (int32_t)best.target_items;
   if (gram_ms) *gram_ms = best_ms;
   return CVGRAM_OK;
-}
+} CVG_ABI_CATCH
 
 }  // extern "C"
 
@@ -2146,7 +2162,7 @@ extern "C" {
 cvgram_status cvgram_folds_all_noalloc(const void* X, const void* Y, const int32_t* fold_id,
                                        int64_t N, int64_t K, int64_t M, cvgram_dtype dtype,
                                        int ddof, cvgram_mode mode, int32_t P, void* stream,
-                                       void* out_XtX, void* out_XtY) {
+                                       void* out_XtX, void* out_XtY) try {
   set_error("");
   cvgram_status st = check_problem(X, Y, fold_id, N, K, M);
   if (st != CVGRAM_OK) return st;
@@ -2197,7 +2213,7 @@ cvgram_status cvgram_folds_all_noalloc(const void* X, const void* Y, const int32
   if (st != CVGRAM_OK) (void)hipStreamSynchronize(b.stream);
   b.release();
   return st;
-}
+} CVG_ABI_CATCH
 
 const char* cvgram_status_string(cvgram_status s) {
   switch (s) {
