@@ -61,26 +61,25 @@ constexpr int solve_threads() {
 // below the diagonal are written: nothing reads the blocks above.  The rows
 // of R^T are factored with the matrix (they become (L^{-1} R)^T: the forward
 // substitution).
-// grid (Kr / kSetupRows, matrices), Kr = Kp + Ma: a workgroup fills
-// kSetupRows rows, two neighbouring columns per thread
+// grid (Kr / kSetupRows, folds), Kr = Kp + Ma: a workgroup fills kSetupRows
+// rows of every lambda's matrix of its fold, two neighbouring columns per
+// thread, reading each product entry once
 constexpr int kSetupRows = 8;
 __global__ __launch_bounds__(kThreads) void ridge_setup_kernel(
     const double* __restrict__ xtx, const double* __restrict__ xty,
     const double* __restrict__ lambdas, int32_t n_lambda, int64_t K, int64_t M, int64_t Kp,
     int64_t Kr, double* __restrict__ A) {
-  const int64_t mat = blockIdx.y;  // fold * n_lambda + lambda
-  const int64_t f = mat / n_lambda;
-  const double lam = lambdas[mat % n_lambda];
+  const int64_t f = blockIdx.y;
   const CVG_GLOBAL double* src = gmem(xtx) + f * K * K;
   const CVG_GLOBAL double* rs = gmem(xty) + f * K * M;
-  CVG_GLOBAL double* dst = gmem(A) + mat * Kr * Kp;
+  CVG_GLOBAL double* dst = gmem(A) + f * n_lambda * Kr * Kp;
   const int64_t i0 = (int64_t)blockIdx.x * kSetupRows;
   auto value = [&](int64_t i, int64_t j) {
     if (i >= Kp) {  // R^T
       const int64_t m = i - Kp;
       return (m < M && j < K) ? rs[j * M + m] : 0.0;
     }
-    return (i < K && j < K) ? src[i * K + j] + (i == j ? lam : 0.0) : (i == j ? 1.0 : 0.0);
+    return (i < K && j < K) ? src[i * K + j] : (i == j ? 1.0 : 0.0);
   };
   for (int rr = 0; rr < kSetupRows; ++rr) {
     const int64_t i = i0 + rr;
@@ -89,7 +88,15 @@ __global__ __launch_bounds__(kThreads) void ridge_setup_kernel(
       double2_t v;
       v.x = value(i, j);
       v.y = value(i, j + 1);
-      *(CVG_GLOBAL double2_t*)&dst[i * Kp + j] = v;
+      // lambda on the diagonal of the K x K part
+      const bool dx = i < K && i == j, dy = i < K && i == j + 1;
+      for (int32_t l = 0; l < n_lambda; ++l) {
+        const double lam = lambdas[l];
+        double2_t w = v;
+        if (dx) w.x += lam;
+        if (dy) w.y += lam;
+        *(CVG_GLOBAL double2_t*)&dst[(l * Kr + i) * Kp + j] = w;
+      }
     }
   }
 }
@@ -139,7 +146,8 @@ __device__ __forceinline__ double from_lane(double x, int lane) {
 // L X = I in the same steps, since step c of the substitution needs only
 // column c of L, final once step c of the factorisation has divided it.
 // Step c: with the pivot p = sqrt(A[c][c]) a factor row takes
-// L[q][c] = A[q][c] / p, an inverse column X[c][t] = X[c][t] / p; then both
+// L[q][c] = A[q][c] / p, an inverse column X[c][t] = X[c][t] / p (both as
+// products with 1 / p); then both
 // updates are one FMA with a broadcast operand (v_readlane): the factor rows
 // L[q][k] -= L[q][c] L[k][c] (c < k <= q), the inverse columns
 // X[k][t] -= L[k][c] X[c][t] (k > c); every entry sums in increasing c.  The
@@ -160,10 +168,18 @@ __device__ __forceinline__ void factor32_wave(double* S, int ld, double* Li, int
   for (int c = 0; c < NB; ++c) {
     const double d = from_lane(u[c], c);  // pivot: A[c][c] after the earlier steps
     bad = bad || !(d > 0.0);
-    const double piv = d > 0.0 ? sqrt(d) : NAN;
+    // y = 1 / sqrt(d): the hardware estimate (about 23 good bits) and two
+    // Newton steps y <- y (3 - d y^2) / 2, each doubling the good bits; then
+    // sqrt(d) = d y, and the column is scaled by y instead of divided by
+    // sqrt(d) (a chain of 7 dependent operations instead of about 25)
+    double y = __builtin_amdgcn_rsq(d);
+    const double hd = 0.5 * d;
+    y = y * fma(-hd, y * y, 1.5);
+    y = y * fma(-hd, y * y, 1.5);
+    if (!(d > 0.0)) y = NAN;
     // L[q][c] below the pivot, X[c][q] in an inverse column (a factor row
-    // above the pivot divides a value that is never read)
-    u[c] = fac && q == c ? piv : u[c] / piv;
+    // above the pivot scales a value that is never read)
+    u[c] = fac && q == c ? d * y : u[c] * y;
 #pragma unroll
     for (int k = c + 1; k < NB; ++k) {
       const double lkc = from_lane(u[c], k);  // L[k][c]
@@ -318,34 +334,53 @@ __global__ __launch_bounds__(kThreads) void chol_diag64_kernel(double* __restric
 // blocks of v_mfma_f64_16x16x4f64 over 16 steps of 4 c.  Element e of
 // acc[a][b] in lane (fr = lane / 16, fc = lane % 16) is
 //   C[32 wm + 16 a + 4 e + fr][32 wn + 16 b + fc].
-template <bool NEG>
+// NU < 2: only the wave's first NU 16-row blocks (acc[u], u < NU).
+template <bool NEG, int NU = 2>
 __device__ inline void mma64(const double* X, const double* Y, double4_t (&acc)[2][2], int wm,
                              int wn, int fr, int fc) {
 #pragma unroll 4
   for (int kk = 0; kk < NB2 / 4; ++kk) {
     double af[2], bf[2];
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
+    for (int u = 0; u < NU; ++u) {
       const double x = X[(32 * wm + 16 * u + fc) * LDB + 4 * kk + fr];
       af[u] = NEG ? -x : x;
-      bf[u] = Y[(32 * wn + 16 * u + fc) * LDB + 4 * kk + fr];
     }
 #pragma unroll
-    for (int u = 0; u < 2; ++u)
+    for (int w = 0; w < 2; ++w) bf[w] = Y[(32 * wn + 16 * w + fc) * LDB + 4 * kk + fr];
+#pragma unroll
+    for (int u = 0; u < NU; ++u)
 #pragma unroll
       for (int w = 0; w < 2; ++w)
         acc[u][w] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[u], bf[w], acc[u][w], 0, 0, 0);
   }
 }
 
+// The 16-row blocks of a wave's 32 rows that hold rows of the system: all
+// of a matrix block; of a block of R^T rows (block row ib >= nb64), those
+// below row M of R^T (the rows past it are zero and stay zero).
+__device__ inline int live_row_blocks(int32_t ib, int32_t nb64, int64_t M, int wm) {
+  if (ib < nb64) return 2;
+  const int64_t live = M - (int64_t)(ib - nb64) * NB2 - 32 * wm;
+  return live <= 0 ? 0 : live >= 32 ? 2 : live > 16 ? 2 : 1;
+}
+template <bool NEG>
+__device__ inline void mma64_rows(const double* X, const double* Y, double4_t (&acc)[2][2], int wm,
+                                  int wn, int fr, int fc, int nu) {
+  if (nu == 2)
+    mma64<NEG, 2>(X, Y, acc, wm, wn, fr, fc);
+  else if (nu == 1)
+    mma64<NEG, 1>(X, Y, acc, wm, wn, fr, fc);
+}
+
 // panel: L_is = A_is Linv_ss^T for block rows i > s (64 x 64 blocks, FP64
 // MFMA), in place; the naug block rows below the matrix (R^T) take the same
-// step.  grid (matrices, block rows below s: nb64 - 1 - s of the matrix, then
-// naug)
+// step (products only for their rows below M).  grid (matrices, block rows
+// below s: nb64 - 1 - s of the matrix, then naug)
 __global__ __launch_bounds__(kThreads) void chol_panel64_kernel(double* __restrict__ A,
                                                                 const double* __restrict__ Linv64,
-                                                                int64_t Kp, int64_t Kr, int32_t s,
-                                                                int32_t nb64) {
+                                                                int64_t Kp, int64_t Kr, int64_t M,
+                                                                int32_t s, int32_t nb64) {
   __shared__ double Xs[NB2 * LDB], Ys[NB2 * LDB];
   const int64_t mat = blockIdx.x;
   const int32_t ib = s + 1 + (int32_t)blockIdx.y;  // >= nb64: a row block of R^T
@@ -362,7 +397,7 @@ __global__ __launch_bounds__(kThreads) void chol_panel64_kernel(double* __restri
   for (int u = 0; u < 2; ++u)
 #pragma unroll
     for (int v = 0; v < 2; ++v) acc[u][v] = double4_t{0.0, 0.0, 0.0, 0.0};
-  mma64<false>(Xs, Ys, acc, wm, wn, fr, fc);
+  mma64_rows<false>(Xs, Ys, acc, wm, wn, fr, fc, live_row_blocks(ib, nb64, M, wm));
   __syncthreads();  // every wave's reads of Xs are done
 #pragma unroll
   for (int u = 0; u < 2; ++u)
@@ -389,8 +424,8 @@ __global__ __launch_bounds__(kThreads) void chol_update64_kernel(double* __restr
                                                                  double* __restrict__ Linv64,
                                                                  double* __restrict__ Linv32,
                                                                  int32_t* __restrict__ flags,
-                                                                 int64_t Kp, int64_t Kr, int32_t s,
-                                                                 int32_t nb64) {
+                                                                 int64_t Kp, int64_t Kr, int64_t M,
+                                                                 int32_t s, int32_t nb64) {
   __shared__ double Xs[NB2 * LDB], Ys[NB2 * LDB];
   const int64_t mat = blockIdx.x;
   const int32_t below = nb64 - 1 - s;
@@ -415,29 +450,32 @@ __global__ __launch_bounds__(kThreads) void chol_update64_kernel(double* __restr
   CVG_GLOBAL double* a = gmem(A) + mat * Kr * Kp;
   CVG_GLOBAL double* out = a + (int64_t)ib * NB2 * Kp + (int64_t)kb * NB2;
   const bool idle = ib == kb && wm < wn;
+  // 16-row blocks of the wave's rows to update (the zero rows of R^T stay)
+  const int nu = idle ? 0 : live_row_blocks(ib, nb64, M, wm);
   double4_t acc[2][2];
-  if (!idle) {
 #pragma unroll
-    for (int u = 0; u < 2; ++u)
+  for (int u = 0; u < 2; ++u)
+    if (u < nu) {
 #pragma unroll
       for (int v = 0; v < 2; ++v)
 #pragma unroll
         for (int e = 0; e < 4; ++e)
           acc[u][v][e] = out[(32 * wm + 16 * u + 4 * e + fr) * Kp + 32 * wn + 16 * v + fc];
-  }
+    }
   load_block64(a + (int64_t)ib * NB2 * Kp + (int64_t)s * NB2, Kp, Xs, t);
   if (kb != ib) load_block64(a + (int64_t)kb * NB2 * Kp + (int64_t)s * NB2, Kp, Ys, t);
   __syncthreads();
-  if (!idle) mma64<true>(Xs, kb != ib ? Ys : Xs, acc, wm, wn, fr, fc);
+  mma64_rows<true>(Xs, kb != ib ? Ys : Xs, acc, wm, wn, fr, fc, nu);
   if (!owner) {
-    if (idle) return;
 #pragma unroll
     for (int u = 0; u < 2; ++u)
+      if (u < nu) {
 #pragma unroll
-      for (int v = 0; v < 2; ++v)
+        for (int v = 0; v < 2; ++v)
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
-          out[(32 * wm + 16 * u + 4 * e + fr) * Kp + 32 * wn + 16 * v + fc] = acc[u][v][e];
+          for (int e = 0; e < 4; ++e)
+            out[(32 * wm + 16 * u + 4 * e + fr) * Kp + 32 * wn + 16 * v + fc] = acc[u][v][e];
+      }
     return;
   }
   // the owner: the updated block to LDS (its lower triangle; the idle
@@ -637,7 +675,7 @@ void ridge_solve(const double* xtx, const double* xty, const double* lambdas, in
   double* Linv32 = Linv + n_mat * nb64 * NB2 * NB2;     // [n_mat][nblk][32][32]
   const int64_t Ma = ridge_aug_rows(M), Kr = Kp + Ma;
   const int32_t naug = (int32_t)(Ma / NB2);
-  ridge_setup_kernel<<<dim3((unsigned)(Kr / kSetupRows), (unsigned)n_mat), kThreads, 0, s>>>(
+  ridge_setup_kernel<<<dim3((unsigned)(Kr / kSetupRows), (unsigned)n_folds), kThreads, 0, s>>>(
       xtx, xty, lambdas, n_lambda, K, M, Kp, Kr, A);
   CVG_LAUNCH_CHECK();
   // diagonal block 0, then per block column s: the panel below it (the
@@ -649,13 +687,13 @@ void ridge_solve(const double* xtx, const double* xty, const double* lambdas, in
     const int32_t below = nb64 - j - 1;
     if (below + naug > 0) {
       chol_panel64_kernel<<<dim3((unsigned)n_mat, (unsigned)(below + naug)), kThreads, 0, s>>>(
-          A, Linv64, Kp, Kr, j, nb64);
+          A, Linv64, Kp, Kr, M, j, nb64);
       CVG_LAUNCH_CHECK();
     }
     if (below > 0) {
       const int32_t blocks = below * (below + 1) / 2 + naug * below;
       chol_update64_kernel<<<dim3((unsigned)n_mat, (unsigned)blocks), kThreads, 0, s>>>(
-          A, Linv64, Linv32, flags, Kp, Kr, j, nb64);
+          A, Linv64, Linv32, flags, Kp, Kr, M, j, nb64);
       CVG_LAUNCH_CHECK();
     }
   }
