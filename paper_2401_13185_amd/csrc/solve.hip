@@ -662,6 +662,121 @@ __global__ __launch_bounds__(solve_threads<MW>()) void tri_solve_kernel(const do
   }
 }
 
+
+// The backward substitution on the FP64 matrix cores, for Kp <= 512: one
+// workgroup of 8 waves per (matrix, 16 columns of B).  The columns of
+// R = (L^{-1} R)^T's transpose are read from the factorisation's R^T rows
+// and stay in the accumulators for the whole walk: row tile tau (rows
+// 16 tau .. 16 tau + 15) belongs to wave tau % 8, slot tau / 8, as one
+// 16 x 16 v_mfma_f64_16x16x4f64 tile.  Step j (32 rows from r0 = 32 j, last
+// block first):
+//   1. the two owners put block j's rows (final: every later block's
+//      update is applied) in LDS;
+//   2. waves 0 and 1 form W_j = Linv_jj^T R_j, 16 rows each (8 MFMAs over
+//      the 32 rows of the block), into LDS and into B (rows below K,
+//      columns below M);
+//   3. every wave updates its tiles above the block, R_i -= L_ji^T W_j
+//      (8 MFMAs a tile, the negated coefficients L[r0 + c][i] as the first
+//      operand, read along rows of the factor's block row j).
+// The coefficients of the next step are loaded during this one's update.
+// Only W crosses between waves (one LDS value per lane per MFMA), where a
+// row-per-thread update reads all of W from LDS in every wave.
+constexpr int kTsWaves = 8;
+constexpr int kTsSlots = 4;  // 16-row tiles per wave: Kp <= 8 x 4 x 16
+constexpr int kTsCols = 16;
+__global__ __launch_bounds__(kTsWaves * kWave) void tri_solve_mfma_kernel(
+    const double* __restrict__ A, const double* __restrict__ Linv, double* __restrict__ B,
+    int64_t K, int64_t M, int64_t Kp, int64_t Kr, int32_t nblk) {
+  __shared__ double Rb[NB][kTsCols + 1];
+  __shared__ double Zs[NB][kTsCols + 1];
+  const int64_t mat = blockIdx.x;
+  const int64_t m0 = (int64_t)blockIdx.y * kTsCols;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int fr = lane >> 4, fc = lane & 15;
+  const CVG_GLOBAL double* a = gmem(A) + mat * Kr * Kp;
+  const int32_t ntile = (int32_t)(Kp / 16);
+  // R[i][m0 + c] = R^T[m0 + c][i], rows of R^T below the factor
+  double4_t acc[kTsSlots];
+#pragma unroll
+  for (int sl = 0; sl < kTsSlots; ++sl) {
+    const int32_t tau = w + kTsWaves * sl;
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      acc[sl][e] = tau < ntile ? a[(Kp + m0 + fc) * Kp + 16 * tau + 4 * e + fr] : 0.0;
+  }
+  // coefficients of step j for the tiles above its block:
+  // cf[sl][kk] = L[32 j + 4 kk + fr][16 tau + fc]
+  double cf[kTsSlots][8];
+  auto load_cf = [&](int32_t j) {
+#pragma unroll
+    for (int sl = 0; sl < kTsSlots; ++sl) {
+      const int32_t tau = w + kTsWaves * sl;
+      if (tau < 2 * j) {
+#pragma unroll
+        for (int kk = 0; kk < 8; ++kk)
+          cf[sl][kk] = a[((int64_t)j * NB + 4 * kk + fr) * Kp + 16 * tau + fc];
+      }
+    }
+  };
+  // Linv_jj^T for wave h < 2: lf[kk] = Linv_jj[4 kk + fr][16 h + fc]
+  double lf[8];
+  auto load_lf = [&](int32_t j) {
+    if (w < 2) {
+      const CVG_GLOBAL double* li = gmem(Linv) + (mat * nblk + j) * NB * NB;
+#pragma unroll
+      for (int kk = 0; kk < 8; ++kk) lf[kk] = li[(4 * kk + fr) * NB + 16 * w + fc];
+    }
+  };
+  load_cf(nblk - 1);
+  load_lf(nblk - 1);
+#pragma unroll 1
+  for (int32_t j = nblk - 1; j >= 0; --j) {
+    const int64_t r0 = (int64_t)j * NB;
+    // 1. block j's two tiles (2 j, 2 j + 1) to LDS
+#pragma unroll
+    for (int sl = 0; sl < kTsSlots; ++sl) {
+      const int32_t tau = w + kTsWaves * sl;
+      if (tau == 2 * j || tau == 2 * j + 1) {
+        const int h = tau - 2 * j;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) Rb[16 * h + 4 * e + fr][fc] = acc[sl][e];
+      }
+    }
+    __syncthreads();
+    // 2. W_j = Linv_jj^T R_j
+    if (w < 2) {
+      double4_t z = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int kk = 0; kk < 8; ++kk)
+        z = __builtin_amdgcn_mfma_f64_16x16x4f64(lf[kk], Rb[4 * kk + fr][fc], z, 0, 0, 0);
+      const int64_t m = m0 + fc;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int rl = 16 * w + 4 * e + fr;
+        Zs[rl][fc] = z[e];
+        const int64_t r = r0 + rl;
+        if (r < K && m < M) gmem(B)[(mat * K + r) * M + m] = z[e];
+      }
+    }
+    __syncthreads();
+    if (j > 0) load_lf(j - 1);
+    // 3. R_i -= L_ji^T W_j for the tiles above the block
+    double bz[8];
+#pragma unroll
+    for (int kk = 0; kk < 8; ++kk) bz[kk] = Zs[4 * kk + fr][fc];
+#pragma unroll
+    for (int sl = 0; sl < kTsSlots; ++sl) {
+      const int32_t tau = w + kTsWaves * sl;
+      if (tau < 2 * j) {
+#pragma unroll
+        for (int kk = 0; kk < 8; ++kk)
+          acc[sl] = __builtin_amdgcn_mfma_f64_16x16x4f64(-cf[sl][kk], bz[kk], acc[sl], 0, 0, 0);
+      }
+    }
+    if (j > 0) load_cf(j - 1);
+  }
+}
+
 }  // namespace
 
 void ridge_solve(const double* xtx, const double* xty, const double* lambdas, int32_t n_folds,
@@ -699,6 +814,12 @@ void ridge_solve(const double* xtx, const double* xty, const double* lambdas, in
   }
   if (M <= 0) return;
   // the forward substitution is done ((L^{-1} R)^T below the factor)
+  if (Kp <= (int64_t)kTsWaves * kTsSlots * 16) {
+    const dim3 grid((unsigned)n_mat, (unsigned)((M + kTsCols - 1) / kTsCols));
+    tri_solve_mfma_kernel<<<grid, kTsWaves * kWave, 0, s>>>(A, Linv32, B, K, M, Kp, Kr, nblk);
+    CVG_LAUNCH_CHECK();
+    return;
+  }
   ridge_z_kernel<<<dim3((unsigned)(Kp / 8), (unsigned)n_mat), kThreads, 0, s>>>(A, Kp, Kr, Mp, R);
   CVG_LAUNCH_CHECK();
   const dim3 grid((unsigned)n_mat, (unsigned)(Mp / NB));
