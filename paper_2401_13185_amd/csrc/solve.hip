@@ -55,51 +55,7 @@ constexpr int solve_threads() {
   return MW <= 16 ? 512 : kThreads;
 }
 
-// padded systems: A + lambda I in Kp x Kp (identity in the padding) and,
-// below it, R^T in Ma rows of Kp (zeros in the padding), from the products
-// (p-major, lambda-minor).  Of the square part only the 64 x 64 blocks on and
-// below the diagonal are written: nothing reads the blocks above.  The rows
-// of R^T are factored with the matrix (they become (L^{-1} R)^T: the forward
-// substitution).
-// grid (Kr / kSetupRows, folds), Kr = Kp + Ma: a workgroup fills kSetupRows
-// rows of every lambda's matrix of its fold, two neighbouring columns per
-// thread, reading each product entry once
-constexpr int kSetupRows = 8;
-__global__ __launch_bounds__(kThreads) void ridge_setup_kernel(
-    const double* __restrict__ xtx, const double* __restrict__ xty,
-    const double* __restrict__ lambdas, int32_t n_lambda, int64_t K, int64_t M, int64_t Kp,
-    int64_t Kr, double* __restrict__ A) {
-  const int64_t f = blockIdx.y;
-  const CVG_GLOBAL double* src = gmem(xtx) + f * K * K;
-  const CVG_GLOBAL double* rs = gmem(xty) + f * K * M;
-  CVG_GLOBAL double* dst = gmem(A) + f * n_lambda * Kr * Kp;
-  const int64_t i0 = (int64_t)blockIdx.x * kSetupRows;
-  auto value = [&](int64_t i, int64_t j) {
-    if (i >= Kp) {  // R^T
-      const int64_t m = i - Kp;
-      return (m < M && j < K) ? rs[j * M + m] : 0.0;
-    }
-    return (i < K && j < K) ? src[i * K + j] : (i == j ? 1.0 : 0.0);
-  };
-  for (int rr = 0; rr < kSetupRows; ++rr) {
-    const int64_t i = i0 + rr;
-    const int64_t jend = i >= Kp ? Kp : (i / NB2 + 1) * NB2;
-    for (int64_t j = 2 * (int64_t)threadIdx.x; j < jend; j += 2 * kThreads) {
-      double2_t v;
-      v.x = value(i, j);
-      v.y = value(i, j + 1);
-      // lambda on the diagonal of the K x K part
-      const bool dx = i < K && i == j, dy = i < K && i == j + 1;
-      for (int32_t l = 0; l < n_lambda; ++l) {
-        const double lam = lambdas[l];
-        double2_t w = v;
-        if (dx) w.x += lam;
-        if (dy) w.y += lam;
-        *(CVG_GLOBAL double2_t*)&dst[(l * Kr + i) * Kp + j] = w;
-      }
-    }
-  }
-}
+constexpr int kSetupRows = 8;  // rows of the padded systems per setup workgroup
 
 // R[mat] (Kp x Mp) = the first Mp rows of (L^{-1} R)^T below the factor,
 // transposed: the backward substitution's input.  grid (Kp / 8, matrices)
@@ -311,22 +267,77 @@ __device__ __forceinline__ void diag64_body(double* S, double* I1, double* I2, d
   if (t == 0 && bad) flags[mat] = 1;
 }
 
-// diagonal block 0 of every matrix (the later ones are factored by the
-// trailing update that finishes them); grid: matrices
-__global__ __launch_bounds__(kThreads) void chol_diag64_kernel(double* __restrict__ A,
-                                                               double* __restrict__ Linv64,
-                                                               double* __restrict__ Linv32,
-                                                               int32_t* __restrict__ flags,
-                                                               int64_t Kp, int64_t Kr,
-                                                               int32_t nb64) {
+// The padded systems and their first diagonal block, in one launch.
+// Padded system: A + lambda I in Kp x Kp (identity in the padding) and,
+// below it, R^T in Ma rows of Kp (zeros in the padding), from the products
+// (p-major, lambda-minor).  Of the square part only the 64 x 64 blocks on and
+// below the diagonal are written: nothing reads the blocks above.  The rows
+// of R^T are factored with the matrix (they become (L^{-1} R)^T: the forward
+// substitution).
+// grid (n_lambda + Kr / kSetupRows, folds), Kr = Kp + Ma.  Workgroup x <
+// n_lambda factors diagonal block 0 of the fold's matrix for penalty x
+// (read from the products; the later diagonal blocks are factored by the
+// trailing update that finishes them), so it runs beside the copies
+// instead of after them.  The others fill kSetupRows rows of every
+// penalty's matrix of the fold below row 64 (block 0 is the diagonal
+// workgroups'), two neighbouring columns per thread, reading each product
+// entry once.
+__global__ __launch_bounds__(kThreads) void ridge_setup_kernel(
+    const double* __restrict__ xtx, const double* __restrict__ xty,
+    const double* __restrict__ lambdas, int32_t n_lambda, int64_t K, int64_t M, int64_t Kp,
+    int64_t Kr, double* __restrict__ A, double* __restrict__ Linv64, double* __restrict__ Linv32,
+    int32_t* __restrict__ flags, int32_t nb64) {
   __shared__ double S[NB2 * LDB];
   __shared__ double I1[NB * (NB + 1)], I2[NB * (NB + 1)], T[NB * (NB + 1)];
-  const int64_t mat = blockIdx.x;
+  const int64_t f = blockIdx.y;
   const int t = threadIdx.x;
-  CVG_GLOBAL double* a = gmem(A) + mat * Kr * Kp;
-  load_block64(a, Kp, S, t);
-  __syncthreads();
-  diag64_body(S, I1, I2, T, a, Linv64, Linv32, flags, Kp, mat, 0, nb64, t);
+  const CVG_GLOBAL double* src = gmem(xtx) + f * K * K;
+  const CVG_GLOBAL double* rs = gmem(xty) + f * K * M;
+  auto value = [&](int64_t i, int64_t j) {
+    if (i >= Kp) {  // R^T
+      const int64_t m = i - Kp;
+      return (m < M && j < K) ? rs[j * M + m] : 0.0;
+    }
+    return (i < K && j < K) ? src[i * K + j] : (i == j ? 1.0 : 0.0);
+  };
+  if ((int32_t)blockIdx.x < n_lambda) {
+    const int64_t mat = f * n_lambda + blockIdx.x;
+    const double lam = lambdas[blockIdx.x];
+    const int r0 = t >> 5, c = (t & 31) * 2;
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+      const int r = r0 + 8 * p;
+      double2_t v;
+      v.x = value(r, c) + (r < K && r == c ? lam : 0.0);
+      v.y = value(r, c + 1) + (r < K && r == c + 1 ? lam : 0.0);
+      *(double2_t*)&S[r * LDB + c] = v;
+    }
+    __syncthreads();
+    diag64_body(S, I1, I2, T, gmem(A) + mat * Kr * Kp, Linv64, Linv32, flags, Kp, mat, 0, nb64,
+                t);
+    return;
+  }
+  CVG_GLOBAL double* dst = gmem(A) + f * n_lambda * Kr * Kp;
+  const int64_t i0 = (int64_t)(blockIdx.x - n_lambda) * kSetupRows;
+  if (i0 < NB2) return;
+  for (int rr = 0; rr < kSetupRows; ++rr) {
+    const int64_t i = i0 + rr;
+    const int64_t jend = i >= Kp ? Kp : (i / NB2 + 1) * NB2;
+    for (int64_t j = 2 * (int64_t)t; j < jend; j += 2 * kThreads) {
+      double2_t v;
+      v.x = value(i, j);
+      v.y = value(i, j + 1);
+      // lambda on the diagonal of the K x K part
+      const bool dx = i < K && i == j, dy = i < K && i == j + 1;
+      for (int32_t l = 0; l < n_lambda; ++l) {
+        const double lam = lambdas[l];
+        double2_t w = v;
+        if (dx) w.x += lam;
+        if (dy) w.y += lam;
+        *(CVG_GLOBAL double2_t*)&dst[(l * Kr + i) * Kp + j] = w;
+      }
+    }
+  }
 }
 
 // C[r][q] += sum_c sign * X[r][c] Y[q][c] over a 64 x 64 tile, X and Y 64 x 64
@@ -704,8 +715,8 @@ __global__ __launch_bounds__(kTsWaves * kWave) void tri_solve_mfma_kernel(
     for (int e = 0; e < 4; ++e)
       acc[sl][e] = tau < ntile ? a[(Kp + m0 + fc) * Kp + 16 * tau + 4 * e + fr] : 0.0;
   }
-  // coefficients of step j for the tiles above its block:
-  // cf[sl][kk] = L[32 j + 4 kk + fr][16 tau + fc]
+  // coefficients of step j for the tiles above its block, negated:
+  // cf[sl][kk] = -L[32 j + 4 kk + fr][16 tau + fc]
   double cf[kTsSlots][8];
   auto load_cf = [&](int32_t j) {
 #pragma unroll
@@ -714,7 +725,7 @@ __global__ __launch_bounds__(kTsWaves * kWave) void tri_solve_mfma_kernel(
       if (tau < 2 * j) {
 #pragma unroll
         for (int kk = 0; kk < 8; ++kk)
-          cf[sl][kk] = a[((int64_t)j * NB + 4 * kk + fr) * Kp + 16 * tau + fc];
+          cf[sl][kk] = -a[((int64_t)j * NB + 4 * kk + fr) * Kp + 16 * tau + fc];
       }
     }
   };
@@ -770,7 +781,7 @@ __global__ __launch_bounds__(kTsWaves * kWave) void tri_solve_mfma_kernel(
       if (tau < 2 * j) {
 #pragma unroll
         for (int kk = 0; kk < 8; ++kk)
-          acc[sl] = __builtin_amdgcn_mfma_f64_16x16x4f64(-cf[sl][kk], bz[kk], acc[sl], 0, 0, 0);
+          acc[sl] = __builtin_amdgcn_mfma_f64_16x16x4f64(cf[sl][kk], bz[kk], acc[sl], 0, 0, 0);
       }
     }
     if (j > 0) load_cf(j - 1);
@@ -790,13 +801,12 @@ void ridge_solve(const double* xtx, const double* xty, const double* lambdas, in
   double* Linv32 = Linv + n_mat * nb64 * NB2 * NB2;     // [n_mat][nblk][32][32]
   const int64_t Ma = ridge_aug_rows(M), Kr = Kp + Ma;
   const int32_t naug = (int32_t)(Ma / NB2);
-  ridge_setup_kernel<<<dim3((unsigned)(Kr / kSetupRows), (unsigned)n_folds), kThreads, 0, s>>>(
-      xtx, xty, lambdas, n_lambda, K, M, Kp, Kr, A);
-  CVG_LAUNCH_CHECK();
-  // diagonal block 0, then per block column s: the panel below it (the
-  // matrix's block rows and the R^T rows) and the trailing update, which
-  // also factors diagonal block s + 1
-  chol_diag64_kernel<<<(unsigned)n_mat, kThreads, 0, s>>>(A, Linv64, Linv32, flags, Kp, Kr, nb64);
+  // the padded systems and diagonal block 0, then per block column s: the
+  // panel below it (the matrix's block rows and the R^T rows) and the
+  // trailing update, which also factors diagonal block s + 1
+  ridge_setup_kernel<<<dim3((unsigned)(n_lambda + Kr / kSetupRows), (unsigned)n_folds), kThreads,
+                       0, s>>>(xtx, xty, lambdas, n_lambda, K, M, Kp, Kr, A, Linv64, Linv32, flags,
+                               nb64);
   CVG_LAUNCH_CHECK();
   for (int32_t j = 0; j < nb64; ++j) {
     const int32_t below = nb64 - j - 1;
