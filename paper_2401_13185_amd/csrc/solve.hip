@@ -715,8 +715,9 @@ __global__ __launch_bounds__(kTsWaves * kWave) void tri_solve_mfma_kernel(
     for (int e = 0; e < 4; ++e)
       acc[sl][e] = tau < ntile ? a[(Kp + m0 + fc) * Kp + 16 * tau + 4 * e + fr] : 0.0;
   }
-  // coefficients of step j for the tiles above its block, negated:
-  // cf[sl][kk] = -L[32 j + 4 kk + fr][16 tau + fc]
+  // coefficients of step j for the tiles above its block (negated as the
+  // MFMA operand, so the loads are not waited for until the products):
+  // cf[sl][kk] = L[32 j + 4 kk + fr][16 tau + fc]
   double cf[kTsSlots][8];
   auto load_cf = [&](int32_t j) {
 #pragma unroll
@@ -725,7 +726,7 @@ __global__ __launch_bounds__(kTsWaves * kWave) void tri_solve_mfma_kernel(
       if (tau < 2 * j) {
 #pragma unroll
         for (int kk = 0; kk < 8; ++kk)
-          cf[sl][kk] = -a[((int64_t)j * NB + 4 * kk + fr) * Kp + 16 * tau + fc];
+          cf[sl][kk] = a[((int64_t)j * NB + 4 * kk + fr) * Kp + 16 * tau + fc];
       }
     }
   };
@@ -781,7 +782,7 @@ __global__ __launch_bounds__(kTsWaves * kWave) void tri_solve_mfma_kernel(
       if (tau < 2 * j) {
 #pragma unroll
         for (int kk = 0; kk < 8; ++kk)
-          acc[sl] = __builtin_amdgcn_mfma_f64_16x16x4f64(cf[sl][kk], bz[kk], acc[sl], 0, 0, 0);
+          acc[sl] = __builtin_amdgcn_mfma_f64_16x16x4f64(-cf[sl][kk], bz[kk], acc[sl], 0, 0, 0);
       }
     }
     if (j > 0) load_cf(j - 1);
