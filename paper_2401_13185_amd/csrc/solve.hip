@@ -172,6 +172,23 @@ __device__ inline void store_block64(CVG_GLOBAL double* g, int64_t ld, const dou
   }
 }
 
+// C = X Y^T (32 x 32 over 32 terms; NEG: C = init - X Y^T) on the FP64
+// matrix cores, wave w computing the 16 x 16 tile (tm, tn) = (w / 2, w % 2);
+// X[r][c] at X[r * ldx + c]; Y[q][c] at Y[q * ldy + c], or at Y[c * ldy + q]
+// when YT.  Element e of the result in lane (fr, fc) is
+// C[16 tm + 4 e + fr][16 tn + fc].
+template <bool YT, bool NEG>
+__device__ inline double4_t mma32(const double* X, int ldx, const double* Y, int ldy, int tm,
+                                  int tn, int fr, int fc, double4_t acc) {
+#pragma unroll
+  for (int kk = 0; kk < NB / 4; ++kk) {
+    const double x = X[(16 * tm + fc) * ldx + 4 * kk + fr];
+    const double y = YT ? Y[(4 * kk + fr) * ldy + 16 * tn + fc] : Y[(16 * tn + fc) * ldy + 4 * kk + fr];
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(NEG ? -x : x, y, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
 // Diagonal block s (64 x 64) of matrix mat by one 256-thread workgroup, the
 // block already in S (LDS, lower triangle valid; I1, I2, T: LDS scratch of
 // 32 x 33 doubles each).  The block is the 2 x 2 arrangement of 32 x 32 blocks
@@ -181,8 +198,8 @@ __device__ inline void store_block64(CVG_GLOBAL double* g, int64_t ld, const dou
 //   [L11^{-1} 0; -L22^{-1} L21 L11^{-1}  L22^{-1}].
 // Written back: the factor to the block's lower triangle; the 64 x 64
 // inverse to Linv64 (the panel step's operand) and the two 32 x 32 diagonal
-// inverses to Linv32 (the backward substitution's).  Small products on the
-// vector ALU in increasing c.
+// inverses to Linv32 (the backward substitution's).  The four 32 x 32
+// products on the FP64 matrix cores, a 16 x 16 tile per wave.
 __device__ __forceinline__ void diag64_body(double* S, double* I1, double* I2, double* T,
                                             CVG_GLOBAL double* a,
                             double* __restrict__ Linv64, double* __restrict__ Linv32,
@@ -190,73 +207,57 @@ __device__ __forceinline__ void diag64_body(double* S, double* I1, double* I2, d
                             int32_t nb64, int t) {
   constexpr int LI = NB + 1;
   CVG_GLOBAL double* blk = a + (int64_t)s * NB2 * Kp + (int64_t)s * NB2;
+  const int lane = t & 63, w = t >> 6;
+  const int fr = lane >> 4, fc = lane & 15, tm = w >> 1, tn = w & 1;
+  const double4_t zero = {0.0, 0.0, 0.0, 0.0};
+  // this lane's entries of a wave's tile: (16 tm + 4 e + fr, 16 tn + fc)
+  auto at = [&](double* M, int ld, int e) -> double& {
+    return M[(16 * tm + 4 * e + fr) * ld + 16 * tn + fc];
+  };
   bool bad = false;  // meaningful in wave 0
   if (t < kWave) factor32_wave(S, LDB, I1, LI, t, bad);
   __syncthreads();
-  const int q = t % NB, rb = t / NB;  // this thread: column q of rows rb + 8 p
-  // the four rows' sums run interleaved (independent FMA chains)
-  double v[kRowsPerThread];
-  // L21[r][q] = sum_c A21[r][c] L11^{-1}[q][c]
+  double* S21 = S + NB * LDB;       // rows 32.., columns 0..
+  double* S22 = S + NB * LDB + NB;  // rows 32.., columns 32..
+  {
+    // L21 = A21 L11^{-T}
+    const double4_t c = mma32<false, false>(S21, LDB, I1, LI, tm, tn, fr, fc, zero);
+    __syncthreads();  // every wave's reads of A21 are done
 #pragma unroll
-  for (int p = 0; p < kRowsPerThread; ++p) v[p] = 0.0;
-#pragma unroll 8
-  for (int c = 0; c < NB; ++c) {
-    const double b = I1[q * LI + c];
-#pragma unroll
-    for (int p = 0; p < kRowsPerThread; ++p)
-      v[p] = fma(S[(NB + rb + kRowStep * p) * LDB + c], b, v[p]);
+    for (int e = 0; e < 4; ++e) at(S21, LDB, e) = c[e];
   }
   __syncthreads();
+  {
+    // A22 -= L21 L21^T (each lane rewrites the entries it read)
+    double4_t c;
 #pragma unroll
-  for (int p = 0; p < kRowsPerThread; ++p) S[(NB + rb + kRowStep * p) * LDB + q] = v[p];
-  __syncthreads();
-  // A22 -= L21 L21^T (reads columns 0..31, writes 32..63)
+    for (int e = 0; e < 4; ++e) c[e] = at(S22, LDB, e);
+    c = mma32<false, true>(S21, LDB, S21, LDB, tm, tn, fr, fc, c);
 #pragma unroll
-  for (int p = 0; p < kRowsPerThread; ++p) v[p] = S[(NB + rb + kRowStep * p) * LDB + NB + q];
-#pragma unroll 8
-  for (int c = 0; c < NB; ++c) {
-    const double b = S[(NB + q) * LDB + c];
-#pragma unroll
-    for (int p = 0; p < kRowsPerThread; ++p)
-      v[p] = fma(-S[(NB + rb + kRowStep * p) * LDB + c], b, v[p]);
+    for (int e = 0; e < 4; ++e) at(S22, LDB, e) = c[e];
   }
-#pragma unroll
-  for (int p = 0; p < kRowsPerThread; ++p) S[(NB + rb + kRowStep * p) * LDB + NB + q] = v[p];
   __syncthreads();
-  if (t < kWave) factor32_wave(S + NB * LDB + NB, LDB, I2, LI, t, bad);
-  // T = L21 L11^{-1}
+  if (t < kWave) factor32_wave(S22, LDB, I2, LI, t, bad);
+  {
+    // T = L21 L11^{-1}
+    const double4_t c = mma32<true, false>(S21, LDB, I1, LI, tm, tn, fr, fc, zero);
 #pragma unroll
-  for (int p = 0; p < kRowsPerThread; ++p) v[p] = 0.0;
-#pragma unroll 8
-  for (int c = 0; c < NB; ++c) {
-    const double b = I1[c * LI + q];
-#pragma unroll
-    for (int p = 0; p < kRowsPerThread; ++p)
-      v[p] = fma(S[(NB + rb + kRowStep * p) * LDB + c], b, v[p]);
+    for (int e = 0; e < 4; ++e) at(T, LI, e) = c[e];
   }
-#pragma unroll
-  for (int p = 0; p < kRowsPerThread; ++p) T[(rb + kRowStep * p) * LI + q] = v[p];
   __syncthreads();
   // the inverse's lower left quadrant: -L22^{-1} T
-#pragma unroll
-  for (int p = 0; p < kRowsPerThread; ++p) v[p] = 0.0;
-#pragma unroll 8
-  for (int c = 0; c < NB; ++c) {
-    const double b = T[c * LI + q];
-#pragma unroll
-    for (int p = 0; p < kRowsPerThread; ++p)
-      v[p] = fma(I2[(rb + kRowStep * p) * LI + c], b, v[p]);
-  }
-#pragma unroll
-  for (int p = 0; p < kRowsPerThread; ++p) v[p] = -v[p];
+  const double4_t vq = mma32<true, false>(I2, LI, T, LI, tm, tn, fr, fc, zero);
   CVG_GLOBAL double* li = gmem(Linv64) + (mat * nb64 + s) * NB2 * NB2;
   CVG_GLOBAL double* l32 = gmem(Linv32) + (mat * 2 * nb64 + 2 * s) * NB * NB;
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+    li[(NB + 16 * tm + 4 * e + fr) * NB2 + 16 * tn + fc] = -vq[e];
+  const int q = t % NB, rb = t / NB;  // this thread: column q of rows rb + 8 p
 #pragma unroll
   for (int p = 0; p < kRowsPerThread; ++p) {
     const int r = rb + kRowStep * p;
     li[r * NB2 + q] = I1[r * LI + q];
     li[r * NB2 + NB + q] = 0.0;
-    li[(NB + r) * NB2 + q] = v[p];
     li[(NB + r) * NB2 + NB + q] = I2[r * LI + q];
     l32[r * NB + q] = I1[r * LI + q];
     l32[NB * NB + r * NB + q] = I2[r * LI + q];
