@@ -95,33 +95,20 @@ __device__ __forceinline__ double from_lane(double x, int lane) {
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-// One wave factors a 32 x 32 block held in LDS (rows q of S, lower triangle
-// read) and inverts the factor, all in registers: lanes 0..31 hold the rows
-// of the block and factor it column by column (right-looking); lanes 32..63
-// hold the columns of the factor's inverse and run the forward substitution
-// L X = I in the same steps, since step c of the substitution needs only
-// column c of L, final once step c of the factorisation has divided it.
-// Step c: with the pivot p = sqrt(A[c][c]) a factor row takes
-// L[q][c] = A[q][c] / p, an inverse column X[c][t] = X[c][t] / p (both as
-// products with 1 / p); then both
-// updates are one FMA with a broadcast operand (v_readlane): the factor rows
-// L[q][k] -= L[q][c] L[k][c] (c < k <= q), the inverse columns
-// X[k][t] -= L[k][c] X[c][t] (k > c); every entry sums in increasing c.  The
-// factor goes back to S (lower triangle, zeros above), its inverse to Li
-// (row-major, zeros above the diagonal); bad is set on a non-positive pivot
+// Steps c = C0 .. C1 - 1 of a one-wave right-looking factorisation over the
+// columns [C0, C1): a lane holds a factor row (fac; row q) or a column of the
+// factor's inverse in u.  Step c: with the pivot p = sqrt(A[c][c]) a factor
+// row takes L[q][c] = A[q][c] / p, an inverse column X[c][t] = X[c][t] / p
+// (both as products with 1 / p); then both updates are one FMA with a
+// broadcast operand (v_readlane): the factor rows L[q][k] -= L[q][c] L[k][c],
+// the inverse columns X[k][t] -= L[k][c] X[c][t] (c < k < C1); every entry
+// sums in increasing c.  Factor rows above the pivot update entries above
+// the diagonal, which are never read.  bad is set on a non-positive pivot
 // (the factorisation then continues with NaN).
-__device__ __forceinline__ void factor32_wave(double* S, int ld, double* Li, int ldi, int l,
-                                              bool& bad) {
-  const bool fac = l < NB;  // a factor row, else an inverse column
-  const int q = l % NB;     // its row / column index
-  double u[NB];
+template <int C0, int C1>
+__device__ __forceinline__ void factor_steps(double (&u)[NB], int q, bool fac, bool& bad) {
 #pragma unroll
-  for (int k = 0; k < NB; ++k) {
-    const double v = S[q * ld + k];
-    u[k] = (fac && k <= q) ? v : (q == k ? 1.0 : 0.0);
-  }
-#pragma unroll
-  for (int c = 0; c < NB; ++c) {
+  for (int c = C0; c < C1; ++c) {
     const double d = from_lane(u[c], c);  // pivot: A[c][c] after the earlier steps
     bad = bad || !(d > 0.0);
     // y = 1 / sqrt(d): the hardware estimate (about 23 good bits) and two
@@ -133,22 +120,108 @@ __device__ __forceinline__ void factor32_wave(double* S, int ld, double* Li, int
     y = y * fma(-hd, y * y, 1.5);
     y = y * fma(-hd, y * y, 1.5);
     if (!(d > 0.0)) y = NAN;
-    // L[q][c] below the pivot, X[c][q] in an inverse column (a factor row
-    // above the pivot scales a value that is never read)
     u[c] = fac && q == c ? d * y : u[c] * y;
 #pragma unroll
-    for (int k = c + 1; k < NB; ++k) {
-      const double lkc = from_lane(u[c], k);  // L[k][c]
-      // factor rows with q < k update entries above the diagonal: never read
-      u[k] = fma(-u[c], lkc, u[k]);
-    }
+    for (int k = c + 1; k < C1; ++k) u[k] = fma(-u[c], from_lane(u[c], k), u[k]);  // L[k][c]
   }
+}
+
+// One wave factors a 32 x 32 block held in LDS (rows q of S, lower triangle
+// read) and inverts the factor, in registers except for three 16 x 16 x 16
+// products: lanes 0..31 hold the rows of the block, lanes 32..63 the columns
+// of the factor's inverse, which run the forward substitution L X = I in the
+// same steps (step c of it needs only column c of L, final once step c of
+// the factorisation has scaled it).  The block is split in 16-column halves,
+//   [A11 .; A21 A22] = [L11 0; L21 L22] [L11 0; L21 L22]^T:
+// the first 16 steps factor columns 0..15 of all 32 rows (L11, L21 = A21
+// L11^{-T}) and invert L11; A22 -= L21 L21^T on the matrix cores; the next
+// 16 steps factor and invert L22; the inverse's lower left quadrant is
+// -L22^{-1} (L21 L11^{-1}) (two more products).  A step broadcasts only the
+// factor entries of its half: 240 broadcasts instead of 496 for the whole
+// block at once.  The factor goes back to S (lower triangle, zeros above),
+// its inverse to Li (row-major, zeros above the diagonal).  LDS traffic
+// between the phases stays within the wave, whose LDS accesses complete in
+// order; the fences keep the compiler from moving them across phases.
+__device__ __forceinline__ void factor32_wave(double* S, int ld, double* Li, int ldi, int l,
+                                              bool& bad) {
+  constexpr int H = NB / 2;
+  const bool fac = l < NB;  // a factor row, else an inverse column
+  const int q = l % NB;     // its row / column index
+  const int fr = (l & 63) >> 4, fc = l & 15;
+  double u[NB];
+  // columns 0..15: rows of [A11; A21], inverse columns 0..15 (lanes 32..47)
+#pragma unroll
+  for (int k = 0; k < NB; ++k) {
+    const double v = k < H ? S[q * ld + k] : 0.0;
+    u[k] = k >= H ? 0.0 : (fac ? (k <= q ? v : 0.0) : (q == k ? 1.0 : 0.0));
+  }
+  factor_steps<0, H>(u, q, fac, bad);
+  // L11 (zeros above it and in the upper right quadrant) and L21 to S,
+  // L11^{-1} to Li
   if (fac) {
 #pragma unroll
-    for (int k = 0; k < NB; ++k) S[q * ld + k] = k <= q ? u[k] : 0.0;
-  } else {
+    for (int k = 0; k < NB; ++k)
+      if (q < H || k < H) S[q * ld + k] = k < H && k <= q ? u[k] : 0.0;
+  } else if (q < H) {
 #pragma unroll
-    for (int r = 0; r < NB; ++r) Li[r * ldi + q] = u[r];
+    for (int r = 0; r < H; ++r) Li[r * ldi + q] = u[r];
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  // A22 -= L21 L21^T: element e of lane (fr, fc) is (H + 4 e + fr, H + fc)
+  {
+    double4_t c;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) c[e] = S[(H + 4 * e + fr) * ld + H + fc];
+#pragma unroll
+    for (int kk = 0; kk < H / 4; ++kk) {
+      const double w = S[(H + fc) * ld + 4 * kk + fr];  // L21[fc][4 kk + fr]
+      c = __builtin_amdgcn_mfma_f64_16x16x4f64(-w, w, c, 0, 0, 0);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) S[(H + 4 * e + fr) * ld + H + fc] = c[e];
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  // columns 16..31: rows 16..31 of A22, inverse columns 16..31 (lanes 48..63)
+#pragma unroll
+  for (int k = H; k < NB; ++k) {
+    const double v = S[q * ld + k];
+    u[k] = fac ? (q >= H && k <= q ? v : 0.0) : (q == k ? 1.0 : 0.0);
+  }
+  factor_steps<H, NB>(u, q, fac, bad);
+  if (fac && q >= H) {
+#pragma unroll
+    for (int k = H; k < NB; ++k) S[q * ld + k] = k <= q ? u[k] : 0.0;
+  } else if (!fac && q >= H) {
+#pragma unroll
+    for (int r = H; r < NB; ++r) Li[r * ldi + q] = u[r];
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  // T = L21 L11^{-1}, kept in Li's upper right quadrant for the moment
+  {
+    double4_t c = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kk = 0; kk < H / 4; ++kk)
+      c = __builtin_amdgcn_mfma_f64_16x16x4f64(S[(H + fc) * ld + 4 * kk + fr],
+                                               Li[(4 * kk + fr) * ldi + fc], c, 0, 0, 0);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) Li[(4 * e + fr) * ldi + H + fc] = c[e];
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  // lower left quadrant of the inverse: -L22^{-1} T; then the zeros of the
+  // upper right one (each lane clears the entries of T it wrote, after the
+  // wave's reads of them)
+  {
+    double4_t c = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kk = 0; kk < H / 4; ++kk)
+      c = __builtin_amdgcn_mfma_f64_16x16x4f64(Li[(H + fc) * ldi + H + 4 * kk + fr],
+                                               Li[(4 * kk + fr) * ldi + H + fc], c, 0, 0, 0);
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      Li[(H + 4 * e + fr) * ldi + fc] = -c[e];
+      Li[(4 * e + fr) * ldi + H + fc] = 0.0;
+    }
   }
 }
 
