@@ -120,3 +120,25 @@ def test_ridge_spectra_workload_one_fold():
     for l, lam in enumerate(lams):
         ref = O.ridge_fold(X, Y, fold, 4, 1, 1, 1, 1, 1, lam)
         assert _relerr(B[4, l], ref) <= 1e-6, lam
+
+
+def test_ridge_many_systems():
+    """256 systems (32 folds x 8 penalties) at K = 384, M = 8 (six block
+    steps, trailing-update launches of up to 5 120 workgroups): every system
+    against the oracle's products and a dense solve."""
+    n, k, m, P = 4000, 384, 8, 32
+    X, Y = _data(n, k, m, 31)
+    fold = np.random.default_rng(31).integers(0, P, size=n).astype(np.int32)
+    fold[:P] = np.arange(P)
+    lams = list(np.logspace(-3, 4, 8))
+    h = cv.cvgram_create(_t(X), _t(Y), _t(fold), 1, 1, 1, 1, ddof=1)
+    print(f"[ridge] N={n} K={k} M={m} P={P} x {len(lams)} penalties", flush=True)
+    B = cv.cvgram_ridge(h, 0, P, lams)
+    torch.cuda.synchronize()
+    B = B.cpu().numpy()
+    cv.cvgram_destroy(h)
+    for p in range(P):
+        xtx, xty = O.fold_products(X, Y, fold, p, 1, 1, 1, 1, 1)
+        for l, lam in enumerate(lams):
+            ref = np.linalg.solve(xtx + lam * np.eye(k), xty)
+            assert _relerr(B[p, l], ref) <= 1e-8, (p, lam)
