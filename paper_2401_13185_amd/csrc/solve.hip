@@ -348,22 +348,25 @@ __device__ __forceinline__ void diag64_body(double* S, double* I1, double* I2, d
 // below the diagonal are written: nothing reads the blocks above.  The rows
 // of R^T are factored with the matrix (they become (L^{-1} R)^T: the forward
 // substitution).
-// grid (n_lambda + Kr / kSetupRows, folds), Kr = Kp + Ma.  Workgroup x <
-// n_lambda factors diagonal block 0 of the fold's matrix for penalty x
+// grid: folds x n_lambda + folds x Kr / kSetupRows workgroups, Kr = Kp +
+// Ma.  The first n_mat workgroups factor diagonal block 0 of one matrix each
 // (read from the products; the later diagonal blocks are factored by the
-// trailing update that finishes them), so it runs beside the copies
-// instead of after them.  The others fill kSetupRows rows of every
-// penalty's matrix of the fold below row 64 (block 0 is the diagonal
-// workgroups'), two neighbouring columns per thread, reading each product
-// entry once.
+// trailing update that finishes them), dispatched first so that they run
+// beside the copies instead of after them.  The others fill kSetupRows rows
+// of every penalty's matrix of one fold below row 64 (block 0 is the
+// diagonal workgroups'), two neighbouring columns per thread, reading each
+// product entry once.
 __global__ __launch_bounds__(kThreads) void ridge_setup_kernel(
     const double* __restrict__ xtx, const double* __restrict__ xty,
-    const double* __restrict__ lambdas, int32_t n_lambda, int64_t K, int64_t M, int64_t Kp,
-    int64_t Kr, double* __restrict__ A, double* __restrict__ Linv64, double* __restrict__ Linv32,
-    int32_t* __restrict__ flags, int32_t nb64) {
+    const double* __restrict__ lambdas, int32_t n_folds, int32_t n_lambda, int64_t K, int64_t M,
+    int64_t Kp, int64_t Kr, double* __restrict__ A, double* __restrict__ Linv64,
+    double* __restrict__ Linv32, int32_t* __restrict__ flags, int32_t nb64) {
   __shared__ double S[NB2 * LDB];
   __shared__ double I1[NB * (NB + 1)], I2[NB * (NB + 1)], T[NB * (NB + 1)];
-  const int64_t f = blockIdx.y;
+  const int64_t nrow = Kr / kSetupRows;
+  const int64_t b = blockIdx.x, n_mat = (int64_t)n_folds * n_lambda;
+  const bool diag = b < n_mat;
+  const int64_t f = diag ? b / n_lambda : (b - n_mat) / nrow;
   const int t = threadIdx.x;
   const CVG_GLOBAL double* src = gmem(xtx) + f * K * K;
   const CVG_GLOBAL double* rs = gmem(xty) + f * K * M;
@@ -374,9 +377,9 @@ __global__ __launch_bounds__(kThreads) void ridge_setup_kernel(
     }
     return (i < K && j < K) ? src[i * K + j] : (i == j ? 1.0 : 0.0);
   };
-  if ((int32_t)blockIdx.x < n_lambda) {
-    const int64_t mat = f * n_lambda + blockIdx.x;
-    const double lam = lambdas[blockIdx.x];
+  if (diag) {
+    const int64_t mat = b;
+    const double lam = lambdas[b % n_lambda];
     const int r0 = t >> 5, c = (t & 31) * 2;
 #pragma unroll
     for (int p = 0; p < 8; ++p) {
@@ -392,20 +395,29 @@ __global__ __launch_bounds__(kThreads) void ridge_setup_kernel(
     return;
   }
   CVG_GLOBAL double* dst = gmem(A) + f * n_lambda * Kr * Kp;
-  const int64_t i0 = (int64_t)(blockIdx.x - n_lambda) * kSetupRows;
+  const int64_t i0 = ((b - n_mat) % nrow) * kSetupRows;
   if (i0 < NB2) return;
-  for (int rr = 0; rr < kSetupRows; ++rr) {
-    const int64_t i = i0 + rr;
-    const int64_t jend = i >= Kp ? Kp : (i / NB2 + 1) * NB2;
-    for (int64_t j = 2 * (int64_t)t; j < jend; j += 2 * kThreads) {
-      double2_t v;
-      v.x = value(i, j);
-      v.y = value(i, j + 1);
+  // per pass of 2 kThreads columns: the rows' values first, all loads in
+  // flight together, then the copies (the stores would otherwise wait for
+  // each row's loads in turn)
+  for (int64_t j = 2 * (int64_t)t; j < Kp; j += 2 * kThreads) {
+    double2_t v[kSetupRows];
+#pragma unroll
+    for (int rr = 0; rr < kSetupRows; ++rr) {
+      const int64_t i = i0 + rr;
+      v[rr].x = value(i, j);
+      v[rr].y = value(i, j + 1);
+    }
+#pragma unroll
+    for (int rr = 0; rr < kSetupRows; ++rr) {
+      const int64_t i = i0 + rr;
+      const int64_t jend = i >= Kp ? Kp : (i / NB2 + 1) * NB2;
+      if (j >= jend) continue;
       // lambda on the diagonal of the K x K part
       const bool dx = i < K && i == j, dy = i < K && i == j + 1;
       for (int32_t l = 0; l < n_lambda; ++l) {
         const double lam = lambdas[l];
-        double2_t w = v;
+        double2_t w = v[rr];
         if (dx) w.x += lam;
         if (dy) w.y += lam;
         *(CVG_GLOBAL double2_t*)&dst[(l * Kr + i) * Kp + j] = w;
@@ -879,9 +891,8 @@ void ridge_solve(const double* xtx, const double* xty, const double* lambdas, in
   // the padded systems and diagonal block 0, then per block column s: the
   // panel below it (the matrix's block rows and the R^T rows) and the
   // trailing update, which also factors diagonal block s + 1
-  ridge_setup_kernel<<<dim3((unsigned)(n_lambda + Kr / kSetupRows), (unsigned)n_folds), kThreads,
-                       0, s>>>(xtx, xty, lambdas, n_lambda, K, M, Kp, Kr, A, Linv64, Linv32, flags,
-                               nb64);
+  ridge_setup_kernel<<<(unsigned)(n_mat + n_folds * (Kr / kSetupRows)), kThreads, 0, s>>>(
+      xtx, xty, lambdas, n_folds, n_lambda, K, M, Kp, Kr, A, Linv64, Linv32, flags, nb64);
   CVG_LAUNCH_CHECK();
   for (int32_t j = 0; j < nb64; ++j) {
     const int32_t below = nb64 - j - 1;
