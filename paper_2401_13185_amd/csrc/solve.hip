@@ -472,39 +472,56 @@ __device__ inline void mma64_rows(const double* X, const double* Y, double4_t (&
 
 // panel: L_is = A_is Linv_ss^T for block rows i > s (64 x 64 blocks, FP64
 // MFMA), in place; the naug block rows below the matrix (R^T) take the same
-// step (products only for their rows below M).  grid (matrices, block rows
-// below s: nb64 - 1 - s of the matrix, then naug)
+// step (products only for their rows below M).  A workgroup forms 32 rows
+// of a block (half the chain of products of a whole block, and LDS for
+// three workgroups a CU): wave w the 16 rows 16 (w / 2) .. and 32 columns
+// 32 (w % 2) ... grid (matrices, 2 x (block rows below s: nb64 - 1 - s of
+// the matrix, then naug)), the two halves of a block adjacent.
 __global__ __launch_bounds__(kThreads) void chol_panel64_kernel(double* __restrict__ A,
                                                                 const double* __restrict__ Linv64,
                                                                 int64_t Kp, int64_t Kr, int64_t M,
                                                                 int32_t s, int32_t nb64) {
-  __shared__ double Xs[NB2 * LDB], Ys[NB2 * LDB];
+  __shared__ double Xs[NB * LDB], Ys[NB2 * LDB];
   const int64_t mat = blockIdx.x;
-  const int32_t ib = s + 1 + (int32_t)blockIdx.y;  // >= nb64: a row block of R^T
+  const int32_t ib = s + 1 + (int32_t)(blockIdx.y >> 1);  // >= nb64: a row block of R^T
+  const int h = blockIdx.y & 1;                            // rows 32 h .. 32 h + 31
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int fr = lane >> 4, fc = lane & 15, wm = w >> 1, wn = w & 1;
   CVG_GLOBAL double* a = gmem(A) + mat * Kr * Kp;
-  CVG_GLOBAL double* blk = a + (int64_t)ib * NB2 * Kp + (int64_t)s * NB2;  // block (ib, s)
+  CVG_GLOBAL double* blk = a + ((int64_t)ib * NB2 + NB * h) * Kp + (int64_t)s * NB2;
   const CVG_GLOBAL double* li = gmem(Linv64) + (mat * nb64 + s) * NB2 * NB2;
-  load_block64(blk, Kp, Xs, t);
+  const int r0 = t >> 5, c0 = (t & 31) * 2;  // thread: columns c0, c0 + 1 of rows r0 + 8 p
+  {
+    double2_t v[NB / 8];
+#pragma unroll
+    for (int p = 0; p < NB / 8; ++p) v[p] = *(const CVG_GLOBAL double2_t*)&blk[(r0 + 8 * p) * Kp + c0];
+#pragma unroll
+    for (int p = 0; p < NB / 8; ++p) *(double2_t*)&Xs[(r0 + 8 * p) * LDB + c0] = v[p];
+  }
   load_block64(li, NB2, Ys, t);
   __syncthreads();
-  double4_t acc[2][2];
+  // the wave's rows hold rows of the system (a block of R^T: below row M)
+  const bool live = ib < nb64 || M - (int64_t)(ib - nb64) * NB2 - NB * h - 16 * wm > 0;
+  double4_t acc[2] = {double4_t{0.0, 0.0, 0.0, 0.0}, double4_t{0.0, 0.0, 0.0, 0.0}};
+  if (live) {
+#pragma unroll 4
+    for (int kk = 0; kk < NB2 / 4; ++kk) {
+      const double x = Xs[(16 * wm + fc) * LDB + 4 * kk + fr];
 #pragma unroll
-  for (int u = 0; u < 2; ++u)
-#pragma unroll
-    for (int v = 0; v < 2; ++v) acc[u][v] = double4_t{0.0, 0.0, 0.0, 0.0};
-  mma64_rows<false>(Xs, Ys, acc, wm, wn, fr, fc, live_row_blocks(ib, nb64, M, wm));
+      for (int v = 0; v < 2; ++v)
+        acc[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+            x, Ys[(32 * wn + 16 * v + fc) * LDB + 4 * kk + fr], acc[v], 0, 0, 0);
+    }
+  }
   __syncthreads();  // every wave's reads of Xs are done
 #pragma unroll
-  for (int u = 0; u < 2; ++u)
+  for (int v = 0; v < 2; ++v)
 #pragma unroll
-    for (int v = 0; v < 2; ++v)
-#pragma unroll
-      for (int e = 0; e < 4; ++e)
-        Xs[(32 * wm + 16 * u + 4 * e + fr) * LDB + 32 * wn + 16 * v + fc] = acc[u][v][e];
+    for (int e = 0; e < 4; ++e) Xs[(16 * wm + 4 * e + fr) * LDB + 32 * wn + 16 * v + fc] = acc[v][e];
   __syncthreads();
-  store_block64(blk, Kp, Xs, t);
+#pragma unroll
+  for (int p = 0; p < NB / 8; ++p)
+    *(CVG_GLOBAL double2_t*)&blk[(r0 + 8 * p) * Kp + c0] = *(const double2_t*)&Xs[(r0 + 8 * p) * LDB + c0];
 }
 
 // trailing update A_ik -= L_is L_ks^T for s < k <= i (64 x 64 blocks, FP64
@@ -897,7 +914,7 @@ void ridge_solve(const double* xtx, const double* xty, const double* lambdas, in
   for (int32_t j = 0; j < nb64; ++j) {
     const int32_t below = nb64 - j - 1;
     if (below + naug > 0) {
-      chol_panel64_kernel<<<dim3((unsigned)n_mat, (unsigned)(below + naug)), kThreads, 0, s>>>(
+      chol_panel64_kernel<<<dim3((unsigned)n_mat, (unsigned)(2 * (below + naug))), kThreads, 0, s>>>(
           A, Linv64, Kp, Kr, M, j, nb64);
       CVG_LAUNCH_CHECK();
     }
