@@ -263,8 +263,9 @@ __device__ inline double4_t mma32(const double* X, int ldx, const double* Y, int
 }
 
 // Diagonal block s (64 x 64) of matrix mat by one 256-thread workgroup, the
-// block already in S (LDS, lower triangle valid; I1, I2, T: LDS scratch of
-// 32 x 33 doubles each).  The block is the 2 x 2 arrangement of 32 x 32 blocks
+// block already in S (LDS, row stride LDB, lower triangle valid; I1, I2: LDS
+// scratch of 32 x 33 doubles each; the block's upper right quadrant, which
+// is above the diagonal, holds a 32 x 32 intermediate).  The block is the 2 x 2 arrangement of 32 x 32 blocks
 //   [A11 .; A21 A22] = [L11 0; L21 L22] [L11 0; L21 L22]^T
 // so L11 = chol(A11) (one wave, above), L21 = A21 L11^{-T},
 // L22 = chol(A22 - L21 L21^T) (one wave), and the inverse of the factor is
@@ -273,12 +274,13 @@ __device__ inline double4_t mma32(const double* X, int ldx, const double* Y, int
 // inverse to Linv64 (the panel step's operand) and the two 32 x 32 diagonal
 // inverses to Linv32 (the backward substitution's).  The four 32 x 32
 // products on the FP64 matrix cores, a 16 x 16 tile per wave.
-__device__ __forceinline__ void diag64_body(double* S, double* I1, double* I2, double* T,
+__device__ __forceinline__ void diag64_body(double* S, double* I1, double* I2,
                                             CVG_GLOBAL double* a,
                             double* __restrict__ Linv64, double* __restrict__ Linv32,
                             int32_t* __restrict__ flags, int64_t Kp, int64_t mat, int32_t s,
                             int32_t nb64, int t) {
   constexpr int LI = NB + 1;
+  double* T = S + NB;  // the upper right quadrant, row stride LDB
   CVG_GLOBAL double* blk = a + (int64_t)s * NB2 * Kp + (int64_t)s * NB2;
   const int lane = t & 63, w = t >> 6;
   const int fr = lane >> 4, fc = lane & 15, tm = w >> 1, tn = w & 1;
@@ -315,11 +317,11 @@ __device__ __forceinline__ void diag64_body(double* S, double* I1, double* I2, d
     // T = L21 L11^{-1}
     const double4_t c = mma32<true, false>(S21, LDB, I1, LI, tm, tn, fr, fc, zero);
 #pragma unroll
-    for (int e = 0; e < 4; ++e) at(T, LI, e) = c[e];
+    for (int e = 0; e < 4; ++e) at(T, LDB, e) = c[e];
   }
   __syncthreads();
   // the inverse's lower left quadrant: -L22^{-1} T
-  const double4_t vq = mma32<true, false>(I2, LI, T, LI, tm, tn, fr, fc, zero);
+  const double4_t vq = mma32<true, false>(I2, LI, T, LDB, tm, tn, fr, fc, zero);
   CVG_GLOBAL double* li = gmem(Linv64) + (mat * nb64 + s) * NB2 * NB2;
   CVG_GLOBAL double* l32 = gmem(Linv32) + (mat * 2 * nb64 + 2 * s) * NB * NB;
 #pragma unroll
@@ -362,7 +364,7 @@ __global__ __launch_bounds__(kThreads) void ridge_setup_kernel(
     int64_t Kp, int64_t Kr, double* __restrict__ A, double* __restrict__ Linv64,
     double* __restrict__ Linv32, int32_t* __restrict__ flags, int32_t nb64) {
   __shared__ double S[NB2 * LDB];
-  __shared__ double I1[NB * (NB + 1)], I2[NB * (NB + 1)], T[NB * (NB + 1)];
+  __shared__ double I1[NB * (NB + 1)], I2[NB * (NB + 1)];
   const int64_t nrow = Kr / kSetupRows;
   const int64_t b = blockIdx.x, n_mat = (int64_t)n_folds * n_lambda;
   const bool diag = b < n_mat;
@@ -390,7 +392,7 @@ __global__ __launch_bounds__(kThreads) void ridge_setup_kernel(
       *(double2_t*)&S[r * LDB + c] = v;
     }
     __syncthreads();
-    diag64_body(S, I1, I2, T, gmem(A) + mat * Kr * Kp, Linv64, Linv32, flags, Kp, mat, 0, nb64,
+    diag64_body(S, I1, I2, gmem(A) + mat * Kr * Kp, Linv64, Linv32, flags, Kp, mat, 0, nb64,
                 t);
     return;
   }
@@ -431,44 +433,27 @@ __global__ __launch_bounds__(kThreads) void ridge_setup_kernel(
 // blocks of v_mfma_f64_16x16x4f64 over 16 steps of 4 c.  Element e of
 // acc[a][b] in lane (fr = lane / 16, fc = lane % 16) is
 //   C[32 wm + 16 a + 4 e + fr][32 wn + 16 b + fc].
-// NU < 2: only the wave's first NU 16-row blocks (acc[u], u < NU).
-template <bool NEG, int NU = 2>
+template <bool NEG>
 __device__ inline void mma64(const double* X, const double* Y, double4_t (&acc)[2][2], int wm,
                              int wn, int fr, int fc) {
 #pragma unroll 4
   for (int kk = 0; kk < NB2 / 4; ++kk) {
     double af[2], bf[2];
 #pragma unroll
-    for (int u = 0; u < NU; ++u) {
+    for (int u = 0; u < 2; ++u) {
       const double x = X[(32 * wm + 16 * u + fc) * LDB + 4 * kk + fr];
       af[u] = NEG ? -x : x;
     }
 #pragma unroll
     for (int w = 0; w < 2; ++w) bf[w] = Y[(32 * wn + 16 * w + fc) * LDB + 4 * kk + fr];
 #pragma unroll
-    for (int u = 0; u < NU; ++u)
+    for (int u = 0; u < 2; ++u)
 #pragma unroll
       for (int w = 0; w < 2; ++w)
         acc[u][w] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[u], bf[w], acc[u][w], 0, 0, 0);
   }
 }
 
-// The 16-row blocks of a wave's 32 rows that hold rows of the system: all
-// of a matrix block; of a block of R^T rows (block row ib >= nb64), those
-// below row M of R^T (the rows past it are zero and stay zero).
-__device__ inline int live_row_blocks(int32_t ib, int32_t nb64, int64_t M, int wm) {
-  if (ib < nb64) return 2;
-  const int64_t live = M - (int64_t)(ib - nb64) * NB2 - 32 * wm;
-  return live <= 0 ? 0 : live >= 32 ? 2 : live > 16 ? 2 : 1;
-}
-template <bool NEG>
-__device__ inline void mma64_rows(const double* X, const double* Y, double4_t (&acc)[2][2], int wm,
-                                  int wn, int fr, int fc, int nu) {
-  if (nu == 2)
-    mma64<NEG, 2>(X, Y, acc, wm, wn, fr, fc);
-  else if (nu == 1)
-    mma64<NEG, 1>(X, Y, acc, wm, wn, fr, fc);
-}
 
 // panel: L_is = A_is Linv_ss^T for block rows i > s (64 x 64 blocks, FP64
 // MFMA), in place; the naug block rows below the matrix (R^T) take the same
@@ -526,27 +511,37 @@ __global__ __launch_bounds__(kThreads) void chol_panel64_kernel(double* __restri
 
 // trailing update A_ik -= L_is L_ks^T for s < k <= i (64 x 64 blocks, FP64
 // MFMA accumulating onto A_ik: the negated L_is is the first operand).
-// grid (matrices, lower triangle of the remaining blocks counted row by row,
-// then naug x (nb64 - 1 - s) blocks of the R^T rows below the matrix).
-// Workgroup 0 of a matrix owns block (s + 1, s + 1), the next
-// diagonal block: once its update is complete (no other workgroup writes
-// it), it keeps the block in LDS and factors it (diag64_body), so the next
-// step's diagonal work runs beside the rest of this update instead of in a
-// launch of its own.  On a diagonal block the wave of the upper right
-// quadrant has nothing to compute.
+// Workgroup 0 of a matrix owns block (s + 1, s + 1), the next diagonal
+// block: once its update is complete (no other workgroup writes it), it
+// keeps the block in LDS and factors it (diag64_body), so the next step's
+// diagonal work runs beside the rest of this update instead of in a launch
+// of its own.  Every other block is updated by two workgroups of 32 rows
+// each (half the chain of products of a whole block, and LDS for three
+// workgroups a CU): wave w the 16 rows 16 (w / 2) .. and 32 columns
+// 32 (w % 2) .. of its half.  Waves whose tile lies above the diagonal of a
+// diagonal block, or in the zero rows of R^T, have nothing to compute.
+// grid (matrices, 1 + 2 x the other blocks: the lower triangle of the
+// remaining blocks counted row by row, then naug x (nb64 - 1 - s) blocks of
+// the R^T rows below the matrix; the halves of a block adjacent)
 __global__ __launch_bounds__(kThreads) void chol_update64_kernel(double* __restrict__ A,
                                                                  double* __restrict__ Linv64,
                                                                  double* __restrict__ Linv32,
                                                                  int32_t* __restrict__ flags,
                                                                  int64_t Kp, int64_t Kr, int64_t M,
                                                                  int32_t s, int32_t nb64) {
-  __shared__ double Xs[NB2 * LDB], Ys[NB2 * LDB];
+  // P: a 64-row block; Q: a 32-row half (non-owners) or the diagonal step's
+  // two 32 x 33 inverses (the owner)
+  __shared__ double P[NB2 * LDB], Q[NB * LDB];
+  static_assert(2 * NB * (NB + 1) <= NB * LDB, "the two inverses must fit in Q");
   const int64_t mat = blockIdx.x;
   const int32_t below = nb64 - 1 - s;
   const int32_t tri = below * (below + 1) / 2;
+  const bool owner = blockIdx.y == 0;  // block (s + 1, s + 1)
+  const int32_t bidx = owner ? 0 : 1 + ((int32_t)blockIdx.y - 1) / 2;
+  const int h = owner ? 0 : ((int32_t)blockIdx.y - 1) & 1;  // rows 32 h .. of the block
   int32_t ib, kb;
-  if ((int32_t)blockIdx.y < tri) {
-    int32_t kk = (int32_t)blockIdx.y, ii = 0;
+  if (bidx < tri) {
+    int32_t kk = bidx, ii = 0;
     while (kk > ii) {
       kk -= ii + 1;
       ++ii;
@@ -554,48 +549,57 @@ __global__ __launch_bounds__(kThreads) void chol_update64_kernel(double* __restr
     ib = s + 1 + ii;
     kb = s + 1 + kk;
   } else {  // a block of the R^T rows
-    const int32_t r = (int32_t)blockIdx.y - tri, ia = r / below;
+    const int32_t r = bidx - tri, ia = r / below;
     ib = nb64 + ia;
     kb = s + 1 + (r - ia * below);
   }
-  const bool owner = blockIdx.y == 0;  // block (s + 1, s + 1)
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int fr = lane >> 4, fc = lane & 15, wm = w >> 1, wn = w & 1;
   CVG_GLOBAL double* a = gmem(A) + mat * Kr * Kp;
-  CVG_GLOBAL double* out = a + (int64_t)ib * NB2 * Kp + (int64_t)kb * NB2;
-  const bool idle = ib == kb && wm < wn;
-  // 16-row blocks of the wave's rows to update (the zero rows of R^T stay)
-  const int nu = idle ? 0 : live_row_blocks(ib, nb64, M, wm);
-  double4_t acc[2][2];
-#pragma unroll
-  for (int u = 0; u < 2; ++u)
-    if (u < nu) {
+  if (!owner) {
+    CVG_GLOBAL double* out = a + ((int64_t)ib * NB2 + NB * h) * Kp + (int64_t)kb * NB2;
+    // rows 32 h + 16 wm .. + 15, columns 32 wn .. + 31 of the block
+    const bool act = (ib != kb || NB * h + 16 * wm + 15 >= 32 * wn) &&
+                     (ib < nb64 || M - (int64_t)(ib - nb64) * NB2 - NB * h - 16 * wm > 0);
+    double4_t acc[2];
+    if (act) {
 #pragma unroll
       for (int v = 0; v < 2; ++v)
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
-          acc[u][v][e] = out[(32 * wm + 16 * u + 4 * e + fr) * Kp + 32 * wn + 16 * v + fc];
+        for (int e = 0; e < 4; ++e) acc[v][e] = out[(16 * wm + 4 * e + fr) * Kp + 32 * wn + 16 * v + fc];
     }
-  load_block64(a + (int64_t)ib * NB2 * Kp + (int64_t)s * NB2, Kp, Xs, t);
-  if (kb != ib) load_block64(a + (int64_t)kb * NB2 * Kp + (int64_t)s * NB2, Kp, Ys, t);
-  __syncthreads();
-  mma64_rows<true>(Xs, kb != ib ? Ys : Xs, acc, wm, wn, fr, fc, nu);
-  if (!owner) {
+    // Q: rows 32 h .. of L_is; P: L_ks
+    {
+      const CVG_GLOBAL double* xs = a + ((int64_t)ib * NB2 + NB * h) * Kp + (int64_t)s * NB2;
+      const int r0 = t >> 5, c0 = (t & 31) * 2;
+      double2_t v[NB / 8];
 #pragma unroll
-    for (int u = 0; u < 2; ++u)
-      if (u < nu) {
+      for (int p = 0; p < NB / 8; ++p) v[p] = *(const CVG_GLOBAL double2_t*)&xs[(r0 + 8 * p) * Kp + c0];
 #pragma unroll
-        for (int v = 0; v < 2; ++v)
+      for (int p = 0; p < NB / 8; ++p) *(double2_t*)&Q[(r0 + 8 * p) * LDB + c0] = v[p];
+    }
+    load_block64(a + (int64_t)kb * NB2 * Kp + (int64_t)s * NB2, Kp, P, t);
+    __syncthreads();
+    if (!act) return;
+#pragma unroll 4
+    for (int kk = 0; kk < NB2 / 4; ++kk) {
+      const double x = -Q[(16 * wm + fc) * LDB + 4 * kk + fr];
 #pragma unroll
-          for (int e = 0; e < 4; ++e)
-            out[(32 * wm + 16 * u + 4 * e + fr) * Kp + 32 * wn + 16 * v + fc] = acc[u][v][e];
-      }
+      for (int v = 0; v < 2; ++v)
+        acc[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+            x, P[(32 * wn + 16 * v + fc) * LDB + 4 * kk + fr], acc[v], 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 2; ++v)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) out[(16 * wm + 4 * e + fr) * Kp + 32 * wn + 16 * v + fc] = acc[v][e];
     return;
   }
-  // the owner: the updated block to LDS (its lower triangle; the idle
-  // wave's quadrant is above the diagonal), then the factorisation of it,
-  // with the diagonal step's scratch in Ys (unused on a diagonal block)
-  __syncthreads();  // every wave's reads of Xs are done
+  // the owner: the whole diagonal block, A_ii -= L_is L_is^T (the wave of
+  // the upper right quadrant idle), then its factorisation
+  CVG_GLOBAL double* out = a + (int64_t)ib * NB2 * Kp + (int64_t)kb * NB2;
+  const bool idle = wm < wn;
+  double4_t acc[2][2];
   if (!idle) {
 #pragma unroll
     for (int u = 0; u < 2; ++u)
@@ -603,12 +607,25 @@ __global__ __launch_bounds__(kThreads) void chol_update64_kernel(double* __restr
       for (int v = 0; v < 2; ++v)
 #pragma unroll
         for (int e = 0; e < 4; ++e)
-          Xs[(32 * wm + 16 * u + 4 * e + fr) * LDB + 32 * wn + 16 * v + fc] = acc[u][v][e];
+          acc[u][v][e] = out[(32 * wm + 16 * u + 4 * e + fr) * Kp + 32 * wn + 16 * v + fc];
+  }
+  load_block64(a + (int64_t)ib * NB2 * Kp + (int64_t)s * NB2, Kp, P, t);
+  __syncthreads();
+  if (!idle) mma64<true>(P, P, acc, wm, wn, fr, fc);
+  // the updated block to LDS (its lower triangle; the idle wave's quadrant
+  // is above the diagonal), then the factorisation of it
+  __syncthreads();  // every wave's reads of P are done
+  if (!idle) {
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int v = 0; v < 2; ++v)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          P[(32 * wm + 16 * u + 4 * e + fr) * LDB + 32 * wn + 16 * v + fc] = acc[u][v][e];
   }
   __syncthreads();
-  constexpr int kI = NB * (NB + 1);
-  static_assert(3 * kI <= NB2 * LDB, "diagonal scratch must fit in the second block buffer");
-  diag64_body(Xs, Ys, Ys + kI, Ys + 2 * kI, a, Linv64, Linv32, flags, Kp, mat, s + 1, nb64, t);
+  diag64_body(P, Q, Q + NB * (NB + 1), a, Linv64, Linv32, flags, Kp, mat, s + 1, nb64, t);
 }
 
 // The backward substitution W = L^{-T} Z in one launch (Z = L^{-1} R, from
@@ -920,7 +937,7 @@ void ridge_solve(const double* xtx, const double* xty, const double* lambdas, in
     }
     if (below > 0) {
       const int32_t blocks = below * (below + 1) / 2 + naug * below;
-      chol_update64_kernel<<<dim3((unsigned)n_mat, (unsigned)blocks), kThreads, 0, s>>>(
+      chol_update64_kernel<<<dim3((unsigned)n_mat, (unsigned)(2 * blocks - 1)), kThreads, 0, s>>>(
           A, Linv64, Linv32, flags, Kp, Kr, M, j, nb64);
       CVG_LAUNCH_CHECK();
     }
