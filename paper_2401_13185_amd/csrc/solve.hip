@@ -816,8 +816,8 @@ constexpr int kTsWaves = 8;
 constexpr int kTsSlots = 4;  // 16-row tiles per wave: Kp <= 8 x 4 x 16
 constexpr int kTsCols = 16;
 __global__ __launch_bounds__(kTsWaves * kWave) void tri_solve_mfma_kernel(
-    const double* __restrict__ A, const double* __restrict__ Linv, double* __restrict__ B,
-    int64_t K, int64_t M, int64_t Kp, int64_t Kr, int32_t nblk) {
+    const double* __restrict__ A, const double* __restrict__ Linv, const double* __restrict__ Linv64,
+    double* __restrict__ B, int64_t K, int64_t M, int64_t Kp, int64_t Kr, int32_t nblk) {
   __shared__ double Rb[NB][kTsCols + 1];
   __shared__ double Zs[NB][kTsCols + 1];
   const int64_t mat = blockIdx.x;
@@ -826,14 +826,31 @@ __global__ __launch_bounds__(kTsWaves * kWave) void tri_solve_mfma_kernel(
   const int fr = lane >> 4, fc = lane & 15;
   const CVG_GLOBAL double* a = gmem(A) + mat * Kr * Kp;
   const int32_t ntile = (int32_t)(Kp / 16);
-  // R[i][m0 + c] = R^T[m0 + c][i], rows of R^T below the factor
+  // R[i][m0 + c] = R^T[m0 + c][i], rows of R^T below the factor.  The last
+  // 64-row block has not been through its panel step (the factorisation
+  // leaves it to this kernel): its four tiles are formed here as
+  // Linv64_last (R^T rows)^T, 16 MFMAs over the block's 64 rows.
+  const int32_t tlast = ntile - 4;  // first tile of the last 64-row block
+  const int64_t rlast = Kp - NB2;
   double4_t acc[kTsSlots];
 #pragma unroll
   for (int sl = 0; sl < kTsSlots; ++sl) {
     const int32_t tau = w + kTsWaves * sl;
+    if (tau < tlast) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e)
-      acc[sl][e] = tau < ntile ? a[(Kp + m0 + fc) * Kp + 16 * tau + 4 * e + fr] : 0.0;
+      for (int e = 0; e < 4; ++e) acc[sl][e] = a[(Kp + m0 + fc) * Kp + 16 * tau + 4 * e + fr];
+    } else if (tau < ntile) {
+      const CVG_GLOBAL double* li =
+          gmem(Linv64) + (mat * (Kp / NB2) + Kp / NB2 - 1) * NB2 * NB2 + (16 * (tau - tlast) + fc) * NB2;
+      const CVG_GLOBAL double* rt = a + (Kp + m0 + fc) * Kp + rlast;
+      double4_t z = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int kk = 0; kk < NB2 / 4; ++kk)
+        z = __builtin_amdgcn_mfma_f64_16x16x4f64(li[4 * kk + fr], rt[4 * kk + fr], z, 0, 0, 0);
+      acc[sl] = z;
+    } else {
+      acc[sl] = double4_t{0.0, 0.0, 0.0, 0.0};
+    }
   }
   // coefficients of step j for the tiles above its block (negated as the
   // MFMA operand, so the loads are not waited for until the products):
@@ -928,9 +945,12 @@ void ridge_solve(const double* xtx, const double* xty, const double* lambdas, in
   ridge_setup_kernel<<<(unsigned)(n_mat + n_folds * (Kr / kSetupRows)), kThreads, 0, s>>>(
       xtx, xty, lambdas, n_folds, n_lambda, K, M, Kp, Kr, A, Linv64, Linv32, flags, nb64);
   CVG_LAUNCH_CHECK();
+  // the substitution on the matrix cores forms the last block column's panel
+  // (its R^T rows only) itself
+  const bool mfma_solve = M > 0 && Kp <= (int64_t)kTsWaves * kTsSlots * 16;
   for (int32_t j = 0; j < nb64; ++j) {
     const int32_t below = nb64 - j - 1;
-    if (below + naug > 0) {
+    if (below + naug > 0 && !(below == 0 && mfma_solve)) {
       chol_panel64_kernel<<<dim3((unsigned)n_mat, (unsigned)(2 * (below + naug))), kThreads, 0, s>>>(
           A, Linv64, Kp, Kr, M, j, nb64);
       CVG_LAUNCH_CHECK();
@@ -943,10 +963,12 @@ void ridge_solve(const double* xtx, const double* xty, const double* lambdas, in
     }
   }
   if (M <= 0) return;
-  // the forward substitution is done ((L^{-1} R)^T below the factor)
-  if (Kp <= (int64_t)kTsWaves * kTsSlots * 16) {
+  // the forward substitution is done ((L^{-1} R)^T below the factor, but for
+  // the last block column with the substitution on the matrix cores)
+  if (mfma_solve) {
     const dim3 grid((unsigned)n_mat, (unsigned)((M + kTsCols - 1) / kTsCols));
-    tri_solve_mfma_kernel<<<grid, kTsWaves * kWave, 0, s>>>(A, Linv32, B, K, M, Kp, Kr, nblk);
+    tri_solve_mfma_kernel<<<grid, kTsWaves * kWave, 0, s>>>(A, Linv32, Linv64, B, K, M, Kp, Kr,
+                                                             nblk);
     CVG_LAUNCH_CHECK();
     return;
   }
