@@ -1625,13 +1625,20 @@ cvgram_status cvgram_ridge(cvgram_t h, int32_t p0, int32_t p1, const double* lam
     double* A = (double*)ws.dev((size_t)nmat * (Kp + ridge_aug_rows(M)) * Kp * 8);
     double* R = (double*)ws.dev((size_t)nmat * Kp * Mp * 8);
     double* Linv = (double*)ws.dev((size_t)nmat * Kp * 96 * 8);
-    int32_t* flags = (int32_t*)ws.dev((size_t)nmat * 4);
-    double* dl = (double*)ws.dev((size_t)n_lambda * 8);
+    int32_t* flags = (int32_t*)ws.dev((size_t)nmat * 4);  // zeroed by the factorisation
     int32_t* hflags = (int32_t*)ws.pinned((size_t)nmat * 4);
-    double* hl = (double*)ws.pinned((size_t)n_lambda * 8);
-    std::memcpy(hl, lambdas, (size_t)n_lambda * 8);
-    CVG_HIP(hipMemcpyAsync(dl, hl, (size_t)n_lambda * 8, hipMemcpyHostToDevice, s));
-    launch_fill_i32(flags, nmat, 0, s);
+    // the penalties by value in the kernel arguments, or (many) copied over
+    RidgeLambdas lv;
+    std::memset(&lv, 0, sizeof(lv));
+    double* dl = nullptr;
+    if (n_lambda <= kRidgeLambdaArgs) {
+      std::memcpy(lv.v, lambdas, (size_t)n_lambda * 8);
+    } else {
+      dl = (double*)ws.dev((size_t)n_lambda * 8);
+      double* hl = (double*)ws.pinned((size_t)n_lambda * 8);
+      std::memcpy(hl, lambdas, (size_t)n_lambda * 8);
+      CVG_HIP(hipMemcpyAsync(dl, hl, (size_t)n_lambda * 8, hipMemcpyHostToDevice, s));
+    }
     // the handle's combination of folds [p0, p1) in FP64, fold-major
     OutDesc od;
     std::memset(&od, 0, sizeof(od));
@@ -1642,7 +1649,7 @@ cvgram_status cvgram_ridge(cvgram_t h, int32_t p0, int32_t p1, const double* lam
     od.p_begin = p0;
     const ProbDesc& d = h->b.h_pd[0];
     launch_correct_single(h->b.d_pd, 0, d.n_ctiles_xx + d.n_ctiles_xy, od, nf, true, s);
-    ridge_solve(xtx, xty, dl, nf, n_lambda, K, M, A, R, Linv, flags, out_B, s);
+    ridge_solve(xtx, xty, lv, dl, nf, n_lambda, K, M, A, R, Linv, flags, out_B, s);
     CVG_HIP(hipMemcpyAsync(hflags, flags, (size_t)nmat * 4, hipMemcpyDeviceToHost, s));
     CVG_HIP(hipStreamSynchronize(s));
     for (int64_t m = 0; m < nmat; ++m)

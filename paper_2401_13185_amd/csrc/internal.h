@@ -250,11 +250,18 @@ void launch_correct_batch(const ProbDesc* pd, const OutDesc* outs, const Item* i
 // R [n_folds n_lambda][Kp][Mp],
 // Linv: n_folds n_lambda Kp 96 doubles (the 64 x 64 inverses of the diagonal
 // blocks of the factor, then their 32 x 32 diagonal blocks);
-// flags: [n_folds n_lambda] (zeroed by the caller; set on a non-positive pivot).
+// flags: [n_folds n_lambda] (set on a non-positive pivot; zeroed by the
+// factorisation itself).  Up to kRidgeLambdaArgs penalties travel by value
+// in lam (lambdas_dev null); more come from the device array lambdas_dev.
 inline int64_t ridge_padded_k(int64_t K) { return (K + 63) / 64 * 64; }
 inline int64_t ridge_aug_rows(int64_t M) { return (M + 63) / 64 * 64; }
-void ridge_solve(const double* xtx, const double* xty, const double* lambdas, int32_t n_folds,
-                 int32_t n_lambda, int64_t K, int64_t M, double* A, double* R, double* Linv,
-                 int32_t* flags, double* B, hipStream_t s);
+constexpr int kRidgeLambdaArgs = 64;
+struct RidgeLambdas {
+  double v[kRidgeLambdaArgs];
+};
+void ridge_solve(const double* xtx, const double* xty, const RidgeLambdas& lam,
+                 const double* lambdas_dev, int32_t n_folds, int32_t n_lambda, int64_t K,
+                 int64_t M, double* A, double* R, double* Linv, int32_t* flags, double* B,
+                 hipStream_t s);
 
 }  // namespace cvg

@@ -357,9 +357,10 @@ __device__ __forceinline__ void diag64_body(double* S, double* I1, double* I2,
 // beside the copies instead of after them.  The others fill kSetupRows rows
 // of every penalty's matrix of one fold below row 64 (block 0 is the
 // diagonal workgroups'), two neighbouring columns per thread, reading each
-// product entry once.
+// product entry once.  The diagonal workgroups zero their matrix's flag
+// first (only later diagonal steps set flags after them).
 __global__ __launch_bounds__(kThreads) void ridge_setup_kernel(
-    const double* __restrict__ xtx, const double* __restrict__ xty,
+    const double* __restrict__ xtx, const double* __restrict__ xty, RidgeLambdas lv,
     const double* __restrict__ lambdas, int32_t n_folds, int32_t n_lambda, int64_t K, int64_t M,
     int64_t Kp, int64_t Kr, double* __restrict__ A, double* __restrict__ Linv64,
     double* __restrict__ Linv32, int32_t* __restrict__ flags, int32_t nb64) {
@@ -379,9 +380,12 @@ __global__ __launch_bounds__(kThreads) void ridge_setup_kernel(
     }
     return (i < K && j < K) ? src[i * K + j] : (i == j ? 1.0 : 0.0);
   };
+  // penalty l: by value, or from the device array when there are more
+  auto lam_of = [&](int32_t l) { return lambdas ? lambdas[l] : lv.v[l]; };
   if (diag) {
     const int64_t mat = b;
-    const double lam = lambdas[b % n_lambda];
+    const double lam = lam_of((int32_t)(b % n_lambda));
+    if (t == 0) flags[mat] = 0;  // diag64_body (thread 0 too) sets it on a bad pivot
     const int r0 = t >> 5, c = (t & 31) * 2;
 #pragma unroll
     for (int p = 0; p < 8; ++p) {
@@ -418,7 +422,7 @@ __global__ __launch_bounds__(kThreads) void ridge_setup_kernel(
       // lambda on the diagonal of the K x K part
       const bool dx = i < K && i == j, dy = i < K && i == j + 1;
       for (int32_t l = 0; l < n_lambda; ++l) {
-        const double lam = lambdas[l];
+        const double lam = lam_of(l);
         double2_t w = v[rr];
         if (dx) w.x += lam;
         if (dy) w.y += lam;
@@ -928,9 +932,10 @@ __global__ __launch_bounds__(kTsWaves * kWave) void tri_solve_mfma_kernel(
 
 }  // namespace
 
-void ridge_solve(const double* xtx, const double* xty, const double* lambdas, int32_t n_folds,
-                 int32_t n_lambda, int64_t K, int64_t M, double* A, double* R, double* Linv,
-                 int32_t* flags, double* B, hipStream_t s) {
+void ridge_solve(const double* xtx, const double* xty, const RidgeLambdas& lam,
+                 const double* lambdas_dev, int32_t n_folds, int32_t n_lambda, int64_t K,
+                 int64_t M, double* A, double* R, double* Linv, int32_t* flags, double* B,
+                 hipStream_t s) {
   const int64_t n_mat = (int64_t)n_folds * n_lambda;
   if (n_mat <= 0 || K <= 0) return;
   const int64_t Kp = ridge_padded_k(K), Mp = (M + NB - 1) / NB * NB;
@@ -943,7 +948,7 @@ void ridge_solve(const double* xtx, const double* xty, const double* lambdas, in
   // panel below it (the matrix's block rows and the R^T rows) and the
   // trailing update, which also factors diagonal block s + 1
   ridge_setup_kernel<<<(unsigned)(n_mat + n_folds * (Kr / kSetupRows)), kThreads, 0, s>>>(
-      xtx, xty, lambdas, n_folds, n_lambda, K, M, Kp, Kr, A, Linv64, Linv32, flags, nb64);
+      xtx, xty, lam, lambdas_dev, n_folds, n_lambda, K, M, Kp, Kr, A, Linv64, Linv32, flags, nb64);
   CVG_LAUNCH_CHECK();
   // the substitution on the matrix cores forms the last block column's panel
   // (its R^T rows only) itself

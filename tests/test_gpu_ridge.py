@@ -142,3 +142,21 @@ def test_ridge_many_systems():
         for l, lam in enumerate(lams):
             ref = np.linalg.solve(xtx + lam * np.eye(k), xty)
             assert _relerr(B[p, l], ref) <= 1e-8, (p, lam)
+
+
+def test_ridge_many_penalties():
+    """65 penalties: one more than travel in the kernel arguments, so they are
+    read from a device copy."""
+    X, Y = _data(600, 20, 3, 5)
+    fold = np.arange(600, dtype=np.int32) % 3
+    lams = list(np.logspace(-3, 3, 65))
+    h = cv.cvgram_create(_t(X), _t(Y), _t(fold), 1, 1, 1, 1, ddof=1)
+    B = cv.cvgram_ridge(h, 0, 3, lams)
+    torch.cuda.synchronize()
+    B = B.cpu().numpy()
+    for p in range(3):
+        xtx, xty = O.fold_products(X, Y, fold, p, 1, 1, 1, 1, 1)
+        for l in (0, 31, 63, 64):
+            ref = np.linalg.solve(xtx + lams[l] * np.eye(20), xty)
+            assert _relerr(B[p, l], ref) <= 1e-8, (p, l)
+    cv.cvgram_destroy(h)
