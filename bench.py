@@ -570,6 +570,11 @@ def spectra_block(cv, torch, G, dev, args):
     out["one_combination"] = {"combination": "1111 (X and Y centred and scaled)",
                               "ms_per_step": ms1, "sets_per_s": sps1}
     log("spectra timed steps done")
+    # the ridge consumer is timed with the other GPU legs, before the CPU
+    # legs (whose BLAS threads can keep the host cores busy for a while and
+    # slow the host's launches of its many short kernels)
+    out["ridge"] = ridge_block(cv, torch, Xd, Yd, fd, P, K, M)
+    log("ridge block done")
     if not args.no_check or not args.no_cpu:
         h = cv.cvgram_create(Xd, Yd, fd, 1, 1, 1, 1, ddof=1, mode="fp64")
         xx, xy = cv.cvgram_folds_all(h, 0, P)
@@ -581,8 +586,6 @@ def spectra_block(cv, torch, G, dev, args):
             out["max_rel_err_vs_oracle"] = max(errs)
             out["median_rel_err_vs_oracle"] = float(np.median(errs))
             log("spectra CPU legs done")
-    out["ridge"] = ridge_block(cv, torch, Xd, Yd, fd, P, K, M)
-    log("ridge block done")
     return out
 
 
