@@ -8,27 +8,33 @@
 // identity in the padding (Kp a multiple of 64) and R^T below it in
 // Ma = ceil(M / 64) 64 rows with zeros in the padding, so no kernel below
 // needs a bounds check and every load can be issued without waiting for the
-// one before it.
+// one before it.  The penalties travel in the setup kernel's arguments (up
+// to 64; more from a device copy).
 //
 // Blocked right-looking Cholesky A = L L^T with 64 x 64 blocks:
 //   for each block column s
-//     diag:   L_ss = chol(A_ss) and its inverse (one workgroup per matrix,
-//             two 32 x 32 factorisations in registers joined by small
-//             products); for s > 0 done inside the previous step's update
-//             by the workgroup that finishes A_ss
+//     diag:   L_ss = chol(A_ss) and its inverse (one workgroup per matrix:
+//             two 32 x 32 one-wave factorisations in registers, joined by
+//             products on the matrix cores); block 0 by extra workgroups
+//             of the setup launch, block s > 0 inside the previous step's
+//             update by the workgroup that finishes A_ss
 //     panel:  L_is = A_is L_ss^{-T} for every block row i > s
 //     update: A_ik -= L_is L_ks^T for every s < k <= i (lower triangle)
 // R^T sits in extra block rows below A and takes the panel and update steps
 // with it, so it leaves the factorisation as (L^{-1} R)^T (the forward
-// substitution); the backward substitution L^{-T} then runs with 32 x 32
-// blocks through the stored inverses of the factor's 32 x 32 diagonal
-// blocks, and the result is copied out.
+// substitution).  The backward substitution L^{-T} runs through the stored
+// inverses of the factor's 32 x 32 diagonal blocks: for Kp <= 512 on the
+// matrix cores, with the right-hand sides held in the accumulators and B
+// written directly (that kernel also forms the last block column's panel of
+// the R^T rows); beyond, one row per thread, from a transposed copy, and the
+// result copied out.
 // A matrix whose pivot is not positive (A + lambda I not positive definite)
 // sets its flag and continues with NaN.
 //
-// Arithmetic: FP64 throughout; the panel and the trailing update (nearly all
-// of the factorisation's flops) on the FP64 matrix cores
-// (v_mfma_f64_16x16x4f64), the rest FP64 FMA on the vector units.  Every sum
+// Arithmetic: FP64 throughout; the panel, the trailing update (nearly all
+// of the factorisation's flops), the diagonal step's block products and the
+// matrix-core substitution on the FP64 matrix cores (v_mfma_f64_16x16x4f64),
+// the rest FP64 FMA on the vector units.  Every sum
 // runs in a fixed order (deterministic).
 #include <cmath>
 
@@ -57,8 +63,9 @@ constexpr int solve_threads() {
 
 constexpr int kSetupRows = 8;  // rows of the padded systems per setup workgroup
 
-// R[mat] (Kp x Mp) = the first Mp rows of (L^{-1} R)^T below the factor,
-// transposed: the backward substitution's input.  grid (Kp / 8, matrices)
+// Row-per-thread substitution (Kp > 512): R[mat] (Kp x Mp) = the first Mp
+// rows of (L^{-1} R)^T below the factor, transposed: the substitution's
+// input.  grid (Kp / 8, matrices)
 __global__ __launch_bounds__(kThreads) void ridge_z_kernel(const double* __restrict__ A, int64_t Kp,
                                                            int64_t Kr, int64_t Mp,
                                                            double* __restrict__ R) {
