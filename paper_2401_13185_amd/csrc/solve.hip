@@ -63,33 +63,54 @@ constexpr int solve_threads() {
 
 constexpr int kSetupRows = 8;  // rows of the padded systems per setup workgroup
 
+// (matrix, block index) of a workgroup of a launch over n_mat matrices x ny
+// blocks: grid (n_mat, ny), or, where ny would pass grid.y's limit, a 1-D
+// grid of n_mat x ny workgroups, the matrix fastest (the same order)
+__device__ inline void mat_and_block(int64_t n_mat, int64_t& mat, int32_t& y) {
+  if (gridDim.y > 1) {
+    mat = blockIdx.x;
+    y = (int32_t)blockIdx.y;
+  } else {
+    const uint32_t n = (uint32_t)n_mat, b = blockIdx.x;
+    mat = b % n;
+    y = (int32_t)(b / n);
+  }
+}
+inline dim3 mat_block_grid(int64_t n_mat, int64_t ny) {
+  return ny <= 65535 ? dim3((unsigned)n_mat, (unsigned)ny) : dim3((unsigned)(n_mat * ny));
+}
+
 // Row-per-thread substitution (Kp > 512): R[mat] (Kp x Mp) = the first Mp
 // rows of (L^{-1} R)^T below the factor, transposed: the substitution's
-// input.  grid (Kp / 8, matrices)
+// input.  grid (Kp / 8, up to 65535 strides over the matrices)
 __global__ __launch_bounds__(kThreads) void ridge_z_kernel(const double* __restrict__ A, int64_t Kp,
-                                                           int64_t Kr, int64_t Mp,
+                                                           int64_t Kr, int64_t Mp, int64_t n_mat,
                                                            double* __restrict__ R) {
-  const int64_t mat = blockIdx.y;
-  const CVG_GLOBAL double* z = gmem(A) + mat * Kr * Kp + Kp * Kp;  // row m: Z^T[m][.]
-  CVG_GLOBAL double* rd = gmem(R) + mat * Kp * Mp;
-  const int64_t j0 = (int64_t)blockIdx.x * 8;
-  for (int64_t e = threadIdx.x; e < 8 * Mp; e += kThreads) {
-    const int64_t m = e / 8, j = j0 + e % 8;
-    rd[j * Mp + m] = z[m * Kp + j];
+  for (int64_t mat = blockIdx.y; mat < n_mat; mat += gridDim.y) {
+    const CVG_GLOBAL double* z = gmem(A) + mat * Kr * Kp + Kp * Kp;  // row m: Z^T[m][.]
+    CVG_GLOBAL double* rd = gmem(R) + mat * Kp * Mp;
+    const int64_t j0 = (int64_t)blockIdx.x * 8;
+    for (int64_t e = threadIdx.x; e < 8 * Mp; e += kThreads) {
+      const int64_t m = e / 8, j = j0 + e % 8;
+      rd[j * Mp + m] = z[m * Kp + j];
+    }
   }
 }
 
-// B[mat] = the first K x M of the padded R[mat]
+// B[mat] = the first K x M of the padded R[mat] (grid.y strides over the
+// matrices)
 __global__ __launch_bounds__(kThreads) void ridge_store_kernel(const double* __restrict__ R,
                                                                int64_t K, int64_t M, int64_t Kp,
-                                                               int64_t Mp, double* __restrict__ B) {
-  const int64_t mat = blockIdx.y;
-  const CVG_GLOBAL double* rs = gmem(R) + mat * Kp * Mp;
-  CVG_GLOBAL double* bd = gmem(B) + mat * K * M;
-  for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < K * M;
-       e += (int64_t)gridDim.x * kThreads) {
-    const int64_t i = e / M, m = e - i * M;
-    bd[e] = rs[i * Mp + m];
+                                                               int64_t Mp, int64_t n_mat,
+                                                               double* __restrict__ B) {
+  for (int64_t mat = blockIdx.y; mat < n_mat; mat += gridDim.y) {
+    const CVG_GLOBAL double* rs = gmem(R) + mat * Kp * Mp;
+    CVG_GLOBAL double* bd = gmem(B) + mat * K * M;
+    for (int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x; e < K * M;
+         e += (int64_t)gridDim.x * kThreads) {
+      const int64_t i = e / M, m = e - i * M;
+      bd[e] = rs[i * Mp + m];
+    }
   }
 }
 
@@ -471,16 +492,20 @@ __device__ inline void mma64(const double* X, const double* Y, double4_t (&acc)[
 // step (products only for their rows below M).  A workgroup forms 32 rows
 // of a block (half the chain of products of a whole block, and LDS for
 // three workgroups a CU): wave w the 16 rows 16 (w / 2) .. and 32 columns
-// 32 (w % 2) ... grid (matrices, 2 x (block rows below s: nb64 - 1 - s of
-// the matrix, then naug)), the two halves of a block adjacent.
+// 32 (w % 2) ... grid (mat_block_grid): matrices x 2 x (block rows below
+// s: nb64 - 1 - s of the matrix, then naug), the two halves of a block
+// adjacent.
 __global__ __launch_bounds__(kThreads) void chol_panel64_kernel(double* __restrict__ A,
                                                                 const double* __restrict__ Linv64,
                                                                 int64_t Kp, int64_t Kr, int64_t M,
-                                                                int32_t s, int32_t nb64) {
+                                                                int64_t n_mat, int32_t s,
+                                                                int32_t nb64) {
   __shared__ double Xs[NB * LDB], Ys[NB2 * LDB];
-  const int64_t mat = blockIdx.x;
-  const int32_t ib = s + 1 + (int32_t)(blockIdx.y >> 1);  // >= nb64: a row block of R^T
-  const int h = blockIdx.y & 1;                            // rows 32 h .. 32 h + 31
+  int64_t mat;
+  int32_t y;
+  mat_and_block(n_mat, mat, y);
+  const int32_t ib = s + 1 + (y >> 1);  // >= nb64: a row block of R^T
+  const int h = y & 1;                  // rows 32 h .. 32 h + 31
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int fr = lane >> 4, fc = lane & 15, wm = w >> 1, wn = w & 1;
   CVG_GLOBAL double* a = gmem(A) + mat * Kr * Kp;
@@ -531,25 +556,29 @@ __global__ __launch_bounds__(kThreads) void chol_panel64_kernel(double* __restri
 // workgroups a CU): wave w the 16 rows 16 (w / 2) .. and 32 columns
 // 32 (w % 2) .. of its half.  Waves whose tile lies above the diagonal of a
 // diagonal block, or in the zero rows of R^T, have nothing to compute.
-// grid (matrices, 1 + 2 x the other blocks: the lower triangle of the
-// remaining blocks counted row by row, then naug x (nb64 - 1 - s) blocks of
-// the R^T rows below the matrix; the halves of a block adjacent)
+// grid (mat_block_grid): matrices x (1 + 2 x the other blocks: the lower
+// triangle of the remaining blocks counted row by row, then naug x
+// (nb64 - 1 - s) blocks of the R^T rows below the matrix; the halves of a
+// block adjacent)
 __global__ __launch_bounds__(kThreads) void chol_update64_kernel(double* __restrict__ A,
                                                                  double* __restrict__ Linv64,
                                                                  double* __restrict__ Linv32,
                                                                  int32_t* __restrict__ flags,
                                                                  int64_t Kp, int64_t Kr, int64_t M,
-                                                                 int32_t s, int32_t nb64) {
+                                                                 int64_t n_mat, int32_t s,
+                                                                 int32_t nb64) {
   // P: a 64-row block; Q: a 32-row half (non-owners) or the diagonal step's
   // two 32 x 33 inverses (the owner)
   __shared__ double P[NB2 * LDB], Q[NB * LDB];
   static_assert(2 * NB * (NB + 1) <= NB * LDB, "the two inverses must fit in Q");
-  const int64_t mat = blockIdx.x;
+  int64_t mat;
+  int32_t y;
+  mat_and_block(n_mat, mat, y);
   const int32_t below = nb64 - 1 - s;
   const int32_t tri = below * (below + 1) / 2;
-  const bool owner = blockIdx.y == 0;  // block (s + 1, s + 1)
-  const int32_t bidx = owner ? 0 : 1 + ((int32_t)blockIdx.y - 1) / 2;
-  const int h = owner ? 0 : ((int32_t)blockIdx.y - 1) & 1;  // rows 32 h .. of the block
+  const bool owner = y == 0;  // block (s + 1, s + 1)
+  const int32_t bidx = owner ? 0 : 1 + (y - 1) / 2;
+  const int h = owner ? 0 : (y - 1) & 1;  // rows 32 h .. of the block
   int32_t ib, kb;
   if (bidx < tri) {
     int32_t kk = bidx, ii = 0;
@@ -963,14 +992,14 @@ void ridge_solve(const double* xtx, const double* xty, const RidgeLambdas& lam,
   for (int32_t j = 0; j < nb64; ++j) {
     const int32_t below = nb64 - j - 1;
     if (below + naug > 0 && !(below == 0 && mfma_solve)) {
-      chol_panel64_kernel<<<dim3((unsigned)n_mat, (unsigned)(2 * (below + naug))), kThreads, 0, s>>>(
-          A, Linv64, Kp, Kr, M, j, nb64);
+      chol_panel64_kernel<<<mat_block_grid(n_mat, 2 * (below + naug)), kThreads, 0, s>>>(
+          A, Linv64, Kp, Kr, M, n_mat, j, nb64);
       CVG_LAUNCH_CHECK();
     }
     if (below > 0) {
       const int32_t blocks = below * (below + 1) / 2 + naug * below;
-      chol_update64_kernel<<<dim3((unsigned)n_mat, (unsigned)(2 * blocks - 1)), kThreads, 0, s>>>(
-          A, Linv64, Linv32, flags, Kp, Kr, M, j, nb64);
+      chol_update64_kernel<<<mat_block_grid(n_mat, 2 * (int64_t)blocks - 1), kThreads, 0, s>>>(
+          A, Linv64, Linv32, flags, Kp, Kr, M, n_mat, j, nb64);
       CVG_LAUNCH_CHECK();
     }
   }
@@ -984,7 +1013,8 @@ void ridge_solve(const double* xtx, const double* xty, const RidgeLambdas& lam,
     CVG_LAUNCH_CHECK();
     return;
   }
-  ridge_z_kernel<<<dim3((unsigned)(Kp / 8), (unsigned)n_mat), kThreads, 0, s>>>(A, Kp, Kr, Mp, R);
+  const unsigned mat_y = (unsigned)(n_mat < 65535 ? n_mat : 65535);  // grid.y strides
+  ridge_z_kernel<<<dim3((unsigned)(Kp / 8), mat_y), kThreads, 0, s>>>(A, Kp, Kr, Mp, n_mat, R);
   CVG_LAUNCH_CHECK();
   const dim3 grid((unsigned)n_mat, (unsigned)(Mp / NB));
   const bool fast = Kp <= solve_threads<16>();  // one row of R per thread
@@ -1006,8 +1036,8 @@ void ridge_solve(const double* xtx, const double* xty, const RidgeLambdas& lam,
   CVG_LAUNCH_CHECK();
   {
     const int64_t per = (K * M + kThreads - 1) / kThreads;
-    dim3 grid((unsigned)(per < 1024 ? per : 1024), (unsigned)n_mat);
-    ridge_store_kernel<<<grid, kThreads, 0, s>>>(R, K, M, Kp, Mp, B);
+    dim3 grid((unsigned)(per < 1024 ? per : 1024), mat_y);
+    ridge_store_kernel<<<grid, kThreads, 0, s>>>(R, K, M, Kp, Mp, n_mat, B);
     CVG_LAUNCH_CHECK();
   }
 }
