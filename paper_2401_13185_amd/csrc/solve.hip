@@ -61,8 +61,6 @@ constexpr int solve_threads() {
   return MW <= 16 ? 512 : kThreads;
 }
 
-constexpr int kSetupRows = 8;  // rows of the padded systems per setup workgroup
-
 // (matrix, block index) of a workgroup of a launch over n_mat matrices x ny
 // blocks: grid (n_mat, ny), or, where ny would pass grid.y's limit, a 1-D
 // grid of n_mat x ny workgroups, the matrix fastest (the same order)
@@ -378,14 +376,14 @@ __device__ __forceinline__ void diag64_body(double* S, double* I1, double* I2,
 // below the diagonal are written: nothing reads the blocks above.  The rows
 // of R^T are factored with the matrix (they become (L^{-1} R)^T: the forward
 // substitution).
-// grid: folds x n_lambda + folds x Kr / kSetupRows workgroups, Kr = Kp +
-// Ma.  The first n_mat workgroups factor diagonal block 0 of one matrix each
-// (read from the products; the later diagonal blocks are factored by the
-// trailing update that finishes them), dispatched first so that they run
-// beside the copies instead of after them.  The others fill kSetupRows rows
-// of every penalty's matrix of one fold below row 64 (block 0 is the
-// diagonal workgroups'), two neighbouring columns per thread, reading each
-// product entry once.  The diagonal workgroups zero their matrix's flag
+// grid: folds x n_lambda + folds x (copy blocks of a fold) workgroups.  The
+// first n_mat workgroups factor diagonal block 0 of one matrix each (read
+// from the products; the later diagonal blocks are factored by the trailing
+// update that finishes them), dispatched first so that they run beside the
+// copies instead of after them.  The others copy one 64 x 64 block (on or
+// below the diagonal but block (0, 0), or of the R^T rows) into every
+// penalty's matrix of one fold, two neighbouring columns of eight rows per
+// thread, reading each product entry once.  The diagonal workgroups zero their matrix's flag
 // first (only later diagonal steps set flags after them).
 __global__ __launch_bounds__(kThreads) void ridge_setup_kernel(
     const double* __restrict__ xtx, const double* __restrict__ xty, RidgeLambdas lv,
@@ -394,10 +392,12 @@ __global__ __launch_bounds__(kThreads) void ridge_setup_kernel(
     double* __restrict__ Linv32, int32_t* __restrict__ flags, int32_t nb64) {
   __shared__ double S[NB2 * LDB];
   __shared__ double I1[NB * (NB + 1)], I2[NB * (NB + 1)];
-  const int64_t nrow = Kr / kSetupRows;
+  // copy blocks per fold: the lower triangle of 64 x 64 blocks but (0, 0),
+  // and the R^T rows' blocks
+  const int64_t nblk = (Kp / NB2) * (Kp / NB2 + 1) / 2 - 1 + (Kr - Kp) / NB2 * (Kp / NB2);
   const int64_t b = blockIdx.x, n_mat = (int64_t)n_folds * n_lambda;
   const bool diag = b < n_mat;
-  const int64_t f = diag ? b / n_lambda : (b - n_mat) / nrow;
+  const int64_t f = diag ? b / n_lambda : (b - n_mat) / nblk;
   const int t = threadIdx.x;
   const CVG_GLOBAL double* src = gmem(xtx) + f * K * K;
   const CVG_GLOBAL double* rs = gmem(xty) + f * K * M;
@@ -428,34 +428,48 @@ __global__ __launch_bounds__(kThreads) void ridge_setup_kernel(
                 t);
     return;
   }
+  // a copy workgroup: one 64 x 64 block of every penalty's matrix of the
+  // fold, the blocks on and below the diagonal counted row by row from
+  // block (1, 0), then the R^T rows' blocks
   CVG_GLOBAL double* dst = gmem(A) + f * n_lambda * Kr * Kp;
-  const int64_t i0 = ((b - n_mat) % nrow) * kSetupRows;
-  if (i0 < NB2) return;
-  // per pass of 2 kThreads columns: the rows' values first, all loads in
-  // flight together, then the copies (the stores would otherwise wait for
-  // each row's loads in turn)
-  for (int64_t j = 2 * (int64_t)t; j < Kp; j += 2 * kThreads) {
-    double2_t v[kSetupRows];
-#pragma unroll
-    for (int rr = 0; rr < kSetupRows; ++rr) {
-      const int64_t i = i0 + rr;
-      v[rr].x = value(i, j);
-      v[rr].y = value(i, j + 1);
-    }
-#pragma unroll
-    for (int rr = 0; rr < kSetupRows; ++rr) {
-      const int64_t i = i0 + rr;
-      const int64_t jend = i >= Kp ? Kp : (i / NB2 + 1) * NB2;
-      if (j >= jend) continue;
-      // lambda on the diagonal of the K x K part
-      const bool dx = i < K && i == j, dy = i < K && i == j + 1;
-      for (int32_t l = 0; l < n_lambda; ++l) {
-        const double lam = lam_of(l);
-        double2_t w = v[rr];
-        if (dx) w.x += lam;
-        if (dy) w.y += lam;
-        *(CVG_GLOBAL double2_t*)&dst[(l * Kr + i) * Kp + j] = w;
+  int32_t bi, bk;
+  {
+    const int32_t idx = (int32_t)((b - n_mat) % nblk) + 1;  // 0 would be block (0, 0)
+    const int32_t ntri = nb64 * (nb64 + 1) / 2;
+    if (idx < ntri) {
+      int32_t kk = idx, ii = 0;
+      while (kk > ii) {
+        kk -= ii + 1;
+        ++ii;
       }
+      bi = ii;
+      bk = kk;
+    } else {
+      const int32_t r = idx - ntri;
+      bi = nb64 + r / nb64;
+      bk = r % nb64;
+    }
+  }
+  // this thread: columns c, c + 1 of rows r0 + 8 p of the block; the loads
+  // first, all in flight together, then the copies
+  const int r0 = t >> 5, c = (t & 31) * 2;
+  const int64_t i0 = (int64_t)bi * NB2 + r0, j = (int64_t)bk * NB2 + c;
+  double2_t v[NB2 / 8];
+#pragma unroll
+  for (int p = 0; p < NB2 / 8; ++p) {
+    v[p].x = value(i0 + 8 * p, j);
+    v[p].y = value(i0 + 8 * p, j + 1);
+  }
+  for (int32_t l = 0; l < n_lambda; ++l) {
+    const double lam = lam_of(l);
+#pragma unroll
+    for (int p = 0; p < NB2 / 8; ++p) {
+      const int64_t i = i0 + 8 * p;
+      // lambda on the diagonal of the K x K part
+      double2_t w = v[p];
+      if (i < K && i == j) w.x += lam;
+      if (i < K && i == j + 1) w.y += lam;
+      *(CVG_GLOBAL double2_t*)&dst[(l * Kr + i) * Kp + j] = w;
     }
   }
 }
@@ -983,7 +997,8 @@ void ridge_solve(const double* xtx, const double* xty, const RidgeLambdas& lam,
   // the padded systems and diagonal block 0, then per block column s: the
   // panel below it (the matrix's block rows and the R^T rows) and the
   // trailing update, which also factors diagonal block s + 1
-  ridge_setup_kernel<<<(unsigned)(n_mat + n_folds * (Kr / kSetupRows)), kThreads, 0, s>>>(
+  const int64_t setup_blocks = (int64_t)nb64 * (nb64 + 1) / 2 - 1 + (int64_t)naug * nb64;
+  ridge_setup_kernel<<<(unsigned)(n_mat + n_folds * setup_blocks), kThreads, 0, s>>>(
       xtx, xty, lam, lambdas_dev, n_folds, n_lambda, K, M, Kp, Kr, A, Linv64, Linv32, flags, nb64);
   CVG_LAUNCH_CHECK();
   // the substitution on the matrix cores forms the last block column's panel
