@@ -32,14 +32,15 @@ def _data(n, k, m, seed):
     return X, Y
 
 
-# K <= 512 (Kp <= 512) takes the matrix-core backward substitution, 16
-# columns of B per workgroup (M = 40: three column blocks, the last ragged;
-# K = 512, M = 17: every wave's four row tiles, two column blocks; M = 130:
-# three 64-row blocks of right-hand sides below the matrix, the last with
-# two live rows); K > 512 the row-per-thread path
-@pytest.mark.parametrize("n,k,m,P", [(600, 40, 3, 5), (900, 45, 40, 4), (1500, 70, 1, 3),
-                                     (1200, 100, 12, 4), (2000, 100, 130, 3),
-                                     (1400, 512, 17, 3), (2500, 600, 4, 3)])
+# K = 1 and K = M = 64: one live row of a padded block, and exactly one block
+# of each without padding.  K <= 512 (Kp <= 512) takes the matrix-core
+# backward substitution, 16 columns of B per workgroup (M = 40: three column
+# blocks, the last ragged; K = 512, M = 17: every wave's four row tiles, two
+# column blocks; M = 130: three 64-row blocks of right-hand sides below the
+# matrix, the last with two live rows); K > 512 the row-per-thread path
+@pytest.mark.parametrize("n,k,m,P", [(300, 1, 2, 3), (600, 40, 3, 5), (900, 45, 40, 4),
+                                     (800, 64, 64, 3), (1500, 70, 1, 3), (1200, 100, 12, 4),
+                                     (2000, 100, 130, 3), (1400, 512, 17, 3), (2500, 600, 4, 3)])
 def test_ridge_matches_oracle(n, k, m, P):
     X, Y = _data(n, k, m, k)
     fold = np.random.default_rng(k).integers(0, P, size=n).astype(np.int32)
