@@ -1623,7 +1623,8 @@ cvgram_status cvgram_ridge(cvgram_t h, int32_t p0, int32_t p1, const double* lam
     double* xtx = (double*)ws.dev((size_t)nf * K * K * 8);
     double* xty = (double*)ws.dev((size_t)nf * K * M * 8);
     double* A = (double*)ws.dev((size_t)nmat * (Kp + ridge_aug_rows(M)) * Kp * 8);
-    double* R = (double*)ws.dev((size_t)nmat * Kp * Mp * 8);
+    double* R = ridge_solve_on_matrix_cores(Kp, M) ? nullptr
+                                                    : (double*)ws.dev((size_t)nmat * Kp * Mp * 8);
     double* Linv = (double*)ws.dev((size_t)nmat * Kp * 96 * 8);
     int32_t* flags = (int32_t*)ws.dev((size_t)nmat * 4);  // zeroed by the factorisation
     int32_t* hflags = (int32_t*)ws.pinned((size_t)nmat * 4);

@@ -247,7 +247,7 @@ void launch_correct_batch(const ProbDesc* pd, const OutDesc* outs, const Item* i
 // matrices p-major, into B: [n_folds n_lambda][K][M].  Workspaces, with
 // Kp = ridge_padded_k(K), Ma = ridge_aug_rows(M) and Mp the multiple of 32
 // at or above M: A [n_folds n_lambda][Kp + Ma][Kp] (the matrix, then R^T),
-// R [n_folds n_lambda][Kp][Mp],
+// R [n_folds n_lambda][Kp][Mp] (only where !ridge_solve_on_matrix_cores),
 // Linv: n_folds n_lambda Kp 96 doubles (the 64 x 64 inverses of the diagonal
 // blocks of the factor, then their 32 x 32 diagonal blocks);
 // flags: [n_folds n_lambda] (set on a non-positive pivot; zeroed by the
@@ -255,6 +255,9 @@ void launch_correct_batch(const ProbDesc* pd, const OutDesc* outs, const Item* i
 // in lam (lambdas_dev null); more come from the device array lambdas_dev.
 inline int64_t ridge_padded_k(int64_t K) { return (K + 63) / 64 * 64; }
 inline int64_t ridge_aug_rows(int64_t M) { return (M + 63) / 64 * 64; }
+// the backward substitution runs on the matrix cores, with the right-hand
+// sides in registers, up to Kp = 512; R is read and written only beyond
+inline bool ridge_solve_on_matrix_cores(int64_t Kp, int64_t M) { return M > 0 && Kp <= 512; }
 constexpr int kRidgeLambdaArgs = 64;
 struct RidgeLambdas {
   double v[kRidgeLambdaArgs];

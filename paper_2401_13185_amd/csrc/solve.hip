@@ -1003,7 +1003,8 @@ void ridge_solve(const double* xtx, const double* xty, const RidgeLambdas& lam,
   CVG_LAUNCH_CHECK();
   // the substitution on the matrix cores forms the last block column's panel
   // (its R^T rows only) itself
-  const bool mfma_solve = M > 0 && Kp <= (int64_t)kTsWaves * kTsSlots * 16;
+  const bool mfma_solve = ridge_solve_on_matrix_cores(Kp, M);
+  static_assert(kTsWaves * kTsSlots * 16 == 512, "the matrix-core substitution covers Kp <= 512");
   for (int32_t j = 0; j < nb64; ++j) {
     const int32_t below = nb64 - j - 1;
     if (below + naug > 0 && !(below == 0 && mfma_solve)) {
