@@ -251,7 +251,7 @@ __device__ __forceinline__ void factor32_wave(double* S, int ld, double* Li, int
   }
 }
 
-// 64 x 64 blocks between global memory (row stride ld, even) and LDS (row
+// a 64 x 64 block from global memory (row stride ld, even) to LDS (row
 // stride LDB): thread t moves columns 2 (t % 32), +1 of rows t / 32 + 8 p,
 // so each wave instruction moves two whole 512-byte rows in 16-byte pieces
 __device__ inline void load_block64(const CVG_GLOBAL double* g, int64_t ld, double* S, int t) {
@@ -261,14 +261,6 @@ __device__ inline void load_block64(const CVG_GLOBAL double* g, int64_t ld, doub
   for (int p = 0; p < 8; ++p) v[p] = *(const CVG_GLOBAL double2_t*)&g[(r0 + 8 * p) * ld + c];
 #pragma unroll
   for (int p = 0; p < 8; ++p) *(double2_t*)&S[(r0 + 8 * p) * LDB + c] = v[p];
-}
-__device__ inline void store_block64(CVG_GLOBAL double* g, int64_t ld, const double* S, int t) {
-  const int r0 = t >> 5, c = (t & 31) * 2;
-#pragma unroll
-  for (int p = 0; p < 8; ++p) {
-    const int r = r0 + 8 * p;
-    *(CVG_GLOBAL double2_t*)&g[r * ld + c] = *(const double2_t*)&S[r * LDB + c];
-  }
 }
 
 // C = X Y^T (32 x 32 over 32 terms; NEG: C = init - X Y^T) on the FP64
