@@ -11,7 +11,12 @@ resident in HBM before timing starts.  ``value`` is sets/s: a set is one
 fold's (X^T X, X^T Y) pair for one combination, P * 12 sets per step.  The
 single-combination form (create + cvgram_fold of every fold for the centred
 and scaled combination, P sets per step) is reported beside it
-(``one_combination``), on this problem and on the spectra shape.
+(``one_combination``), on this problem and on the spectra shape.  The large
+problem's Gram plan comes from the library's built-in rule (every fold has
+a tile per work item there, whatever the work-list size); the spectra and
+precision-stress problems are tuned first with cvgram_autotune (its choice
+and time reported as ``autotune``, outside the timed steps), the batch with
+cvgram_batch_autotune.
 
 Further blocks on the same line (each on by default; ``--blocks`` picks):
   headline  the large problem in FP64 (above), the same inputs in BF16X3
@@ -553,16 +558,28 @@ def headline_block(cv, torch, G, dev, args):
     return res
 
 
+def autotune(cv, Xd, Yd, fd, mode):
+    """The library's autotuner on this problem before it is timed (recorded
+    in the process's table; the following creates of this shape use it):
+    the chosen tile and work-list size, and the tuning's own time, which is
+    not part of any timed step."""
+    t0 = time.perf_counter()
+    tile, items = cv.cvgram_autotune(Xd, Yd, fd, mode=mode)
+    return {"tile": tile, "target_items": items, "seconds": round(time.perf_counter() - t0, 3)}
+
+
 def spectra_block(cv, torch, G, dev, args):
     """N=1e5, K=512, M=8, P=10 spectra, FP64 input, Dirichlet(2) folds."""
     shape, (X, Y, fold) = G.workload(2)
     N, K, M, P = shape.n, shape.k, shape.m, shape.p
     log(f"workload {shape.name} generated")
     Xd, Yd, fd = (torch.from_numpy(a).to(dev) for a in (X, Y, fold))
+    tune = autotune(cv, Xd, Yd, fd, "fp64")
     ms, st, plan = time_steps(cv, torch, Xd, Yd, fd, P, K, M, "fp64", args.steps, args.warmup, P,
                               stages_inline=False)
     out = {"workload": shape.name, "ms_per_step": ms, "sets_per_s": P * 12 / (ms * 1e-3),
            "tflops_alg": f_alg(N, K, M) / (ms * 1e-3) / 1e12, "stage_ms": st, "plan": plan,
+           "autotune": tune,
            "roofline": roofline("fp64", N, K, M, st, shape.name, plan),
            "hbm": stage_bandwidth(N, K, M, P, X.itemsize, "fp64", st)}
     ms1, sps1 = time_one_combination(cv, torch, Xd, Yd, fd, P, K, M, "fp64", args.steps,
@@ -642,11 +659,12 @@ def mixed_block(cv, torch, G, dev, args):
     del X, Y
     res = {"workload": shape.name, "classes_per_fold": 12, "modes": {}}
     for mode in ("fp64", "fp32", "bf16x3"):
+        tune = autotune(cv, Xd, Yd, fd, mode)
         ms, st, plan = time_steps(cv, torch, Xd, Yd, fd, P, K, M, mode, args.mixed_steps, 1, 25,
                                   stages_inline=True)
         rl = roofline(mode, N, K, M, st, shape.name, plan)
         res["modes"][mode] = {"sets_per_s": P * 12 / (ms * 1e-3), "ms_per_step": ms,
-                              "stage_ms": st, "plan": plan, "roofline": rl}
+                              "stage_ms": st, "plan": plan, "autotune": tune, "roofline": rl}
         log(f"mixed-block mode {mode}: {ms:.2f} ms/step, Gram {st['gram']:.2f} ms")
     f64 = res["modes"]["fp64"]["ms_per_step"]
     for mode in ("fp32", "bf16x3"):
