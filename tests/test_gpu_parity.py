@@ -143,6 +143,22 @@ def test_fp64_ragged_shapes(n, k, m, p, values, dtype):
     _check_all_folds(X, Y, fold, 1, label=shape.name)
 
 
+@pytest.mark.parametrize("n,k,m,p", [
+    (4, 1, 1, 2),       # two folds of two rows: each training partition is two rows
+    (5, 3, 2, 2),       # folds of 3 and 2 rows
+    (9, 2, 1, 3),
+    (65, 17, 3, 13),    # thirteen folds of five rows: the fold sums formed per fold
+])
+@pytest.mark.parametrize("ddof", [1, 0])
+@pytest.mark.parametrize("mode", ["fp64", "bf16x3"])
+def test_smallest_problems(n, k, m, p, ddof, mode):
+    shape = G.Shape(f"gaussian N={n} K={k} M={m} P={p}", n, k, m, p, "f64", "gaussian",
+                    "near_equal")
+    X, Y, fold = G.make(shape, 950 + n, 0)
+    _check_all_folds(X, Y, fold, ddof, mode=mode, tol=FP64_TOL if mode == "fp64" else 2e-5,
+                     label=f"{shape.name} {mode}")
+
+
 def test_fp64_constant_columns():
     rng = np.random.default_rng(3)
     n, k, m, P = 600, 70, 3, 5
