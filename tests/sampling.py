@@ -91,3 +91,54 @@ def compare_block(gxx, gxy, ref):
 def compare_fold(gxx, gxy, Xs, Ys, fold, p, ddof=1):
     """compare_block against the oracle block of fold p."""
     return compare_block(gxx, gxy, oracle_block(Xs, Ys, fold, p, ddof))
+
+
+def split_bf16_bound(X, Y, fold, p: int, ddof: int = 1):
+    """Per-entry error bounds of fold p's split-bf16 (BF16X3) products, for
+    problems whose sums are too short to average rounding out.
+
+    Reading (the paper fixes no tolerance for reduced precision): a
+    pivot-shifted value z = x - c is carried as hi + lo, hi = bf16(z),
+    lo = bf16(z - hi); bf16 rounds to within 2^-9 relative, so
+    |z - hi - lo| <= 2^-18 |z|.  The product (hi + lo)(hi' + lo') less the
+    dropped lo lo' then errs by at most 3 2^-18 |z z'|, and the FP32 sum
+    over the |T| training rows adds at most |T| 2^-24 sum |z z'|.  The pivot
+    is a mean of the column's values, so |z| is at most the column's range
+    R (over all rows) and sum_T |z_i z_j| <= |T| R_i R_j.  Undoing the shift
+    and centring run in FP64 on FP64 statistics and add nothing at this
+    scale; a scaled class divides by the training deviations.
+    Returns ([4 X^T X bounds], [8 X^T Y bounds])."""
+    X = np.asarray(X, np.float64)
+    Y = np.asarray(Y, np.float64)
+    T = np.asarray(fold) != p
+    nT = int(T.sum())
+    eps = 3.0 * 2.0 ** -18 + nT * 2.0 ** -24
+
+    def col_range(A):
+        if A.shape[1] == 0:
+            return np.zeros(0)
+        # slack for a pivot rounded to FP32
+        return A.max(axis=0) - A.min(axis=0) + 2.0 ** -20 * np.abs(A).max(axis=0)
+
+    def deviations(A):
+        if A.shape[1] == 0:
+            return np.zeros(0)
+        At = A[T]
+        s = At.std(axis=0, ddof=ddof)
+        const = (At == At[0]).all(axis=0)
+        return np.where(const | (s == 0.0), 1.0, s)
+
+    Rx, Ry = col_range(X), col_range(Y)
+    sx, sy = deviations(X), deviations(Y)
+    bxx, bxy = [], []
+    for _c, (_cx, scx, _cy, _sy) in O.XTX_CLASS_COMBO.items():
+        b = eps * nT * np.outer(Rx, Rx)
+        bxx.append(b / np.outer(sx, sx) if scx else b)
+    for _c, (_cx, scx, _cy, scy) in O.XTY_CLASS_COMBO.items():
+        b = eps * nT * np.outer(Rx, Ry)
+        if scx:
+            b = b / sx[:, None]
+        if scy:
+            b = b / sy[None, :]
+        bxy.append(b)
+    return bxx, bxy

@@ -89,6 +89,48 @@ def test_batch_matches_oracle(mode, dtype):
 
 
 @pytest.mark.parametrize("mode", ["fp64", "bf16x3"])
+def test_batch_with_smallest_problems(mode):
+    # problems of 4 to 65 rows (two-row training partitions, no Y) in one
+    # batch with a larger one: their items, slabs and corrections share the
+    # launches
+    shapes = [(4, 1, 1, 2), (5, 3, 2, 2), (1500, 100, 5, 7), (9, 2, 0, 3), (65, 17, 3, 13)]
+    probs = [G.make(G.Shape(f"small batch case {i}", n, k, m, p, "f64", "gaussian",
+                            "near_equal"), 470 + i, 0)
+             for i, (n, k, m, p) in enumerate(shapes)]
+    print(f"[batch] smallest problems mode={mode}", flush=True)
+    dev_probs = [(_t(X), _t(Y) if Y.shape[1] else None, _t(f)) for X, Y, f in probs]
+    b = cv.cvgram_batch_create(dev_probs, ddof=1, mode=mode)
+    cv.cvgram_batch_run(b)
+    torch.cuda.synchronize()
+    # BF16X3: sums of a few rows do not average the split's rounding out, so
+    # every entry is held to the split arithmetic's own bound
+    # (tests/sampling.py: split_bf16_bound) and the relative Frobenius bar
+    # to the problem with long sums
+    from tests import sampling as S
+    for i, (X, Y, f) in enumerate(probs):
+        P, scalable = cv.cvgram_batch_problem_info(b, i)
+        assert P == int(f.max()) + 1 and scalable
+        xx = b.outs[i][0].cpu().numpy()
+        xy = b.outs[i][1].cpu().numpy() if b.outs[i][1] is not None else None
+        for q in range(P):
+            oxx, oxy = O.fold_all_classes(X, Y, f, q, ddof=1)
+            tol = FP64_TOL if mode == "fp64" else (BF16X3_BOUND if X.shape[0] >= 1000 else None)
+            bxx, bxy = S.split_bf16_bound(X, Y, f, q, ddof=1) if mode == "bf16x3" else (None, None)
+            for c in range(4):
+                e = _relerr(xx[q, c], oxx[c])
+                assert tol is None or e <= tol, (mode, i, q, "XtX", c, e)
+                if bxx is not None:
+                    assert np.all(np.abs(xx[q, c] - oxx[c]) <= bxx[c]), (mode, i, q, "XtX", c)
+                assert np.array_equal(xx[q, c], xx[q, c].T)
+            for c in range(8 if Y.shape[1] else 0):
+                e = _relerr(xy[q, c], oxy[c])
+                assert tol is None or e <= tol, (mode, i, q, "XtY", c, e)
+                if bxy is not None:
+                    assert np.all(np.abs(xy[q, c] - oxy[c]) <= bxy[c]), (mode, i, q, "XtY", c)
+    cv.cvgram_batch_destroy(b)
+
+
+@pytest.mark.parametrize("mode", ["fp64", "bf16x3"])
 def test_graph_replays_match_eager_runs(mode):
     probs = _problems("f32" if mode == "bf16x3" else "f64")
     dev_probs = [(_t(X), _t(Y) if Y.shape[1] else None, _t(f)) for X, Y, f in probs]

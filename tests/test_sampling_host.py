@@ -64,3 +64,31 @@ def test_pick_columns_keeps_ends_and_is_distinct():
     cols = S.pick_columns(1024, 16, rng)
     assert cols[0] == 0 and cols[-1] == 1023 and len(set(cols)) == len(cols) == 16
     assert S.pick_columns(5, 16, rng) == [0, 1, 2, 3, 4]
+
+
+def test_split_bf16_bound_covers_an_emulated_split_product():
+    # the bound against a CPU emulation of the split products: hi = bf16(z),
+    # lo = bf16(z - hi), hi hi' + hi lo' + lo hi' summed in FP64, with the
+    # shift by a column mean rounded to FP32; and it is not vacuous (the
+    # emulated error reaches a visible part of it)
+    import torch
+    from synth import generators as G
+
+    def bf16(a):
+        return torch.tensor(a, dtype=torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
+
+    worst = 0.0
+    for (n, k, m, p), seed in [((5, 3, 2, 2), 471), ((4, 1, 1, 2), 470), ((65, 17, 3, 13), 474)]:
+        X, Y, f = G.make(G.Shape("t", n, k, m, p, "f64", "gaussian", "near_equal"), seed, 0)
+        c = X.mean(axis=0).astype(np.float32).astype(np.float64)
+        for q in range(p):
+            bxx, bxy = S.split_bf16_bound(X, Y, f, q, ddof=1)
+            assert len(bxx) == 4 and len(bxy) == 8
+            T = f != q
+            z = (X[T] - c).astype(np.float32).astype(np.float64)
+            hi = bf16(z)
+            lo = bf16(z - hi)
+            err = np.abs(hi.T @ hi + hi.T @ lo + lo.T @ hi - (X[T] - c).T @ (X[T] - c))
+            assert np.all(err <= bxx[0])
+            worst = max(worst, float((err / bxx[0]).max()))
+    assert worst > 1e-3
